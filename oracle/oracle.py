@@ -1,0 +1,244 @@
+"""ctypes binding of the CPU oracle (``liboracle_sabr.so``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg.  The product path never loads it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle_sabr.so")
+SRC = os.path.join(HERE, "sabr_oracle.cpp")
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (FP64, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(LIB_PATH):
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", "-o", LIB_PATH + ".tmp", SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class OracleMarket(ctypes.Structure):
+    _fields_ = [
+        ("n_inst", ctypes.c_int32),
+        ("fwd_off", _i32p), ("fwd_T", _f64p), ("fwd_tau", _f64p), ("fwd_F", _f64p),
+        ("fwd_P", _f64p),
+        ("und_off", _i32p), ("und_first", _i32p), ("und_len", _i32p),
+        ("q_off", _i32p), ("q_und", _i32p), ("q_kind", _i32p),
+        ("q_K", _f64p), ("q_vol", _f64p), ("q_w", _f64p),
+        ("model", ctypes.c_int32), ("formula", ctypes.c_int32), ("residual", ctypes.c_int32),
+        ("beta", ctypes.c_double),
+    ]
+
+
+class OracleSAConfig(ctypes.Structure):
+    _fields_ = [
+        ("T0", ctypes.c_double), ("cool", ctypes.c_double), ("step_frac", ctypes.c_double),
+        ("n_levels", ctypes.c_int32), ("n_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("T0_per_inst", _f64p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build(force=True)
+        L = ctypes.CDLL(LIB_PATH)
+        L.oracle_last_error.restype = ctypes.c_char_p
+        L.oracle_hagan2002_vol.restype = ctypes.c_double
+        L.oracle_hagan2002_vol.argtypes = [ctypes.c_double] * 7
+        L.oracle_paper_eq3_vol.restype = ctypes.c_double
+        L.oracle_paper_eq3_vol.argtypes = [ctypes.c_double] * 6
+        L.oracle_chi.restype = ctypes.c_double
+        L.oracle_chi.argtypes = [ctypes.c_double] * 2
+        L.oracle_black.restype = ctypes.c_double
+        L.oracle_black.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 5
+        L.oracle_black_vega.restype = ctypes.c_double
+        L.oracle_black_vega.argtypes = [ctypes.c_double] * 5
+        L.oracle_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+class Market:
+    """Keeps the numpy arrays alive while the C struct points into them."""
+
+    def __init__(self, m: dict):
+        self.arrays = {}
+        for k in ("fwd_off", "und_off", "q_off", "und_first", "und_len", "q_und", "q_kind"):
+            self.arrays[k] = np.ascontiguousarray(m[k], dtype=np.int32)
+        for k in ("fwd_T", "fwd_tau", "fwd_F", "fwd_P", "q_K", "q_vol", "q_w"):
+            self.arrays[k] = np.ascontiguousarray(m[k], dtype=np.float64)
+        a = self.arrays
+        self.n_inst = len(a["q_off"]) - 1
+        self.model = int(m["model"])
+        self.P = 4 if self.model == 0 else 12
+        self.nq = np.diff(a["q_off"])
+        self.nu = np.diff(a["und_off"])
+        self.s = OracleMarket(
+            self.n_inst,
+            _p(a["fwd_off"], _i32p), _p(a["fwd_T"], _f64p), _p(a["fwd_tau"], _f64p),
+            _p(a["fwd_F"], _f64p), _p(a["fwd_P"], _f64p),
+            _p(a["und_off"], _i32p), _p(a["und_first"], _i32p), _p(a["und_len"], _i32p),
+            _p(a["q_off"], _i32p), _p(a["q_und"], _i32p), _p(a["q_kind"], _i32p),
+            _p(a["q_K"], _f64p), _p(a["q_vol"], _f64p), _p(a["q_w"], _f64p),
+            self.model, int(m["formula"]), int(m["residual"]), float(m["beta"]))
+
+
+def _check(rc):
+    if rc < 0:
+        raise ValueError("oracle: " + lib().oracle_last_error().decode())
+    return rc
+
+
+def _mk(m):
+    return m if isinstance(m, Market) else Market(m)
+
+
+def hagan2002_vol(f, K, T, alpha, beta, rho, nu):
+    return lib().oracle_hagan2002_vol(f, K, T, alpha, beta, rho, nu)
+
+
+def paper_eq3_vol(f, K, alpha, beta, rho, nu):
+    return lib().oracle_paper_eq3_vol(f, K, alpha, beta, rho, nu)
+
+
+def chi(z, rho):
+    return lib().oracle_chi(z, rho)
+
+
+def black(kind, f, K, T, sigma, D):
+    return lib().oracle_black(kind, f, K, T, sigma, D)
+
+
+def black_vega(f, K, T, sigma, D):
+    return lib().oracle_black_vega(f, K, T, sigma, D)
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().oracle_philox4x64_10(_p(c, _u64p), _p(k, _u64p), _p(out, _u64p))
+    return out
+
+
+def underlyings(m, inst=0):
+    M = _mk(m)
+    n = int(M.nu[inst])
+    S0, A, T = np.zeros(n), np.zeros(n), np.zeros(n)
+    _check(lib().oracle_underlyings(ctypes.byref(M.s), inst, _p(S0, _f64p), _p(A, _f64p),
+                                    _p(T, _f64p)))
+    return S0, A, T
+
+
+def map_params(m, inst, p):
+    M = _mk(m)
+    out = np.zeros(int(M.nu[inst]) * 4)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    rc = _check(lib().oracle_map_params(ctypes.byref(M.s), inst, _p(p, _f64p), _p(out, _f64p)))
+    return out.reshape(-1, 4), rc == 0
+
+
+def model_values(m, inst, p):
+    """(model, target, weight) per quote of instance `inst`."""
+    M = _mk(m)
+    n = int(M.nq[inst])
+    mv, tg, w = np.zeros(n), np.zeros(n), np.zeros(n)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    rc = _check(lib().oracle_model_values(ctypes.byref(M.s), inst, _p(p, _f64p), _p(mv, _f64p),
+                                          _p(tg, _f64p), _p(w, _f64p)))
+    return mv, tg, w, rc == 0
+
+
+def cost_batch(m, params, pt_inst=None, resid=False):
+    M = _mk(m)
+    params = np.ascontiguousarray(np.atleast_2d(params), dtype=np.float64)
+    n = params.shape[0]
+    pt = np.zeros(n, np.int32) if pt_inst is None else np.ascontiguousarray(pt_inst, np.int32)
+    cost = np.zeros(n)
+    stride = int(M.nq.max()) if len(M.nq) else 0
+    r = np.full((n, stride), np.nan) if resid else None
+    _check(lib().oracle_cost_batch(ctypes.byref(M.s), n, _p(pt, _i32p), _p(params, _f64p),
+                                   _p(cost, _f64p), _p(r, _f64p), stride))
+    return (cost, r) if resid else cost
+
+
+def cost_grad(m, params, pt_inst=None, normal=False):
+    M = _mk(m)
+    params = np.ascontiguousarray(np.atleast_2d(params), dtype=np.float64)
+    n, P = params.shape
+    pt = np.zeros(n, np.int32) if pt_inst is None else np.ascontiguousarray(pt_inst, np.int32)
+    cost, grad = np.zeros(n), np.zeros((n, P))
+    A = np.zeros((n, P, P)) if normal else None
+    g = np.zeros((n, P)) if normal else None
+    _check(lib().oracle_cost_grad(ctypes.byref(M.s), n, _p(pt, _i32p), _p(params, _f64p),
+                                  _p(cost, _f64p), _p(grad, _f64p), _p(A, _f64p), _p(g, _f64p)))
+    return (cost, grad, A, g) if normal else (cost, grad)
+
+
+def sa_calibrate(m, chains, lb, ub, T0, cool, n_levels, n_steps, seed, step_frac=0.05,
+                 x0=None, T0_per_inst=None, record=False):
+    M = _mk(m)
+    P = M.P
+    ch = np.ascontiguousarray(np.broadcast_to(np.asarray(chains, np.int32), (M.n_inst,)),
+                              dtype=np.int32)
+    lb = np.ascontiguousarray(np.broadcast_to(lb, (M.n_inst, P)), dtype=np.float64)
+    ub = np.ascontiguousarray(np.broadcast_to(ub, (M.n_inst, P)), dtype=np.float64)
+    x0a = None if x0 is None else np.ascontiguousarray(np.broadcast_to(x0, (M.n_inst, P)),
+                                                       dtype=np.float64)
+    t0i = None if T0_per_inst is None else np.ascontiguousarray(T0_per_inst, dtype=np.float64)
+    cfg = OracleSAConfig(T0, cool, step_frac, n_levels, n_steps, seed, _p(t0i, _f64p))
+    best_x = np.zeros((M.n_inst, P))
+    best_f = np.zeros(M.n_inst)
+    tot = int(ch.sum())
+    cbx = np.zeros((tot, P))
+    cbf = np.zeros(tot)
+    acc = np.zeros(int(n_levels) * int(n_steps) * tot, np.uint8) if record else None
+    trace = np.zeros((M.n_inst, n_levels, 3))
+    lbest = np.zeros((M.n_inst, n_levels), np.int32)
+    nev = np.zeros(M.n_inst, np.int64)
+    _check(lib().oracle_sa_calibrate(
+        ctypes.byref(M.s), ctypes.byref(cfg), _p(ch, _i32p), _p(lb, _f64p), _p(ub, _f64p),
+        _p(x0a, _f64p), _p(best_x, _f64p), _p(best_f, _f64p), _p(cbx, _f64p), _p(cbf, _f64p),
+        _p(acc, _u8p), _p(trace, _f64p), _p(lbest, _i32p), _p(nev, _i64p)))
+    return dict(best_x=best_x, best_f=best_f, chain_best_x=cbx, chain_best_f=cbf, accept=acc,
+                trace=trace, level_best=lbest, n_evals=nev)
+
+
+def lm_polish(m, params, pt_inst, lb, ub, max_iter=50, mu0=1e-3, tol=1e-12):
+    M = _mk(m)
+    P = M.P
+    x = np.ascontiguousarray(np.atleast_2d(params), dtype=np.float64).copy()
+    n = x.shape[0]
+    pt = np.zeros(n, np.int32) if pt_inst is None else np.ascontiguousarray(pt_inst, np.int32)
+    lb = np.ascontiguousarray(np.broadcast_to(lb, (M.n_inst, P)), dtype=np.float64)
+    ub = np.ascontiguousarray(np.broadcast_to(ub, (M.n_inst, P)), dtype=np.float64)
+    f = np.zeros(n)
+    it = np.zeros(n, np.int32)
+    _check(lib().oracle_lm_polish(ctypes.byref(M.s), n, _p(pt, _i32p), _p(x, _f64p),
+                                  _p(lb, _f64p), _p(ub, _f64p), int(max_iter), ctypes.c_double(mu0),
+                                  ctypes.c_double(tol), _p(f, _f64p), _p(it, _i32p)))
+    return x, f, it

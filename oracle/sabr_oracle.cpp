@@ -1,0 +1,953 @@
+// sabr_oracle.cpp -- CPU reference for SA calibration of SABR/LIBOR models.
+//
+// TEST INFRASTRUCTURE ONLY: called by the tests, the smoke check and the CPU
+// baseline leg of the benchmark, never by the product path.  FP64 throughout,
+// glibc libm, no fast-math, no FMA contraction (-ffp-contract=off).  Every
+// function is written for readability, not speed; each cites the passage of
+// arXiv 2408.01470 it follows.  The one scalar template parameter S is either
+// double or a forward-mode dual number, so the same code yields exact
+// gradients (to rounding) for the adjoint checks.
+//
+// Parity status: the cost, maps, Black, Philox, SA and LM functions are pinned
+// by tests (paper worked example, closed forms, library references, brute
+// force).  See the test-suite for each pin.
+#include "sabr_oracle.h"
+
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+thread_local std::string g_err;
+int32_t fail(const std::string &msg) {
+  g_err = msg;
+  return -1;
+}
+const double kInf = std::numeric_limits<double>::infinity();
+
+// ---------------------------------------------------------------------------
+// Forward-mode dual numbers: value plus N partial derivatives.
+// ---------------------------------------------------------------------------
+template <int N>
+struct Dual {
+  double v;
+  double d[N];
+  Dual() : v(0.0) {
+    for (int i = 0; i < N; ++i) d[i] = 0.0;
+  }
+  Dual(double x) : v(x) {  // NOLINT: implicit promotion of constants
+    for (int i = 0; i < N; ++i) d[i] = 0.0;
+  }
+};
+
+inline double val(double x) { return x; }
+template <int N>
+inline double val(const Dual<N> &x) { return x.v; }
+
+template <int N>
+Dual<N> chain(double v, double dv, const Dual<N> &a) {  // f(a) with f'(a) = dv
+  Dual<N> r(v);
+  for (int i = 0; i < N; ++i) r.d[i] = dv * a.d[i];
+  return r;
+}
+template <int N>
+Dual<N> operator+(const Dual<N> &a, const Dual<N> &b) {
+  Dual<N> r(a.v + b.v);
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i];
+  return r;
+}
+template <int N>
+Dual<N> operator-(const Dual<N> &a, const Dual<N> &b) {
+  Dual<N> r(a.v - b.v);
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i];
+  return r;
+}
+template <int N>
+Dual<N> operator-(const Dual<N> &a) {
+  Dual<N> r(-a.v);
+  for (int i = 0; i < N; ++i) r.d[i] = -a.d[i];
+  return r;
+}
+template <int N>
+Dual<N> operator*(const Dual<N> &a, const Dual<N> &b) {
+  Dual<N> r(a.v * b.v);
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
+  return r;
+}
+template <int N>
+Dual<N> operator/(const Dual<N> &a, const Dual<N> &b) {
+  Dual<N> r(a.v / b.v);
+  for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v);
+  return r;
+}
+template <int N> Dual<N> operator+(const Dual<N> &a, double b) { return a + Dual<N>(b); }
+template <int N> Dual<N> operator+(double a, const Dual<N> &b) { return Dual<N>(a) + b; }
+template <int N> Dual<N> operator-(const Dual<N> &a, double b) { return a - Dual<N>(b); }
+template <int N> Dual<N> operator-(double a, const Dual<N> &b) { return Dual<N>(a) - b; }
+template <int N> Dual<N> operator*(const Dual<N> &a, double b) { return a * Dual<N>(b); }
+template <int N> Dual<N> operator*(double a, const Dual<N> &b) { return Dual<N>(a) * b; }
+template <int N> Dual<N> operator/(const Dual<N> &a, double b) { return a / Dual<N>(b); }
+template <int N> Dual<N> operator/(double a, const Dual<N> &b) { return Dual<N>(a) / b; }
+template <int N> Dual<N> &operator+=(Dual<N> &a, const Dual<N> &b) { return a = a + b; }
+
+template <int N>
+Dual<N> exp(const Dual<N> &a) {
+  double e = std::exp(a.v);
+  return chain(e, e, a);
+}
+template <int N>
+Dual<N> log(const Dual<N> &a) { return chain(std::log(a.v), 1.0 / a.v, a); }
+template <int N>
+Dual<N> log1p(const Dual<N> &a) { return chain(std::log1p(a.v), 1.0 / (1.0 + a.v), a); }
+template <int N>
+Dual<N> sqrt(const Dual<N> &a) {
+  double s = std::sqrt(a.v);
+  return chain(s, 0.5 / s, a);
+}
+template <int N>
+Dual<N> erfc(const Dual<N> &a) {
+  // d/dx erfc(x) = -2/sqrt(pi) exp(-x^2)
+  return chain(std::erfc(a.v), -2.0 / std::sqrt(M_PI) * std::exp(-a.v * a.v), a);
+}
+// base^e for a constant base (market data) and a parameter-dependent exponent
+template <int N>
+Dual<N> pow(double base, const Dual<N> &e) {
+  double p = std::pow(base, e.v);
+  return chain(p, p * std::log(base), e);
+}
+
+using std::erfc;
+using std::exp;
+using std::log;
+using std::log1p;
+using std::pow;
+using std::sqrt;
+
+// ---------------------------------------------------------------------------
+// Hagan 2002 lognormal implied volatility (the formula the paper cites for
+// the SABR model, with z / x(z) and the O(T) correction; Sec. 2.1 cites Hagan
+// et al. and Obloj).  Written out from its textbook definition:
+//   L = ln(f/K), q = (f K)^((1-beta)/2), z = (nu/alpha) q L,
+//   x(z) = ln((sqrt(1 - 2 rho z + z^2) + z - rho) / (1 - rho)),
+//   sigma = alpha / (q D1) * z/x(z) * corr,
+//   D1 = 1 + (1-beta)^2 L^2/24 + (1-beta)^4 L^4/1920,
+//   corr = 1 + [(1-beta)^2 alpha^2/(24 q^2) + rho beta nu alpha/(4 q)
+//              + (2 - 3 rho^2) nu^2/24] T.
+// ---------------------------------------------------------------------------
+template <class S>
+S chi(const S &z, const S &rho) {
+  // z / x(z) with the removable singularity chi(0) = 1.  x(z) is evaluated in
+  // one of three algebraically identical forms so that no branch subtracts
+  // nearly equal numbers:  with s = sqrt(1 - 2 rho z + z^2),
+  //   (s + z - rho)/(1 - rho) = 1 + 2z/(s + 1 - z) = (1 + rho)/(s - z + rho).
+  if (val(z) == 0.0) return S(1.0);
+  S s = sqrt(1.0 - 2.0 * rho * z + z * z);
+  S x;
+  if (val(z) > 1.0)
+    x = log((s + z - rho) / (1.0 - rho));
+  else if (val(z) < -1.0)
+    x = log((1.0 + rho) / (s - z + rho));
+  else
+    x = log1p(2.0 * z / (s + 1.0 - z));
+  return z / x;
+}
+
+template <class S>
+S hagan2002_vol(double f, double K, double T, const S &alpha, const S &beta, const S &rho,
+                const S &nu) {
+  const double L = log(f / K);
+  S omb = 1.0 - beta;
+  S q = pow(f * K, 0.5 * omb);
+  S z = (nu / alpha) * q * L;
+  S ch = chi(z, rho);
+  S omb2 = omb * omb;
+  S D1 = 1.0 + omb2 * (L * L) / 24.0 + omb2 * omb2 * (L * L * L * L) / 1920.0;
+  S corr = 1.0 + (omb2 * alpha * alpha / (24.0 * q * q) + rho * beta * nu * alpha / (4.0 * q) +
+                  (2.0 - 3.0 * rho * rho) * nu * nu / 24.0) *
+                     T;
+  return alpha / (q * D1) * ch * corr;
+}
+
+// Paper eq. (sigmaHagan), Sec. 2.1, exactly as printed: second order in the
+// moneyness k = ln(K/f), omega = f^(1-beta)/alpha, no expiry dependence.
+template <class S>
+S paper_eq3_vol(double f, double K, const S &alpha, const S &beta, const S &rho, const S &nu) {
+  S omb = 1.0 - beta;
+  S fpow = pow(f, omb);
+  S omega = fpow / alpha;
+  const double k = log(K / f);
+  S rso = rho * nu * omega;
+  S bracket = 1.0 - 0.5 * (omb - rso) * k +
+              (omb * omb + (2.0 - 3.0 * rho * rho) * nu * nu * omega * omega +
+               3.0 * (omb - rso)) *
+                  (k * k) / 12.0;
+  return alpha / fpow * bracket;
+}
+
+// ---------------------------------------------------------------------------
+// Black-76 (named for caplets and swaptions in Sec. 1 and in f_s, Sec. 3):
+//   call = D [f N(d1) - K N(d2)], put = D [K N(-d2) - f N(-d1)],
+//   d1,2 = (ln(f/K) +- sigma^2 T/2) / (sigma sqrt T), N(x) = erfc(-x/sqrt 2)/2.
+// The out-of-the-money side is evaluated directly and the other side through
+// put-call parity, call - put = D (f - K).
+// ---------------------------------------------------------------------------
+template <class S>
+S norm_cdf(const S &x) { return 0.5 * erfc(-x / std::sqrt(2.0)); }
+
+template <class S>
+S black_price(int kind, double f, double K, double T, const S &sigma, double D) {
+  S sd = sigma * std::sqrt(T);
+  S d1 = (log(f / K) + 0.5 * sigma * sigma * T) / sd;
+  S d2 = d1 - sd;
+  const bool otm_call = K >= f;
+  S v = otm_call ? D * (f * norm_cdf(d1) - K * norm_cdf(d2))
+                 : D * (K * norm_cdf(-d2) - f * norm_cdf(-d1));
+  const bool want_call = (kind == 0);
+  if (want_call == otm_call) return v;
+  return want_call ? v + D * (f - K) : v + D * (K - f);
+}
+
+double black_vega(double f, double K, double T, double sigma, double D) {
+  const double sd = sigma * std::sqrt(T);
+  const double d1 = (std::log(f / K) + 0.5 * sigma * sigma * T) / sd;
+  return D * f * std::exp(-0.5 * d1 * d1) / std::sqrt(2.0 * M_PI) * std::sqrt(T);
+}
+
+// ---------------------------------------------------------------------------
+// Market data of one instance and the market-only quantities of each
+// underlying: caplet on forward i = swap over the single period i.  For a
+// swap over forwards k in [e, e+n): annuity A = sum tau_k P_k, weights
+// w_k = tau_k P_k / A, swap rate S0 = sum w_k F_k, expiry T_e.
+// ---------------------------------------------------------------------------
+struct Fwd {
+  double T, tau, F, P;
+};
+struct Und {
+  int first, len;
+  double A, S0, Te;
+  std::vector<double> w;
+};
+struct Quote {
+  int und, kind;
+  double K, vol, w;
+  double target, weight;  // what the residual is measured against, and its weight
+};
+struct Inst {
+  int model, formula, residual;
+  double beta;
+  std::vector<Fwd> f;
+  std::vector<Und> u;
+  std::vector<Quote> q;
+};
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int32_t build_inst(const oracle_market *m, int i, Inst &I) {
+  if (!m) return fail("null market");
+  if (i < 0 || i >= m->n_inst) return fail("instance index out of range");
+  if (m->model < 0 || m->model > 1) return fail("unknown model");
+  if (m->formula < 0 || m->formula > 1) return fail("unknown vol formula");
+  if (m->residual < 0 || m->residual > 1) return fail("unknown residual mode");
+  I.model = m->model;
+  I.formula = m->formula;
+  I.residual = m->residual;
+  I.beta = m->beta;
+  if (m->model == 1 && !(m->beta >= 0.0 && m->beta <= 1.0)) return fail("beta outside [0,1]");
+  const int f0 = m->fwd_off[i], f1 = m->fwd_off[i + 1];
+  const int u0 = m->und_off[i], u1 = m->und_off[i + 1];
+  const int q0 = m->q_off[i], q1 = m->q_off[i + 1];
+  if (f1 < f0 || u1 < u0 || q1 < q0) return fail("offsets not monotone");
+  I.f.clear();
+  I.u.clear();
+  I.q.clear();
+  for (int k = f0; k < f1; ++k) {
+    Fwd F{m->fwd_T[k], m->fwd_tau[k], m->fwd_F[k], m->fwd_P[k]};
+    if (!(std::isfinite(F.T) && F.T >= 0.0) || !finite_pos(F.tau) || !finite_pos(F.F) ||
+        !finite_pos(F.P))
+      return fail("bad forward data");
+    I.f.push_back(F);
+  }
+  const int nf = f1 - f0;
+  for (int k = u0; k < u1; ++k) {
+    Und U;
+    U.first = m->und_first[k];
+    U.len = m->und_len[k];
+    if (U.len < 1 || U.first < 0 || U.first + U.len > nf) return fail("bad underlying range");
+    if (m->model == 0 && U.len != 1) return fail("GLOBAL4 markets hold caplets only");
+    U.A = 0.0;
+    for (int j = U.first; j < U.first + U.len; ++j) U.A += I.f[j].tau * I.f[j].P;
+    U.S0 = 0.0;
+    for (int j = U.first; j < U.first + U.len; ++j) {
+      const double wk = I.f[j].tau * I.f[j].P / U.A;
+      U.w.push_back(wk);
+      U.S0 += wk * I.f[j].F;
+    }
+    U.Te = I.f[U.first].T;
+    if (!(U.Te > 0.0)) return fail("underlying expiry must be positive");
+    I.u.push_back(U);
+  }
+  const int nu = u1 - u0;
+  int prev = 0;
+  for (int k = q0; k < q1; ++k) {
+    Quote Q;
+    Q.und = m->q_und[k];
+    Q.kind = m->q_kind[k];
+    Q.K = m->q_K[k];
+    Q.vol = m->q_vol[k];
+    Q.w = m->q_w[k];
+    if (Q.und < 0 || Q.und >= nu) return fail("quote underlying out of range");
+    if (Q.und < prev) return fail("quotes not sorted by underlying");
+    prev = Q.und;
+    if (Q.kind != 0 && Q.kind != 1) return fail("bad quote kind");
+    if (!finite_pos(Q.K) || !finite_pos(Q.vol) || !(std::isfinite(Q.w) && Q.w >= 0.0))
+      return fail("bad quote data");
+    const Und &U = I.u[Q.und];
+    if (I.residual == 0) {
+      Q.target = Q.vol;
+      Q.weight = Q.w;
+    } else {
+      // Price residuals: market price from Black at the market vol; weight
+      // divided by vega^2 so the cost is close to vol units.
+      Q.target = black_price<double>(Q.kind, U.S0, Q.K, U.Te, Q.vol, U.A);
+      const double vg = black_vega(U.S0, Q.K, U.Te, Q.vol, U.A);
+      if (!finite_pos(vg)) return fail("zero market vega");
+      Q.weight = Q.w / (vg * vg);
+    }
+    I.q.push_back(Q);
+  }
+  return 0;
+}
+
+int num_params(int model) { return model == 0 ? 4 : (model == 1 ? 12 : -1); }
+
+// ---------------------------------------------------------------------------
+// Parameter maps: model parameters -> SABR (alpha, beta, rho, nu) per
+// underlying.
+//  GLOBAL4: p = (alpha, beta, rho, nu) shared by every forward (the Hagan
+//    model with common parameters; the paper's x = (phi_ii, sigma_i, alpha_i)
+//    with phi_ii = rho, sigma_i = nu).
+//  LMM12: p = (a, b, c, d, a_n, b_n, c_n, d_n, rho, lambda1, eta2, lambda2),
+//    beta fixed.  alpha_i = (a + b T_i) e^{-c T_i} + d and
+//    nu_i = (a_n + b_n T_i) e^{-c_n T_i} + d_n are the abcd forms of Sec. 2.3
+//    at t = 0; phi_ii = rho; rho_ij from eq. (rhoij) with eta1 = 0; theta_ij
+//    from eq. (thetaij); phi_ij from eq. (phiij) with lambda3 = 0 (= rho).
+//    A swap rate over several forwards gets SABR parameters from a
+//    first-order freeze of dS = sum w_k dF_k at t = 0 with u_k = w_k F_k^beta:
+//      V = sum_kl u_k u_l alpha_k alpha_l rho_kl,  alpha_S = sqrt(V)/S0^beta,
+//      c_k = u_k alpha_k sum_l u_l alpha_l rho_kl / V,
+//      nu_S^2 = sum_kl c_k c_l nu_k nu_l theta_kl,
+//      rho_S = sum_kl (u_k alpha_k)(c_l nu_l) phi_kl / (alpha_S S0^beta nu_S).
+// Returns false when the point is outside the model's domain.
+// ---------------------------------------------------------------------------
+template <class S>
+struct Theta {
+  S alpha, beta, rho, nu;
+};
+
+template <class S>
+bool map_params(const Inst &I, const S *p, std::vector<Theta<S>> &th) {
+  th.assign(I.u.size(), Theta<S>());
+  if (I.model == 0) {
+    const S &alpha = p[0], &beta = p[1], &rho = p[2], &nu = p[3];
+    if (!(val(alpha) > 0.0) || !(val(beta) >= 0.0 && val(beta) <= 1.0) ||
+        !(std::fabs(val(rho)) < 1.0) || !(val(nu) >= 0.0))
+      return false;
+    for (size_t u = 0; u < I.u.size(); ++u) th[u] = Theta<S>{alpha, beta, rho, nu};
+    return true;
+  }
+  const S &a = p[0], &b = p[1], &c = p[2], &d = p[3];
+  const S &an = p[4], &bn = p[5], &cn = p[6], &dn = p[7];
+  const S &rho = p[8], &lam1 = p[9], &eta2 = p[10], &lam2 = p[11];
+  if (!(std::fabs(val(rho)) < 1.0) || !(val(lam1) >= 0.0) || !(val(lam2) >= 0.0) ||
+      !(val(eta2) >= 0.0 && val(eta2) <= 1.0))
+    return false;
+  const S beta(I.beta);
+  const size_t nf = I.f.size();
+  std::vector<S> al(nf), nv(nf);
+  for (size_t k = 0; k < nf; ++k) {
+    const double T = I.f[k].T;
+    al[k] = (a + b * T) * exp(-(c * T)) + d;
+    nv[k] = (an + bn * T) * exp(-(cn * T)) + dn;
+  }
+  for (size_t ui = 0; ui < I.u.size(); ++ui) {
+    const Und &U = I.u[ui];
+    for (int k = U.first; k < U.first + U.len; ++k)
+      if (!(val(al[k]) > 0.0) || !(val(nv[k]) >= 0.0)) return false;
+    if (U.len == 1) {
+      th[ui] = Theta<S>{al[U.first], beta, rho, nv[U.first]};
+      continue;
+    }
+    const int n = U.len;
+    std::vector<S> ua(n);  // u_k alpha_k
+    for (int k = 0; k < n; ++k) {
+      const Fwd &Fk = I.f[U.first + k];
+      ua[k] = U.w[k] * std::pow(Fk.F, I.beta) * al[U.first + k];
+    }
+    std::vector<S> R(n, S(0.0));  // R_k = sum_l u_l alpha_l rho_kl
+    for (int k = 0; k < n; ++k)
+      for (int l = 0; l < n; ++l) {
+        const double dT = std::fabs(I.f[U.first + k].T - I.f[U.first + l].T);
+        R[k] += ua[l] * exp(-(lam1 * dT));
+      }
+    S V(0.0);
+    for (int k = 0; k < n; ++k) V += ua[k] * R[k];
+    if (!(val(V) > 0.0)) return false;
+    const double S0b = std::pow(U.S0, I.beta);
+    S alphaS = sqrt(V) / S0b;
+    std::vector<S> cnu(n);  // c_k nu_k
+    for (int k = 0; k < n; ++k) cnu[k] = ua[k] * R[k] / V * nv[U.first + k];
+    S nu2(0.0);
+    for (int k = 0; k < n; ++k)
+      for (int l = 0; l < n; ++l) {
+        const double dT = std::fabs(I.f[U.first + k].T - I.f[U.first + l].T);
+        S theta = eta2 + (1.0 - eta2) * exp(-(lam2 * dT));
+        nu2 += cnu[k] * cnu[l] * theta;
+      }
+    S nuS = sqrt(nu2);
+    S rhoS(0.0);
+    if (val(nuS) > 0.0) {
+      S acc(0.0);
+      for (int k = 0; k < n; ++k)
+        for (int l = 0; l < n; ++l) acc += ua[k] * cnu[l] * rho;
+      rhoS = acc / (alphaS * S0b * nuS);
+    }
+    if (!(std::fabs(val(rhoS)) < 1.0)) return false;
+    th[ui] = Theta<S>{alphaS, beta, rhoS, nuS};
+  }
+  return true;
+}
+
+// Model value of every quote (vol or Black price); false on domain failure
+// (model vol not finite and positive, or price not finite).
+template <class S>
+bool model_values(const Inst &I, const S *p, std::vector<S> &mv) {
+  std::vector<Theta<S>> th;
+  if (!map_params(I, p, th)) return false;
+  mv.assign(I.q.size(), S(0.0));
+  for (size_t k = 0; k < I.q.size(); ++k) {
+    const Quote &Q = I.q[k];
+    const Und &U = I.u[Q.und];
+    const Theta<S> &t = th[Q.und];
+    S sig = (I.formula == 0) ? hagan2002_vol(U.S0, Q.K, U.Te, t.alpha, t.beta, t.rho, t.nu)
+                             : paper_eq3_vol(U.S0, Q.K, t.alpha, t.beta, t.rho, t.nu);
+    if (!(std::isfinite(val(sig)) && val(sig) > 0.0)) return false;
+    S m = (I.residual == 0) ? sig : black_price(Q.kind, U.S0, Q.K, U.Te, sig, U.A);
+    if (!std::isfinite(val(m))) return false;
+    mv[k] = m;
+  }
+  return true;
+}
+
+// Cost f = sum_q w_q (m_q - mkt_q)^2 (f_c and f_s of Sec. 3 with weights);
+// +inf on a domain failure or a non-finite sum.
+template <class S>
+S cost_point(const Inst &I, const S *p, double *resid) {
+  std::vector<S> mv;
+  if (!model_values(I, p, mv)) {
+    if (resid)
+      for (size_t k = 0; k < I.q.size(); ++k) resid[k] = std::nan("");
+    return S(kInf);
+  }
+  S f(0.0);
+  for (size_t k = 0; k < I.q.size(); ++k) {
+    S r = mv[k] - I.q[k].target;
+    if (resid) resid[k] = val(r);
+    f += I.q[k].weight * r * r;
+  }
+  if (!std::isfinite(val(f))) return S(kInf);
+  return f;
+}
+
+double cost_d(const Inst &I, const double *p) { return cost_point<double>(I, p, nullptr); }
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC 2011): 10 rounds of two 64x64->128 multiplies with the
+// published multipliers and Weyl key increments.
+// ---------------------------------------------------------------------------
+void philox4x64_10(const uint64_t in[4], const uint64_t key_in[2], uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+  uint64_t c[4] = {in[0], in[1], in[2], in[3]};
+  uint64_t k[2] = {key_in[0], key_in[1]};
+  for (int r = 0; r < 10; ++r) {
+    const unsigned __int128 p0 = (unsigned __int128)M0 * c[0];
+    const unsigned __int128 p1 = (unsigned __int128)M1 * c[2];
+    const uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    const uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    const uint64_t n0 = hi1 ^ c[1] ^ k[0], n1 = lo1, n2 = hi0 ^ c[3] ^ k[1], n3 = lo0;
+    c[0] = n0;
+    c[1] = n1;
+    c[2] = n2;
+    c[3] = n3;
+    k[0] += W0;
+    k[1] += W1;
+  }
+  for (int j = 0; j < 4; ++j) out[j] = c[j];
+}
+
+// u_j, j = 0..P, for (instance, level, step, chain): words of consecutive
+// Philox blocks b = 0, 1, ... at counter (l*N + s, chain, b, 0), key
+// (seed, instance); u = (word >> 11) * 2^-53 in [0, 1).
+void sa_uniforms(uint64_t seed, int inst, int l, int N, int s, int chain, int P, double *u) {
+  const int nblk = (P + 1 + 3) / 4;
+  for (int b = 0; b < nblk; ++b) {
+    const uint64_t ctr[4] = {(uint64_t)l * (uint64_t)N + (uint64_t)s, (uint64_t)chain,
+                             (uint64_t)b, 0};
+    const uint64_t key[2] = {seed, (uint64_t)inst};
+    uint64_t w[4];
+    philox4x64_10(ctr, key, w);
+    for (int j = 0; j < 4; ++j) {
+      const int idx = 4 * b + j;
+      if (idx <= P) u[idx] = (double)(w[j] >> 11) * 0x1.0p-53;
+    }
+  }
+}
+
+// Neighbour (the paper leaves ComputeNeighbour undefined; reading: every
+// coordinate moves uniformly by at most step_frac (ub - lb), is mirrored
+// back into the box, then clamped).
+void propose(int P, const double *x, const double *u, const double *lb, const double *ub,
+             double step_frac, double *xp) {
+  for (int k = 0; k < P; ++k) {
+    const double delta = step_frac * (ub[k] - lb[k]);
+    double y = x[k] + delta * (2.0 * u[k] - 1.0);
+    if (y > ub[k]) y = 2.0 * ub[k] - y;
+    if (y < lb[k]) y = 2.0 * lb[k] - y;
+    if (y > ub[k]) y = ub[k];
+    if (y < lb[k]) y = lb[k];
+    xp[k] = y;
+  }
+}
+
+// Dense Cholesky solve of the (small) symmetric positive-definite system
+// M x = rhs; false if M is not positive definite.
+bool cholesky_solve(int P, std::vector<double> M, const double *rhs, double *x) {
+  for (int j = 0; j < P; ++j) {
+    double s = M[j * P + j];
+    for (int k = 0; k < j; ++k) s -= M[j * P + k] * M[j * P + k];
+    if (!(s > 0.0) || !std::isfinite(s)) return false;
+    const double ljj = std::sqrt(s);
+    M[j * P + j] = ljj;
+    for (int i = j + 1; i < P; ++i) {
+      double t = M[i * P + j];
+      for (int k = 0; k < j; ++k) t -= M[i * P + k] * M[j * P + k];
+      M[i * P + j] = t / ljj;
+    }
+  }
+  std::vector<double> y(P);
+  for (int i = 0; i < P; ++i) {
+    double t = rhs[i];
+    for (int k = 0; k < i; ++k) t -= M[i * P + k] * y[k];
+    y[i] = t / M[i * P + i];
+  }
+  for (int i = P - 1; i >= 0; --i) {
+    double t = y[i];
+    for (int k = i + 1; k < P; ++k) t -= M[k * P + i] * x[k];
+    x[i] = t / M[i * P + i];
+  }
+  return true;
+}
+
+// Residuals r_q = m_q - mkt_q, J_q = dm_q/dp and f; false on domain failure.
+template <int P>
+bool residual_jacobian(const Inst &I, const double *p, std::vector<double> &r,
+                       std::vector<double> &J, double &f) {
+  std::vector<Dual<P>> pd(P);
+  for (int k = 0; k < P; ++k) {
+    pd[k] = Dual<P>(p[k]);
+    pd[k].d[k] = 1.0;
+  }
+  std::vector<Dual<P>> mv;
+  const size_t nq = I.q.size();
+  r.assign(nq, 0.0);
+  J.assign(nq * P, 0.0);
+  if (!model_values(I, pd.data(), mv)) return false;
+  f = 0.0;
+  for (size_t q = 0; q < nq; ++q) {
+    r[q] = mv[q].v - I.q[q].target;
+    for (int k = 0; k < P; ++k) J[q * P + k] = mv[q].d[k];
+    f += I.q[q].weight * r[q] * r[q];
+  }
+  return std::isfinite(f);
+}
+
+template <int P>
+void normal_equations(const Inst &I, const std::vector<double> &r, const std::vector<double> &J,
+                      double *jtwj, double *jtwr) {
+  for (int a = 0; a < P; ++a) {
+    jtwr[a] = 0.0;
+    for (int b = 0; b < P; ++b) jtwj[a * P + b] = 0.0;
+  }
+  for (size_t q = 0; q < I.q.size(); ++q) {
+    const double w = I.q[q].weight;
+    for (int a = 0; a < P; ++a) {
+      jtwr[a] += w * J[q * P + a] * r[q];
+      for (int b = 0; b < P; ++b) jtwj[a * P + b] += w * J[q * P + a] * J[q * P + b];
+    }
+  }
+}
+
+// Projected Levenberg-Marquardt (the gradient polish of the annealing's best
+// points; the paper polishes with Nelder-Mead after SA, Sec. 3):
+//   (J^T W J + mu diag(J^T W J)) delta = -J^T W r, trial = clamp(p + delta),
+//   accept if f decreases (mu /= 10, stop when the relative decrease < tol),
+//   else mu *= 10 (stop once mu > 1e16).  A zero diagonal entry is replaced by
+//   1.  Coordinates that
+//   are fixed (lb = ub) or sit on a bound the descent direction -J^T W r
+//   points out of are frozen for the iteration (their row and column of the
+//   system become the identity, their right-hand side 0).
+template <int P>
+void lm_one(const Inst &I, double *p, const double *lb, const double *ub, int max_iter,
+            double mu0, double tol, double *f_out, int *it_out) {
+  std::vector<double> r, J;
+  double f;
+  if (!residual_jacobian<P>(I, p, r, J, f)) {
+    *f_out = kInf;
+    *it_out = 0;
+    return;
+  }
+  double mu = mu0;
+  int it = 0;
+  std::vector<double> A(P * P), g(P), M(P * P), delta(P), trial(P);
+  for (; it < max_iter; ++it) {
+    normal_equations<P>(I, r, J, A.data(), g.data());
+    M = A;
+    for (int k = 0; k < P; ++k) {
+      const double dk = A[k * P + k] > 0.0 ? A[k * P + k] : 1.0;
+      M[k * P + k] = A[k * P + k] + mu * dk;
+    }
+    std::vector<double> rhs(P);
+    for (int k = 0; k < P; ++k) rhs[k] = -g[k];
+    for (int k = 0; k < P; ++k) {
+      const bool frozen = (lb[k] == ub[k]) || (p[k] <= lb[k] && g[k] > 0.0) ||
+                          (p[k] >= ub[k] && g[k] < 0.0);
+      if (!frozen) continue;
+      for (int j = 0; j < P; ++j) M[k * P + j] = M[j * P + k] = 0.0;
+      M[k * P + k] = 1.0;
+      rhs[k] = 0.0;
+    }
+    if (!cholesky_solve(P, M, rhs.data(), delta.data())) {
+      mu *= 10.0;
+      continue;
+    }
+    for (int k = 0; k < P; ++k) {
+      double y = p[k] + delta[k];
+      if (y > ub[k]) y = ub[k];
+      if (y < lb[k]) y = lb[k];
+      trial[k] = y;
+    }
+    const double ft = cost_d(I, trial.data());
+    if (ft < f) {
+      const double rel = (f - ft) / f;
+      for (int k = 0; k < P; ++k) p[k] = trial[k];
+      double fnew;
+      residual_jacobian<P>(I, p, r, J, fnew);
+      f = ft;
+      mu /= 10.0;
+      if (rel < tol) {
+        ++it;
+        break;
+      }
+    } else {
+      mu *= 10.0;
+      if (mu > 1e16) {  // steps no longer change p: converged to rounding
+        ++it;
+        break;
+      }
+    }
+  }
+  *f_out = f;
+  *it_out = it;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *oracle_last_error(void) { return g_err.c_str(); }
+int32_t oracle_num_params(int32_t model) { return num_params(model); }
+
+double oracle_hagan2002_vol(double f, double K, double T, double alpha, double beta, double rho,
+                            double nu) {
+  return hagan2002_vol<double>(f, K, T, alpha, beta, rho, nu);
+}
+double oracle_paper_eq3_vol(double f, double K, double alpha, double beta, double rho,
+                            double nu) {
+  return paper_eq3_vol<double>(f, K, alpha, beta, rho, nu);
+}
+double oracle_chi(double z, double rho) { return chi<double>(z, rho); }
+double oracle_black(int32_t kind, double f, double K, double T, double sigma, double D) {
+  return black_price<double>(kind, f, K, T, sigma, D);
+}
+double oracle_black_vega(double f, double K, double T, double sigma, double D) {
+  return black_vega(f, K, T, sigma, D);
+}
+void oracle_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  philox4x64_10(ctr, key, out);
+}
+
+int32_t oracle_underlyings(const oracle_market *m, int32_t inst, double *S0, double *A,
+                           double *T) {
+  Inst I;
+  if (build_inst(m, inst, I)) return -1;
+  for (size_t u = 0; u < I.u.size(); ++u) {
+    S0[u] = I.u[u].S0;
+    A[u] = I.u[u].A;
+    T[u] = I.u[u].Te;
+  }
+  return 0;
+}
+
+int32_t oracle_map_params(const oracle_market *m, int32_t inst, const double *p, double *out) {
+  Inst I;
+  if (build_inst(m, inst, I)) return -1;
+  std::vector<Theta<double>> th;
+  if (!map_params(I, p, th)) {
+    for (size_t u = 0; u < I.u.size() * 4; ++u) out[u] = std::nan("");
+    return 1;
+  }
+  for (size_t u = 0; u < th.size(); ++u) {
+    out[4 * u + 0] = th[u].alpha;
+    out[4 * u + 1] = th[u].beta;
+    out[4 * u + 2] = th[u].rho;
+    out[4 * u + 3] = th[u].nu;
+  }
+  return 0;
+}
+
+int32_t oracle_model_values(const oracle_market *m, int32_t inst, const double *p,
+                            double *model, double *target, double *weight) {
+  Inst I;
+  if (build_inst(m, inst, I)) return -1;
+  std::vector<double> mv;
+  const bool ok = model_values(I, p, mv);
+  for (size_t q = 0; q < I.q.size(); ++q) {
+    if (model) model[q] = ok ? mv[q] : std::nan("");
+    if (target) target[q] = I.q[q].target;
+    if (weight) weight[q] = I.q[q].weight;
+  }
+  return ok ? 0 : 1;
+}
+
+int32_t oracle_cost_batch(const oracle_market *m, int32_t n_pts, const int32_t *pt_inst,
+                          const double *params, double *cost, double *resid,
+                          int32_t resid_stride) {
+  if (!m) return fail("null market");
+  std::vector<Inst> insts(m->n_inst);
+  for (int i = 0; i < m->n_inst; ++i)
+    if (build_inst(m, i, insts[i])) return -1;
+  const int P = num_params(m->model);
+  for (int i = 0; i < n_pts; ++i)
+    if (pt_inst[i] < 0 || pt_inst[i] >= m->n_inst) return fail("point instance out of range");
+#pragma omp parallel for schedule(dynamic)
+  for (int i = 0; i < n_pts; ++i) {
+    const Inst &I = insts[pt_inst[i]];
+    cost[i] = cost_point<double>(I, params + (size_t)i * P,
+                                 resid ? resid + (size_t)i * resid_stride : nullptr);
+  }
+  return 0;
+}
+
+int32_t oracle_cost_grad(const oracle_market *m, int32_t n_pts, const int32_t *pt_inst,
+                         const double *params, double *cost, double *grad, double *jtwj,
+                         double *jtwr) {
+  if (!m) return fail("null market");
+  std::vector<Inst> insts(m->n_inst);
+  for (int i = 0; i < m->n_inst; ++i)
+    if (build_inst(m, i, insts[i])) return -1;
+  const int P = num_params(m->model);
+  for (int i = 0; i < n_pts; ++i)
+    if (pt_inst[i] < 0 || pt_inst[i] >= m->n_inst) return fail("point instance out of range");
+#pragma omp parallel for schedule(dynamic)
+  for (int i = 0; i < n_pts; ++i) {
+    const Inst &I = insts[pt_inst[i]];
+    const double *p = params + (size_t)i * P;
+    if (P == 4) {
+      Dual<4> pd[4];
+      for (int k = 0; k < 4; ++k) {
+        pd[k] = Dual<4>(p[k]);
+        pd[k].d[k] = 1.0;
+      }
+      Dual<4> f = cost_point<Dual<4>>(I, pd, nullptr);
+      cost[i] = f.v;
+      for (int k = 0; k < 4; ++k) grad[(size_t)i * 4 + k] = std::isfinite(f.v) ? f.d[k] : 0.0;
+      if (jtwj || jtwr) {
+        std::vector<double> r, J, A(16), g(4);
+        double ff;
+        const bool ok = residual_jacobian<4>(I, p, r, J, ff);
+        if (ok) normal_equations<4>(I, r, J, A.data(), g.data());
+        for (int k = 0; k < 16; ++k)
+          if (jtwj) jtwj[(size_t)i * 16 + k] = ok ? A[k] : 0.0;
+        for (int k = 0; k < 4; ++k)
+          if (jtwr) jtwr[(size_t)i * 4 + k] = ok ? g[k] : 0.0;
+      }
+    } else {
+      Dual<12> pd[12];
+      for (int k = 0; k < 12; ++k) {
+        pd[k] = Dual<12>(p[k]);
+        pd[k].d[k] = 1.0;
+      }
+      Dual<12> f = cost_point<Dual<12>>(I, pd, nullptr);
+      cost[i] = f.v;
+      for (int k = 0; k < 12; ++k)
+        grad[(size_t)i * 12 + k] = std::isfinite(f.v) ? f.d[k] : 0.0;
+      if (jtwj || jtwr) {
+        std::vector<double> r, J, A(144), g(12);
+        double ff;
+        const bool ok = residual_jacobian<12>(I, p, r, J, ff);
+        if (ok) normal_equations<12>(I, r, J, A.data(), g.data());
+        for (int k = 0; k < 144; ++k)
+          if (jtwj) jtwj[(size_t)i * 144 + k] = ok ? A[k] : 0.0;
+        for (int k = 0; k < 12; ++k)
+          if (jtwr) jtwr[(size_t)i * 12 + k] = ok ? g[k] : 0.0;
+      }
+    }
+  }
+  return 0;
+}
+
+// Synchronous parallel simulated annealing (Sec. 3: the boxed SA loop, run by
+// many Markov chains; at the end of every temperature level all chains
+// restart from the final point with the lowest cost).
+int32_t oracle_sa_calibrate(const oracle_market *m, const oracle_sa_config *cfg,
+                            const int32_t *chains, const double *lb, const double *ub,
+                            const double *x0, double *best_x, double *best_f,
+                            double *chain_best_x, double *chain_best_f, uint8_t *accept,
+                            double *level_trace, int32_t *level_best, int64_t *n_evals) {
+  if (!m || !cfg) return fail("null argument");
+  const int P = num_params(m->model);
+  if (P < 0) return fail("unknown model");
+  if (cfg->n_levels < 0 || cfg->n_steps < 0) return fail("negative level or step count");
+  if (!(cfg->cool > 0.0 && cfg->cool <= 1.0) || !(cfg->T0 > 0.0)) return fail("bad schedule");
+  const int L = cfg->n_levels, N = cfg->n_steps;
+  int64_t chain_base = 0, acc_base = 0;
+  for (int i = 0; i < m->n_inst; ++i) {
+    Inst I;
+    if (build_inst(m, i, I)) return -1;
+    const int C = chains[i];
+    if (C < 1) return fail("need at least one chain per instance");
+    const double *lo = lb + (size_t)i * P, *hi = ub + (size_t)i * P;
+    for (int k = 0; k < P; ++k)
+      if (!(lo[k] <= hi[k])) return fail("lb > ub");
+    // 1. every chain starts at x0 (default: box midpoint) and evaluates it
+    std::vector<double> start(P);
+    for (int k = 0; k < P; ++k) start[k] = x0 ? x0[(size_t)i * P + k] : 0.5 * (lo[k] + hi[k]);
+    std::vector<double> X((size_t)C * P), F(C), BX((size_t)C * P), BF(C);
+    for (int c = 0; c < C; ++c) {
+      for (int k = 0; k < P; ++k) X[(size_t)c * P + k] = start[k];
+      F[c] = cost_d(I, start.data());
+      for (int k = 0; k < P; ++k) BX[(size_t)c * P + k] = start[k];
+      BF[c] = F[c];
+    }
+    int64_t evals = C;
+    double T = (cfg->T0_per_inst ? cfg->T0_per_inst[i] : cfg->T0);
+    std::vector<int> nacc(C);
+    for (int l = 0; l < L; ++l) {
+      // 2. N Metropolis steps per chain at temperature T (chains independent)
+#pragma omp parallel for schedule(static)
+      for (int c = 0; c < C; ++c) {
+        std::vector<double> u(P + 1), xp(P);
+        double *x = &X[(size_t)c * P];
+        int na = 0;
+        for (int s = 0; s < N; ++s) {
+          sa_uniforms(cfg->seed, i, l, N, s, c, P, u.data());
+          propose(P, x, u.data(), lo, hi, cfg->step_frac, xp.data());
+          double fp = cost_d(I, xp.data());
+          if (std::isnan(fp)) fp = kInf;
+          const double dE = fp - F[c];
+          const bool acc = (dE <= 0.0) || (u[P] < std::exp(-dE / T));
+          if (acc) {
+            for (int k = 0; k < P; ++k) x[k] = xp[k];
+            F[c] = fp;
+            ++na;
+          }
+          if (accept) accept[acc_base + ((int64_t)l * N + s) * C + c] = acc ? 1 : 0;
+          if (fp < BF[c]) {
+            BF[c] = fp;
+            for (int k = 0; k < P; ++k) BX[(size_t)c * P + k] = xp[k];
+          }
+        }
+        nacc[c] = na;
+      }
+      evals += (int64_t)C * N;
+      // 3. level end: restart every chain at the lowest final cost (ties ->
+      //    lowest chain index); the restart point is copied, not re-evaluated
+      int bstar = 0;
+      for (int c = 1; c < C; ++c)
+        if (F[c] < F[bstar]) bstar = c;
+      for (int c = 0; c < C; ++c) {
+        if (c == bstar) continue;
+        for (int k = 0; k < P; ++k) X[(size_t)c * P + k] = X[(size_t)bstar * P + k];
+        F[c] = F[bstar];
+      }
+      if (level_best) level_best[(size_t)i * L + l] = bstar;
+      if (level_trace) {
+        int gb = 0;
+        for (int c = 1; c < C; ++c)
+          if (BF[c] < BF[gb]) gb = c;
+        int64_t tot = 0;
+        for (int c = 0; c < C; ++c) tot += nacc[c];
+        double *tr = level_trace + ((size_t)i * L + l) * 3;
+        tr[0] = BF[gb];
+        tr[1] = N > 0 ? (double)tot / ((double)C * N) : 0.0;
+        tr[2] = 0.0;
+      }
+      T = cfg->cool * T;
+    }
+    // 4. best ever over all chains (ties -> lowest chain index)
+    int gb = 0;
+    for (int c = 1; c < C; ++c)
+      if (BF[c] < BF[gb]) gb = c;
+    for (int k = 0; k < P; ++k) best_x[(size_t)i * P + k] = BX[(size_t)gb * P + k];
+    best_f[i] = BF[gb];
+    if (chain_best_x)
+      for (size_t k = 0; k < (size_t)C * P; ++k) chain_best_x[chain_base * P + k] = BX[k];
+    if (chain_best_f)
+      for (int c = 0; c < C; ++c) chain_best_f[chain_base + c] = BF[c];
+    if (n_evals) n_evals[i] = evals;
+    chain_base += C;
+    acc_base += (int64_t)L * N * C;
+  }
+  return 0;
+}
+
+int32_t oracle_lm_polish(const oracle_market *m, int32_t n_pts, const int32_t *pt_inst,
+                         double *params, const double *lb, const double *ub, int32_t max_iter,
+                         double mu0, double tol, double *cost_out, int32_t *iters_out) {
+  if (!m) return fail("null market");
+  std::vector<Inst> insts(m->n_inst);
+  for (int i = 0; i < m->n_inst; ++i)
+    if (build_inst(m, i, insts[i])) return -1;
+  const int P = num_params(m->model);
+  for (int i = 0; i < n_pts; ++i)
+    if (pt_inst[i] < 0 || pt_inst[i] >= m->n_inst) return fail("point instance out of range");
+#pragma omp parallel for schedule(dynamic)
+  for (int i = 0; i < n_pts; ++i) {
+    const int inst = pt_inst[i];
+    const Inst &I = insts[inst];
+    double f;
+    int it;
+    if (P == 4)
+      lm_one<4>(I, params + (size_t)i * 4, lb + (size_t)inst * 4, ub + (size_t)inst * 4,
+                max_iter, mu0, tol, &f, &it);
+    else
+      lm_one<12>(I, params + (size_t)i * 12, lb + (size_t)inst * 12, ub + (size_t)inst * 12,
+                 max_iter, mu0, tol, &f, &it);
+    if (cost_out) cost_out[i] = f;
+    if (iters_out) iters_out[i] = it;
+  }
+  return 0;
+}
+
+}  // extern "C"

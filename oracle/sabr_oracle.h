@@ -1,0 +1,124 @@
+/*
+ * sabr_oracle.h -- CPU reference ("oracle") for SA calibration of SABR/LIBOR
+ * market models to caplet and swaption quotes.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Plain, slow, obviously-correct FP64 code used to
+ * check the GPU library.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load it.  It shares no code with the GPU
+ * library: no headers, helpers, tables or kernels.
+ *
+ * Source of every formula: Ferreiro, Garcia, Lopez-Salas, Vazquez,
+ * "SABR/LIBOR market models: pricing and calibration for some interest rate
+ * derivatives" (arXiv 2408.01470):
+ *   - Hagan second-order moneyness formula, eq. (sigmaHagan), Sec. 2.1;
+ *   - correlation parameterisations eq. (rhoij), (thetaij), (phiij), Sec. 2.1;
+ *   - abcd volatility functions g_i, h_i, Sec. 2.3 (Rebonato model);
+ *   - caplet cost f_c and swaption cost f_s, Sec. 3;
+ *   - simulated annealing loop (boxed pseudocode) and the synchronous
+ *     one-GPU parallel variant (restart of all chains at the best final
+ *     point of each temperature level), Sec. 3.
+ * Where the paper names a formula without printing it (the full Hagan 2002
+ * lognormal expansion with z/x(z), Black-76) the oracle writes out the
+ * textbook definition.  Items the paper leaves open (neighbour rule, search
+ * box, swaption closed form, LM polish) follow the readings listed in the
+ * design notes of the repository.
+ *
+ * All arrays are HOST memory owned by the caller.  Return 0 on success,
+ * negative on invalid input (message via oracle_last_error()).
+ */
+#ifndef SABR_ORACLE_H
+#define SABR_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* CSR batch of independent markets (instances); indices are local to the
+ * instance (und_first into its forwards, q_und into its underlyings). */
+typedef struct {
+  int32_t n_inst;
+  const int32_t *fwd_off;                 /* [n_inst+1] */
+  const double *fwd_T, *fwd_tau, *fwd_F, *fwd_P; /* fixing, accrual, F_i(0), P(0,T_i+tau_i) */
+  const int32_t *und_off;                 /* [n_inst+1] */
+  const int32_t *und_first, *und_len;     /* forward range [first, first+len) */
+  const int32_t *q_off;                   /* [n_inst+1] */
+  const int32_t *q_und, *q_kind;          /* underlying, 0 = call/payer, 1 = put/receiver */
+  const double *q_K, *q_vol, *q_w;        /* strike, market implied vol, user weight */
+  int32_t model;                          /* 0 = GLOBAL4, 1 = LMM12 */
+  int32_t formula;                        /* 0 = Hagan 2002, 1 = paper eq. (sigmaHagan) */
+  int32_t residual;                       /* 0 = vol residuals, 1 = Black price residuals */
+  double beta;                            /* fixed beta (LMM12) */
+} oracle_market;
+
+const char *oracle_last_error(void);
+int32_t oracle_num_params(int32_t model);
+
+/* Single-quote primitives (pins). */
+double oracle_hagan2002_vol(double f, double K, double T, double alpha, double beta,
+                            double rho, double nu);
+double oracle_paper_eq3_vol(double f, double K, double alpha, double beta, double rho,
+                            double nu);
+double oracle_chi(double z, double rho);               /* z / x(z), chi(0) = 1 */
+double oracle_black(int32_t kind, double f, double K, double T, double sigma, double D);
+double oracle_black_vega(double f, double K, double T, double sigma, double D);
+void oracle_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* Per-underlying SABR parameters (alpha, beta, rho, nu) of one parameter
+ * point for instance `inst`: out[4*n_und]. */
+int32_t oracle_map_params(const oracle_market *m, int32_t inst, const double *p, double *out);
+
+/* Market-derived quantities per underlying: S0, annuity A, expiry T. */
+int32_t oracle_underlyings(const oracle_market *m, int32_t inst, double *S0, double *A,
+                           double *T);
+
+/* Model values (vol or price, per residual mode) and the effective market
+ * target and weight used by the cost: per quote of instance `inst`. */
+int32_t oracle_model_values(const oracle_market *m, int32_t inst, const double *p,
+                            double *model, double *target, double *weight);
+
+/* cost[i] = sum_q w_q (m_q - mkt_q)^2 for point i of instance pt_inst[i];
+ * resid (nullable) gets r_q, row stride = max quotes per instance. */
+int32_t oracle_cost_batch(const oracle_market *m, int32_t n_pts, const int32_t *pt_inst,
+                          const double *params, double *cost, double *resid,
+                          int32_t resid_stride);
+
+/* Exact gradient of the cost (forward-mode dual numbers):
+ * grad[i*P + k] = d cost_i / d p_k.  jtwj [n_pts][P][P], jtwr [n_pts][P] nullable. */
+int32_t oracle_cost_grad(const oracle_market *m, int32_t n_pts, const int32_t *pt_inst,
+                         const double *params, double *cost, double *grad, double *jtwj,
+                         double *jtwr);
+
+typedef struct {
+  double T0;          /* initial temperature */
+  double cool;        /* T_{l+1} = cool * T_l */
+  double step_frac;   /* neighbour half-width as a fraction of (ub - lb) */
+  int32_t n_levels;   /* L */
+  int32_t n_steps;    /* N */
+  uint64_t seed;      /* Philox key word 0; key word 1 = instance id */
+  const double *T0_per_inst; /* nullable */
+} oracle_sa_config;
+
+/* Synchronous parallel SA, chains[i] chains on instance i.
+ * best_x [n_inst][P], best_f [n_inst]; nullable outputs:
+ *   chain_best_x [sum chains][P], chain_best_f [sum chains]   (per-chain best ever)
+ *   accept      [n_inst] blocks of [L][N][chains[i]] bytes  (offset by prefix sums)
+ *   level_trace [n_inst][L][3] = {best-ever f, acceptance rate, 0}
+ *   level_best  [n_inst][L] = level-end argmin chain (restart point index)
+ * n_evals [n_inst] nullable: cost evaluations performed. */
+int32_t oracle_sa_calibrate(const oracle_market *m, const oracle_sa_config *cfg,
+                            const int32_t *chains, const double *lb, const double *ub,
+                            const double *x0, double *best_x, double *best_f,
+                            double *chain_best_x, double *chain_best_f, uint8_t *accept,
+                            double *level_trace, int32_t *level_best, int64_t *n_evals);
+
+/* Projected Levenberg-Marquardt polish of n_pts points (in place). */
+int32_t oracle_lm_polish(const oracle_market *m, int32_t n_pts, const int32_t *pt_inst,
+                         double *params, const double *lb, const double *ub,
+                         int32_t max_iter, double mu0, double tol, double *cost_out,
+                         int32_t *iters_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

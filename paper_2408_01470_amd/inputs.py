@@ -1,0 +1,263 @@
+"""Seeded synthetic market generators (shared by the GPU path and its checks).
+
+This module only lays out market *structure* and draws random numbers: forward
+curves, fixing grids, strikes, quote kinds, true parameters, noise draws and
+random search-box points.  It holds none of the calibration method's
+arithmetic (no implied-vol formula, no Black price, no parameter map, no
+cost): market quotes are completed by the caller from model vols at the true
+parameters (``complete_market``), computed by whichever implementation the
+caller is exercising.
+
+Workload shapes follow the paper's caplet/swaption calibration (Sec. 4:
+semiannual EURIBOR forwards, smiles over a moneyness grid ln(K/F) of
+-80%..80%, Table "Smiles of forward rates") at the sizes of the benchmark
+configurations:
+
+* ``caplet_market``      -- 10 semiannual forwards, 3% + N(0, 0.002),
+  11 strikes F +- 200 bp (ATM included), GLOBAL4 (alpha, beta, rho, nu).
+* ``lmm_market``         -- M semiannual forwards on an upward 2%..4% curve,
+  caplet smiles on forwards 1..M-1 plus an expiry x tenor swaption grid,
+  LMM12 parameters, price residuals (optionally both option sides).
+* ``batch_markets``      -- many caplet markets of uneven size
+  (10..40 forwards x 5..15 strikes).
+
+All randomness comes from ``numpy.random.Generator(Philox(key))``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+MODEL_GLOBAL4 = 0
+MODEL_LMM12 = 1
+FORMULA_HAGAN2002 = 0
+FORMULA_PAPER_EQ3 = 1
+RESID_VOL = 0
+RESID_PRICE = 1
+KIND_CALL = 0
+KIND_PUT = 1
+
+SEED_BASE = 2408014700
+
+GLOBAL4_NAMES = ("alpha", "beta", "rho", "nu")
+LMM12_NAMES = ("a", "b", "c", "d", "a_nu", "b_nu", "c_nu", "d_nu", "rho", "lambda1", "eta2",
+               "lambda2")
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.Philox(key=int(seed)))
+
+
+def num_params(model: int) -> int:
+    return 4 if model == MODEL_GLOBAL4 else 12
+
+
+def box(model: int):
+    """Search box (lb, ub).  The paper prints no box; values sitting on round
+    bounds in its calibrated tables (sigma_1 = 1, phi = -1, kappa = 0.001)
+    suggest plain interval bounds, chosen here wide enough to hold the
+    synthetic true parameters."""
+    if model == MODEL_GLOBAL4:
+        lb = np.array([0.001, 0.0, -0.99, 0.001])
+        ub = np.array([0.2, 1.0, 0.99, 1.5])
+    else:
+        lb = np.array([0.0, -0.05, 0.01, 0.001, 0.0, -0.5, 0.01, 0.001, -0.99, 0.001, 0.0, 0.001])
+        ub = np.array([0.1, 0.1, 3.0, 0.1, 1.0, 1.0, 3.0, 1.0, 0.99, 5.0, 0.999, 5.0])
+    return lb, ub
+
+
+def _curve_discounts(T, tau, F):
+    """Payment discount factors P(0, T_i + tau_i) of a curve whose forwards
+    are F (simple compounding), starting from P(0, T_0) given by the caller's
+    first entry of ``T`` at 3%: a curve consistent with its own forwards."""
+    P = np.empty_like(F)
+    d = 1.0 / (1.0 + T[0] * 0.03) if T[0] > 0 else 1.0
+    for i in range(len(F)):
+        d = d / (1.0 + tau[i] * F[i])
+        P[i] = d
+    return P
+
+
+def _empty():
+    return dict(fwd_T=[], fwd_tau=[], fwd_F=[], fwd_P=[], und_first=[], und_len=[], q_und=[],
+                q_kind=[], q_K=[], q_w=[], fwd_off=[0], und_off=[0], q_off=[0])
+
+
+def _finish(parts, model, formula, residual, beta):
+    m = {}
+    for k in ("fwd_T", "fwd_tau", "fwd_F", "fwd_P", "q_K", "q_w"):
+        m[k] = np.ascontiguousarray(np.concatenate(parts[k]) if parts[k] else np.zeros(0),
+                                    dtype=np.float64)
+    for k in ("und_first", "und_len", "q_und", "q_kind"):
+        m[k] = np.ascontiguousarray(np.concatenate(parts[k]) if parts[k] else np.zeros(0),
+                                    dtype=np.int32)
+    for k in ("fwd_off", "und_off", "q_off"):
+        m[k] = np.asarray(parts[k], dtype=np.int32)
+    m["q_vol"] = np.ones_like(m["q_K"])  # placeholder until complete_market
+    m["model"] = int(model)
+    m["formula"] = int(formula)
+    m["residual"] = int(residual)
+    m["beta"] = float(beta)
+    return m
+
+
+def _append(parts, T, tau, F, P, und_first, und_len, q_und, q_kind, q_K):
+    parts["fwd_T"].append(np.asarray(T, float))
+    parts["fwd_tau"].append(np.asarray(tau, float))
+    parts["fwd_F"].append(np.asarray(F, float))
+    parts["fwd_P"].append(np.asarray(P, float))
+    parts["und_first"].append(np.asarray(und_first, np.int32))
+    parts["und_len"].append(np.asarray(und_len, np.int32))
+    parts["q_und"].append(np.asarray(q_und, np.int32))
+    parts["q_kind"].append(np.asarray(q_kind, np.int32))
+    parts["q_K"].append(np.asarray(q_K, float))
+    parts["q_w"].append(np.ones(len(q_K)))
+    parts["fwd_off"].append(parts["fwd_off"][-1] + len(T))
+    parts["und_off"].append(parts["und_off"][-1] + len(und_first))
+    parts["q_off"].append(parts["q_off"][-1] + len(q_K))
+
+
+def _caplet_instance(g, M, nK, spread=0.02):
+    T = 0.5 * np.arange(1, M + 1)
+    tau = np.full(M, 0.5)
+    F = 0.03 + g.normal(0.0, 0.002, M)
+    P = _curve_discounts(T, tau, F)
+    und_first = np.arange(M)
+    und_len = np.ones(M, np.int32)
+    offs = np.linspace(-spread, spread, nK)
+    q_und = np.repeat(np.arange(M), nK)
+    q_K = (F[:, None] + offs[None, :]).reshape(-1)
+    # the ATM strike (offset exactly 0 when nK is odd) is F itself
+    if nK % 2 == 1:
+        q_K.reshape(M, nK)[:, nK // 2] = F
+    q_kind = np.zeros(M * nK, np.int32)
+    return T, tau, F, P, und_first, und_len, q_und, q_kind, q_K
+
+
+def _global4_truth(g):
+    return np.array([g.uniform(0.02, 0.05), 0.5, g.uniform(-0.5, 0.0), g.uniform(0.2, 0.6)])
+
+
+def caplet_market(seed=SEED_BASE + 1000, M=10, nK=11, formula=FORMULA_HAGAN2002,
+                  residual=RESID_VOL):
+    """One caplet market: M semiannual forwards (fixings 0.5..0.5M years),
+    F_i = 3% + N(0, 0.002), nK strikes evenly spread over F +- 200 bp."""
+    g = rng(seed)
+    parts = _empty()
+    _append(parts, *_caplet_instance(g, M, nK))
+    m = _finish(parts, MODEL_GLOBAL4, formula, residual, 0.5)
+    truth = _global4_truth(g)[None, :]
+    noise = g.normal(0.0, 0.002, m["q_K"].shape[0])
+    return m, truth, noise
+
+
+def batch_markets(n_markets=256, seed=SEED_BASE + 3000, M_range=(10, 40), nK_range=(5, 15)):
+    """Independent caplet markets of uneven size (per-market seeds): M ~ U{10..40},
+    nK ~ U{5..15}, so each holds 50..600 quotes."""
+    parts = _empty()
+    truths, noises = [], []
+    for j in range(n_markets):
+        g = rng(seed + j)
+        M = int(g.integers(M_range[0], M_range[1] + 1))
+        nK = int(g.integers(nK_range[0], nK_range[1] + 1))
+        _append(parts, *_caplet_instance(g, M, nK))
+        truths.append(_global4_truth(g))
+        noises.append(g.normal(0.0, 0.002, M * nK))
+    m = _finish(parts, MODEL_GLOBAL4, FORMULA_HAGAN2002, RESID_VOL, 0.5)
+    return m, np.array(truths), np.concatenate(noises)
+
+
+def _lmm12_truth(g):
+    return np.array([
+        g.uniform(0.01, 0.03), g.uniform(0.0, 0.02), g.uniform(0.5, 1.5), g.uniform(0.02, 0.04),
+        g.uniform(0.1, 0.3), g.uniform(0.0, 0.2), g.uniform(0.5, 1.5), g.uniform(0.2, 0.4),
+        g.uniform(-0.4, 0.0), g.uniform(0.05, 0.3), g.uniform(0.5, 0.9), g.uniform(0.1, 1.0),
+    ])
+
+
+def _moneyness_grid(n, lo=-0.8, hi=0.8):
+    g = np.linspace(lo, hi, n)
+    if n % 2 == 1:
+        g[n // 2] = 0.0          # exact ATM strike
+    return g
+
+
+def _lmm_instance(M, n_cap_K, n_exp, n_ten, n_swp_K, both_sides):
+    T = 0.5 * np.arange(M)
+    tau = np.full(M, 0.5)
+    F = 0.02 + 0.02 * np.arange(M) / (M - 1)
+    P = _curve_discounts(T, tau, F)
+    und_first, und_len = [], []
+    for i in range(1, M):                    # caplets on forwards 1..M-1
+        und_first.append(i)
+        und_len.append(1)
+    for e in range(1, n_exp + 1):            # swaptions: expiry T_e, n periods
+        for n in range(1, n_ten + 1):
+            if e + n - 1 <= M - 1:
+                und_first.append(e)
+                und_len.append(n)
+    und_first = np.array(und_first, np.int32)
+    und_len = np.array(und_len, np.int32)
+    cap_m = _moneyness_grid(n_cap_K)
+    swp_m = _moneyness_grid(n_swp_K)
+    sides = (KIND_CALL, KIND_PUT) if both_sides else (KIND_CALL,)
+    q_und, q_kind, q_K = [], [], []
+    for u in range(len(und_first)):
+        f0, n = und_first[u], und_len[u]
+        # strike centre: the forward itself for a caplet, the plain mean of
+        # the swap's forwards for a swaption (close to, not equal to, S0)
+        centre = F[f0] if n == 1 else float(np.mean(F[f0:f0 + n]))
+        for mny in (cap_m if n == 1 else swp_m):
+            for kind in sides:
+                q_und.append(u)
+                q_kind.append(kind)
+                q_K.append(centre if mny == 0.0 else centre * np.exp(mny))
+    return T, tau, F, P, und_first, und_len, np.array(q_und, np.int32), \
+        np.array(q_kind, np.int32), np.array(q_K)
+
+
+def lmm_market(seed=SEED_BASE + 2000, n_markets=1, M=20, n_cap_K=15, n_exp=10, n_ten=10,
+               n_swp_K=7, both_sides=False, residual=RESID_PRICE, beta=0.5):
+    """LMM12 markets: caplet smiles (n_cap_K strikes) on forwards 1..M-1 and an
+    n_exp x n_ten swaption grid (n_swp_K strikes), strikes K = centre exp(m),
+    m evenly spread over [-0.8, 0.8] (the paper's moneyness range)."""
+    parts = _empty()
+    truths, noises = [], []
+    for j in range(n_markets):
+        g = rng(seed + j)
+        inst = _lmm_instance(M, n_cap_K, n_exp, n_ten, n_swp_K, both_sides)
+        _append(parts, *inst)
+        truths.append(_lmm12_truth(g))
+        noises.append(g.normal(0.0, 0.002, len(inst[-1])))
+    m = _finish(parts, MODEL_LMM12, FORMULA_HAGAN2002, residual, beta)
+    return m, np.array(truths), np.concatenate(noises)
+
+
+def complete_market(market, model_vols, noise):
+    """Market vols = model vols at the true parameters + noise."""
+    m = dict(market)
+    m["q_vol"] = np.ascontiguousarray(np.asarray(model_vols, float) + np.asarray(noise, float))
+    return m
+
+
+def as_vol_market(market):
+    """Same market, vol residuals (used to read model vols)."""
+    m = dict(market)
+    m["residual"] = RESID_VOL
+    return m
+
+
+def random_box_points(model, n, seed, lb=None, ub=None):
+    lb0, ub0 = box(model)
+    lb = lb0 if lb is None else np.asarray(lb, float)
+    ub = ub0 if ub is None else np.asarray(ub, float)
+    g = rng(seed)
+    u = g.random((n, len(lb)))
+    return lb + (ub - lb) * u
+
+
+def n_quotes(market):
+    return np.diff(np.asarray(market["q_off"]))
+
+
+def n_inst(market):
+    return len(market["q_off"]) - 1

@@ -1,0 +1,158 @@
+"""Pins of the oracle's simulated annealing and Levenberg-Marquardt polish."""
+import math
+
+import numpy as np
+import pytest
+from scipy import optimize
+
+from paper_2408_01470_amd import inputs as I
+
+
+def test_paper_eval_count_matches_loop_structure(oracle, c1_market):
+    """Sec. 4.1.1: T0 = 10, Tmin = 0.01, rho = 0.99, N = 10, w = 256 x 64 chains
+    evaluated the cost 112738304 times.  The do-while loop of the SA box runs
+    until T <= Tmin; every chain evaluates x0 once and each step once, and the
+    level-end restart copies the best point without re-evaluating it."""
+    T, levels = 10.0, 0
+    while True:
+        levels += 1
+        T = 0.99 * T
+        if not T > 0.01:
+            break
+    assert levels == 688
+    # the oracle's count for a small run has the same structure C (1 + N L)
+    mk, _ = c1_market
+    lb, ub = I.box(0)
+    r = oracle.sa_calibrate(mk, 7, lb, ub, T0=1.0, cool=0.9, n_levels=3, n_steps=4, seed=2)
+    assert r["n_evals"][0] == 7 * (1 + 4 * 3)
+    assert 256 * 64 * (1 + 10 * levels) == 112738304
+
+
+def _minus_one(ctr):
+    """numpy's Philox adds one to its 256-bit counter before each block."""
+    v = sum(int(w) << (64 * i) for i, w in enumerate(ctr)) - 1
+    v %= 1 << 256
+    return np.array([(v >> (64 * i)) & ((1 << 64) - 1) for i in range(4)], np.uint64)
+
+
+def _python_sa_replay(oracle, mk, C, L, N, T0, cool, seed, step_frac, lb, ub):
+    """The SA loop written out in Python with numpy's Philox (counter
+    pre-incremented by numpy, hence ctr - 1) and the oracle's cost."""
+    P = len(lb)
+    x0 = 0.5 * (lb + ub)
+    X = np.tile(x0, (C, 1))
+    F = np.full(C, oracle.cost_batch(mk, x0)[0])
+    acc_all = []
+    best = []
+    T = T0
+    for l in range(L):
+        for s in range(N):
+            flags = []
+            for c in range(C):
+                u = []
+                for b in range((P + 1 + 3) // 4):
+                    bg = np.random.Philox(counter=_minus_one([l * N + s, c, b, 0]),
+                                          key=np.array([seed, 0], np.uint64))
+                    u += [(int(bg.random_raw()) >> 11) * 2.0 ** -53 for _ in range(4)]
+                xp = X[c] + step_frac * (ub - lb) * (2 * np.array(u[:P]) - 1)
+                xp = np.where(xp > ub, 2 * ub - xp, xp)
+                xp = np.where(xp < lb, 2 * lb - xp, xp)
+                xp = np.clip(xp, lb, ub)
+                fp = oracle.cost_batch(mk, xp)[0]
+                dE = fp - F[c]
+                a = dE <= 0 or u[P] < math.exp(-dE / T)
+                if a:
+                    X[c], F[c] = xp, fp
+                flags.append(a)
+            acc_all.append(flags)
+        b = int(np.argmin(F))
+        best.append(b)
+        X[:] = X[b]
+        F[:] = F[b]
+        T = cool * T
+    return np.array(acc_all, np.uint8).reshape(-1), np.array(best)
+
+
+def test_sa_loop_replay_with_library_philox(oracle, c1_market):
+    mk, _ = c1_market
+    lb, ub = I.box(0)
+    C, L, N = 3, 3, 4
+    acc, best = _python_sa_replay(oracle, mk, C, L, N, 0.05, 0.5, 99, 0.05, lb, ub)
+    r = oracle.sa_calibrate(mk, C, lb, ub, T0=0.05, cool=0.5, n_levels=L, n_steps=N, seed=99,
+                            record=True)
+    assert np.array_equal(r["accept"], acc)
+    assert np.array_equal(r["level_best"][0], best)
+    assert 0 < acc.sum() < acc.size
+
+
+def test_sa_deterministic_and_restart_semantics(oracle, c1_market):
+    mk, _ = c1_market
+    lb, ub = I.box(0)
+    kw = dict(T0=0.05, cool=0.8, n_levels=6, n_steps=20, seed=5, record=True)
+    a = oracle.sa_calibrate(mk, 16, lb, ub, **kw)
+    b = oracle.sa_calibrate(mk, 16, lb, ub, **kw)
+    for k in ("best_x", "best_f", "accept", "trace", "chain_best_f"):
+        assert np.array_equal(a[k], b[k])
+    # best ever is the minimum of the per-chain bests, and the trace is monotone
+    assert a["best_f"][0] == a["chain_best_f"].min()
+    assert np.all(np.diff(a["trace"][0, :, 0]) <= 0)
+    acc = a["accept"].reshape(6, 20, 16)
+    np.testing.assert_allclose(acc.mean(axis=(1, 2)), a["trace"][0, :, 1])
+    # different seed, different path
+    c = oracle.sa_calibrate(mk, 16, lb, ub, **dict(kw, seed=6))
+    assert not np.array_equal(a["accept"], c["accept"])
+
+
+def test_sa_and_lm_beat_brute_force_grid_on_two_parameter_toy(oracle, c1_market):
+    """beta and rho fixed at their true values (lb = ub); a 401 x 401 grid over
+    (alpha, nu) bounds the global minimum; SA must reach the grid minimum and
+    LM from the grid argmin converges to the continuous minimum below it."""
+    mk, truth = c1_market
+    lb, ub = I.box(0)
+    lb, ub = lb.copy(), ub.copy()
+    lb[1] = ub[1] = truth[0, 1]
+    lb[2] = ub[2] = truth[0, 2]
+    al = np.linspace(lb[0], ub[0], 401)
+    nu = np.linspace(lb[3], ub[3], 401)
+    A, Nn = np.meshgrid(al, nu, indexing="ij")
+    pts = np.stack([A.ravel(), np.full(A.size, lb[1]), np.full(A.size, lb[2]), Nn.ravel()], 1)
+    cost = oracle.cost_batch(mk, pts)
+    gmin = np.nanmin(cost)
+    r = oracle.sa_calibrate(mk, 32, lb, ub, T0=0.05, cool=0.9, n_levels=60, n_steps=25, seed=3)
+    assert r["best_f"][0] <= gmin * (1 + 1e-6)
+    x, f, it = oracle.lm_polish(mk, pts[np.nanargmin(cost)], None, lb, ub)
+    assert f[0] <= gmin
+    x2, f2, _ = oracle.lm_polish(mk, r["best_x"], None, lb, ub)
+    assert f2[0] == pytest.approx(f[0], rel=1e-8)
+    np.testing.assert_allclose(x2[0], x[0], rtol=1e-5)
+
+
+def test_lm_matches_scipy_on_unconstrained_toy(oracle, c1_market):
+    """With an inactive box, projected LM is plain LM: it reaches the local
+    minimum scipy's MINPACK LM reaches from the same start."""
+    mk, truth = c1_market
+    lb = np.array([1e-4, 0.0, -0.999, 1e-4])
+    ub = np.array([1.0, 1.0, 0.999, 5.0])
+    lb[1] = ub[1] = 0.5                      # fix beta, free alpha, rho, nu
+    start = truth[0] * np.array([1.3, 1.0, 0.7, 0.8])
+    x, f, it = oracle.lm_polish(mk, start, None, lb, ub, max_iter=200, tol=1e-15)
+
+    def resid(q):
+        p = np.array([q[0], 0.5, q[1], q[2]])
+        _, r = oracle.cost_batch(mk, p, resid=True)
+        return r[0]
+
+    sol = optimize.least_squares(resid, start[[0, 2, 3]], method="lm", xtol=1e-15, ftol=1e-15,
+                                 gtol=1e-15)
+    assert f[0] == pytest.approx(2 * sol.cost, rel=1e-9)
+    np.testing.assert_allclose(x[0, [0, 2, 3]], sol.x, rtol=1e-5)
+
+
+def test_lm_decreases_cost(oracle, c2_market):
+    mk, truth = c2_market
+    lb, ub = I.box(1)
+    start = np.clip(truth[0] * 1.1, lb, ub)
+    f0 = oracle.cost_batch(mk, start)[0]
+    x, f, it = oracle.lm_polish(mk, start, None, lb, ub, max_iter=15)
+    assert f[0] < f0
+    assert np.all(x >= lb) and np.all(x <= ub)
