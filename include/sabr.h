@@ -1,0 +1,196 @@
+/*
+ * sabr.h -- C ABI of the MI355X (gfx950) simulated-annealing calibrator of
+ * SABR/LIBOR market models to caplet and swaption quotes.
+ *
+ * Method: Ferreiro, Garcia, Lopez-Salas, Vazquez, "SABR/LIBOR market models:
+ * pricing and calibration for some interest rate derivatives"
+ * (arXiv 2408.01470).  The library minimises the weighted quote cost
+ *     f(p) = sum_q w_q (m_q(p) - mkt_q)^2
+ * (the caplet cost f_c and swaption cost f_s of Sec. 3, with weights) over a
+ * box by synchronous parallel simulated annealing (Sec. 3: the boxed SA loop
+ * T <- rho T, N Metropolis steps per level, all chains restarted at the best
+ * final point of each level), where m_q is the Hagan implied vol of quote q
+ * (Sec. 2.1, eq. (sigmaHagan), or the full Hagan 2002 lognormal expansion the
+ * paper cites) or its Black-76 price.
+ *
+ * Conventions
+ *  - Market data enter once, as HOST arrays, through sabr_plan_create (which
+ *    validates everything before any GPU work) and sabr_plan_upload (which
+ *    copies a packed image into caller-owned DEVICE memory).
+ *  - Every other array argument is DEVICE memory owned by the caller unless
+ *    marked [host].  The library never frees or retains caller pointers
+ *    beyond the plan's device image (valid until the plan is destroyed or
+ *    re-uploaded).
+ *  - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL
+ *    = default stream); results are valid after the stream is synchronised.
+ *  - Return values: SABR_OK, or a negative sabr_status; sabr_last_error()
+ *    gives a thread-local message.  Invalid arguments are reported before
+ *    anything is enqueued.
+ *  - Domain failures are not errors: a point whose parameters leave the
+ *    model's domain (alpha <= 0, |rho| >= 1, nu < 0, a model vol that is not
+ *    finite and positive, ...) gets cost +inf.
+ *  - All arithmetic is IEEE FP64.
+ */
+#ifndef SABR_H
+#define SABR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SABR_OK = 0,
+  SABR_EINVAL = -1,        /* invalid argument or market data */
+  SABR_ENOMEM = -2,        /* host allocation failed */
+  SABR_EHIP = -3,          /* HIP runtime error */
+  SABR_EUNSUPPORTED = -4,  /* combination not supported */
+  SABR_EWORKSPACE = -5     /* device buffer too small */
+} sabr_status;
+
+/* Parameter layouts.
+ *  GLOBAL4: p = (alpha, beta, rho, nu) shared by every forward (the Hagan
+ *           model with common parameters: x = (phi_ii, sigma_i, alpha_i) of
+ *           Sec. 3 with phi_ii = rho, sigma_i = nu).  Caplet markets only.
+ *  LMM12:   p = (a, b, c, d, a_nu, b_nu, c_nu, d_nu, rho, lambda1, eta2,
+ *           lambda2), beta fixed (sabr_problem.beta):
+ *             alpha_i = (a + b T_i) exp(-c T_i) + d   (abcd form, Sec. 2.3)
+ *             nu_i    = (a_nu + b_nu T_i) exp(-c_nu T_i) + d_nu
+ *             phi_ii = rho, rho_ij = exp(-lambda1 |T_i - T_j|)  (eq. (rhoij), eta1 = 0)
+ *             theta_ij = eta2 + (1 - eta2) exp(-lambda2 |T_i - T_j|)  (eq. (thetaij))
+ *             phi_ij = rho  (eq. (phiij), lambda3 = 0).
+ *           A swaption on forwards [e, e+n) gets SABR parameters from a
+ *           first-order freeze of dS = sum_k w_k dF_k at t = 0 (the paper
+ *           prices swaptions by Monte Carlo; this closed-form map replaces it):
+ *             u_k = w_k F_k^beta, a_k = u_k alpha_k, R_k = sum_l a_l rho_kl,
+ *             V = sum_k a_k R_k, alpha_S = sqrt(V) / S0^beta,
+ *             c_k = a_k R_k / V, nu_S^2 = sum_kl c_k c_l nu_k nu_l theta_kl,
+ *             rho_S = sum_kl a_k c_l nu_l phi_kl / (alpha_S S0^beta nu_S). */
+typedef enum { SABR_MODEL_GLOBAL4 = 0, SABR_MODEL_LMM12 = 1 } sabr_model;
+
+/* Implied-vol formula.
+ *  HAGAN2002: L = ln(f/K), q = (fK)^((1-beta)/2), z = (nu/alpha) q L,
+ *    sigma = alpha/(q D1) * z/x(z) * [1 + ((1-beta)^2 alpha^2/(24 q^2)
+ *            + rho beta nu alpha/(4q) + (2 - 3 rho^2) nu^2/24) T],
+ *    x(z) = ln((sqrt(1 - 2 rho z + z^2) + z - rho)/(1 - rho)),
+ *    D1 = 1 + (1-beta)^2 L^2/24 + (1-beta)^4 L^4/1920.
+ *  PAPER_EQ3: eq. (sigmaHagan) of Sec. 2.1 exactly as printed (second order
+ *    in ln(K/f), no expiry dependence). */
+typedef enum { SABR_VOL_HAGAN2002 = 0, SABR_VOL_PAPER_EQ3 = 1 } sabr_vol_formula;
+
+/* Residual: model vol minus market vol, or Black-76 price minus the Black
+ * price of the market vol (weight divided by the market vega squared). */
+typedef enum { SABR_RES_VOL = 0, SABR_RES_PRICE = 1 } sabr_residual;
+
+/* Quote kinds: call (caplet, payer swaption) or put (floorlet, receiver). */
+typedef enum { SABR_Q_CALL = 0, SABR_Q_PUT = 1 } sabr_quote_kind;
+
+/* A CSR batch of n_inst independent markets (instances), all [host].
+ * Instance i owns forwards [fwd_off[i], fwd_off[i+1]), underlyings
+ * [und_off[i], und_off[i+1]) and quotes [q_off[i], q_off[i+1]).  Indices
+ * stored in und_first and q_und are local to the instance.  An underlying is
+ * the swap over forwards [first, first+len): len = 1 is a caplet on that
+ * forward, with expiry T_first, annuity A = sum tau_k P_k, weights
+ * w_k = tau_k P_k / A and swap rate S0 = sum w_k F_k.  Quotes must be sorted
+ * by underlying within each instance. */
+typedef struct {
+  int32_t n_inst;
+  const int32_t *fwd_off;                         /* [n_inst+1] */
+  const double *fwd_T, *fwd_tau, *fwd_F, *fwd_P;  /* fixing, accrual, F(0), P(0, T+tau) */
+  const int32_t *und_off;                         /* [n_inst+1] */
+  const int32_t *und_first, *und_len;
+  const int32_t *q_off;                           /* [n_inst+1] */
+  const int32_t *q_und, *q_kind;
+  const double *q_K, *q_vol, *q_w;                /* strike, market implied vol, weight */
+  int32_t model, vol_formula, residual;
+  double beta;                                    /* fixed beta for LMM12, in [0, 1] */
+} sabr_problem;
+
+typedef struct sabr_plan sabr_plan; /* opaque; host memory only */
+
+/* Validate the market (offsets monotone and in range, positive finite
+ * forwards, strikes, accruals, discounts and vols, non-negative weights,
+ * positive expiries, quotes sorted by underlying, GLOBAL4 without swaps) and
+ * build its packed image.  On success *out owns host memory only. */
+sabr_status sabr_plan_create(const sabr_problem *prob /*[host]*/, sabr_plan **out /*[host]*/);
+void sabr_plan_destroy(sabr_plan *plan);
+
+/* Bytes of device memory the plan's image needs (256-byte aligned blocks). */
+size_t sabr_plan_device_bytes(const sabr_plan *plan);
+
+/* Copy the image into dev_buf (device, >= sabr_plan_device_bytes) and run the
+ * market precompute kernel (logs, square roots, fixed-beta powers, Black
+ * market prices and vegas in price mode).  The plan keeps dev_buf. */
+sabr_status sabr_plan_upload(sabr_plan *plan, void *dev_buf, size_t bytes, void *stream);
+
+int32_t sabr_num_params(int32_t model);             /* 4 or 12; -1 if unknown */
+int32_t sabr_plan_num_params(const sabr_plan *plan);
+int32_t sabr_plan_num_inst(const sabr_plan *plan);
+int32_t sabr_plan_max_quotes(const sabr_plan *plan); /* largest quotes per instance */
+
+/* Swap rate S0, annuity A and expiry T of every underlying [host out,
+ * concatenated over instances in CSR order]. */
+sabr_status sabr_plan_underlyings(const sabr_plan *plan, double *S0, double *A, double *T);
+
+/* Cost of n_pts points: point i belongs to instance pt_inst[i] and has
+ * parameters params[i*P .. i*P+P).  cost[i] = sum_q w_q (m_q - mkt_q)^2 over
+ * that instance's quotes, +inf on a domain failure, NaN if pt_inst[i] is out
+ * of range.  resid (nullable) receives r_q = m_q - mkt_q at
+ * resid[i*stride + q]; model (nullable) receives m_q (vol or price, per the
+ * residual mode) at model[i*stride + q].  stride >= max quotes per instance
+ * when either is given.  (Sec. 3, f_c and f_s.) */
+sabr_status sabr_cost_batch(const sabr_plan *plan, int32_t n_pts, const int32_t *pt_inst,
+                            const double *params, double *cost, double *resid, double *model,
+                            int32_t stride, void *stream);
+
+/* Annealing schedule and options (Sec. 3 boxed SA loop: T_0 = T0,
+ * T_{l+1} = cool * T_l by FP64 multiplication, N = n_steps Metropolis steps
+ * per level, n_levels levels). */
+typedef struct {
+  double T0;             /* initial temperature (> 0) */
+  double cool;           /* cooling factor in (0, 1] */
+  double step_frac;      /* neighbour half-width as a fraction of (ub - lb), (0, 1] */
+  int32_t n_levels;      /* L >= 0 */
+  int32_t n_steps;       /* N >= 0 */
+  uint64_t seed;         /* Philox key word 0; key word 1 = instance index */
+  const double *T0_per_inst; /* [host] nullable [n_inst] per-instance T0 */
+  int32_t waves_per_group;   /* chains per workgroup (0 = library default) */
+  int32_t use_graph;         /* 1: capture the launch sequence in a hipGraph and replay it */
+} sa_config;
+
+/* Device workspace bytes sa_calibrate needs for these chain counts. */
+size_t sa_workspace_size(const sabr_plan *plan, const sa_config *cfg /*[host]*/,
+                         const int32_t *chains /*[host][n_inst]*/);
+
+/* Synchronous parallel simulated annealing on every instance at once.
+ * Instance i runs chains[i] >= 1 Markov chains in the box [lb, ub]
+ * ([host][n_inst][P], lb <= ub) from x0 ([host] nullable -> box midpoint).
+ * Step s of level l of chain c of instance i draws u_0..u_P from
+ * Philox4x64-10 with counter (l N + s, c, b, 0) and key (seed, i), block b =
+ * 0, 1, ..., word j of the concatenation, u = (word >> 11) 2^-53; the
+ * proposal is x'_k = x_k + step_frac (ub_k - lb_k)(2 u_k - 1) mirrored into
+ * the box then clamped; it is accepted iff f' - f <= 0 or
+ * u_P < exp(-(f' - f)/T_l).  At each level end every chain restarts at the
+ * final point of lowest cost (ties -> lowest chain index).
+ * Outputs (device): best_x [n_inst][P], best_f [n_inst] = best point ever
+ * evaluated; nullable: chain_best_x [sum chains][P] / chain_best_f [sum
+ * chains] (per-chain best ever), accept [sum_i L N chains[i]] bytes in
+ * (instance, level, step, chain) order, level_trace [n_inst][L][3] =
+ * {best-ever f, acceptance rate, ns since start}, level_best [n_inst][L] =
+ * restart chain of each level.  Cost evaluations: chains[i] (1 + N L). */
+sabr_status sa_calibrate(const sabr_plan *plan, const sa_config *cfg /*[host]*/,
+                         const int32_t *chains /*[host]*/, const double *lb /*[host]*/,
+                         const double *ub /*[host]*/, const double *x0 /*[host] nullable*/,
+                         double *best_x, double *best_f, double *chain_best_x,
+                         double *chain_best_f, uint8_t *accept, double *level_trace,
+                         int32_t *level_best, void *workspace, size_t ws_bytes, void *stream);
+
+/* Last error message of the calling thread ("" if none). */
+const char *sabr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SABR_H */

@@ -201,14 +201,20 @@ S paper_eq3_vol(double f, double K, const S &alpha, const S &beta, const S &rho,
 template <class S>
 S norm_cdf(const S &x) { return 0.5 * erfc(-x / std::sqrt(2.0)); }
 
+// Out-of-the-money side: the call when K >= f, else the put.
 template <class S>
-S black_price(int kind, double f, double K, double T, const S &sigma, double D) {
+S black_otm(double f, double K, double T, const S &sigma, double D) {
   S sd = sigma * std::sqrt(T);
   S d1 = (log(f / K) + 0.5 * sigma * sigma * T) / sd;
   S d2 = d1 - sd;
+  return (K >= f) ? D * (f * norm_cdf(d1) - K * norm_cdf(d2))
+                  : D * (K * norm_cdf(-d2) - f * norm_cdf(-d1));
+}
+
+template <class S>
+S black_price(int kind, double f, double K, double T, const S &sigma, double D) {
+  S v = black_otm(f, K, T, sigma, D);
   const bool otm_call = K >= f;
-  S v = otm_call ? D * (f * norm_cdf(d1) - K * norm_cdf(d2))
-                 : D * (K * norm_cdf(-d2) - f * norm_cdf(-d1));
   const bool want_call = (kind == 0);
   if (want_call == otm_call) return v;
   return want_call ? v + D * (f - K) : v + D * (K - f);
@@ -237,7 +243,8 @@ struct Und {
 struct Quote {
   int und, kind;
   double K, vol, w;
-  double target, weight;  // what the residual is measured against, and its weight
+  double target, weight;  // market value of the quoted instrument, weight
+  double target_otm;      // price mode: market price of the out-of-the-money side
 };
 struct Inst {
   int model, formula, residual;
@@ -316,6 +323,7 @@ int32_t build_inst(const oracle_market *m, int i, Inst &I) {
       // Price residuals: market price from Black at the market vol; weight
       // divided by vega^2 so the cost is close to vol units.
       Q.target = black_price<double>(Q.kind, U.S0, Q.K, U.Te, Q.vol, U.A);
+      Q.target_otm = black_otm<double>(U.S0, Q.K, U.Te, Q.vol, U.A);
       const double vg = black_vega(U.S0, Q.K, U.Te, Q.vol, U.A);
       if (!finite_pos(vg)) return fail("zero market vega");
       Q.weight = Q.w / (vg * vg);
@@ -424,13 +432,17 @@ bool map_params(const Inst &I, const S *p, std::vector<Theta<S>> &th) {
   return true;
 }
 
-// Model value of every quote (vol or Black price); false on domain failure
-// (model vol not finite and positive, or price not finite).
+// Model value of every quote (vol or Black price of the quoted instrument)
+// and its residual r_q = m_q - mkt_q; false on domain failure (model vol not
+// finite and positive, or price not finite).  In price mode the residual is
+// taken between the out-of-the-money sides: by put-call parity it equals the
+// quoted side's difference exactly, without cancelling the intrinsic value.
 template <class S>
-bool model_values(const Inst &I, const S *p, std::vector<S> &mv) {
+bool model_values(const Inst &I, const S *p, std::vector<S> &mv, std::vector<S> &rv) {
   std::vector<Theta<S>> th;
   if (!map_params(I, p, th)) return false;
   mv.assign(I.q.size(), S(0.0));
+  rv.assign(I.q.size(), S(0.0));
   for (size_t k = 0; k < I.q.size(); ++k) {
     const Quote &Q = I.q[k];
     const Und &U = I.u[Q.und];
@@ -438,9 +450,14 @@ bool model_values(const Inst &I, const S *p, std::vector<S> &mv) {
     S sig = (I.formula == 0) ? hagan2002_vol(U.S0, Q.K, U.Te, t.alpha, t.beta, t.rho, t.nu)
                              : paper_eq3_vol(U.S0, Q.K, t.alpha, t.beta, t.rho, t.nu);
     if (!(std::isfinite(val(sig)) && val(sig) > 0.0)) return false;
-    S m = (I.residual == 0) ? sig : black_price(Q.kind, U.S0, Q.K, U.Te, sig, U.A);
-    if (!std::isfinite(val(m))) return false;
-    mv[k] = m;
+    if (I.residual == 0) {
+      mv[k] = sig;
+      rv[k] = sig - Q.target;
+    } else {
+      mv[k] = black_price(Q.kind, U.S0, Q.K, U.Te, sig, U.A);
+      rv[k] = black_otm(U.S0, Q.K, U.Te, sig, U.A) - Q.target_otm;
+    }
+    if (!std::isfinite(val(mv[k])) || !std::isfinite(val(rv[k]))) return false;
   }
   return true;
 }
@@ -449,15 +466,15 @@ bool model_values(const Inst &I, const S *p, std::vector<S> &mv) {
 // +inf on a domain failure or a non-finite sum.
 template <class S>
 S cost_point(const Inst &I, const S *p, double *resid) {
-  std::vector<S> mv;
-  if (!model_values(I, p, mv)) {
+  std::vector<S> mv, rv;
+  if (!model_values(I, p, mv, rv)) {
     if (resid)
       for (size_t k = 0; k < I.q.size(); ++k) resid[k] = std::nan("");
     return S(kInf);
   }
   S f(0.0);
   for (size_t k = 0; k < I.q.size(); ++k) {
-    S r = mv[k] - I.q[k].target;
+    const S &r = rv[k];
     if (resid) resid[k] = val(r);
     f += I.q[k].weight * r * r;
   }
@@ -565,15 +582,15 @@ bool residual_jacobian(const Inst &I, const double *p, std::vector<double> &r,
     pd[k] = Dual<P>(p[k]);
     pd[k].d[k] = 1.0;
   }
-  std::vector<Dual<P>> mv;
+  std::vector<Dual<P>> mv, rv;
   const size_t nq = I.q.size();
   r.assign(nq, 0.0);
   J.assign(nq * P, 0.0);
-  if (!model_values(I, pd.data(), mv)) return false;
+  if (!model_values(I, pd.data(), mv, rv)) return false;
   f = 0.0;
   for (size_t q = 0; q < nq; ++q) {
-    r[q] = mv[q].v - I.q[q].target;
-    for (int k = 0; k < P; ++k) J[q * P + k] = mv[q].d[k];
+    r[q] = rv[q].v;
+    for (int k = 0; k < P; ++k) J[q * P + k] = rv[q].d[k];
     f += I.q[q].weight * r[q] * r[q];
   }
   return std::isfinite(f);
@@ -730,8 +747,8 @@ int32_t oracle_model_values(const oracle_market *m, int32_t inst, const double *
                             double *model, double *target, double *weight) {
   Inst I;
   if (build_inst(m, inst, I)) return -1;
-  std::vector<double> mv;
-  const bool ok = model_values(I, p, mv);
+  std::vector<double> mv, rv;
+  const bool ok = model_values(I, p, mv, rv);
   for (size_t q = 0; q < I.q.size(); ++q) {
     if (model) model[q] = ok ? mv[q] : std::nan("");
     if (target) target[q] = I.q[q].target;

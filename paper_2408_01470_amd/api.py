@@ -1,0 +1,174 @@
+"""Python front end of the HIP calibrator: torch tensors in, torch tensors out.
+
+Argument marshalling only -- every step of the calibration runs in the HIP
+kernels behind the C ABI (include/sabr.h).  PyTorch supplies device memory and
+streams.  There is no CPU fallback: without the built library or a GPU these
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import SAConfig, SabrProblem, check, lib
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("the HIP calibrator needs a GPU (no CPU fallback)")
+
+
+class Plan:
+    """A validated market batch uploaded to device memory."""
+
+    def __init__(self, market: dict, device: str = "cuda", stream=None):
+        _require_gpu()
+        L = lib()
+        self.device = torch.device(device)
+        self._keep = {}
+        for k in ("fwd_off", "und_off", "q_off", "und_first", "und_len", "q_und", "q_kind"):
+            self._keep[k] = np.ascontiguousarray(market[k], dtype=np.int32)
+        for k in ("fwd_T", "fwd_tau", "fwd_F", "fwd_P", "q_K", "q_vol", "q_w"):
+            self._keep[k] = np.ascontiguousarray(market[k], dtype=np.float64)
+        a = self._keep
+        p = lambda k, t: a[k].ctypes.data_as(t)
+        self._prob = SabrProblem(
+            len(a["q_off"]) - 1,
+            p("fwd_off", _i32p), p("fwd_T", _f64p), p("fwd_tau", _f64p), p("fwd_F", _f64p),
+            p("fwd_P", _f64p), p("und_off", _i32p), p("und_first", _i32p), p("und_len", _i32p),
+            p("q_off", _i32p), p("q_und", _i32p), p("q_kind", _i32p), p("q_K", _f64p),
+            p("q_vol", _f64p), p("q_w", _f64p), int(market["model"]), int(market["formula"]),
+            int(market["residual"]), float(market["beta"]))
+        h = ctypes.c_void_p()
+        check(L.sabr_plan_create(ctypes.byref(self._prob), ctypes.byref(h)))
+        self._h = h
+        self.model = int(market["model"])
+        self.P = int(L.sabr_plan_num_params(h))
+        self.n_inst = int(L.sabr_plan_num_inst(h))
+        self.max_q = int(L.sabr_plan_max_quotes(h))
+        self.nq = np.diff(a["q_off"])
+        nbytes = int(L.sabr_plan_device_bytes(h))
+        self._dev = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        check(L.sabr_plan_upload(h, _ptr(self._dev), nbytes, _stream(stream)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib._lib is not None:
+            _lib._lib.sabr_plan_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------------
+    def underlyings(self):
+        n = int(self._keep["und_off"][-1])
+        S0, A, T = np.zeros(n), np.zeros(n), np.zeros(n)
+        check(lib().sabr_plan_underlyings(self._h, S0.ctypes.data_as(_f64p),
+                                          A.ctypes.data_as(_f64p), T.ctypes.data_as(_f64p)))
+        return S0, A, T
+
+    def _pts(self, params, pt_inst):
+        params = torch.as_tensor(params, dtype=torch.float64, device=self.device)
+        params = params.reshape(-1, self.P).contiguous()
+        n = params.shape[0]
+        if pt_inst is None:
+            pt_inst = torch.zeros(n, dtype=torch.int32, device=self.device)
+        else:
+            pt_inst = torch.as_tensor(pt_inst, dtype=torch.int32, device=self.device).contiguous()
+        return params, pt_inst, n
+
+    def cost(self, params, pt_inst=None, resid=False, model=False, stream=None):
+        """cost[n] (and optionally resid[n, max_q], model[n, max_q])."""
+        params, pt_inst, n = self._pts(params, pt_inst)
+        cost = torch.empty(n, dtype=torch.float64, device=self.device)
+        r = torch.full((n, self.max_q), float("nan"), dtype=torch.float64,
+                       device=self.device) if resid else None
+        m = torch.full((n, self.max_q), float("nan"), dtype=torch.float64,
+                       device=self.device) if model else None
+        check(lib().sabr_cost_batch(self._h, n, _ptr(pt_inst), _ptr(params), _ptr(cost), _ptr(r),
+                                    _ptr(m), self.max_q, _stream(stream)))
+        out = [cost]
+        if resid:
+            out.append(r)
+        if model:
+            out.append(m)
+        return out[0] if len(out) == 1 else tuple(out)
+
+    # ------------------------------------------------------------------
+    def sa_config(self, T0, cool, n_levels, n_steps, seed, step_frac=0.05, T0_per_inst=None,
+                  waves=0, use_graph=False):
+        t0i = None
+        if T0_per_inst is not None:
+            t0i = np.ascontiguousarray(T0_per_inst, dtype=np.float64)
+            self._keep["_t0i"] = t0i
+        return SAConfig(float(T0), float(cool), float(step_frac), int(n_levels), int(n_steps),
+                        int(seed), t0i.ctypes.data_as(_f64p) if t0i is not None else None,
+                        int(waves), 1 if use_graph else 0)
+
+    def sa_workspace_bytes(self, cfg, chains):
+        ch = np.ascontiguousarray(np.broadcast_to(chains, (self.n_inst,)), dtype=np.int32)
+        return int(lib().sa_workspace_size(self._h, ctypes.byref(cfg), ch.ctypes.data_as(_i32p)))
+
+    def _sa_outputs(self, tot, n_levels, n_steps, record, trace, chain_best):
+        n, P, dev = self.n_inst, self.P, self.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        return dict(
+            best_x=torch.empty((n, P), **f64),
+            best_f=torch.empty(n, **f64),
+            chain_best_x=torch.empty((tot, P), **f64) if chain_best else None,
+            chain_best_f=torch.empty(tot, **f64) if chain_best else None,
+            accept=torch.empty(int(n_levels) * int(n_steps) * tot, dtype=torch.uint8,
+                               device=dev) if record else None,
+            trace=torch.zeros((n, int(n_levels), 3), **f64) if trace else None,
+            level_best=torch.empty((n, int(n_levels)), dtype=torch.int32, device=dev)
+            if record else None,
+        )
+
+    def sa(self, chains, lb, ub, T0, cool, n_levels, n_steps, seed, step_frac=0.05, x0=None,
+           T0_per_inst=None, record=False, trace=True, chain_best=False, waves=0,
+           use_graph=False, stream=None, workspace=None, out=None):
+        """Synchronous parallel simulated annealing on every instance.  ``out``
+        (a dict returned by an earlier call with the same shapes) reuses its
+        output tensors, so a captured graph can be replayed."""
+        L = lib()
+        n, P = self.n_inst, self.P
+        cfg = self.sa_config(T0, cool, n_levels, n_steps, seed, step_frac, T0_per_inst, waves,
+                             use_graph)
+        ch = np.ascontiguousarray(np.broadcast_to(chains, (n,)), dtype=np.int32)
+        lb = np.ascontiguousarray(np.broadcast_to(lb, (n, P)), dtype=np.float64)
+        ub = np.ascontiguousarray(np.broadcast_to(ub, (n, P)), dtype=np.float64)
+        x0a = None if x0 is None else np.ascontiguousarray(np.broadcast_to(x0, (n, P)),
+                                                           dtype=np.float64)
+        ws = int(L.sa_workspace_size(self._h, ctypes.byref(cfg), ch.ctypes.data_as(_i32p)))
+        if ws == 0:
+            check(-1 if L.sabr_last_error() else 0)
+            raise _lib.SabrError("sa_workspace_size: " + L.sabr_last_error().decode())
+        if workspace is None or workspace.numel() < ws:
+            workspace = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        tot = int(ch.sum())
+        out = dict(out) if out is not None else self._sa_outputs(tot, n_levels, n_steps,
+                                                                  record, trace, chain_best)
+        o = out
+        check(L.sa_calibrate(self._h, ctypes.byref(cfg), ch.ctypes.data_as(_i32p),
+                             lb.ctypes.data_as(_f64p), ub.ctypes.data_as(_f64p),
+                             x0a.ctypes.data_as(_f64p) if x0a is not None else None,
+                             _ptr(o["best_x"]), _ptr(o["best_f"]), _ptr(o["chain_best_x"]),
+                             _ptr(o["chain_best_f"]), _ptr(o["accept"]), _ptr(o["trace"]),
+                             _ptr(o["level_best"]), _ptr(workspace), workspace.numel(),
+                             _stream(stream)))
+        out["workspace"] = workspace
+        out["n_evals"] = ch.astype(np.int64) * (1 + int(n_steps) * int(n_levels))
+        return out

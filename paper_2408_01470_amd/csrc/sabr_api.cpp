@@ -1,0 +1,582 @@
+// sabr_api.cpp -- C ABI of the SA calibrator (see include/sabr.h): host-side
+// validation, packed device image, workspace layout, launch sequence and the
+// hipGraph replay cache.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sabr.h"
+#include "sabr_internal.hpp"
+
+using sabr::DevInst;
+using sabr::DevMarket;
+
+namespace {
+
+thread_local std::string g_err;
+
+sabr_status fail(sabr_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+sabr_status hip_fail(hipError_t e, const char *what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return SABR_EHIP;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Bump allocator over one device buffer: every block is 256-byte aligned.
+struct Layout {
+  size_t off = 0;
+  template <class T>
+  size_t take(size_t n) {
+    const size_t o = off;
+    off = align256(off + n * sizeof(T));
+    return o;
+  }
+};
+
+}  // namespace
+
+struct sabr_plan {
+  int n_inst = 0, model = 0, formula = 0, residual = 0;
+  double beta = 0.5;
+  int nF = 0, nU = 0, nQ = 0;
+  int max_nq = 0, max_nu = 0, max_nf = 0, max_len = 0;
+  // host copies of the uploaded arrays
+  std::vector<DevInst> inst;
+  std::vector<double> f_T, f_tauP, f_F;
+  std::vector<int> u_first, u_len;
+  std::vector<double> u_S0, u_A, u_invA, u_T;
+  std::vector<int> q_und, q_kind;
+  std::vector<double> q_f, q_K, q_T, q_D, q_vol, q_wuser;
+  // device image offsets
+  size_t o_inst, o_fT, o_ftauP, o_fF, o_ufirst, o_ulen, o_uS0, o_uA, o_uinvA, o_qund, o_qkind,
+      o_qf, o_qK, o_qT, o_qD, o_qvol, o_qwuser;  // uploaded (contiguous prefix)
+  size_t upload_bytes = 0;
+  size_t o_fv, o_uS0b, o_qsqrtT, o_qL, o_qlfk, o_qlnf, o_qqfix, o_qD1fix, o_qfpfix, o_qtgt, o_qw;
+  size_t total_bytes = 0;
+  std::vector<unsigned char> staging;
+  char *dev = nullptr;
+  DevMarket dm{};
+  // SA state reused across calls
+  std::vector<unsigned char> sa_staging;
+  std::mutex mu;
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<uint64_t> graph_key;
+  ~sabr_plan() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+  }
+};
+
+extern "C" {
+
+const char *sabr_last_error(void) { return g_err.c_str(); }
+
+int32_t sabr_num_params(int32_t model) { return model == 0 ? 4 : (model == 1 ? 12 : -1); }
+
+sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
+  if (!pr || !out) return fail(SABR_EINVAL, "null argument");
+  *out = nullptr;
+  if (pr->n_inst < 1) return fail(SABR_EINVAL, "n_inst must be >= 1");
+  if (pr->model < 0 || pr->model > 1) return fail(SABR_EINVAL, "unknown model");
+  if (pr->vol_formula < 0 || pr->vol_formula > 1) return fail(SABR_EINVAL, "unknown formula");
+  if (pr->residual < 0 || pr->residual > 1) return fail(SABR_EINVAL, "unknown residual mode");
+  if (!(pr->beta >= 0.0 && pr->beta <= 1.0)) return fail(SABR_EINVAL, "beta outside [0, 1]");
+  if (!pr->fwd_off || !pr->und_off || !pr->q_off || !pr->fwd_T || !pr->fwd_tau || !pr->fwd_F ||
+      !pr->fwd_P || !pr->und_first || !pr->und_len || !pr->q_und || !pr->q_kind || !pr->q_K ||
+      !pr->q_vol || !pr->q_w)
+    return fail(SABR_EINVAL, "null market array");
+  const int n = pr->n_inst;
+  for (const int32_t *off : {pr->fwd_off, pr->und_off, pr->q_off}) {
+    if (off[0] != 0) return fail(SABR_EINVAL, "CSR offsets must start at 0");
+    for (int i = 0; i < n; ++i)
+      if (off[i + 1] < off[i]) return fail(SABR_EINVAL, "CSR offsets not monotone");
+  }
+  sabr_plan *P = new (std::nothrow) sabr_plan;
+  if (!P) return fail(SABR_ENOMEM, "out of host memory");
+  P->n_inst = n;
+  P->model = pr->model;
+  P->formula = pr->vol_formula;
+  P->residual = pr->residual;
+  P->beta = pr->beta;
+  P->nF = pr->fwd_off[n];
+  P->nU = pr->und_off[n];
+  P->nQ = pr->q_off[n];
+  auto bad = [&](const std::string &m) {
+    delete P;
+    return fail(SABR_EINVAL, m);
+  };
+  for (int k = 0; k < P->nF; ++k) {
+    const double T = pr->fwd_T[k], tau = pr->fwd_tau[k], F = pr->fwd_F[k], Pk = pr->fwd_P[k];
+    if (!(std::isfinite(T) && T >= 0.0) || !finite_pos(tau) || !finite_pos(F) || !finite_pos(Pk))
+      return bad("forward " + std::to_string(k) + ": bad T, tau, F or P");
+    P->f_T.push_back(T);
+    P->f_tauP.push_back(tau * Pk);
+    P->f_F.push_back(F);
+  }
+  for (int i = 0; i < n; ++i) {
+    DevInst d{};
+    d.f0 = pr->fwd_off[i];
+    d.nf = pr->fwd_off[i + 1] - d.f0;
+    d.u0 = pr->und_off[i];
+    d.nu = pr->und_off[i + 1] - d.u0;
+    d.q0 = pr->q_off[i];
+    d.nq = pr->q_off[i + 1] - d.q0;
+    if (d.nq < 1) return bad("instance " + std::to_string(i) + " has no quotes");
+    d.maxlen = 1;
+    for (int u = d.u0; u < d.u0 + d.nu; ++u) {
+      const int first = pr->und_first[u], len = pr->und_len[u];
+      if (len < 1 || first < 0 || first + len > d.nf)
+        return bad("underlying " + std::to_string(u) + ": forward range out of bounds");
+      if (pr->model == 0 && len != 1) return bad("GLOBAL4 markets hold caplets only");
+      if (len > d.maxlen) d.maxlen = len;
+      // annuity, weights and swap rate, summed in forward order
+      double A = 0.0;
+      for (int k = first; k < first + len; ++k)
+        A += pr->fwd_tau[d.f0 + k] * pr->fwd_P[d.f0 + k];
+      double S0 = 0.0;
+      for (int k = first; k < first + len; ++k) {
+        const double wk = pr->fwd_tau[d.f0 + k] * pr->fwd_P[d.f0 + k] / A;
+        S0 += wk * pr->fwd_F[d.f0 + k];
+      }
+      const double Te = pr->fwd_T[d.f0 + first];
+      if (!(Te > 0.0)) return bad("underlying " + std::to_string(u) + ": expiry must be > 0");
+      P->u_first.push_back(first);
+      P->u_len.push_back(len);
+      P->u_S0.push_back(S0);
+      P->u_A.push_back(A);
+      P->u_invA.push_back(1.0 / A);
+      P->u_T.push_back(Te);
+    }
+    int prev = 0;
+    for (int q = d.q0; q < d.q0 + d.nq; ++q) {
+      const int u = pr->q_und[q], kind = pr->q_kind[q];
+      const double K = pr->q_K[q], vol = pr->q_vol[q], w = pr->q_w[q];
+      if (u < 0 || u >= d.nu) return bad("quote " + std::to_string(q) + ": underlying out of range");
+      if (u < prev) return bad("quotes of instance " + std::to_string(i) + " not sorted by underlying");
+      prev = u;
+      if (kind != 0 && kind != 1) return bad("quote " + std::to_string(q) + ": bad kind");
+      if (!finite_pos(K) || !finite_pos(vol) || !(std::isfinite(w) && w >= 0.0))
+        return bad("quote " + std::to_string(q) + ": bad strike, vol or weight");
+      const int gu = d.u0 + u;
+      P->q_und.push_back(u);
+      P->q_kind.push_back(kind);
+      P->q_f.push_back(P->u_S0[gu]);
+      P->q_K.push_back(K);
+      P->q_T.push_back(P->u_T[gu]);
+      P->q_D.push_back(P->u_A[gu]);
+      P->q_vol.push_back(vol);
+      P->q_wuser.push_back(w);
+    }
+    if (d.nq > P->max_nq) P->max_nq = d.nq;
+    if (d.nu > P->max_nu) P->max_nu = d.nu;
+    if (d.nf > P->max_nf) P->max_nf = d.nf;
+    if (d.maxlen > P->max_len) P->max_len = d.maxlen;
+    P->inst.push_back(d);
+  }
+  // device image: uploaded prefix, then the precomputed arrays
+  Layout L;
+  P->o_inst = L.take<DevInst>(n);
+  P->o_fT = L.take<double>(P->nF);
+  P->o_ftauP = L.take<double>(P->nF);
+  P->o_fF = L.take<double>(P->nF);
+  P->o_ufirst = L.take<int>(P->nU);
+  P->o_ulen = L.take<int>(P->nU);
+  P->o_uS0 = L.take<double>(P->nU);
+  P->o_uA = L.take<double>(P->nU);
+  P->o_uinvA = L.take<double>(P->nU);
+  P->o_qund = L.take<int>(P->nQ);
+  P->o_qkind = L.take<int>(P->nQ);
+  P->o_qf = L.take<double>(P->nQ);
+  P->o_qK = L.take<double>(P->nQ);
+  P->o_qT = L.take<double>(P->nQ);
+  P->o_qD = L.take<double>(P->nQ);
+  P->o_qvol = L.take<double>(P->nQ);
+  P->o_qwuser = L.take<double>(P->nQ);
+  P->upload_bytes = L.off;
+  P->o_fv = L.take<double>(P->nF);
+  P->o_uS0b = L.take<double>(P->nU);
+  P->o_qsqrtT = L.take<double>(P->nQ);
+  P->o_qL = L.take<double>(P->nQ);
+  P->o_qlfk = L.take<double>(P->nQ);
+  P->o_qlnf = L.take<double>(P->nQ);
+  P->o_qqfix = L.take<double>(P->nQ);
+  P->o_qD1fix = L.take<double>(P->nQ);
+  P->o_qfpfix = L.take<double>(P->nQ);
+  P->o_qtgt = L.take<double>(P->nQ);
+  P->o_qw = L.take<double>(P->nQ);
+  P->total_bytes = L.off;
+  P->staging.assign(P->upload_bytes, 0);
+  auto put = [&](size_t off, const void *src, size_t bytes) {
+    if (bytes) std::memcpy(P->staging.data() + off, src, bytes);
+  };
+  put(P->o_inst, P->inst.data(), n * sizeof(DevInst));
+  put(P->o_fT, P->f_T.data(), P->nF * 8);
+  put(P->o_ftauP, P->f_tauP.data(), P->nF * 8);
+  put(P->o_fF, P->f_F.data(), P->nF * 8);
+  put(P->o_ufirst, P->u_first.data(), P->nU * 4);
+  put(P->o_ulen, P->u_len.data(), P->nU * 4);
+  put(P->o_uS0, P->u_S0.data(), P->nU * 8);
+  put(P->o_uA, P->u_A.data(), P->nU * 8);
+  put(P->o_uinvA, P->u_invA.data(), P->nU * 8);
+  put(P->o_qund, P->q_und.data(), P->nQ * 4);
+  put(P->o_qkind, P->q_kind.data(), P->nQ * 4);
+  put(P->o_qf, P->q_f.data(), P->nQ * 8);
+  put(P->o_qK, P->q_K.data(), P->nQ * 8);
+  put(P->o_qT, P->q_T.data(), P->nQ * 8);
+  put(P->o_qD, P->q_D.data(), P->nQ * 8);
+  put(P->o_qvol, P->q_vol.data(), P->nQ * 8);
+  put(P->o_qwuser, P->q_wuser.data(), P->nQ * 8);
+  *out = P;
+  return SABR_OK;
+}
+
+void sabr_plan_destroy(sabr_plan *plan) { delete plan; }
+
+size_t sabr_plan_device_bytes(const sabr_plan *plan) { return plan ? plan->total_bytes : 0; }
+int32_t sabr_plan_num_params(const sabr_plan *plan) {
+  return plan ? sabr_num_params(plan->model) : -1;
+}
+int32_t sabr_plan_num_inst(const sabr_plan *plan) { return plan ? plan->n_inst : -1; }
+int32_t sabr_plan_max_quotes(const sabr_plan *plan) { return plan ? plan->max_nq : -1; }
+
+sabr_status sabr_plan_underlyings(const sabr_plan *plan, double *S0, double *A, double *T) {
+  if (!plan) return fail(SABR_EINVAL, "null plan");
+  for (int u = 0; u < plan->nU; ++u) {
+    if (S0) S0[u] = plan->u_S0[u];
+    if (A) A[u] = plan->u_A[u];
+    if (T) T[u] = plan->u_T[u];
+  }
+  return SABR_OK;
+}
+
+sabr_status sabr_plan_upload(sabr_plan *P, void *dev_buf, size_t bytes, void *stream) {
+  if (!P || !dev_buf) return fail(SABR_EINVAL, "null argument");
+  if (bytes < P->total_bytes) return fail(SABR_EWORKSPACE, "device buffer smaller than the image");
+  if (reinterpret_cast<uintptr_t>(dev_buf) % 256) return fail(SABR_EINVAL, "device buffer not 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char *d = static_cast<char *>(dev_buf);
+  hipError_t e = hipMemcpyAsync(d, P->staging.data(), P->upload_bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "upload");
+  DevMarket m{};
+  m.n_inst = P->n_inst;
+  m.model = P->model;
+  m.formula = P->formula;
+  m.residual = P->residual;
+  m.beta = P->beta;
+  m.max_nq = P->max_nq;
+  m.max_nu = P->max_nu;
+  m.max_nf = P->max_nf;
+  m.max_len = P->max_len;
+  m.inst = reinterpret_cast<const DevInst *>(d + P->o_inst);
+  auto D = [&](size_t o) { return reinterpret_cast<double *>(d + o); };
+  auto I = [&](size_t o) { return reinterpret_cast<int *>(d + o); };
+  m.f_T = D(P->o_fT);
+  m.f_v = D(P->o_fv);
+  m.u_first = I(P->o_ufirst);
+  m.u_len = I(P->o_ulen);
+  m.u_S0 = D(P->o_uS0);
+  m.u_A = D(P->o_uA);
+  m.u_invA = D(P->o_uinvA);
+  m.u_S0b = D(P->o_uS0b);
+  m.q_und = I(P->o_qund);
+  m.q_kind = I(P->o_qkind);
+  m.q_f = D(P->o_qf);
+  m.q_K = D(P->o_qK);
+  m.q_T = D(P->o_qT);
+  m.q_sqrtT = D(P->o_qsqrtT);
+  m.q_D = D(P->o_qD);
+  m.q_L = D(P->o_qL);
+  m.q_lfk = D(P->o_qlfk);
+  m.q_lnf = D(P->o_qlnf);
+  m.q_qfix = D(P->o_qqfix);
+  m.q_D1fix = D(P->o_qD1fix);
+  m.q_fpfix = D(P->o_qfpfix);
+  m.q_tgt = D(P->o_qtgt);
+  m.q_w = D(P->o_qw);
+  e = sabr::launch_prep(m, D(P->o_qtgt), D(P->o_qw), D(P->o_qL), D(P->o_qlfk), D(P->o_qlnf),
+                        D(P->o_qsqrtT), D(P->o_qqfix), D(P->o_qD1fix), D(P->o_qfpfix),
+                        D(P->o_fv), D(P->o_uS0b), D(P->o_qvol), D(P->o_qwuser), D(P->o_ftauP),
+                        D(P->o_fF), P->nQ, P->nF, P->nU, s);
+  if (e != hipSuccess) return hip_fail(e, "market precompute launch");
+  P->dev = d;
+  P->dm = m;
+  std::lock_guard<std::mutex> g(P->mu);
+  if (P->graph_exec) {
+    (void)hipGraphExecDestroy(P->graph_exec);
+    P->graph_exec = nullptr;
+    P->graph_key.clear();
+  }
+  return SABR_OK;
+}
+
+sabr_status sabr_cost_batch(const sabr_plan *P, int32_t n_pts, const int32_t *pt_inst,
+                            const double *params, double *cost, double *resid, double *model,
+                            int32_t stride, void *stream) {
+  if (!P) return fail(SABR_EINVAL, "null plan");
+  if (!P->dev) return fail(SABR_EINVAL, "plan not uploaded");
+  if (n_pts < 0) return fail(SABR_EINVAL, "n_pts < 0");
+  if (n_pts == 0) return SABR_OK;
+  if (!pt_inst || !params || !cost) return fail(SABR_EINVAL, "null pt_inst, params or cost");
+  if ((resid || model) && stride < P->max_nq) return fail(SABR_EINVAL, "stride < max quotes");
+  hipError_t e = sabr::launch_cost(P->dm, n_pts, pt_inst, params, cost, resid, model, stride,
+                                   static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "cost launch");
+  return SABR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Simulated annealing
+// ---------------------------------------------------------------------------
+namespace {
+
+struct SALayout {
+  size_t o_chains, o_cbase, o_abase, o_tinst, o_tchain, o_lb, o_ub, o_x0, o_T0;
+  size_t upload_bytes;
+  size_t o_X, o_F, o_BX, o_BF, o_NACC, o_RX, o_RF, o_Tcur, o_tstart;
+  size_t total;
+  int n_tiles, waves;
+  int64_t tot_chains;
+};
+
+SALayout sa_layout(const sabr_plan *P, const sa_config *cfg, const int32_t *chains) {
+  SALayout S{};
+  const int n = P->n_inst;
+  const int Pn = sabr_num_params(P->model);
+  int want = cfg && cfg->waves_per_group > 0 ? cfg->waves_per_group : 4;
+  if (want > 4) want = 4;
+  DevMarket shape{};  // LDS budget depends on the market's shape only
+  shape.model = P->model;
+  shape.max_nf = P->max_nf;
+  shape.max_nu = P->max_nu;
+  shape.max_len = P->max_len;
+  S.waves = sabr::sa_waves_per_group(shape, want);
+  S.n_tiles = 0;
+  S.tot_chains = 0;
+  for (int i = 0; i < n; ++i) {
+    S.n_tiles += (chains[i] + S.waves - 1) / S.waves;
+    S.tot_chains += chains[i];
+  }
+  Layout L;
+  S.o_chains = L.take<int>(n);
+  S.o_cbase = L.take<int64_t>(n);
+  S.o_abase = L.take<int64_t>(n);
+  S.o_tinst = L.take<int>(S.n_tiles);
+  S.o_tchain = L.take<int>(S.n_tiles);
+  S.o_lb = L.take<double>((size_t)n * Pn);
+  S.o_ub = L.take<double>((size_t)n * Pn);
+  S.o_x0 = L.take<double>((size_t)n * Pn);
+  S.o_T0 = L.take<double>(n);
+  S.upload_bytes = L.off;
+  S.o_X = L.take<double>(S.tot_chains * Pn);
+  S.o_F = L.take<double>(S.tot_chains);
+  S.o_BX = L.take<double>(S.tot_chains * Pn);
+  S.o_BF = L.take<double>(S.tot_chains);
+  S.o_NACC = L.take<int>(S.tot_chains);
+  S.o_RX = L.take<double>((size_t)n * Pn);
+  S.o_RF = L.take<double>(n);
+  S.o_Tcur = L.take<double>(n);
+  S.o_tstart = L.take<uint64_t>(1);
+  S.total = L.off;
+  return S;
+}
+
+sabr_status check_sa_args(const sabr_plan *P, const sa_config *cfg, const int32_t *chains) {
+  if (!P) return fail(SABR_EINVAL, "null plan");
+  if (!cfg || !chains) return fail(SABR_EINVAL, "null config or chains");
+  if (!(cfg->T0 > 0.0) || !std::isfinite(cfg->T0)) return fail(SABR_EINVAL, "T0 must be > 0");
+  if (!(cfg->cool > 0.0 && cfg->cool <= 1.0)) return fail(SABR_EINVAL, "cool outside (0, 1]");
+  if (!(cfg->step_frac > 0.0 && cfg->step_frac <= 1.0))
+    return fail(SABR_EINVAL, "step_frac outside (0, 1]");
+  if (cfg->n_levels < 0 || cfg->n_steps < 0) return fail(SABR_EINVAL, "negative L or N");
+  for (int i = 0; i < P->n_inst; ++i) {
+    if (chains[i] < 1) return fail(SABR_EINVAL, "every instance needs >= 1 chain");
+    if (cfg->T0_per_inst && !(cfg->T0_per_inst[i] > 0.0 && std::isfinite(cfg->T0_per_inst[i])))
+      return fail(SABR_EINVAL, "T0_per_inst must be > 0");
+  }
+  return SABR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sa_workspace_size(const sabr_plan *P, const sa_config *cfg, const int32_t *chains) {
+  if (check_sa_args(P, cfg, chains) != SABR_OK) return 0;
+  return sa_layout(P, cfg, chains).total;
+}
+
+sabr_status sa_calibrate(const sabr_plan *Pc, const sa_config *cfg, const int32_t *chains,
+                         const double *lb, const double *ub, const double *x0, double *best_x,
+                         double *best_f, double *chain_best_x, double *chain_best_f,
+                         uint8_t *accept, double *level_trace, int32_t *level_best,
+                         void *workspace, size_t ws_bytes, void *stream) {
+  sabr_status st = check_sa_args(Pc, cfg, chains);
+  if (st != SABR_OK) return st;
+  sabr_plan *P = const_cast<sabr_plan *>(Pc);
+  if (!P->dev) return fail(SABR_EINVAL, "plan not uploaded");
+  if (!lb || !ub) return fail(SABR_EINVAL, "null box");
+  if (!best_x || !best_f) return fail(SABR_EINVAL, "null best_x or best_f");
+  if (!workspace) return fail(SABR_EINVAL, "null workspace");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(SABR_EINVAL, "workspace not 256-byte aligned");
+  const int n = P->n_inst;
+  const int Pn = sabr_num_params(P->model);
+  for (int i = 0; i < n * Pn; ++i) {
+    if (!std::isfinite(lb[i]) || !std::isfinite(ub[i]) || !(lb[i] <= ub[i]))
+      return fail(SABR_EINVAL, "box bound " + std::to_string(i) + ": need finite lb <= ub");
+    if (x0 && !(x0[i] >= lb[i] && x0[i] <= ub[i]))
+      return fail(SABR_EINVAL, "x0 outside the box");
+  }
+  const SALayout S = sa_layout(P, cfg, chains);
+  if (ws_bytes < S.total) return fail(SABR_EWORKSPACE, "workspace too small");
+  const int L = cfg->n_levels, N = cfg->n_steps;
+  // host-side tables
+  std::lock_guard<std::mutex> guard(P->mu);
+  std::vector<unsigned char> &stg = P->sa_staging;
+  stg.assign(S.upload_bytes, 0);
+  int *h_chains = reinterpret_cast<int *>(stg.data() + S.o_chains);
+  int64_t *h_cbase = reinterpret_cast<int64_t *>(stg.data() + S.o_cbase);
+  int64_t *h_abase = reinterpret_cast<int64_t *>(stg.data() + S.o_abase);
+  int *h_tinst = reinterpret_cast<int *>(stg.data() + S.o_tinst);
+  int *h_tchain = reinterpret_cast<int *>(stg.data() + S.o_tchain);
+  double *h_lb = reinterpret_cast<double *>(stg.data() + S.o_lb);
+  double *h_ub = reinterpret_cast<double *>(stg.data() + S.o_ub);
+  double *h_x0 = reinterpret_cast<double *>(stg.data() + S.o_x0);
+  double *h_T0 = reinterpret_cast<double *>(stg.data() + S.o_T0);
+  int64_t cb = 0, ab = 0;
+  int t = 0;
+  for (int i = 0; i < n; ++i) {
+    h_chains[i] = chains[i];
+    h_cbase[i] = cb;
+    h_abase[i] = ab;
+    cb += chains[i];
+    ab += (int64_t)L * N * chains[i];
+    for (int c = 0; c < chains[i]; c += S.waves) {
+      h_tinst[t] = i;
+      h_tchain[t] = c;
+      ++t;
+    }
+    h_T0[i] = cfg->T0_per_inst ? cfg->T0_per_inst[i] : cfg->T0;
+    for (int k = 0; k < Pn; ++k) {
+      const size_t j = (size_t)i * Pn + k;
+      h_lb[j] = lb[j];
+      h_ub[j] = ub[j];
+      h_x0[j] = x0 ? x0[j] : 0.5 * (lb[j] + ub[j]);
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char *w = static_cast<char *>(workspace);
+  hipError_t e = hipMemcpyAsync(w, stg.data(), S.upload_bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "SA table upload");
+  int rate_khz = 0;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+      rate_khz <= 0)
+    rate_khz = 100000;
+  sabr::SAArgs a{};
+  a.n_inst = n;
+  a.P = Pn;
+  a.N = N;
+  a.L = L;
+  a.seed = cfg->seed;
+  a.step_frac = cfg->step_frac;
+  a.cool = cfg->cool;
+  a.ns_per_tick = 1.0e6 / (double)rate_khz;
+  a.chains = reinterpret_cast<const int *>(w + S.o_chains);
+  a.chain_base = reinterpret_cast<const int64_t *>(w + S.o_cbase);
+  a.acc_base = reinterpret_cast<const int64_t *>(w + S.o_abase);
+  a.tile_inst = reinterpret_cast<const int *>(w + S.o_tinst);
+  a.tile_chain = reinterpret_cast<const int *>(w + S.o_tchain);
+  a.lb = reinterpret_cast<const double *>(w + S.o_lb);
+  a.ub = reinterpret_cast<const double *>(w + S.o_ub);
+  a.x0 = reinterpret_cast<const double *>(w + S.o_x0);
+  a.T0 = reinterpret_cast<const double *>(w + S.o_T0);
+  a.X = reinterpret_cast<double *>(w + S.o_X);
+  a.F = reinterpret_cast<double *>(w + S.o_F);
+  a.BX = reinterpret_cast<double *>(w + S.o_BX);
+  a.BF = reinterpret_cast<double *>(w + S.o_BF);
+  a.NACC = reinterpret_cast<int *>(w + S.o_NACC);
+  a.RX = reinterpret_cast<double *>(w + S.o_RX);
+  a.RF = reinterpret_cast<double *>(w + S.o_RF);
+  a.Tcur = reinterpret_cast<double *>(w + S.o_Tcur);
+  a.t_start = reinterpret_cast<uint64_t *>(w + S.o_tstart);
+  a.accept = accept;
+  a.trace = level_trace;
+  a.level_best = level_best;
+  a.best_x = best_x;
+  a.best_f = best_f;
+  a.chain_best_x = chain_best_x;
+  a.chain_best_f = chain_best_f;
+
+  auto enqueue = [&](hipStream_t q) -> hipError_t {
+    hipError_t r = sabr::launch_sa_init(P->dm, a, S.n_tiles, S.waves, q);
+    if (r != hipSuccess) return r;
+    for (int l = 0; l < L; ++l) {
+      if (N > 0) {
+        r = sabr::launch_sa_level(P->dm, a, l, S.n_tiles, S.waves, q);
+        if (r != hipSuccess) return r;
+      }
+      r = sabr::launch_sa_level_end(a, l, q);
+      if (r != hipSuccess) return r;
+    }
+    return sabr::launch_sa_final(a, q);
+  };
+
+  if (!cfg->use_graph) {
+    e = enqueue(s);
+    if (e != hipSuccess) return hip_fail(e, "SA launch");
+    return SABR_OK;
+  }
+  if (s == nullptr) return fail(SABR_EINVAL, "graph replay needs a non-default stream");
+  // replay key: every pointer and scalar baked into the captured kernels
+  std::vector<uint64_t> key = {(uint64_t)(uintptr_t)P->dev, (uint64_t)(uintptr_t)w,
+                               (uint64_t)(uintptr_t)best_x, (uint64_t)(uintptr_t)best_f,
+                               (uint64_t)(uintptr_t)chain_best_x,
+                               (uint64_t)(uintptr_t)chain_best_f, (uint64_t)(uintptr_t)accept,
+                               (uint64_t)(uintptr_t)level_trace, (uint64_t)(uintptr_t)level_best,
+                               (uint64_t)L, (uint64_t)N, cfg->seed, (uint64_t)S.waves,
+                               (uint64_t)S.n_tiles};
+  uint64_t bits;
+  std::memcpy(&bits, &cfg->step_frac, 8);
+  key.push_back(bits);
+  std::memcpy(&bits, &cfg->cool, 8);
+  key.push_back(bits);
+  for (int i = 0; i < n; ++i) key.push_back((uint64_t)chains[i]);
+  if (!P->graph_exec || key != P->graph_key) {
+    if (P->graph_exec) {
+      (void)hipGraphExecDestroy(P->graph_exec);
+      P->graph_exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "begin capture");
+    hipError_t er = enqueue(s);
+    e = hipStreamEndCapture(s, &graph);
+    if (er != hipSuccess) return hip_fail(er, "SA capture");
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    e = hipGraphInstantiate(&P->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      P->graph_exec = nullptr;
+      return hip_fail(e, "graph instantiate");
+    }
+    P->graph_key = key;
+  }
+  e = hipGraphLaunch(P->graph_exec, s);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  return SABR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// sabr_internal.hpp -- interface between the C-ABI runtime (sabr_api.cpp) and
+// the kernels (sabr_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sabr_device.hpp"
+
+namespace sabr {
+
+// Doubles of LDS one wavefront needs for the LMM12 maps: per-forward alpha,
+// nu and the two correlation gap factors, per-underlying (alpha, rho, nu,
+// nu/alpha), and a per-lane column of max_len doubles for the swap recursion.
+inline int wave_lds_doubles(const DevMarket &m) {
+  if (m.model == 0) return 0;
+  return 4 * m.max_nf + 4 * m.max_nu + kWave * m.max_len;
+}
+
+struct SAArgs {
+  int n_inst, P, N, L;
+  uint64_t seed;
+  double step_frac, cool, ns_per_tick;
+  const int *chains;            // [n_inst]
+  const int64_t *chain_base;    // [n_inst] first global chain of each instance
+  const int64_t *acc_base;      // [n_inst] offset of each instance's accept flags
+  const int *tile_inst;         // [n_tiles]
+  const int *tile_chain;        // [n_tiles] first chain of the tile
+  const double *lb, *ub, *x0;   // [n_inst][P]
+  const double *T0;             // [n_inst]
+  double *X, *F, *BX, *BF;      // per-chain current and best-ever state
+  int *NACC;                    // per-chain accepted moves in the current level
+  double *RX, *RF, *Tcur;       // per-instance restart point and temperature
+  uint64_t *t_start;            // wall clock at initialisation
+  uint8_t *accept;              // nullable: [inst][level][step][chain]
+  double *trace;                // nullable: [inst][level][3]
+  int *level_best;              // nullable: [inst][level]
+  double *best_x, *best_f;      // [n_inst][P], [n_inst]
+  double *chain_best_x, *chain_best_f;  // nullable
+};
+
+hipError_t launch_prep(const DevMarket &m, double *q_tgt, double *q_w, double *q_L,
+                       double *q_lfk, double *q_lnf, double *q_sqrtT, double *q_qfix,
+                       double *q_D1fix, double *q_fpfix, double *f_v, double *u_S0b,
+                       const double *q_vol, const double *q_wuser, const double *f_tauP,
+                       const double *f_F, int n_q, int n_f, int n_u, hipStream_t s);
+
+hipError_t launch_cost(const DevMarket &m, int n_pts, const int *pt_inst, const double *params,
+                       double *cost, double *resid, double *model, int stride, hipStream_t s);
+
+hipError_t launch_sa_init(const DevMarket &m, const SAArgs &a, int n_tiles, int waves,
+                          hipStream_t s);
+hipError_t launch_sa_level(const DevMarket &m, const SAArgs &a, int level, int n_tiles,
+                           int waves, hipStream_t s);
+hipError_t launch_sa_level_end(const SAArgs &a, int level, hipStream_t s);
+hipError_t launch_sa_final(const SAArgs &a, hipStream_t s);
+
+// Wavefronts per SA/cost workgroup that fit the LDS budget (at most `want`).
+int sa_waves_per_group(const DevMarket &m, int want);
+
+}  // namespace sabr

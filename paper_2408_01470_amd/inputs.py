@@ -186,15 +186,17 @@ def _lmm_instance(M, n_cap_K, n_exp, n_ten, n_swp_K, both_sides):
     tau = np.full(M, 0.5)
     F = 0.02 + 0.02 * np.arange(M) / (M - 1)
     P = _curve_discounts(T, tau, F)
-    und_first, und_len = [], []
+    und_first, und_len, is_swp = [], [], []
     for i in range(1, M):                    # caplets on forwards 1..M-1
         und_first.append(i)
         und_len.append(1)
+        is_swp.append(False)
     for e in range(1, n_exp + 1):            # swaptions: expiry T_e, n periods
         for n in range(1, n_ten + 1):
             if e + n - 1 <= M - 1:
                 und_first.append(e)
                 und_len.append(n)
+                is_swp.append(True)
     und_first = np.array(und_first, np.int32)
     und_len = np.array(und_len, np.int32)
     cap_m = _moneyness_grid(n_cap_K)
@@ -206,7 +208,7 @@ def _lmm_instance(M, n_cap_K, n_exp, n_ten, n_swp_K, both_sides):
         # strike centre: the forward itself for a caplet, the plain mean of
         # the swap's forwards for a swaption (close to, not equal to, S0)
         centre = F[f0] if n == 1 else float(np.mean(F[f0:f0 + n]))
-        for mny in (cap_m if n == 1 else swp_m):
+        for mny in (swp_m if is_swp[u] else cap_m):
             for kind in sides:
                 q_und.append(u)
                 q_kind.append(kind)

@@ -1,0 +1,198 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bars: model values (vol or price) and finite costs agree to 1e-12 relative,
+domain failures (cost = +inf) agree exactly, and annealing runs driven by the
+same Philox streams take the same accept/reject decisions and restart points.
+"""
+import numpy as np
+import pytest
+
+from conftest import complete_with_oracle
+from paper_2408_01470_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_01470_amd import api as A
+    return A
+
+
+def _cmp_cost(c_gpu, c_ora, what):
+    fin = np.isfinite(c_ora)
+    assert np.array_equal(fin, np.isfinite(c_gpu)), f"{what}: domain flags differ"
+    rel = np.abs(c_gpu[fin] - c_ora[fin]) / np.abs(c_ora[fin])
+    assert rel.max(initial=0.0) <= RTOL, f"{what}: cost rel err {rel.max():.3e}"
+    return fin
+
+
+def _cmp_model(plan, oracle, mk, pts, pt_inst, what):
+    c, r, mvals = plan.cost(torch.tensor(pts, device="cuda"), pt_inst=pt_inst, resid=True,
+                            model=True)
+    mvals = mvals.cpu().numpy()
+    r = r.cpu().numpy()
+    nq = np.diff(mk["q_off"])
+    _, r_ora = oracle.cost_batch(mk, pts, pt_inst, resid=True)
+    worst_m, worst_r = 0.0, 0.0
+    for i, p in enumerate(pts):
+        inst = 0 if pt_inst is None else int(pt_inst[i])
+        mo, tg, w, ok = oracle.model_values(mk, inst, p)
+        if not ok:
+            continue
+        q = nq[inst]
+        worst_m = max(worst_m, np.max(np.abs(mvals[i, :q] - mo) / np.abs(mo)))
+        # residuals: 1e-12 of the larger of model and market value
+        scale = np.maximum(np.abs(mo), np.abs(tg))
+        worst_r = max(worst_r, np.max(np.abs(r[i, :q] - r_ora[i, :q]) / scale))
+    assert worst_m <= RTOL, f"{what}: model value rel err {worst_m:.3e}"
+    assert worst_r <= RTOL, f"{what}: residual err {worst_r:.3e}"
+
+
+def _points(model, truth, n_rand, seed):
+    lb, ub = I.box(model)
+    g = np.random.default_rng(seed)
+    near = np.clip(truth[None, :] * g.uniform(0.8, 1.2, (n_rand, len(lb))), lb, ub)
+    return np.vstack([truth[None, :], near, I.random_box_points(model, n_rand, seed)])
+
+
+@pytest.mark.parametrize("formula,residual", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_cost_parity_caplets(api, oracle, formula, residual):
+    m, truth, noise = I.caplet_market(formula=formula, residual=residual)
+    mk = complete_with_oracle(oracle, m, truth, noise)
+    plan = api.Plan(mk)
+    pts = _points(0, truth[0], 100, 1)
+    c_gpu = plan.cost(torch.tensor(pts, device="cuda")).cpu().numpy()
+    fin = _cmp_cost(c_gpu, oracle.cost_batch(mk, pts), f"caplets f{formula} r{residual}")
+    assert fin.sum() > 100
+    _cmp_model(plan, oracle, mk, pts[fin][:40], None, "caplets")
+
+
+@pytest.mark.parametrize("formula", [0, 1])
+def test_cost_parity_lmm_caplets_and_swaptions(api, oracle, c2_market, formula):
+    mk, truth = c2_market
+    mk = dict(mk, formula=formula)
+    plan = api.Plan(mk)
+    pts = _points(1, truth[0], 60, 2)
+    c_gpu = plan.cost(torch.tensor(pts, device="cuda")).cpu().numpy()
+    fin = _cmp_cost(c_gpu, oracle.cost_batch(mk, pts), "LMM12")
+    assert fin.sum() > 30
+    _cmp_model(plan, oracle, mk, pts[fin][:8], None, "LMM12")
+
+
+def test_cost_parity_both_sides_vol_mode(api, oracle):
+    m, truth, noise = I.lmm_market(M=12, n_cap_K=5, n_exp=5, n_ten=6, n_swp_K=5,
+                                   both_sides=True, residual=I.RESID_VOL)
+    mk = complete_with_oracle(oracle, m, truth, noise)
+    plan = api.Plan(mk)
+    pts = _points(1, truth[0], 40, 3)
+    c_gpu = plan.cost(torch.tensor(pts, device="cuda")).cpu().numpy()
+    _cmp_cost(c_gpu, oracle.cost_batch(mk, pts), "LMM12 vol both sides")
+
+
+def test_cost_parity_ragged_batch(api, oracle):
+    m, truth, noise = I.batch_markets(n_markets=7, M_range=(1, 40), nK_range=(1, 15))
+    mk = complete_with_oracle(oracle, m, truth, noise)
+    plan = api.Plan(mk)
+    pts, inst = [], []
+    for i in range(7):
+        p = _points(0, truth[i], 10, 10 + i)
+        pts.append(p)
+        inst += [i] * len(p)
+    pts = np.vstack(pts)
+    inst = np.array(inst, np.int32)
+    c_gpu = plan.cost(torch.tensor(pts, device="cuda"),
+                      pt_inst=torch.tensor(inst, device="cuda")).cpu().numpy()
+    _cmp_cost(c_gpu, oracle.cost_batch(mk, pts, inst), "ragged batch")
+    _cmp_model(plan, oracle, mk, pts[::7], inst[::7], "ragged batch")
+
+
+def test_cost_single_quote_and_bad_instance(api, oracle):
+    m, truth, noise = I.caplet_market(M=1, nK=1)
+    mk = complete_with_oracle(oracle, m, truth, noise)
+    plan = api.Plan(mk)
+    pts = _points(0, truth[0], 5, 4)
+    c_gpu = plan.cost(torch.tensor(pts, device="cuda")).cpu().numpy()
+    _cmp_cost(c_gpu, oracle.cost_batch(mk, pts), "Q = 1")
+    bad = plan.cost(torch.tensor(pts[:2], device="cuda"),
+                    pt_inst=torch.tensor([0, 5], dtype=torch.int32, device="cuda")).cpu().numpy()
+    assert np.isfinite(bad[0]) and np.isnan(bad[1])
+
+
+def first_divergence(acc_g, acc_o, L, N, chains):
+    """(level, step, chain) of the first differing accept flag, or None."""
+    a = acc_g.reshape(L, N, chains)
+    b = acc_o.reshape(L, N, chains)
+    d = np.argwhere(a != b)
+    return None if len(d) == 0 else tuple(int(v) for v in d[0])
+
+
+def _sa_parity(api, oracle, mk, chains, L, N, T0, cool, seed, model):
+    lb, ub = I.box(model)
+    plan = api.Plan(mk)
+    kw = dict(T0=T0, cool=cool, n_levels=L, n_steps=N, seed=seed)
+    g = plan.sa(chains, lb, ub, record=True, chain_best=True, **kw)
+    o = oracle.sa_calibrate(mk, chains, lb, ub, record=True, **kw)
+    acc = g["accept"].cpu().numpy()
+    div = first_divergence(acc, o["accept"], L, N, chains)
+    assert div is None, f"first divergence at (level, step, chain) = {div}"
+    assert np.array_equal(g["level_best"].cpu().numpy(), o["level_best"])
+    bf = g["best_f"].cpu().numpy()
+    assert abs(bf[0] - o["best_f"][0]) <= RTOL * abs(o["best_f"][0])
+    assert np.array_equal(g["best_x"].cpu().numpy(), o["best_x"])
+    tr = g["trace"].cpu().numpy()
+    np.testing.assert_allclose(tr[0, :, 0], o["trace"][0, :, 0], rtol=RTOL)
+    np.testing.assert_array_equal(tr[0, :, 1], o["trace"][0, :, 1])
+    cbf = g["chain_best_f"].cpu().numpy()
+    np.testing.assert_allclose(cbf, o["chain_best_f"], rtol=RTOL)
+    assert 0 < acc.mean() < 1
+    return g, o
+
+
+def test_sa_accept_parity_caplets(api, oracle, c1_market):
+    mk, _ = c1_market
+    _sa_parity(api, oracle, mk, 64, 20, 25, 0.05, 0.8, 11, 0)
+
+
+def test_sa_accept_parity_lmm(api, oracle, c2_market):
+    mk, _ = c2_market
+    _sa_parity(api, oracle, mk, 8, 4, 5, 1e-3, 0.7, 12, 1)
+
+
+def test_sa_accept_parity_ragged_batch(api, oracle):
+    m, truth, noise = I.batch_markets(n_markets=5, M_range=(3, 20), nK_range=(3, 11))
+    mk = complete_with_oracle(oracle, m, truth, noise)
+    lb, ub = I.box(0)
+    plan = api.Plan(mk)
+    chains = np.array([3, 17, 64, 1, 9], np.int32)
+    kw = dict(T0=0.05, cool=0.8, n_levels=6, n_steps=12, seed=13)
+    g = plan.sa(chains, lb, ub, record=True, **kw)
+    o = oracle.sa_calibrate(mk, chains, lb, ub, record=True, **kw)
+    assert np.array_equal(g["accept"].cpu().numpy(), o["accept"])
+    assert np.array_equal(g["level_best"].cpu().numpy(), o["level_best"])
+    np.testing.assert_allclose(g["best_f"].cpu().numpy(), o["best_f"], rtol=RTOL)
+
+
+def test_sa_graph_replay_matches_eager(api, oracle, c1_market):
+    mk, _ = c1_market
+    lb, ub = I.box(0)
+    plan = api.Plan(mk)
+    kw = dict(T0=0.05, cool=0.8, n_levels=8, n_steps=10, seed=21, record=True)
+    eager = plan.sa(32, lb, ub, **kw)
+    side = torch.cuda.Stream()
+    ws = eager["workspace"]
+    outs = None
+    for rep in range(3):
+        with torch.cuda.stream(side):
+            g = plan.sa(32, lb, ub, use_graph=True, stream=side, workspace=ws, out=outs, **kw)
+        outs = g
+        side.synchronize()
+        torch.cuda.synchronize()
+        assert torch.equal(g["accept"], eager["accept"]), f"replay {rep}"
+        assert torch.equal(g["best_x"], eager["best_x"])
+        assert torch.equal(g["best_f"], eager["best_f"])
