@@ -1,0 +1,201 @@
+#!/usr/bin/env python
+"""Benchmark of the MI355X SA calibrator (one JSON line on stdout).
+
+A step is one full calibration of the workload: simulated annealing over all
+levels (proposal, parameter map, swaption map, Hagan vol, Black price,
+weighted residual reduction, Metropolis, level-end restart).  The default
+workload is the joint caplet + swaption LMM12 calibration (985 quotes, 4096
+chains, 688 levels x 10 steps).  Throughput is quote-evaluations per second
+with the market already resident in HBM.
+
+Also reported: the dominant kernel (the per-level annealing kernel) against
+the FP64 vector roofline, timed with HIP events recorded on its own stream,
+and the CPU oracle's throughput on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "quote-evals/s + time-to-RMSE (SA vs SA+adjoint polish), 1 MI355X"
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--levels", type=int, default=None, help="override the level count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-levels", type=int, default=6,
+                    help="levels of the oracle's bounded sample")
+    return ap.parse_args()
+
+
+def gpu_vols(api, vol_market, truth):
+    import torch
+    plan = api.Plan(vol_market)
+    n = plan.n_inst
+    _, mv = plan.cost(torch.tensor(truth, device="cuda"),
+                      pt_inst=torch.arange(n, dtype=torch.int32, device="cuda"), model=True)
+    mv = mv.cpu().numpy()
+    return np.concatenate([mv[i, :plan.nq[i]] for i in range(n)])
+
+
+def oracle_vols(O, vol_market, truth):
+    M = O.Market(vol_market)
+    out = []
+    for i in range(M.n_inst):
+        mv, _, _, ok = O.model_values(M, i, truth[i])
+        assert ok
+        out.append(mv)
+    return np.concatenate(out)
+
+
+def cpu_baseline(w, n_levels):
+    """The oracle, as it stands, on the first n_levels levels of the same
+    calibration (its own copy of the market and schedule)."""
+    from oracle import oracle as O
+    from paper_2408_01470_amd import inputs as I
+    from paper_2408_01470_amd import workloads as W
+
+    mk = W.synthesize(w, lambda vm, t: oracle_vols(O, vm, t))
+    M = O.Market(mk)
+    lb, ub = I.box(w.model)
+    pts = W.schedule_points(w.model, w.seed)
+    nq = I.n_quotes(mk)
+    T0s, cool = [], None
+    for i in range(w.n_inst):
+        c = O.cost_batch(M, pts, np.full(len(pts), i, np.int32))
+        T0, cool = W.schedule(c, nq[i], w.n_levels)
+        T0s.append(T0)
+    threads = int(O.max_threads())
+    t = time.perf_counter()
+    O.sa_calibrate(M, w.chains, lb, ub, T0=T0s[0], cool=cool, n_levels=n_levels,
+                   n_steps=w.n_steps, seed=w.seed, T0_per_inst=np.array(T0s))
+    dt = time.perf_counter() - t
+    qe = w.quote_evals(n_levels=n_levels)
+    return dict(value=qe / dt, unit="quote-evals/s", cores=threads, kind="oracle",
+                sample=f"first {n_levels} of {w.n_levels} levels of the same calibration "
+                       f"({qe:.3e} quote-evals, {dt:.1f} s, OpenMP over chains)")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
+              "multi-GPU sharding of chains and markets is described in DESIGN.md",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2408_01470_amd import api, flops
+    from paper_2408_01470_amd import inputs as I
+    from paper_2408_01470_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = W.CONFIGS[args.config]()
+    if args.levels is not None:
+        w.n_levels = args.levels
+    mk = W.synthesize(w, lambda vm, t: gpu_vols(api, vm, t))
+    plan = api.Plan(mk)
+    lb, ub = I.box(w.model)
+    nq = I.n_quotes(mk)
+    pts = torch.tensor(W.schedule_points(w.model, w.seed), device="cuda")
+    T0s, cool = [], None
+    for i in range(w.n_inst):
+        c = plan.cost(pts, pt_inst=torch.full((len(pts),), i, dtype=torch.int32,
+                                              device="cuda")).cpu().numpy()
+        T0, cool = W.schedule(c, nq[i], w.n_levels)
+        T0s.append(T0)
+    T0s = np.array(T0s)
+    kw = dict(T0=T0s[0], cool=cool, n_levels=w.n_levels, n_steps=w.n_steps, seed=w.seed,
+              step_frac=w.step_frac, T0_per_inst=T0s, trace=True)
+    stream = torch.cuda.current_stream()
+    ws = None
+    for _ in range(args.warmup):
+        r = plan.sa(w.chains, lb, ub, workspace=ws, **kw)
+        ws = r["workspace"]
+    torch.cuda.synchronize()
+    L = w.n_levels
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * L)]
+              for _ in range(args.steps)]
+    for evs in events:          # create the HIP events on this stream
+        for e in evs:
+            e.record(stream)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    results = []
+    for k in range(args.steps):
+        results.append(plan.sa(w.chains, lb, ub, workspace=ws, level_events=events[k], **kw))
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = start.elapsed_time(end)
+    ms_per_step = ms_total / args.steps
+    qe = w.quote_evals()
+    value = qe / (ms_per_step / 1e3)
+    lvl_ms = np.array([[evs[2 * l].elapsed_time(evs[2 * l + 1]) for l in range(L)]
+                       for evs in events])
+    avg_launch_s = float(lvl_ms.mean()) / 1e3
+    flop_launch = flops.level_launch_flops(mk, w.chains, w.n_steps)
+    achieved = flop_launch / avg_launch_s / 1e12
+    best_f = results[-1]["best_f"].cpu().numpy()
+    rmse = np.sqrt(best_f / nq)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "quote-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "instances": int(w.n_inst),
+            "quotes_per_instance": int(nq.max()),
+            "chains": int(w.chains),
+            "levels": int(w.n_levels),
+            "steps_per_level": int(w.n_steps),
+            "quote_evals_per_step": qe,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "sa_level_kernel",
+            "achieved": achieved,
+            "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+            "flop_per_launch": flop_launch,
+            "avg_launch_ms": avg_launch_s * 1e3,
+            "launches_timed": int(lvl_ms.size),
+        },
+        "calibration": {
+            "rmse_best": float(rmse.max()),
+            "wall_s_per_step": wall / args.steps,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_levels, w.n_levels))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -158,6 +158,9 @@ typedef struct {
   const double *T0_per_inst; /* [host] nullable [n_inst] per-instance T0 */
   int32_t waves_per_group;   /* chains per workgroup (0 = library default) */
   int32_t use_graph;         /* 1: capture the launch sequence in a hipGraph and replay it */
+  void *const *level_events; /* [host] nullable: 2 * n_levels hipEvent_t recorded on `stream`
+                                just before and just after each level's annealing kernel
+                                (eager launches only; ignored when use_graph = 1) */
 } sa_config;
 
 /* Device workspace bytes sa_calibrate needs for these chain counts. */

@@ -117,6 +117,10 @@ def _mk(m):
     return m if isinstance(m, Market) else Market(m)
 
 
+def max_threads():
+    return lib().oracle_max_threads()
+
+
 def hagan2002_vol(f, K, T, alpha, beta, rho, nu):
     return lib().oracle_hagan2002_vol(f, K, T, alpha, beta, rho, nu)
 

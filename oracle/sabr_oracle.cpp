@@ -695,6 +695,14 @@ extern "C" {
 const char *oracle_last_error(void) { return g_err.c_str(); }
 int32_t oracle_num_params(int32_t model) { return num_params(model); }
 
+int32_t oracle_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 double oracle_hagan2002_vol(double f, double K, double T, double alpha, double beta, double rho,
                             double nu) {
   return hagan2002_vol<double>(f, K, T, alpha, beta, rho, nu);

@@ -53,6 +53,7 @@ typedef struct {
 
 const char *oracle_last_error(void);
 int32_t oracle_num_params(int32_t model);
+int32_t oracle_max_threads(void);   /* OpenMP threads the parallel loops use */
 
 /* Single-quote primitives (pins). */
 double oracle_hagan2002_vol(double f, double K, double T, double alpha, double beta,

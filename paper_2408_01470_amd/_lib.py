@@ -39,7 +39,7 @@ class SAConfig(ctypes.Structure):
         ("T0", ctypes.c_double), ("cool", ctypes.c_double), ("step_frac", ctypes.c_double),
         ("n_levels", ctypes.c_int32), ("n_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
         ("T0_per_inst", _f64p), ("waves_per_group", ctypes.c_int32),
-        ("use_graph", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32), ("level_events", ctypes.POINTER(ctypes.c_void_p)),
     ]
 
 

@@ -109,14 +109,21 @@ class Plan:
 
     # ------------------------------------------------------------------
     def sa_config(self, T0, cool, n_levels, n_steps, seed, step_frac=0.05, T0_per_inst=None,
-                  waves=0, use_graph=False):
+                  waves=0, use_graph=False, level_events=None):
         t0i = None
         if T0_per_inst is not None:
             t0i = np.ascontiguousarray(T0_per_inst, dtype=np.float64)
             self._keep["_t0i"] = t0i
+        ev = None
+        if level_events is not None:
+            # torch.cuda.Event objects, created (recorded once) on the caller's stream
+            ev = (ctypes.c_void_p * len(level_events))(*[e.cuda_event for e in level_events])
+            self._keep["_ev"] = ev
         return SAConfig(float(T0), float(cool), float(step_frac), int(n_levels), int(n_steps),
                         int(seed), t0i.ctypes.data_as(_f64p) if t0i is not None else None,
-                        int(waves), 1 if use_graph else 0)
+                        int(waves), 1 if use_graph else 0,
+                        ctypes.cast(ev, ctypes.POINTER(ctypes.c_void_p)) if ev is not None
+                        else None)
 
     def sa_workspace_bytes(self, cfg, chains):
         ch = np.ascontiguousarray(np.broadcast_to(chains, (self.n_inst,)), dtype=np.int32)
@@ -139,14 +146,14 @@ class Plan:
 
     def sa(self, chains, lb, ub, T0, cool, n_levels, n_steps, seed, step_frac=0.05, x0=None,
            T0_per_inst=None, record=False, trace=True, chain_best=False, waves=0,
-           use_graph=False, stream=None, workspace=None, out=None):
+           use_graph=False, stream=None, workspace=None, out=None, level_events=None):
         """Synchronous parallel simulated annealing on every instance.  ``out``
         (a dict returned by an earlier call with the same shapes) reuses its
         output tensors, so a captured graph can be replayed."""
         L = lib()
         n, P = self.n_inst, self.P
         cfg = self.sa_config(T0, cool, n_levels, n_steps, seed, step_frac, T0_per_inst, waves,
-                             use_graph)
+                             use_graph, level_events)
         ch = np.ascontiguousarray(np.broadcast_to(chains, (n,)), dtype=np.int32)
         lb = np.ascontiguousarray(np.broadcast_to(lb, (n, P)), dtype=np.float64)
         ub = np.ascontiguousarray(np.broadcast_to(ub, (n, P)), dtype=np.float64)

@@ -520,13 +520,20 @@ sabr_status sa_calibrate(const sabr_plan *Pc, const sa_config *cfg, const int32_
   a.chain_best_x = chain_best_x;
   a.chain_best_f = chain_best_f;
 
+  void *const *events = cfg->level_events;
   auto enqueue = [&](hipStream_t q) -> hipError_t {
     hipError_t r = sabr::launch_sa_init(P->dm, a, S.n_tiles, S.waves, q);
     if (r != hipSuccess) return r;
+    const bool ev = events && !cfg->use_graph;
     for (int l = 0; l < L; ++l) {
       if (N > 0) {
+        if (ev && (r = hipEventRecord(static_cast<hipEvent_t>(events[2 * l]), q)) != hipSuccess)
+          return r;
         r = sabr::launch_sa_level(P->dm, a, l, S.n_tiles, S.waves, q);
         if (r != hipSuccess) return r;
+        if (ev && (r = hipEventRecord(static_cast<hipEvent_t>(events[2 * l + 1]), q)) !=
+                      hipSuccess)
+          return r;
       }
       r = sabr::launch_sa_level_end(a, l, q);
       if (r != hipSuccess) return r;
