@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -54,15 +55,16 @@ struct sabr_plan {
   // host copies of the uploaded arrays
   std::vector<DevInst> inst;
   std::vector<double> f_T, f_tauP, f_F;
-  std::vector<int> u_first, u_len;
+  std::vector<int> u_first, u_len, u_order;
   std::vector<double> u_S0, u_A, u_invA, u_T;
-  std::vector<int> q_und, q_kind;
-  std::vector<double> q_f, q_K, q_T, q_D, q_vol, q_wuser;
+  std::vector<sabr::QuoteRec> q;  // und, kind, K filled on the host
+  std::vector<int> q_und_g;
+  std::vector<double> q_vol, q_wuser;
   // device image offsets
-  size_t o_inst, o_fT, o_ftauP, o_fF, o_ufirst, o_ulen, o_uS0, o_uA, o_uinvA, o_qund, o_qkind,
-      o_qf, o_qK, o_qT, o_qD, o_qvol, o_qwuser;  // uploaded (contiguous prefix)
+  size_t o_inst, o_fT, o_ftauP, o_fF, o_ufirst, o_ulen, o_uorder, o_uS0, o_uA, o_uinvA, o_uT,
+      o_q, o_qundg, o_qvol, o_qwuser;  // uploaded (contiguous prefix)
   size_t upload_bytes = 0;
-  size_t o_fv, o_uS0b, o_qsqrtT, o_qL, o_qlfk, o_qlnf, o_qqfix, o_qD1fix, o_qfpfix, o_qtgt, o_qw;
+  size_t o_fv, o_uS0b;
   size_t total_bytes = 0;
   std::vector<unsigned char> staging;
   char *dev = nullptr;
@@ -167,16 +169,22 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
       if (kind != 0 && kind != 1) return bad("quote " + std::to_string(q) + ": bad kind");
       if (!finite_pos(K) || !finite_pos(vol) || !(std::isfinite(w) && w >= 0.0))
         return bad("quote " + std::to_string(q) + ": bad strike, vol or weight");
-      const int gu = d.u0 + u;
-      P->q_und.push_back(u);
-      P->q_kind.push_back(kind);
-      P->q_f.push_back(P->u_S0[gu]);
-      P->q_K.push_back(K);
-      P->q_T.push_back(P->u_T[gu]);
-      P->q_D.push_back(P->u_A[gu]);
+      sabr::QuoteRec R{};
+      R.und = u;
+      R.kind = kind;
+      R.K = K;
+      P->q.push_back(R);
+      P->q_und_g.push_back(d.u0 + u);
       P->q_vol.push_back(vol);
       P->q_wuser.push_back(w);
     }
+    // underlyings by decreasing length (stable), for the swap-map passes
+    std::vector<int> ord(d.nu);
+    for (int u = 0; u < d.nu; ++u) ord[u] = u;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+      return P->u_len[d.u0 + x] > P->u_len[d.u0 + y];
+    });
+    P->u_order.insert(P->u_order.end(), ord.begin(), ord.end());
     if (d.nq > P->max_nq) P->max_nq = d.nq;
     if (d.nu > P->max_nu) P->max_nu = d.nu;
     if (d.nf > P->max_nf) P->max_nf = d.nf;
@@ -191,29 +199,18 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   P->o_fF = L.take<double>(P->nF);
   P->o_ufirst = L.take<int>(P->nU);
   P->o_ulen = L.take<int>(P->nU);
+  P->o_uorder = L.take<int>(P->nU);
   P->o_uS0 = L.take<double>(P->nU);
   P->o_uA = L.take<double>(P->nU);
   P->o_uinvA = L.take<double>(P->nU);
-  P->o_qund = L.take<int>(P->nQ);
-  P->o_qkind = L.take<int>(P->nQ);
-  P->o_qf = L.take<double>(P->nQ);
-  P->o_qK = L.take<double>(P->nQ);
-  P->o_qT = L.take<double>(P->nQ);
-  P->o_qD = L.take<double>(P->nQ);
+  P->o_uT = L.take<double>(P->nU);
+  P->o_q = L.take<sabr::QuoteRec>(P->nQ);
+  P->o_qundg = L.take<int>(P->nQ);
   P->o_qvol = L.take<double>(P->nQ);
   P->o_qwuser = L.take<double>(P->nQ);
   P->upload_bytes = L.off;
   P->o_fv = L.take<double>(P->nF);
   P->o_uS0b = L.take<double>(P->nU);
-  P->o_qsqrtT = L.take<double>(P->nQ);
-  P->o_qL = L.take<double>(P->nQ);
-  P->o_qlfk = L.take<double>(P->nQ);
-  P->o_qlnf = L.take<double>(P->nQ);
-  P->o_qqfix = L.take<double>(P->nQ);
-  P->o_qD1fix = L.take<double>(P->nQ);
-  P->o_qfpfix = L.take<double>(P->nQ);
-  P->o_qtgt = L.take<double>(P->nQ);
-  P->o_qw = L.take<double>(P->nQ);
   P->total_bytes = L.off;
   P->staging.assign(P->upload_bytes, 0);
   auto put = [&](size_t off, const void *src, size_t bytes) {
@@ -225,15 +222,13 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   put(P->o_fF, P->f_F.data(), P->nF * 8);
   put(P->o_ufirst, P->u_first.data(), P->nU * 4);
   put(P->o_ulen, P->u_len.data(), P->nU * 4);
+  put(P->o_uorder, P->u_order.data(), P->nU * 4);
   put(P->o_uS0, P->u_S0.data(), P->nU * 8);
   put(P->o_uA, P->u_A.data(), P->nU * 8);
   put(P->o_uinvA, P->u_invA.data(), P->nU * 8);
-  put(P->o_qund, P->q_und.data(), P->nQ * 4);
-  put(P->o_qkind, P->q_kind.data(), P->nQ * 4);
-  put(P->o_qf, P->q_f.data(), P->nQ * 8);
-  put(P->o_qK, P->q_K.data(), P->nQ * 8);
-  put(P->o_qT, P->q_T.data(), P->nQ * 8);
-  put(P->o_qD, P->q_D.data(), P->nQ * 8);
+  put(P->o_uT, P->u_T.data(), P->nU * 8);
+  put(P->o_q, P->q.data(), P->nQ * sizeof(sabr::QuoteRec));
+  put(P->o_qundg, P->q_und_g.data(), P->nQ * 4);
   put(P->o_qvol, P->q_vol.data(), P->nQ * 8);
   put(P->o_qwuser, P->q_wuser.data(), P->nQ * 8);
   *out = P;
@@ -284,29 +279,16 @@ sabr_status sabr_plan_upload(sabr_plan *P, void *dev_buf, size_t bytes, void *st
   m.f_v = D(P->o_fv);
   m.u_first = I(P->o_ufirst);
   m.u_len = I(P->o_ulen);
+  m.u_order = I(P->o_uorder);
   m.u_S0 = D(P->o_uS0);
   m.u_A = D(P->o_uA);
   m.u_invA = D(P->o_uinvA);
   m.u_S0b = D(P->o_uS0b);
-  m.q_und = I(P->o_qund);
-  m.q_kind = I(P->o_qkind);
-  m.q_f = D(P->o_qf);
-  m.q_K = D(P->o_qK);
-  m.q_T = D(P->o_qT);
-  m.q_sqrtT = D(P->o_qsqrtT);
-  m.q_D = D(P->o_qD);
-  m.q_L = D(P->o_qL);
-  m.q_lfk = D(P->o_qlfk);
-  m.q_lnf = D(P->o_qlnf);
-  m.q_qfix = D(P->o_qqfix);
-  m.q_D1fix = D(P->o_qD1fix);
-  m.q_fpfix = D(P->o_qfpfix);
-  m.q_tgt = D(P->o_qtgt);
-  m.q_w = D(P->o_qw);
-  e = sabr::launch_prep(m, D(P->o_qtgt), D(P->o_qw), D(P->o_qL), D(P->o_qlfk), D(P->o_qlnf),
-                        D(P->o_qsqrtT), D(P->o_qqfix), D(P->o_qD1fix), D(P->o_qfpfix),
-                        D(P->o_fv), D(P->o_uS0b), D(P->o_qvol), D(P->o_qwuser), D(P->o_ftauP),
-                        D(P->o_fF), P->nQ, P->nF, P->nU, s);
+  m.u_T = D(P->o_uT);
+  m.q = reinterpret_cast<const sabr::QuoteRec *>(d + P->o_q);
+  e = sabr::launch_prep(m, reinterpret_cast<sabr::QuoteRec *>(d + P->o_q), D(P->o_fv),
+                        D(P->o_uS0b), D(P->o_qvol), D(P->o_qwuser), I(P->o_qundg),
+                        D(P->o_ftauP), D(P->o_fF), P->nQ, P->nF, P->nU, s);
   if (e != hipSuccess) return hip_fail(e, "market precompute launch");
   P->dev = d;
   P->dm = m;

@@ -2,9 +2,9 @@
 // (gfx950, FP64 vector ALU).
 //
 // Market layout, Philox4x64-10, the Hagan 2002 lognormal implied vol, the
-// paper's eq. (sigmaHagan), Black-76 and wavefront helpers.  Everything here
-// is written for a 64-lane wavefront in which the lanes of one wave either
-// share one parameter point (lanes over quotes) or hold one quote each.
+// paper's eq. (sigmaHagan), Black-76 and wavefront helpers.  The kernels run
+// one 64-lane wavefront per parameter point with the lanes spread over the
+// market's quotes.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -15,10 +15,10 @@ constexpr int kWave = 64;
 constexpr double kInf = __builtin_huge_val();
 
 // ---------------------------------------------------------------------------
-// Packed market (device image).  All arrays are structure-of-arrays over the
-// whole batch; per-instance ranges come from DevInst.  Indices stored in the
-// arrays (underlying of a quote, first forward of an underlying) are local to
-// their instance.
+// Packed market (device image).  Arrays are structure-of-arrays over the
+// whole batch except the quote records, which are 64-byte array-of-structs
+// entries read with 16-byte loads.  Indices stored in the image (underlying
+// of a quote, first forward of an underlying) are local to their instance.
 // ---------------------------------------------------------------------------
 struct DevInst {
   int f0, nf;   // forward range
@@ -27,6 +27,21 @@ struct DevInst {
   int maxlen;   // longest underlying (forwards per swap)
   int pad;
 };
+
+// One quote.  qa/qb/qc hold the market-only factors of the vol formula:
+//   beta a parameter (GLOBAL4): qa = ln(f K), qb = 0, qc = ln f;
+//   beta fixed (LMM12):         qa = (f K)^((1-b)/2), qb = D1(L), qc = f^(1-b).
+struct QuoteRec {
+  double L;     // ln(f/K)
+  double qa, qb;
+  double tgt;   // market vol, or out-of-the-money Black price of the market vol
+  double w;     // weight (price mode: user weight / market vega^2)
+  double qc;
+  int und;      // underlying (local index)
+  int kind;     // 0 call, 1 put
+  double K;     // strike
+};
+static_assert(sizeof(QuoteRec) == 64, "quote record must be 64 bytes");
 
 struct DevMarket {
   int n_inst, model, formula, residual;
@@ -38,18 +53,15 @@ struct DevMarket {
   const double *f_v;     // tau_k P_k F_k^beta (fixed beta)
   // underlyings (caplet = one-period swap)
   const int *u_first, *u_len;
-  const double *u_S0, *u_A, *u_invA, *u_S0b;  // swap rate, annuity, 1/A, S0^beta
+  const int *u_order;    // per instance: underlyings by decreasing length
+  const double *u_S0, *u_A, *u_invA, *u_S0b, *u_T;  // swap rate, annuity, 1/A, S0^beta, expiry
   // quotes
-  const int *q_und, *q_kind;
-  const double *q_f, *q_K, *q_T, *q_sqrtT, *q_D;
-  const double *q_L;      // ln(f/K)
-  const double *q_lfk;    // ln(f K)
-  const double *q_lnf;    // ln f
-  const double *q_qfix;   // (f K)^((1-beta)/2), fixed beta
-  const double *q_D1fix;  // 1 + (1-b)^2 L^2/24 + (1-b)^4 L^4/1920, fixed beta
-  const double *q_fpfix;  // f^(1-beta), fixed beta
-  const double *q_tgt;    // market vol or market Black price
-  const double *q_w;      // weight (price mode: user weight / vega^2)
+  const QuoteRec *q;
+};
+
+// Per-underlying market values staged in LDS by every workgroup.
+struct UndMkt {
+  double f, D, T, sqrtT, isqrtT;
 };
 
 // ---------------------------------------------------------------------------
@@ -91,6 +103,14 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Value of lane l as a wave-uniform (scalar) register.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Orders LDS traffic of one wavefront: a wave's LDS operations execute in
 // issue order, so only the compiler must be kept from reordering them.
 __device__ __forceinline__ void wave_lds_sync() {
@@ -102,53 +122,50 @@ __device__ __forceinline__ void wave_lds_sync() {
 // ---------------------------------------------------------------------------
 // SABR constants of one (alpha, beta, rho, nu): everything in the Hagan
 // formula that does not depend on the quote.
+//   corr q^2 = q^2 + (ca + cb q + cc q^2) T, ca = (1-b)^2 alpha^2/24,
+//   cb = rho beta nu alpha/4, cc = (2 - 3 rho^2) nu^2/24;
+//   z/x(z) = 1 - (rho/2) z + ((2 - 3 rho^2)/12) z^2 + O(z^3)   (s2 below).
 // ---------------------------------------------------------------------------
 struct SabrConst {
-  double alpha, rho, nua;   // nu / alpha
-  double omb, omb2;         // 1 - beta, (1 - beta)^2
-  double ca, cb, cc;        // corr q^2 = q^2 + (ca + cb q + cc q^2) T
-  double s1, s2, s3, s4, s5;  // series of z / x(z) around z = 0
-  double a_fp;              // alpha (eq3 scale numerator)
-  double nu;
+  double alpha, rho, nua;   // nua = nu / alpha
+  double ca, cb, cc, s2;
 };
 
 __device__ __forceinline__ SabrConst sabr_const(double alpha, double beta, double rho, double nu) {
   SabrConst k;
+  const double omb = 1.0 - beta;
+  const double r2 = rho * rho;
   k.alpha = alpha;
   k.rho = rho;
-  k.nu = nu;
   k.nua = nu / alpha;
-  k.omb = 1.0 - beta;
-  k.omb2 = k.omb * k.omb;
-  k.ca = k.omb2 * alpha * alpha * (1.0 / 24.0);
+  k.ca = omb * omb * alpha * alpha * (1.0 / 24.0);
   k.cb = rho * beta * nu * alpha * 0.25;
-  const double r2 = rho * rho;
   k.cc = (2.0 - 3.0 * r2) * nu * nu * (1.0 / 24.0);
-  // z / x(z) = 1 + s1 z + ... + s5 z^5 + O(z^6)  (coefficients from the
-  // Taylor expansion of x(z) = ln((sqrt(1 - 2 rho z + z^2) + z - rho)/(1 - rho)))
-  k.s1 = -0.5 * rho;
   k.s2 = (2.0 - 3.0 * r2) * (1.0 / 12.0);
-  k.s3 = -rho * (6.0 * r2 - 5.0) * (1.0 / 24.0);
-  k.s4 = -((225.0 * r2 - 240.0) * r2 + 34.0) * (1.0 / 720.0);
-  k.s5 = -rho * ((210.0 * r2 - 275.0) * r2 + 74.0) * (1.0 / 480.0);
-  k.a_fp = alpha;
   return k;
 }
 
-constexpr double kZSeries = 0x1.0p-10;  // |z| below which z/x(z) uses the series
+// |z| below which z/x(z) takes its series: three terms leave a truncation
+// error below 1e-17 here, and for larger |z| the log1p form is accurate.
+constexpr double kZSeries = 0x1.0p-18;
 
 // Hagan 2002 lognormal vol given L = ln(f/K), q = (f K)^((1-beta)/2),
-// D1 = 1 + (1-b)^2 L^2/24 + (1-b)^4 L^4/1920 and expiry T:
-//   sigma = alpha chi(z) corr / (q D1),  corr q^2 = q^2 + (ca + cb q + cc q^2) T,
-// evaluated as one division.  x(z) = log1p(t) with t = num/den chosen so that
-// neither num nor den cancels:
+// D1 = 1 + (1-b)^2 L^2/24 + (1-b)^4 L^4/1920 and expiry T, as a fraction
+//   sigma = numer / denom,  numer = alpha corr q^2 chi_num,
+//                           denom = q^3 D1 chi_den,
+// with chi = z/x(z) = chi_num/chi_den.  x(z) = log1p(t), t = num/den chosen so
+// that neither num nor den cancels:
 //   |z| <= 1:  t = 2z / (s + 1 - z)
 //   z  >  1:   t = (s + z - 1) / (1 - rho)
 //   z  < -1:   t = (1 + z - s) / (s - z + rho),      s = sqrt(1 - 2 rho z + z^2);
-// for |z| < 2^-10 the series of z/x(z) replaces the quotient (removable
-// singularity at z = 0, truncation error below 1e-17).
-__device__ __forceinline__ double hagan2002(const SabrConst &k, double L, double q, double D1,
-                                            double T) {
+// for |z| < kZSeries the series replaces the quotient (removable singularity
+// at z = 0).
+struct VolFrac {
+  double numer, denom;
+};
+
+__device__ __forceinline__ VolFrac hagan2002_frac(const SabrConst &k, double L, double q,
+                                                  double D1, double T) {
   const double z = k.nua * q * L;
   const double s = sqrt(fma(z, z - 2.0 * k.rho, 1.0));
   const double az = fabs(z);
@@ -157,11 +174,12 @@ __device__ __forceinline__ double hagan2002(const SabrConst &k, double L, double
   const double den = mid ? (s + 1.0) - z : (z > 0.0 ? 1.0 - k.rho : (s - z) + k.rho);
   const double x = log1p(num / den);
   const bool small = az < kZSeries;
-  const double ser = fma(z, fma(z, fma(z, fma(z, fma(z, k.s5, k.s4), k.s3), k.s2), k.s1), 1.0);
+  const double ser = fma(z, fma(z, k.s2, -0.5 * k.rho), 1.0);
   const double Pq = fma(q, q, T * fma(q, fma(q, k.cc, k.cb), k.ca));
-  const double numer = k.alpha * Pq * (small ? ser : z);
-  const double denom = q * q * q * D1 * (small ? 1.0 : x);
-  return numer / denom;
+  VolFrac v;
+  v.numer = k.alpha * Pq * (small ? ser : z);
+  v.denom = q * q * q * D1 * (small ? 1.0 : x);
+  return v;
 }
 
 __device__ __forceinline__ double d1_term(double omb2, double L) {
@@ -171,36 +189,48 @@ __device__ __forceinline__ double d1_term(double omb2, double L) {
 
 // Paper eq. (sigmaHagan): sigma = (alpha/f^(1-b)) [1 - (1/2)(1-b - rho nu w) k
 //   + (1/12)((1-b)^2 + (2 - 3 rho^2) nu^2 w^2 + 3((1-b) - rho nu w)) k^2],
-// w = f^(1-b)/alpha, k = ln(K/f) = -L, fp = f^(1-b).
-__device__ __forceinline__ double paper_eq3(const SabrConst &k, double L, double fp) {
+// w = f^(1-b)/alpha, k = ln(K/f) = -L, fp = f^(1-b); as a fraction
+// numer/denom like the Hagan 2002 form.
+__device__ __forceinline__ VolFrac paper_eq3_frac(const SabrConst &k, double omb, double L,
+                                                  double fp) {
+  const double nu = k.nua * k.alpha;
   const double w = fp / k.alpha;
-  const double rnw = k.rho * k.nu * w;
+  const double rnw = k.rho * nu * w;
   const double kk = -L;
-  const double c1 = -0.5 * (k.omb - rnw);
-  const double c2 = (k.omb2 + (2.0 - 3.0 * k.rho * k.rho) * k.nu * k.nu * w * w +
-                     3.0 * (k.omb - rnw)) * (1.0 / 12.0);
-  return k.alpha / fp * fma(kk, fma(kk, c2, c1), 1.0);
+  const double c1 = -0.5 * (omb - rnw);
+  const double c2 = (omb * omb + (2.0 - 3.0 * k.rho * k.rho) * nu * nu * w * w +
+                     3.0 * (omb - rnw)) * (1.0 / 12.0);
+  VolFrac v;
+  v.numer = k.alpha * fma(kk, fma(kk, c2, c1), 1.0);
+  v.denom = fp;
+  return v;
 }
 
 // ---------------------------------------------------------------------------
-// Black-76.  The out-of-the-money side (call when K >= f, i.e. L <= 0) is
-// evaluated directly, the other side through put-call parity.  Price
-// residuals are taken between out-of-the-money sides (equal to the quoted
-// side's difference by parity, without cancelling the intrinsic value).
+// Black-76 on the out-of-the-money side (the call when K >= f, i.e. L <= 0;
+// the other side follows by put-call parity, call - put = D (f - K)):
 //   call = D [f N(d1) - K N(d2)],  put = D [K N(-d2) - f N(-d1)],
-//   d1 = L/(sigma sqrt T) + sigma sqrt T / 2,  N(x) = erfc(-x/sqrt 2)/2.
+//   d1 = L/(sigma sqrt T) + sigma sqrt T / 2,  d2 = d1 - sigma sqrt T.
+// With E = exp(-d1^2/2), K exp(-d2^2/2) = f E, and N(y) = E(y) X(y)/2 for
+// y <= 0, 1 - E(y) X(y)/2 for y > 0, X(y) = erfcx(|y|/sqrt 2), one
+// exponential serves both normal tails:
+//   call (d2 < 0 always):  D f [d1 <= 0 ? E (X1 - X2)/2 : 1 - E (X1 + X2)/2]
+//   put  (-d1 < 0 always): D [-d2 <= 0 ? f E (X2 - X1)/2 : K - f E (X1 + X2)/2].
+// Takes 1/sigma so the caller can share one division between sigma and 1/sigma.
 // ---------------------------------------------------------------------------
-// Price of the out-of-the-money side (call when L <= 0).
 __device__ __forceinline__ double black_otm(double f, double K, double L, double sqrtT,
-                                            double sigma, double D) {
+                                            double isqrtT, double sigma, double isigma,
+                                            double D) {
   const double sd = sigma * sqrtT;
-  const double d1 = L / sd + 0.5 * sd;
+  const double d1 = fma(L * isigma, isqrtT, 0.5 * sd);
   const double d2 = d1 - sd;
-  const bool otm_call = L <= 0.0;
-  const double sg = otm_call ? 1.0 : -1.0;  // N(sg d) with sg = -1 for the put
-  const double n1 = 0.5 * erfc(-sg * d1 * M_SQRT1_2);
-  const double n2 = 0.5 * erfc(-sg * d2 * M_SQRT1_2);
-  return otm_call ? D * (f * n1 - K * n2) : D * (K * n2 - f * n1);
+  const double E = exp(-0.5 * d1 * d1);
+  const double X1 = erfcx(fabs(d1) * M_SQRT1_2);
+  const double X2 = erfcx(fabs(d2) * M_SQRT1_2);
+  const double hE = 0.5 * f * E;
+  if (L <= 0.0)
+    return D * (d1 <= 0.0 ? hE * (X1 - X2) : fma(-hE, X1 + X2, f));
+  return D * (d2 >= 0.0 ? hE * (X2 - X1) : fma(-hE, X1 + X2, K));
 }
 
 // Intrinsic value to add to the out-of-the-money price to get the quoted side.
@@ -209,13 +239,6 @@ __device__ __forceinline__ double parity_shift(int kind, double f, double K, dou
   const bool want_call = (kind == 0);
   if (want_call == otm_call) return 0.0;
   return want_call ? D * (f - K) : D * (K - f);
-}
-
-__device__ __forceinline__ double black(int kind, double f, double K, double L, double sqrtT,
-                                        double sigma, double D) {
-  const double v = black_otm(f, K, L, sqrtT, sigma, D);
-  const double sh = parity_shift(kind, f, K, L, D);
-  return sh == 0.0 ? v : v + sh;
 }
 
 __device__ __forceinline__ double black_vega(double f, double L, double sqrtT, double sigma,

@@ -9,11 +9,12 @@
 namespace sabr {
 
 // Doubles of LDS one wavefront needs for the LMM12 maps: per-forward alpha,
-// nu and the two correlation gap factors, per-underlying (alpha, rho, nu,
-// nu/alpha), and a per-lane column of max_len doubles for the swap recursion.
+// nu and the two correlation gap factors, seven SABR constants per
+// underlying, and a per-lane column of max_len doubles for the swap
+// recursion.  Each workgroup adds 5 doubles per underlying of market values.
 inline int wave_lds_doubles(const DevMarket &m) {
   if (m.model == 0) return 0;
-  return 4 * m.max_nf + 4 * m.max_nu + kWave * m.max_len;
+  return 4 * m.max_nf + 7 * m.max_nu + kWave * m.max_len;
 }
 
 struct SAArgs {
@@ -38,11 +39,10 @@ struct SAArgs {
   double *chain_best_x, *chain_best_f;  // nullable
 };
 
-hipError_t launch_prep(const DevMarket &m, double *q_tgt, double *q_w, double *q_L,
-                       double *q_lfk, double *q_lnf, double *q_sqrtT, double *q_qfix,
-                       double *q_D1fix, double *q_fpfix, double *f_v, double *u_S0b,
-                       const double *q_vol, const double *q_wuser, const double *f_tauP,
-                       const double *f_F, int n_q, int n_f, int n_u, hipStream_t s);
+hipError_t launch_prep(const DevMarket &m, QuoteRec *q, double *f_v, double *u_S0b,
+                       const double *q_vol, const double *q_wuser, const int *q_und_g,
+                       const double *f_tauP, const double *f_F, int n_q, int n_f, int n_u,
+                       hipStream_t s);
 
 hipError_t launch_cost(const DevMarket &m, int n_pts, const int *pt_inst, const double *params,
                        double *cost, double *resid, double *model, int stride, hipStream_t s);

@@ -1,9 +1,13 @@
 // sabr_kernels.hip -- HIP kernels of the SA calibrator for gfx950.
 //
 // Mapping: one 64-lane wavefront evaluates one parameter point (one Markov
-// chain) with its lanes spread over the market's quotes; the per-quote
-// squared errors are summed per lane and reduced across the wave.  The
-// FP64 vector ALU bounds every kernel here (no dense contraction: no MFMA).
+// chain) with its lanes spread over the market's quotes; each lane sums its
+// quotes' weighted squared errors and the wave reduces the sums.  A
+// workgroup holds W chains of one instance and stages that instance's
+// per-underlying market values in LDS.  Parameter vectors live distributed
+// over lanes (lane k holds coordinate k) and are broadcast to scalar
+// registers when the cost needs them.  The FP64 vector ALU bounds every
+// kernel here (no dense contraction: no MFMA).
 #include <hip/hip_runtime.h>
 
 #include "sabr_internal.hpp"
@@ -23,10 +27,13 @@ struct NP<1> {
   static constexpr int P = 12;
 };
 
+// Per-wave LDS scratch of the LMM12 map: per forward alpha, nu and the two
+// correlation gap factors; per underlying the SABR constants; a per-lane
+// column for the swap recursion.
 struct WaveLds {
-  double *al, *nv, *g1, *g2;  // per forward
-  double *ta, *tr, *tn, *tq;  // per underlying
-  double *lk;                 // per-lane recursion column
+  double *al, *nv, *g1, *g2;                     // [max_nf]
+  double *ta, *tr, *tq, *tca, *tcb, *tcc, *ts2;  // [max_nu]
+  double *lk;                                    // [max_len][64]
 };
 
 __device__ __forceinline__ WaveLds wave_lds(const DevMarket &m, double *base) {
@@ -37,10 +44,19 @@ __device__ __forceinline__ WaveLds wave_lds(const DevMarket &m, double *base) {
   w.g2 = w.g1 + m.max_nf;
   w.ta = w.g2 + m.max_nf;
   w.tr = w.ta + m.max_nu;
-  w.tn = w.tr + m.max_nu;
-  w.tq = w.tn + m.max_nu;
-  w.lk = w.tq + m.max_nu;
+  w.tq = w.tr + m.max_nu;
+  w.tca = w.tq + m.max_nu;
+  w.tcb = w.tca + m.max_nu;
+  w.tcc = w.tcb + m.max_nu;
+  w.ts2 = w.tcc + m.max_nu;
+  w.lk = w.ts2 + m.max_nu;
   return w;
+}
+
+__device__ __forceinline__ UndMkt und_mkt(const DevMarket &m, int g) {
+  const double T = m.u_T[g];
+  const double sT = sqrt(T);
+  return UndMkt{m.u_S0[g], m.u_A[g], T, sT, 1.0 / sT};
 }
 
 // LMM12 parameter map of one point into the wave's LDS.  Returns true when
@@ -48,23 +64,27 @@ __device__ __forceinline__ WaveLds wave_lds(const DevMarket &m, double *base) {
 //   alpha_k = (a + b T_k) e^{-c T_k} + d, nu_k likewise (abcd forms);
 //   rho_kl = exp(-lambda1 |T_k - T_l|) = product of per-gap factors g1,
 //   theta_kl = eta2 + (1 - eta2) exp(-lambda2 |T_k - T_l|), phi_kl = rho.
-// Swap of forwards [e, e+n) with a_k = u_k alpha_k (u_k = tau_k P_k F_k^b / A):
+// Swap of forwards [e, e+n) with a_k = v_k alpha_k (v_k = tau_k P_k F_k^b;
+// the weights w_k = tau_k P_k / A enter through the common factor 1/A):
 //   R_k = sum_l a_l rho_kl (forward and backward recursions, O(n)),
 //   V = sum a_k R_k, b_k = a_k R_k nu_k,
 //   Nb = eta2 (sum b)^2 + (1 - eta2) sum_kl b_k b_l exp(-lambda2 |dT|),
-//   alpha_S = sqrt(V)/S0^b, nu_S = sqrt(Nb)/V,
+//   alpha_S = sqrt(V)/(A S0^b), nu_S = sqrt(Nb)/V,
 //   rho_S = rho (sum a)(sum b) / (sqrt(V) sqrt(Nb))   (0 if Nb = 0).
+// Underlyings are visited in decreasing length so the lanes of a pass run
+// recursions of similar length.
 __device__ bool lmm12_map(const DevMarket &m, const DevInst &in, const double *p, WaveLds w) {
   const int lane = lane_id();
   const double a = p[0], b = p[1], c = p[2], d = p[3];
   const double an = p[4], bn = p[5], cn = p[6], dn = p[7];
   const double rho = p[8], lam1 = p[9], eta2 = p[10], lam2 = p[11];
+  const double beta = m.beta, omb = 1.0 - beta;
   bool bad = !(fabs(rho) < 1.0) || !(lam1 >= 0.0) || !(lam2 >= 0.0) ||
              !(eta2 >= 0.0 && eta2 <= 1.0);
   for (int k = lane; k < in.nf; k += kWave) {
     const double T = m.f_T[in.f0 + k];
-    w.al[k] = (a + b * T) * exp(-(c * T)) + d;
-    w.nv[k] = (an + bn * T) * exp(-(cn * T)) + dn;
+    w.al[k] = fma(b, T, a) * exp(-(c * T)) + d;
+    w.nv[k] = fma(bn, T, an) * exp(-(cn * T)) + dn;
     if (k + 1 < in.nf) {
       const double dT = m.f_T[in.f0 + k + 1] - T;
       w.g1[k] = exp(-(lam1 * dT));
@@ -73,23 +93,24 @@ __device__ bool lmm12_map(const DevMarket &m, const DevInst &in, const double *p
   }
   wave_lds_sync();
   double *lk = w.lk + lane;
-  for (int u = lane; u < in.nu; u += kWave) {
+  const double *v = m.f_v + in.f0;
+  for (int i = lane; i < in.nu; i += kWave) {
+    const int u = m.u_order[in.u0 + i];
     const int e = m.u_first[in.u0 + u];
     const int n = m.u_len[in.u0 + u];
-    for (int k = e; k < e + n; ++k) bad |= !(w.al[k] > 0.0) || !(w.nv[k] >= 0.0);
     double ta, tr, tn;
     if (n == 1) {
       ta = w.al[e];
       tr = rho;
       tn = w.nv[e];
+      bad |= !(ta > 0.0) || !(tn >= 0.0);
     } else {
-      const double invA = m.u_invA[in.u0 + u];
-      const double S0b = m.u_S0b[in.u0 + u];
-      const double *v = m.f_v + in.f0;
       double Lacc = 0.0, suma = 0.0;
       for (int j = 0; j < n; ++j) {
         const int k = e + j;
-        const double aj = v[k] * invA * w.al[k];
+        const double alk = w.al[k];
+        bad |= !(alk > 0.0) || !(w.nv[k] >= 0.0);
+        const double aj = v[k] * alk;
         lk[j * kWave] = Lacc;
         suma += aj;
         Lacc = w.g1[k] * (Lacc + aj);
@@ -97,93 +118,105 @@ __device__ bool lmm12_map(const DevMarket &m, const DevInst &in, const double *p
       double Rr = 0.0, Rb = 0.0, V = 0.0, Sb = 0.0, Sbb = 0.0;
       for (int j = n - 1; j >= 0; --j) {
         const int k = e + j;
-        const double aj = v[k] * invA * w.al[k];
+        const double aj = v[k] * w.al[k];
         const double Rj = lk[j * kWave] + aj + Rr;
         const double ar = aj * Rj;
         V += ar;
         const double bj = ar * w.nv[k];
         Sb += bj;
-        Sbb += bj * (bj + 2.0 * Rb);
+        Sbb = fma(bj, fma(2.0, Rb, bj), Sbb);
         if (j > 0) {
           Rr = w.g1[k - 1] * (Rr + aj);
           Rb = w.g2[k - 1] * (Rb + bj);
         }
       }
-      const double Nb = eta2 * Sb * Sb + (1.0 - eta2) * Sbb;
+      const double Nb = fma(eta2 * Sb, Sb, (1.0 - eta2) * Sbb);
       const double sV = sqrt(V), sN = sqrt(Nb);
-      ta = sV / S0b;
+      ta = sV * m.u_invA[in.u0 + u] / m.u_S0b[in.u0 + u];
       tn = sN / V;
       tr = (sN > 0.0) ? rho * suma * Sb / (sV * sN) : 0.0;
       bad |= !(V > 0.0) || !(fabs(tr) < 1.0);
     }
+    const double r2 = tr * tr;
     w.ta[u] = ta;
     w.tr[u] = tr;
-    w.tn[u] = tn;
     w.tq[u] = tn / ta;
+    w.tca[u] = omb * omb * ta * ta * (1.0 / 24.0);
+    w.tcb[u] = tr * beta * tn * ta * 0.25;
+    w.tcc[u] = (2.0 - 3.0 * r2) * tn * tn * (1.0 / 24.0);
+    w.ts2[u] = (2.0 - 3.0 * r2) * (1.0 / 12.0);
   }
   wave_lds_sync();
   return __any(bad);
 }
 
-// Cost of one point for the wave: f = sum_q w_q (m_q - mkt_q)^2, +inf on a
-// domain failure.  Optional per-quote residual and model outputs.
+// Cost of one point for the wave: f = sum_q w_q r_q^2, +inf on a domain
+// failure.  p[] is wave-uniform.  Optional per-quote residual and model
+// outputs (the quoted side in price mode).
 template <int MODEL, int FORMULA, int RESID>
-__device__ double point_cost(const DevMarket &m, int inst, const double *p, WaveLds w,
-                             double *resid, double *model) {
-  const DevInst in = m.inst[inst];
+__device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt *um,
+                             const double *p, WaveLds w, double *resid, double *model) {
   const int lane = lane_id();
   bool bad = false;
   SabrConst g{};
+  double omb, omb2 = 0.0;
   if (MODEL == 0) {
     bad = !(p[0] > 0.0) || !(p[1] >= 0.0 && p[1] <= 1.0) || !(fabs(p[2]) < 1.0) ||
           !(p[3] >= 0.0);
     g = sabr_const(p[0], p[1], p[2], p[3]);
+    omb = 1.0 - p[1];
+    omb2 = omb * omb;
   } else {
     bad = lmm12_map(m, in, p, w);
+    omb = 1.0 - m.beta;
   }
-  const double beta = (MODEL == 0) ? p[1] : m.beta;
   double acc = 0.0;
   for (int q = lane; q < in.nq; q += kWave) {
-    const int gq = in.q0 + q;
-    const double L = m.q_L[gq];
-    const double T = m.q_T[gq];
+    const QuoteRec &R = m.q[in.q0 + q];
+    const double L = R.L;
+    const int u = R.und;
+    const UndMkt U = um[u];
     SabrConst k;
-    double qv = 1.0, D1 = 1.0, fp = 1.0;
     if (MODEL == 0) {
       k = g;
-      if (FORMULA == 0) {
-        qv = exp(0.5 * k.omb * m.q_lfk[gq]);
-        D1 = d1_term(k.omb2, L);
-      } else {
-        fp = exp(k.omb * m.q_lnf[gq]);
-      }
     } else {
-      const int u = m.q_und[gq];
-      k = sabr_const(w.ta[u], beta, w.tr[u], w.tn[u]);
+      k.alpha = w.ta[u];
+      k.rho = w.tr[u];
       k.nua = w.tq[u];
-      if (FORMULA == 0) {
-        qv = m.q_qfix[gq];
-        D1 = m.q_D1fix[gq];
-      } else {
-        fp = m.q_fpfix[gq];
-      }
+      k.ca = w.tca[u];
+      k.cb = w.tcb[u];
+      k.cc = w.tcc[u];
+      k.s2 = w.ts2[u];
     }
-    const double sig = (FORMULA == 0) ? hagan2002(k, L, qv, D1, T) : paper_eq3(k, L, fp);
-    bad |= !(sig > 0.0) || !(fabs(sig) < kInf);
-    double mv = sig;
-    if (RESID == 1) {
-      const double f = m.q_f[gq], K = m.q_K[gq], D = m.q_D[gq];
-      mv = black_otm(f, K, L, m.q_sqrtT[gq], sig, D);
+    VolFrac vf;
+    if (FORMULA == 0) {
+      const double qv = (MODEL == 0) ? exp(0.5 * omb * R.qa) : R.qa;
+      const double D1 = (MODEL == 0) ? d1_term(omb2, L) : R.qb;
+      vf = hagan2002_frac(k, L, qv, D1, U.T);
+    } else {
+      const double fp = (MODEL == 0) ? exp(omb * R.qc) : R.qc;
+      vf = paper_eq3_frac(k, omb, L, fp);
+    }
+    double mv;
+    if (RESID == 0) {
+      mv = vf.numer / vf.denom;
+      bad |= !(mv > 0.0) || !(mv < kInf);
+      if (model) model[q] = mv;
+    } else {
+      // one division gives sigma = numer/denom and 1/sigma = denom/numer
+      const double rr = 1.0 / (vf.numer * vf.denom);
+      const double sig = vf.numer * (vf.numer * rr);
+      const double isig = vf.denom * (vf.denom * rr);
+      bad |= !(sig > 0.0) || !(sig < kInf);
+      mv = black_otm(U.f, R.K, L, U.sqrtT, U.isqrtT, sig, isig, U.D);
       bad |= !(fabs(mv) < kInf);
       if (model) {
-        const double sh = parity_shift(m.q_kind[gq], f, K, L, D);
+        const double sh = parity_shift(R.kind, U.f, R.K, L, U.D);
         model[q] = sh == 0.0 ? mv : mv + sh;
       }
-    } else if (model) {
-      model[q] = mv;
     }
-    const double r = mv - m.q_tgt[gq];
-    acc += m.q_w[gq] * r * r;
+    const double r = mv - R.tgt;
+    acc = fma(R.w * r, r, acc);
     if (resid) resid[q] = r;
   }
   const double tot = wave_sum(acc);
@@ -192,37 +225,42 @@ __device__ double point_cost(const DevMarket &m, int inst, const double *p, Wave
 }
 
 // ---------------------------------------------------------------------------
-// Market precompute (market-only quantities, once per upload).
+// Market precompute (market-only quantities, once per upload).  The host has
+// written und, kind and K of every quote record; this fills the rest.
 // ---------------------------------------------------------------------------
-__global__ void prep_kernel(DevMarket m, double *q_tgt, double *q_w, double *q_L, double *q_lfk,
-                            double *q_lnf, double *q_sqrtT, double *q_qfix, double *q_D1fix,
-                            double *q_fpfix, double *f_v, double *u_S0b, const double *q_vol,
-                            const double *q_wuser, const double *f_tauP, const double *f_F,
-                            int n_q, int n_f, int n_u) {
+__global__ void prep_kernel(DevMarket m, QuoteRec *q, double *f_v, double *u_S0b,
+                            const double *q_vol, const double *q_wuser, const int *q_und_g,
+                            const double *f_tauP, const double *f_F, int n_q, int n_f, int n_u) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const double beta = m.beta, omb = 1.0 - beta;
   if (i < n_f) f_v[i] = f_tauP[i] * pow(f_F[i], beta);
   if (i < n_u) u_S0b[i] = pow(m.u_S0[i], beta);
   if (i >= n_q) return;
-  const double f = m.q_f[i], K = m.q_K[i], T = m.q_T[i];
+  const int gu = q_und_g[i];
+  QuoteRec R = q[i];
+  const double f = m.u_S0[gu], K = R.K, T = m.u_T[gu], D = m.u_A[gu];
   const double L = log(f / K);
   const double sT = sqrt(T);
-  q_L[i] = L;
-  q_lfk[i] = log(f * K);
-  q_lnf[i] = log(f);
-  q_sqrtT[i] = sT;
-  q_qfix[i] = pow(f * K, 0.5 * omb);
-  q_D1fix[i] = d1_term(omb * omb, L);
-  q_fpfix[i] = pow(f, omb);
+  R.L = L;
+  if (m.model == 0) {
+    R.qa = log(f * K);
+    R.qb = 0.0;
+    R.qc = log(f);
+  } else {
+    R.qa = pow(f * K, 0.5 * omb);
+    R.qb = d1_term(omb * omb, L);
+    R.qc = pow(f, omb);
+  }
   const double vol = q_vol[i];
   if (m.residual == 0) {
-    q_tgt[i] = vol;
-    q_w[i] = q_wuser[i];
+    R.tgt = vol;
+    R.w = q_wuser[i];
   } else {
-    q_tgt[i] = black_otm(f, K, L, sT, vol, m.q_D[i]);
-    const double vg = black_vega(f, L, sT, vol, m.q_D[i]);
-    q_w[i] = q_wuser[i] / (vg * vg);
+    R.tgt = black_otm(f, K, L, sT, 1.0 / sT, vol, 1.0 / vol, D);
+    const double vg = black_vega(f, L, sT, vol, D);
+    R.w = q_wuser[i] / (vg * vg);
   }
+  q[i] = R;
 }
 
 // ---------------------------------------------------------------------------
@@ -235,20 +273,27 @@ __global__ __launch_bounds__(256) void cost_kernel(DevMarket m, int n_pts, const
                                                    int lds_per_wave) {
   extern __shared__ double smem[];
   constexpr int P = NP<MODEL>::P;
-  const int wid = threadIdx.x / kWave;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int pt = blockIdx.x * (blockDim.x / kWave) + wid;
   if (pt >= n_pts) return;
-  const int inst = pt_inst[pt];
+  const int inst = __builtin_amdgcn_readfirstlane(pt_inst[pt]);
   if (inst < 0 || inst >= m.n_inst) {
     if (lane_id() == 0) cost[pt] = __builtin_nan("");
     return;
   }
+  const DevInst in = m.inst[inst];
+  // each wave stages its own copy: the points of one workgroup may belong to
+  // different instances
+  double *base = smem + (size_t)wid * lds_per_wave;
+  UndMkt *um = reinterpret_cast<UndMkt *>(base);
+  for (int u = lane_id(); u < in.nu; u += kWave) um[u] = und_mkt(m, in.u0 + u);
+  wave_lds_sync();
   double p[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) p[k] = params[(size_t)pt * P + k];
-  WaveLds w = wave_lds(m, smem + (size_t)wid * lds_per_wave);
+  WaveLds w = wave_lds(m, base + 5 * m.max_nu);
   const double c = point_cost<MODEL, FORMULA, RESID>(
-      m, inst, p, w, resid ? resid + (size_t)pt * stride : nullptr,
+      m, in, um, p, w, resid ? resid + (size_t)pt * stride : nullptr,
       model ? model + (size_t)pt * stride : nullptr);
   if (lane_id() == 0) cost[pt] = c;
 }
@@ -273,29 +318,46 @@ __device__ __forceinline__ double propose1(double x, double u, double lo, double
   return y;
 }
 
+template <int P>
+__device__ __forceinline__ void broadcast_params(double xl, double *p) {
+#pragma unroll
+  for (int k = 0; k < P; ++k) p[k] = readlane_d(xl, k);
+}
+
+__device__ __forceinline__ UndMkt *stage_underlyings(const DevMarket &m, const DevInst &in,
+                                                     double *smem) {
+  UndMkt *um = reinterpret_cast<UndMkt *>(smem);
+  for (int u = threadIdx.x; u < in.nu; u += blockDim.x) um[u] = und_mkt(m, in.u0 + u);
+  __syncthreads();
+  return um;
+}
+
 template <int MODEL, int FORMULA, int RESID>
 __global__ __launch_bounds__(256) void sa_init_kernel(DevMarket m, SAArgs a, int lds_per_wave) {
   extern __shared__ double smem[];
   constexpr int P = NP<MODEL>::P;
-  const int wid = threadIdx.x / kWave;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = lane_id();
   const int inst = a.tile_inst[blockIdx.x];
+  const DevInst in = m.inst[inst];
+  const UndMkt *um = stage_underlyings(m, in, smem);
   const int c = a.tile_chain[blockIdx.x] + wid;
   if (c >= a.chains[inst]) return;
+  const double xl = (lane < P) ? a.x0[(size_t)inst * P + lane] : 0.0;
   double x[P];
-#pragma unroll
-  for (int k = 0; k < P; ++k) x[k] = a.x0[(size_t)inst * P + k];
-  WaveLds w = wave_lds(m, smem + (size_t)wid * lds_per_wave);
-  const double f = point_cost<MODEL, FORMULA, RESID>(m, inst, x, w, nullptr, nullptr);
-  if (lane_id() == 0) {
-    const int64_t gc = a.chain_base[inst] + c;
-    for (int k = 0; k < P; ++k) {
-      a.X[gc * P + k] = x[k];
-      a.BX[gc * P + k] = x[k];
-    }
+  broadcast_params<P>(xl, x);
+  WaveLds w = wave_lds(m, smem + 5 * m.max_nu + (size_t)wid * lds_per_wave);
+  const double f = point_cost<MODEL, FORMULA, RESID>(m, in, um, x, w, nullptr, nullptr);
+  const int64_t gc = a.chain_base[inst] + c;
+  if (lane < P) {
+    a.X[gc * P + lane] = xl;
+    a.BX[gc * P + lane] = xl;
+    if (c == 0) a.RX[(size_t)inst * P + lane] = xl;
+  }
+  if (lane == 0) {
     a.F[gc] = f;
     a.BF[gc] = f;
     if (c == 0) {
-      for (int k = 0; k < P; ++k) a.RX[(size_t)inst * P + k] = x[k];
       a.RF[inst] = f;
       a.Tcur[inst] = a.T0[inst];
       if (inst == 0) a.t_start[0] = wall_clock64();
@@ -308,46 +370,47 @@ __global__ __launch_bounds__(256) void sa_level_kernel(DevMarket m, SAArgs a, in
                                                        int lds_per_wave) {
   extern __shared__ double smem[];
   constexpr int P = NP<MODEL>::P;
-  constexpr int NBLK = (P + 1 + 3) / 4;
-  const int wid = threadIdx.x / kWave;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = lane_id();
   const int inst = a.tile_inst[blockIdx.x];
+  const DevInst in = m.inst[inst];
+  const UndMkt *um = stage_underlyings(m, in, smem);
   const int C = a.chains[inst];
   const int c = a.tile_chain[blockIdx.x] + wid;
   if (c >= C) return;
   const int64_t gc = a.chain_base[inst] + c;
-  double x[P], lo[P], hi[P];
-#pragma unroll
-  for (int k = 0; k < P; ++k) {
-    x[k] = a.RX[(size_t)inst * P + k];
-    lo[k] = a.lb[(size_t)inst * P + k];
-    hi[k] = a.ub[(size_t)inst * P + k];
-  }
+  // lane k < P holds coordinate k of the chain's point, best point and box
+  const bool own = lane < P;
+  double x = own ? a.RX[(size_t)inst * P + lane] : 0.0;
+  const double lo = own ? a.lb[(size_t)inst * P + lane] : 0.0;
+  const double hi = own ? a.ub[(size_t)inst * P + lane] : 0.0;
+  double bx = own ? a.BX[gc * P + lane] : 0.0;
   double f = a.RF[inst];
   double bf = a.BF[gc];
   const double T = a.Tcur[inst];
-  WaveLds w = wave_lds(m, smem + (size_t)wid * lds_per_wave);
+  WaveLds w = wave_lds(m, smem + 5 * m.max_nu + (size_t)wid * lds_per_wave);
   int nacc = 0;
   for (int s = 0; s < a.N; ++s) {
-    double u[4 * NBLK];
-    const uint64_t ctr0 = (uint64_t)level * (uint64_t)a.N + (uint64_t)s;
-#pragma unroll
-    for (int b = 0; b < NBLK; ++b) {
+    // uniforms u_0..u_P: lane k <= P takes word k mod 4 of Philox block k/4
+    double u = 0.0;
+    if (lane <= P) {
       uint64_t wds[4];
-      philox4x64_10(ctr0, (uint64_t)c, (uint64_t)b, 0, a.seed, (uint64_t)inst, wds);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) u[4 * b + j] = u53(wds[j]);
+      philox4x64_10((uint64_t)level * (uint64_t)a.N + (uint64_t)s, (uint64_t)c,
+                    (uint64_t)(lane >> 2), 0, a.seed, (uint64_t)inst, wds);
+      const int j = lane & 3;
+      const uint64_t wd = j == 0 ? wds[0] : (j == 1 ? wds[1] : (j == 2 ? wds[2] : wds[3]));
+      u = u53(wd);
     }
-    double xp[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) xp[k] = propose1(x[k], u[k], lo[k], hi[k], a.step_frac);
-    double fp = point_cost<MODEL, FORMULA, RESID>(m, inst, xp, w, nullptr, nullptr);
+    const double xp = own ? propose1(x, u, lo, hi, a.step_frac) : 0.0;
+    double p[P];
+    broadcast_params<P>(xp, p);
+    double fp = point_cost<MODEL, FORMULA, RESID>(m, in, um, p, w, nullptr, nullptr);
     if (fp != fp) fp = kInf;
+    const double uP = readlane_d(u, P);
     const double dE = fp - f;
-    const bool acc = (dE <= 0.0) || (u[P] < exp(-dE / T));
+    const bool acc = (dE <= 0.0) || (uP < exp(-dE / T));
     if (acc) {
-#pragma unroll
-      for (int k = 0; k < P; ++k) x[k] = xp[k];
+      x = xp;
       f = fp;
       ++nacc;
     }
@@ -355,12 +418,14 @@ __global__ __launch_bounds__(256) void sa_level_kernel(DevMarket m, SAArgs a, in
       a.accept[a.acc_base[inst] + ((int64_t)level * a.N + s) * C + c] = acc ? 1 : 0;
     if (fp < bf) {
       bf = fp;
-      if (lane == 0)
-        for (int k = 0; k < P; ++k) a.BX[gc * P + k] = xp[k];
+      bx = xp;
     }
   }
+  if (own) {
+    a.X[gc * P + lane] = x;
+    a.BX[gc * P + lane] = bx;
+  }
   if (lane == 0) {
-    for (int k = 0; k < P; ++k) a.X[gc * P + k] = x[k];
     a.F[gc] = f;
     a.BF[gc] = bf;
     a.NACC[gc] = nacc;
@@ -475,18 +540,16 @@ __global__ __launch_bounds__(256) void sa_final_kernel(SAArgs a) {
 // ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
-hipError_t launch_prep(const DevMarket &m, double *q_tgt, double *q_w, double *q_L,
-                       double *q_lfk, double *q_lnf, double *q_sqrtT, double *q_qfix,
-                       double *q_D1fix, double *q_fpfix, double *f_v, double *u_S0b,
-                       const double *q_vol, const double *q_wuser, const double *f_tauP,
-                       const double *f_F, int n_q, int n_f, int n_u, hipStream_t s) {
+hipError_t launch_prep(const DevMarket &m, QuoteRec *q, double *f_v, double *u_S0b,
+                       const double *q_vol, const double *q_wuser, const int *q_und_g,
+                       const double *f_tauP, const double *f_F, int n_q, int n_f, int n_u,
+                       hipStream_t s) {
   int n = n_q;
   if (n_f > n) n = n_f;
   if (n_u > n) n = n_u;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(prep_kernel, dim3((n + 255) / 256), dim3(256), 0, s, m, q_tgt, q_w, q_L,
-                     q_lfk, q_lnf, q_sqrtT, q_qfix, q_D1fix, q_fpfix, f_v, u_S0b, q_vol, q_wuser,
-                     f_tauP, f_F, n_q, n_f, n_u);
+  hipLaunchKernelGGL(prep_kernel, dim3((n + 255) / 256), dim3(256), 0, s, m, q, f_v, u_S0b,
+                     q_vol, q_wuser, q_und_g, f_tauP, f_F, n_q, n_f, n_u);
   return hipGetLastError();
 }
 
@@ -507,18 +570,38 @@ hipError_t launch_prep(const DevMarket &m, double *q_tgt, double *q_w, double *q
     }                                                                \
   } while (0)
 
-static int waves_for_lds(int lds_doubles, int want) {
-  if (lds_doubles == 0) return want;
-  int w = (64 * 1024) / (lds_doubles * 8);
-  if (w > want) w = want;
-  return w < 1 ? 1 : w;
+int lds_budget_bytes() {
+  static int bytes = 0;
+  if (bytes == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        v > 0)
+      bytes = v;
+    else
+      bytes = 64 * 1024;
+  }
+  return bytes;
+}
+
+size_t sa_lds_bytes(const DevMarket &m, int waves) {
+  return (size_t)(5 * m.max_nu + waves * wave_lds_doubles(m)) * 8;
+}
+
+int sa_waves_per_group(const DevMarket &m, int want) {
+  int w = want;
+  while (w > 1 && (long)sa_lds_bytes(m, w) > lds_budget_bytes()) --w;
+  return w;
 }
 
 hipError_t launch_cost(const DevMarket &m, int n_pts, const int *pt_inst, const double *params,
                        double *cost, double *resid, double *model, int stride, hipStream_t s) {
   if (n_pts == 0) return hipSuccess;
-  const int ld = wave_lds_doubles(m);
-  const int waves = waves_for_lds(ld, 4);
+  // cost waves keep their own copy of the per-underlying market values
+  const int ld = wave_lds_doubles(m) + 5 * m.max_nu;
+  if ((long)ld * 8 > lds_budget_bytes()) return hipErrorInvalidValue;
+  int waves = 4;
+  while (waves > 1 && (long)ld * 8 * waves > lds_budget_bytes()) --waves;
   const dim3 grid((n_pts + waves - 1) / waves), block(kWave * waves);
   const size_t lds = (size_t)ld * 8 * waves;
 #define CALL(A, B, C)                                                                      \
@@ -532,7 +615,7 @@ hipError_t launch_cost(const DevMarket &m, int n_pts, const int *pt_inst, const 
 hipError_t launch_sa_init(const DevMarket &m, const SAArgs &a, int n_tiles, int waves,
                           hipStream_t s) {
   const int ld = wave_lds_doubles(m);
-  const size_t lds = (size_t)ld * 8 * waves;
+  const size_t lds = sa_lds_bytes(m, waves);
 #define CALL(A, B, C)                                                                    \
   hipLaunchKernelGGL((sa_init_kernel<A, B, C>), dim3(n_tiles), dim3(kWave * waves), lds, s, \
                      m, a, ld)
@@ -544,7 +627,7 @@ hipError_t launch_sa_init(const DevMarket &m, const SAArgs &a, int n_tiles, int 
 hipError_t launch_sa_level(const DevMarket &m, const SAArgs &a, int level, int n_tiles,
                            int waves, hipStream_t s) {
   const int ld = wave_lds_doubles(m);
-  const size_t lds = (size_t)ld * 8 * waves;
+  const size_t lds = sa_lds_bytes(m, waves);
 #define CALL(A, B, C)                                                                     \
   hipLaunchKernelGGL((sa_level_kernel<A, B, C>), dim3(n_tiles), dim3(kWave * waves), lds, s, \
                      m, a, level, ld)
@@ -562,7 +645,5 @@ hipError_t launch_sa_final(const SAArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(sa_final_kernel, dim3(a.n_inst), dim3(256), 0, s, a);
   return hipGetLastError();
 }
-
-int sa_waves_per_group(const DevMarket &m, int want) { return waves_for_lds(wave_lds_doubles(m), want); }
 
 }  // namespace sabr
