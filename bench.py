@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-levels", type=int, default=6,
                     help="levels of the oracle's bounded sample")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-time-to-rmse", action="store_true")
     return ap.parse_args()
 
 
@@ -88,6 +90,69 @@ def cpu_baseline(w, n_levels):
                        f"({qe:.3e} quote-evals, {dt:.1f} s, OpenMP over chains)")
 
 
+def time_to_rmse(api, W, I, autotune):
+    """Config c4: SA (512 chains, 50 levels x 100 steps) then LM polish of the
+    64 best chain points, against plain SA (same chains) run for up to 4 x 200
+    levels.  R* = (1 + 1e-3) x the RMSE of the polished optimum; the hybrid's
+    time is its wall time to the end of the polish, plain SA's time the device
+    timestamp of the first level whose best-ever RMSE <= R* (a lower bound
+    when never reached)."""
+    import torch
+    w = W.config4()
+    mk = W.synthesize(w, lambda vm, t: gpu_vols(api, vm, t))
+    plan = api.Plan(mk)
+    lb, ub = I.box(w.model)
+    Q = int(I.n_quotes(mk)[0])
+    c = plan.cost(torch.tensor(W.schedule_points(w.model, w.seed), device="cuda")).cpu().numpy()
+    T0, cool_h = W.schedule(c, Q, w.n_levels)
+    L_plain = 4 * 200
+    _, cool_p = W.schedule(c, Q, L_plain)
+    shape = {}
+    if autotune:
+        from paper_2408_01470_amd import autotune as AT
+        t = AT.tune(plan, w.chains, lb, ub, w.n_steps)
+        shape = dict(waves=t["waves"], occupancy=t["occupancy"])
+    kw = dict(T0=T0, n_steps=w.n_steps, seed=w.seed, step_frac=w.step_frac, **shape)
+    plan.sa(w.chains, lb, ub, cool=cool_h, n_levels=2, **kw)      # warm-up
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(s)
+    r = plan.sa(w.chains, lb, ub, cool=cool_h, n_levels=w.n_levels, chain_best=True, **kw)
+    e1.record(s)
+    k = w.extra["polish"]
+    idx = torch.topk(-r["chain_best_f"], k).indices
+    x, f, it = plan.lm(r["chain_best_x"][idx], lb, ub, max_iter=50)
+    e2.record(s)
+    torch.cuda.synchronize()
+    t_sa = e0.elapsed_time(e1) / 1e3
+    t_hyb = e0.elapsed_time(e2) / 1e3
+    f_opt = float(f.min())
+    rmse_opt = np.sqrt(f_opt / Q)
+    target = (1 + 1e-3) * rmse_opt
+    rp = plan.sa(w.chains, lb, ub, cool=cool_p, n_levels=L_plain, **kw)
+    torch.cuda.synchronize()
+    tr = rp["trace"].cpu().numpy()[0]
+    rmse_p = np.sqrt(tr[:, 0] / Q)
+    hit = np.nonzero(rmse_p <= target)[0]
+    reached = len(hit) > 0
+    t_plain = float(tr[hit[0], 2] if reached else tr[-1, 2]) / 1e9
+    return {
+        "workload": w.name,
+        "rmse_target": target,
+        "rmse_sa_plus_lm": rmse_opt,
+        "rmse_sa_before_polish": float(np.sqrt(r["best_f"].item() / Q)),
+        "rmse_plain_sa_final": float(rmse_p[-1]),
+        "t_sa_plus_lm_s": t_hyb,
+        "t_sa_part_s": t_sa,
+        "lm_iterations_max": int(it.max()),
+        "t_plain_sa_s": t_plain,
+        "plain_reached_target": bool(reached),
+        "speedup": t_plain / t_hyb,
+        "speedup_is_lower_bound": not reached,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -118,6 +183,11 @@ def main():
     T0s = np.array(T0s)
     kw = dict(T0=T0s[0], cool=cool, n_levels=w.n_levels, n_steps=w.n_steps, seed=w.seed,
               step_frac=w.step_frac, T0_per_inst=T0s, trace=True)
+    tuned = None
+    if not args.no_autotune:
+        from paper_2408_01470_amd import autotune as AT
+        tuned = AT.tune(plan, w.chains, lb, ub, w.n_steps)
+        kw.update(waves=tuned["waves"], occupancy=tuned["occupancy"])
     stream = torch.cuda.current_stream()
     ws = None
     for _ in range(args.warmup):
@@ -191,7 +261,12 @@ def main():
             "rmse_best": float(rmse.max()),
             "wall_s_per_step": wall / args.steps,
         },
+        "launch_shape": {"waves_per_group": kw.get("waves", 0),
+                         "occupancy": kw.get("occupancy", 0),
+                         "autotuned": tuned is not None},
     }
+    if not args.no_time_to_rmse:
+        out["time_to_rmse"] = time_to_rmse(api, W, I, not args.no_autotune)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_levels, w.n_levels))
     print(json.dumps(out))

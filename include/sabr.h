@@ -161,6 +161,8 @@ typedef struct {
   void *const *level_events; /* [host] nullable: 2 * n_levels hipEvent_t recorded on `stream`
                                 just before and just after each level's annealing kernel
                                 (eager launches only; ignored when use_graph = 1) */
+  int32_t occupancy;         /* register budget of the level kernel: minimum waves per SIMD
+                                (0 or 1 = compiler's choice, 3, 4); a tuning knob */
 } sa_config;
 
 /* Device workspace bytes sa_calibrate needs for these chain counts. */
@@ -189,6 +191,38 @@ sabr_status sa_calibrate(const sabr_plan *plan, const sa_config *cfg /*[host]*/,
                          double *best_x, double *best_f, double *chain_best_x,
                          double *chain_best_f, uint8_t *accept, double *level_trace,
                          int32_t *level_best, void *workspace, size_t ws_bytes, void *stream);
+
+/* Device workspace bytes sabr_cost_vjp and sabr_lm_polish need for n_pts
+ * points (per-wave scratch of the LMM12 map Jacobian, box tables). */
+size_t sabr_adjoint_workspace_size(const sabr_plan *plan, int32_t n_pts);
+
+/* Hand-written adjoint of the cost (reverse sweep of the implied-vol formula,
+ * Black-76 and the parameter map): for point i,
+ *   g_params[i*P + k] = g_cost[i] * d cost_i / d p_k   (g_cost nullable -> 1),
+ *   cost[i] (nullable)   = cost_i,
+ *   jtwj[i*P*P ..] (nullable) = J^T W J,  jtwr[i*P ..] (nullable) = J^T W r,
+ * with r_q the residuals, W = diag(w_q) and J_q = d r_q / d p; note
+ * d cost/d p = 2 J^T W r.  Out-of-domain points give cost +inf and zero
+ * derivatives.  The derivative of the cost follows from the paper's f_c and
+ * f_s (Sec. 3); the paper itself polishes with Nelder-Mead and has no
+ * gradient. */
+sabr_status sabr_cost_vjp(const sabr_plan *plan, int32_t n_pts, const int32_t *pt_inst,
+                          const double *params, const double *g_cost, double *cost,
+                          double *g_params, double *jtwj, double *jtwr, void *workspace,
+                          size_t ws_bytes, void *stream);
+
+/* Projected Levenberg-Marquardt polish of n_pts points in place (the local
+ * refinement after annealing; the paper uses Nelder-Mead there, Sec. 3):
+ *   (J^T W J + mu diag(J^T W J)) delta = -J^T W r, trial = clamp(p + delta),
+ *   accept if the cost decreases (mu /= 10; stop when the relative decrease
+ *   is below tol), else mu *= 10 (stop once mu > 1e16); mu starts at mu0.
+ * A zero diagonal entry is replaced by 1; coordinates with lb = ub, or on a
+ * bound that -J^T W r points out of, are frozen for the iteration.  lb, ub:
+ * [host][n_inst][P].  cost_out [n_pts] and iters_out [n_pts] nullable. */
+sabr_status sabr_lm_polish(const sabr_plan *plan, int32_t n_pts, const int32_t *pt_inst,
+                           double *params, const double *lb, const double *ub, int32_t max_iter,
+                           double mu0, double tol, double *cost_out, int32_t *iters_out,
+                           void *workspace, size_t ws_bytes, void *stream);
 
 /* Last error message of the calling thread ("" if none). */
 const char *sabr_last_error(void);

@@ -12,14 +12,6 @@ _f64p = ctypes.POINTER(ctypes.c_double)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
 _vp = ctypes.c_void_p
 
-# Exported symbols declared in include/sabr.h (checked by the test-suite).
-EXPORTS = (
-    "sabr_plan_create", "sabr_plan_destroy", "sabr_plan_device_bytes", "sabr_plan_upload",
-    "sabr_num_params", "sabr_plan_num_params", "sabr_plan_num_inst", "sabr_plan_max_quotes",
-    "sabr_plan_underlyings", "sabr_cost_batch", "sa_workspace_size", "sa_calibrate",
-    "sabr_cost_vjp", "sabr_lm_workspace_size", "sabr_lm_polish", "sabr_last_error",
-)
-
 
 class SabrProblem(ctypes.Structure):
     _fields_ = [
@@ -40,6 +32,7 @@ class SAConfig(ctypes.Structure):
         ("n_levels", ctypes.c_int32), ("n_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
         ("T0_per_inst", _f64p), ("waves_per_group", ctypes.c_int32),
         ("use_graph", ctypes.c_int32), ("level_events", ctypes.POINTER(ctypes.c_void_p)),
+        ("occupancy", ctypes.c_int32),
     ]
 
 
@@ -77,14 +70,13 @@ def lib():
     L.sa_workspace_size.restype = ctypes.c_size_t
     L.sa_calibrate.argtypes = [_vp, ctypes.POINTER(SAConfig), _i32p, _f64p, _f64p, _f64p,
                                _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
-    if hasattr(L, "sabr_cost_vjp"):
-        L.sabr_cost_vjp.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
-    if hasattr(L, "sabr_lm_polish"):
-        L.sabr_lm_workspace_size.argtypes = [_vp, ctypes.c_int32]
-        L.sabr_lm_workspace_size.restype = ctypes.c_size_t
-        L.sabr_lm_polish.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _f64p, _f64p,
-                                     ctypes.c_int32, ctypes.c_double, ctypes.c_double, _vp, _vp,
-                                     _vp, ctypes.c_size_t, _vp]
+    L.sabr_adjoint_workspace_size.argtypes = [_vp, ctypes.c_int32]
+    L.sabr_adjoint_workspace_size.restype = ctypes.c_size_t
+    L.sabr_cost_vjp.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                ctypes.c_size_t, _vp]
+    L.sabr_lm_polish.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _f64p, _f64p, ctypes.c_int32,
+                                 ctypes.c_double, ctypes.c_double, _vp, _vp, _vp,
+                                 ctypes.c_size_t, _vp]
     _lib = L
     return _lib
 

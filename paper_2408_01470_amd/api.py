@@ -58,6 +58,8 @@ class Plan:
         check(L.sabr_plan_create(ctypes.byref(self._prob), ctypes.byref(h)))
         self._h = h
         self.model = int(market["model"])
+        self.formula = int(market["formula"])
+        self.residual = int(market["residual"])
         self.P = int(L.sabr_plan_num_params(h))
         self.n_inst = int(L.sabr_plan_num_inst(h))
         self.max_q = int(L.sabr_plan_max_quotes(h))
@@ -68,9 +70,12 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and _lib._lib is not None:
-            _lib._lib.sabr_plan_destroy(h)
-            self._h = None
+        try:
+            if h is not None and _lib is not None and _lib._lib is not None:
+                _lib._lib.sabr_plan_destroy(h)
+        except Exception:  # interpreter shutdown: modules may be gone
+            pass
+        self._h = None
 
     # ------------------------------------------------------------------
     def underlyings(self):
@@ -109,7 +114,7 @@ class Plan:
 
     # ------------------------------------------------------------------
     def sa_config(self, T0, cool, n_levels, n_steps, seed, step_frac=0.05, T0_per_inst=None,
-                  waves=0, use_graph=False, level_events=None):
+                  waves=0, use_graph=False, level_events=None, occupancy=0):
         t0i = None
         if T0_per_inst is not None:
             t0i = np.ascontiguousarray(T0_per_inst, dtype=np.float64)
@@ -123,7 +128,7 @@ class Plan:
                         int(seed), t0i.ctypes.data_as(_f64p) if t0i is not None else None,
                         int(waves), 1 if use_graph else 0,
                         ctypes.cast(ev, ctypes.POINTER(ctypes.c_void_p)) if ev is not None
-                        else None)
+                        else None, int(occupancy))
 
     def sa_workspace_bytes(self, cfg, chains):
         ch = np.ascontiguousarray(np.broadcast_to(chains, (self.n_inst,)), dtype=np.int32)
@@ -146,14 +151,15 @@ class Plan:
 
     def sa(self, chains, lb, ub, T0, cool, n_levels, n_steps, seed, step_frac=0.05, x0=None,
            T0_per_inst=None, record=False, trace=True, chain_best=False, waves=0,
-           use_graph=False, stream=None, workspace=None, out=None, level_events=None):
+           use_graph=False, stream=None, workspace=None, out=None, level_events=None,
+           occupancy=0):
         """Synchronous parallel simulated annealing on every instance.  ``out``
         (a dict returned by an earlier call with the same shapes) reuses its
         output tensors, so a captured graph can be replayed."""
         L = lib()
         n, P = self.n_inst, self.P
         cfg = self.sa_config(T0, cool, n_levels, n_steps, seed, step_frac, T0_per_inst, waves,
-                             use_graph, level_events)
+                             use_graph, level_events, occupancy)
         ch = np.ascontiguousarray(np.broadcast_to(chains, (n,)), dtype=np.int32)
         lb = np.ascontiguousarray(np.broadcast_to(lb, (n, P)), dtype=np.float64)
         ub = np.ascontiguousarray(np.broadcast_to(ub, (n, P)), dtype=np.float64)
@@ -179,3 +185,70 @@ class Plan:
         out["workspace"] = workspace
         out["n_evals"] = ch.astype(np.int64) * (1 + int(n_steps) * int(n_levels))
         return out
+
+    # ------------------------------------------------------------------
+    def _adj_workspace(self, n, workspace=None):
+        ws = int(lib().sabr_adjoint_workspace_size(self._h, n))
+        if workspace is None or workspace.numel() < ws:
+            workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=self.device)
+        return workspace
+
+    def vjp(self, params, pt_inst=None, g_cost=None, normal=False, stream=None, workspace=None):
+        """Hand-written adjoint: dict(cost, grad = g_cost * d cost/d p, and with
+        normal=True jtwj [n,P,P], jtwr [n,P])."""
+        params, pt_inst, n = self._pts(params, pt_inst)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        cost = torch.empty(n, **f64)
+        grad = torch.empty((n, self.P), **f64)
+        jtwj = torch.empty((n, self.P, self.P), **f64) if normal else None
+        jtwr = torch.empty((n, self.P), **f64) if normal else None
+        if g_cost is not None:
+            g_cost = torch.as_tensor(g_cost, **f64).reshape(n).contiguous()
+        ws = self._adj_workspace(n, workspace)
+        check(lib().sabr_cost_vjp(self._h, n, _ptr(pt_inst), _ptr(params), _ptr(g_cost),
+                                  _ptr(cost), _ptr(grad), _ptr(jtwj), _ptr(jtwr), _ptr(ws),
+                                  ws.numel(), _stream(stream)))
+        return dict(cost=cost, grad=grad, jtwj=jtwj, jtwr=jtwr)
+
+    def lm(self, params, lb, ub, pt_inst=None, max_iter=50, mu0=1e-3, tol=1e-12, stream=None,
+           workspace=None):
+        """Projected Levenberg-Marquardt polish; returns (params, cost, iterations)."""
+        params, pt_inst, n = self._pts(params, pt_inst)
+        x = params.clone()
+        lb = np.ascontiguousarray(np.broadcast_to(lb, (self.n_inst, self.P)), dtype=np.float64)
+        ub = np.ascontiguousarray(np.broadcast_to(ub, (self.n_inst, self.P)), dtype=np.float64)
+        cost = torch.empty(n, dtype=torch.float64, device=self.device)
+        iters = torch.empty(n, dtype=torch.int32, device=self.device)
+        ws = self._adj_workspace(n, workspace)
+        check(lib().sabr_lm_polish(self._h, n, _ptr(pt_inst), _ptr(x), lb.ctypes.data_as(_f64p),
+                                   ub.ctypes.data_as(_f64p), int(max_iter), float(mu0),
+                                   float(tol), _ptr(cost), _ptr(iters), _ptr(ws), ws.numel(),
+                                   _stream(stream)))
+        return x, cost, iters
+
+
+class SabrCost(torch.autograd.Function):
+    """cost = f(params) through sabr_cost_batch; backward through the
+    hand-written adjoint sabr_cost_vjp."""
+
+    @staticmethod
+    def forward(ctx, params, plan, pt_inst):
+        params = params.contiguous()
+        cost = plan.cost(params, pt_inst)
+        ctx.plan = plan
+        ctx.save_for_backward(params, pt_inst)
+        return cost
+
+    @staticmethod
+    def backward(ctx, g):
+        params, pt_inst = ctx.saved_tensors
+        out = ctx.plan.vjp(params, pt_inst, g_cost=g.contiguous())
+        return out["grad"], None, None
+
+
+def sabr_cost(plan: Plan, params, pt_inst=None):
+    """Differentiable cost of points (torch.float64 [n, P] on the GPU)."""
+    n = params.reshape(-1, plan.P).shape[0]
+    if pt_inst is None:
+        pt_inst = torch.zeros(n, dtype=torch.int32, device=plan.device)
+    return SabrCost.apply(params.reshape(-1, plan.P), plan, pt_inst)

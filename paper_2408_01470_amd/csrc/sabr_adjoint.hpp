@@ -1,0 +1,24 @@
+// sabr_adjoint.hpp -- launch interface of the adjoint and Levenberg-Marquardt
+// kernels (sabr_adjoint.hip).  Not part of the public ABI.
+#pragma once
+#include "sabr_internal.hpp"
+
+namespace sabr {
+
+// Waves of the persistent adjoint / LM grid; each owns one slot of the
+// M_u scratch (max_nu x 36 doubles, LMM12 only).
+constexpr int kAdjointMaxWaves = 2048;
+
+size_t adjoint_scratch_bytes(const DevMarket &m, int n_waves);
+int adjoint_waves(int n_pts);
+size_t adjoint_lds_bytes(const DevMarket &m);
+
+hipError_t launch_vjp(const DevMarket &m, int n_pts, const int *pt_inst, const double *params,
+                      const double *g_cost, double *cost, double *g_params, double *jtwj,
+                      double *jtwr, double *scratch, hipStream_t s);
+
+hipError_t launch_lm(const DevMarket &m, int n_pts, const int *pt_inst, double *params,
+                     const double *lb, const double *ub, int max_iter, double mu0, double tol,
+                     double *cost_out, int *iters_out, double *scratch, hipStream_t s);
+
+}  // namespace sabr

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/sabr.h"
+#include "sabr_adjoint.hpp"
 #include "sabr_internal.hpp"
 
 using sabr::DevInst;
@@ -69,8 +70,8 @@ struct sabr_plan {
   std::vector<unsigned char> staging;
   char *dev = nullptr;
   DevMarket dm{};
-  // SA state reused across calls
-  std::vector<unsigned char> sa_staging;
+  // host staging of per-call tables (kept until the next call)
+  std::vector<unsigned char> sa_staging, lm_staging;
   std::mutex mu;
   hipGraphExec_t graph_exec = nullptr;
   std::vector<uint64_t> graph_key;
@@ -511,7 +512,7 @@ sabr_status sa_calibrate(const sabr_plan *Pc, const sa_config *cfg, const int32_
       if (N > 0) {
         if (ev && (r = hipEventRecord(static_cast<hipEvent_t>(events[2 * l]), q)) != hipSuccess)
           return r;
-        r = sabr::launch_sa_level(P->dm, a, l, S.n_tiles, S.waves, q);
+        r = sabr::launch_sa_level(P->dm, a, l, S.n_tiles, S.waves, cfg->occupancy, q);
         if (r != hipSuccess) return r;
         if (ev && (r = hipEventRecord(static_cast<hipEvent_t>(events[2 * l + 1]), q)) !=
                       hipSuccess)
@@ -536,7 +537,7 @@ sabr_status sa_calibrate(const sabr_plan *Pc, const sa_config *cfg, const int32_
                                (uint64_t)(uintptr_t)chain_best_f, (uint64_t)(uintptr_t)accept,
                                (uint64_t)(uintptr_t)level_trace, (uint64_t)(uintptr_t)level_best,
                                (uint64_t)L, (uint64_t)N, cfg->seed, (uint64_t)S.waves,
-                               (uint64_t)S.n_tiles};
+                               (uint64_t)S.n_tiles, (uint64_t)cfg->occupancy};
   uint64_t bits;
   std::memcpy(&bits, &cfg->step_frac, 8);
   key.push_back(bits);
@@ -565,6 +566,99 @@ sabr_status sa_calibrate(const sabr_plan *Pc, const sa_config *cfg, const int32_
   }
   e = hipGraphLaunch(P->graph_exec, s);
   if (e != hipSuccess) return hip_fail(e, "graph launch");
+  return SABR_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Adjoint and Levenberg-Marquardt
+// ---------------------------------------------------------------------------
+namespace {
+
+struct AdjLayout {
+  size_t o_lb, o_ub, o_scratch, total;
+};
+
+AdjLayout adj_layout(const sabr_plan *P, int n_pts) {
+  AdjLayout A{};
+  Layout L;
+  const int Pn = sabr_num_params(P->model);
+  A.o_lb = L.take<double>((size_t)P->n_inst * Pn);
+  A.o_ub = L.take<double>((size_t)P->n_inst * Pn);
+  DevMarket shape{};
+  shape.model = P->model;
+  shape.max_nu = P->max_nu;
+  A.o_scratch = L.take<unsigned char>(sabr::adjoint_scratch_bytes(shape, sabr::adjoint_waves(n_pts)));
+  A.total = L.off;
+  return A;
+}
+
+sabr_status check_points(const sabr_plan *P, int32_t n_pts) {
+  if (!P) return fail(SABR_EINVAL, "null plan");
+  if (!P->dev) return fail(SABR_EINVAL, "plan not uploaded");
+  if (n_pts < 0) return fail(SABR_EINVAL, "n_pts < 0");
+  return SABR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sabr_adjoint_workspace_size(const sabr_plan *P, int32_t n_pts) {
+  if (!P || n_pts < 0) return 0;
+  return adj_layout(P, n_pts).total;
+}
+
+sabr_status sabr_cost_vjp(const sabr_plan *P, int32_t n_pts, const int32_t *pt_inst,
+                          const double *params, const double *g_cost, double *cost,
+                          double *g_params, double *jtwj, double *jtwr, void *workspace,
+                          size_t ws_bytes, void *stream) {
+  sabr_status st = check_points(P, n_pts);
+  if (st != SABR_OK) return st;
+  if (n_pts == 0) return SABR_OK;
+  if (!pt_inst || !params || !g_params) return fail(SABR_EINVAL, "null pt_inst, params or g_params");
+  const AdjLayout A = adj_layout(P, n_pts);
+  if (A.total > 0 && (!workspace || ws_bytes < A.total))
+    return fail(SABR_EWORKSPACE, "workspace too small");
+  char *w = static_cast<char *>(workspace);
+  hipError_t e = sabr::launch_vjp(P->dm, n_pts, pt_inst, params, g_cost, cost, g_params, jtwj,
+                                  jtwr, w ? reinterpret_cast<double *>(w + A.o_scratch) : nullptr,
+                                  static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+  return SABR_OK;
+}
+
+sabr_status sabr_lm_polish(const sabr_plan *Pc, int32_t n_pts, const int32_t *pt_inst,
+                           double *params, const double *lb, const double *ub, int32_t max_iter,
+                           double mu0, double tol, double *cost_out, int32_t *iters_out,
+                           void *workspace, size_t ws_bytes, void *stream) {
+  sabr_status st = check_points(Pc, n_pts);
+  if (st != SABR_OK) return st;
+  if (n_pts == 0) return SABR_OK;
+  if (!pt_inst || !params || !lb || !ub) return fail(SABR_EINVAL, "null argument");
+  if (max_iter < 0 || !(mu0 > 0.0) || !(tol >= 0.0)) return fail(SABR_EINVAL, "bad LM settings");
+  sabr_plan *P = const_cast<sabr_plan *>(Pc);
+  const int Pn = sabr_num_params(P->model);
+  for (int i = 0; i < P->n_inst * Pn; ++i)
+    if (!std::isfinite(lb[i]) || !std::isfinite(ub[i]) || !(lb[i] <= ub[i]))
+      return fail(SABR_EINVAL, "box bound " + std::to_string(i) + ": need finite lb <= ub");
+  const AdjLayout A = adj_layout(P, n_pts);
+  if (!workspace || ws_bytes < A.total) return fail(SABR_EWORKSPACE, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(SABR_EINVAL, "workspace not 256-byte aligned");
+  char *w = static_cast<char *>(workspace);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> guard(P->mu);
+  std::vector<unsigned char> &stg = P->lm_staging;
+  stg.assign(A.o_scratch, 0);
+  std::memcpy(stg.data() + A.o_lb, lb, sizeof(double) * P->n_inst * Pn);
+  std::memcpy(stg.data() + A.o_ub, ub, sizeof(double) * P->n_inst * Pn);
+  hipError_t e = hipMemcpyAsync(w, stg.data(), A.o_scratch, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "LM box upload");
+  e = sabr::launch_lm(P->dm, n_pts, pt_inst, params, reinterpret_cast<const double *>(w + A.o_lb),
+                      reinterpret_cast<const double *>(w + A.o_ub), max_iter, mu0, tol, cost_out,
+                      iters_out, reinterpret_cast<double *>(w + A.o_scratch), s);
+  if (e != hipSuccess) return hip_fail(e, "LM launch");
   return SABR_OK;
 }
 

@@ -1,0 +1,210 @@
+// sabr_cost.hpp -- the per-point cost evaluation shared by the annealing,
+// cost, adjoint and Levenberg-Marquardt kernels: LDS layout of a wavefront,
+// the LMM12 parameter map and the quote loop.
+#pragma once
+#include "sabr_internal.hpp"
+
+namespace sabr {
+
+template <int MODEL>
+struct NP;
+template <>
+struct NP<0> {
+  static constexpr int P = 4;
+};
+template <>
+struct NP<1> {
+  static constexpr int P = 12;
+};
+
+// Per-wave LDS scratch of the LMM12 map: per forward {alpha, nu, g1, g2}
+// (g1, g2: correlation factors of the gap to the next forward); per
+// underlying its SABR constants; a per-lane column for the swap recursion.
+struct FwdMap {
+  double al, nv, g1, g2;
+};
+
+struct WaveLds {
+  FwdMap *fw;      // [max_nf]
+  SabrConst *th;   // [max_nu]
+  double *lk;      // [max_len][64]
+};
+
+__device__ __forceinline__ WaveLds wave_lds(const DevMarket &m, double *base) {
+  WaveLds w;
+  w.fw = reinterpret_cast<FwdMap *>(base);
+  w.th = reinterpret_cast<SabrConst *>(base + 4 * m.max_nf);
+  w.lk = base + 4 * m.max_nf + 8 * m.max_nu;
+  return w;
+}
+
+__device__ __forceinline__ UndMkt und_mkt(const DevMarket &m, int g) {
+  const double T = m.u_T[g];
+  const double sT = sqrt(T);
+  return UndMkt{m.u_S0[g], m.u_A[g], T, sT, 1.0 / sT, 0.0};
+}
+
+// LMM12 parameter map of one point into the wave's LDS.  Returns true when
+// the point lies outside the model's domain (wave-uniform).
+//   alpha_k = (a + b T_k) e^{-c T_k} + d, nu_k likewise (abcd forms);
+//   rho_kl = exp(-lambda1 |T_k - T_l|) = product of per-gap factors g1,
+//   theta_kl = eta2 + (1 - eta2) exp(-lambda2 |T_k - T_l|), phi_kl = rho.
+// Swap of forwards [e, e+n) with a_k = v_k alpha_k (v_k = tau_k P_k F_k^b;
+// the weights w_k = tau_k P_k / A enter through the common factor 1/A):
+//   R_k = sum_l a_l rho_kl (forward and backward recursions, O(n)),
+//   V = sum a_k R_k, b_k = a_k R_k nu_k,
+//   Nb = eta2 (sum b)^2 + (1 - eta2) sum_kl b_k b_l exp(-lambda2 |dT|),
+//   alpha_S = sqrt(V)/(A S0^b), nu_S = sqrt(Nb)/V,
+//   rho_S = rho (sum a)(sum b) / (sqrt(V) sqrt(Nb))   (0 if Nb = 0).
+// Underlyings are visited in decreasing length so the lanes of a pass run
+// recursions of similar length.
+__device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const double *p, WaveLds w) {
+  const int lane = lane_id();
+  const double a = p[0], b = p[1], c = p[2], d = p[3];
+  const double an = p[4], bn = p[5], cn = p[6], dn = p[7];
+  const double rho = p[8], lam1 = p[9], eta2 = p[10], lam2 = p[11];
+  const double beta = m.beta, omb = 1.0 - beta;
+  bool bad = !(fabs(rho) < 1.0) || !(lam1 >= 0.0) || !(lam2 >= 0.0) ||
+             !(eta2 >= 0.0 && eta2 <= 1.0);
+  for (int k = lane; k < in.nf; k += kWave) {
+    const double T = m.f_T[in.f0 + k];
+    FwdMap F;
+    F.al = fma(b, T, a) * exp(-(c * T)) + d;
+    F.nv = fma(bn, T, an) * exp(-(cn * T)) + dn;
+    F.g1 = F.g2 = 0.0;
+    if (k + 1 < in.nf) {
+      const double dT = m.f_T[in.f0 + k + 1] - T;
+      F.g1 = exp(-(lam1 * dT));
+      F.g2 = exp(-(lam2 * dT));
+    }
+    w.fw[k] = F;
+  }
+  wave_lds_sync();
+  double *lk = w.lk + lane;
+  const double *v = m.f_v + in.f0;
+  for (int i = lane; i < in.nu; i += kWave) {
+    const int u = m.u_order[in.u0 + i];
+    const int e = m.u_first[in.u0 + u];
+    const int n = m.u_len[in.u0 + u];
+    double ta, tr, tn;
+    if (n == 1) {
+      const FwdMap F = w.fw[e];
+      ta = F.al;
+      tr = rho;
+      tn = F.nv;
+      bad |= !(ta > 0.0) || !(tn >= 0.0);
+    } else {
+      double Lacc = 0.0, suma = 0.0;
+      for (int j = 0; j < n; ++j) {
+        const int k = e + j;
+        const FwdMap F = w.fw[k];
+        bad |= !(F.al > 0.0) || !(F.nv >= 0.0);
+        const double aj = v[k] * F.al;
+        lk[j * kWave] = Lacc;
+        suma += aj;
+        Lacc = F.g1 * (Lacc + aj);
+      }
+      double Rr = 0.0, Rb = 0.0, V = 0.0, Sb = 0.0, Sbb = 0.0;
+      for (int j = n - 1; j >= 0; --j) {
+        const int k = e + j;
+        const FwdMap F = w.fw[k];
+        const double aj = v[k] * F.al;
+        const double Rj = lk[j * kWave] + aj + Rr;
+        const double ar = aj * Rj;
+        V += ar;
+        const double bj = ar * F.nv;
+        Sb += bj;
+        Sbb = fma(bj, fma(2.0, Rb, bj), Sbb);
+        if (j > 0) {
+          const FwdMap G = w.fw[k - 1];
+          Rr = G.g1 * (Rr + aj);
+          Rb = G.g2 * (Rb + bj);
+        }
+      }
+      const double Nb = fma(eta2 * Sb, Sb, (1.0 - eta2) * Sbb);
+      const double sV = sqrt(V), sN = sqrt(Nb);
+      ta = sV * m.u_invA[in.u0 + u] / m.u_S0b[in.u0 + u];
+      tn = sN / V;
+      tr = (sN > 0.0) ? rho * suma * Sb / (sV * sN) : 0.0;
+      bad |= !(V > 0.0) || !(fabs(tr) < 1.0);
+    }
+    const double r2 = tr * tr;
+    SabrConst K;
+    K.alpha = ta;
+    K.rho = tr;
+    K.nua = tn / ta;
+    K.ca = omb * omb * ta * ta * (1.0 / 24.0);
+    K.cb = tr * beta * tn * ta * 0.25;
+    K.cc = (2.0 - 3.0 * r2) * tn * tn * (1.0 / 24.0);
+    K.s2 = (2.0 - 3.0 * r2) * (1.0 / 12.0);
+    K.pad = 0.0;
+    w.th[u] = K;
+  }
+  wave_lds_sync();
+  return __any(bad);
+}
+
+// Cost of one point for the wave: f = sum_q w_q r_q^2, +inf on a domain
+// failure.  p[] is wave-uniform.  Optional per-quote residual and model
+// outputs (the quoted side in price mode).
+template <int MODEL, int FORMULA, int RESID>
+__device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt *um,
+                             const double *p, WaveLds w, double *resid, double *model) {
+  const int lane = lane_id();
+  bool bad = false;
+  SabrConst g{};
+  double omb, omb2 = 0.0;
+  if (MODEL == 0) {
+    bad = !(p[0] > 0.0) || !(p[1] >= 0.0 && p[1] <= 1.0) || !(fabs(p[2]) < 1.0) ||
+          !(p[3] >= 0.0);
+    g = sabr_const(p[0], p[1], p[2], p[3]);
+    omb = 1.0 - p[1];
+    omb2 = omb * omb;
+  } else {
+    bad = lmm12_map(m, in, p, w);
+    omb = 1.0 - m.beta;
+  }
+  double acc = 0.0;
+  for (int q = lane; q < in.nq; q += kWave) {
+    const QuoteRec &R = m.q[in.q0 + q];
+    const double L = R.L;
+    const int u = R.und;
+    const UndMkt U = um[u];
+    const SabrConst k = (MODEL == 0) ? g : w.th[u];
+    VolFrac vf;
+    if (FORMULA == 0) {
+      const double qv = (MODEL == 0) ? exp(0.5 * omb * R.qa) : R.qa;
+      const double D1 = (MODEL == 0) ? d1_term(omb2, L) : R.qb;
+      vf = hagan2002_frac(k, L, qv, D1, U.T);
+    } else {
+      const double fp = (MODEL == 0) ? exp(omb * R.qc) : R.qc;
+      vf = paper_eq3_frac(k, omb, L, fp);
+    }
+    double mv;
+    if (RESID == 0) {
+      mv = vf.numer / vf.denom;
+      bad |= !(mv > 0.0) || !(mv < kInf);
+      if (model) model[q] = mv;
+    } else {
+      // one division gives sigma = numer/denom and 1/sigma = denom/numer
+      const double rr = 1.0 / (vf.numer * vf.denom);
+      const double sig = vf.numer * (vf.numer * rr);
+      const double isig = vf.denom * (vf.denom * rr);
+      bad |= !(sig > 0.0) || !(sig < kInf);
+      mv = black_otm(U.f, R.K, L, U.sqrtT, U.isqrtT, sig, isig, U.D);
+      bad |= !(fabs(mv) < kInf);
+      if (model) {
+        const double sh = parity_shift(R.kind, U.f, R.K, L, U.D);
+        model[q] = sh == 0.0 ? mv : mv + sh;
+      }
+    }
+    const double r = mv - R.tgt;
+    acc = fma(R.w * r, r, acc);
+    if (resid) resid[q] = r;
+  }
+  const double tot = wave_sum(acc);
+  const bool any_bad = __any(bad);
+  return (any_bad || !(tot < kInf)) ? kInf : tot;
+}
+
+}  // namespace sabr

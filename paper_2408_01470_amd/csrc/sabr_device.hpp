@@ -61,8 +61,9 @@ struct DevMarket {
 
 // Per-underlying market values staged in LDS by every workgroup.
 struct UndMkt {
-  double f, D, T, sqrtT, isqrtT;
+  double f, D, T, sqrtT, isqrtT, pad;
 };
+static_assert(sizeof(UndMkt) == 48, "16-byte aligned LDS record");
 
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon et al., SC 2011).
@@ -129,7 +130,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 struct SabrConst {
   double alpha, rho, nua;   // nua = nu / alpha
   double ca, cb, cc, s2;
+  double pad;
 };
+static_assert(sizeof(SabrConst) == 64, "16-byte aligned LDS record");
 
 __device__ __forceinline__ SabrConst sabr_const(double alpha, double beta, double rho, double nu) {
   SabrConst k;

@@ -9,12 +9,12 @@
 namespace sabr {
 
 // Doubles of LDS one wavefront needs for the LMM12 maps: per-forward alpha,
-// nu and the two correlation gap factors, seven SABR constants per
-// underlying, and a per-lane column of max_len doubles for the swap
-// recursion.  Each workgroup adds 5 doubles per underlying of market values.
-inline int wave_lds_doubles(const DevMarket &m) {
+// nu and the two correlation gap factors, a 64-byte record of SABR constants
+// per underlying, and a per-lane column of max_len doubles for the swap
+// recursion.  Each workgroup adds 6 doubles per underlying of market values.
+__host__ __device__ inline int wave_lds_doubles(const DevMarket &m) {
   if (m.model == 0) return 0;
-  return 4 * m.max_nf + 7 * m.max_nu + kWave * m.max_len;
+  return 4 * m.max_nf + 8 * m.max_nu + kWave * m.max_len;
 }
 
 struct SAArgs {
@@ -50,7 +50,7 @@ hipError_t launch_cost(const DevMarket &m, int n_pts, const int *pt_inst, const 
 hipError_t launch_sa_init(const DevMarket &m, const SAArgs &a, int n_tiles, int waves,
                           hipStream_t s);
 hipError_t launch_sa_level(const DevMarket &m, const SAArgs &a, int level, int n_tiles,
-                           int waves, hipStream_t s);
+                           int waves, int occupancy, hipStream_t s);
 hipError_t launch_sa_level_end(const SAArgs &a, int level, hipStream_t s);
 hipError_t launch_sa_final(const SAArgs &a, hipStream_t s);
 

@@ -10,219 +10,11 @@
 // kernel here (no dense contraction: no MFMA).
 #include <hip/hip_runtime.h>
 
-#include "sabr_internal.hpp"
+#include "sabr_cost.hpp"
 
 namespace sabr {
 
 namespace {
-
-template <int MODEL>
-struct NP;
-template <>
-struct NP<0> {
-  static constexpr int P = 4;
-};
-template <>
-struct NP<1> {
-  static constexpr int P = 12;
-};
-
-// Per-wave LDS scratch of the LMM12 map: per forward alpha, nu and the two
-// correlation gap factors; per underlying the SABR constants; a per-lane
-// column for the swap recursion.
-struct WaveLds {
-  double *al, *nv, *g1, *g2;                     // [max_nf]
-  double *ta, *tr, *tq, *tca, *tcb, *tcc, *ts2;  // [max_nu]
-  double *lk;                                    // [max_len][64]
-};
-
-__device__ __forceinline__ WaveLds wave_lds(const DevMarket &m, double *base) {
-  WaveLds w;
-  w.al = base;
-  w.nv = w.al + m.max_nf;
-  w.g1 = w.nv + m.max_nf;
-  w.g2 = w.g1 + m.max_nf;
-  w.ta = w.g2 + m.max_nf;
-  w.tr = w.ta + m.max_nu;
-  w.tq = w.tr + m.max_nu;
-  w.tca = w.tq + m.max_nu;
-  w.tcb = w.tca + m.max_nu;
-  w.tcc = w.tcb + m.max_nu;
-  w.ts2 = w.tcc + m.max_nu;
-  w.lk = w.ts2 + m.max_nu;
-  return w;
-}
-
-__device__ __forceinline__ UndMkt und_mkt(const DevMarket &m, int g) {
-  const double T = m.u_T[g];
-  const double sT = sqrt(T);
-  return UndMkt{m.u_S0[g], m.u_A[g], T, sT, 1.0 / sT};
-}
-
-// LMM12 parameter map of one point into the wave's LDS.  Returns true when
-// the point lies outside the model's domain (wave-uniform).
-//   alpha_k = (a + b T_k) e^{-c T_k} + d, nu_k likewise (abcd forms);
-//   rho_kl = exp(-lambda1 |T_k - T_l|) = product of per-gap factors g1,
-//   theta_kl = eta2 + (1 - eta2) exp(-lambda2 |T_k - T_l|), phi_kl = rho.
-// Swap of forwards [e, e+n) with a_k = v_k alpha_k (v_k = tau_k P_k F_k^b;
-// the weights w_k = tau_k P_k / A enter through the common factor 1/A):
-//   R_k = sum_l a_l rho_kl (forward and backward recursions, O(n)),
-//   V = sum a_k R_k, b_k = a_k R_k nu_k,
-//   Nb = eta2 (sum b)^2 + (1 - eta2) sum_kl b_k b_l exp(-lambda2 |dT|),
-//   alpha_S = sqrt(V)/(A S0^b), nu_S = sqrt(Nb)/V,
-//   rho_S = rho (sum a)(sum b) / (sqrt(V) sqrt(Nb))   (0 if Nb = 0).
-// Underlyings are visited in decreasing length so the lanes of a pass run
-// recursions of similar length.
-__device__ bool lmm12_map(const DevMarket &m, const DevInst &in, const double *p, WaveLds w) {
-  const int lane = lane_id();
-  const double a = p[0], b = p[1], c = p[2], d = p[3];
-  const double an = p[4], bn = p[5], cn = p[6], dn = p[7];
-  const double rho = p[8], lam1 = p[9], eta2 = p[10], lam2 = p[11];
-  const double beta = m.beta, omb = 1.0 - beta;
-  bool bad = !(fabs(rho) < 1.0) || !(lam1 >= 0.0) || !(lam2 >= 0.0) ||
-             !(eta2 >= 0.0 && eta2 <= 1.0);
-  for (int k = lane; k < in.nf; k += kWave) {
-    const double T = m.f_T[in.f0 + k];
-    w.al[k] = fma(b, T, a) * exp(-(c * T)) + d;
-    w.nv[k] = fma(bn, T, an) * exp(-(cn * T)) + dn;
-    if (k + 1 < in.nf) {
-      const double dT = m.f_T[in.f0 + k + 1] - T;
-      w.g1[k] = exp(-(lam1 * dT));
-      w.g2[k] = exp(-(lam2 * dT));
-    }
-  }
-  wave_lds_sync();
-  double *lk = w.lk + lane;
-  const double *v = m.f_v + in.f0;
-  for (int i = lane; i < in.nu; i += kWave) {
-    const int u = m.u_order[in.u0 + i];
-    const int e = m.u_first[in.u0 + u];
-    const int n = m.u_len[in.u0 + u];
-    double ta, tr, tn;
-    if (n == 1) {
-      ta = w.al[e];
-      tr = rho;
-      tn = w.nv[e];
-      bad |= !(ta > 0.0) || !(tn >= 0.0);
-    } else {
-      double Lacc = 0.0, suma = 0.0;
-      for (int j = 0; j < n; ++j) {
-        const int k = e + j;
-        const double alk = w.al[k];
-        bad |= !(alk > 0.0) || !(w.nv[k] >= 0.0);
-        const double aj = v[k] * alk;
-        lk[j * kWave] = Lacc;
-        suma += aj;
-        Lacc = w.g1[k] * (Lacc + aj);
-      }
-      double Rr = 0.0, Rb = 0.0, V = 0.0, Sb = 0.0, Sbb = 0.0;
-      for (int j = n - 1; j >= 0; --j) {
-        const int k = e + j;
-        const double aj = v[k] * w.al[k];
-        const double Rj = lk[j * kWave] + aj + Rr;
-        const double ar = aj * Rj;
-        V += ar;
-        const double bj = ar * w.nv[k];
-        Sb += bj;
-        Sbb = fma(bj, fma(2.0, Rb, bj), Sbb);
-        if (j > 0) {
-          Rr = w.g1[k - 1] * (Rr + aj);
-          Rb = w.g2[k - 1] * (Rb + bj);
-        }
-      }
-      const double Nb = fma(eta2 * Sb, Sb, (1.0 - eta2) * Sbb);
-      const double sV = sqrt(V), sN = sqrt(Nb);
-      ta = sV * m.u_invA[in.u0 + u] / m.u_S0b[in.u0 + u];
-      tn = sN / V;
-      tr = (sN > 0.0) ? rho * suma * Sb / (sV * sN) : 0.0;
-      bad |= !(V > 0.0) || !(fabs(tr) < 1.0);
-    }
-    const double r2 = tr * tr;
-    w.ta[u] = ta;
-    w.tr[u] = tr;
-    w.tq[u] = tn / ta;
-    w.tca[u] = omb * omb * ta * ta * (1.0 / 24.0);
-    w.tcb[u] = tr * beta * tn * ta * 0.25;
-    w.tcc[u] = (2.0 - 3.0 * r2) * tn * tn * (1.0 / 24.0);
-    w.ts2[u] = (2.0 - 3.0 * r2) * (1.0 / 12.0);
-  }
-  wave_lds_sync();
-  return __any(bad);
-}
-
-// Cost of one point for the wave: f = sum_q w_q r_q^2, +inf on a domain
-// failure.  p[] is wave-uniform.  Optional per-quote residual and model
-// outputs (the quoted side in price mode).
-template <int MODEL, int FORMULA, int RESID>
-__device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt *um,
-                             const double *p, WaveLds w, double *resid, double *model) {
-  const int lane = lane_id();
-  bool bad = false;
-  SabrConst g{};
-  double omb, omb2 = 0.0;
-  if (MODEL == 0) {
-    bad = !(p[0] > 0.0) || !(p[1] >= 0.0 && p[1] <= 1.0) || !(fabs(p[2]) < 1.0) ||
-          !(p[3] >= 0.0);
-    g = sabr_const(p[0], p[1], p[2], p[3]);
-    omb = 1.0 - p[1];
-    omb2 = omb * omb;
-  } else {
-    bad = lmm12_map(m, in, p, w);
-    omb = 1.0 - m.beta;
-  }
-  double acc = 0.0;
-  for (int q = lane; q < in.nq; q += kWave) {
-    const QuoteRec &R = m.q[in.q0 + q];
-    const double L = R.L;
-    const int u = R.und;
-    const UndMkt U = um[u];
-    SabrConst k;
-    if (MODEL == 0) {
-      k = g;
-    } else {
-      k.alpha = w.ta[u];
-      k.rho = w.tr[u];
-      k.nua = w.tq[u];
-      k.ca = w.tca[u];
-      k.cb = w.tcb[u];
-      k.cc = w.tcc[u];
-      k.s2 = w.ts2[u];
-    }
-    VolFrac vf;
-    if (FORMULA == 0) {
-      const double qv = (MODEL == 0) ? exp(0.5 * omb * R.qa) : R.qa;
-      const double D1 = (MODEL == 0) ? d1_term(omb2, L) : R.qb;
-      vf = hagan2002_frac(k, L, qv, D1, U.T);
-    } else {
-      const double fp = (MODEL == 0) ? exp(omb * R.qc) : R.qc;
-      vf = paper_eq3_frac(k, omb, L, fp);
-    }
-    double mv;
-    if (RESID == 0) {
-      mv = vf.numer / vf.denom;
-      bad |= !(mv > 0.0) || !(mv < kInf);
-      if (model) model[q] = mv;
-    } else {
-      // one division gives sigma = numer/denom and 1/sigma = denom/numer
-      const double rr = 1.0 / (vf.numer * vf.denom);
-      const double sig = vf.numer * (vf.numer * rr);
-      const double isig = vf.denom * (vf.denom * rr);
-      bad |= !(sig > 0.0) || !(sig < kInf);
-      mv = black_otm(U.f, R.K, L, U.sqrtT, U.isqrtT, sig, isig, U.D);
-      bad |= !(fabs(mv) < kInf);
-      if (model) {
-        const double sh = parity_shift(R.kind, U.f, R.K, L, U.D);
-        model[q] = sh == 0.0 ? mv : mv + sh;
-      }
-    }
-    const double r = mv - R.tgt;
-    acc = fma(R.w * r, r, acc);
-    if (resid) resid[q] = r;
-  }
-  const double tot = wave_sum(acc);
-  const bool any_bad = __any(bad);
-  return (any_bad || !(tot < kInf)) ? kInf : tot;
-}
 
 // ---------------------------------------------------------------------------
 // Market precompute (market-only quantities, once per upload).  The host has
@@ -291,7 +83,7 @@ __global__ __launch_bounds__(256) void cost_kernel(DevMarket m, int n_pts, const
   double p[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) p[k] = params[(size_t)pt * P + k];
-  WaveLds w = wave_lds(m, base + 5 * m.max_nu);
+  WaveLds w = wave_lds(m, base + 6 * m.max_nu);
   const double c = point_cost<MODEL, FORMULA, RESID>(
       m, in, um, p, w, resid ? resid + (size_t)pt * stride : nullptr,
       model ? model + (size_t)pt * stride : nullptr);
@@ -346,7 +138,7 @@ __global__ __launch_bounds__(256) void sa_init_kernel(DevMarket m, SAArgs a, int
   const double xl = (lane < P) ? a.x0[(size_t)inst * P + lane] : 0.0;
   double x[P];
   broadcast_params<P>(xl, x);
-  WaveLds w = wave_lds(m, smem + 5 * m.max_nu + (size_t)wid * lds_per_wave);
+  WaveLds w = wave_lds(m, smem + 6 * m.max_nu + (size_t)wid * lds_per_wave);
   const double f = point_cost<MODEL, FORMULA, RESID>(m, in, um, x, w, nullptr, nullptr);
   const int64_t gc = a.chain_base[inst] + c;
   if (lane < P) {
@@ -365,9 +157,11 @@ __global__ __launch_bounds__(256) void sa_init_kernel(DevMarket m, SAArgs a, int
   }
 }
 
-template <int MODEL, int FORMULA, int RESID>
-__global__ __launch_bounds__(256) void sa_level_kernel(DevMarket m, SAArgs a, int level,
-                                                       int lds_per_wave) {
+// OCC: minimum waves per SIMD the register allocation must allow (1 = the
+// compiler's choice); a tuning knob traded against spills.
+template <int MODEL, int FORMULA, int RESID, int OCC>
+__global__ __launch_bounds__(256, OCC) void sa_level_kernel(DevMarket m, SAArgs a, int level,
+                                                            int lds_per_wave) {
   extern __shared__ double smem[];
   constexpr int P = NP<MODEL>::P;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -388,7 +182,7 @@ __global__ __launch_bounds__(256) void sa_level_kernel(DevMarket m, SAArgs a, in
   double f = a.RF[inst];
   double bf = a.BF[gc];
   const double T = a.Tcur[inst];
-  WaveLds w = wave_lds(m, smem + 5 * m.max_nu + (size_t)wid * lds_per_wave);
+  WaveLds w = wave_lds(m, smem + 6 * m.max_nu + (size_t)wid * lds_per_wave);
   int nacc = 0;
   for (int s = 0; s < a.N; ++s) {
     // uniforms u_0..u_P: lane k <= P takes word k mod 4 of Philox block k/4
@@ -585,7 +379,7 @@ int lds_budget_bytes() {
 }
 
 size_t sa_lds_bytes(const DevMarket &m, int waves) {
-  return (size_t)(5 * m.max_nu + waves * wave_lds_doubles(m)) * 8;
+  return (size_t)(6 * m.max_nu + waves * wave_lds_doubles(m)) * 8;
 }
 
 int sa_waves_per_group(const DevMarket &m, int want) {
@@ -598,7 +392,7 @@ hipError_t launch_cost(const DevMarket &m, int n_pts, const int *pt_inst, const 
                        double *cost, double *resid, double *model, int stride, hipStream_t s) {
   if (n_pts == 0) return hipSuccess;
   // cost waves keep their own copy of the per-underlying market values
-  const int ld = wave_lds_doubles(m) + 5 * m.max_nu;
+  const int ld = wave_lds_doubles(m) + 6 * m.max_nu;
   if ((long)ld * 8 > lds_budget_bytes()) return hipErrorInvalidValue;
   int waves = 4;
   while (waves > 1 && (long)ld * 8 * waves > lds_budget_bytes()) --waves;
@@ -625,14 +419,24 @@ hipError_t launch_sa_init(const DevMarket &m, const SAArgs &a, int n_tiles, int 
 }
 
 hipError_t launch_sa_level(const DevMarket &m, const SAArgs &a, int level, int n_tiles,
-                           int waves, hipStream_t s) {
+                           int waves, int occupancy, hipStream_t s) {
   const int ld = wave_lds_doubles(m);
   const size_t lds = sa_lds_bytes(m, waves);
-#define CALL(A, B, C)                                                                     \
-  hipLaunchKernelGGL((sa_level_kernel<A, B, C>), dim3(n_tiles), dim3(kWave * waves), lds, s, \
-                     m, a, level, ld)
+#define LAUNCH(A, B, C, O)                                                                   \
+  hipLaunchKernelGGL((sa_level_kernel<A, B, C, O>), dim3(n_tiles), dim3(kWave * waves), lds, \
+                     s, m, a, level, ld)
+#define CALL(A, B, C)              \
+  do {                             \
+    if (occupancy >= 4)            \
+      LAUNCH(A, B, C, 4);          \
+    else if (occupancy == 3)       \
+      LAUNCH(A, B, C, 3);          \
+    else                           \
+      LAUNCH(A, B, C, 1);          \
+  } while (0)
   SABR_SELECT(m.model, m.formula, m.residual, CALL);
 #undef CALL
+#undef LAUNCH
   return hipGetLastError();
 }
 

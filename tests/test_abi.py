@@ -134,11 +134,11 @@ def test_sa_rejects_bad_config_without_gpu(L):
     assert rc == 0
     ch = np.array([0], np.int32)
     i32 = ctypes.POINTER(ctypes.c_int32)
-    cfg = SAConfig(1.0, 0.9, 0.05, 10, 10, 1, None, 0, 0, None)
+    cfg = SAConfig(1.0, 0.9, 0.05, 10, 10, 1, None, 0, 0, None, 0)
     assert L.sa_workspace_size(h, ctypes.byref(cfg), ch.ctypes.data_as(i32)) == 0  # 0 chains
     ch[0] = 16
     assert L.sa_workspace_size(h, ctypes.byref(cfg), ch.ctypes.data_as(i32)) > 16 * 8
-    bad = SAConfig(1.0, 1.5, 0.05, 10, 10, 1, None, 0, 0, None)   # cool > 1
+    bad = SAConfig(1.0, 1.5, 0.05, 10, 10, 1, None, 0, 0, None, 0)   # cool > 1
     assert L.sa_workspace_size(h, ctypes.byref(bad), ch.ctypes.data_as(i32)) == 0
     # not uploaded: sa_calibrate refuses before touching the GPU
     f64 = ctypes.POINTER(ctypes.c_double)
