@@ -16,8 +16,24 @@ HIPCC_FLAGS = [
 ]
 
 
+CALIB_SRC = os.path.join(CSRC, "elementary_calib.hip")
+CALIB_BIN = os.path.join(HERE, "elementary_calib")
+
+
+def build_calib(hipcc: str) -> str:
+    """The elementary-function pricing program (profiling only)."""
+    flags = [f for f in HIPCC_FLAGS if f not in ("-fPIC", "-shared")]
+    res = subprocess.run([hipcc, *flags, "-o", CALIB_BIN + ".tmp", CALIB_SRC], capture_output=True,
+                         text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
+    os.replace(CALIB_BIN + ".tmp", CALIB_BIN)
+    return CALIB_BIN
+
+
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    build_calib(hipcc)
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     tmp = LIB + ".tmp"
     cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, *srcs]

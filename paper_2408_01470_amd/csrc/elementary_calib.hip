@@ -1,0 +1,86 @@
+// elementary_calib.hip -- prices the FP64 elementary functions the
+// calibrator calls, for the algorithmic FLOP count of the roofline.
+//
+// Each kernel evaluates one function once per thread over n inputs drawn
+// from the ranges the cost kernels see; under
+//   rocprofv3 --pmc SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64
+//                   SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64
+// the FP64 FLOP per call is 64 (ADD + MUL + TRANS + 2 FMA) / n minus the
+// identical counts of the "copy" kernel (load, store, no arithmetic).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#define CHECK(x)                                                             \
+  do {                                                                       \
+    hipError_t e_ = (x);                                                     \
+    if (e_ != hipSuccess) {                                                  \
+      std::fprintf(stderr, "%s: %s\n", #x, hipGetErrorString(e_));           \
+      return 1;                                                              \
+    }                                                                        \
+  } while (0)
+
+template <int FN>
+__global__ void elem_kernel(const double *__restrict__ x, const double *__restrict__ y,
+                            double *__restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = x[i], b = y[i];
+  double r;
+  if (FN == 0) r = a;                 // copy: the baseline
+  else if (FN == 1) r = exp(a);
+  else if (FN == 2) r = log1p(a);
+  else if (FN == 3) r = sqrt(a);
+  else if (FN == 4) r = a / b;
+  else r = erfcx(a);
+  out[i] = r;
+}
+
+int main() {
+  const int n = 1 << 20;
+  // inputs per function: exp in [-12, 0], log1p in [-0.6, 1.5], sqrt in
+  // [0.2, 4], div in [0.1, 10]/[0.1, 10], erfcx in [0, 8]
+  const double lo[6] = {0.0, -12.0, -0.6, 0.2, 0.1, 0.0};
+  const double hi[6] = {1.0, 0.0, 1.5, 4.0, 10.0, 8.0};
+  const char *names[6] = {"copy", "exp", "log1p", "sqrt", "div", "erfcx"};
+  double *dx, *dy, *dout;
+  CHECK(hipMalloc(&dx, n * sizeof(double)));
+  CHECK(hipMalloc(&dy, n * sizeof(double)));
+  CHECK(hipMalloc(&dout, n * sizeof(double)));
+  std::vector<double> hx(n), hy(n);
+  for (int f = 0; f < 6; ++f) {
+    unsigned long long s = 88172645463325252ULL + f;
+    for (int i = 0; i < n; ++i) {
+      s ^= s << 13;
+      s ^= s >> 7;
+      s ^= s << 17;
+      const double u = (double)(s >> 11) * 0x1.0p-53;
+      s ^= s << 13;
+      s ^= s >> 7;
+      s ^= s << 17;
+      const double v = (double)(s >> 11) * 0x1.0p-53;
+      hx[i] = lo[f] + (hi[f] - lo[f]) * u;
+      hy[i] = lo[f] + (hi[f] - lo[f]) * v;
+    }
+    CHECK(hipMemcpy(dx, hx.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    CHECK(hipMemcpy(dy, hy.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    const dim3 grid(n / 256), block(256);
+    switch (f) {
+      case 0: hipLaunchKernelGGL(elem_kernel<0>, grid, block, 0, 0, dx, dy, dout, n); break;
+      case 1: hipLaunchKernelGGL(elem_kernel<1>, grid, block, 0, 0, dx, dy, dout, n); break;
+      case 2: hipLaunchKernelGGL(elem_kernel<2>, grid, block, 0, 0, dx, dy, dout, n); break;
+      case 3: hipLaunchKernelGGL(elem_kernel<3>, grid, block, 0, 0, dx, dy, dout, n); break;
+      case 4: hipLaunchKernelGGL(elem_kernel<4>, grid, block, 0, 0, dx, dy, dout, n); break;
+      default: hipLaunchKernelGGL(elem_kernel<5>, grid, block, 0, 0, dx, dy, dout, n); break;
+    }
+    CHECK(hipGetLastError());
+    CHECK(hipDeviceSynchronize());
+    std::printf("%s: %d calls\n", names[f], n);
+  }
+  CHECK(hipFree(dx));
+  CHECK(hipFree(dy));
+  CHECK(hipFree(dout));
+  return 0;
+}
