@@ -39,6 +39,10 @@ def parse():
                     help="levels of the oracle's bounded sample")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-time-to-rmse", action="store_true")
+    ap.add_argument("--waves", type=int, default=None,
+                    help="fixed waves per workgroup of the level kernel (skips the autotuner)")
+    ap.add_argument("--occupancy", type=int, default=None,
+                    help="fixed register budget in waves per SIMD (with --waves)")
     return ap.parse_args()
 
 
@@ -184,7 +188,9 @@ def main():
     kw = dict(T0=T0s[0], cool=cool, n_levels=w.n_levels, n_steps=w.n_steps, seed=w.seed,
               step_frac=w.step_frac, T0_per_inst=T0s, trace=True)
     tuned = None
-    if not args.no_autotune:
+    if args.waves is not None:
+        kw.update(waves=args.waves, occupancy=args.occupancy or 1)
+    elif not args.no_autotune:
         from paper_2408_01470_amd import autotune as AT
         tuned = AT.tune(plan, w.chains, lb, ub, w.n_steps)
         kw.update(waves=tuned["waves"], occupancy=tuned["occupancy"])

@@ -1,92 +1,106 @@
 """Algorithmic FP64 work of the calibrator, for the roofline.
 
-Counts follow the formulas as the kernels evaluate them: add, sub and mul
-count 1, fma counts 2, comparisons and selects count 0.  An elementary
-function counts the FP64 operations of one call of the device math library
-(``ELEMENTARY``), measured once on MI355X with the hardware counters
-(SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 of a kernel that only calls the
-function; see the profiles directory).  Units: FLOP per quote evaluation, per
-chain step (parameter maps, proposal, Metropolis) and per launch of the
-per-level annealing kernel.
+Counts follow the formulas as the kernels state them, each operation counted
+once where the definition needs it: add, sub and mul count 1, fma counts 2,
+comparisons, selects, negations and integer work (the Philox generator) count
+0; a branch counts its common side only (the |z| <= 1 quotient of z/x(z),
+not its series).  An elementary function counts the FP64 operations of one
+call of the device math library (``ELEMENTARY``): the hardware counters
+SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 of a kernel that calls only that
+function on a million inputs drawn from the ranges the cost kernels see,
+minus a plain copy kernel, as ADD + MUL + TRANS + 2 FMA per call.
+Units: FLOP per quote evaluation, per underlying, per chain step (parameter
+map, proposal, Metropolis) and per launch of the per-level annealing kernel.
 """
 from __future__ import annotations
 
 import numpy as np
 
-# FP64 FLOP per call (ADD + MUL + TRANS + 2 FMA), measured: see module docstring.
-ELEMENTARY = {"exp": 27.0, "log1p": 45.0, "sqrt": 9.0, "div": 13.0, "erfc": 60.0}
+# FP64 FLOP per call of the device math library, measured as described above.
+ELEMENTARY = {"exp": 27.0, "log1p": 45.0, "sqrt": 9.0, "div": 13.0, "erfcx": 60.0}
 
 
 def _e(name, n=1):
     return n * ELEMENTARY[name]
 
 
-# SABR constants of one (alpha, beta, rho, nu): (1-b), (1-b)^2, the three
-# corr coefficients and the five z/x(z) series coefficients.
-SABR_CONST = 34.0
+def sabr_const() -> float:
+    """Constants of one (alpha, beta, rho, nu): rho^2 and 2 - 3 rho^2 (3),
+    nu/alpha (a division), the three corr coefficients alpha^2 (1-b)^2/24,
+    rho b nu alpha/4, (2 - 3 rho^2) nu^2/24 (3 + 4 + 3) and the series
+    coefficient (2 - 3 rho^2)/12 (1); (1-b) and (1-b)^2 add 2 when beta is a
+    parameter."""
+    return 14.0 + _e("div")
 
 
 def hagan_quote(fixed_beta: bool) -> float:
-    """Hagan 2002 vol for one quote: z, s = sqrt(1 - 2 rho z + z^2), the
-    log1p argument (one division), the series, corr q^2 and the final
-    division; plus q = exp(...) and D1 when beta is a parameter."""
-    arith = 2 + 4 + 3 + 10 + 7 + 2 + 4
-    f = arith + _e("sqrt") + _e("log1p") + _e("div", 2)
+    """Hagan 2002 vol fraction for one quote: z = (nu/alpha) q L (2),
+    s = sqrt(1 - 2 rho z + z^2) (4), the log1p argument 2z/(s + 1 - z)
+    (3 and a division), P = q^2 + T (ca + cb q + cc q^2) (7), the numerator
+    alpha P z (2) and denominator q^3 D1 x (4); with beta a parameter also
+    q = exp((1-b)/2 ln(fK)) (2) and D1 = 1 + u/24 + u^2/1920,
+    u = (1-b)^2 L^2 (6)."""
+    f = 22 + _e("sqrt") + _e("log1p") + _e("div")
     if not fixed_beta:
         f += 2 + _e("exp") + 6
     return f
 
 
 def eq3_quote(fixed_beta: bool) -> float:
-    """Paper eq. (sigmaHagan) for one quote: w = f^(1-b)/alpha, two bracket
-    coefficients, the quadratic in k and the scale."""
-    f = 1 + 2 + 2 + 9 + 4 + 1 + _e("div", 2)
+    """Paper eq. (sigmaHagan) for one quote: nu = (nu/alpha) alpha (1),
+    w = f^(1-b)/alpha (a division), rho nu w (2), the two bracket
+    coefficients (2 and 12), the quadratic in k (4) and the numerator scale
+    (1); fp = exp((1-b) ln f) (1) when beta is a parameter."""
+    f = 22 + _e("div")
     if not fixed_beta:
         f += 1 + _e("exp")
     return f
 
 
 def black_quote() -> float:
-    """Black-76 out-of-the-money price: sd, d1 (one division), d2, two erfc
-    and the combination."""
-    return 14 + _e("div") + _e("erfc", 2)
+    """sigma and 1/sigma from the vol fraction (5 and one division), then the
+    Black-76 out-of-the-money price: sd, d1, d2 (6), E = exp(-d1^2/2) (2),
+    the two erfcx arguments (2), f E/2 (2), the combination (3) and the
+    discount (1)."""
+    return 5 + _e("div") + 16 + _e("exp") + _e("erfcx", 2)
 
 
-RESIDUAL = 4.0   # r = m - mkt, acc += w r r
+RESIDUAL = 4.0   # r = m - target, acc += (w r) r
 
 
 def quote_flops(model: int, formula: int, residual: int) -> float:
     fixed = model == 1
     f = hagan_quote(fixed) if formula == 0 else eq3_quote(fixed)
-    if model == 1:
-        f += SABR_CONST          # per underlying constants, evaluated per quote
-    if residual == 1:
-        f += black_quote()
+    f += black_quote() if residual == 1 else _e("div")
     return f + RESIDUAL
 
 
 def map_flops_inst(market: dict, inst: int) -> float:
-    """LMM12 map per chain step: abcd forms and correlation gap factors per
-    forward; per underlying nu/alpha, and for a swap over n forwards the O(n)
-    frozen-weight recursion (21 n) plus its closing square roots and
-    divisions."""
+    """Parameter map per chain step.  GLOBAL4: the SABR constants once.
+    LMM12: per forward the two abcd forms (10 and 2 exp), per gap between
+    consecutive forwards the two correlation factors (3 and 2 exp); per
+    underlying its SABR constants; for a swap over n forwards the O(n)
+    frozen-weight recursion (4 per forward forward, 14 per forward
+    backward) and its closing Nb, alpha_S, nu_S, rho_S (9, 2 sqrt,
+    3 divisions)."""
     if int(market["model"]) == 0:
-        return SABR_CONST + _e("div")
+        return sabr_const() + 2
     f0, f1 = market["fwd_off"][inst], market["fwd_off"][inst + 1]
     u0, u1 = market["und_off"][inst], market["und_off"][inst + 1]
     nf = f1 - f0
     lens = np.asarray(market["und_len"][u0:u1])
     fwd = nf * (10 + _e("exp", 2)) + max(nf - 1, 0) * (3 + _e("exp", 2))
-    und = len(lens) * _e("div")
+    und = len(lens) * sabr_const()
     swp = lens[lens > 1]
-    und += float(np.sum(21 * swp)) + len(swp) * (8 + _e("sqrt", 2) + _e("div", 3))
+    und += float(np.sum(18 * swp)) + len(swp) * (9 + _e("sqrt", 2) + _e("div", 3))
     return fwd + und
 
 
 def step_overhead(model: int) -> float:
-    """Proposal (7 per coordinate), uniform conversion, Metropolis."""
+    """Proposal (6 per coordinate), uniform conversion (1 per uniform, P+1),
+    Metropolis (dE, a division and an exponential)."""
     P = 4 if model == 0 else 12
-    return 7 * P + (P + 1) + 2 + _e("div") + _e("exp")
+    return 6 * P + (P + 1) + 1 + _e("div") + _e("exp")
 
 
 def level_launch_flops(market: dict, chains, n_steps: int) -> float:
