@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+
+#include "sabr_device.hpp"
 #include <cstdio>
 #include <vector>
 
@@ -34,7 +36,7 @@ __global__ void elem_kernel(const double *__restrict__ x, const double *__restri
   else if (FN == 2) r = log1p(a);
   else if (FN == 3) r = sqrt(a);
   else if (FN == 4) r = a / b;
-  else r = erfcx(a);
+  else r = sabr::erfcx_pos(a);   // the kernels' own erfcx
   out[i] = r;
 }
 

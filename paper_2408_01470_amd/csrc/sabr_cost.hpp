@@ -165,8 +165,14 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
     omb = 1.0 - m.beta;
   }
   double acc = 0.0;
+  // The next pass's record is loaded while this pass computes, so the global
+  // load latency hides behind the quote arithmetic.
+  const QuoteRec *qrec = m.q + in.q0;
+  QuoteRec Rn{};
+  if (lane < in.nq) Rn = qrec[lane];
   for (int q = lane; q < in.nq; q += kWave) {
-    const QuoteRec &R = m.q[in.q0 + q];
+    const QuoteRec R = Rn;
+    if (q + kWave < in.nq) Rn = qrec[q + kWave];
     const double L = R.L;
     const int u = R.und;
     const UndMkt U = um[u];

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "erfcx_poly.hpp"
+
 namespace sabr {
 
 constexpr int kWave = 64;
@@ -209,6 +211,24 @@ __device__ __forceinline__ VolFrac paper_eq3_frac(const SabrConst &k, double omb
   return v;
 }
 
+// erfcx(x) = exp(x^2) erfc(x) for x >= 0 (method of erfcx_poly.hpp): one
+// reciprocal r = 1/(x + K) from v_rcp_f64 and two Newton steps (x + K >= K,
+// so no range scaling is needed), t = (x - K) r, erfcx = h(t) r with h a
+// degree-24 polynomial; branch-free, no tables.  Arguments above 1e100 are
+// clamped: callers multiply the result by exp(-x^2), which is zero there.
+__device__ __forceinline__ double erfcx_pos(double x) {
+  x = fmin(x, 1e100);
+  const double den = x + kErfcxK;
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(r, fma(-den, r, 1.0), r);
+  r = fma(r, fma(-den, r, 1.0), r);
+  const double t = (x - kErfcxK) * r;
+  double h = kErfcxPoly[kErfcxDeg];
+#pragma unroll
+  for (int k = kErfcxDeg - 1; k >= 0; --k) h = fma(h, t, kErfcxPoly[k]);
+  return h * r;
+}
+
 // ---------------------------------------------------------------------------
 // Black-76 on the out-of-the-money side (the call when K >= f, i.e. L <= 0;
 // the other side follows by put-call parity, call - put = D (f - K)):
@@ -228,8 +248,8 @@ __device__ __forceinline__ double black_otm(double f, double K, double L, double
   const double d1 = fma(L * isigma, isqrtT, 0.5 * sd);
   const double d2 = d1 - sd;
   const double E = exp(-0.5 * d1 * d1);
-  const double X1 = erfcx(fabs(d1) * M_SQRT1_2);
-  const double X2 = erfcx(fabs(d2) * M_SQRT1_2);
+  const double X1 = erfcx_pos(fabs(d1) * M_SQRT1_2);
+  const double X2 = erfcx_pos(fabs(d2) * M_SQRT1_2);
   const double hE = 0.5 * f * E;
   if (L <= 0.0)
     return D * (d1 <= 0.0 ? hE * (X1 - X2) : fma(-hE, X1 + X2, f));
