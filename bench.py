@@ -117,14 +117,20 @@ def time_to_rmse(api, W, I, autotune):
         t = AT.tune(plan, w.chains, lb, ub, w.n_steps)
         shape = dict(waves=t["waves"], occupancy=t["occupancy"])
     kw = dict(T0=T0, n_steps=w.n_steps, seed=w.seed, step_frac=w.step_frac, **shape)
-    plan.sa(w.chains, lb, ub, cool=cool_h, n_levels=2, **kw)      # warm-up
+    k = w.extra["polish"]
+
+    def hybrid():
+        r = plan.sa(w.chains, lb, ub, cool=cool_h, n_levels=w.n_levels, chain_best=True, **kw)
+        idx = torch.topk(-r["chain_best_f"], k).indices
+        return r, plan.lm(r["chain_best_x"][idx], lb, ub, max_iter=50)
+
+    hybrid()                    # warm-up: first-call costs stay out of the timing
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
     e0.record(s)
     r = plan.sa(w.chains, lb, ub, cool=cool_h, n_levels=w.n_levels, chain_best=True, **kw)
     e1.record(s)
-    k = w.extra["polish"]
     idx = torch.topk(-r["chain_best_f"], k).indices
     x, f, it = plan.lm(r["chain_best_x"][idx], lb, ub, max_iter=50)
     e2.record(s)

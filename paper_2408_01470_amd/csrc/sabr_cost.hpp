@@ -69,13 +69,13 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const do
   for (int k = lane; k < in.nf; k += kWave) {
     const double T = m.f_T[in.f0 + k];
     FwdMap F;
-    F.al = fma(b, T, a) * exp(-(c * T)) + d;
-    F.nv = fma(bn, T, an) * exp(-(cn * T)) + dn;
+    F.al = fma(b, T, a) * exp_cw(-(c * T)) + d;
+    F.nv = fma(bn, T, an) * exp_cw(-(cn * T)) + dn;
     F.g1 = F.g2 = 0.0;
     if (k + 1 < in.nf) {
       const double dT = m.f_T[in.f0 + k + 1] - T;
-      F.g1 = exp(-(lam1 * dT));
-      F.g2 = exp(-(lam2 * dT));
+      F.g1 = exp_cw(-(lam1 * dT));
+      F.g2 = exp_cw(-(lam2 * dT));
     }
     w.fw[k] = F;
   }
@@ -122,7 +122,7 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const do
         }
       }
       const double Nb = fma(eta2 * Sb, Sb, (1.0 - eta2) * Sbb);
-      const double sV = sqrt(V), sN = sqrt(Nb);
+      const double sV = sqrt_gs(V), sN = sqrt_gs(Nb);
       ta = sV * m.u_invA[in.u0 + u] / m.u_S0b[in.u0 + u];
       tn = sN / V;
       tr = (sN > 0.0) ? rho * suma * Sb / (sV * sN) : 0.0;
@@ -179,21 +179,21 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
     const SabrConst k = (MODEL == 0) ? g : w.th[u];
     VolFrac vf;
     if (FORMULA == 0) {
-      const double qv = (MODEL == 0) ? exp(0.5 * omb * R.qa) : R.qa;
+      const double qv = (MODEL == 0) ? exp_cw(0.5 * omb * R.qa) : R.qa;
       const double D1 = (MODEL == 0) ? d1_term(omb2, L) : R.qb;
       vf = hagan2002_frac(k, L, qv, D1, U.T);
     } else {
-      const double fp = (MODEL == 0) ? exp(omb * R.qc) : R.qc;
+      const double fp = (MODEL == 0) ? exp_cw(omb * R.qc) : R.qc;
       vf = paper_eq3_frac(k, omb, L, fp);
     }
     double mv;
     if (RESID == 0) {
-      mv = vf.numer / vf.denom;
+      mv = vf.numer * rcp_nr(vf.denom);
       bad |= !(mv > 0.0) || !(mv < kInf);
       if (model) model[q] = mv;
     } else {
       // one division gives sigma = numer/denom and 1/sigma = denom/numer
-      const double rr = 1.0 / (vf.numer * vf.denom);
+      const double rr = rcp_nr(vf.numer * vf.denom);
       const double sig = vf.numer * (vf.numer * rr);
       const double isig = vf.denom * (vf.denom * rr);
       bad |= !(sig > 0.0) || !(sig < kInf);

@@ -10,6 +10,8 @@
 #include <stdint.h>
 
 #include "erfcx_poly.hpp"
+#include "exp_poly.hpp"
+#include "log1p_poly.hpp"
 
 namespace sabr {
 
@@ -123,6 +125,94 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // ---------------------------------------------------------------------------
+// Elementary functions of the quote loop, branch-free.
+// ---------------------------------------------------------------------------
+// 1/d for a normal, finite d: v_rcp_f64 and two Newton steps (each squares
+// the relative error), within an ulp or so of the rounded quotient.  A zero,
+// infinite or NaN d gives NaN, which every caller treats as a domain failure.
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
+// sqrt(a) for a normal or zero a: Goldschmidt iteration (Markstein, IA-64
+// and Elementary Functions, 2000) from the v_rsq_f64 seed, g -> sqrt(a),
+// h -> 1/(2 sqrt(a)), two passes and a final Newton correction.
+__device__ __forceinline__ double sqrt_gs(double a) {
+  const double y = __builtin_amdgcn_rsq(a);
+  double g = a * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  g = fma(fma(-g, g, a), h, g);
+  if (a > 0.0 && a < kInf) return g;
+  return (a == 0.0 || a == kInf) ? a : __builtin_nan("");
+}
+
+// exp(x) (method of exp_poly.hpp): k = rint(x/ln2), r = x - k ln2 in two fma
+// steps, 2^k p(r).  Underflows to 0 below -746, overflows to +inf above 710,
+// NaN stays NaN.
+__device__ __forceinline__ double exp_cw(double x) {
+  const double xc = fmin(fmax(x, -746.0), 710.0);
+  const double kd = rint(xc * kExpInvLn2);
+  double r = fma(-kd, kExpLn2Hi, xc);
+  r = fma(-kd, kExpLn2Lo, r);
+  double p = kExpPoly[kExpDeg];
+#pragma unroll
+  for (int j = kExpDeg - 1; j >= 0; --j) p = fma(p, r, kExpPoly[j]);
+  const double e = ldexp(p, (int)kd);
+  return x == x ? e : x;
+}
+
+// log1p(t) (method of log1p_poly.hpp): v = 1 + t rounded with its exact
+// error e (two-sum), v = 2^k m with m in [sqrt(1/2), sqrt(2)), f = m - 1,
+// s = f/(2 + f), log m = f - s (f - s^2 P(s^2)), and
+// log1p(t) = k ln2 + log m + e/v.  -inf at t = -1, NaN below -1 or for NaN,
+// +inf at +inf; branch-free.
+__device__ __forceinline__ double log1p_tang(double t) {
+  const double v = 1.0 + t;
+  const double vv = v - 1.0;
+  const double e = (1.0 - (v - vv)) + (t - vv);
+  double m = __builtin_amdgcn_frexp_mant(v);
+  int k = __builtin_amdgcn_frexp_exp(v);
+  const bool up = m < M_SQRT1_2;
+  m = up ? m + m : m;
+  k = up ? k - 1 : k;
+  const double f = m - 1.0;
+  const double s = f * rcp_nr(2.0 + f);
+  const double z = s * s;
+  double p = kLog1pPoly[kLog1pDeg];
+#pragma unroll
+  for (int j = kLog1pDeg - 1; j >= 0; --j) p = fma(p, z, kLog1pPoly[j]);
+  const double lf = fma(-s, fma(-z, p, f), f);
+  double rv = __builtin_amdgcn_rcp(v);
+  rv = fma(rv, fma(-v, rv, 1.0), rv);
+  const double kd = (double)k;
+  const double res = fma(kd, kLn2Hi, lf + fma(kd, kLn2Lo, e * rv));
+  if (v > 0.0 && v < kInf) return res;
+  return v == 0.0 ? -kInf : (v == kInf ? kInf : __builtin_nan(""));
+}
+
+// erfcx(x) = exp(x^2) erfc(x) for x >= 0 (method of erfcx_poly.hpp): one
+// reciprocal r = 1/(x + K) from v_rcp_f64 and two Newton steps (x + K >= K,
+// so no range scaling is needed), t = (x - K) r, erfcx = h(t) r with h a
+// degree-24 polynomial; branch-free, no tables.  Arguments above 1e100 are
+// clamped: callers multiply the result by exp(-x^2), which is zero there.
+__device__ __forceinline__ double erfcx_pos(double x) {
+  x = x > 1e100 ? 1e100 : x;
+  const double r = rcp_nr(x + kErfcxK);
+  const double t = (x - kErfcxK) * r;
+  double h = kErfcxPoly[kErfcxDeg];
+#pragma unroll
+  for (int k = kErfcxDeg - 1; k >= 0; --k) h = fma(h, t, kErfcxPoly[k]);
+  return h * r;
+}
+
+// ---------------------------------------------------------------------------
 // SABR constants of one (alpha, beta, rho, nu): everything in the Hagan
 // formula that does not depend on the quote.
 //   corr q^2 = q^2 + (ca + cb q + cc q^2) T, ca = (1-b)^2 alpha^2/24,
@@ -172,12 +262,12 @@ struct VolFrac {
 __device__ __forceinline__ VolFrac hagan2002_frac(const SabrConst &k, double L, double q,
                                                   double D1, double T) {
   const double z = k.nua * q * L;
-  const double s = sqrt(fma(z, z - 2.0 * k.rho, 1.0));
+  const double s = sqrt_gs(fma(z, z - 2.0 * k.rho, 1.0));
   const double az = fabs(z);
   const bool mid = az <= 1.0;
   const double num = mid ? 2.0 * z : (z > 0.0 ? (s + z) - 1.0 : (1.0 + z) - s);
   const double den = mid ? (s + 1.0) - z : (z > 0.0 ? 1.0 - k.rho : (s - z) + k.rho);
-  const double x = log1p(num / den);
+  const double x = log1p_tang(num * rcp_nr(den));
   const bool small = az < kZSeries;
   const double ser = fma(z, fma(z, k.s2, -0.5 * k.rho), 1.0);
   const double Pq = fma(q, q, T * fma(q, fma(q, k.cc, k.cb), k.ca));
@@ -211,24 +301,6 @@ __device__ __forceinline__ VolFrac paper_eq3_frac(const SabrConst &k, double omb
   return v;
 }
 
-// erfcx(x) = exp(x^2) erfc(x) for x >= 0 (method of erfcx_poly.hpp): one
-// reciprocal r = 1/(x + K) from v_rcp_f64 and two Newton steps (x + K >= K,
-// so no range scaling is needed), t = (x - K) r, erfcx = h(t) r with h a
-// degree-24 polynomial; branch-free, no tables.  Arguments above 1e100 are
-// clamped: callers multiply the result by exp(-x^2), which is zero there.
-__device__ __forceinline__ double erfcx_pos(double x) {
-  x = fmin(x, 1e100);
-  const double den = x + kErfcxK;
-  double r = __builtin_amdgcn_rcp(den);
-  r = fma(r, fma(-den, r, 1.0), r);
-  r = fma(r, fma(-den, r, 1.0), r);
-  const double t = (x - kErfcxK) * r;
-  double h = kErfcxPoly[kErfcxDeg];
-#pragma unroll
-  for (int k = kErfcxDeg - 1; k >= 0; --k) h = fma(h, t, kErfcxPoly[k]);
-  return h * r;
-}
-
 // ---------------------------------------------------------------------------
 // Black-76 on the out-of-the-money side (the call when K >= f, i.e. L <= 0;
 // the other side follows by put-call parity, call - put = D (f - K)):
@@ -247,7 +319,7 @@ __device__ __forceinline__ double black_otm(double f, double K, double L, double
   const double sd = sigma * sqrtT;
   const double d1 = fma(L * isigma, isqrtT, 0.5 * sd);
   const double d2 = d1 - sd;
-  const double E = exp(-0.5 * d1 * d1);
+  const double E = exp_cw(-0.5 * d1 * d1);
   const double X1 = erfcx_pos(fabs(d1) * M_SQRT1_2);
   const double X2 = erfcx_pos(fabs(d2) * M_SQRT1_2);
   const double hE = 0.5 * f * E;
