@@ -16,7 +16,7 @@ import os
 import numpy as np
 import torch
 
-CANDIDATES = ((1, 1), (2, 1), (4, 1), (4, 3), (2, 3), (1, 3))
+CANDIDATES = ((1, 1), (2, 1), (4, 1), (1, 3), (2, 3), (4, 3), (2, 4), (4, 4))
 
 
 def cache_path():

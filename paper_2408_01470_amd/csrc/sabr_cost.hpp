@@ -27,7 +27,7 @@ struct FwdMap {
 struct WaveLds {
   FwdMap *fw;      // [max_nf]
   SabrConst *th;   // [max_nu]
-  double *lk;      // [max_len][64]
+  double *lk;      // [max_len][64], used for swaps longer than kMapRegLen
 };
 
 __device__ __forceinline__ WaveLds wave_lds(const DevMarket &m, double *base) {
@@ -42,6 +42,90 @@ __device__ __forceinline__ UndMkt und_mkt(const DevMarket &m, int g) {
   const double T = m.u_T[g];
   const double sT = sqrt(T);
   return UndMkt{m.u_S0[g], m.u_A[g], T, sT, 1.0 / sT, 0.0};
+}
+
+// Moments of the frozen-weight map of one swap over forwards [e, e+n),
+// n >= 2, with a_j = v_j alpha_j and R_j = sum_l a_l rho_jl:
+//   V = sum_j a_j R_j, suma = sum_j a_j, b_j = a_j R_j nu_j, Sb = sum_j b_j,
+//   Sbb = sum_kl b_k b_l exp(-lambda2 |T_k - T_l|).
+// R_j = (left sum) + a_j + (right sum); the left sums come from a forward
+// recursion and are kept per lane, the right sums and the b recursion run
+// backward.  Two storage variants of the per-lane column: registers for
+// swaps of up to kMapRegLen forwards (loops unrolled so every index is
+// static), an LDS column of max_len doubles per lane beyond that.
+struct SwapMoments {
+  double V, suma, Sb, Sbb;
+  bool bad;
+};
+
+template <int NMAX>
+__device__ __forceinline__ SwapMoments swap_moments_reg(const FwdMap *fw, const double *v, int e,
+                                                        int n) {
+  double Lk[NMAX];
+  double Lacc = 0.0, suma = 0.0;
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j) {
+    if (j < n) {
+      const FwdMap F = fw[e + j];
+      bad |= !(F.al > 0.0) || !(F.nv >= 0.0);
+      const double aj = v[e + j] * F.al;
+      Lk[j] = Lacc;
+      suma += aj;
+      Lacc = F.g1 * (Lacc + aj);
+    }
+  }
+  double Rr = 0.0, Rb = 0.0, V = 0.0, Sb = 0.0, Sbb = 0.0;
+#pragma unroll
+  for (int j = NMAX - 1; j >= 0; --j) {
+    if (j < n) {
+      const FwdMap F = fw[e + j];
+      const double aj = v[e + j] * F.al;
+      const double Rj = Lk[j] + aj + Rr;
+      const double ar = aj * Rj;
+      V += ar;
+      const double bj = ar * F.nv;
+      Sb += bj;
+      Sbb = fma(bj, fma(2.0, Rb, bj), Sbb);
+      if (j > 0) {
+        const FwdMap G = fw[e + j - 1];
+        Rr = G.g1 * (Rr + aj);
+        Rb = G.g2 * (Rb + bj);
+      }
+    }
+  }
+  return SwapMoments{V, suma, Sb, Sbb, bad};
+}
+
+__device__ __forceinline__ SwapMoments swap_moments_lds(const FwdMap *fw, const double *v, int e,
+                                                        int n, double *lk) {
+  double Lacc = 0.0, suma = 0.0;
+  bool bad = false;
+  for (int j = 0; j < n; ++j) {
+    const FwdMap F = fw[e + j];
+    bad |= !(F.al > 0.0) || !(F.nv >= 0.0);
+    const double aj = v[e + j] * F.al;
+    lk[j * kWave] = Lacc;
+    suma += aj;
+    Lacc = F.g1 * (Lacc + aj);
+  }
+  double Rr = 0.0, Rb = 0.0, V = 0.0, Sb = 0.0, Sbb = 0.0;
+  for (int j = n - 1; j >= 0; --j) {
+    const FwdMap F = fw[e + j];
+    const double aj = v[e + j] * F.al;
+    const double Rj = lk[j * kWave] + aj + Rr;
+    const double ar = aj * Rj;
+    V += ar;
+    const double bj = ar * F.nv;
+    Sb += bj;
+    Sbb = fma(bj, fma(2.0, Rb, bj), Sbb);
+    if (j > 0) {
+      const FwdMap G = fw[e + j - 1];
+      Rr = G.g1 * (Rr + aj);
+      Rb = G.g2 * (Rb + bj);
+    }
+  }
+  return SwapMoments{V, suma, Sb, Sbb, bad};
 }
 
 // LMM12 parameter map of one point into the wave's LDS.  Returns true when
@@ -94,45 +178,23 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const do
       tn = F.nv;
       bad |= !(ta > 0.0) || !(tn >= 0.0);
     } else {
-      double Lacc = 0.0, suma = 0.0;
-      for (int j = 0; j < n; ++j) {
-        const int k = e + j;
-        const FwdMap F = w.fw[k];
-        bad |= !(F.al > 0.0) || !(F.nv >= 0.0);
-        const double aj = v[k] * F.al;
-        lk[j * kWave] = Lacc;
-        suma += aj;
-        Lacc = F.g1 * (Lacc + aj);
-      }
-      double Rr = 0.0, Rb = 0.0, V = 0.0, Sb = 0.0, Sbb = 0.0;
-      for (int j = n - 1; j >= 0; --j) {
-        const int k = e + j;
-        const FwdMap F = w.fw[k];
-        const double aj = v[k] * F.al;
-        const double Rj = lk[j * kWave] + aj + Rr;
-        const double ar = aj * Rj;
-        V += ar;
-        const double bj = ar * F.nv;
-        Sb += bj;
-        Sbb = fma(bj, fma(2.0, Rb, bj), Sbb);
-        if (j > 0) {
-          const FwdMap G = w.fw[k - 1];
-          Rr = G.g1 * (Rr + aj);
-          Rb = G.g2 * (Rb + bj);
-        }
-      }
+      const SwapMoments S = (m.max_len <= kMapRegLen)
+                                ? swap_moments_reg<kMapRegLen>(w.fw, v, e, n)
+                                : swap_moments_lds(w.fw, v, e, n, lk);
+      const double V = S.V, suma = S.suma, Sb = S.Sb, Sbb = S.Sbb;
+      bad |= S.bad;
       const double Nb = fma(eta2 * Sb, Sb, (1.0 - eta2) * Sbb);
       const double sV = sqrt_gs(V), sN = sqrt_gs(Nb);
-      ta = sV * m.u_invA[in.u0 + u] / m.u_S0b[in.u0 + u];
-      tn = sN / V;
-      tr = (sN > 0.0) ? rho * suma * Sb / (sV * sN) : 0.0;
+      ta = sV * m.u_invA[in.u0 + u] * rcp_nr(m.u_S0b[in.u0 + u]);
+      tn = sN * rcp_nr(V);
+      tr = (sN > 0.0) ? rho * suma * Sb * rcp_nr(sV * sN) : 0.0;
       bad |= !(V > 0.0) || !(fabs(tr) < 1.0);
     }
     const double r2 = tr * tr;
     SabrConst K;
     K.alpha = ta;
     K.rho = tr;
-    K.nua = tn / ta;
+    K.nua = tn * rcp_nr(ta);
     K.ca = omb * omb * ta * ta * (1.0 / 24.0);
     K.cb = tr * beta * tn * ta * 0.25;
     K.cc = (2.0 - 3.0 * r2) * tn * tn * (1.0 / 24.0);

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "erfcx_poly.hpp"
 #include "exp_poly.hpp"
 #include "log1p_poly.hpp"
@@ -127,6 +129,41 @@ __device__ __forceinline__ void wave_lds_sync() {
 // ---------------------------------------------------------------------------
 // Elementary functions of the quote loop, branch-free.
 // ---------------------------------------------------------------------------
+// A double constant materialized in a scalar register pair where it is used.
+// Left alone, the compiler hoists the polynomial coefficients below out of
+// the quote loop into vector registers, where they stay pinned for the whole
+// loop and cost occupancy; volatile scalar moves keep each coefficient local
+// to its use (SALU work, which issues beside other waves' vector work).
+template <unsigned long long BITS>
+__device__ __forceinline__ double sconst() {
+  unsigned lo, hi;
+  asm volatile("s_mov_b32 %0, %1" : "=s"(lo) : "i"((unsigned)(BITS & 0xffffffffull)));
+  asm volatile("s_mov_b32 %0, %1" : "=s"(hi) : "i"((unsigned)(BITS >> 32)));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+#define SABR_SCONST(x) ::sabr::sconst<__builtin_bit_cast(unsigned long long, (x))>()
+
+// Horner's rule on the coefficients C[0..DEG] (constant arrays), one chain
+// or two interleaved chains sharing each coefficient.
+template <const double *C, int DEG, size_t... I>
+__device__ __forceinline__ double horner_s(double t, std::index_sequence<I...>) {
+  double h = SABR_SCONST(C[DEG]);
+  ((h = fma(h, t, SABR_SCONST(C[DEG - 1 - I]))), ...);
+  return h;
+}
+template <const double *C, int DEG>
+__device__ __forceinline__ double horner_s(double t) {
+  return horner_s<C, DEG>(t, std::make_index_sequence<DEG>{});
+}
+template <const double *C, int DEG, size_t... I>
+__device__ __forceinline__ void horner2_s(double t1, double t2, double &h1, double &h2,
+                                          std::index_sequence<I...>) {
+  double c = SABR_SCONST(C[DEG]);
+  h1 = c;
+  h2 = c;
+  ((c = SABR_SCONST(C[DEG - 1 - I]), h1 = fma(h1, t1, c), h2 = fma(h2, t2, c)), ...);
+}
+
 // 1/d for a normal, finite d: v_rcp_f64 and two Newton steps (each squares
 // the relative error), within an ulp or so of the rounded quotient.  A zero,
 // infinite or NaN d gives NaN, which every caller treats as a domain failure.
@@ -161,9 +198,7 @@ __device__ __forceinline__ double exp_cw(double x) {
   const double kd = rint(xc * kExpInvLn2);
   double r = fma(-kd, kExpLn2Hi, xc);
   r = fma(-kd, kExpLn2Lo, r);
-  double p = kExpPoly[kExpDeg];
-#pragma unroll
-  for (int j = kExpDeg - 1; j >= 0; --j) p = fma(p, r, kExpPoly[j]);
+  const double p = horner_s<kExpPoly, kExpDeg>(r);
   const double e = ldexp(p, (int)kd);
   return x == x ? e : x;
 }
@@ -185,9 +220,7 @@ __device__ __forceinline__ double log1p_tang(double t) {
   const double f = m - 1.0;
   const double s = f * rcp_nr(2.0 + f);
   const double z = s * s;
-  double p = kLog1pPoly[kLog1pDeg];
-#pragma unroll
-  for (int j = kLog1pDeg - 1; j >= 0; --j) p = fma(p, z, kLog1pPoly[j]);
+  const double p = horner_s<kLog1pPoly, kLog1pDeg>(z);
   const double lf = fma(-s, fma(-z, p, f), f);
   double rv = __builtin_amdgcn_rcp(v);
   rv = fma(rv, fma(-v, rv, 1.0), rv);
@@ -206,10 +239,19 @@ __device__ __forceinline__ double erfcx_pos(double x) {
   x = x > 1e100 ? 1e100 : x;
   const double r = rcp_nr(x + kErfcxK);
   const double t = (x - kErfcxK) * r;
-  double h = kErfcxPoly[kErfcxDeg];
-#pragma unroll
-  for (int k = kErfcxDeg - 1; k >= 0; --k) h = fma(h, t, kErfcxPoly[k]);
-  return h * r;
+  return horner_s<kErfcxPoly, kErfcxDeg>(t) * r;
+}
+
+// erfcx_pos of two arguments, the two polynomial chains interleaved.
+__device__ __forceinline__ void erfcx_pos2(double x1, double x2, double &X1, double &X2) {
+  x1 = x1 > 1e100 ? 1e100 : x1;
+  x2 = x2 > 1e100 ? 1e100 : x2;
+  const double r1 = rcp_nr(x1 + kErfcxK), r2 = rcp_nr(x2 + kErfcxK);
+  double h1, h2;
+  horner2_s<kErfcxPoly, kErfcxDeg>((x1 - kErfcxK) * r1, (x2 - kErfcxK) * r2, h1, h2,
+                                    std::make_index_sequence<kErfcxDeg>{});
+  X1 = h1 * r1;
+  X2 = h2 * r2;
 }
 
 // ---------------------------------------------------------------------------
@@ -320,8 +362,8 @@ __device__ __forceinline__ double black_otm(double f, double K, double L, double
   const double d1 = fma(L * isigma, isqrtT, 0.5 * sd);
   const double d2 = d1 - sd;
   const double E = exp_cw(-0.5 * d1 * d1);
-  const double X1 = erfcx_pos(fabs(d1) * M_SQRT1_2);
-  const double X2 = erfcx_pos(fabs(d2) * M_SQRT1_2);
+  double X1, X2;
+  erfcx_pos2(fabs(d1) * M_SQRT1_2, fabs(d2) * M_SQRT1_2, X1, X2);
   const double hE = 0.5 * f * E;
   if (L <= 0.0)
     return D * (d1 <= 0.0 ? hE * (X1 - X2) : fma(-hE, X1 + X2, f));

@@ -8,13 +8,18 @@
 
 namespace sabr {
 
+// Swaps of up to this many forwards keep the map's per-lane recursion column
+// in registers; longer ones in LDS.
+constexpr int kMapRegLen = 16;
+
 // Doubles of LDS one wavefront needs for the LMM12 maps: per-forward alpha,
 // nu and the two correlation gap factors, a 64-byte record of SABR constants
-// per underlying, and a per-lane column of max_len doubles for the swap
-// recursion.  Each workgroup adds 6 doubles per underlying of market values.
+// per underlying, and (for swaps longer than kMapRegLen) a per-lane column of
+// max_len doubles for the swap recursion.  Each workgroup adds 6 doubles per
+// underlying of market values.
 __host__ __device__ inline int wave_lds_doubles(const DevMarket &m) {
   if (m.model == 0) return 0;
-  return 4 * m.max_nf + 8 * m.max_nu + kWave * m.max_len;
+  return 4 * m.max_nf + 8 * m.max_nu + (m.max_len > kMapRegLen ? kWave * m.max_len : 0);
 }
 
 struct SAArgs {
