@@ -94,6 +94,25 @@ def cpu_baseline(w, n_levels):
                        f"({qe:.3e} quote-evals, {dt:.1f} s, OpenMP over chains)")
 
 
+def measured_traffic(config, shape):
+    """HBM bytes per launch of the level kernel from the committed counter
+    record (FETCH_SIZE and WRITE_SIZE passes scaled by a copy kernel's
+    readings), or None when there is no record for this workload and launch
+    shape or the kernel sources changed since the counters were taken."""
+    from paper_2408_01470_amd import build
+    path = os.path.join(ROOT, "profiles", f"sa_level_kernel_{config}_counters.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if (rec.get("source_sha256") != build.source_digest()
+            or rec.get("waves_per_group") != shape.get("waves_per_group")
+            or rec.get("occupancy") != shape.get("occupancy")):
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def time_to_rmse(api, W, I, autotune):
     """Config c4: SA (512 chains, 50 levels x 100 steps) then LM polish of the
     64 best chain points, against plain SA (same chains) run for up to 4 x 200
@@ -264,7 +283,8 @@ def main():
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(args.config, {"waves_per_group": kw.get("waves", 0),
+                                                      "occupancy": kw.get("occupancy", 0)}),
             "flop_per_launch": flop_launch,
             "avg_launch_ms": avg_launch_s * 1e3,
             "launches_timed": int(lvl_ms.size),

@@ -16,6 +16,20 @@ HIPCC_FLAGS = [
 ]
 
 
+def source_digest() -> str:
+    """SHA-256 over the library's kernel and runtime sources (every .hip,
+    .hpp and .cpp under csrc/ except the pricing program), in name order:
+    identifies the kernel build that a set of hardware counters belongs to."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp", ".cpp")) and name != "elementary_calib.hip":
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
 CALIB_SRC = os.path.join(CSRC, "elementary_calib.hip")
 CALIB_BIN = os.path.join(HERE, "elementary_calib")
 

@@ -2,7 +2,9 @@
 // calibrator calls, for the algorithmic FLOP count of the roofline.
 //
 // Each kernel evaluates one function once per thread over n inputs drawn
-// from the ranges the cost kernels see; under
+// from the ranges the cost kernels see (the device library's exp, log1p,
+// sqrt and division, and the kernels' own erfcx, exp, log1p, sqrt and
+// reciprocal); under
 //   rocprofv3 --pmc SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64
 //                   SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64
 // the FP64 FLOP per call is 64 (ADD + MUL + TRANS + 2 FMA) / n minus the
@@ -36,23 +38,30 @@ __global__ void elem_kernel(const double *__restrict__ x, const double *__restri
   else if (FN == 2) r = log1p(a);
   else if (FN == 3) r = sqrt(a);
   else if (FN == 4) r = a / b;
-  else r = sabr::erfcx_pos(a);   // the kernels' own erfcx
+  else if (FN == 5) r = sabr::erfcx_pos(a);   // the kernels' own functions from here on
+  else if (FN == 6) r = sabr::exp_cw(a);
+  else if (FN == 7) r = sabr::log1p_tang(a);
+  else if (FN == 8) r = sabr::sqrt_gs(a);
+  else r = a * sabr::rcp_nr(b);
   out[i] = r;
 }
 
 int main() {
   const int n = 1 << 20;
   // inputs per function: exp in [-12, 0], log1p in [-0.6, 1.5], sqrt in
-  // [0.2, 4], div in [0.1, 10]/[0.1, 10], erfcx in [0, 8]
-  const double lo[6] = {0.0, -12.0, -0.6, 0.2, 0.1, 0.0};
-  const double hi[6] = {1.0, 0.0, 1.5, 4.0, 10.0, 8.0};
-  const char *names[6] = {"copy", "exp", "log1p", "sqrt", "div", "erfcx"};
+  // [0.2, 4], div in [0.1, 10]/[0.1, 10], erfcx in [0, 8]; the library
+  // functions (1-4), then the kernels' own (5-9)
+  constexpr int NF = 10;
+  const double lo[NF] = {0.0, -12.0, -0.6, 0.2, 0.1, 0.0, -12.0, -0.6, 0.2, 0.1};
+  const double hi[NF] = {1.0, 0.0, 1.5, 4.0, 10.0, 8.0, 0.0, 1.5, 4.0, 10.0};
+  const char *names[NF] = {"copy", "exp", "log1p", "sqrt", "div",
+                           "erfcx_pos", "exp_cw", "log1p_tang", "sqrt_gs", "rcp_nr*x"};
   double *dx, *dy, *dout;
   CHECK(hipMalloc(&dx, n * sizeof(double)));
   CHECK(hipMalloc(&dy, n * sizeof(double)));
   CHECK(hipMalloc(&dout, n * sizeof(double)));
   std::vector<double> hx(n), hy(n);
-  for (int f = 0; f < 6; ++f) {
+  for (int f = 0; f < NF; ++f) {
     unsigned long long s = 88172645463325252ULL + f;
     for (int i = 0; i < n; ++i) {
       s ^= s << 13;
@@ -75,7 +84,11 @@ int main() {
       case 2: hipLaunchKernelGGL(elem_kernel<2>, grid, block, 0, 0, dx, dy, dout, n); break;
       case 3: hipLaunchKernelGGL(elem_kernel<3>, grid, block, 0, 0, dx, dy, dout, n); break;
       case 4: hipLaunchKernelGGL(elem_kernel<4>, grid, block, 0, 0, dx, dy, dout, n); break;
-      default: hipLaunchKernelGGL(elem_kernel<5>, grid, block, 0, 0, dx, dy, dout, n); break;
+      case 5: hipLaunchKernelGGL(elem_kernel<5>, grid, block, 0, 0, dx, dy, dout, n); break;
+      case 6: hipLaunchKernelGGL(elem_kernel<6>, grid, block, 0, 0, dx, dy, dout, n); break;
+      case 7: hipLaunchKernelGGL(elem_kernel<7>, grid, block, 0, 0, dx, dy, dout, n); break;
+      case 8: hipLaunchKernelGGL(elem_kernel<8>, grid, block, 0, 0, dx, dy, dout, n); break;
+      default: hipLaunchKernelGGL(elem_kernel<9>, grid, block, 0, 0, dx, dy, dout, n); break;
     }
     CHECK(hipGetLastError());
     CHECK(hipDeviceSynchronize());

@@ -2,35 +2,47 @@
 
 Counts follow the formulas as the kernels state them, each operation counted
 once where the definition needs it: add, sub and mul count 1, fma counts 2,
-comparisons, selects, negations and integer work (the Philox generator) count
-0; a branch counts its common side only (the |z| <= 1 quotient of z/x(z),
-not its series).  An elementary function counts the FP64 operations of one
-call of the device math library (``ELEMENTARY``): the hardware counters
-SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 of a kernel that calls only that
-function on a million inputs drawn from the ranges the cost kernels see,
-minus a plain copy kernel, as ADD + MUL + TRANS + 2 FMA per call.
-Units: FLOP per quote evaluation, per underlying, per chain step (parameter
-map, proposal, Metropolis) and per launch of the per-level annealing kernel.
+a hardware reciprocal or reciprocal square root seed counts 1, comparisons,
+selects, negations, exponent manipulation and integer work (the Philox
+generator) count 0; a branch counts its common side only (the |z| <= 1
+quotient of z/x(z), not its series).  Elementary functions count the FP64
+operations of their implementation (``ELEMENTARY``): the kernels' own
+branch-free exp, log1p, sqrt, reciprocal and erfcx (counted from their
+definitions; the erfcx count is confirmed by the hardware counters
+SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 of a kernel calling only it, as
+ADD + MUL + TRANS + 2 FMA per call), and the device library's division,
+measured the same way.  Units: FLOP per quote evaluation, per underlying,
+per chain step (parameter map, proposal, Metropolis) and per launch of the
+per-level annealing kernel.
 """
 from __future__ import annotations
 
 import numpy as np
 
-# FP64 FLOP per call of the device math library, measured as described above.
-ELEMENTARY = {"exp": 27.0, "log1p": 45.0, "sqrt": 9.0, "div": 13.0, "erfcx": 60.0}
+# FP64 FLOP per call.
+#   exp   : x/ln2, two-step Cody-Waite reduction, degree-11 Horner      1+4+22
+#   log1p : two-sum, reduction, reciprocal, degree-6 Horner in s^2, sum    47
+#   sqrt  : rsq seed, two Goldschmidt passes, final correction         3+12+4
+#   rcp   : rcp seed and two Newton steps                                 1+8
+#   erfcx : x +- K, reciprocal, degree-24 Horner, scale              2+9+48+2
+#   div   : device library division (measured)                             14
+ELEMENTARY = {"exp": 27.0, "log1p": 47.0, "sqrt": 19.0, "rcp": 9.0, "erfcx": 61.0, "div": 14.0}
 
 
 def _e(name, n=1):
     return n * ELEMENTARY[name]
 
 
-def sabr_const() -> float:
+def sabr_const(model: int) -> float:
     """Constants of one (alpha, beta, rho, nu): rho^2 and 2 - 3 rho^2 (3),
-    nu/alpha (a division), the three corr coefficients alpha^2 (1-b)^2/24,
+    nu/alpha (a library division for GLOBAL4, a reciprocal and a product
+    for LMM12), the three corr coefficients alpha^2 (1-b)^2/24,
     rho b nu alpha/4, (2 - 3 rho^2) nu^2/24 (3 + 4 + 3) and the series
     coefficient (2 - 3 rho^2)/12 (1); (1-b) and (1-b)^2 add 2 when beta is a
     parameter."""
-    return 14.0 + _e("div")
+    if model == 0:
+        return 16.0 + _e("div")
+    return 15.0 + _e("rcp")
 
 
 def hagan_quote(fixed_beta: bool) -> float:
@@ -39,8 +51,8 @@ def hagan_quote(fixed_beta: bool) -> float:
     (3 and a division), P = q^2 + T (ca + cb q + cc q^2) (7), the numerator
     alpha P z (2) and denominator q^3 D1 x (4); with beta a parameter also
     q = exp((1-b)/2 ln(fK)) (2) and D1 = 1 + u/24 + u^2/1920,
-    u = (1-b)^2 L^2 (6)."""
-    f = 22 + _e("sqrt") + _e("log1p") + _e("div")
+    u = (1-b)^2 L^2 (6).  The quotient is a reciprocal and a product."""
+    f = 22 + _e("sqrt") + _e("log1p") + _e("rcp")
     if not fixed_beta:
         f += 2 + _e("exp") + 6
     return f
@@ -48,7 +60,7 @@ def hagan_quote(fixed_beta: bool) -> float:
 
 def eq3_quote(fixed_beta: bool) -> float:
     """Paper eq. (sigmaHagan) for one quote: nu = (nu/alpha) alpha (1),
-    w = f^(1-b)/alpha (a division), rho nu w (2), the two bracket
+    w = f^(1-b)/alpha (a library division), rho nu w (2), the two bracket
     coefficients (2 and 12), the quadratic in k (4) and the numerator scale
     (1); fp = exp((1-b) ln f) (1) when beta is a parameter."""
     f = 22 + _e("div")
@@ -58,11 +70,11 @@ def eq3_quote(fixed_beta: bool) -> float:
 
 
 def black_quote() -> float:
-    """sigma and 1/sigma from the vol fraction (5 and one division), then the
-    Black-76 out-of-the-money price: sd, d1, d2 (6), E = exp(-d1^2/2) (2),
-    the two erfcx arguments (2), f E/2 (2), the combination (3) and the
+    """sigma and 1/sigma from the vol fraction (5 and one reciprocal), then
+    the Black-76 out-of-the-money price: sd, d1, d2 (6), E = exp(-d1^2/2)
+    (2), the two erfcx arguments (2), f E/2 (2), the combination (3) and the
     discount (1)."""
-    return 5 + _e("div") + 16 + _e("exp") + _e("erfcx", 2)
+    return 5 + _e("rcp") + 16 + _e("exp") + _e("erfcx", 2)
 
 
 RESIDUAL = 4.0   # r = m - target, acc += (w r) r
@@ -71,7 +83,7 @@ RESIDUAL = 4.0   # r = m - target, acc += (w r) r
 def quote_flops(model: int, formula: int, residual: int) -> float:
     fixed = model == 1
     f = hagan_quote(fixed) if formula == 0 else eq3_quote(fixed)
-    f += black_quote() if residual == 1 else _e("div")
+    f += black_quote() if residual == 1 else 1 + _e("rcp")
     return f + RESIDUAL
 
 
@@ -81,24 +93,24 @@ def map_flops_inst(market: dict, inst: int) -> float:
     consecutive forwards the two correlation factors (3 and 2 exp); per
     underlying its SABR constants; for a swap over n forwards the O(n)
     frozen-weight recursion (4 per forward forward, 14 per forward
-    backward) and its closing Nb, alpha_S, nu_S, rho_S (9, 2 sqrt,
-    3 divisions)."""
+    backward) and its closing Nb, alpha_S, nu_S, rho_S (12, 2 sqrt,
+    3 reciprocals)."""
     if int(market["model"]) == 0:
-        return sabr_const() + 2
+        return sabr_const(0) + 2
     f0, f1 = market["fwd_off"][inst], market["fwd_off"][inst + 1]
     u0, u1 = market["und_off"][inst], market["und_off"][inst + 1]
     nf = f1 - f0
     lens = np.asarray(market["und_len"][u0:u1])
     fwd = nf * (10 + _e("exp", 2)) + max(nf - 1, 0) * (3 + _e("exp", 2))
-    und = len(lens) * sabr_const()
+    und = len(lens) * sabr_const(1)
     swp = lens[lens > 1]
-    und += float(np.sum(18 * swp)) + len(swp) * (9 + _e("sqrt", 2) + _e("div", 3))
+    und += float(np.sum(18 * swp)) + len(swp) * (12 + _e("sqrt", 2) + _e("rcp", 3))
     return fwd + und
 
 
 def step_overhead(model: int) -> float:
     """Proposal (6 per coordinate), uniform conversion (1 per uniform, P+1),
-    Metropolis (dE, a division and an exponential)."""
+    Metropolis (dE, a library division and exponential)."""
     P = 4 if model == 0 else 12
     return 6 * P + (P + 1) + 1 + _e("div") + _e("exp")
 
