@@ -232,6 +232,33 @@ def sa_calibrate(m, chains, lb, ub, T0, cool, n_levels, n_steps, seed, step_frac
                 trace=trace, level_best=lbest, n_evals=nev)
 
 
+def sa_level0_sample(m, chains, lb, ub, T0, n_steps, seed, sample_inst, sample_chain,
+                     step_frac=0.05, x0=None, T0_per_inst=None):
+    """Level 0 of sa_calibrate for sampled (instance, chain) pairs."""
+    M = _mk(m)
+    P = M.P
+    ch = np.ascontiguousarray(np.broadcast_to(np.asarray(chains, np.int32), (M.n_inst,)),
+                              dtype=np.int32)
+    lb = np.ascontiguousarray(np.broadcast_to(lb, (M.n_inst, P)), dtype=np.float64)
+    ub = np.ascontiguousarray(np.broadcast_to(ub, (M.n_inst, P)), dtype=np.float64)
+    x0a = None if x0 is None else np.ascontiguousarray(np.broadcast_to(x0, (M.n_inst, P)),
+                                                       dtype=np.float64)
+    t0i = None if T0_per_inst is None else np.ascontiguousarray(T0_per_inst, dtype=np.float64)
+    cfg = OracleSAConfig(T0, 1.0, step_frac, 1, n_steps, seed, _p(t0i, _f64p))
+    si = np.ascontiguousarray(sample_inst, np.int32)
+    sc = np.ascontiguousarray(sample_chain, np.int32)
+    n = len(si)
+    acc = np.zeros((n, int(n_steps)), np.uint8)
+    F = np.zeros(n)
+    BF = np.zeros(n)
+    BX = np.zeros((n, P))
+    _check(lib().oracle_sa_level0_sample(
+        ctypes.byref(M.s), ctypes.byref(cfg), _p(ch, _i32p), _p(lb, _f64p), _p(ub, _f64p),
+        _p(x0a, _f64p), n, _p(si, _i32p), _p(sc, _i32p), _p(acc, _u8p), _p(F, _f64p),
+        _p(BF, _f64p), _p(BX, _f64p)))
+    return dict(accept=acc, F=F, BF=BF, BX=BX)
+
+
 def lm_polish(m, params, pt_inst, lb, ub, max_iter=50, mu0=1e-3, tol=1e-12):
     M = _mk(m)
     P = M.P

@@ -845,6 +845,37 @@ int32_t oracle_cost_grad(const oracle_market *m, int32_t n_pts, const int32_t *p
 // Synchronous parallel simulated annealing (Sec. 3: the boxed SA loop, run by
 // many Markov chains; at the end of every temperature level all chains
 // restart from the final point with the lowest cost).
+// One chain's N Metropolis steps of level l at temperature T: proposal from
+// the level's uniforms, cost, acceptance test, best-ever update.  x, F, bx,
+// BF are the chain's state (updated); accept flags go to acc[s * stride].
+// Returns the number of accepted proposals.
+static int chain_level(const Inst &I, const oracle_sa_config &cfg, int i, int l, int c, double T,
+                       int P, const double *lo, const double *hi, double *x, double &F,
+                       double *bx, double &BF, uint8_t *acc, int64_t stride) {
+  const int N = cfg.n_steps;
+  std::vector<double> u(P + 1), xp(P);
+  int na = 0;
+  for (int s = 0; s < N; ++s) {
+    sa_uniforms(cfg.seed, i, l, N, s, c, P, u.data());
+    propose(P, x, u.data(), lo, hi, cfg.step_frac, xp.data());
+    double fp = cost_d(I, xp.data());
+    if (std::isnan(fp)) fp = kInf;
+    const double dE = fp - F;
+    const bool a = (dE <= 0.0) || (u[P] < std::exp(-dE / T));
+    if (a) {
+      for (int k = 0; k < P; ++k) x[k] = xp[k];
+      F = fp;
+      ++na;
+    }
+    if (acc) acc[(int64_t)s * stride] = a ? 1 : 0;
+    if (fp < BF) {
+      BF = fp;
+      for (int k = 0; k < P; ++k) bx[k] = xp[k];
+    }
+  }
+  return na;
+}
+
 int32_t oracle_sa_calibrate(const oracle_market *m, const oracle_sa_config *cfg,
                             const int32_t *chains, const double *lb, const double *ub,
                             const double *x0, double *best_x, double *best_f,
@@ -881,30 +912,10 @@ int32_t oracle_sa_calibrate(const oracle_market *m, const oracle_sa_config *cfg,
     for (int l = 0; l < L; ++l) {
       // 2. N Metropolis steps per chain at temperature T (chains independent)
 #pragma omp parallel for schedule(static)
-      for (int c = 0; c < C; ++c) {
-        std::vector<double> u(P + 1), xp(P);
-        double *x = &X[(size_t)c * P];
-        int na = 0;
-        for (int s = 0; s < N; ++s) {
-          sa_uniforms(cfg->seed, i, l, N, s, c, P, u.data());
-          propose(P, x, u.data(), lo, hi, cfg->step_frac, xp.data());
-          double fp = cost_d(I, xp.data());
-          if (std::isnan(fp)) fp = kInf;
-          const double dE = fp - F[c];
-          const bool acc = (dE <= 0.0) || (u[P] < std::exp(-dE / T));
-          if (acc) {
-            for (int k = 0; k < P; ++k) x[k] = xp[k];
-            F[c] = fp;
-            ++na;
-          }
-          if (accept) accept[acc_base + ((int64_t)l * N + s) * C + c] = acc ? 1 : 0;
-          if (fp < BF[c]) {
-            BF[c] = fp;
-            for (int k = 0; k < P; ++k) BX[(size_t)c * P + k] = xp[k];
-          }
-        }
-        nacc[c] = na;
-      }
+      for (int c = 0; c < C; ++c)
+        nacc[c] = chain_level(I, *cfg, i, l, c, T, P, lo, hi, &X[(size_t)c * P], F[c],
+                              &BX[(size_t)c * P], BF[c],
+                              accept ? accept + acc_base + (int64_t)l * N * C + c : nullptr, C);
       evals += (int64_t)C * N;
       // 3. level end: restart every chain at the lowest final cost (ties ->
       //    lowest chain index); the restart point is copied, not re-evaluated
@@ -943,6 +954,52 @@ int32_t oracle_sa_calibrate(const oracle_market *m, const oracle_sa_config *cfg,
     if (n_evals) n_evals[i] = evals;
     chain_base += C;
     acc_base += (int64_t)L * N * C;
+  }
+  return 0;
+}
+
+// Level 0 of the same annealing for a sample of chains (chains are
+// independent until the first level end): chain sample_chain[j] of
+// instance sample_inst[j] starts at x0 (default: box midpoint) and takes the
+// level's N steps at T0.  Outputs per sample: accept [n][N], final cost F,
+// best-ever cost BF and point BX [n][P].
+int32_t oracle_sa_level0_sample(const oracle_market *m, const oracle_sa_config *cfg,
+                                const int32_t *chains, const double *lb, const double *ub,
+                                const double *x0, int32_t n_sample, const int32_t *sample_inst,
+                                const int32_t *sample_chain, uint8_t *accept, double *F_out,
+                                double *BF_out, double *BX_out) {
+  if (!m || !cfg) return fail("null argument");
+  const int P = num_params(m->model);
+  if (P < 0) return fail("unknown model");
+  if (cfg->n_steps < 0) return fail("negative step count");
+  if (!(cfg->T0 > 0.0)) return fail("bad schedule");
+  const int N = cfg->n_steps;
+  std::vector<Inst> insts(m->n_inst);
+  std::vector<char> built(m->n_inst, 0);
+  for (int j = 0; j < n_sample; ++j) {
+    const int i = sample_inst[j];
+    if (i < 0 || i >= m->n_inst) return fail("sample instance out of range");
+    if (sample_chain[j] < 0 || sample_chain[j] >= chains[i]) return fail("sample chain out of range");
+    if (!built[i]) {
+      if (build_inst(m, i, insts[i])) return -1;
+      built[i] = 1;
+    }
+  }
+#pragma omp parallel for schedule(dynamic)
+  for (int j = 0; j < n_sample; ++j) {
+    const int i = sample_inst[j];
+    const double *lo = lb + (size_t)i * P, *hi = ub + (size_t)i * P;
+    std::vector<double> x(P);
+    for (int k = 0; k < P; ++k) x[k] = x0 ? x0[(size_t)i * P + k] : 0.5 * (lo[k] + hi[k]);
+    double F = cost_d(insts[i], x.data());
+    double BF = F;
+    double *bx = BX_out + (size_t)j * P;
+    for (int k = 0; k < P; ++k) bx[k] = x[k];
+    const double T = cfg->T0_per_inst ? cfg->T0_per_inst[i] : cfg->T0;
+    chain_level(insts[i], *cfg, i, 0, sample_chain[j], T, P, lo, hi, x.data(), F, bx, BF,
+                accept + (size_t)j * N, 1);
+    F_out[j] = F;
+    BF_out[j] = BF;
   }
   return 0;
 }

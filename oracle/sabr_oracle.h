@@ -113,6 +113,16 @@ int32_t oracle_sa_calibrate(const oracle_market *m, const oracle_sa_config *cfg,
                             double *chain_best_x, double *chain_best_f, uint8_t *accept,
                             double *level_trace, int32_t *level_best, int64_t *n_evals);
 
+/* Level 0 of the same annealing for sampled chains (chains are independent
+ * until the first level end): sample j is chain sample_chain[j] of instance
+ * sample_inst[j]; accept [n_sample][N], F_out / BF_out [n_sample] (final and
+ * best-ever cost), BX_out [n_sample][P] (best-ever point). */
+int32_t oracle_sa_level0_sample(const oracle_market *m, const oracle_sa_config *cfg,
+                                const int32_t *chains, const double *lb, const double *ub,
+                                const double *x0, int32_t n_sample, const int32_t *sample_inst,
+                                const int32_t *sample_chain, uint8_t *accept, double *F_out,
+                                double *BF_out, double *BX_out);
+
 /* Projected Levenberg-Marquardt polish of n_pts points (in place). */
 int32_t oracle_lm_polish(const oracle_market *m, int32_t n_pts, const int32_t *pt_inst,
                          double *params, const double *lb, const double *ub,

@@ -156,3 +156,22 @@ def test_lm_decreases_cost(oracle, c2_market):
     x, f, it = oracle.lm_polish(mk, start, None, lb, ub, max_iter=15)
     assert f[0] < f0
     assert np.all(x >= lb) and np.all(x <= ub)
+
+
+def test_level0_sample_matches_full_annealing(oracle, c1_market):
+    """The sampled-chain replay of level 0 reproduces sa_calibrate's level 0
+    (accept flags, per-chain best-ever cost and point) chain by chain."""
+    mk, _ = c1_market
+    lb, ub = I.box(0)
+    C, N = 40, 12
+    full = oracle.sa_calibrate(mk, C, lb, ub, T0=0.05, cool=0.8, n_levels=1, n_steps=N,
+                               seed=31, record=True)
+    chains = np.array([0, 7, 39, 12], np.int32)
+    smp = oracle.sa_level0_sample(mk, C, lb, ub, T0=0.05, n_steps=N, seed=31,
+                                  sample_inst=np.zeros(len(chains), np.int32),
+                                  sample_chain=chains)
+    acc = full["accept"].reshape(N, C)
+    for j, c in enumerate(chains):
+        assert np.array_equal(smp["accept"][j], acc[:, c])
+        assert smp["BF"][j] == full["chain_best_f"][c]
+        assert np.array_equal(smp["BX"][j], full["chain_best_x"][c])
