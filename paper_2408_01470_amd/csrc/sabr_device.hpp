@@ -143,12 +143,22 @@ __device__ __forceinline__ double sconst() {
 }
 #define SABR_SCONST(x) ::sabr::sconst<__builtin_bit_cast(unsigned long long, (x))>()
 
+// h t + c with c in a scalar register pair, as one VOP3 v_fma_f64.  Written
+// as fma() the compiler emits the two-address v_fmac_f64 instead, which
+// needs c copied into the destination vector register first (two extra
+// vector moves per Horner step).
+__device__ __forceinline__ double fma_s(double h, double t, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(h), "v"(t), "s"(c));
+  return r;
+}
+
 // Horner's rule on the coefficients C[0..DEG] (constant arrays), one chain
 // or two interleaved chains sharing each coefficient.
 template <const double *C, int DEG, size_t... I>
 __device__ __forceinline__ double horner_s(double t, std::index_sequence<I...>) {
   double h = SABR_SCONST(C[DEG]);
-  ((h = fma(h, t, SABR_SCONST(C[DEG - 1 - I]))), ...);
+  ((h = fma_s(h, t, SABR_SCONST(C[DEG - 1 - I]))), ...);
   return h;
 }
 template <const double *C, int DEG>
@@ -161,7 +171,7 @@ __device__ __forceinline__ void horner2_s(double t1, double t2, double &h1, doub
   double c = SABR_SCONST(C[DEG]);
   h1 = c;
   h2 = c;
-  ((c = SABR_SCONST(C[DEG - 1 - I]), h1 = fma(h1, t1, c), h2 = fma(h2, t2, c)), ...);
+  ((c = SABR_SCONST(C[DEG - 1 - I]), h1 = fma_s(h1, t1, c), h2 = fma_s(h2, t2, c)), ...);
 }
 
 // 1/d for a normal, finite d: v_rcp_f64 and two Newton steps (each squares
