@@ -153,13 +153,13 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const do
   for (int k = lane; k < in.nf; k += kWave) {
     const double T = m.f_T[in.f0 + k];
     FwdMap F;
-    F.al = fma(b, T, a) * exp_cw(-(c * T)) + d;
-    F.nv = fma(bn, T, an) * exp_cw(-(cn * T)) + dn;
+    F.al = fma(b, T, a) * exp_neg(-(c * T)) + d;
+    F.nv = fma(bn, T, an) * exp_neg(-(cn * T)) + dn;
     F.g1 = F.g2 = 0.0;
     if (k + 1 < in.nf) {
       const double dT = m.f_T[in.f0 + k + 1] - T;
-      F.g1 = exp_cw(-(lam1 * dT));
-      F.g2 = exp_cw(-(lam2 * dT));
+      F.g1 = exp_neg(-(lam1 * dT));
+      F.g2 = exp_neg(-(lam2 * dT));
     }
     w.fw[k] = F;
   }
@@ -227,14 +227,7 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
     omb = 1.0 - m.beta;
   }
   double acc = 0.0;
-  // The next pass's record is loaded while this pass computes, so the global
-  // load latency hides behind the quote arithmetic.
-  const QuoteRec *qrec = m.q + in.q0;
-  QuoteRec Rn{};
-  if (lane < in.nq) Rn = qrec[lane];
-  for (int q = lane; q < in.nq; q += kWave) {
-    const QuoteRec R = Rn;
-    if (q + kWave < in.nq) Rn = qrec[q + kWave];
+  auto quote = [&](const QuoteRec &R, int q) {
     const double L = R.L;
     const int u = R.und;
     const UndMkt U = um[u];
@@ -254,7 +247,7 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
       bad |= !(mv > 0.0) || !(mv < kInf);
       if (model) model[q] = mv;
     } else {
-      // one division gives sigma = numer/denom and 1/sigma = denom/numer
+      // one reciprocal gives sigma = numer/denom and 1/sigma = denom/numer
       const double rr = rcp_nr(vf.numer * vf.denom);
       const double sig = vf.numer * (vf.numer * rr);
       const double isig = vf.denom * (vf.denom * rr);
@@ -269,6 +262,20 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
     const double r = mv - R.tgt;
     acc = fma(R.w * r, r, acc);
     if (resid) resid[q] = r;
+  };
+  // Two record buffers in turn: the next pass's record is loaded while this
+  // pass computes (the global load latency hides behind the arithmetic), and
+  // no register copies are needed between passes.
+  const QuoteRec *qrec = m.q + in.q0;
+  const int nq = in.nq;
+  QuoteRec Ra{}, Rb{};
+  if (lane < nq) Ra = qrec[lane];
+  for (int q = lane; q < nq; q += 2 * kWave) {
+    if (q + kWave < nq) Rb = qrec[q + kWave];
+    quote(Ra, q);
+    if (q + kWave >= nq) break;
+    if (q + 2 * kWave < nq) Ra = qrec[q + 2 * kWave];
+    quote(Rb, q + kWave);
   }
   const double tot = wave_sum(acc);
   const bool any_bad = __any(bad);

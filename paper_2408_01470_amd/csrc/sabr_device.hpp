@@ -174,35 +174,36 @@ __device__ __forceinline__ void horner2_s(double t1, double t2, double &h1, doub
   ((c = SABR_SCONST(C[DEG - 1 - I]), h1 = fma_s(h1, t1, c), h2 = fma_s(h2, t2, c)), ...);
 }
 
-// 1/d for a normal, finite d: v_rcp_f64 and two Newton steps (each squares
-// the relative error), within an ulp or so of the rounded quotient.  A zero,
-// infinite or NaN d gives NaN, which every caller treats as a domain failure.
+// 1/d for a normal, finite d.  The v_rcp_f64 seed r0 has a relative error
+// below 2^-24 on MI355X (measured over 4M inputs: 4.6e-8); with
+// e = 1 - d r0 (exact to 2^-77 in one fma), 1/d = r0 (1 + e + e^2 + ...) and
+// r0 + r0 (e + e^2) leaves a truncation error e^3 < 2^-72: within an ulp or
+// so of the rounded quotient.  A zero, infinite or NaN d gives NaN, which
+// every caller treats as a domain failure.
 __device__ __forceinline__ double rcp_nr(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  r = fma(r, fma(-d, r, 1.0), r);
-  return fma(r, fma(-d, r, 1.0), r);
+  const double r = __builtin_amdgcn_rcp(d);
+  const double e = fma(-d, r, 1.0);
+  return fma(r, fma(e, e, e), r);
 }
 
-// sqrt(a) for a normal or zero a: Goldschmidt iteration (Markstein, IA-64
-// and Elementary Functions, 2000) from the v_rsq_f64 seed, g -> sqrt(a),
-// h -> 1/(2 sqrt(a)), two passes and a final Newton correction.
+// sqrt(a) for a positive normal a: Goldschmidt iteration (Markstein, IA-64
+// and Elementary Functions, 2000) from the v_rsq_f64 seed (relative error
+// below 2^-24 on MI355X, measured: 5.3e-8), g -> sqrt(a), h -> 1/(2 sqrt(a)):
+// one pass (error ~2^-47) and a final Newton correction g + (a - g^2) h.
+// Zero, infinite, negative or NaN a gives NaN.
 __device__ __forceinline__ double sqrt_gs(double a) {
   const double y = __builtin_amdgcn_rsq(a);
   double g = a * y, h = 0.5 * y;
-  double r = fma(-g, h, 0.5);
+  const double r = fma(-g, h, 0.5);
   g = fma(g, r, g);
   h = fma(h, r, h);
-  r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  g = fma(fma(-g, g, a), h, g);
-  if (a > 0.0 && a < kInf) return g;
-  return (a == 0.0 || a == kInf) ? a : __builtin_nan("");
+  return fma(fma(-g, g, a), h, g);
 }
 
 // exp(x) (method of exp_poly.hpp): k = rint(x/ln2), r = x - k ln2 in two fma
 // steps, 2^k p(r).  Underflows to 0 below -746, overflows to +inf above 710,
-// NaN stays NaN.
+// NaN stays NaN.  exp_neg below is the same for finite x <= 0 without the
+// upper clamp and the NaN test.
 __device__ __forceinline__ double exp_cw(double x) {
   const double xc = fmin(fmax(x, -746.0), 710.0);
   const double kd = rint(xc * kExpInvLn2);
@@ -213,11 +214,19 @@ __device__ __forceinline__ double exp_cw(double x) {
   return x == x ? e : x;
 }
 
-// log1p(t) (method of log1p_poly.hpp): v = 1 + t rounded with its exact
-// error e (two-sum), v = 2^k m with m in [sqrt(1/2), sqrt(2)), f = m - 1,
-// s = f/(2 + f), log m = f - s (f - s^2 P(s^2)), and
-// log1p(t) = k ln2 + log m + e/v.  -inf at t = -1, NaN below -1 or for NaN,
-// +inf at +inf; branch-free.
+__device__ __forceinline__ double exp_neg(double x) {
+  const double xc = fmax(x, -746.0);
+  const double kd = rint(xc * kExpInvLn2);
+  double r = fma(-kd, kExpLn2Hi, xc);
+  r = fma(-kd, kExpLn2Lo, r);
+  return ldexp(horner_s<kExpPoly, kExpDeg>(r), (int)kd);
+}
+
+// log1p(t) for t > -1 (method of log1p_poly.hpp): v = 1 + t rounded with its
+// exact error e (two-sum), v = 2^k m with m in [sqrt(1/2), sqrt(2)),
+// f = m - 1, s = f/(2 + f), log m = f - s (f - s^2 P(s^2)), and
+// log1p(t) = k ln2 + log m + e/v.  NaN for t <= -1, t = +inf or NaN t;
+// branch-free.
 __device__ __forceinline__ double log1p_tang(double t) {
   const double v = 1.0 + t;
   const double vv = v - 1.0;
@@ -232,21 +241,20 @@ __device__ __forceinline__ double log1p_tang(double t) {
   const double z = s * s;
   const double p = horner_s<kLog1pPoly, kLog1pDeg>(z);
   const double lf = fma(-s, fma(-z, p, f), f);
-  double rv = __builtin_amdgcn_rcp(v);
+  double rv = __builtin_amdgcn_rcp(v);   // e/v is below 2^-53 |v|: one step suffices
   rv = fma(rv, fma(-v, rv, 1.0), rv);
   const double kd = (double)k;
   const double res = fma(kd, kLn2Hi, lf + fma(kd, kLn2Lo, e * rv));
-  if (v > 0.0 && v < kInf) return res;
-  return v == 0.0 ? -kInf : (v == kInf ? kInf : __builtin_nan(""));
+  return v > 0.0 ? res : __builtin_nan("");
 }
 
 // erfcx(x) = exp(x^2) erfc(x) for x >= 0 (method of erfcx_poly.hpp): one
-// reciprocal r = 1/(x + K) from v_rcp_f64 and two Newton steps (x + K >= K,
-// so no range scaling is needed), t = (x - K) r, erfcx = h(t) r with h a
-// degree-24 polynomial; branch-free, no tables.  Arguments above 1e100 are
-// clamped: callers multiply the result by exp(-x^2), which is zero there.
+// reciprocal r = 1/(x + K) (x + K >= K, so no range scaling is needed),
+// t = (x - K) r, erfcx = h(t) r with h a degree-24 polynomial; branch-free,
+// no tables.  Arguments above 1e100 (and NaN) are taken as 1e100: callers
+// multiply the result by exp(-x^2), which is zero there.
 __device__ __forceinline__ double erfcx_pos(double x) {
-  x = x > 1e100 ? 1e100 : x;
+  x = fmin(x, 1e100);
   const double r = rcp_nr(x + kErfcxK);
   const double t = (x - kErfcxK) * r;
   return horner_s<kErfcxPoly, kErfcxDeg>(t) * r;
@@ -254,8 +262,8 @@ __device__ __forceinline__ double erfcx_pos(double x) {
 
 // erfcx_pos of two arguments, the two polynomial chains interleaved.
 __device__ __forceinline__ void erfcx_pos2(double x1, double x2, double &X1, double &X2) {
-  x1 = x1 > 1e100 ? 1e100 : x1;
-  x2 = x2 > 1e100 ? 1e100 : x2;
+  x1 = fmin(x1, 1e100);
+  x2 = fmin(x2, 1e100);
   const double r1 = rcp_nr(x1 + kErfcxK), r2 = rcp_nr(x2 + kErfcxK);
   double h1, h2;
   horner2_s<kErfcxPoly, kErfcxDeg>((x1 - kErfcxK) * r1, (x2 - kErfcxK) * r2, h1, h2,
@@ -371,7 +379,7 @@ __device__ __forceinline__ double black_otm(double f, double K, double L, double
   const double sd = sigma * sqrtT;
   const double d1 = fma(L * isigma, isqrtT, 0.5 * sd);
   const double d2 = d1 - sd;
-  const double E = exp_cw(-0.5 * d1 * d1);
+  const double E = exp_neg(-0.5 * d1 * d1);
   double X1, X2;
   erfcx_pos2(fabs(d1) * M_SQRT1_2, fabs(d2) * M_SQRT1_2, X1, X2);
   const double hE = 0.5 * f * E;
