@@ -17,12 +17,15 @@ struct NP<1> {
   static constexpr int P = 12;
 };
 
-// Per-wave LDS scratch of the LMM12 map: per forward {alpha, nu, g1, g2}
-// (g1, g2: correlation factors of the gap to the next forward); per
-// underlying its SABR constants; a per-lane column for the swap recursion.
+// Per-wave LDS scratch of the LMM12 map: per forward {alpha, nu, g1, g2, a}
+// (g1, g2: correlation factors of the gap to the next forward; a = v alpha,
+// the forward's term of the swap recursions); per underlying its SABR
+// constants; a per-lane column for long swap recursions.
 struct FwdMap {
-  double al, nv, g1, g2;
+  double al, nv, g1, g2, a, pad;
 };
+static_assert(sizeof(FwdMap) == 48, "16-byte aligned LDS record");
+constexpr int kFwdMapDoubles = 6;
 
 struct WaveLds {
   FwdMap *fw;      // [max_nf]
@@ -33,8 +36,8 @@ struct WaveLds {
 __device__ __forceinline__ WaveLds wave_lds(const DevMarket &m, double *base) {
   WaveLds w;
   w.fw = reinterpret_cast<FwdMap *>(base);
-  w.th = reinterpret_cast<SabrConst *>(base + 4 * m.max_nf);
-  w.lk = base + 4 * m.max_nf + 8 * m.max_nu;
+  w.th = reinterpret_cast<SabrConst *>(base + kFwdMapDoubles * m.max_nf);
+  w.lk = base + kFwdMapDoubles * m.max_nf + kSabrConstDoubles * m.max_nu;
   return w;
 }
 
@@ -59,8 +62,7 @@ struct SwapMoments {
 };
 
 template <int NMAX>
-__device__ __forceinline__ SwapMoments swap_moments_reg(const FwdMap *fw, const double *v, int e,
-                                                        int n) {
+__device__ __forceinline__ SwapMoments swap_moments_reg(const FwdMap *fw, int e, int n) {
   double Lk[NMAX];
   double Lacc = 0.0, suma = 0.0;
   bool bad = false;
@@ -69,7 +71,7 @@ __device__ __forceinline__ SwapMoments swap_moments_reg(const FwdMap *fw, const 
     if (j < n) {
       const FwdMap F = fw[e + j];
       bad |= !(F.al > 0.0) || !(F.nv >= 0.0);
-      const double aj = v[e + j] * F.al;
+      const double aj = F.a;
       Lk[j] = Lacc;
       suma += aj;
       Lacc = F.g1 * (Lacc + aj);
@@ -80,7 +82,7 @@ __device__ __forceinline__ SwapMoments swap_moments_reg(const FwdMap *fw, const 
   for (int j = NMAX - 1; j >= 0; --j) {
     if (j < n) {
       const FwdMap F = fw[e + j];
-      const double aj = v[e + j] * F.al;
+      const double aj = F.a;
       const double Rj = Lk[j] + aj + Rr;
       const double ar = aj * Rj;
       V += ar;
@@ -97,14 +99,14 @@ __device__ __forceinline__ SwapMoments swap_moments_reg(const FwdMap *fw, const 
   return SwapMoments{V, suma, Sb, Sbb, bad};
 }
 
-__device__ __forceinline__ SwapMoments swap_moments_lds(const FwdMap *fw, const double *v, int e,
-                                                        int n, double *lk) {
+__device__ __forceinline__ SwapMoments swap_moments_lds(const FwdMap *fw, int e, int n,
+                                                        double *lk) {
   double Lacc = 0.0, suma = 0.0;
   bool bad = false;
   for (int j = 0; j < n; ++j) {
     const FwdMap F = fw[e + j];
     bad |= !(F.al > 0.0) || !(F.nv >= 0.0);
-    const double aj = v[e + j] * F.al;
+    const double aj = F.a;
     lk[j * kWave] = Lacc;
     suma += aj;
     Lacc = F.g1 * (Lacc + aj);
@@ -112,7 +114,7 @@ __device__ __forceinline__ SwapMoments swap_moments_lds(const FwdMap *fw, const 
   double Rr = 0.0, Rb = 0.0, V = 0.0, Sb = 0.0, Sbb = 0.0;
   for (int j = n - 1; j >= 0; --j) {
     const FwdMap F = fw[e + j];
-    const double aj = v[e + j] * F.al;
+    const double aj = F.a;
     const double Rj = lk[j * kWave] + aj + Rr;
     const double ar = aj * Rj;
     V += ar;
@@ -155,6 +157,8 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const do
     FwdMap F;
     F.al = fma(b, T, a) * exp_neg(-(c * T)) + d;
     F.nv = fma(bn, T, an) * exp_neg(-(cn * T)) + dn;
+    F.a = m.f_v[in.f0 + k] * F.al;
+    F.pad = 0.0;
     F.g1 = F.g2 = 0.0;
     if (k + 1 < in.nf) {
       const double dT = m.f_T[in.f0 + k + 1] - T;
@@ -165,7 +169,6 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const do
   }
   wave_lds_sync();
   double *lk = w.lk + lane;
-  const double *v = m.f_v + in.f0;
   for (int i = lane; i < in.nu; i += kWave) {
     const int u = m.u_order[in.u0 + i];
     const int e = m.u_first[in.u0 + u];
@@ -179,8 +182,8 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const do
       bad |= !(ta > 0.0) || !(tn >= 0.0);
     } else {
       const SwapMoments S = (m.max_len <= kMapRegLen)
-                                ? swap_moments_reg<kMapRegLen>(w.fw, v, e, n)
-                                : swap_moments_lds(w.fw, v, e, n, lk);
+                                ? swap_moments_reg<kMapRegLen>(w.fw, e, n)
+                                : swap_moments_lds(w.fw, e, n, lk);
       const double V = S.V, suma = S.suma, Sb = S.Sb, Sbb = S.Sbb;
       bad |= S.bad;
       const double Nb = fma(eta2 * Sb, Sb, (1.0 - eta2) * Sbb);
@@ -198,8 +201,6 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const do
     K.ca = omb * omb * ta * ta * (1.0 / 24.0);
     K.cb = tr * beta * tn * ta * 0.25;
     K.cc = (2.0 - 3.0 * r2) * tn * tn * (1.0 / 24.0);
-    K.s2 = (2.0 - 3.0 * r2) * (1.0 / 12.0);
-    K.pad = 0.0;
     w.th[u] = K;
   }
   wave_lds_sync();

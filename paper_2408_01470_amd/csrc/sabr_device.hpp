@@ -277,14 +277,14 @@ __device__ __forceinline__ void erfcx_pos2(double x1, double x2, double &X1, dou
 // formula that does not depend on the quote.
 //   corr q^2 = q^2 + (ca + cb q + cc q^2) T, ca = (1-b)^2 alpha^2/24,
 //   cb = rho beta nu alpha/4, cc = (2 - 3 rho^2) nu^2/24;
-//   z/x(z) = 1 - (rho/2) z + ((2 - 3 rho^2)/12) z^2 + O(z^3)   (s2 below).
+//   z/x(z) = 1 - (rho/2) z + ((2 - 3 rho^2)/12) z^2 + O(z^3)   (near z = 0).
 // ---------------------------------------------------------------------------
 struct SabrConst {
   double alpha, rho, nua;   // nua = nu / alpha
-  double ca, cb, cc, s2;
-  double pad;
+  double ca, cb, cc;
 };
-static_assert(sizeof(SabrConst) == 64, "16-byte aligned LDS record");
+static_assert(sizeof(SabrConst) == 48, "16-byte aligned LDS record");
+constexpr int kSabrConstDoubles = 6;
 
 __device__ __forceinline__ SabrConst sabr_const(double alpha, double beta, double rho, double nu) {
   SabrConst k;
@@ -296,7 +296,6 @@ __device__ __forceinline__ SabrConst sabr_const(double alpha, double beta, doubl
   k.ca = omb * omb * alpha * alpha * (1.0 / 24.0);
   k.cb = rho * beta * nu * alpha * 0.25;
   k.cc = (2.0 - 3.0 * r2) * nu * nu * (1.0 / 24.0);
-  k.s2 = (2.0 - 3.0 * r2) * (1.0 / 12.0);
   return k;
 }
 
@@ -327,13 +326,15 @@ __device__ __forceinline__ VolFrac hagan2002_frac(const SabrConst &k, double L, 
   const bool mid = az <= 1.0;
   const double num = mid ? 2.0 * z : (z > 0.0 ? (s + z) - 1.0 : (1.0 + z) - s);
   const double den = mid ? (s + 1.0) - z : (z > 0.0 ? 1.0 - k.rho : (s - z) + k.rho);
-  const double x = log1p_tang(num * rcp_nr(den));
-  const bool small = az < kZSeries;
-  const double ser = fma(z, fma(z, k.s2, -0.5 * k.rho), 1.0);
+  double cn = z, cd = log1p_tang(num * rcp_nr(den));   // chi = cn / cd
+  if (az < kZSeries) {   // rare: the series, with (2 - 3 rho^2)/12 = 1/6 - rho^2/4
+    cn = fma(z, fma(z, fma(-0.25, k.rho * k.rho, 1.0 / 6.0), -0.5 * k.rho), 1.0);
+    cd = 1.0;
+  }
   const double Pq = fma(q, q, T * fma(q, fma(q, k.cc, k.cb), k.ca));
   VolFrac v;
-  v.numer = k.alpha * Pq * (small ? ser : z);
-  v.denom = q * q * q * D1 * (small ? 1.0 : x);
+  v.numer = k.alpha * Pq * cn;
+  v.denom = q * q * q * D1 * cd;
   return v;
 }
 

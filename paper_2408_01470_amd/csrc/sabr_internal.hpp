@@ -12,14 +12,25 @@ namespace sabr {
 // in registers; longer ones in LDS.
 constexpr int kMapRegLen = 16;
 
-// Doubles of LDS one wavefront needs for the LMM12 maps: per-forward alpha,
-// nu and the two correlation gap factors, a 64-byte record of SABR constants
-// per underlying, and (for swaps longer than kMapRegLen) a per-lane column of
-// max_len doubles for the swap recursion.  Each workgroup adds 6 doubles per
-// underlying of market values.
+// Doubles of LDS one wavefront needs for the LMM12 maps: a 48-byte record per
+// forward (alpha, nu, the two correlation gap factors, v alpha), a 48-byte
+// record of SABR constants per underlying, and (for swaps longer than
+// kMapRegLen) a per-lane column of max_len doubles for the swap recursion.
+// Each workgroup adds 6 doubles per underlying of market values.
 __host__ __device__ inline int wave_lds_doubles(const DevMarket &m) {
   if (m.model == 0) return 0;
-  return 4 * m.max_nf + 8 * m.max_nu + (m.max_len > kMapRegLen ? kWave * m.max_len : 0);
+  return 6 * m.max_nf + kSabrConstDoubles * m.max_nu +
+         (m.max_len > kMapRegLen ? kWave * m.max_len : 0);
+}
+
+// Steps whose uniforms one Philox pass of the annealing kernel produces: lane
+// l computes block (l & 3) of step (l >> 2), and the uniforms wait in LDS.
+constexpr int kUniSteps = 16;
+
+// Doubles of LDS per wave of the annealing kernels: the map's scratch and
+// kUniSteps x (P + 1) uniforms.
+__host__ __device__ inline int sa_wave_doubles(const DevMarket &m) {
+  return wave_lds_doubles(m) + kUniSteps * ((m.model == 0 ? 4 : 12) + 1);
 }
 
 struct SAArgs {

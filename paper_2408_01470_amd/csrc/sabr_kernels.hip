@@ -182,38 +182,54 @@ __global__ __launch_bounds__(256, OCC) void sa_level_kernel(DevMarket m, SAArgs 
   double f = a.RF[inst];
   double bf = a.BF[gc];
   const double T = a.Tcur[inst];
-  WaveLds w = wave_lds(m, smem + 6 * m.max_nu + (size_t)wid * lds_per_wave);
+  const double iT = 1.0 / T;
+  double *wbase = smem + 6 * m.max_nu + (size_t)wid * lds_per_wave;
+  WaveLds w = wave_lds(m, wbase);
+  double *uw = wbase + wave_lds_doubles(m);   // [kUniSteps][P + 1] uniforms
   int nacc = 0;
-  for (int s = 0; s < a.N; ++s) {
-    // uniforms u_0..u_P: lane k <= P takes word k mod 4 of Philox block k/4
-    double u = 0.0;
-    if (lane <= P) {
-      uint64_t wds[4];
-      philox4x64_10((uint64_t)level * (uint64_t)a.N + (uint64_t)s, (uint64_t)c,
-                    (uint64_t)(lane >> 2), 0, a.seed, (uint64_t)inst, wds);
-      const int j = lane & 3;
-      const uint64_t wd = j == 0 ? wds[0] : (j == 1 ? wds[1] : (j == 2 ? wds[2] : wds[3]));
-      u = u53(wd);
+  for (int s0 = 0; s0 < a.N; s0 += kUniSteps) {
+    // Uniforms u_0..u_P of step s are the words of Philox blocks 0..P/4 of
+    // counter (level N + s, chain, block, 0): word k mod 4 of block k/4.  One
+    // pass over the lanes makes those of kUniSteps steps.
+    {
+      const int sl = lane >> 2, blk = lane & 3;
+      if (s0 + sl < a.N && 4 * blk <= P) {
+        uint64_t wds[4];
+        philox4x64_10((uint64_t)level * (uint64_t)a.N + (uint64_t)(s0 + sl), (uint64_t)c,
+                      (uint64_t)blk, 0, a.seed, (uint64_t)inst, wds);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (4 * blk + j <= P) uw[sl * (P + 1) + 4 * blk + j] = u53(wds[j]);
+      }
     }
-    const double xp = own ? propose1(x, u, lo, hi, a.step_frac) : 0.0;
-    double p[P];
-    broadcast_params<P>(xp, p);
-    double fp = point_cost<MODEL, FORMULA, RESID>(m, in, um, p, w, nullptr, nullptr);
-    if (fp != fp) fp = kInf;
-    const double uP = readlane_d(u, P);
-    const double dE = fp - f;
-    const bool acc = (dE <= 0.0) || (uP < exp(-dE / T));
-    if (acc) {
-      x = xp;
-      f = fp;
-      ++nacc;
+    wave_lds_sync();
+    const int s1 = min(a.N, s0 + kUniSteps);
+    for (int s = s0; s < s1; ++s) {
+      const double *us = uw + (s - s0) * (P + 1);
+      const double u = lane <= P ? us[lane] : 0.0;
+      const double xp = own ? propose1(x, u, lo, hi, a.step_frac) : 0.0;
+      double p[P];
+      broadcast_params<P>(xp, p);
+      double fp = point_cost<MODEL, FORMULA, RESID>(m, in, um, p, w, nullptr, nullptr);
+      if (fp != fp) fp = kInf;
+      const double uP = us[P];
+      const double dE = fp - f;
+      // dE > 0 here: the argument is <= 0 (or NaN when both costs are +inf,
+      // which exp_neg maps to 0: a rejection, as exp(NaN) would give)
+      const bool acc = (dE <= 0.0) || (uP < exp_neg(-dE * iT));
+      if (acc) {
+        x = xp;
+        f = fp;
+        ++nacc;
+      }
+      if (a.accept && lane == 0)
+        a.accept[a.acc_base[inst] + ((int64_t)level * a.N + s) * C + c] = acc ? 1 : 0;
+      if (fp < bf) {
+        bf = fp;
+        bx = xp;
+      }
     }
-    if (a.accept && lane == 0)
-      a.accept[a.acc_base[inst] + ((int64_t)level * a.N + s) * C + c] = acc ? 1 : 0;
-    if (fp < bf) {
-      bf = fp;
-      bx = xp;
-    }
+    wave_lds_sync();   // the next chunk overwrites the uniforms
   }
   if (own) {
     a.X[gc * P + lane] = x;
@@ -379,7 +395,7 @@ int lds_budget_bytes() {
 }
 
 size_t sa_lds_bytes(const DevMarket &m, int waves) {
-  return (size_t)(6 * m.max_nu + waves * wave_lds_doubles(m)) * 8;
+  return (size_t)(6 * m.max_nu + waves * sa_wave_doubles(m)) * 8;
 }
 
 int sa_waves_per_group(const DevMarket &m, int want) {
@@ -408,7 +424,7 @@ hipError_t launch_cost(const DevMarket &m, int n_pts, const int *pt_inst, const 
 
 hipError_t launch_sa_init(const DevMarket &m, const SAArgs &a, int n_tiles, int waves,
                           hipStream_t s) {
-  const int ld = wave_lds_doubles(m);
+  const int ld = sa_wave_doubles(m);
   const size_t lds = sa_lds_bytes(m, waves);
 #define CALL(A, B, C)                                                                    \
   hipLaunchKernelGGL((sa_init_kernel<A, B, C>), dim3(n_tiles), dim3(kWave * waves), lds, s, \
@@ -420,7 +436,7 @@ hipError_t launch_sa_init(const DevMarket &m, const SAArgs &a, int n_tiles, int 
 
 hipError_t launch_sa_level(const DevMarket &m, const SAArgs &a, int level, int n_tiles,
                            int waves, int occupancy, hipStream_t s) {
-  const int ld = wave_lds_doubles(m);
+  const int ld = sa_wave_doubles(m);
   const size_t lds = sa_lds_bytes(m, waves);
 #define LAUNCH(A, B, C, O)                                                                   \
   hipLaunchKernelGGL((sa_level_kernel<A, B, C, O>), dim3(n_tiles), dim3(kWave * waves), lds, \
