@@ -57,6 +57,7 @@ struct sabr_plan {
   std::vector<DevInst> inst;
   std::vector<double> f_T, f_tauP, f_F;
   std::vector<int> u_first, u_len, u_order;
+  std::vector<sabr::UndMap> u_map;
   std::vector<double> u_S0, u_A, u_invA, u_T;
   std::vector<sabr::QuoteRec> q;  // und, kind, K filled on the host
   std::vector<int> q_und_g;
@@ -65,7 +66,7 @@ struct sabr_plan {
   size_t o_inst, o_fT, o_ftauP, o_fF, o_ufirst, o_ulen, o_uorder, o_uS0, o_uA, o_uinvA, o_uT,
       o_q, o_qundg, o_qvol, o_qwuser;  // uploaded (contiguous prefix)
   size_t upload_bytes = 0;
-  size_t o_fv, o_uS0b;
+  size_t o_fv, o_uS0b, o_uc0, o_umap;
   size_t total_bytes = 0;
   std::vector<unsigned char> staging;
   char *dev = nullptr;
@@ -186,6 +187,8 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
       return P->u_len[d.u0 + x] > P->u_len[d.u0 + y];
     });
     P->u_order.insert(P->u_order.end(), ord.begin(), ord.end());
+    for (int u : ord)
+      P->u_map.push_back(sabr::UndMap{u, P->u_first[d.u0 + u], P->u_len[d.u0 + u], 0});
     if (d.nq > P->max_nq) P->max_nq = d.nq;
     if (d.nu > P->max_nu) P->max_nu = d.nu;
     if (d.nf > P->max_nf) P->max_nf = d.nf;
@@ -205,6 +208,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   P->o_uA = L.take<double>(P->nU);
   P->o_uinvA = L.take<double>(P->nU);
   P->o_uT = L.take<double>(P->nU);
+  P->o_umap = L.take<sabr::UndMap>(P->nU);
   P->o_q = L.take<sabr::QuoteRec>(P->nQ);
   P->o_qundg = L.take<int>(P->nQ);
   P->o_qvol = L.take<double>(P->nQ);
@@ -212,6 +216,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   P->upload_bytes = L.off;
   P->o_fv = L.take<double>(P->nF);
   P->o_uS0b = L.take<double>(P->nU);
+  P->o_uc0 = L.take<double>(P->nU);
   P->total_bytes = L.off;
   P->staging.assign(P->upload_bytes, 0);
   auto put = [&](size_t off, const void *src, size_t bytes) {
@@ -228,6 +233,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   put(P->o_uA, P->u_A.data(), P->nU * 8);
   put(P->o_uinvA, P->u_invA.data(), P->nU * 8);
   put(P->o_uT, P->u_T.data(), P->nU * 8);
+  put(P->o_umap, P->u_map.data(), P->nU * sizeof(sabr::UndMap));
   put(P->o_q, P->q.data(), P->nQ * sizeof(sabr::QuoteRec));
   put(P->o_qundg, P->q_und_g.data(), P->nQ * 4);
   put(P->o_qvol, P->q_vol.data(), P->nQ * 8);
@@ -286,9 +292,11 @@ sabr_status sabr_plan_upload(sabr_plan *P, void *dev_buf, size_t bytes, void *st
   m.u_invA = D(P->o_uinvA);
   m.u_S0b = D(P->o_uS0b);
   m.u_T = D(P->o_uT);
+  m.u_map = reinterpret_cast<const sabr::UndMap *>(d + P->o_umap);
+  m.u_c0 = D(P->o_uc0);
   m.q = reinterpret_cast<const sabr::QuoteRec *>(d + P->o_q);
   e = sabr::launch_prep(m, reinterpret_cast<sabr::QuoteRec *>(d + P->o_q), D(P->o_fv),
-                        D(P->o_uS0b), D(P->o_qvol), D(P->o_qwuser), I(P->o_qundg),
+                        D(P->o_uS0b), D(P->o_uc0), D(P->o_qvol), D(P->o_qwuser), I(P->o_qundg),
                         D(P->o_ftauP), D(P->o_fF), P->nQ, P->nF, P->nU, s);
   if (e != hipSuccess) return hip_fail(e, "market precompute launch");
   P->dev = d;

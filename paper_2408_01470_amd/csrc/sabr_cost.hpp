@@ -142,8 +142,8 @@ __device__ __forceinline__ SwapMoments swap_moments_lds(const FwdMap *fw, int e,
 //   Nb = eta2 (sum b)^2 + (1 - eta2) sum_kl b_k b_l exp(-lambda2 |dT|),
 //   alpha_S = sqrt(V)/(A S0^b), nu_S = sqrt(Nb)/V,
 //   rho_S = rho (sum a)(sum b) / (sqrt(V) sqrt(Nb))   (0 if Nb = 0).
-// Underlyings are visited in decreasing length so the lanes of a pass run
-// recursions of similar length.
+// Underlyings are visited in decreasing length (the u_map table) so the lanes
+// of a pass run recursions of similar length.
 __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const double *p, WaveLds w) {
   const int lane = lane_id();
   const double a = p[0], b = p[1], c = p[2], d = p[3];
@@ -152,6 +152,10 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const do
   const double beta = m.beta, omb = 1.0 - beta;
   bool bad = !(fabs(rho) < 1.0) || !(lam1 >= 0.0) || !(lam2 >= 0.0) ||
              !(eta2 >= 0.0 && eta2 <= 1.0);
+  // the first underlying pass's entry is loaded before the forward pass
+  const UndMap *umap = m.u_map + in.u0;
+  UndMap un{0, 0, 1, 0};
+  if (lane < in.nu) un = umap[lane];
   for (int k = lane; k < in.nf; k += kWave) {
     const double T = m.f_T[in.f0 + k];
     FwdMap F;
@@ -170,9 +174,8 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const do
   wave_lds_sync();
   double *lk = w.lk + lane;
   for (int i = lane; i < in.nu; i += kWave) {
-    const int u = m.u_order[in.u0 + i];
-    const int e = m.u_first[in.u0 + u];
-    const int n = m.u_len[in.u0 + u];
+    const int u = un.u, e = un.e, n = un.n;
+    if (i + kWave < in.nu) un = umap[i + kWave];   // next pass's entry
     double ta, tr, tn;
     if (n == 1) {
       const FwdMap F = w.fw[e];
@@ -188,7 +191,7 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const do
       bad |= S.bad;
       const double Nb = fma(eta2 * Sb, Sb, (1.0 - eta2) * Sbb);
       const double sV = sqrt_gs(V), sN = sqrt_gs(Nb);
-      ta = sV * m.u_invA[in.u0 + u] * rcp_nr(m.u_S0b[in.u0 + u]);
+      ta = sV * m.u_c0[in.u0 + u];
       tn = sN * rcp_nr(V);
       tr = (sN > 0.0) ? rho * suma * Sb * rcp_nr(sV * sN) : 0.0;
       bad |= !(V > 0.0) || !(fabs(tr) < 1.0);

@@ -49,6 +49,12 @@ struct QuoteRec {
 };
 static_assert(sizeof(QuoteRec) == 64, "quote record must be 64 bytes");
 
+// One underlying in the order the map visits them (per instance, decreasing
+// swap length): local index, first forward, length.
+struct alignas(16) UndMap {
+  int u, e, n, pad;
+};
+
 struct DevMarket {
   int n_inst, model, formula, residual;
   double beta;           // fixed beta (LMM12)
@@ -61,6 +67,8 @@ struct DevMarket {
   const int *u_first, *u_len;
   const int *u_order;    // per instance: underlyings by decreasing length
   const double *u_S0, *u_A, *u_invA, *u_S0b, *u_T;  // swap rate, annuity, 1/A, S0^beta, expiry
+  const UndMap *u_map;   // per instance: u_order[i] with its first forward and length
+  const double *u_c0;    // 1/(A S0^beta) per underlying
   // quotes
   const QuoteRec *q;
 };

@@ -20,13 +20,17 @@ namespace {
 // Market precompute (market-only quantities, once per upload).  The host has
 // written und, kind and K of every quote record; this fills the rest.
 // ---------------------------------------------------------------------------
-__global__ void prep_kernel(DevMarket m, QuoteRec *q, double *f_v, double *u_S0b,
+__global__ void prep_kernel(DevMarket m, QuoteRec *q, double *f_v, double *u_S0b, double *u_c0,
                             const double *q_vol, const double *q_wuser, const int *q_und_g,
                             const double *f_tauP, const double *f_F, int n_q, int n_f, int n_u) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const double beta = m.beta, omb = 1.0 - beta;
   if (i < n_f) f_v[i] = f_tauP[i] * pow(f_F[i], beta);
-  if (i < n_u) u_S0b[i] = pow(m.u_S0[i], beta);
+  if (i < n_u) {
+    const double S0b = pow(m.u_S0[i], beta);
+    u_S0b[i] = S0b;
+    u_c0[i] = m.u_invA[i] / S0b;
+  }
   if (i >= n_q) return;
   const int gu = q_und_g[i];
   QuoteRec R = q[i];
@@ -350,7 +354,7 @@ __global__ __launch_bounds__(256) void sa_final_kernel(SAArgs a) {
 // ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
-hipError_t launch_prep(const DevMarket &m, QuoteRec *q, double *f_v, double *u_S0b,
+hipError_t launch_prep(const DevMarket &m, QuoteRec *q, double *f_v, double *u_S0b, double *u_c0,
                        const double *q_vol, const double *q_wuser, const int *q_und_g,
                        const double *f_tauP, const double *f_F, int n_q, int n_f, int n_u,
                        hipStream_t s) {
@@ -358,7 +362,7 @@ hipError_t launch_prep(const DevMarket &m, QuoteRec *q, double *f_v, double *u_S
   if (n_f > n) n = n_f;
   if (n_u > n) n = n_u;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(prep_kernel, dim3((n + 255) / 256), dim3(256), 0, s, m, q, f_v, u_S0b,
+  hipLaunchKernelGGL(prep_kernel, dim3((n + 255) / 256), dim3(256), 0, s, m, q, f_v, u_S0b, u_c0,
                      q_vol, q_wuser, q_und_g, f_tauP, f_F, n_q, n_f, n_u);
   return hipGetLastError();
 }
