@@ -128,6 +128,99 @@ __device__ __forceinline__ UndMkt *stage_underlyings(const DevMarket &m, const D
   return um;
 }
 
+// Lexicographic (f, chain) minimum over the wavefront; chain C marks an empty
+// slot.  Every lane ends with the minimum.
+__device__ __forceinline__ void wave_argmin(double &f, int &i, int C) {
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) {
+    const double f2 = __shfl_xor(f, o, kWave);
+    const int i2 = __shfl_xor(i, o, kWave);
+    if (i2 < C && (i == C || f2 < f || (f2 == f && i2 < i))) {
+      f = f2;
+      i = i2;
+    }
+  }
+}
+
+// Level end of one instance by one workgroup: the chain with the lowest final
+// cost (ties: lowest chain) becomes every chain's restart point; the trace
+// gets the best-ever cost, the acceptance rate and the device time; T is
+// cooled.  scratch: 5 doubles per wave + 1 of LDS.
+__device__ void level_end_block(const SAArgs &a, int inst, int level, double *scratch) {
+  const int C = a.chains[inst];
+  const int64_t base = a.chain_base[inst];
+  double bestf = kInf, bestb = kInf, na = 0.0;
+  int bi = C, bj = C;
+  // four chains per thread and pass, their loads issued together
+  const int stride = blockDim.x;
+  for (int c0 = threadIdx.x; c0 < C; c0 += 4 * stride) {
+    double fc[4], bc[4];
+    int nc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = c0 + j * stride;
+      const bool in = c < C;
+      fc[j] = in ? a.F[base + c] : kInf;
+      bc[j] = in ? a.BF[base + c] : kInf;
+      nc[j] = in ? a.NACC[base + c] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {   // chains in increasing order
+      const int c = c0 + j * stride;
+      if (c < C && (bi == C || fc[j] < bestf)) {  // strict: the lowest chain wins ties
+        bestf = fc[j];
+        bi = c;
+      }
+      if (c < C && (bj == C || bc[j] < bestb)) {
+        bestb = bc[j];
+        bj = c;
+      }
+      na += (double)nc[j];
+    }
+  }
+  wave_argmin(bestf, bi, C);
+  wave_argmin(bestb, bj, C);
+  na = wave_sum(na);
+  const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  if (lane_id() == 0) {
+    scratch[5 * wid + 0] = bestf;
+    scratch[5 * wid + 1] = (double)bi;
+    scratch[5 * wid + 2] = bestb;
+    scratch[5 * wid + 3] = (double)bj;
+    scratch[5 * wid + 4] = na;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int v = 1; v < nw; ++v) {
+      const double f2 = scratch[5 * v], b2 = scratch[5 * v + 2];
+      const int i2 = (int)scratch[5 * v + 1], j2 = (int)scratch[5 * v + 3];
+      if (i2 < C && (bi == C || f2 < bestf || (f2 == bestf && i2 < bi))) {
+        bestf = f2;
+        bi = i2;
+      }
+      if (j2 < C && (bj == C || b2 < bestb || (b2 == bestb && j2 < bj))) {
+        bestb = b2;
+        bj = j2;
+      }
+      na += scratch[5 * v + 4];
+    }
+    scratch[5 * nw] = (double)bi;
+    a.RF[inst] = a.F[base + bi];
+    if (a.level_best) a.level_best[(size_t)inst * a.L + level] = bi;
+    if (a.trace) {
+      double *tr = a.trace + ((size_t)inst * a.L + level) * 3;
+      tr[0] = bestb;
+      tr[1] = a.N > 0 ? na / ((double)C * a.N) : 0.0;
+      tr[2] = (double)(wall_clock64() - a.t_start[0]) * a.ns_per_tick;
+    }
+    a.Tcur[inst] = a.cool * a.Tcur[inst];
+  }
+  __syncthreads();
+  const int bstar = (int)scratch[5 * nw];
+  const int P = a.P;
+  if (threadIdx.x < P) a.RX[(size_t)inst * P + threadIdx.x] = a.X[(base + bstar) * P + threadIdx.x];
+}
+
 template <int MODEL, int FORMULA, int RESID>
 __global__ __launch_bounds__(256) void sa_init_kernel(DevMarket m, SAArgs a, int lds_per_wave) {
   extern __shared__ double smem[];
@@ -175,139 +268,83 @@ __global__ __launch_bounds__(256, OCC) void sa_level_kernel(DevMarket m, SAArgs 
   const UndMkt *um = stage_underlyings(m, in, smem);
   const int C = a.chains[inst];
   const int c = a.tile_chain[blockIdx.x] + wid;
-  if (c >= C) return;
-  const int64_t gc = a.chain_base[inst] + c;
-  // lane k < P holds coordinate k of the chain's point, best point and box
-  const bool own = lane < P;
-  double x = own ? a.RX[(size_t)inst * P + lane] : 0.0;
-  const double lo = own ? a.lb[(size_t)inst * P + lane] : 0.0;
-  const double hi = own ? a.ub[(size_t)inst * P + lane] : 0.0;
-  double bx = own ? a.BX[gc * P + lane] : 0.0;
-  double f = a.RF[inst];
-  double bf = a.BF[gc];
-  const double T = a.Tcur[inst];
-  const double iT = 1.0 / T;
-  double *wbase = smem + 6 * m.max_nu + (size_t)wid * lds_per_wave;
-  WaveLds w = wave_lds(m, wbase);
-  double *uw = wbase + wave_lds_doubles(m);   // [kUniSteps][P + 1] uniforms
-  int nacc = 0;
-  for (int s0 = 0; s0 < a.N; s0 += kUniSteps) {
-    // Uniforms u_0..u_P of step s are the words of Philox blocks 0..P/4 of
-    // counter (level N + s, chain, block, 0): word k mod 4 of block k/4.  One
-    // pass over the lanes makes those of kUniSteps steps.
-    {
-      const int sl = lane >> 2, blk = lane & 3;
-      if (s0 + sl < a.N && 4 * blk <= P) {
-        uint64_t wds[4];
-        philox4x64_10((uint64_t)level * (uint64_t)a.N + (uint64_t)(s0 + sl), (uint64_t)c,
-                      (uint64_t)blk, 0, a.seed, (uint64_t)inst, wds);
+  if (c < C) {   // wave-uniform: waves past the instance's last chain have no work
+    const int64_t gc = a.chain_base[inst] + c;
+    // lane k < P holds coordinate k of the chain's point, best point and box
+    const bool own = lane < P;
+    double x = own ? a.RX[(size_t)inst * P + lane] : 0.0;
+    const double lo = own ? a.lb[(size_t)inst * P + lane] : 0.0;
+    const double hi = own ? a.ub[(size_t)inst * P + lane] : 0.0;
+    double bx = own ? a.BX[gc * P + lane] : 0.0;
+    double f = a.RF[inst];
+    double bf = a.BF[gc];
+    const double T = a.Tcur[inst];
+    const double iT = 1.0 / T;
+    double *wbase = smem + 6 * m.max_nu + (size_t)wid * lds_per_wave;
+    WaveLds w = wave_lds(m, wbase);
+    double *uw = wbase + wave_lds_doubles(m);   // [kUniSteps][P + 1] uniforms
+    int nacc = 0;
+    for (int s0 = 0; s0 < a.N; s0 += kUniSteps) {
+      // Uniforms u_0..u_P of step s are the words of Philox blocks 0..P/4 of
+      // counter (level N + s, chain, block, 0): word k mod 4 of block k/4.  One
+      // pass over the lanes makes those of kUniSteps steps.
+      {
+        const int sl = lane >> 2, blk = lane & 3;
+        if (s0 + sl < a.N && 4 * blk <= P) {
+          uint64_t wds[4];
+          philox4x64_10((uint64_t)level * (uint64_t)a.N + (uint64_t)(s0 + sl), (uint64_t)c,
+                        (uint64_t)blk, 0, a.seed, (uint64_t)inst, wds);
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (4 * blk + j <= P) uw[sl * (P + 1) + 4 * blk + j] = u53(wds[j]);
+          for (int j = 0; j < 4; ++j)
+            if (4 * blk + j <= P) uw[sl * (P + 1) + 4 * blk + j] = u53(wds[j]);
+        }
       }
+      wave_lds_sync();
+      const int s1 = min(a.N, s0 + kUniSteps);
+      for (int s = s0; s < s1; ++s) {
+        const double *us = uw + (s - s0) * (P + 1);
+        const double u = lane <= P ? us[lane] : 0.0;
+        const double xp = own ? propose1(x, u, lo, hi, a.step_frac) : 0.0;
+        double p[P];
+        broadcast_params<P>(xp, p);
+        double fp = point_cost<MODEL, FORMULA, RESID>(m, in, um, p, w, nullptr, nullptr);
+        if (fp != fp) fp = kInf;
+        const double uP = us[P];
+        const double dE = fp - f;
+        // dE > 0 here: the argument is <= 0 (or NaN when both costs are +inf,
+        // which exp_neg maps to 0: a rejection, as exp(NaN) would give)
+        const bool acc = (dE <= 0.0) || (uP < exp_neg(-dE * iT));
+        if (acc) {
+          x = xp;
+          f = fp;
+          ++nacc;
+        }
+        if (a.accept && lane == 0)
+          a.accept[a.acc_base[inst] + ((int64_t)level * a.N + s) * C + c] = acc ? 1 : 0;
+        if (fp < bf) {
+          bf = fp;
+          bx = xp;
+        }
+      }
+      wave_lds_sync();   // the next chunk overwrites the uniforms
     }
-    wave_lds_sync();
-    const int s1 = min(a.N, s0 + kUniSteps);
-    for (int s = s0; s < s1; ++s) {
-      const double *us = uw + (s - s0) * (P + 1);
-      const double u = lane <= P ? us[lane] : 0.0;
-      const double xp = own ? propose1(x, u, lo, hi, a.step_frac) : 0.0;
-      double p[P];
-      broadcast_params<P>(xp, p);
-      double fp = point_cost<MODEL, FORMULA, RESID>(m, in, um, p, w, nullptr, nullptr);
-      if (fp != fp) fp = kInf;
-      const double uP = us[P];
-      const double dE = fp - f;
-      // dE > 0 here: the argument is <= 0 (or NaN when both costs are +inf,
-      // which exp_neg maps to 0: a rejection, as exp(NaN) would give)
-      const bool acc = (dE <= 0.0) || (uP < exp_neg(-dE * iT));
-      if (acc) {
-        x = xp;
-        f = fp;
-        ++nacc;
-      }
-      if (a.accept && lane == 0)
-        a.accept[a.acc_base[inst] + ((int64_t)level * a.N + s) * C + c] = acc ? 1 : 0;
-      if (fp < bf) {
-        bf = fp;
-        bx = xp;
-      }
+    if (own) {
+      a.X[gc * P + lane] = x;
+      a.BX[gc * P + lane] = bx;
     }
-    wave_lds_sync();   // the next chunk overwrites the uniforms
-  }
-  if (own) {
-    a.X[gc * P + lane] = x;
-    a.BX[gc * P + lane] = bx;
-  }
-  if (lane == 0) {
-    a.F[gc] = f;
-    a.BF[gc] = bf;
-    a.NACC[gc] = nacc;
+    if (lane == 0) {
+      a.F[gc] = f;
+      a.BF[gc] = bf;
+      a.NACC[gc] = nacc;
+    }
   }
 }
 
 // Level end, one workgroup per instance: argmin of the final costs (ties ->
 // lowest chain), restart point, best-ever trace, next temperature.
 __global__ __launch_bounds__(256) void sa_level_end_kernel(SAArgs a, int level) {
-  __shared__ double sf[256], sb[256];
-  __shared__ int si[256], sj[256];
-  __shared__ long long sn[256];
-  const int inst = blockIdx.x;
-  const int C = a.chains[inst];
-  const int64_t base = a.chain_base[inst];
-  double bestf = kInf, bestb = kInf;
-  int bi = C, bj = C;
-  long long na = 0;
-  for (int c = threadIdx.x; c < C; c += blockDim.x) {
-    const double fc = a.F[base + c], bc = a.BF[base + c];
-    if (bi == C || fc < bestf) {  // strict: the lowest chain wins ties
-      bestf = fc;
-      bi = c;
-    }
-    if (bj == C || bc < bestb) {
-      bestb = bc;
-      bj = c;
-    }
-    na += a.NACC[base + c];
-  }
-  sf[threadIdx.x] = bestf;
-  si[threadIdx.x] = bi;
-  sb[threadIdx.x] = bestb;
-  sj[threadIdx.x] = bj;
-  sn[threadIdx.x] = na;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      const int t = threadIdx.x + o;
-      // lexicographic (f, chain) minimum; chain C marks an empty slot
-      if (si[t] < C && (si[threadIdx.x] == C || sf[t] < sf[threadIdx.x] ||
-                        (sf[t] == sf[threadIdx.x] && si[t] < si[threadIdx.x]))) {
-        sf[threadIdx.x] = sf[t];
-        si[threadIdx.x] = si[t];
-      }
-      if (sj[t] < C && (sj[threadIdx.x] == C || sb[t] < sb[threadIdx.x] ||
-                        (sb[t] == sb[threadIdx.x] && sj[t] < sj[threadIdx.x]))) {
-        sb[threadIdx.x] = sb[t];
-        sj[threadIdx.x] = sj[t];
-      }
-      sn[threadIdx.x] += sn[t];
-    }
-    __syncthreads();
-  }
-  const int bstar = si[0];
-  const int P = a.P;
-  if (threadIdx.x < P) a.RX[(size_t)inst * P + threadIdx.x] = a.X[(base + bstar) * P + threadIdx.x];
-  if (threadIdx.x == 0) {
-    a.RF[inst] = a.F[base + bstar];
-    if (a.level_best) a.level_best[(size_t)inst * a.L + level] = bstar;
-    if (a.trace) {
-      double *tr = a.trace + ((size_t)inst * a.L + level) * 3;
-      tr[0] = sb[0];
-      tr[1] = a.N > 0 ? (double)sn[0] / ((double)C * a.N) : 0.0;
-      tr[2] = (double)(wall_clock64() - a.t_start[0]) * a.ns_per_tick;
-    }
-    a.Tcur[inst] = a.cool * a.Tcur[inst];
-  }
+  __shared__ double scratch[5 * 4 + 1];
+  level_end_block(a, blockIdx.x, level, scratch);
 }
 
 // Best ever over all chains of each instance (ties -> lowest chain).
