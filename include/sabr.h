@@ -160,7 +160,8 @@ typedef struct {
   int32_t use_graph;         /* 1: capture the launch sequence in a hipGraph and replay it */
   void *const *level_events; /* [host] nullable: 2 * n_levels hipEvent_t recorded on `stream`
                                 just before and just after each level's annealing kernel
-                                (eager launches only; ignored when use_graph = 1) */
+                                (eager launches only; ignored when use_graph = 1); a null
+                                pair skips that level */
   int32_t occupancy;         /* register budget of the level kernel: minimum waves per SIMD
                                 (0 or 1 = compiler's choice, 3, 4); a tuning knob */
 } sa_config;

@@ -122,7 +122,9 @@ class Plan:
         ev = None
         if level_events is not None:
             # torch.cuda.Event objects, created (recorded once) on the caller's stream
-            ev = (ctypes.c_void_p * len(level_events))(*[e.cuda_event for e in level_events])
+            # None entries (in pairs) skip a level
+            ev = (ctypes.c_void_p * len(level_events))(
+                *[e.cuda_event if e is not None else None for e in level_events])
             self._keep["_ev"] = ev
         return SAConfig(float(T0), float(cool), float(step_frac), int(n_levels), int(n_steps),
                         int(seed), t0i.ctypes.data_as(_f64p) if t0i is not None else None,

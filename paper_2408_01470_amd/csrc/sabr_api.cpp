@@ -518,12 +518,13 @@ sabr_status sa_calibrate(const sabr_plan *Pc, const sa_config *cfg, const int32_
     const bool ev = events && !cfg->use_graph;
     for (int l = 0; l < L; ++l) {
       if (N > 0) {
-        if (ev && (r = hipEventRecord(static_cast<hipEvent_t>(events[2 * l]), q)) != hipSuccess)
+        const bool evl = ev && events[2 * l] && events[2 * l + 1];
+        if (evl && (r = hipEventRecord(static_cast<hipEvent_t>(events[2 * l]), q)) != hipSuccess)
           return r;
         r = sabr::launch_sa_level(P->dm, a, l, S.n_tiles, S.waves, cfg->occupancy, q);
         if (r != hipSuccess) return r;
-        if (ev && (r = hipEventRecord(static_cast<hipEvent_t>(events[2 * l + 1]), q)) !=
-                      hipSuccess)
+        if (evl && (r = hipEventRecord(static_cast<hipEvent_t>(events[2 * l + 1]), q)) !=
+                       hipSuccess)
           return r;
       }
       r = sabr::launch_sa_level_end(a, l, q);
