@@ -8,9 +8,9 @@ generator) count 0; a branch counts its common side only (the |z| <= 1
 quotient of z/x(z), not its series).  Elementary functions count the FP64
 operations of their implementation (``ELEMENTARY``): the kernels' own
 branch-free exp, log1p, sqrt, reciprocal and erfcx (counted from their
-definitions; the erfcx count is confirmed by the hardware counters
-SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 of a kernel calling only it, as
-ADD + MUL + TRANS + 2 FMA per call), and the device library's division,
+definitions, and confirmed by the hardware counters
+SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 of a kernel calling only one of them,
+as ADD + MUL + TRANS + 2 FMA per call), and the device library's division,
 measured the same way.  Units: FLOP per quote evaluation, per underlying,
 per chain step (parameter map, proposal, Metropolis) and per launch of the
 per-level annealing kernel.
@@ -19,14 +19,14 @@ from __future__ import annotations
 
 import numpy as np
 
-# FP64 FLOP per call.
+# FP64 FLOP per call (confirmed by the counters of the pricing program).
 #   exp   : x/ln2, two-step Cody-Waite reduction, degree-11 Horner      1+4+22
-#   log1p : two-sum, reduction, reciprocal, degree-6 Horner in s^2, sum    47
-#   sqrt  : rsq seed, two Goldschmidt passes, final correction         3+12+4
-#   rcp   : rcp seed and two Newton steps                                 1+8
-#   erfcx : x +- K, reciprocal, degree-24 Horner, scale              2+9+48+2
-#   div   : device library division (measured)                             14
-ELEMENTARY = {"exp": 27.0, "log1p": 47.0, "sqrt": 19.0, "rcp": 9.0, "erfcx": 61.0, "div": 14.0}
+#   log1p : two-sum, reduction, reciprocal, degree-6 Horner in s^2, sum    45
+#   sqrt  : rsq seed, one Goldschmidt pass, final correction          1+2+10
+#   rcp   : rcp seed, r0 + r0 (e + e^2)                                  1+6
+#   erfcx : x +- K, reciprocal, degree-24 Horner, scale              2+7+48+2
+#   div   : device library division                                        14
+ELEMENTARY = {"exp": 27.0, "log1p": 45.0, "sqrt": 13.0, "rcp": 7.0, "erfcx": 59.0, "div": 14.0}
 
 
 def _e(name, n=1):
