@@ -40,6 +40,8 @@ def parse():
                     help="levels of the oracle's bounded sample")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-time-to-rmse", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the cost / adjoint / LM measurement on c5")
     ap.add_argument("--waves", type=int, default=None,
                     help="fixed waves per workgroup of the level kernel (skips the autotuner)")
     ap.add_argument("--occupancy", type=int, default=None,
@@ -90,9 +92,84 @@ def cpu_baseline(w, n_levels):
                    n_steps=w.n_steps, seed=w.seed, T0_per_inst=np.array(T0s))
     dt = time.perf_counter() - t
     qe = w.quote_evals(n_levels=n_levels)
+    # one core: the first level of 512 of the chains
+    c1 = min(512, w.chains)
+    O.set_threads(1)
+    t = time.perf_counter()
+    O.sa_calibrate(M, c1, lb, ub, T0=T0s[0], cool=cool, n_levels=1, n_steps=w.n_steps,
+                   seed=w.seed, T0_per_inst=np.array(T0s))
+    dt1 = time.perf_counter() - t
+    O.set_threads(threads)
+    qe1 = w.n_inst * c1 * (1 + w.n_steps) * int(I.n_quotes(mk).max())
     return dict(value=qe / dt, unit="quote-evals/s", cores=threads, kind="oracle",
                 sample=f"first {n_levels} of {w.n_levels} levels of the same calibration "
-                       f"({qe:.3e} quote-evals, {dt:.1f} s, OpenMP over chains)")
+                       f"({qe:.3e} quote-evals, {dt:.1f} s, OpenMP over chains)",
+                single_core={"value": qe1 / dt1, "sample": f"first level, {c1} chains "
+                                                          f"({qe1:.3e} quote-evals, {dt1:.1f} s)"},
+                host_cpu=host_cpu())
+
+
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cost_and_adjoint(api, W, I):
+    """sabr_cost_batch, sabr_cost_vjp and sabr_lm_polish on config c5 (64
+    LMM12 markets x 8838 quotes): cost and gradient of 64 x 8192 points near
+    each market's true parameters, then LM on 128 such points per market.
+    Rates are n_pts x Q per second (device time, HIP events)."""
+    import torch
+    w = W.config5()
+    mk = W.synthesize(w, lambda vm, t: gpu_vols(api, vm, t))
+    plan = api.Plan(mk)
+    lb, ub = I.box(w.model)
+    Q = int(I.n_quotes(mk)[0])
+    per = w.chains
+    g = np.random.default_rng(I.SEED_BASE + 5001)
+    pts = np.clip(np.repeat(w.truth, per, axis=0) * g.uniform(0.95, 1.05, (w.n_inst * per, 12)),
+                  lb, ub)
+    inst = np.repeat(np.arange(w.n_inst, dtype=np.int32), per)
+    P = torch.tensor(pts, device="cuda")
+    pi = torch.tensor(inst, device="cuda")
+    s = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()                                  # warm-up (first-call costs)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        r = fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1) / 1e3
+
+    n = len(pts)
+    c, t_cost = timed(lambda: plan.cost(P, pt_inst=pi))
+    o, t_vjp = timed(lambda: plan.vjp(P, pt_inst=pi))
+    k = 128
+    sel = np.concatenate([np.arange(i * per, i * per + k) for i in range(w.n_inst)])
+    X0 = P[torch.tensor(sel, device="cuda")].contiguous()
+    I0 = pi[torch.tensor(sel, device="cuda")].contiguous()
+    (x, f, it), t_lm = timed(lambda: plan.lm(X0, lb, ub, pt_inst=I0, max_iter=50))
+    f0 = c[torch.tensor(sel, device="cuda")].cpu().numpy()
+    f = f.cpu().numpy()
+    it = it.cpu().numpy()
+    return {
+        "workload": "c5: 64 LMM12 markets x 8838 quotes",
+        "cost_batch": {"points": n, "s": t_cost, "quote_evals_per_s": n * Q / t_cost},
+        "cost_vjp": {"points": n, "s": t_vjp, "quote_evals_per_s": n * Q / t_vjp,
+                     "finite_gradients": int(np.isfinite(o["grad"].cpu().numpy()).all(axis=1).sum())},
+        "lm_polish": {"points": len(sel), "max_iter": 50, "s": t_lm,
+                      "iterations_mean": float(it.mean()), "iterations_max": int(it.max()),
+                      "median_cost_ratio": float(np.median(f / f0))},
+    }
 
 
 def measured_traffic(config, shape):
@@ -307,6 +384,8 @@ def main():
     }
     if not args.no_time_to_rmse:
         out["time_to_rmse"] = time_to_rmse(api, W, I, not args.no_autotune)
+    if not args.no_adjoint:
+        out["cost_and_adjoint"] = cost_and_adjoint(api, W, I)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_levels, w.n_levels))
     print(json.dumps(out))

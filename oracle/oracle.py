@@ -121,6 +121,10 @@ def max_threads():
     return lib().oracle_max_threads()
 
 
+def set_threads(n):
+    lib().oracle_set_threads(int(n))
+
+
 def hagan2002_vol(f, K, T, alpha, beta, rho, nu):
     return lib().oracle_hagan2002_vol(f, K, T, alpha, beta, rho, nu)
 

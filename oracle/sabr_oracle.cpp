@@ -695,6 +695,10 @@ extern "C" {
 const char *oracle_last_error(void) { return g_err.c_str(); }
 int32_t oracle_num_params(int32_t model) { return num_params(model); }
 
+void oracle_set_threads(int32_t n) {
+  if (n > 0) omp_set_num_threads(n);
+}
+
 int32_t oracle_max_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

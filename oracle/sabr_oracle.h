@@ -53,6 +53,8 @@ typedef struct {
 
 const char *oracle_last_error(void);
 int32_t oracle_num_params(int32_t model);
+/* OpenMP threads of the calls below (n > 0); for timing on one core. */
+void oracle_set_threads(int32_t n);
 int32_t oracle_max_threads(void);   /* OpenMP threads the parallel loops use */
 
 /* Single-quote primitives (pins). */
