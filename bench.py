@@ -41,7 +41,10 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-time-to-rmse", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true",
-                    help="skip the cost / adjoint / LM measurement on c5")
+                    help="skip the cost / adjoint / LM measurement")
+    ap.add_argument("--adjoint-config", default="c5", choices=["c2", "c5"])
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the cost / adjoint / LM measurement (one JSON line)")
     ap.add_argument("--waves", type=int, default=None,
                     help="fixed waves per workgroup of the level kernel (skips the autotuner)")
     ap.add_argument("--occupancy", type=int, default=None,
@@ -120,13 +123,13 @@ def host_cpu():
     return None
 
 
-def cost_and_adjoint(api, W, I):
-    """sabr_cost_batch, sabr_cost_vjp and sabr_lm_polish on config c5 (64
-    LMM12 markets x 8838 quotes): cost and gradient of 64 x 8192 points near
-    each market's true parameters, then LM on 128 such points per market.
-    Rates are n_pts x Q per second (device time, HIP events)."""
+def cost_and_adjoint(api, W, I, config="c5"):
+    """sabr_cost_batch, sabr_cost_vjp and sabr_lm_polish on an LMM12 workload
+    (default c5, 64 markets x 8838 quotes): cost and gradient of `chains`
+    points per market near its true parameters, then LM on 128 such points
+    per market.  Rates are n_pts x Q per second (device time, HIP events)."""
     import torch
-    w = W.config5()
+    w = W.CONFIGS[config]()
     mk = W.synthesize(w, lambda vm, t: gpu_vols(api, vm, t))
     plan = api.Plan(mk)
     lb, ub = I.box(w.model)
@@ -162,7 +165,7 @@ def cost_and_adjoint(api, W, I):
     f = f.cpu().numpy()
     it = it.cpu().numpy()
     return {
-        "workload": "c5: 64 LMM12 markets x 8838 quotes",
+        "workload": w.name.split(",")[0],
         "cost_batch": {"points": n, "s": t_cost, "quote_evals_per_s": n * Q / t_cost},
         "cost_vjp": {"points": n, "s": t_vjp, "quote_evals_per_s": n * Q / t_vjp,
                      "finite_gradients": int(np.isfinite(o["grad"].cpu().numpy()).all(axis=1).sum())},
@@ -273,6 +276,9 @@ def main():
     from paper_2408_01470_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.adjoint_only:
+        print(json.dumps(cost_and_adjoint(api, W, I, args.adjoint_config)))
+        return
     w = W.CONFIGS[args.config]()
     if args.levels is not None:
         w.n_levels = args.levels
@@ -385,7 +391,7 @@ def main():
     if not args.no_time_to_rmse:
         out["time_to_rmse"] = time_to_rmse(api, W, I, not args.no_autotune)
     if not args.no_adjoint:
-        out["cost_and_adjoint"] = cost_and_adjoint(api, W, I)
+        out["cost_and_adjoint"] = cost_and_adjoint(api, W, I, args.adjoint_config)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_levels, w.n_levels))
     print(json.dumps(out))
