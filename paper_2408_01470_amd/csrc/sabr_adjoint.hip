@@ -183,22 +183,25 @@ struct FwdExp {
 __device__ void lmm12_jacobian(const DevMarket &m, const DevInst &in, const double *p, WaveLds w,
                                const FwdExp *ef, double *col, double *M) {
   const int lane = lane_id();
-  const double a = p[0], b = p[1], c = p[2];
-  const double an = p[4], bn = p[5], cn = p[6];
+  const double a = p[0], b = p[1];
+  const double an = p[4], bn = p[5];
   const double rho = p[8], eta2 = p[10];
   const int ML = m.max_len;
-  double *ca = col;             // a_j
-  double *cR = col + ML * kWave;      // R_j
-  double *cb = col + 2 * ML * kWave;  // b_j
-  double *cB = col + 3 * ML * kWave;  // Be_j
-  double *cRb = col + 4 * ML * kWave; // R-bar_j
+  // per-lane columns (stride kWave): R_j, b_j, Be_j, and two scratch columns
+  double *cR = col + lane;
+  double *cb = col + ML * kWave + lane;
+  double *cB = col + 2 * ML * kWave + lane;
+  double *c3 = col + 3 * ML * kWave + lane;
+  double *c4 = col + 4 * ML * kWave + lane;
+  const double *fT = m.f_T + in.f0;
+  const double *fv = m.f_v + in.f0;
   for (int u = lane; u < in.nu; u += kWave) {
     double *Mu = M + (size_t)u * 36;
-    for (int j = 0; j < 36; ++j) Mu[j] = 0.0;
     const int e = m.u_first[in.u0 + u];
     const int n = m.u_len[in.u0 + u];
     if (n == 1) {
-      const double T = m.f_T[in.f0 + e];
+      for (int j = 0; j < 36; ++j) Mu[j] = 0.0;
+      const double T = fT[e];
       const double E = ef[e].E, En = ef[e].En;
       Mu[0] = E;
       Mu[1] = T * E;
@@ -211,56 +214,54 @@ __device__ void lmm12_jacobian(const DevMarket &m, const DevInst &in, const doub
       Mu[24 + 7] = 1.0;
       continue;
     }
-    const double *v = m.f_v + in.f0;
-    const double *fT = m.f_T + in.f0;
-    // forward values
-    double V = 0.0, sa = 0.0, Sb = 0.0;
-    for (int j = 0; j < n; ++j) {
-      const double aj = v[e + j] * w.fw[e + j].al;
-      ca[j * kWave + lane] = aj;
+    const FwdMap *fw = w.fw + e;
+    // Forward values in O(n): every sum over pairs with a factor
+    // exp(-lambda |T_j - T_l|) is a left plus a right recursion over the gap
+    // factors (g1 for rho_jl, g2 for the theta kernel e_jl); the |T_l - T_j|
+    // weighted sums add a time-weighted recursion (sum x_l k_jl (T_j - T_l)
+    // over l < j = T_j L_j - LT_j, and symmetrically on the right).
+    double sa = 0.0, V = 0.0, Sb = 0.0;
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) {        // left sums of a (g1)
+      cR[j * kWave] = acc;
+      const double aj = fw[j].a;
       sa += aj;
+      acc = fw[j].g1 * (acc + aj);
     }
-    for (int j = 0; j < n; ++j) {
-      double R = ca[j * kWave + lane];
-      double pr = 1.0;
-      for (int l = j + 1; l < n; ++l) {
-        pr *= w.fw[e + l - 1].g1;
-        R = fma(ca[l * kWave + lane], pr, R);
-      }
-      pr = 1.0;
-      for (int l = j - 1; l >= 0; --l) {
-        pr *= w.fw[e + l].g1;
-        R = fma(ca[l * kWave + lane], pr, R);
-      }
-      cR[j * kWave + lane] = R;
-      const double aj = ca[j * kWave + lane];
-      V = fma(aj, R, V);
-      const double bj = aj * R * w.fw[e + j].nv;
-      cb[j * kWave + lane] = bj;
+    acc = 0.0;
+    for (int j = n - 1; j >= 0; --j) {   // R_j = left + a_j + right; b_j
+      const double aj = fw[j].a;
+      const double Rj = cR[j * kWave] + aj + acc;
+      cR[j * kWave] = Rj;
+      V = fma(aj, Rj, V);
+      const double bj = aj * Rj * fw[j].nv;
+      cb[j * kWave] = bj;
       Sb += bj;
+      if (j > 0) acc = fw[j - 1].g1 * (acc + aj);
     }
-    double Nb = 0.0, bBe = 0.0, lam2_pairs = 0.0;
-    for (int j = 0; j < n; ++j) {
-      double Be = cb[j * kWave + lane], dBe = 0.0;  // sum_l b_l e_jl and sum_l b_l e_jl |dT|
-      double pr = 1.0;
-      for (int l = j + 1; l < n; ++l) {
-        pr *= w.fw[e + l - 1].g2;
-        const double bl = cb[l * kWave + lane];
-        Be = fma(bl, pr, Be);
-        dBe = fma(bl * pr, fT[e + l] - fT[e + j], dBe);
-      }
-      pr = 1.0;
-      for (int l = j - 1; l >= 0; --l) {
-        pr *= w.fw[e + l].g2;
-        const double bl = cb[l * kWave + lane];
-        Be = fma(bl, pr, Be);
-        dBe = fma(bl * pr, fT[e + j] - fT[e + l], dBe);
-      }
-      cB[j * kWave + lane] = Be;
-      const double bj = cb[j * kWave + lane];
+    double Lb = 0.0, LbT = 0.0;
+    for (int j = 0; j < n; ++j) {        // left sums of b (g2), plain and time-weighted
+      const double bj = cb[j * kWave], T = fT[e + j];
+      cB[j * kWave] = Lb;
+      c3[j * kWave] = fma(T, Lb, -LbT);
+      const double g2 = fw[j].g2;
+      Lb = g2 * (Lb + bj);
+      LbT = g2 * fma(bj, T, LbT);
+    }
+    double Nb = 0.0, bBe = 0.0, lam2_pairs = 0.0, Rb = 0.0, RbT = 0.0;
+    for (int j = n - 1; j >= 0; --j) {   // Be_j, sum_l b_l e_jl |T_l - T_j|
+      const double bj = cb[j * kWave], T = fT[e + j];
+      const double Be = cB[j * kWave] + bj + Rb;
+      cB[j * kWave] = Be;
+      const double dBe = c3[j * kWave] + fma(-T, Rb, RbT);
       Nb = fma(bj, fma(eta2, Sb, (1.0 - eta2) * Be), Nb);
       bBe = fma(bj, Be, bBe);
       lam2_pairs = fma(bj, dBe, lam2_pairs);
+      if (j > 0) {
+        const double g2 = fw[j - 1].g2;
+        Rb = g2 * (Rb + bj);
+        RbT = g2 * fma(bj, T, RbT);
+      }
     }
     const double sV = sqrt(V), sN = sqrt(Nb);
     const double c0 = m.u_invA[in.u0 + u] / m.u_S0b[in.u0 + u];
@@ -278,57 +279,63 @@ __device__ void lmm12_jacobian(const DevMarket &m, const DevInst &in, const doub
         Sbb = sR * rho * sa * inv;
         rb = sR * sa * Sb * inv;
       }
-      double *Mr = Mu + row * 12;
-      Mr[8] = rb;
-      Mr[10] = Nbb * (Sb * Sb - bBe);                // eta2
-      Mr[11] = -Nbb * (1.0 - eta2) * lam2_pairs;      // lambda2 (ordered pairs)
-      // R-bar_j = b-bar_j a_j nu_j + V-bar a_j with b-bar_j = 2 Nb-bar Btheta_j + S_b-bar
-      for (int j = 0; j < n; ++j) {
-        const double Bth = fma(eta2, Sb, (1.0 - eta2) * cB[j * kWave + lane]);
-        const double bbj = fma(2.0 * Nbb, Bth, Sbb);
-        const double aj = ca[j * kWave + lane];
-        cRb[j * kWave + lane] = aj * fma(bbj, w.fw[e + j].nv, Vb);
-      }
-      double l1 = 0.0;
-      for (int j = 0; j < n; ++j) {
-        const double Bth = fma(eta2, Sb, (1.0 - eta2) * cB[j * kWave + lane]);
-        const double bbj = fma(2.0 * Nbb, Bth, Sbb);
-        const double aj = ca[j * kWave + lane], Rj = cR[j * kWave + lane];
-        const double nuj = w.fw[e + j].nv;
-        // a-bar_j = b-bar_j R_j nu_j + V-bar R_j + s_a-bar + sum_m R-bar_m rho_mj
-        double abar = fma(bbj * nuj, Rj, fma(Vb, Rj, sab)) + cRb[j * kWave + lane];
-        double pr = 1.0;
-        for (int l = j + 1; l < n; ++l) {
-          pr *= w.fw[e + l - 1].g1;
-          const double Rbl = cRb[l * kWave + lane];
-          abar = fma(Rbl, pr, abar);
-          l1 = fma(Rbl * aj * pr, -(fT[e + l] - fT[e + j]), l1);
-        }
-        pr = 1.0;
-        for (int l = j - 1; l >= 0; --l) {
-          pr *= w.fw[e + l].g1;
-          const double Rbl = cRb[l * kWave + lane];
-          abar = fma(Rbl, pr, abar);
-          l1 = fma(Rbl * aj * pr, -(fT[e + j] - fT[e + l]), l1);
-        }
-        const double alb = abar * v[e + j];        // alpha-bar_j
-        const double nub = bbj * aj * Rj;          // nu-bar_j
+      // R-bar_j = a_j (b-bar_j nu_j + V-bar), b-bar_j = 2 Nb-bar Btheta_j + S_b-bar;
+      // right sums of R-bar (g1), plain (cb) and time-weighted (c4)
+      double RR = 0.0, RRT = 0.0;
+      for (int j = n - 1; j >= 0; --j) {
         const double T = fT[e + j];
-        const double E = ef[e + j].E, En = ef[e + j].En;
-        Mr[0] += alb * E;
-        Mr[1] += alb * T * E;
-        Mr[2] -= alb * T * fma(b, T, a) * E;
-        Mr[3] += alb;
-        Mr[4] += nub * En;
-        Mr[5] += nub * T * En;
-        Mr[6] -= nub * T * fma(bn, T, an) * En;
-        Mr[7] += nub;
+        const double bbj = fma(2.0 * Nbb, fma(eta2, Sb, (1.0 - eta2) * cB[j * kWave]), Sbb);
+        const double Rbj = fw[j].a * fma(bbj, fw[j].nv, Vb);
+        c3[j * kWave] = Rbj;
+        cb[j * kWave] = RR;
+        c4[j * kWave] = fma(-T, RR, RRT);
+        if (j > 0) {
+          const double g1 = fw[j - 1].g1;
+          RR = g1 * (RR + Rbj);
+          RRT = g1 * fma(Rbj, T, RRT);
+        }
       }
-      Mr[9] = l1;  // lambda1
+      // a-bar_j = b-bar_j nu_j R_j + V-bar R_j + s_a-bar + sum_m R-bar_m rho_mj, and
+      // the lambda1 term -sum_j a_j sum_l R-bar_l rho_jl |T_l - T_j|
+      double LR = 0.0, LRT = 0.0, l1 = 0.0;
+      double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0, m5 = 0.0, m6 = 0.0, m7 = 0.0;
+      for (int j = 0; j < n; ++j) {
+        const FwdMap F = fw[j];
+        const double T = fT[e + j];
+        const double aj = F.a, Rj = cR[j * kWave], Rbj = c3[j * kWave];
+        const double bbj = fma(2.0 * Nbb, fma(eta2, Sb, (1.0 - eta2) * cB[j * kWave]), Sbb);
+        const double abar =
+            fma(bbj * F.nv, Rj, fma(Vb, Rj, sab)) + ((LR + Rbj) + cb[j * kWave]);
+        l1 = fma(-aj, fma(T, LR, -LRT) + c4[j * kWave], l1);
+        const double alb = abar * fv[e + j];   // alpha-bar_j
+        const double nub = bbj * aj * Rj;      // nu-bar_j
+        const double E = ef[e + j].E, En = ef[e + j].En;
+        m0 = fma(alb, E, m0);
+        m1 = fma(alb * T, E, m1);
+        m2 = fma(-alb * T * fma(b, T, a), E, m2);
+        m3 += alb;
+        m4 = fma(nub, En, m4);
+        m5 = fma(nub * T, En, m5);
+        m6 = fma(-nub * T * fma(bn, T, an), En, m6);
+        m7 += nub;
+        LR = F.g1 * (LR + Rbj);
+        LRT = F.g1 * fma(Rbj, T, LRT);
+      }
+      double *Mr = Mu + row * 12;
+      Mr[0] = m0;
+      Mr[1] = m1;
+      Mr[2] = m2;
+      Mr[3] = m3;
+      Mr[4] = m4;
+      Mr[5] = m5;
+      Mr[6] = m6;
+      Mr[7] = m7;
+      Mr[8] = rb;
+      Mr[9] = l1;                                     // lambda1
+      Mr[10] = Nbb * (Sb * Sb - bBe);                 // eta2
+      Mr[11] = -Nbb * (1.0 - eta2) * lam2_pairs;      // lambda2 (ordered pairs)
     }
   }
-  (void)c;
-  (void)cn;
 }
 
 // Accumulates the cost, gradient and (optionally) normal equations of one

@@ -136,3 +136,37 @@ def test_lm_polish_matches_oracle(api, oracle, c1_market, c2_market, which):
     xg = xg.cpu().numpy()
     assert np.all(xg >= lb2) and np.all(xg <= ub2)
     assert np.all(xg[:, 10] == lb2[10]) if which == "lmm" else True
+
+
+def test_vjp_full_size_long_swaps(api, oracle):
+    """The 64-market workload at full size (8838 quotes, swaps of up to 20
+    forwards): gradient, J^T W J and J^T W r of sampled points of three
+    markets against the oracle's dual numbers."""
+    from paper_2408_01470_amd import workloads as W
+    w = W.config5()
+
+    def vols(vm, truth):
+        M = oracle.Market(vm)
+        out = []
+        for i in range(M.n_inst):
+            mv, _, _, ok = oracle.model_values(M, i, truth[i])
+            assert ok
+            out.append(mv)
+        return np.concatenate(out)
+
+    mk = W.synthesize(w, vols)
+    assert max(mk["und_len"]) == 20
+    g = np.random.default_rng(8)
+    insts = np.array([0, 0, 31, 63, 63], np.int32)
+    lb, ub = I.box(1)
+    pts = np.clip(w.truth[insts] * g.uniform(0.93, 1.07, (len(insts), 12)), lb, ub)
+    c_o, g_o, A_o, b_o = oracle.cost_grad(mk, pts, insts, normal=True)
+    plan = api.Plan(mk)
+    out = plan.vjp(torch.tensor(pts, device="cuda"), pt_inst=torch.tensor(insts, device="cuda"),
+                   normal=True)
+    np.testing.assert_allclose(out["cost"].cpu().numpy(), c_o, rtol=1e-12)
+    _grad_close(out["grad"].cpu().numpy(), g_o, 1e-10, "c5")
+    A_g = out["jtwj"].cpu().numpy()
+    sA = np.abs(A_o).max(axis=(1, 2), keepdims=True)
+    assert np.max(np.abs(A_g - A_o) / sA) <= 1e-10
+    _grad_close(out["jtwr"].cpu().numpy(), b_o, 1e-10, "c5 J^T W r")
