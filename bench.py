@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the cost / adjoint / LM measurement")
     ap.add_argument("--adjoint-config", default="c5", choices=["c2", "c5"])
+    ap.add_argument("--no-paper-e2", action="store_true",
+                    help="skip the replay of the paper's timed caplet calibration")
+    ap.add_argument("--paper-e2-only", action="store_true")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the cost / adjoint / LM measurement (one JSON line)")
     ap.add_argument("--waves", type=int, default=None,
@@ -263,6 +266,97 @@ def time_to_rmse(api, W, I, autotune):
     }
 
 
+def paper_e2(api, W, I, flops, autotune):
+    """The paper's own timed caplet calibration (Sec. 4.1.1) on its printed
+    EURIBOR data: PERFWD (13 forwards, P = 39), eq. (sigmaHagan), SA with
+    T0 = 10, Tmin = 0.01, rho = 0.99 (688 levels), N = 10, 16384 chains
+    (112,738,304 cost evaluations), then LM on each forward as a GLOBAL4
+    instance with beta frozen at 0.5 (the paper: Nelder-Mead).  Device time
+    of the annealing (HIP events) and wall time of the polish including its
+    host-side re-layout; MRE = mean |sigma_model - sigma_market| /
+    sigma_market over the 117 quotes, before and after the polish."""
+    import torch
+    w = W.paper_e2()
+    mk = w.market
+    plan = api.Plan(mk)
+    n_fwd = int(mk["fwd_off"][1])
+    lb, ub = I.box(I.MODEL_PERFWD, n_fwd)
+    kw = dict(T0=w.extra["T0"], cool=w.extra["cool"], n_levels=w.n_levels, n_steps=w.n_steps,
+              seed=w.seed, step_frac=w.step_frac)
+    shape = {}
+    if autotune:
+        from paper_2408_01470_amd import autotune as AT
+        t = AT.tune(plan, w.chains, lb, ub, w.n_steps)
+        shape = dict(waves=t["waves"], occupancy=t["occupancy"])
+    g4 = I.perfwd_as_global4(mk)
+    plan4 = api.Plan(g4)
+    beta = float(mk["beta"])
+    lb4 = np.tile([lb[0], beta, lb[1], lb[2]], (n_fwd, 1))
+    ub4 = np.tile([ub[0], beta, ub[1], ub[2]], (n_fwd, 1))
+    inst4 = torch.arange(n_fwd, dtype=torch.int32, device="cuda")
+    vol = np.asarray(mk["q_vol"])
+
+    def polish(x):
+        starts = torch.tensor(I.perfwd_points_as_global4(x, beta), device="cuda")
+        y, f4, it = plan4.lm(starts, lb4, ub4, pt_inst=inst4, max_iter=100)
+        return I.global4_points_as_perfwd(y.cpu().numpy()), it.cpu().numpy()
+
+    def mre(x):
+        _, mv = plan.cost(torch.tensor(x[None, :], device="cuda"), model=True)
+        mv = mv.cpu().numpy()[0, :len(vol)]
+        return float(np.mean(np.abs(mv - vol) / vol))
+
+    r = plan.sa(w.chains, lb, ub, trace=False, **shape, **kw)        # warm-up
+    polish(r["best_x"].cpu().numpy()[0])
+    ws = r["workspace"]
+    L = w.n_levels
+    sampled = list(range(0, L, EVENT_STRIDE))
+    s = torch.cuda.current_stream()
+    evs = [None] * (2 * L)
+    for l in sampled:
+        evs[2 * l] = torch.cuda.Event(enable_timing=True)
+        evs[2 * l + 1] = torch.cuda.Event(enable_timing=True)
+        evs[2 * l].record(s)
+        evs[2 * l + 1].record(s)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    r = plan.sa(w.chains, lb, ub, trace=False, workspace=ws, level_events=evs, **shape, **kw)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_sa = e0.elapsed_time(e1) / 1e3
+    x_sa = r["best_x"].cpu().numpy()[0]
+    t0 = time.perf_counter()
+    x_pol, it = polish(x_sa)
+    t_pol = time.perf_counter() - t0
+    lvl_ms = np.array([evs[2 * l].elapsed_time(evs[2 * l + 1]) for l in sampled])
+    flop_launch = flops.level_launch_flops(mk, w.chains, w.n_steps)
+    achieved = flop_launch / (float(lvl_ms.mean()) / 1e3) / 1e12
+    evals = w.chains * (1 + w.n_steps * L)
+    t = x_pol.reshape(-1, 3)
+    return {
+        "workload": w.name,
+        "cost_evaluations": evals,
+        "quote_evals": w.quote_evals(),
+        "t_sa_s": t_sa,
+        "cost_evals_per_s": evals / t_sa,
+        "quote_evals_per_s": w.quote_evals() / t_sa,
+        "level_kernel_avg_ms": float(lvl_ms.mean()),
+        "level_kernel_fp64_frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+        "t_polish_s": t_pol,
+        "polish_lm_iterations_max": int(it.max()),
+        "mre_sa": mre(x_sa),
+        "mre_polished": mre(x_pol),
+        "cost_sa": float(r["best_f"].item()),
+        "params_polished": {"alpha": t[:, 0].round(5).tolist(), "phi": t[:, 1].round(4).tolist(),
+                            "sigma": t[:, 2].round(4).tolist()},
+        "launch_shape": shape,
+        "paper": {"t_sa_s": w.extra["paper_sa_s"], "t_nelder_mead_s": w.extra["paper_nm_s"],
+                  "cost_evaluations": w.extra["paper_evals"], "mre": w.extra["paper_mre"],
+                  "hardware": "one GTX 470 (context, not a target)"},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -278,6 +372,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.adjoint_only:
         print(json.dumps(cost_and_adjoint(api, W, I, args.adjoint_config)))
+        return
+    if args.paper_e2_only:
+        print(json.dumps(paper_e2(api, W, I, flops, not args.no_autotune)))
         return
     w = W.CONFIGS[args.config]()
     if args.levels is not None:
@@ -392,6 +489,8 @@ def main():
         out["time_to_rmse"] = time_to_rmse(api, W, I, not args.no_autotune)
     if not args.no_adjoint:
         out["cost_and_adjoint"] = cost_and_adjoint(api, W, I, args.adjoint_config)
+    if not args.no_paper_e2:
+        out["paper_e2"] = paper_e2(api, W, I, flops, not args.no_autotune)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_levels, w.n_levels))
     print(json.dumps(out))

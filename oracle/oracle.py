@@ -94,7 +94,8 @@ class Market:
         a = self.arrays
         self.n_inst = len(a["q_off"]) - 1
         self.model = int(m["model"])
-        self.P = 4 if self.model == 0 else 12
+        fo = a["fwd_off"]
+        self.P = {0: 4, 1: 12}.get(self.model, 3 * int(fo[1] - fo[0]) if len(fo) > 1 else -1)
         self.nq = np.diff(a["q_off"])
         self.nu = np.diff(a["und_off"])
         self.s = OracleMarket(

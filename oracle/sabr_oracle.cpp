@@ -259,14 +259,14 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 int32_t build_inst(const oracle_market *m, int i, Inst &I) {
   if (!m) return fail("null market");
   if (i < 0 || i >= m->n_inst) return fail("instance index out of range");
-  if (m->model < 0 || m->model > 1) return fail("unknown model");
+  if (m->model < 0 || m->model > 2) return fail("unknown model");
   if (m->formula < 0 || m->formula > 1) return fail("unknown vol formula");
   if (m->residual < 0 || m->residual > 1) return fail("unknown residual mode");
   I.model = m->model;
   I.formula = m->formula;
   I.residual = m->residual;
   I.beta = m->beta;
-  if (m->model == 1 && !(m->beta >= 0.0 && m->beta <= 1.0)) return fail("beta outside [0,1]");
+  if (m->model != 0 && !(m->beta >= 0.0 && m->beta <= 1.0)) return fail("beta outside [0,1]");
   const int f0 = m->fwd_off[i], f1 = m->fwd_off[i + 1];
   const int u0 = m->und_off[i], u1 = m->und_off[i + 1];
   const int q0 = m->q_off[i], q1 = m->q_off[i + 1];
@@ -287,7 +287,7 @@ int32_t build_inst(const oracle_market *m, int i, Inst &I) {
     U.first = m->und_first[k];
     U.len = m->und_len[k];
     if (U.len < 1 || U.first < 0 || U.first + U.len > nf) return fail("bad underlying range");
-    if (m->model == 0 && U.len != 1) return fail("GLOBAL4 markets hold caplets only");
+    if (m->model != 1 && U.len != 1) return fail("GLOBAL4 and PERFWD markets hold caplets only");
     U.A = 0.0;
     for (int j = U.first; j < U.first + U.len; ++j) U.A += I.f[j].tau * I.f[j].P;
     U.S0 = 0.0;
@@ -335,12 +335,28 @@ int32_t build_inst(const oracle_market *m, int i, Inst &I) {
 
 int num_params(int model) { return model == 0 ? 4 : (model == 1 ? 12 : -1); }
 
+// Parameters per point of a market: 4 or 12, or 3 per forward for PERFWD,
+// whose instances must all hold the same number of forwards; -1 otherwise.
+int market_params(const oracle_market *m) {
+  if (m->model != 2) return num_params(m->model);
+  if (m->n_inst < 1) return -1;
+  const int nf = m->fwd_off[1] - m->fwd_off[0];
+  for (int i = 1; i < m->n_inst; ++i)
+    if (m->fwd_off[i + 1] - m->fwd_off[i] != nf) return -1;
+  return nf >= 1 ? 3 * nf : -1;
+}
+
 // ---------------------------------------------------------------------------
 // Parameter maps: model parameters -> SABR (alpha, beta, rho, nu) per
 // underlying.
 //  GLOBAL4: p = (alpha, beta, rho, nu) shared by every forward (the Hagan
 //    model with common parameters; the paper's x = (phi_ii, sigma_i, alpha_i)
 //    with phi_ii = rho, sigma_i = nu).
+//  PERFWD: p = (alpha_1, rho_1, nu_1, ..., alpha_n, rho_n, nu_n), one
+//    triple per forward, beta fixed: the Hagan model of Sec. 3 with its
+//    per-forward parameters x = (phi_ii, sigma_i, alpha_i) (phi_ii = rho_i,
+//    sigma_i = nu_i), the model calibrated to caplets in Sec. 4.1.1.  Every
+//    triple must lie in the domain, quoted or not.
 //  LMM12: p = (a, b, c, d, a_n, b_n, c_n, d_n, rho, lambda1, eta2, lambda2),
 //    beta fixed.  alpha_i = (a + b T_i) e^{-c T_i} + d and
 //    nu_i = (a_n + b_n T_i) e^{-c_n T_i} + d_n are the abcd forms of Sec. 2.3
@@ -368,6 +384,17 @@ bool map_params(const Inst &I, const S *p, std::vector<Theta<S>> &th) {
         !(std::fabs(val(rho)) < 1.0) || !(val(nu) >= 0.0))
       return false;
     for (size_t u = 0; u < I.u.size(); ++u) th[u] = Theta<S>{alpha, beta, rho, nu};
+    return true;
+  }
+  if (I.model == 2) {
+    for (size_t k = 0; k < I.f.size(); ++k)
+      if (!(val(p[3 * k]) > 0.0) || !(std::fabs(val(p[3 * k + 1])) < 1.0) ||
+          !(val(p[3 * k + 2]) >= 0.0))
+        return false;
+    for (size_t u = 0; u < I.u.size(); ++u) {
+      const int k = I.u[u].first;
+      th[u] = Theta<S>{p[3 * k], S(I.beta), p[3 * k + 1], p[3 * k + 2]};
+    }
     return true;
   }
   const S &a = p[0], &b = p[1], &c = p[2], &d = p[3];
@@ -694,6 +721,7 @@ extern "C" {
 
 const char *oracle_last_error(void) { return g_err.c_str(); }
 int32_t oracle_num_params(int32_t model) { return num_params(model); }
+int32_t oracle_market_num_params(const oracle_market *m) { return m ? market_params(m) : -1; }
 
 void oracle_set_threads(int32_t n) {
   if (n > 0) omp_set_num_threads(n);
@@ -776,7 +804,8 @@ int32_t oracle_cost_batch(const oracle_market *m, int32_t n_pts, const int32_t *
   std::vector<Inst> insts(m->n_inst);
   for (int i = 0; i < m->n_inst; ++i)
     if (build_inst(m, i, insts[i])) return -1;
-  const int P = num_params(m->model);
+  const int P = market_params(m);
+  if (P < 0) return fail("unknown model or PERFWD instances of unequal size");
   for (int i = 0; i < n_pts; ++i)
     if (pt_inst[i] < 0 || pt_inst[i] >= m->n_inst) return fail("point instance out of range");
 #pragma omp parallel for schedule(dynamic)
@@ -795,7 +824,8 @@ int32_t oracle_cost_grad(const oracle_market *m, int32_t n_pts, const int32_t *p
   std::vector<Inst> insts(m->n_inst);
   for (int i = 0; i < m->n_inst; ++i)
     if (build_inst(m, i, insts[i])) return -1;
-  const int P = num_params(m->model);
+  const int P = market_params(m);
+  if (m->model == 2 || P < 0) return fail("gradients and LM need GLOBAL4 or LMM12");
   for (int i = 0; i < n_pts; ++i)
     if (pt_inst[i] < 0 || pt_inst[i] >= m->n_inst) return fail("point instance out of range");
 #pragma omp parallel for schedule(dynamic)
@@ -886,8 +916,8 @@ int32_t oracle_sa_calibrate(const oracle_market *m, const oracle_sa_config *cfg,
                             double *chain_best_x, double *chain_best_f, uint8_t *accept,
                             double *level_trace, int32_t *level_best, int64_t *n_evals) {
   if (!m || !cfg) return fail("null argument");
-  const int P = num_params(m->model);
-  if (P < 0) return fail("unknown model");
+  const int P = market_params(m);
+  if (P < 0) return fail("unknown model or PERFWD instances of unequal size");
   if (cfg->n_levels < 0 || cfg->n_steps < 0) return fail("negative level or step count");
   if (!(cfg->cool > 0.0 && cfg->cool <= 1.0) || !(cfg->T0 > 0.0)) return fail("bad schedule");
   const int L = cfg->n_levels, N = cfg->n_steps;
@@ -973,8 +1003,8 @@ int32_t oracle_sa_level0_sample(const oracle_market *m, const oracle_sa_config *
                                 const int32_t *sample_chain, uint8_t *accept, double *F_out,
                                 double *BF_out, double *BX_out) {
   if (!m || !cfg) return fail("null argument");
-  const int P = num_params(m->model);
-  if (P < 0) return fail("unknown model");
+  const int P = market_params(m);
+  if (P < 0) return fail("unknown model or PERFWD instances of unequal size");
   if (cfg->n_steps < 0) return fail("negative step count");
   if (!(cfg->T0 > 0.0)) return fail("bad schedule");
   const int N = cfg->n_steps;
@@ -1015,7 +1045,8 @@ int32_t oracle_lm_polish(const oracle_market *m, int32_t n_pts, const int32_t *p
   std::vector<Inst> insts(m->n_inst);
   for (int i = 0; i < m->n_inst; ++i)
     if (build_inst(m, i, insts[i])) return -1;
-  const int P = num_params(m->model);
+  const int P = market_params(m);
+  if (m->model == 2 || P < 0) return fail("gradients and LM need GLOBAL4 or LMM12");
   for (int i = 0; i < n_pts; ++i)
     if (pt_inst[i] < 0 || pt_inst[i] >= m->n_inst) return fail("point instance out of range");
 #pragma omp parallel for schedule(dynamic)

@@ -601,7 +601,7 @@ __global__ __launch_bounds__(64) void lm_kernel(DevMarket m, int n_pts, const in
           if (y < lo[k]) y = lo[k];
           trial[k] = y;
         }
-        const double ft = point_cost<MODEL, FORMULA, RESID>(m, in, um, trial, w, nullptr, nullptr);
+        const double ft = point_cost<MODEL, FORMULA, RESID>(m, in, um, trial, 0.0, w, nullptr, nullptr);
         if (ft < f) {
           const double rel = (f - ft) / f;
 #pragma unroll
@@ -669,6 +669,7 @@ hipError_t launch_vjp(const DevMarket &m, int n_pts, const int *pt_inst, const d
                       const double *g_cost, double *cost, double *g_params, double *jtwj,
                       double *jtwr, double *scratch, hipStream_t s) {
   if (n_pts == 0) return hipSuccess;
+  if (m.model != 0 && m.model != 1) return hipErrorInvalidValue;   // GLOBAL4 and LMM12 only
   const size_t lds = adjoint_lds_bytes(m);
   const int waves = adjoint_waves(n_pts);
 #define CALL(A, B, C)                                                                        \
@@ -689,6 +690,7 @@ hipError_t launch_lm(const DevMarket &m, int n_pts, const int *pt_inst, double *
                      const double *lb, const double *ub, int max_iter, double mu0, double tol,
                      double *cost_out, int *iters_out, double *scratch, hipStream_t s) {
   if (n_pts == 0) return hipSuccess;
+  if (m.model != 0 && m.model != 1) return hipErrorInvalidValue;   // GLOBAL4 and LMM12 only
   const size_t lds = adjoint_lds_bytes(m);
   const int waves = adjoint_waves(n_pts);
 #define CALL(A, B, C)                                                                       \

@@ -50,6 +50,7 @@ struct Layout {
 
 struct sabr_plan {
   int n_inst = 0, model = 0, formula = 0, residual = 0;
+  int np = 0;  // parameters per point
   double beta = 0.5;
   int nF = 0, nU = 0, nQ = 0;
   int max_nq = 0, max_nu = 0, max_nf = 0, max_len = 0;
@@ -91,7 +92,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   if (!pr || !out) return fail(SABR_EINVAL, "null argument");
   *out = nullptr;
   if (pr->n_inst < 1) return fail(SABR_EINVAL, "n_inst must be >= 1");
-  if (pr->model < 0 || pr->model > 1) return fail(SABR_EINVAL, "unknown model");
+  if (pr->model < 0 || pr->model > 2) return fail(SABR_EINVAL, "unknown model");
   if (pr->vol_formula < 0 || pr->vol_formula > 1) return fail(SABR_EINVAL, "unknown formula");
   if (pr->residual < 0 || pr->residual > 1) return fail(SABR_EINVAL, "unknown residual mode");
   if (!(pr->beta >= 0.0 && pr->beta <= 1.0)) return fail(SABR_EINVAL, "beta outside [0, 1]");
@@ -112,6 +113,22 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   P->formula = pr->vol_formula;
   P->residual = pr->residual;
   P->beta = pr->beta;
+  P->np = sabr_num_params(pr->model);
+  if (pr->model == 2) {
+    // PERFWD: one (alpha, rho, nu) per forward, lanes k < 3 nf of a wave
+    // hold the point, so every instance has the same nf <= 21
+    const int nf = pr->fwd_off[1] - pr->fwd_off[0];
+    for (int i = 1; i < n; ++i)
+      if (pr->fwd_off[i + 1] - pr->fwd_off[i] != nf) {
+        delete P;
+        return fail(SABR_EINVAL, "PERFWD instances must hold equally many forwards");
+      }
+    if (nf < 1 || 3 * nf > sabr::kWave - 1) {
+      delete P;
+      return fail(SABR_EINVAL, "PERFWD needs 1..21 forwards per instance");
+    }
+    P->np = 3 * nf;
+  }
   P->nF = pr->fwd_off[n];
   P->nU = pr->und_off[n];
   P->nQ = pr->q_off[n];
@@ -141,7 +158,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
       const int first = pr->und_first[u], len = pr->und_len[u];
       if (len < 1 || first < 0 || first + len > d.nf)
         return bad("underlying " + std::to_string(u) + ": forward range out of bounds");
-      if (pr->model == 0 && len != 1) return bad("GLOBAL4 markets hold caplets only");
+      if (pr->model != 1 && len != 1) return bad("GLOBAL4 and PERFWD markets hold caplets only");
       if (len > d.maxlen) d.maxlen = len;
       // annuity, weights and swap rate, summed in forward order
       double A = 0.0;
@@ -245,9 +262,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
 void sabr_plan_destroy(sabr_plan *plan) { delete plan; }
 
 size_t sabr_plan_device_bytes(const sabr_plan *plan) { return plan ? plan->total_bytes : 0; }
-int32_t sabr_plan_num_params(const sabr_plan *plan) {
-  return plan ? sabr_num_params(plan->model) : -1;
-}
+int32_t sabr_plan_num_params(const sabr_plan *plan) { return plan ? plan->np : -1; }
 int32_t sabr_plan_num_inst(const sabr_plan *plan) { return plan ? plan->n_inst : -1; }
 int32_t sabr_plan_max_quotes(const sabr_plan *plan) { return plan ? plan->max_nq : -1; }
 
@@ -272,6 +287,7 @@ sabr_status sabr_plan_upload(sabr_plan *P, void *dev_buf, size_t bytes, void *st
   DevMarket m{};
   m.n_inst = P->n_inst;
   m.model = P->model;
+  m.np = P->np;
   m.formula = P->formula;
   m.residual = P->residual;
   m.beta = P->beta;
@@ -344,11 +360,12 @@ struct SALayout {
 SALayout sa_layout(const sabr_plan *P, const sa_config *cfg, const int32_t *chains) {
   SALayout S{};
   const int n = P->n_inst;
-  const int Pn = sabr_num_params(P->model);
+  const int Pn = P->np;
   int want = cfg && cfg->waves_per_group > 0 ? cfg->waves_per_group : 4;
   if (want > 4) want = 4;
   DevMarket shape{};  // LDS budget depends on the market's shape only
   shape.model = P->model;
+  shape.np = P->np;
   shape.max_nf = P->max_nf;
   shape.max_nu = P->max_nu;
   shape.max_len = P->max_len;
@@ -422,7 +439,7 @@ sabr_status sa_calibrate(const sabr_plan *Pc, const sa_config *cfg, const int32_
   if (!workspace) return fail(SABR_EINVAL, "null workspace");
   if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(SABR_EINVAL, "workspace not 256-byte aligned");
   const int n = P->n_inst;
-  const int Pn = sabr_num_params(P->model);
+  const int Pn = P->np;
   for (int i = 0; i < n * Pn; ++i) {
     if (!std::isfinite(lb[i]) || !std::isfinite(ub[i]) || !(lb[i] <= ub[i]))
       return fail(SABR_EINVAL, "box bound " + std::to_string(i) + ": need finite lb <= ub");
@@ -592,11 +609,12 @@ struct AdjLayout {
 AdjLayout adj_layout(const sabr_plan *P, int n_pts) {
   AdjLayout A{};
   Layout L;
-  const int Pn = sabr_num_params(P->model);
+  const int Pn = P->np;
   A.o_lb = L.take<double>((size_t)P->n_inst * Pn);
   A.o_ub = L.take<double>((size_t)P->n_inst * Pn);
   DevMarket shape{};
   shape.model = P->model;
+  shape.np = P->np;
   shape.max_nu = P->max_nu;
   A.o_scratch = L.take<unsigned char>(sabr::adjoint_scratch_bytes(shape, sabr::adjoint_waves(n_pts)));
   A.total = L.off;
@@ -627,6 +645,7 @@ sabr_status sabr_cost_vjp(const sabr_plan *P, int32_t n_pts, const int32_t *pt_i
   if (st != SABR_OK) return st;
   if (n_pts == 0) return SABR_OK;
   if (!pt_inst || !params || !g_params) return fail(SABR_EINVAL, "null pt_inst, params or g_params");
+  if (P->model == 2) return fail(SABR_EUNSUPPORTED, "the adjoint takes GLOBAL4 and LMM12 plans");
   const AdjLayout A = adj_layout(P, n_pts);
   if (A.total > 0 && (!workspace || ws_bytes < A.total))
     return fail(SABR_EWORKSPACE, "workspace too small");
@@ -647,8 +666,9 @@ sabr_status sabr_lm_polish(const sabr_plan *Pc, int32_t n_pts, const int32_t *pt
   if (n_pts == 0) return SABR_OK;
   if (!pt_inst || !params || !lb || !ub) return fail(SABR_EINVAL, "null argument");
   if (max_iter < 0 || !(mu0 > 0.0) || !(tol >= 0.0)) return fail(SABR_EINVAL, "bad LM settings");
+  if (Pc->model == 2) return fail(SABR_EUNSUPPORTED, "LM takes GLOBAL4 and LMM12 plans");
   sabr_plan *P = const_cast<sabr_plan *>(Pc);
-  const int Pn = sabr_num_params(P->model);
+  const int Pn = P->np;
   for (int i = 0; i < P->n_inst * Pn; ++i)
     if (!std::isfinite(lb[i]) || !std::isfinite(ub[i]) || !(lb[i] <= ub[i]))
       return fail(SABR_EINVAL, "box bound " + std::to_string(i) + ": need finite lb <= ub");

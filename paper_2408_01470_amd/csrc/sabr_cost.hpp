@@ -16,6 +16,11 @@ template <>
 struct NP<1> {
   static constexpr int P = 12;
 };
+// PERFWD: three parameters per forward, known at run time (DevMarket::np).
+template <>
+struct NP<2> {
+  static constexpr int P = 0;
+};
 
 // Per-wave LDS scratch of the LMM12 map: per forward {alpha, nu, g1, g2, a}
 // (g1, g2: correlation factors of the gap to the next forward; a = v alpha,
@@ -210,12 +215,51 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const do
   return __any(bad);
 }
 
+// PERFWD map (the Hagan model of Sec. 3 with per-forward parameters, as
+// calibrated to caplets in Sec. 4.1.1): lane k < np holds coordinate k of
+// (alpha_1, rho_1, nu_1, alpha_2, ...), beta is fixed.  Each caplet's SABR
+// constants come from its forward's triple, fetched across lanes.  Every
+// triple must lie in the domain (alpha > 0, |rho| < 1, nu >= 0).  Returns
+// true (wave-uniform) on a domain failure.
+__device__ bool perfwd_map(const DevMarket &m, const DevInst &in, double xl, WaveLds w) {
+  const int lane = lane_id();
+  const double beta = m.beta, omb = 1.0 - beta;
+  const int role = lane % 3;
+  bool bad = false;
+  if (lane < m.np)
+    bad = (role == 0) ? !(xl > 0.0) : (role == 1) ? !(fabs(xl) < 1.0) : !(xl >= 0.0);
+  const UndMap *umap = m.u_map + in.u0;
+  for (int i0 = 0; i0 < in.nu; i0 += kWave) {   // wave-uniform trip count: every lane shuffles
+    const int i = i0 + lane;
+    UndMap un{0, 0, 1, 0};
+    if (i < in.nu) un = umap[i];
+    const int src = 3 * un.e;
+    const double ta = __shfl(xl, src, kWave);
+    const double tr = __shfl(xl, src + 1, kWave);
+    const double tn = __shfl(xl, src + 2, kWave);
+    if (i < in.nu) {
+      SabrConst K;
+      K.alpha = ta;
+      K.rho = tr;
+      K.nua = tn * rcp_nr(ta);
+      K.ca = omb * omb * ta * ta * (1.0 / 24.0);
+      K.cb = tr * beta * tn * ta * 0.25;
+      K.cc = (2.0 - 3.0 * (tr * tr)) * tn * tn * (1.0 / 24.0);
+      w.th[un.u] = K;
+    }
+  }
+  wave_lds_sync();
+  return __any(bad);
+}
+
 // Cost of one point for the wave: f = sum_q w_q r_q^2, +inf on a domain
-// failure.  p[] is wave-uniform.  Optional per-quote residual and model
-// outputs (the quoted side in price mode).
+// failure.  p[] is wave-uniform (GLOBAL4, LMM12); PERFWD reads the point
+// from the lanes instead (xl: lane k holds coordinate k).  Optional
+// per-quote residual and model outputs (the quoted side in price mode).
 template <int MODEL, int FORMULA, int RESID>
 __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt *um,
-                             const double *p, WaveLds w, double *resid, double *model) {
+                             const double *p, double xl, WaveLds w, double *resid,
+                             double *model) {
   const int lane = lane_id();
   bool bad = false;
   SabrConst g{};
@@ -226,8 +270,11 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
     g = sabr_const(p[0], p[1], p[2], p[3]);
     omb = 1.0 - p[1];
     omb2 = omb * omb;
-  } else {
+  } else if (MODEL == 1) {
     bad = lmm12_map(m, in, p, w);
+    omb = 1.0 - m.beta;
+  } else {
+    bad = perfwd_map(m, in, xl, w);
     omb = 1.0 - m.beta;
   }
   double acc = 0.0;

@@ -57,7 +57,8 @@ struct alignas(16) UndMap {
 
 struct DevMarket {
   int n_inst, model, formula, residual;
-  double beta;           // fixed beta (LMM12)
+  int np;                // parameters per point (3 per forward for PERFWD)
+  double beta;           // fixed beta (LMM12, PERFWD)
   int max_nq, max_nu, max_nf, max_len;
   const DevInst *inst;
   // forwards

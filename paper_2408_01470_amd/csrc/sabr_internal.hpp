@@ -12,10 +12,11 @@ namespace sabr {
 // in registers; longer ones in LDS.
 constexpr int kMapRegLen = 16;
 
-// Doubles of LDS one wavefront needs for the LMM12 maps: a 48-byte record per
-// forward (alpha, nu, the two correlation gap factors, v alpha), a 48-byte
-// record of SABR constants per underlying, and (for swaps longer than
-// kMapRegLen) a per-lane column of max_len doubles for the swap recursion.
+// Doubles of LDS one wavefront needs for the LMM12 and PERFWD maps: a 48-byte
+// record per forward (alpha, nu, the two correlation gap factors, v alpha;
+// unused by PERFWD), a 48-byte record of SABR constants per underlying, and
+// (for swaps longer than kMapRegLen) a per-lane column of max_len doubles for
+// the swap recursion.
 // Each workgroup adds 6 doubles per underlying of market values.
 __host__ __device__ inline int wave_lds_doubles(const DevMarket &m) {
   if (m.model == 0) return 0;
@@ -23,14 +24,20 @@ __host__ __device__ inline int wave_lds_doubles(const DevMarket &m) {
          (m.max_len > kMapRegLen ? kWave * m.max_len : 0);
 }
 
-// Steps whose uniforms one Philox pass of the annealing kernel produces: lane
-// l computes block (l & 3) of step (l >> 2), and the uniforms wait in LDS.
+// Steps whose uniforms one Philox pass of the annealing kernel produces: a
+// step takes P + 1 uniforms, the words of (P + 4) / 4 Philox blocks; lane l
+// computes block l mod nb of step l / nb, at most kUniSteps steps a pass, and
+// the uniforms wait in LDS.
 constexpr int kUniSteps = 16;
+__host__ __device__ constexpr int uni_blocks(int P) { return (P + 4) / 4; }
+__host__ __device__ constexpr int uni_steps(int P) {
+  return kWave / uni_blocks(P) < kUniSteps ? kWave / uni_blocks(P) : kUniSteps;
+}
 
 // Doubles of LDS per wave of the annealing kernels: the map's scratch and
-// kUniSteps x (P + 1) uniforms.
+// uni_steps(P) x (P + 1) uniforms.
 __host__ __device__ inline int sa_wave_doubles(const DevMarket &m) {
-  return wave_lds_doubles(m) + kUniSteps * ((m.model == 0 ? 4 : 12) + 1);
+  return wave_lds_doubles(m) + uni_steps(m.np) * (m.np + 1);
 }
 
 struct SAArgs {

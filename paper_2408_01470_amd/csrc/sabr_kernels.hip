@@ -68,7 +68,8 @@ __global__ __launch_bounds__(256) void cost_kernel(DevMarket m, int n_pts, const
                                                    double *resid, double *model, int stride,
                                                    int lds_per_wave) {
   extern __shared__ double smem[];
-  constexpr int P = NP<MODEL>::P;
+  constexpr int PC = NP<MODEL>::P;       // 0: known at run time (PERFWD)
+  const int P = PC > 0 ? PC : m.np;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int pt = blockIdx.x * (blockDim.x / kWave) + wid;
   if (pt >= n_pts) return;
@@ -84,12 +85,13 @@ __global__ __launch_bounds__(256) void cost_kernel(DevMarket m, int n_pts, const
   UndMkt *um = reinterpret_cast<UndMkt *>(base);
   for (int u = lane_id(); u < in.nu; u += kWave) um[u] = und_mkt(m, in.u0 + u);
   wave_lds_sync();
-  double p[P];
+  double p[PC > 0 ? PC : 1];
 #pragma unroll
-  for (int k = 0; k < P; ++k) p[k] = params[(size_t)pt * P + k];
+  for (int k = 0; k < PC; ++k) p[k] = params[(size_t)pt * PC + k];
+  const double xl = (PC == 0 && lane_id() < P) ? params[(size_t)pt * P + lane_id()] : 0.0;
   WaveLds w = wave_lds(m, base + 6 * m.max_nu);
   const double c = point_cost<MODEL, FORMULA, RESID>(
-      m, in, um, p, w, resid ? resid + (size_t)pt * stride : nullptr,
+      m, in, um, p, xl, w, resid ? resid + (size_t)pt * stride : nullptr,
       model ? model + (size_t)pt * stride : nullptr);
   if (lane_id() == 0) cost[pt] = c;
 }
@@ -224,7 +226,8 @@ __device__ void level_end_block(const SAArgs &a, int inst, int level, double *sc
 template <int MODEL, int FORMULA, int RESID>
 __global__ __launch_bounds__(256) void sa_init_kernel(DevMarket m, SAArgs a, int lds_per_wave) {
   extern __shared__ double smem[];
-  constexpr int P = NP<MODEL>::P;
+  constexpr int PC = NP<MODEL>::P;       // 0: known at run time (PERFWD)
+  const int P = PC > 0 ? PC : a.P;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = lane_id();
   const int inst = a.tile_inst[blockIdx.x];
@@ -233,10 +236,10 @@ __global__ __launch_bounds__(256) void sa_init_kernel(DevMarket m, SAArgs a, int
   const int c = a.tile_chain[blockIdx.x] + wid;
   if (c >= a.chains[inst]) return;
   const double xl = (lane < P) ? a.x0[(size_t)inst * P + lane] : 0.0;
-  double x[P];
-  broadcast_params<P>(xl, x);
+  double x[PC > 0 ? PC : 1];
+  broadcast_params<PC>(xl, x);
   WaveLds w = wave_lds(m, smem + 6 * m.max_nu + (size_t)wid * lds_per_wave);
-  const double f = point_cost<MODEL, FORMULA, RESID>(m, in, um, x, w, nullptr, nullptr);
+  const double f = point_cost<MODEL, FORMULA, RESID>(m, in, um, x, xl, w, nullptr, nullptr);
   const int64_t gc = a.chain_base[inst] + c;
   if (lane < P) {
     a.X[gc * P + lane] = xl;
@@ -260,7 +263,9 @@ template <int MODEL, int FORMULA, int RESID, int OCC>
 __global__ __launch_bounds__(256, OCC) void sa_level_kernel(DevMarket m, SAArgs a, int level,
                                                             int lds_per_wave) {
   extern __shared__ double smem[];
-  constexpr int P = NP<MODEL>::P;
+  constexpr int PC = NP<MODEL>::P;       // 0: known at run time (PERFWD)
+  const int P = PC > 0 ? PC : a.P;
+  const int nb = uni_blocks(P), spp = uni_steps(P);
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = lane_id();
   const int inst = a.tile_inst[blockIdx.x];
@@ -282,15 +287,15 @@ __global__ __launch_bounds__(256, OCC) void sa_level_kernel(DevMarket m, SAArgs 
     const double iT = 1.0 / T;
     double *wbase = smem + 6 * m.max_nu + (size_t)wid * lds_per_wave;
     WaveLds w = wave_lds(m, wbase);
-    double *uw = wbase + wave_lds_doubles(m);   // [kUniSteps][P + 1] uniforms
+    double *uw = wbase + wave_lds_doubles(m);   // [spp][P + 1] uniforms
     int nacc = 0;
-    for (int s0 = 0; s0 < a.N; s0 += kUniSteps) {
+    for (int s0 = 0; s0 < a.N; s0 += spp) {
       // Uniforms u_0..u_P of step s are the words of Philox blocks 0..P/4 of
       // counter (level N + s, chain, block, 0): word k mod 4 of block k/4.  One
-      // pass over the lanes makes those of kUniSteps steps.
+      // pass over the lanes makes those of spp steps.
       {
-        const int sl = lane >> 2, blk = lane & 3;
-        if (s0 + sl < a.N && 4 * blk <= P) {
+        const int sl = lane / nb, blk = lane - sl * nb;
+        if (sl < spp && s0 + sl < a.N) {
           uint64_t wds[4];
           philox4x64_10((uint64_t)level * (uint64_t)a.N + (uint64_t)(s0 + sl), (uint64_t)c,
                         (uint64_t)blk, 0, a.seed, (uint64_t)inst, wds);
@@ -300,14 +305,14 @@ __global__ __launch_bounds__(256, OCC) void sa_level_kernel(DevMarket m, SAArgs 
         }
       }
       wave_lds_sync();
-      const int s1 = min(a.N, s0 + kUniSteps);
+      const int s1 = min(a.N, s0 + spp);
       for (int s = s0; s < s1; ++s) {
         const double *us = uw + (s - s0) * (P + 1);
         const double u = lane <= P ? us[lane] : 0.0;
         const double xp = own ? propose1(x, u, lo, hi, a.step_frac) : 0.0;
-        double p[P];
-        broadcast_params<P>(xp, p);
-        double fp = point_cost<MODEL, FORMULA, RESID>(m, in, um, p, w, nullptr, nullptr);
+        double p[PC > 0 ? PC : 1];
+        broadcast_params<PC>(xp, p);
+        double fp = point_cost<MODEL, FORMULA, RESID>(m, in, um, p, xp, w, nullptr, nullptr);
         if (fp != fp) fp = kInf;
         const double uP = us[P];
         const double dE = fp - f;
@@ -412,11 +417,17 @@ hipError_t launch_prep(const DevMarket &m, QuoteRec *q, double *f_v, double *u_S
       } else {                                                       \
         if ((RESID_) == 0) { CALL(0, 1, 0); } else { CALL(0, 1, 1); } \
       }                                                              \
-    } else {                                                         \
+    } else if ((MODEL_) == 1) {                                      \
       if ((FORMULA_) == 0) {                                         \
         if ((RESID_) == 0) { CALL(1, 0, 0); } else { CALL(1, 0, 1); } \
       } else {                                                       \
         if ((RESID_) == 0) { CALL(1, 1, 0); } else { CALL(1, 1, 1); } \
+      }                                                              \
+    } else {                                                         \
+      if ((FORMULA_) == 0) {                                         \
+        if ((RESID_) == 0) { CALL(2, 0, 0); } else { CALL(2, 0, 1); } \
+      } else {                                                       \
+        if ((RESID_) == 0) { CALL(2, 1, 0); } else { CALL(2, 1, 1); } \
       }                                                              \
     }                                                                \
   } while (0)

@@ -81,7 +81,7 @@ RESIDUAL = 4.0   # r = m - target, acc += (w r) r
 
 
 def quote_flops(model: int, formula: int, residual: int) -> float:
-    fixed = model == 1
+    fixed = model != 0          # LMM12 and PERFWD fix beta
     f = hagan_quote(fixed) if formula == 0 else eq3_quote(fixed)
     f += black_quote() if residual == 1 else 1 + _e("rcp")
     return f + RESIDUAL
@@ -94,11 +94,14 @@ def map_flops_inst(market: dict, inst: int) -> float:
     underlying its SABR constants; for a swap over n forwards the O(n)
     frozen-weight recursion (4 per forward forward, 14 per forward
     backward) and its closing Nb, alpha_S, nu_S, rho_S (12, 2 sqrt,
-    3 reciprocals)."""
+    3 reciprocals).  PERFWD: per underlying the SABR constants of its
+    forward's triple (fixed beta)."""
     if int(market["model"]) == 0:
         return sabr_const(0) + 2
     f0, f1 = market["fwd_off"][inst], market["fwd_off"][inst + 1]
     u0, u1 = market["und_off"][inst], market["und_off"][inst + 1]
+    if int(market["model"]) == 2:
+        return (u1 - u0) * sabr_const(1)
     nf = f1 - f0
     lens = np.asarray(market["und_len"][u0:u1])
     fwd = nf * (10 + _e("exp", 2)) + max(nf - 1, 0) * (3 + _e("exp", 2))
@@ -108,10 +111,16 @@ def map_flops_inst(market: dict, inst: int) -> float:
     return fwd + und
 
 
-def step_overhead(model: int) -> float:
+def num_params(market: dict) -> int:
+    model = int(market["model"])
+    if model == 2:
+        return 3 * int(market["fwd_off"][1] - market["fwd_off"][0])
+    return 4 if model == 0 else 12
+
+
+def step_overhead(P: int) -> float:
     """Proposal (6 per coordinate), uniform conversion (1 per uniform, P+1),
     Metropolis (dE, a library division and exponential)."""
-    P = 4 if model == 0 else 12
     return 6 * P + (P + 1) + 1 + _e("div") + _e("exp")
 
 
@@ -126,7 +135,7 @@ def level_launch_flops(market: dict, chains, n_steps: int) -> float:
     qf = quote_flops(model, formula, residual)
     tot = 0.0
     for i in range(n):
-        per_step = nq[i] * qf + map_flops_inst(market, i) + step_overhead(model)
+        per_step = nq[i] * qf + map_flops_inst(market, i) + step_overhead(num_params(market))
         tot += float(ch[i]) * n_steps * per_step
     return tot
 

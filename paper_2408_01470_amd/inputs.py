@@ -20,15 +20,25 @@ configurations:
   LMM12 parameters, price residuals (optionally both option sides).
 * ``batch_markets``      -- many caplet markets of uneven size
   (10..40 forwards x 5..15 strikes).
+* ``perfwd_markets``     -- equal-size caplet markets with per-forward
+  (alpha, rho, nu) truths, for the PERFWD model.
+* ``paper_caplet_market`` -- not synthetic: the paper's own 6M EURIBOR
+  caplet data of 21/11/2011 (13 forwards x 9 moneyness values, Sec. 4,
+  Tables "Discount factor curve" and "Smiles of forward rates"), for the
+  per-forward (PERFWD) Hagan model calibrated in Sec. 4.1.1.
 
 All randomness comes from ``numpy.random.Generator(Philox(key))``.
 """
 from __future__ import annotations
 
+import datetime
+import os
+
 import numpy as np
 
 MODEL_GLOBAL4 = 0
 MODEL_LMM12 = 1
+MODEL_PERFWD = 2
 FORMULA_HAGAN2002 = 0
 FORMULA_PAPER_EQ3 = 1
 RESID_VOL = 0
@@ -47,15 +57,24 @@ def rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.Philox(key=int(seed)))
 
 
-def num_params(model: int) -> int:
+def num_params(model: int, n_fwd: int | None = None) -> int:
+    if model == MODEL_PERFWD:
+        return 3 * int(n_fwd)
     return 4 if model == MODEL_GLOBAL4 else 12
 
 
-def box(model: int):
+def box(model: int, n_fwd: int | None = None):
     """Search box (lb, ub).  The paper prints no box; values sitting on round
     bounds in its calibrated tables (sigma_1 = 1, phi = -1, kappa = 0.001)
     suggest plain interval bounds, chosen here wide enough to hold the
-    synthetic true parameters."""
+    synthetic true parameters.  PERFWD (n_fwd triples (alpha, rho, nu)):
+    alpha in [0.001, 0.2] as for GLOBAL4, rho in [-0.99, 0.99], nu in
+    [0.001, 1] (the printed sigma_1 = 1.0000 of Sec. 4.1.1 sits on that
+    bound)."""
+    if model == MODEL_PERFWD:
+        lb = np.tile([0.001, -0.99, 0.001], int(n_fwd))
+        ub = np.tile([0.2, 0.99, 1.0], int(n_fwd))
+        return lb, ub
     if model == MODEL_GLOBAL4:
         lb = np.array([0.001, 0.0, -0.99, 0.001])
         ub = np.array([0.2, 1.0, 0.99, 1.5])
@@ -234,6 +253,23 @@ def lmm_market(seed=SEED_BASE + 2000, n_markets=1, M=20, n_cap_K=15, n_exp=10, n
     return m, np.array(truths), np.concatenate(noises)
 
 
+def perfwd_markets(seed=SEED_BASE + 6000, n_markets=3, M=13, nK=9, formula=FORMULA_HAGAN2002,
+                   residual=RESID_VOL):
+    """PERFWD caplet markets (equal size: M forwards x nK strikes each, the
+    shape of the paper's 13 x 9 data), per-forward true triples
+    alpha ~ U[0.02, 0.05], rho ~ U[-0.5, 0], nu ~ U[0.2, 0.6]."""
+    parts = _empty()
+    truths, noises = [], []
+    for j in range(n_markets):
+        g = rng(seed + j)
+        _append(parts, *_caplet_instance(g, M, nK))
+        truths.append(np.column_stack([g.uniform(0.02, 0.05, M), g.uniform(-0.5, 0.0, M),
+                                       g.uniform(0.2, 0.6, M)]).ravel())
+        noises.append(g.normal(0.0, 0.002, M * nK))
+    m = _finish(parts, MODEL_PERFWD, formula, residual, 0.5)
+    return m, np.array(truths), np.concatenate(noises)
+
+
 def complete_market(market, model_vols, noise):
     """Market vols = model vols at the true parameters + noise."""
     m = dict(market)
@@ -263,3 +299,113 @@ def n_quotes(market):
 
 def n_inst(market):
     return len(market["q_off"]) - 1
+
+
+# ---------------------------------------------------------------------------
+# The paper's market data (Sec. 4): 6M EURIBOR, valuation date 21/11/2011.
+# ---------------------------------------------------------------------------
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests",
+                          "golden")
+PAPER_MONEYNESS = (-0.8, -0.6, -0.4, -0.2, 0.0, 0.2, 0.4, 0.6, 0.8)
+_VALUATION = datetime.date(2011, 11, 21)
+
+
+def _rows(name, golden_dir=None):
+    rows = []
+    with open(os.path.join(golden_dir or GOLDEN_DIR, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+def _date(text):
+    d, m, y = (int(v) for v in text.replace("-", "/").split("/"))
+    return datetime.date(y + 2000 if y < 100 else y, m, d)
+
+
+def paper_discount(dates, golden_dir=None):
+    """P(0, t) on the paper's discount factor curve at the given dates:
+    log-linear interpolation in calendar days between pillars (the paper
+    names no interpolation; this one reproduces the forward F_1 = 1.196%
+    implied by its calibrated Hagan parameters)."""
+    pts = [(_date(r[0]), float(r[1])) for r in _rows("paper_discount_curve.txt", golden_dir)]
+    days = np.array([(d - _VALUATION).days for d, _ in pts], float)
+    logp = np.log([p for _, p in pts])
+    x = np.array([(d - _VALUATION).days for d in dates], float)
+    return np.exp(np.interp(x, days, logp))
+
+
+def paper_caplet_market(golden_dir=None, model=MODEL_PERFWD, formula=FORMULA_PAPER_EQ3,
+                        residual=RESID_VOL, beta=0.5, fwd_F=None):
+    """The caplet market of the paper's Sec. 4.1.1 calibration, one instance.
+
+    Forward i (i = 1..13) fixes on the i-th date of the smiles table and pays
+    six months later on the next one (the 13th: 21/11/2018).  T_i = ACT/365
+    years from 21/11/2011; tau_i = ACT/360 accrual; F_i = (P(0, T_i) /
+    P(0, T_i + tau_i) - 1) / tau_i from the discount curve; P = P(0, pay).
+    Quotes: K = F_i exp(m), m = -80%..80% (the table's moneyness ln(K/F)),
+    market vols in % / 100, weight 1 (the paper's f_c: plain sum of squared
+    vol differences), out-of-the-money side (put below F, call above).
+    Quote order: forward-major, moneyness ascending.  ``fwd_F`` replaces
+    the curve's forwards (strikes follow them)."""
+    smiles = _rows("paper_forward_smiles.txt", golden_dir)
+    fix = [_date(r[0]) for r in smiles]
+    pay = fix[1:] + [datetime.date(fix[-1].year, fix[-1].month + 6, fix[-1].day)
+                     if fix[-1].month <= 6 else
+                     datetime.date(fix[-1].year + 1, fix[-1].month - 6, fix[-1].day)]
+    P0 = paper_discount(fix, golden_dir)
+    P1 = paper_discount(pay, golden_dir)
+    T = np.array([(d - _VALUATION).days / 365.0 for d in fix])
+    tau = np.array([(b - a).days / 360.0 for a, b in zip(fix, pay)])
+    F = (P0 / P1 - 1.0) / tau if fwd_F is None else np.asarray(fwd_F, float)
+    n = len(fix)
+    mny = np.array(PAPER_MONEYNESS)
+    q_und = np.repeat(np.arange(n), len(mny)).astype(np.int32)
+    q_K = (F[:, None] * np.exp(mny)[None, :]).ravel()
+    q_kind = np.where(np.tile(mny, n) < 0.0, KIND_PUT, KIND_CALL).astype(np.int32)
+    parts = _empty()
+    _append(parts, T, tau, F, P1, np.arange(n), np.ones(n, np.int32), q_und, q_kind, q_K)
+    m = _finish(parts, model, formula, residual, beta)
+    m["q_vol"] = np.array([[float(v) / 100.0 for v in r[1:]] for r in smiles]).ravel()
+    return m
+
+
+def perfwd_as_global4(market):
+    """A PERFWD market re-laid as a GLOBAL4 market with one instance per
+    forward (that forward and its caplets): the PERFWD cost is the sum of
+    these instances' costs at (alpha_i, beta, rho_i, nu_i).  Single-instance
+    PERFWD markets only."""
+    assert len(market["fwd_off"]) == 2, "one PERFWD instance"
+    nf = int(market["fwd_off"][1])
+    q_und = np.asarray(market["q_und"])
+    first = np.asarray(market["und_first"])
+    parts = _empty()
+    q_idx = []
+    for i in range(nf):
+        us = np.nonzero(first == i)[0]
+        qs = np.nonzero(np.isin(q_und, us))[0]
+        q_idx.append(qs)
+        local_u = np.searchsorted(us, q_und[qs])
+        _append(parts, [market["fwd_T"][i]], [market["fwd_tau"][i]], [market["fwd_F"][i]],
+                [market["fwd_P"][i]], np.zeros(len(us), np.int32), np.ones(len(us), np.int32),
+                local_u, np.asarray(market["q_kind"])[qs], np.asarray(market["q_K"])[qs])
+    m = _finish(parts, MODEL_GLOBAL4, market["formula"], market["residual"], market["beta"])
+    qi = np.concatenate(q_idx)
+    m["q_vol"] = np.asarray(market["q_vol"], float)[qi].copy()
+    m["q_w"] = np.asarray(market["q_w"], float)[qi].copy()
+    return m
+
+
+def perfwd_points_as_global4(x, beta):
+    """(n_fwd * 3,) PERFWD point -> (n_fwd, 4) GLOBAL4 points (alpha, beta,
+    rho, nu), one per forward instance of ``perfwd_as_global4``."""
+    t = np.asarray(x, float).reshape(-1, 3)
+    return np.column_stack([t[:, 0], np.full(len(t), beta), t[:, 1], t[:, 2]])
+
+
+def global4_points_as_perfwd(y):
+    """Inverse of ``perfwd_points_as_global4`` (drops beta)."""
+    y = np.asarray(y, float)
+    return y[:, [0, 2, 3]].ravel()
