@@ -266,7 +266,7 @@ def time_to_rmse(api, W, I, autotune):
     }
 
 
-def paper_e2(api, W, I, flops, autotune):
+def paper_e2(api, W, I, flops, autotune, shape=None):
     """The paper's own timed caplet calibration (Sec. 4.1.1) on its printed
     EURIBOR data: PERFWD (13 forwards, P = 39), eq. (sigmaHagan), SA with
     T0 = 10, Tmin = 0.01, rho = 0.99 (688 levels), N = 10, 16384 chains
@@ -279,15 +279,18 @@ def paper_e2(api, W, I, flops, autotune):
     w = W.paper_e2()
     mk = w.market
     plan = api.Plan(mk)
+    tuning = None
     n_fwd = int(mk["fwd_off"][1])
     lb, ub = I.box(I.MODEL_PERFWD, n_fwd)
     kw = dict(T0=w.extra["T0"], cool=w.extra["cool"], n_levels=w.n_levels, n_steps=w.n_steps,
               seed=w.seed, step_frac=w.step_frac)
-    shape = {}
-    if autotune:
-        from paper_2408_01470_amd import autotune as AT
-        t = AT.tune(plan, w.chains, lb, ub, w.n_steps)
-        shape = dict(waves=t["waves"], occupancy=t["occupancy"])
+    if shape is None:
+        shape = {}
+        if autotune:
+            from paper_2408_01470_amd import autotune as AT
+            t = AT.tune(plan, w.chains, lb, ub, w.n_steps)
+            shape = dict(waves=t["waves"], occupancy=t["occupancy"])
+            tuning = [[d["waves"], d["occupancy"], round(d["level_ms"], 4)] for d in t["all"]]
     g4 = I.perfwd_as_global4(mk)
     plan4 = api.Plan(g4)
     beta = float(mk["beta"])
@@ -351,6 +354,7 @@ def paper_e2(api, W, I, flops, autotune):
         "params_polished": {"alpha": t[:, 0].round(5).tolist(), "phi": t[:, 1].round(4).tolist(),
                             "sigma": t[:, 2].round(4).tolist()},
         "launch_shape": shape,
+        "tuning_level_ms": tuning,
         "paper": {"t_sa_s": w.extra["paper_sa_s"], "t_nelder_mead_s": w.extra["paper_nm_s"],
                   "cost_evaluations": w.extra["paper_evals"], "mre": w.extra["paper_mre"],
                   "hardware": "one GTX 470 (context, not a target)"},
@@ -373,8 +377,10 @@ def main():
     if args.adjoint_only:
         print(json.dumps(cost_and_adjoint(api, W, I, args.adjoint_config)))
         return
+    fixed_shape = (dict(waves=args.waves, occupancy=args.occupancy or 1)
+                   if args.waves is not None else None)
     if args.paper_e2_only:
-        print(json.dumps(paper_e2(api, W, I, flops, not args.no_autotune)))
+        print(json.dumps(paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape)))
         return
     w = W.CONFIGS[args.config]()
     if args.levels is not None:
@@ -490,7 +496,7 @@ def main():
     if not args.no_adjoint:
         out["cost_and_adjoint"] = cost_and_adjoint(api, W, I, args.adjoint_config)
     if not args.no_paper_e2:
-        out["paper_e2"] = paper_e2(api, W, I, flops, not args.no_autotune)
+        out["paper_e2"] = paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_levels, w.n_levels))
     print(json.dumps(out))

@@ -355,7 +355,7 @@ __device__ double point_normal(const DevMarket &m, const DevInst &in, const UndM
           !(p[3] >= 0.0);
     beta = p[1];
   } else {
-    bad = lmm12_map(m, in, p, w);
+    bad = lmm12_map<FORMULA>(m, in, um, p, w);
     beta = m.beta;
     for (int k = lane; k < in.nf; k += kWave) {
       const double T = m.f_T[in.f0 + k];

@@ -67,7 +67,7 @@ struct sabr_plan {
   size_t o_inst, o_fT, o_ftauP, o_fF, o_ufirst, o_ulen, o_uorder, o_uS0, o_uA, o_uinvA, o_uT,
       o_q, o_qundg, o_qvol, o_qwuser;  // uploaded (contiguous prefix)
   size_t upload_bytes = 0;
-  size_t o_fv, o_uS0b, o_uc0, o_umap;
+  size_t o_fv, o_uS0b, o_uc0, o_ufp, o_umap;
   size_t total_bytes = 0;
   std::vector<unsigned char> staging;
   char *dev = nullptr;
@@ -233,6 +233,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   P->upload_bytes = L.off;
   P->o_fv = L.take<double>(P->nF);
   P->o_uS0b = L.take<double>(P->nU);
+  P->o_ufp = L.take<double>(P->nU);
   P->o_uc0 = L.take<double>(P->nU);
   P->total_bytes = L.off;
   P->staging.assign(P->upload_bytes, 0);
@@ -307,12 +308,14 @@ sabr_status sabr_plan_upload(sabr_plan *P, void *dev_buf, size_t bytes, void *st
   m.u_A = D(P->o_uA);
   m.u_invA = D(P->o_uinvA);
   m.u_S0b = D(P->o_uS0b);
+  m.u_fp = D(P->o_ufp);
   m.u_T = D(P->o_uT);
   m.u_map = reinterpret_cast<const sabr::UndMap *>(d + P->o_umap);
   m.u_c0 = D(P->o_uc0);
   m.q = reinterpret_cast<const sabr::QuoteRec *>(d + P->o_q);
   e = sabr::launch_prep(m, reinterpret_cast<sabr::QuoteRec *>(d + P->o_q), D(P->o_fv),
-                        D(P->o_uS0b), D(P->o_uc0), D(P->o_qvol), D(P->o_qwuser), I(P->o_qundg),
+                        D(P->o_uS0b), D(P->o_uc0), D(P->o_ufp), D(P->o_qvol), D(P->o_qwuser),
+                        I(P->o_qundg),
                         D(P->o_ftauP), D(P->o_fF), P->nQ, P->nF, P->nU, s);
   if (e != hipSuccess) return hip_fail(e, "market precompute launch");
   P->dev = d;

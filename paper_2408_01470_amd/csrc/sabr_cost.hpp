@@ -49,7 +49,7 @@ __device__ __forceinline__ WaveLds wave_lds(const DevMarket &m, double *base) {
 __device__ __forceinline__ UndMkt und_mkt(const DevMarket &m, int g) {
   const double T = m.u_T[g];
   const double sT = sqrt(T);
-  return UndMkt{m.u_S0[g], m.u_A[g], T, sT, 1.0 / sT, 0.0};
+  return UndMkt{m.u_S0[g], m.u_A[g], T, sT, 1.0 / sT, m.model != 0 ? m.u_fp[g] : 0.0};
 }
 
 // Moments of the frozen-weight map of one swap over forwards [e, e+n),
@@ -135,6 +135,40 @@ __device__ __forceinline__ SwapMoments swap_moments_lds(const FwdMap *fw, int e,
   return SwapMoments{V, suma, Sb, Sbb, bad};
 }
 
+// SABR constants of one underlying with SABR parameters (alpha, rho, nu) and
+// beta fixed; fp = f^(1-beta).  Hagan 2002 (FORMULA 0): alpha, rho,
+// nu/alpha and the expiry-correction coefficients
+//   ca = (1-b)^2 alpha^2/24, cb = rho b nu alpha/4, cc = (2 - 3 rho^2) nu^2/24.
+// Paper eq. (sigmaHagan) (FORMULA 1): its vol is a quadratic in k = ln(K/f)
+// whose coefficients depend on the underlying only, so ca, cb, cc hold them:
+//   sigma = ca + cb k + cc k^2,  ca = alpha/fp,  cb = -ca (1-b - rho nu w)/2,
+//   cc = ca ((1-b)^2 + (2 - 3 rho^2) nu^2 w^2 + 3 (1-b - rho nu w))/12,
+//   w = fp/alpha.
+template <int FORMULA>
+__device__ __forceinline__ SabrConst und_const(double ta, double tr, double tn, double beta,
+                                               double fp) {
+  const double omb = 1.0 - beta;
+  const double ia = rcp_nr(ta);
+  SabrConst K;
+  K.alpha = ta;
+  K.rho = tr;
+  K.nua = tn * ia;
+  if (FORMULA == 0) {
+    K.ca = omb * omb * ta * ta * (1.0 / 24.0);
+    K.cb = tr * beta * tn * ta * 0.25;
+    K.cc = (2.0 - 3.0 * (tr * tr)) * tn * tn * (1.0 / 24.0);
+  } else {
+    const double wv = fp * ia;
+    const double e0 = ta * rcp_nr(fp);
+    const double d = omb - tr * tn * wv;
+    const double nw = tn * wv;
+    K.ca = e0;
+    K.cb = -0.5 * e0 * d;
+    K.cc = e0 * ((omb * omb + (2.0 - 3.0 * (tr * tr)) * nw * nw + 3.0 * d) * (1.0 / 12.0));
+  }
+  return K;
+}
+
 // LMM12 parameter map of one point into the wave's LDS.  Returns true when
 // the point lies outside the model's domain (wave-uniform).
 //   alpha_k = (a + b T_k) e^{-c T_k} + d, nu_k likewise (abcd forms);
@@ -149,12 +183,14 @@ __device__ __forceinline__ SwapMoments swap_moments_lds(const FwdMap *fw, int e,
 //   rho_S = rho (sum a)(sum b) / (sqrt(V) sqrt(Nb))   (0 if Nb = 0).
 // Underlyings are visited in decreasing length (the u_map table) so the lanes
 // of a pass run recursions of similar length.
-__device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const double *p, WaveLds w) {
+template <int FORMULA>
+__device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const UndMkt *um,
+                                 const double *p, WaveLds w) {
   const int lane = lane_id();
   const double a = p[0], b = p[1], c = p[2], d = p[3];
   const double an = p[4], bn = p[5], cn = p[6], dn = p[7];
   const double rho = p[8], lam1 = p[9], eta2 = p[10], lam2 = p[11];
-  const double beta = m.beta, omb = 1.0 - beta;
+  const double beta = m.beta;
   bool bad = !(fabs(rho) < 1.0) || !(lam1 >= 0.0) || !(lam2 >= 0.0) ||
              !(eta2 >= 0.0 && eta2 <= 1.0);
   // the first underlying pass's entry is loaded before the forward pass
@@ -201,15 +237,7 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const do
       tr = (sN > 0.0) ? rho * suma * Sb * rcp_nr(sV * sN) : 0.0;
       bad |= !(V > 0.0) || !(fabs(tr) < 1.0);
     }
-    const double r2 = tr * tr;
-    SabrConst K;
-    K.alpha = ta;
-    K.rho = tr;
-    K.nua = tn * rcp_nr(ta);
-    K.ca = omb * omb * ta * ta * (1.0 / 24.0);
-    K.cb = tr * beta * tn * ta * 0.25;
-    K.cc = (2.0 - 3.0 * r2) * tn * tn * (1.0 / 24.0);
-    w.th[u] = K;
+    w.th[u] = und_const<FORMULA>(ta, tr, tn, beta, um[u].fp);
   }
   wave_lds_sync();
   return __any(bad);
@@ -221,9 +249,11 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const do
 // constants come from its forward's triple, fetched across lanes.  Every
 // triple must lie in the domain (alpha > 0, |rho| < 1, nu >= 0).  Returns
 // true (wave-uniform) on a domain failure.
-__device__ bool perfwd_map(const DevMarket &m, const DevInst &in, double xl, WaveLds w) {
+template <int FORMULA>
+__device__ bool perfwd_map(const DevMarket &m, const DevInst &in, const UndMkt *um, double xl,
+                           WaveLds w) {
   const int lane = lane_id();
-  const double beta = m.beta, omb = 1.0 - beta;
+  const double beta = m.beta;
   const int role = lane % 3;
   bool bad = false;
   if (lane < m.np)
@@ -237,16 +267,7 @@ __device__ bool perfwd_map(const DevMarket &m, const DevInst &in, double xl, Wav
     const double ta = __shfl(xl, src, kWave);
     const double tr = __shfl(xl, src + 1, kWave);
     const double tn = __shfl(xl, src + 2, kWave);
-    if (i < in.nu) {
-      SabrConst K;
-      K.alpha = ta;
-      K.rho = tr;
-      K.nua = tn * rcp_nr(ta);
-      K.ca = omb * omb * ta * ta * (1.0 / 24.0);
-      K.cb = tr * beta * tn * ta * 0.25;
-      K.cc = (2.0 - 3.0 * (tr * tr)) * tn * tn * (1.0 / 24.0);
-      w.th[un.u] = K;
-    }
+    if (i < in.nu) w.th[un.u] = und_const<FORMULA>(ta, tr, tn, beta, um[un.u].fp);
   }
   wave_lds_sync();
   return __any(bad);
@@ -271,10 +292,10 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
     omb = 1.0 - p[1];
     omb2 = omb * omb;
   } else if (MODEL == 1) {
-    bad = lmm12_map(m, in, p, w);
+    bad = lmm12_map<FORMULA>(m, in, um, p, w);
     omb = 1.0 - m.beta;
   } else {
-    bad = perfwd_map(m, in, xl, w);
+    bad = perfwd_map<FORMULA>(m, in, um, xl, w);
     omb = 1.0 - m.beta;
   }
   double acc = 0.0;
@@ -283,25 +304,30 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
     const int u = R.und;
     const UndMkt U = um[u];
     const SabrConst k = (MODEL == 0) ? g : w.th[u];
+    // eq. (sigmaHagan) with beta fixed: the vol itself, a quadratic in
+    // k = ln(K/f) = -L with the underlying's coefficients
+    constexpr bool direct = (FORMULA == 1 && MODEL != 0);
     VolFrac vf;
     if (FORMULA == 0) {
       const double qv = (MODEL == 0) ? exp_cw(0.5 * omb * R.qa) : R.qa;
       const double D1 = (MODEL == 0) ? d1_term(omb2, L) : R.qb;
       vf = hagan2002_frac(k, L, qv, D1, U.T);
+    } else if (direct) {
+      vf.numer = fma(-L, fma(-L, k.cc, k.cb), k.ca);
+      vf.denom = 1.0;
     } else {
-      const double fp = (MODEL == 0) ? exp_cw(omb * R.qc) : R.qc;
-      vf = paper_eq3_frac(k, omb, L, fp);
+      vf = paper_eq3_frac(k, omb, L, exp_cw(omb * R.qc));
     }
     double mv;
     if (RESID == 0) {
-      mv = vf.numer * rcp_nr(vf.denom);
+      mv = direct ? vf.numer : vf.numer * rcp_nr(vf.denom);
       bad |= !(mv > 0.0) || !(mv < kInf);
       if (model) model[q] = mv;
     } else {
       // one reciprocal gives sigma = numer/denom and 1/sigma = denom/numer
       const double rr = rcp_nr(vf.numer * vf.denom);
-      const double sig = vf.numer * (vf.numer * rr);
-      const double isig = vf.denom * (vf.denom * rr);
+      const double sig = direct ? vf.numer : vf.numer * (vf.numer * rr);
+      const double isig = direct ? rr : vf.denom * (vf.denom * rr);
       bad |= !(sig > 0.0) || !(sig < kInf);
       mv = black_otm(U.f, R.K, L, U.sqrtT, U.isqrtT, sig, isig, U.D);
       bad |= !(fabs(mv) < kInf);

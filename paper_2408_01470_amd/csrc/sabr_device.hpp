@@ -70,13 +70,15 @@ struct DevMarket {
   const double *u_S0, *u_A, *u_invA, *u_S0b, *u_T;  // swap rate, annuity, 1/A, S0^beta, expiry
   const UndMap *u_map;   // per instance: u_order[i] with its first forward and length
   const double *u_c0;    // 1/(A S0^beta) per underlying
+  const double *u_fp;    // S0^(1-beta) per underlying (fixed beta)
   // quotes
   const QuoteRec *q;
 };
 
 // Per-underlying market values staged in LDS by every workgroup.
 struct UndMkt {
-  double f, D, T, sqrtT, isqrtT, pad;
+  double f, D, T, sqrtT, isqrtT;
+  double fp;   // f^(1-beta) for a fixed beta (LMM12, PERFWD), else 0
 };
 static_assert(sizeof(UndMkt) == 48, "16-byte aligned LDS record");
 
@@ -108,16 +110,9 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t
 __device__ __forceinline__ double u53(uint64_t w) { return (double)(w >> 11) * 0x1.0p-53; }
 
 // ---------------------------------------------------------------------------
-// Wavefront helpers.  Butterfly sums give bitwise-identical totals in every
-// lane (each pairwise add is commutative).
+// Wavefront helpers.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
 
 // Value of lane l as a wave-uniform (scalar) register.
 __device__ __forceinline__ double readlane_d(double v, int l) {
@@ -125,6 +120,31 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// A double moved across lanes by a DPP pattern (both halves); lanes whose
+// row is not in ROW_MASK read 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROW_MASK, 0xf,
+                                             false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes (all active), returned wave-uniform.  Register-to-
+// register lane moves only: quad swaps (lane ^ 1, lane ^ 2), the half-row and
+// row mirrors (every lane of a 16-lane row then holds the row's sum), then
+// the row broadcasts of lanes 15 and 31 fold the four rows into lane 63.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0xB1>(v);        // quad_perm [1, 0, 3, 2]
+  v += dpp_d<0x4E>(v);        // quad_perm [2, 3, 0, 1]
+  v += dpp_d<0x141>(v);       // row_half_mirror
+  v += dpp_d<0x140>(v);       // row_mirror
+  v += dpp_d<0x142, 0xa>(v);  // row_bcast15 into rows 1 and 3
+  v += dpp_d<0x143, 0xc>(v);  // row_bcast31 into rows 2 and 3
+  return readlane_d(v, kWave - 1);
 }
 
 // Orders LDS traffic of one wavefront: a wave's LDS operations execute in

@@ -63,6 +63,7 @@ struct SAArgs {
 };
 
 hipError_t launch_prep(const DevMarket &m, QuoteRec *q, double *f_v, double *u_S0b, double *u_c0,
+                       double *u_fp,
                        const double *q_vol, const double *q_wuser, const int *q_und_g,
                        const double *f_tauP, const double *f_F, int n_q, int n_f, int n_u,
                        hipStream_t s);

@@ -21,6 +21,7 @@ namespace {
 // written und, kind and K of every quote record; this fills the rest.
 // ---------------------------------------------------------------------------
 __global__ void prep_kernel(DevMarket m, QuoteRec *q, double *f_v, double *u_S0b, double *u_c0,
+                            double *u_fp,
                             const double *q_vol, const double *q_wuser, const int *q_und_g,
                             const double *f_tauP, const double *f_F, int n_q, int n_f, int n_u) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -30,6 +31,7 @@ __global__ void prep_kernel(DevMarket m, QuoteRec *q, double *f_v, double *u_S0b
     const double S0b = pow(m.u_S0[i], beta);
     u_S0b[i] = S0b;
     u_c0[i] = m.u_invA[i] / S0b;
+    u_fp[i] = pow(m.u_S0[i], omb);
   }
   if (i >= n_q) return;
   const int gu = q_und_g[i];
@@ -397,6 +399,7 @@ __global__ __launch_bounds__(256) void sa_final_kernel(SAArgs a) {
 // Launch wrappers
 // ---------------------------------------------------------------------------
 hipError_t launch_prep(const DevMarket &m, QuoteRec *q, double *f_v, double *u_S0b, double *u_c0,
+                       double *u_fp,
                        const double *q_vol, const double *q_wuser, const int *q_und_g,
                        const double *f_tauP, const double *f_F, int n_q, int n_f, int n_u,
                        hipStream_t s) {
@@ -405,6 +408,7 @@ hipError_t launch_prep(const DevMarket &m, QuoteRec *q, double *f_v, double *u_S
   if (n_u > n) n = n_u;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(prep_kernel, dim3((n + 255) / 256), dim3(256), 0, s, m, q, f_v, u_S0b, u_c0,
+                     u_fp,
                      q_vol, q_wuser, q_und_g, f_tauP, f_F, n_q, n_f, n_u);
   return hipGetLastError();
 }

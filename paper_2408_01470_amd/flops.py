@@ -33,15 +33,20 @@ def _e(name, n=1):
     return n * ELEMENTARY[name]
 
 
-def sabr_const(model: int) -> float:
+def sabr_const(model: int, formula: int = 0) -> float:
     """Constants of one (alpha, beta, rho, nu): rho^2 and 2 - 3 rho^2 (3),
     nu/alpha (a library division for GLOBAL4, a reciprocal and a product
-    for LMM12), the three corr coefficients alpha^2 (1-b)^2/24,
+    for LMM12 and PERFWD), the three corr coefficients alpha^2 (1-b)^2/24,
     rho b nu alpha/4, (2 - 3 rho^2) nu^2/24 (3 + 4 + 3) and the series
     coefficient (2 - 3 rho^2)/12 (1); (1-b) and (1-b)^2 add 2 when beta is a
-    parameter."""
+    parameter.  Eq. (sigmaHagan) with beta fixed instead takes the three
+    coefficients of its quadratic in k: nu/alpha (reciprocal and product),
+    w = fp/alpha (1), alpha/fp (reciprocal and product), d = 1-b - rho nu w
+    (3), nu w (1), the linear coefficient (2) and the quadratic one (13)."""
     if model == 0:
         return 16.0 + _e("div")
+    if formula == 1:
+        return 22.0 + _e("rcp", 2)
     return 15.0 + _e("rcp")
 
 
@@ -59,22 +64,23 @@ def hagan_quote(fixed_beta: bool) -> float:
 
 
 def eq3_quote(fixed_beta: bool) -> float:
-    """Paper eq. (sigmaHagan) for one quote: nu = (nu/alpha) alpha (1),
-    w = f^(1-b)/alpha (a library division), rho nu w (2), the two bracket
-    coefficients (2 and 12), the quadratic in k (4) and the numerator scale
-    (1); fp = exp((1-b) ln f) (1) when beta is a parameter."""
-    f = 22 + _e("div")
-    if not fixed_beta:
-        f += 1 + _e("exp")
-    return f
+    """Paper eq. (sigmaHagan) for one quote.  beta a parameter: nu =
+    (nu/alpha) alpha (1), w = f^(1-b)/alpha (a library division), rho nu w
+    (2), the two bracket coefficients (2 and 12), the quadratic in k (4),
+    the numerator scale (1) and fp = exp((1-b) ln f) (1).  beta fixed: the
+    quadratic in k with the underlying's coefficients (two fma, 4)."""
+    if fixed_beta:
+        return 4.0
+    return 23 + _e("div") + _e("exp")
 
 
-def black_quote() -> float:
-    """sigma and 1/sigma from the vol fraction (5 and one reciprocal), then
-    the Black-76 out-of-the-money price: sd, d1, d2 (6), E = exp(-d1^2/2)
-    (2), the two erfcx arguments (2), f E/2 (2), the combination (3) and the
-    discount (1)."""
-    return 5 + _e("rcp") + 16 + _e("exp") + _e("erfcx", 2)
+def black_quote(direct: bool = False) -> float:
+    """sigma and 1/sigma from the vol fraction (5 and one reciprocal; one
+    reciprocal when the formula gives sigma itself), then the Black-76
+    out-of-the-money price: sd, d1, d2 (6), E = exp(-d1^2/2) (2), the two
+    erfcx arguments (2), f E/2 (2), the combination (3) and the discount
+    (1)."""
+    return (1 if direct else 5) + _e("rcp") + 16 + _e("exp") + _e("erfcx", 2)
 
 
 RESIDUAL = 4.0   # r = m - target, acc += (w r) r
@@ -82,8 +88,12 @@ RESIDUAL = 4.0   # r = m - target, acc += (w r) r
 
 def quote_flops(model: int, formula: int, residual: int) -> float:
     fixed = model != 0          # LMM12 and PERFWD fix beta
+    direct = fixed and formula == 1   # the formula gives sigma itself
     f = hagan_quote(fixed) if formula == 0 else eq3_quote(fixed)
-    f += black_quote() if residual == 1 else 1 + _e("rcp")
+    if residual == 1:
+        f += black_quote(direct)
+    elif not direct:
+        f += 1 + _e("rcp")
     return f + RESIDUAL
 
 
@@ -100,12 +110,13 @@ def map_flops_inst(market: dict, inst: int) -> float:
         return sabr_const(0) + 2
     f0, f1 = market["fwd_off"][inst], market["fwd_off"][inst + 1]
     u0, u1 = market["und_off"][inst], market["und_off"][inst + 1]
+    formula = int(market["formula"])
     if int(market["model"]) == 2:
-        return (u1 - u0) * sabr_const(1)
+        return (u1 - u0) * sabr_const(2, formula)
     nf = f1 - f0
     lens = np.asarray(market["und_len"][u0:u1])
     fwd = nf * (10 + _e("exp", 2)) + max(nf - 1, 0) * (3 + _e("exp", 2))
-    und = len(lens) * sabr_const(1)
+    und = len(lens) * sabr_const(1, formula)
     swp = lens[lens > 1]
     und += float(np.sum(18 * swp)) + len(swp) * (12 + _e("sqrt", 2) + _e("rcp", 3))
     return fwd + und
