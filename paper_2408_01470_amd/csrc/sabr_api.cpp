@@ -352,9 +352,10 @@ sabr_status sabr_cost_batch(const sabr_plan *P, int32_t n_pts, const int32_t *pt
 namespace {
 
 struct SALayout {
-  size_t o_chains, o_cbase, o_abase, o_tinst, o_tchain, o_lb, o_ub, o_x0, o_T0;
+  size_t o_chains, o_cbase, o_abase, o_tinst, o_tchain, o_toff, o_lb, o_ub, o_x0, o_T0;
   size_t upload_bytes;
-  size_t o_X, o_F, o_BX, o_BF, o_NACC, o_RX, o_RF, o_Tcur, o_tstart;
+  size_t o_X, o_BX, o_BF, o_RX, o_RF, o_Tcur, o_tstart;
+  size_t o_TF, o_TB, o_TI, o_TJ, o_TN;
   size_t total;
   int n_tiles, waves;
   int64_t tot_chains;
@@ -385,20 +386,24 @@ SALayout sa_layout(const sabr_plan *P, const sa_config *cfg, const int32_t *chai
   S.o_abase = L.take<int64_t>(n);
   S.o_tinst = L.take<int>(S.n_tiles);
   S.o_tchain = L.take<int>(S.n_tiles);
+  S.o_toff = L.take<int>(n + 1);
   S.o_lb = L.take<double>((size_t)n * Pn);
   S.o_ub = L.take<double>((size_t)n * Pn);
   S.o_x0 = L.take<double>((size_t)n * Pn);
   S.o_T0 = L.take<double>(n);
   S.upload_bytes = L.off;
   S.o_X = L.take<double>(S.tot_chains * Pn);
-  S.o_F = L.take<double>(S.tot_chains);
   S.o_BX = L.take<double>(S.tot_chains * Pn);
   S.o_BF = L.take<double>(S.tot_chains);
-  S.o_NACC = L.take<int>(S.tot_chains);
   S.o_RX = L.take<double>((size_t)n * Pn);
   S.o_RF = L.take<double>(n);
   S.o_Tcur = L.take<double>(n);
   S.o_tstart = L.take<uint64_t>(1);
+  S.o_TF = L.take<double>(S.n_tiles);
+  S.o_TB = L.take<double>(S.n_tiles);
+  S.o_TI = L.take<int>(S.n_tiles);
+  S.o_TJ = L.take<int>(S.n_tiles);
+  S.o_TN = L.take<int>(S.n_tiles);
   S.total = L.off;
   return S;
 }
@@ -461,6 +466,7 @@ sabr_status sa_calibrate(const sabr_plan *Pc, const sa_config *cfg, const int32_
   int64_t *h_abase = reinterpret_cast<int64_t *>(stg.data() + S.o_abase);
   int *h_tinst = reinterpret_cast<int *>(stg.data() + S.o_tinst);
   int *h_tchain = reinterpret_cast<int *>(stg.data() + S.o_tchain);
+  int *h_toff = reinterpret_cast<int *>(stg.data() + S.o_toff);
   double *h_lb = reinterpret_cast<double *>(stg.data() + S.o_lb);
   double *h_ub = reinterpret_cast<double *>(stg.data() + S.o_ub);
   double *h_x0 = reinterpret_cast<double *>(stg.data() + S.o_x0);
@@ -471,6 +477,7 @@ sabr_status sa_calibrate(const sabr_plan *Pc, const sa_config *cfg, const int32_
     h_chains[i] = chains[i];
     h_cbase[i] = cb;
     h_abase[i] = ab;
+    h_toff[i] = t;
     cb += chains[i];
     ab += (int64_t)L * N * chains[i];
     for (int c = 0; c < chains[i]; c += S.waves) {
@@ -486,6 +493,7 @@ sabr_status sa_calibrate(const sabr_plan *Pc, const sa_config *cfg, const int32_
       h_x0[j] = x0 ? x0[j] : 0.5 * (lb[j] + ub[j]);
     }
   }
+  h_toff[n] = t;
   hipStream_t s = static_cast<hipStream_t>(stream);
   char *w = static_cast<char *>(workspace);
   hipError_t e = hipMemcpyAsync(w, stg.data(), S.upload_bytes, hipMemcpyHostToDevice, s);
@@ -510,15 +518,19 @@ sabr_status sa_calibrate(const sabr_plan *Pc, const sa_config *cfg, const int32_
   a.acc_base = reinterpret_cast<const int64_t *>(w + S.o_abase);
   a.tile_inst = reinterpret_cast<const int *>(w + S.o_tinst);
   a.tile_chain = reinterpret_cast<const int *>(w + S.o_tchain);
+  a.tile_off = reinterpret_cast<const int *>(w + S.o_toff);
+  a.TF = reinterpret_cast<double *>(w + S.o_TF);
+  a.TB = reinterpret_cast<double *>(w + S.o_TB);
+  a.TI = reinterpret_cast<int *>(w + S.o_TI);
+  a.TJ = reinterpret_cast<int *>(w + S.o_TJ);
+  a.TN = reinterpret_cast<int *>(w + S.o_TN);
   a.lb = reinterpret_cast<const double *>(w + S.o_lb);
   a.ub = reinterpret_cast<const double *>(w + S.o_ub);
   a.x0 = reinterpret_cast<const double *>(w + S.o_x0);
   a.T0 = reinterpret_cast<const double *>(w + S.o_T0);
   a.X = reinterpret_cast<double *>(w + S.o_X);
-  a.F = reinterpret_cast<double *>(w + S.o_F);
   a.BX = reinterpret_cast<double *>(w + S.o_BX);
   a.BF = reinterpret_cast<double *>(w + S.o_BF);
-  a.NACC = reinterpret_cast<int *>(w + S.o_NACC);
   a.RX = reinterpret_cast<double *>(w + S.o_RX);
   a.RF = reinterpret_cast<double *>(w + S.o_RF);
   a.Tcur = reinterpret_cast<double *>(w + S.o_Tcur);

@@ -49,10 +49,15 @@ struct SAArgs {
   const int64_t *acc_base;      // [n_inst] offset of each instance's accept flags
   const int *tile_inst;         // [n_tiles]
   const int *tile_chain;        // [n_tiles] first chain of the tile
+  const int *tile_off;          // [n_inst + 1] each instance's tiles, in chain order
+  // per-tile partials of the level end, written by the init and level
+  // kernels: lowest final cost and its chain (ties: lowest chain), lowest
+  // best-ever cost and its chain, accepted moves of the level
+  double *TF, *TB;
+  int *TI, *TJ, *TN;
   const double *lb, *ub, *x0;   // [n_inst][P]
   const double *T0;             // [n_inst]
-  double *X, *F, *BX, *BF;      // per-chain current and best-ever state
-  int *NACC;                    // per-chain accepted moves in the current level
+  double *X, *BX, *BF;          // per-chain final point, best-ever point and cost
   double *RX, *RF, *Tcur;       // per-instance restart point and temperature
   uint64_t *t_start;            // wall clock at initialisation
   uint8_t *accept;              // nullable: [inst][level][step][chain]

@@ -146,38 +146,81 @@ __device__ __forceinline__ void wave_argmin(double &f, int &i, int C) {
   }
 }
 
-// Level end of one instance by one workgroup: the chain with the lowest final
-// cost (ties: lowest chain) becomes every chain's restart point; the trace
-// gets the best-ever cost, the acceptance rate and the device time; T is
-// cooled.  scratch: 5 doubles per wave + 1 of LDS.
+// Level-end partial of one workgroup's chains (its waves hold consecutive
+// chains of one instance): lowest final cost (ties: lowest chain), lowest
+// best-ever cost, accepted moves.  Every wave of the workgroup calls it; a
+// wave without a chain passes c = C.
+__device__ void tile_partial(const SAArgs &a, int C, int c, double f, double bf, int nacc) {
+  __shared__ double red_f[4], red_b[4];
+  __shared__ int red_c[4], red_n[4];
+  const int wid = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    red_f[wid] = f;
+    red_b[wid] = bf;
+    red_c[wid] = c;
+    red_n[wid] = nacc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bestf = kInf, bestb = kInf;
+    int bi = C, bj = C, na = 0;
+    for (int v = 0; v < (int)(blockDim.x / kWave); ++v) {   // chains in increasing order
+      const int cv = red_c[v];
+      if (cv >= C) continue;
+      if (bi == C || red_f[v] < bestf) {   // strict: the lowest chain wins ties
+        bestf = red_f[v];
+        bi = cv;
+      }
+      if (bj == C || red_b[v] < bestb) {
+        bestb = red_b[v];
+        bj = cv;
+      }
+      na += red_n[v];
+    }
+    const int t = blockIdx.x;
+    a.TF[t] = bestf;
+    a.TI[t] = bi;
+    a.TB[t] = bestb;
+    a.TJ[t] = bj;
+    a.TN[t] = na;
+  }
+}
+
+// Level end of one instance by one workgroup, from its tiles' partials: the
+// chain with the lowest final cost (ties: lowest chain) becomes every
+// chain's restart point; the trace gets the best-ever cost, the acceptance
+// rate and the device time; T is cooled.  scratch: 5 doubles per wave + 1 of
+// LDS.
 __device__ void level_end_block(const SAArgs &a, int inst, int level, double *scratch) {
   const int C = a.chains[inst];
   const int64_t base = a.chain_base[inst];
+  const int t0 = a.tile_off[inst], t1 = a.tile_off[inst + 1];
   double bestf = kInf, bestb = kInf, na = 0.0;
   int bi = C, bj = C;
-  // four chains per thread and pass, their loads issued together
+  // four tiles per thread and pass, their loads issued together
   const int stride = blockDim.x;
-  for (int c0 = threadIdx.x; c0 < C; c0 += 4 * stride) {
+  for (int k0 = t0 + (int)threadIdx.x; k0 < t1; k0 += 4 * stride) {
     double fc[4], bc[4];
-    int nc[4];
+    int ic[4], jc[4], nc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int c = c0 + j * stride;
-      const bool in = c < C;
-      fc[j] = in ? a.F[base + c] : kInf;
-      bc[j] = in ? a.BF[base + c] : kInf;
-      nc[j] = in ? a.NACC[base + c] : 0;
+      const int k = k0 + j * stride;
+      const bool in = k < t1;
+      fc[j] = in ? a.TF[k] : kInf;
+      bc[j] = in ? a.TB[k] : kInf;
+      ic[j] = in ? a.TI[k] : C;
+      jc[j] = in ? a.TJ[k] : C;
+      nc[j] = in ? a.TN[k] : 0;
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {   // chains in increasing order
-      const int c = c0 + j * stride;
-      if (c < C && (bi == C || fc[j] < bestf)) {  // strict: the lowest chain wins ties
+    for (int j = 0; j < 4; ++j) {   // tiles, hence chains, in increasing order
+      if (ic[j] < C && (bi == C || fc[j] < bestf)) {  // strict: the lowest chain wins ties
         bestf = fc[j];
-        bi = c;
+        bi = ic[j];
       }
-      if (c < C && (bj == C || bc[j] < bestb)) {
+      if (jc[j] < C && (bj == C || bc[j] < bestb)) {
         bestb = bc[j];
-        bj = c;
+        bj = jc[j];
       }
       na += (double)nc[j];
     }
@@ -209,7 +252,7 @@ __device__ void level_end_block(const SAArgs &a, int inst, int level, double *sc
       na += scratch[5 * v + 4];
     }
     scratch[5 * nw] = (double)bi;
-    a.RF[inst] = a.F[base + bi];
+    a.RF[inst] = bestf;
     if (a.level_best) a.level_best[(size_t)inst * a.L + level] = bi;
     if (a.trace) {
       double *tr = a.trace + ((size_t)inst * a.L + level) * 3;
@@ -235,28 +278,31 @@ __global__ __launch_bounds__(256) void sa_init_kernel(DevMarket m, SAArgs a, int
   const int inst = a.tile_inst[blockIdx.x];
   const DevInst in = m.inst[inst];
   const UndMkt *um = stage_underlyings(m, in, smem);
+  const int C = a.chains[inst];
   const int c = a.tile_chain[blockIdx.x] + wid;
-  if (c >= a.chains[inst]) return;
-  const double xl = (lane < P) ? a.x0[(size_t)inst * P + lane] : 0.0;
-  double x[PC > 0 ? PC : 1];
-  broadcast_params<PC>(xl, x);
-  WaveLds w = wave_lds(m, smem + 6 * m.max_nu + (size_t)wid * lds_per_wave);
-  const double f = point_cost<MODEL, FORMULA, RESID>(m, in, um, x, xl, w, nullptr, nullptr);
-  const int64_t gc = a.chain_base[inst] + c;
-  if (lane < P) {
-    a.X[gc * P + lane] = xl;
-    a.BX[gc * P + lane] = xl;
-    if (c == 0) a.RX[(size_t)inst * P + lane] = xl;
-  }
-  if (lane == 0) {
-    a.F[gc] = f;
-    a.BF[gc] = f;
-    if (c == 0) {
-      a.RF[inst] = f;
-      a.Tcur[inst] = a.T0[inst];
-      if (inst == 0) a.t_start[0] = wall_clock64();
+  double f = kInf;
+  if (c < C) {   // wave-uniform
+    const double xl = (lane < P) ? a.x0[(size_t)inst * P + lane] : 0.0;
+    double x[PC > 0 ? PC : 1];
+    broadcast_params<PC>(xl, x);
+    WaveLds w = wave_lds(m, smem + 6 * m.max_nu + (size_t)wid * lds_per_wave);
+    f = point_cost<MODEL, FORMULA, RESID>(m, in, um, x, xl, w, nullptr, nullptr);
+    const int64_t gc = a.chain_base[inst] + c;
+    if (lane < P) {
+      a.X[gc * P + lane] = xl;
+      a.BX[gc * P + lane] = xl;
+      if (c == 0) a.RX[(size_t)inst * P + lane] = xl;
+    }
+    if (lane == 0) {
+      a.BF[gc] = f;
+      if (c == 0) {
+        a.RF[inst] = f;
+        a.Tcur[inst] = a.T0[inst];
+        if (inst == 0) a.t_start[0] = wall_clock64();
+      }
     }
   }
+  tile_partial(a, C, c < C ? c : C, f, f, 0);
 }
 
 // OCC: minimum waves per SIMD the register allocation must allow (1 = the
@@ -275,6 +321,8 @@ __global__ __launch_bounds__(256, OCC) void sa_level_kernel(DevMarket m, SAArgs 
   const UndMkt *um = stage_underlyings(m, in, smem);
   const int C = a.chains[inst];
   const int c = a.tile_chain[blockIdx.x] + wid;
+  double f_end = kInf, bf_end = kInf;
+  int nacc_end = 0;
   if (c < C) {   // wave-uniform: waves past the instance's last chain have no work
     const int64_t gc = a.chain_base[inst] + c;
     // lane k < P holds coordinate k of the chain's point, best point and box
@@ -296,7 +344,11 @@ __global__ __launch_bounds__(256, OCC) void sa_level_kernel(DevMarket m, SAArgs 
       // counter (level N + s, chain, block, 0): word k mod 4 of block k/4.  One
       // pass over the lanes makes those of spp steps.
       {
-        const int sl = lane / nb, blk = lane - sl * nb;
+        // the lane index is re-read each pass so nothing derived from it
+        // stays live in registers across the steps
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        const int sl = ln / nb, blk = ln - sl * nb;
         if (sl < spp && s0 + sl < a.N) {
           uint64_t wds[4];
           philox4x64_10((uint64_t)level * (uint64_t)a.N + (uint64_t)(s0 + sl), (uint64_t)c,
@@ -340,11 +392,13 @@ __global__ __launch_bounds__(256, OCC) void sa_level_kernel(DevMarket m, SAArgs 
       a.BX[gc * P + lane] = bx;
     }
     if (lane == 0) {
-      a.F[gc] = f;
       a.BF[gc] = bf;
-      a.NACC[gc] = nacc;
     }
+    f_end = f;
+    bf_end = bf;
+    nacc_end = nacc;
   }
+  tile_partial(a, C, c < C ? c : C, f_end, bf_end, nacc_end);
 }
 
 // Level end, one workgroup per instance: argmin of the final costs (ties ->
