@@ -16,17 +16,28 @@ HIPCC_FLAGS = [
 ]
 
 
+LAUNCH_MARKER = b"// Launch wrappers"
+
+
 def source_digest() -> str:
-    """SHA-256 over the library's kernel and runtime sources (every .hip,
-    .hpp and .cpp under csrc/ except the pricing program), in name order:
-    identifies the kernel build that a set of hardware counters belongs to."""
+    """SHA-256 over the device code of the annealing kernels: every header
+    under csrc/ and sabr_kernels.hip up to its host-side launch wrappers, in
+    name order.  Identifies the kernel build that a set of hardware counters
+    of those kernels belongs to (the adjoint's kernels, the host runtime and
+    the pricing program do not enter)."""
     import hashlib
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".hpp", ".cpp")) and name != "elementary_calib.hip":
-            h.update(name.encode())
-            with open(os.path.join(CSRC, name), "rb") as fh:
-                h.update(fh.read())
+        if not (name.endswith(".hpp") or name == "sabr_kernels.hip") or name == "sabr_adjoint.hpp":
+            continue
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            text = fh.read()
+        if name == "sabr_kernels.hip":
+            cut = text.find(LAUNCH_MARKER)
+            assert cut > 0, "launch wrapper marker missing"
+            text = text[:cut]
+        h.update(name.encode())
+        h.update(text)
     return h.hexdigest()
 
 

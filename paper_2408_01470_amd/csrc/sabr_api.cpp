@@ -357,7 +357,7 @@ struct SALayout {
   size_t o_X, o_BX, o_BF, o_RX, o_RF, o_Tcur, o_tstart;
   size_t o_TF, o_TB, o_TI, o_TJ, o_TN;
   size_t total;
-  int n_tiles, waves;
+  int n_tiles, waves, max_tiles;
   int64_t tot_chains;
 };
 
@@ -375,9 +375,12 @@ SALayout sa_layout(const sabr_plan *P, const sa_config *cfg, const int32_t *chai
   shape.max_len = P->max_len;
   S.waves = sabr::sa_waves_per_group(shape, want);
   S.n_tiles = 0;
+  S.max_tiles = 0;
   S.tot_chains = 0;
   for (int i = 0; i < n; ++i) {
-    S.n_tiles += (chains[i] + S.waves - 1) / S.waves;
+    const int ti = (chains[i] + S.waves - 1) / S.waves;
+    S.n_tiles += ti;
+    if (ti > S.max_tiles) S.max_tiles = ti;
     S.tot_chains += chains[i];
   }
   Layout L;
@@ -559,7 +562,7 @@ sabr_status sa_calibrate(const sabr_plan *Pc, const sa_config *cfg, const int32_
                        hipSuccess)
           return r;
       }
-      r = sabr::launch_sa_level_end(a, l, q);
+      r = sabr::launch_sa_level_end(a, l, S.max_tiles, q);
       if (r != hipSuccess) return r;
     }
     return sabr::launch_sa_final(a, q);

@@ -80,7 +80,9 @@ hipError_t launch_sa_init(const DevMarket &m, const SAArgs &a, int n_tiles, int 
                           hipStream_t s);
 hipError_t launch_sa_level(const DevMarket &m, const SAArgs &a, int level, int n_tiles,
                            int waves, int occupancy, hipStream_t s);
-hipError_t launch_sa_level_end(const SAArgs &a, int level, hipStream_t s);
+// max_tiles: the most workgroups (tiles) any instance has; sizes the
+// level-end block (256 threads, 1024 beyond 1024 tiles).
+hipError_t launch_sa_level_end(const SAArgs &a, int level, int max_tiles, hipStream_t s);
 hipError_t launch_sa_final(const SAArgs &a, hipStream_t s);
 
 // Wavefronts per SA/cost workgroup that fit the LDS budget (at most `want`).

@@ -403,8 +403,9 @@ __global__ __launch_bounds__(256, OCC) void sa_level_kernel(DevMarket m, SAArgs 
 
 // Level end, one workgroup per instance: argmin of the final costs (ties ->
 // lowest chain), restart point, best-ever trace, next temperature.
-__global__ __launch_bounds__(256) void sa_level_end_kernel(SAArgs a, int level) {
-  __shared__ double scratch[5 * 4 + 1];
+constexpr int kLevelEndThreads = 1024;
+__global__ __launch_bounds__(kLevelEndThreads) void sa_level_end_kernel(SAArgs a, int level) {
+  __shared__ double scratch[5 * (kLevelEndThreads / kWave) + 1];
   level_end_block(a, blockIdx.x, level, scratch);
 }
 
@@ -566,8 +567,9 @@ hipError_t launch_sa_level(const DevMarket &m, const SAArgs &a, int level, int n
   return hipGetLastError();
 }
 
-hipError_t launch_sa_level_end(const SAArgs &a, int level, hipStream_t s) {
-  hipLaunchKernelGGL(sa_level_end_kernel, dim3(a.n_inst), dim3(256), 0, s, a, level);
+hipError_t launch_sa_level_end(const SAArgs &a, int level, int max_tiles, hipStream_t s) {
+  const int threads = max_tiles > 1024 ? kLevelEndThreads : 256;
+  hipLaunchKernelGGL(sa_level_end_kernel, dim3(a.n_inst), dim3(threads), 0, s, a, level);
   return hipGetLastError();
 }
 
