@@ -266,22 +266,24 @@ def time_to_rmse(api, W, I, autotune):
     }
 
 
-def paper_e2(api, W, I, flops, autotune, shape=None):
-    """The paper's own timed caplet calibration (Sec. 4.1.1) on its printed
-    EURIBOR data: PERFWD (13 forwards, P = 39), eq. (sigmaHagan), SA with
-    T0 = 10, Tmin = 0.01, rho = 0.99 (688 levels), N = 10, 16384 chains
-    (112,738,304 cost evaluations), then LM on each forward as a GLOBAL4
-    instance with beta frozen at 0.5 (the paper: Nelder-Mead).  Device time
-    of the annealing (HIP events) and wall time of the polish including its
-    host-side re-layout; MRE = mean |sigma_model - sigma_market| /
-    sigma_market over the 117 quotes, before and after the polish."""
+def paper_e2(api, W, I, flops, autotune, shape=None, which="e2"):
+    """The paper's own timed caplet calibrations on its printed EURIBOR data
+    (Sec. 4.1.1 and 4.2.1), eq. (sigmaHagan), SA with T0 = 10, Tmin = 0.01,
+    rho = 0.99 (688 levels), N = 10, 16384 chains (112,738,304 cost
+    evaluations).  which = "e2": the per-forward Hagan model (PERFWD, P = 39),
+    then LM on each forward as a GLOBAL4 instance with beta frozen at 0.5 (the
+    paper: Nelder-Mead).  which = "mm": the Mercurio-Morini model (P = 27),
+    annealing only (its cost does not separate per forward, and LM takes
+    GLOBAL4 and LMM12 plans).  Device time of the annealing (HIP events) and
+    wall time of the polish including its host-side re-layout; MRE = mean
+    |sigma_model - sigma_market| / sigma_market over the 117 quotes."""
     import torch
-    w = W.paper_e2()
+    w = W.paper_e2() if which == "e2" else W.paper_mm()
     mk = w.market
     plan = api.Plan(mk)
     tuning = None
     n_fwd = int(mk["fwd_off"][1])
-    lb, ub = I.box(I.MODEL_PERFWD, n_fwd)
+    lb, ub = I.box(int(mk["model"]), n_fwd)
     kw = dict(T0=w.extra["T0"], cool=w.extra["cool"], n_levels=w.n_levels, n_steps=w.n_steps,
               seed=w.seed, step_frac=w.step_frac)
     if shape is None:
@@ -291,8 +293,8 @@ def paper_e2(api, W, I, flops, autotune, shape=None):
             t = AT.tune(plan, w.chains, lb, ub, w.n_steps)
             shape = dict(waves=t["waves"], occupancy=t["occupancy"])
             tuning = [[d["waves"], d["occupancy"], round(d["level_ms"], 4)] for d in t["all"]]
-    g4 = I.perfwd_as_global4(mk)
-    plan4 = api.Plan(g4)
+    g4 = I.perfwd_as_global4(mk) if which == "e2" else None
+    plan4 = api.Plan(g4) if which == "e2" else None
     beta = float(mk["beta"])
     lb4 = np.tile([lb[0], beta, lb[1], lb[2]], (n_fwd, 1))
     ub4 = np.tile([ub[0], beta, ub[1], ub[2]], (n_fwd, 1))
@@ -300,6 +302,8 @@ def paper_e2(api, W, I, flops, autotune, shape=None):
     vol = np.asarray(mk["q_vol"])
 
     def polish(x):
+        if which != "e2":
+            return x, np.zeros(1, np.int32)
         starts = torch.tensor(I.perfwd_points_as_global4(x, beta), device="cuda")
         y, f4, it = plan4.lm(starts, lb4, ub4, pt_inst=inst4, max_iter=100)
         return I.global4_points_as_perfwd(y.cpu().numpy()), it.cpu().numpy()
@@ -336,8 +340,15 @@ def paper_e2(api, W, I, flops, autotune, shape=None):
     flop_launch = flops.level_launch_flops(mk, w.chains, w.n_steps)
     achieved = flop_launch / (float(lvl_ms.mean()) / 1e3) / 1e12
     evals = w.chains * (1 + w.n_steps * L)
-    t = x_pol.reshape(-1, 3)
-    return {
+    if which == "e2":
+        t = x_pol.reshape(-1, 3)
+        params = {"alpha": t[:, 0].round(5).tolist(), "phi": t[:, 1].round(4).tolist(),
+                  "sigma": t[:, 2].round(4).tolist()}
+    else:
+        t = x_pol[:-1].reshape(-1, 2)
+        params = {"alpha": t[:, 0].round(5).tolist(), "phi": t[:, 1].round(4).tolist(),
+                  "sigma": round(float(x_pol[-1]), 4)}
+    out = {
         "workload": w.name,
         "cost_evaluations": evals,
         "quote_evals": w.quote_evals(),
@@ -346,19 +357,20 @@ def paper_e2(api, W, I, flops, autotune, shape=None):
         "quote_evals_per_s": w.quote_evals() / t_sa,
         "level_kernel_avg_ms": float(lvl_ms.mean()),
         "level_kernel_fp64_frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-        "t_polish_s": t_pol,
-        "polish_lm_iterations_max": int(it.max()),
         "mre_sa": mre(x_sa),
-        "mre_polished": mre(x_pol),
         "cost_sa": float(r["best_f"].item()),
-        "params_polished": {"alpha": t[:, 0].round(5).tolist(), "phi": t[:, 1].round(4).tolist(),
-                            "sigma": t[:, 2].round(4).tolist()},
         "launch_shape": shape,
         "tuning_level_ms": tuning,
         "paper": {"t_sa_s": w.extra["paper_sa_s"], "t_nelder_mead_s": w.extra["paper_nm_s"],
                   "cost_evaluations": w.extra["paper_evals"], "mre": w.extra["paper_mre"],
                   "hardware": "one GTX 470 (context, not a target)"},
     }
+    if which == "e2":
+        out.update({"t_polish_s": t_pol, "polish_lm_iterations_max": int(it.max()),
+                    "mre_polished": mre(x_pol), "params_polished": params})
+    else:
+        out["params_sa"] = params
+    return out
 
 
 def main():
@@ -381,6 +393,7 @@ def main():
                    if args.waves is not None else None)
     if args.paper_e2_only:
         print(json.dumps(paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape)))
+        print(json.dumps(paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape, "mm")))
         return
     w = W.CONFIGS[args.config]()
     if args.levels is not None:
@@ -497,6 +510,7 @@ def main():
         out["cost_and_adjoint"] = cost_and_adjoint(api, W, I, args.adjoint_config)
     if not args.no_paper_e2:
         out["paper_e2"] = paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape)
+        out["paper_mm"] = paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape, "mm")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_levels, w.n_levels))
     print(json.dumps(out))

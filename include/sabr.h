@@ -77,8 +77,24 @@ typedef enum {
  *           Every triple must lie in the domain, quoted or not.  The adjoint
  *           and LM entry points return SABR_EUNSUPPORTED for it (its cost
  *           separates per forward: polish each forward as a GLOBAL4 instance
- *           with beta frozen by lb = ub). */
-typedef enum { SABR_MODEL_GLOBAL4 = 0, SABR_MODEL_LMM12 = 1, SABR_MODEL_PERFWD = 2 } sabr_model;
+ *           with beta frozen by lb = ub).
+ *  MM:      p = (alpha_1, phi_1, ..., alpha_n, phi_n, sigma), beta fixed: the
+ *           Mercurio-Morini model of Sec. 2.2 (x = (phi_i, sigma, alpha_i)) with
+ *           the SABR parameters of eq. (haganForMercurio): rho_i = phi_i,
+ *           nu_i = sigma, alpha_i^SABR = alpha_i exp(-sigma D_i),
+ *           D_i = sum_{j<=i} T_{j-1} tau_j phi_j alpha_j F_j^beta / (1 + tau_j F_j)
+ *           with T_{j-1} the previous forward's fixing (0 for the first): the
+ *           drift sum runs from the forward after the first unfixed one.
+ *           Caplet markets only; every instance holds the same number
+ *           n <= 31 of forwards, P = 2 n + 1.  Domain: alpha_j > 0,
+ *           |phi_j| < 1, sigma >= 0.  The adjoint and LM entry points return
+ *           SABR_EUNSUPPORTED for it. */
+typedef enum {
+  SABR_MODEL_GLOBAL4 = 0,
+  SABR_MODEL_LMM12 = 1,
+  SABR_MODEL_PERFWD = 2,
+  SABR_MODEL_MM = 3
+} sabr_model;
 
 /* Implied-vol formula.
  *  HAGAN2002: L = ln(f/K), q = (fK)^((1-beta)/2), z = (nu/alpha) q L,
@@ -115,15 +131,15 @@ typedef struct {
   const int32_t *q_und, *q_kind;
   const double *q_K, *q_vol, *q_w;                /* strike, market implied vol, weight */
   int32_t model, vol_formula, residual;
-  double beta;                                    /* fixed beta for LMM12 and PERFWD, in [0, 1] */
+  double beta;                                    /* fixed beta (LMM12, PERFWD, MM), in [0, 1] */
 } sabr_problem;
 
 typedef struct sabr_plan sabr_plan; /* opaque; host memory only */
 
 /* Validate the market (offsets monotone and in range, positive finite
  * forwards, strikes, accruals, discounts and vols, non-negative weights,
- * positive expiries, quotes sorted by underlying, GLOBAL4 and PERFWD without
- * swaps, PERFWD instances of equal size) and
+ * positive expiries, quotes sorted by underlying, GLOBAL4, PERFWD and MM
+ * without swaps, PERFWD and MM instances of equal size) and
  * build its packed image.  On success *out owns host memory only. */
 sabr_status sabr_plan_create(const sabr_problem *prob /*[host]*/, sabr_plan **out /*[host]*/);
 void sabr_plan_destroy(sabr_plan *plan);
@@ -136,8 +152,8 @@ size_t sabr_plan_device_bytes(const sabr_plan *plan);
  * market prices and vegas in price mode).  The plan keeps dev_buf. */
 sabr_status sabr_plan_upload(sabr_plan *plan, void *dev_buf, size_t bytes, void *stream);
 
-int32_t sabr_num_params(int32_t model);             /* 4 or 12; -1 if unknown or PERFWD */
-int32_t sabr_plan_num_params(const sabr_plan *plan); /* P of the plan (PERFWD: 3 n) */
+int32_t sabr_num_params(int32_t model);  /* 4 or 12; -1 if unknown, PERFWD or MM */
+int32_t sabr_plan_num_params(const sabr_plan *plan); /* P of the plan (PERFWD 3 n, MM 2 n + 1) */
 int32_t sabr_plan_num_inst(const sabr_plan *plan);
 int32_t sabr_plan_max_quotes(const sabr_plan *plan); /* largest quotes per instance */
 
@@ -217,7 +233,7 @@ size_t sabr_adjoint_workspace_size(const sabr_plan *plan, int32_t n_pts);
  * d cost/d p = 2 J^T W r.  Out-of-domain points give cost +inf and zero
  * derivatives.  The derivative of the cost follows from the paper's f_c and
  * f_s (Sec. 3); the paper itself polishes with Nelder-Mead and has no
- * gradient.  GLOBAL4 and LMM12 plans (PERFWD: SABR_EUNSUPPORTED). */
+ * gradient.  GLOBAL4 and LMM12 plans (PERFWD, MM: SABR_EUNSUPPORTED). */
 sabr_status sabr_cost_vjp(const sabr_plan *plan, int32_t n_pts, const int32_t *pt_inst,
                           const double *params, const double *g_cost, double *cost,
                           double *g_params, double *jtwj, double *jtwr, void *workspace,
@@ -231,7 +247,7 @@ sabr_status sabr_cost_vjp(const sabr_plan *plan, int32_t n_pts, const int32_t *p
  * A zero diagonal entry is replaced by 1; coordinates with lb = ub, or on a
  * bound that -J^T W r points out of, are frozen for the iteration.  lb, ub:
  * [host][n_inst][P].  cost_out [n_pts] and iters_out [n_pts] nullable.
- * GLOBAL4 and LMM12 plans (PERFWD: SABR_EUNSUPPORTED). */
+ * GLOBAL4 and LMM12 plans (PERFWD, MM: SABR_EUNSUPPORTED). */
 sabr_status sabr_lm_polish(const sabr_plan *plan, int32_t n_pts, const int32_t *pt_inst,
                            double *params, const double *lb, const double *ub, int32_t max_iter,
                            double mu0, double tol, double *cost_out, int32_t *iters_out,

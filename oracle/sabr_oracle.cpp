@@ -259,7 +259,7 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 int32_t build_inst(const oracle_market *m, int i, Inst &I) {
   if (!m) return fail("null market");
   if (i < 0 || i >= m->n_inst) return fail("instance index out of range");
-  if (m->model < 0 || m->model > 2) return fail("unknown model");
+  if (m->model < 0 || m->model > 3) return fail("unknown model");
   if (m->formula < 0 || m->formula > 1) return fail("unknown vol formula");
   if (m->residual < 0 || m->residual > 1) return fail("unknown residual mode");
   I.model = m->model;
@@ -287,7 +287,7 @@ int32_t build_inst(const oracle_market *m, int i, Inst &I) {
     U.first = m->und_first[k];
     U.len = m->und_len[k];
     if (U.len < 1 || U.first < 0 || U.first + U.len > nf) return fail("bad underlying range");
-    if (m->model != 1 && U.len != 1) return fail("GLOBAL4 and PERFWD markets hold caplets only");
+    if (m->model != 1 && U.len != 1) return fail("GLOBAL4, PERFWD and MM markets hold caplets only");
     U.A = 0.0;
     for (int j = U.first; j < U.first + U.len; ++j) U.A += I.f[j].tau * I.f[j].P;
     U.S0 = 0.0;
@@ -335,15 +335,17 @@ int32_t build_inst(const oracle_market *m, int i, Inst &I) {
 
 int num_params(int model) { return model == 0 ? 4 : (model == 1 ? 12 : -1); }
 
-// Parameters per point of a market: 4 or 12, or 3 per forward for PERFWD,
-// whose instances must all hold the same number of forwards; -1 otherwise.
+// Parameters per point of a market: 4 or 12; 3 per forward for PERFWD; 2
+// per forward plus one for MM.  PERFWD and MM instances must all hold the
+// same number of forwards; -1 otherwise.
 int market_params(const oracle_market *m) {
-  if (m->model != 2) return num_params(m->model);
+  if (m->model != 2 && m->model != 3) return num_params(m->model);
   if (m->n_inst < 1) return -1;
   const int nf = m->fwd_off[1] - m->fwd_off[0];
   for (int i = 1; i < m->n_inst; ++i)
     if (m->fwd_off[i + 1] - m->fwd_off[i] != nf) return -1;
-  return nf >= 1 ? 3 * nf : -1;
+  if (nf < 1) return -1;
+  return m->model == 2 ? 3 * nf : 2 * nf + 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -357,6 +359,19 @@ int market_params(const oracle_market *m) {
 //    per-forward parameters x = (phi_ii, sigma_i, alpha_i) (phi_ii = rho_i,
 //    sigma_i = nu_i), the model calibrated to caplets in Sec. 4.1.1.  Every
 //    triple must lie in the domain, quoted or not.
+//  MM: p = (alpha_1, phi_1, ..., alpha_n, phi_n, sigma), beta fixed: the
+//    Mercurio-Morini model of Sec. 2.2, x = (phi_i, sigma, alpha_i), with the
+//    SABR parameters of eq. (haganForMercurio): beta_i = beta, rho_i =
+//    phi_i, nu_i = sigma, alpha_i^SABR = alpha_i exp(int_0^{T_i} M_i(s) ds),
+//    M_i(s) = -sigma sum_j tau_j phi_j alpha_j F_j^beta / (1 + tau_j F_j)
+//    over the forwards j <= i of the drift sum at s.  The drift sum starts
+//    at the forward after h(s) (reading: this reproduces the paper's
+//    printed ATM levels), so forward j enters while s < T_{j-1}, the fixing
+//    of the forward before it (0 for the first):
+//      int_0^{T_i} M_i = -sigma sum_{j<=i} c_j T_{j-1},
+//      c_j = tau_j phi_j alpha_j F_j^beta / (1 + tau_j F_j).
+//    Every (alpha_j, phi_j) must lie in the domain (alpha > 0, |phi| < 1),
+//    and sigma >= 0.
 //  LMM12: p = (a, b, c, d, a_n, b_n, c_n, d_n, rho, lambda1, eta2, lambda2),
 //    beta fixed.  alpha_i = (a + b T_i) e^{-c T_i} + d and
 //    nu_i = (a_n + b_n T_i) e^{-c_n T_i} + d_n are the abcd forms of Sec. 2.3
@@ -384,6 +399,27 @@ bool map_params(const Inst &I, const S *p, std::vector<Theta<S>> &th) {
         !(std::fabs(val(rho)) < 1.0) || !(val(nu) >= 0.0))
       return false;
     for (size_t u = 0; u < I.u.size(); ++u) th[u] = Theta<S>{alpha, beta, rho, nu};
+    return true;
+  }
+  if (I.model == 3) {
+    const size_t nf = I.f.size();
+    const S &sigma = p[2 * nf];
+    if (!(val(sigma) >= 0.0)) return false;
+    for (size_t k = 0; k < nf; ++k)
+      if (!(val(p[2 * k]) > 0.0) || !(std::fabs(val(p[2 * k + 1])) < 1.0)) return false;
+    std::vector<S> aS(nf);
+    S D(0.0);   // sum_{j<=k} c_j T_{j-1}
+    for (size_t k = 0; k < nf; ++k) {
+      const Fwd &F = I.f[k];
+      const double Tprev = (k == 0) ? 0.0 : I.f[k - 1].T;
+      const S c = F.tau * p[2 * k + 1] * p[2 * k] * std::pow(F.F, I.beta) / (1.0 + F.tau * F.F);
+      D += c * Tprev;
+      aS[k] = p[2 * k] * exp(-(sigma * D));
+    }
+    for (size_t u = 0; u < I.u.size(); ++u) {
+      const int k = I.u[u].first;
+      th[u] = Theta<S>{aS[k], S(I.beta), p[2 * k + 1], sigma};
+    }
     return true;
   }
   if (I.model == 2) {
@@ -825,7 +861,7 @@ int32_t oracle_cost_grad(const oracle_market *m, int32_t n_pts, const int32_t *p
   for (int i = 0; i < m->n_inst; ++i)
     if (build_inst(m, i, insts[i])) return -1;
   const int P = market_params(m);
-  if (m->model == 2 || P < 0) return fail("gradients and LM need GLOBAL4 or LMM12");
+  if (m->model >= 2 || P < 0) return fail("gradients and LM need GLOBAL4 or LMM12");
   for (int i = 0; i < n_pts; ++i)
     if (pt_inst[i] < 0 || pt_inst[i] >= m->n_inst) return fail("point instance out of range");
 #pragma omp parallel for schedule(dynamic)
@@ -1046,7 +1082,7 @@ int32_t oracle_lm_polish(const oracle_market *m, int32_t n_pts, const int32_t *p
   for (int i = 0; i < m->n_inst; ++i)
     if (build_inst(m, i, insts[i])) return -1;
   const int P = market_params(m);
-  if (m->model == 2 || P < 0) return fail("gradients and LM need GLOBAL4 or LMM12");
+  if (m->model >= 2 || P < 0) return fail("gradients and LM need GLOBAL4 or LMM12");
   for (int i = 0; i < n_pts; ++i)
     if (pt_inst[i] < 0 || pt_inst[i] >= m->n_inst) return fail("point instance out of range");
 #pragma omp parallel for schedule(dynamic)

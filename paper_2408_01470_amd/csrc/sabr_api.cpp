@@ -56,7 +56,7 @@ struct sabr_plan {
   int max_nq = 0, max_nu = 0, max_nf = 0, max_len = 0;
   // host copies of the uploaded arrays
   std::vector<DevInst> inst;
-  std::vector<double> f_T, f_tauP, f_F;
+  std::vector<double> f_T, f_tauP, f_F, f_mmw;
   std::vector<int> u_first, u_len, u_order;
   std::vector<sabr::UndMap> u_map;
   std::vector<double> u_S0, u_A, u_invA, u_T;
@@ -64,7 +64,7 @@ struct sabr_plan {
   std::vector<int> q_und_g;
   std::vector<double> q_vol, q_wuser;
   // device image offsets
-  size_t o_inst, o_fT, o_ftauP, o_fF, o_ufirst, o_ulen, o_uorder, o_uS0, o_uA, o_uinvA, o_uT,
+  size_t o_inst, o_fT, o_ftauP, o_fF, o_fmmw, o_ufirst, o_ulen, o_uorder, o_uS0, o_uA, o_uinvA, o_uT,
       o_q, o_qundg, o_qvol, o_qwuser;  // uploaded (contiguous prefix)
   size_t upload_bytes = 0;
   size_t o_fv, o_uS0b, o_uc0, o_ufp, o_umap;
@@ -92,7 +92,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   if (!pr || !out) return fail(SABR_EINVAL, "null argument");
   *out = nullptr;
   if (pr->n_inst < 1) return fail(SABR_EINVAL, "n_inst must be >= 1");
-  if (pr->model < 0 || pr->model > 2) return fail(SABR_EINVAL, "unknown model");
+  if (pr->model < 0 || pr->model > 3) return fail(SABR_EINVAL, "unknown model");
   if (pr->vol_formula < 0 || pr->vol_formula > 1) return fail(SABR_EINVAL, "unknown formula");
   if (pr->residual < 0 || pr->residual > 1) return fail(SABR_EINVAL, "unknown residual mode");
   if (!(pr->beta >= 0.0 && pr->beta <= 1.0)) return fail(SABR_EINVAL, "beta outside [0, 1]");
@@ -114,20 +114,24 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   P->residual = pr->residual;
   P->beta = pr->beta;
   P->np = sabr_num_params(pr->model);
-  if (pr->model == 2) {
-    // PERFWD: one (alpha, rho, nu) per forward, lanes k < 3 nf of a wave
-    // hold the point, so every instance has the same nf <= 21
+  if (pr->model == 2 || pr->model == 3) {
+    // PERFWD: one (alpha, rho, nu) per forward; MM: one (alpha, phi) per
+    // forward and sigma.  Lanes k < P of a wave hold the point next to the
+    // Metropolis uniform, so every instance has the same nf with P <= 63.
+    const char *name = pr->model == 2 ? "PERFWD" : "MM";
     const int nf = pr->fwd_off[1] - pr->fwd_off[0];
     for (int i = 1; i < n; ++i)
       if (pr->fwd_off[i + 1] - pr->fwd_off[i] != nf) {
         delete P;
-        return fail(SABR_EINVAL, "PERFWD instances must hold equally many forwards");
+        return fail(SABR_EINVAL, std::string(name) + " instances must hold equally many forwards");
       }
-    if (nf < 1 || 3 * nf > sabr::kWave - 1) {
+    const int np = pr->model == 2 ? 3 * nf : 2 * nf + 1;
+    if (nf < 1 || np > sabr::kWave - 1) {
       delete P;
-      return fail(SABR_EINVAL, "PERFWD needs 1..21 forwards per instance");
+      return fail(SABR_EINVAL, std::string(name) + (pr->model == 2 ? " needs 1..21 forwards per instance"
+                                                                   : " needs 1..31 forwards per instance"));
     }
-    P->np = 3 * nf;
+    P->np = np;
   }
   P->nF = pr->fwd_off[n];
   P->nU = pr->und_off[n];
@@ -144,6 +148,13 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
     P->f_tauP.push_back(tau * Pk);
     P->f_F.push_back(F);
   }
+  // MM drift weights T_{k-1} tau_k F_k^beta / (1 + tau_k F_k), T_{-1} = 0 per instance
+  P->f_mmw.assign(P->nF, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = pr->fwd_off[i] + 1; k < pr->fwd_off[i + 1]; ++k) {
+      const double tau = pr->fwd_tau[k], F = pr->fwd_F[k];
+      P->f_mmw[k] = pr->fwd_T[k - 1] * tau * std::pow(F, pr->beta) / (1.0 + tau * F);
+    }
   for (int i = 0; i < n; ++i) {
     DevInst d{};
     d.f0 = pr->fwd_off[i];
@@ -158,7 +169,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
       const int first = pr->und_first[u], len = pr->und_len[u];
       if (len < 1 || first < 0 || first + len > d.nf)
         return bad("underlying " + std::to_string(u) + ": forward range out of bounds");
-      if (pr->model != 1 && len != 1) return bad("GLOBAL4 and PERFWD markets hold caplets only");
+      if (pr->model != 1 && len != 1) return bad("GLOBAL4, PERFWD and MM markets hold caplets only");
       if (len > d.maxlen) d.maxlen = len;
       // annuity, weights and swap rate, summed in forward order
       double A = 0.0;
@@ -218,6 +229,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   P->o_fT = L.take<double>(P->nF);
   P->o_ftauP = L.take<double>(P->nF);
   P->o_fF = L.take<double>(P->nF);
+  P->o_fmmw = L.take<double>(P->nF);
   P->o_ufirst = L.take<int>(P->nU);
   P->o_ulen = L.take<int>(P->nU);
   P->o_uorder = L.take<int>(P->nU);
@@ -244,6 +256,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   put(P->o_fT, P->f_T.data(), P->nF * 8);
   put(P->o_ftauP, P->f_tauP.data(), P->nF * 8);
   put(P->o_fF, P->f_F.data(), P->nF * 8);
+  put(P->o_fmmw, P->f_mmw.data(), P->nF * 8);
   put(P->o_ufirst, P->u_first.data(), P->nU * 4);
   put(P->o_ulen, P->u_len.data(), P->nU * 4);
   put(P->o_uorder, P->u_order.data(), P->nU * 4);
@@ -301,6 +314,7 @@ sabr_status sabr_plan_upload(sabr_plan *P, void *dev_buf, size_t bytes, void *st
   auto I = [&](size_t o) { return reinterpret_cast<int *>(d + o); };
   m.f_T = D(P->o_fT);
   m.f_v = D(P->o_fv);
+  m.f_mmw = D(P->o_fmmw);
   m.u_first = I(P->o_ufirst);
   m.u_len = I(P->o_ulen);
   m.u_order = I(P->o_uorder);
@@ -663,7 +677,7 @@ sabr_status sabr_cost_vjp(const sabr_plan *P, int32_t n_pts, const int32_t *pt_i
   if (st != SABR_OK) return st;
   if (n_pts == 0) return SABR_OK;
   if (!pt_inst || !params || !g_params) return fail(SABR_EINVAL, "null pt_inst, params or g_params");
-  if (P->model == 2) return fail(SABR_EUNSUPPORTED, "the adjoint takes GLOBAL4 and LMM12 plans");
+  if (P->model >= 2) return fail(SABR_EUNSUPPORTED, "the adjoint takes GLOBAL4 and LMM12 plans");
   const AdjLayout A = adj_layout(P, n_pts);
   if (A.total > 0 && (!workspace || ws_bytes < A.total))
     return fail(SABR_EWORKSPACE, "workspace too small");
@@ -684,7 +698,7 @@ sabr_status sabr_lm_polish(const sabr_plan *Pc, int32_t n_pts, const int32_t *pt
   if (n_pts == 0) return SABR_OK;
   if (!pt_inst || !params || !lb || !ub) return fail(SABR_EINVAL, "null argument");
   if (max_iter < 0 || !(mu0 > 0.0) || !(tol >= 0.0)) return fail(SABR_EINVAL, "bad LM settings");
-  if (Pc->model == 2) return fail(SABR_EUNSUPPORTED, "LM takes GLOBAL4 and LMM12 plans");
+  if (Pc->model >= 2) return fail(SABR_EUNSUPPORTED, "LM takes GLOBAL4 and LMM12 plans");
   sabr_plan *P = const_cast<sabr_plan *>(Pc);
   const int Pn = P->np;
   for (int i = 0; i < P->n_inst * Pn; ++i)

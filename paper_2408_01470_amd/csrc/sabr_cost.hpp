@@ -16,9 +16,14 @@ template <>
 struct NP<1> {
   static constexpr int P = 12;
 };
-// PERFWD: three parameters per forward, known at run time (DevMarket::np).
+// PERFWD (three parameters per forward) and MM (two per forward and one):
+// known at run time (DevMarket::np).
 template <>
 struct NP<2> {
+  static constexpr int P = 0;
+};
+template <>
+struct NP<3> {
   static constexpr int P = 0;
 };
 
@@ -273,9 +278,51 @@ __device__ bool perfwd_map(const DevMarket &m, const DevInst &in, const UndMkt *
   return __any(bad);
 }
 
+// MM map (the Mercurio-Morini model of Sec. 2.2 with the SABR parameters of
+// eq. (haganForMercurio)): lane k < np holds coordinate k of
+// (alpha_1, phi_1, ..., alpha_n, phi_n, sigma), beta fixed.  Lane j < n
+// computes alpha_j^SABR = alpha_j exp(-sigma D_j), D_j = sum_{l<=j} phi_l
+// alpha_l w_l with the plan's drift weights w_l = T_{l-1} tau_l F_l^beta /
+// (1 + tau_l F_l) (T_{-1} = 0: the drift sum starts at the forward after the
+// first unfixed one), by a prefix sum over the lanes; each caplet fetches
+// its forward's alpha^SABR and phi across lanes, nu = sigma.  Domain:
+// alpha_j > 0, |phi_j| < 1, sigma >= 0.  Returns true (wave-uniform) on a
+// domain failure.
+template <int FORMULA>
+__device__ bool mm_map(const DevMarket &m, const DevInst &in, const UndMkt *um, double xl,
+                       WaveLds w) {
+  const int lane = lane_id();
+  const int np = m.np;   // 2 nf + 1
+  const double beta = m.beta;
+  bool bad = false;
+  if (lane < np)
+    bad = (lane == np - 1) ? !(xl >= 0.0) : ((lane & 1) == 0) ? !(xl > 0.0) : !(fabs(xl) < 1.0);
+  const double sigma = readlane_d(xl, np - 1);
+  const double al = __shfl(xl, 2 * lane, kWave);       // lanes j < nf: alpha_j, phi_j
+  const double ph = __shfl(xl, 2 * lane + 1, kWave);
+  double d = (lane < in.nf) ? ph * al * m.f_mmw[in.f0 + lane] : 0.0;
+#pragma unroll
+  for (int o = 1; o < kWave / 2; o <<= 1) {   // inclusive prefix sum over lanes 0..31
+    const double t = __shfl_up(d, o, kWave);
+    if (lane >= o) d += t;
+  }
+  const double aS = al * exp_cw(-(sigma * d));
+  const UndMap *umap = m.u_map + in.u0;
+  for (int i0 = 0; i0 < in.nu; i0 += kWave) {   // wave-uniform trip count: every lane shuffles
+    const int i = i0 + lane;
+    UndMap un{0, 0, 1, 0};
+    if (i < in.nu) un = umap[i];
+    const double ta = __shfl(aS, un.e, kWave);
+    const double tr = __shfl(ph, un.e, kWave);
+    if (i < in.nu) w.th[un.u] = und_const<FORMULA>(ta, tr, sigma, beta, um[un.u].fp);
+  }
+  wave_lds_sync();
+  return __any(bad);
+}
+
 // Cost of one point for the wave: f = sum_q w_q r_q^2, +inf on a domain
-// failure.  p[] is wave-uniform (GLOBAL4, LMM12); PERFWD reads the point
-// from the lanes instead (xl: lane k holds coordinate k).  Optional
+// failure.  p[] is wave-uniform (GLOBAL4, LMM12); PERFWD and MM read the
+// point from the lanes instead (xl: lane k holds coordinate k).  Optional
 // per-quote residual and model outputs (the quoted side in price mode).
 template <int MODEL, int FORMULA, int RESID>
 __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt *um,
@@ -294,8 +341,11 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
   } else if (MODEL == 1) {
     bad = lmm12_map<FORMULA>(m, in, um, p, w);
     omb = 1.0 - m.beta;
-  } else {
+  } else if (MODEL == 2) {
     bad = perfwd_map<FORMULA>(m, in, um, xl, w);
+    omb = 1.0 - m.beta;
+  } else {
+    bad = mm_map<FORMULA>(m, in, um, xl, w);
     omb = 1.0 - m.beta;
   }
   double acc = 0.0;

@@ -64,6 +64,7 @@ struct DevMarket {
   // forwards
   const double *f_T;     // fixing time T_k
   const double *f_v;     // tau_k P_k F_k^beta (fixed beta)
+  const double *f_mmw;   // MM drift weight T_{k-1} tau_k F_k^beta / (1 + tau_k F_k)
   // underlyings (caplet = one-period swap)
   const int *u_first, *u_len;
   const int *u_order;    // per instance: underlyings by decreasing length

@@ -22,6 +22,8 @@ configurations:
   (10..40 forwards x 5..15 strikes).
 * ``perfwd_markets``     -- equal-size caplet markets with per-forward
   (alpha, rho, nu) truths, for the PERFWD model.
+* ``mm_markets``         -- equal-size caplet markets with Mercurio-Morini
+  truths (alpha_i, phi_i per forward, one sigma).
 * ``paper_caplet_market`` -- not synthetic: the paper's own 6M EURIBOR
   caplet data of 21/11/2011 (13 forwards x 9 moneyness values, Sec. 4,
   Tables "Discount factor curve" and "Smiles of forward rates"), for the
@@ -39,6 +41,7 @@ import numpy as np
 MODEL_GLOBAL4 = 0
 MODEL_LMM12 = 1
 MODEL_PERFWD = 2
+MODEL_MM = 3
 FORMULA_HAGAN2002 = 0
 FORMULA_PAPER_EQ3 = 1
 RESID_VOL = 0
@@ -60,6 +63,8 @@ def rng(seed: int) -> np.random.Generator:
 def num_params(model: int, n_fwd: int | None = None) -> int:
     if model == MODEL_PERFWD:
         return 3 * int(n_fwd)
+    if model == MODEL_MM:
+        return 2 * int(n_fwd) + 1
     return 4 if model == MODEL_GLOBAL4 else 12
 
 
@@ -70,10 +75,15 @@ def box(model: int, n_fwd: int | None = None):
     synthetic true parameters.  PERFWD (n_fwd triples (alpha, rho, nu)):
     alpha in [0.001, 0.2] as for GLOBAL4, rho in [-0.99, 0.99], nu in
     [0.001, 1] (the printed sigma_1 = 1.0000 of Sec. 4.1.1 sits on that
-    bound)."""
+    bound).  MM (n_fwd pairs (alpha, phi), then sigma): alpha and phi as for
+    PERFWD, sigma in [0.001, 1]."""
     if model == MODEL_PERFWD:
         lb = np.tile([0.001, -0.99, 0.001], int(n_fwd))
         ub = np.tile([0.2, 0.99, 1.0], int(n_fwd))
+        return lb, ub
+    if model == MODEL_MM:
+        lb = np.concatenate([np.tile([0.001, -0.99], int(n_fwd)), [0.001]])
+        ub = np.concatenate([np.tile([0.2, 0.99], int(n_fwd)), [1.0]])
         return lb, ub
     if model == MODEL_GLOBAL4:
         lb = np.array([0.001, 0.0, -0.99, 0.001])
@@ -267,6 +277,23 @@ def perfwd_markets(seed=SEED_BASE + 6000, n_markets=3, M=13, nK=9, formula=FORMU
                                        g.uniform(0.2, 0.6, M)]).ravel())
         noises.append(g.normal(0.0, 0.002, M * nK))
     m = _finish(parts, MODEL_PERFWD, formula, residual, 0.5)
+    return m, np.array(truths), np.concatenate(noises)
+
+
+def mm_markets(seed=SEED_BASE + 7000, n_markets=3, M=13, nK=9, formula=FORMULA_HAGAN2002,
+               residual=RESID_VOL):
+    """Mercurio-Morini caplet markets (equal size: M forwards x nK strikes
+    each), true alpha_i ~ U[0.02, 0.05], phi_i ~ U[-0.5, 0], sigma ~
+    U[0.2, 0.6]; point layout (alpha_1, phi_1, ..., alpha_M, phi_M, sigma)."""
+    parts = _empty()
+    truths, noises = [], []
+    for j in range(n_markets):
+        g = rng(seed + j)
+        _append(parts, *_caplet_instance(g, M, nK))
+        pairs = np.column_stack([g.uniform(0.02, 0.05, M), g.uniform(-0.5, 0.0, M)]).ravel()
+        truths.append(np.concatenate([pairs, [g.uniform(0.2, 0.6)]]))
+        noises.append(g.normal(0.0, 0.002, M * nK))
+    m = _finish(parts, MODEL_MM, formula, residual, 0.5)
     return m, np.array(truths), np.concatenate(noises)
 
 

@@ -126,6 +126,23 @@ def paper_e2(chains=16384):
                                paper_nm_s=0.174, paper_evals=112738304, paper_mre=1.80e-2))
 
 
+def paper_mm(chains=16384):
+    """The paper's Mercurio-Morini caplet calibration (Sec. 4.2.1) replayed on
+    its printed data: MM (13 forwards, P = 27, beta = 0.5), eq.
+    (sigmaHagan), the same annealing settings as E2 (T0 = 10, Tmin = 0.01,
+    rho = 0.99, 688 levels, N = 10, 16384 chains: 112,738,304 cost
+    evaluations).  Printed for comparison: SA 9.124 s and Nelder-Mead
+    0.041 s on one GTX 470, MRE 3.11e-2."""
+    m = I.paper_caplet_market(model=I.MODEL_MM)
+    T0, T_min, cool = 10.0, 0.01, 0.99
+    return Workload("mm: the paper's EURIBOR caplets 13x9, Mercurio-Morini P=27, eq. "
+                    f"(sigmaHagan), {chains} chains, T0=10, Tmin=0.01, rho=0.99, N=10", m, None,
+                    None, chains=chains, n_levels=paper_levels(T0, T_min, cool), n_steps=10,
+                    seed=7, extra=dict(T0=T0, T_min=T_min, cool=cool, paper_sa_s=9.124,
+                                       paper_nm_s=0.041, paper_evals=112738304,
+                                       paper_mre=3.11e-2))
+
+
 CONFIGS = {"c1": config1, "c2": config2, "c3": config3, "c4": config4, "c5": config5}
 
 

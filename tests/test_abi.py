@@ -98,7 +98,7 @@ def test_plan_create_and_queries(L):
     (lambda m: m["und_first"].__setitem__(9, 10), "forward range"),
     (lambda m: m["q_kind"].__setitem__(4, 2), "kind"),
     (lambda m: m["q_w"].__setitem__(4, -1.0), "weight"),
-    (lambda m: m.__setitem__("model", 3), "model"),
+    (lambda m: m.__setitem__("model", 4), "model"),
     (lambda m: m.__setitem__("beta", 1.5), "beta"),
 ])
 def test_plan_rejects_bad_market(L, mutate, msg):

@@ -125,12 +125,13 @@ def test_max_params_accept_parity(api, oracle):
     lb, ub = I.box(I.MODEL_PERFWD, 21)
     lb2, ub2 = np.tile(lb, (2, 1)), np.tile(ub, (2, 1))
     x0 = np.clip(truth * 1.05, lb2, ub2)
-    kw = dict(T0=1.0, cool=0.7, n_levels=3, n_steps=7, seed=61, x0=x0,
-              T0_per_inst=np.array([1e-3, 1e-2]))
+    kw = dict(T0=1.0, cool=0.7, n_levels=3, n_steps=7, seed=61, x0=x0, step_frac=0.01,
+              T0_per_inst=np.array([0.01, 0.1]))
     chains = np.array([24, 9], np.int32)
     g = api.Plan(mk).sa(chains, lb2, ub2, record=True, chain_best=True, **kw)
     o = oracle.sa_calibrate(mk, chains, lb2, ub2, record=True, **kw)
     _sa_compare(g, o)
+    assert 0.0 < g["accept"].cpu().numpy().mean() < 1.0
 
 
 @pytest.mark.parametrize("waves,occ", [(4, 4), (1, 1)])
