@@ -266,16 +266,19 @@ def time_to_rmse(api, W, I, autotune):
     }
 
 
+NM_ITERS = 20000
+
+
 def paper_e2(api, W, I, flops, autotune, shape=None, which="e2"):
     """The paper's own timed caplet calibrations on its printed EURIBOR data
     (Sec. 4.1.1 and 4.2.1), eq. (sigmaHagan), SA with T0 = 10, Tmin = 0.01,
     rho = 0.99 (688 levels), N = 10, 16384 chains (112,738,304 cost
     evaluations).  which = "e2": the per-forward Hagan model (PERFWD, P = 39),
-    then LM on each forward as a GLOBAL4 instance with beta frozen at 0.5 (the
-    paper: Nelder-Mead).  which = "mm": the Mercurio-Morini model (P = 27),
-    annealing only (its cost does not separate per forward, and LM takes
-    GLOBAL4 and LMM12 plans).  Device time of the annealing (HIP events) and
-    wall time of the polish including its host-side re-layout; MRE = mean
+    then LM on each forward as a GLOBAL4 instance with beta frozen at 0.5.
+    which = "mm": the Mercurio-Morini model (P = 27).  Both are also polished
+    the paper's way, by Nelder-Mead on the whole point (sabr_nm_polish, at
+    most NM_ITERS iterations).  Device time of the annealing (HIP events) and
+    wall time of each polish including its host-side re-layout; MRE = mean
     |sigma_model - sigma_market| / sigma_market over the 117 quotes."""
     import torch
     w = W.paper_e2() if which == "e2" else W.paper_mm()
@@ -301,6 +304,11 @@ def paper_e2(api, W, I, flops, autotune, shape=None, which="e2"):
     inst4 = torch.arange(n_fwd, dtype=torch.int32, device="cuda")
     vol = np.asarray(mk["q_vol"])
 
+    def nm(x):
+        y, f, it = plan.nm(torch.tensor(x[None, :], device="cuda"), lb, ub, max_iter=NM_ITERS,
+                           tol=1e-12)
+        return y.cpu().numpy()[0], it.cpu().numpy()
+
     def polish(x):
         if which != "e2":
             return x, np.zeros(1, np.int32)
@@ -315,6 +323,7 @@ def paper_e2(api, W, I, flops, autotune, shape=None, which="e2"):
 
     r = plan.sa(w.chains, lb, ub, trace=False, **shape, **kw)        # warm-up
     polish(r["best_x"].cpu().numpy()[0])
+    nm(r["best_x"].cpu().numpy()[0])
     ws = r["workspace"]
     L = w.n_levels
     sampled = list(range(0, L, EVENT_STRIDE))
@@ -336,6 +345,10 @@ def paper_e2(api, W, I, flops, autotune, shape=None, which="e2"):
     t0 = time.perf_counter()
     x_pol, it = polish(x_sa)
     t_pol = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x_nm, it_nm = nm(x_sa)
+    t_nm = time.perf_counter() - t0
     lvl_ms = np.array([evs[2 * l].elapsed_time(evs[2 * l + 1]) for l in sampled])
     flop_launch = flops.level_launch_flops(mk, w.chains, w.n_steps)
     achieved = flop_launch / (float(lvl_ms.mean()) / 1e3) / 1e12
@@ -365,11 +378,16 @@ def paper_e2(api, W, I, flops, autotune, shape=None, which="e2"):
                   "cost_evaluations": w.extra["paper_evals"], "mre": w.extra["paper_mre"],
                   "hardware": "one GTX 470 (context, not a target)"},
     }
+    out.update({"t_nelder_mead_s": t_nm, "nelder_mead_iterations": int(it_nm[0]),
+                "mre_nelder_mead": mre(x_nm)})
     if which == "e2":
         out.update({"t_polish_s": t_pol, "polish_lm_iterations_max": int(it.max()),
                     "mre_polished": mre(x_pol), "params_polished": params})
     else:
-        out["params_sa"] = params
+        t = x_nm[:-1].reshape(-1, 2)
+        out["params_nelder_mead"] = {"alpha": t[:, 0].round(5).tolist(),
+                                     "phi": t[:, 1].round(4).tolist(),
+                                     "sigma": round(float(x_nm[-1]), 4)}
     return out
 
 

@@ -253,6 +253,27 @@ sabr_status sabr_lm_polish(const sabr_plan *plan, int32_t n_pts, const int32_t *
                            double mu0, double tol, double *cost_out, int32_t *iters_out,
                            void *workspace, size_t ws_bytes, void *stream);
 
+/* Device workspace bytes sabr_nm_polish needs (the box tables). */
+size_t sabr_nm_workspace_size(const sabr_plan *plan);
+
+/* Nelder-Mead polish of n_pts points in place: the local minimizer the paper
+ * runs on the annealing's result (Sec. 3), for every model.  Standard
+ * coefficients (reflection 1, expansion 2, contraction 1/2, shrink 1/2),
+ * every trial point clamped into [lb, ub]; initial simplex x0 and
+ * x0 + step (ub_k - lb_k) e_k (x0 - that step when it leaves the box);
+ * vertices ordered by cost (best: lowest index on ties; worst: highest);
+ * stop when f_worst - f_best <= tol |f_best| or after max_iter iterations.
+ * One wavefront per point with the simplex in LDS ((P + 1)(P + 2) doubles
+ * beside the cost's own LDS; SABR_EUNSUPPORTED if that exceeds the LDS of a
+ * workgroup).  params: [n_pts][P] device, in/out (the best vertex); lb, ub:
+ * [host][n_inst][P] with 0 < step <= 1; cost_out [n_pts] and iters_out
+ * [n_pts] (device, nullable): the best cost (NaN for an invalid pt_inst)
+ * and the iterations taken. */
+sabr_status sabr_nm_polish(const sabr_plan *plan, int32_t n_pts, const int32_t *pt_inst,
+                           double *params, const double *lb, const double *ub, int32_t max_iter,
+                           double step, double tol, double *cost_out, int32_t *iters_out,
+                           void *workspace, size_t ws_bytes, void *stream);
+
 /* Last error message of the calling thread ("" if none). */
 const char *sabr_last_error(void);
 

@@ -265,6 +265,23 @@ def sa_level0_sample(m, chains, lb, ub, T0, n_steps, seed, sample_inst, sample_c
     return dict(accept=acc, F=F, BF=BF, BX=BX)
 
 
+def nm_polish(m, params, pt_inst, lb, ub, max_iter=1000, step=0.05, tol=1e-12):
+    M = _mk(m)
+    P = M.P
+    x = np.ascontiguousarray(np.atleast_2d(params), dtype=np.float64).copy()
+    n = x.shape[0]
+    pt = np.zeros(n, np.int32) if pt_inst is None else np.ascontiguousarray(pt_inst, np.int32)
+    lb = np.ascontiguousarray(np.broadcast_to(lb, (M.n_inst, P)), dtype=np.float64)
+    ub = np.ascontiguousarray(np.broadcast_to(ub, (M.n_inst, P)), dtype=np.float64)
+    f = np.zeros(n)
+    it = np.zeros(n, np.int32)
+    _check(lib().oracle_nm_polish(ctypes.byref(M.s), n, _p(pt, _i32p), _p(x, _f64p),
+                                  _p(lb, _f64p), _p(ub, _f64p), int(max_iter),
+                                  ctypes.c_double(step), ctypes.c_double(tol), _p(f, _f64p),
+                                  _p(it, _i32p)))
+    return x, f, it
+
+
 def lm_polish(m, params, pt_inst, lb, ub, max_iter=50, mu0=1e-3, tol=1e-12):
     M = _mk(m)
     P = M.P

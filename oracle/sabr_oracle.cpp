@@ -748,6 +748,106 @@ void lm_one(const Inst &I, double *p, const double *lb, const double *ub, int ma
   *it_out = it;
 }
 
+// ---------------------------------------------------------------------------
+// Nelder-Mead polish of one point (the paper's local minimizer, Sec. 3, after
+// the annealing), in the standard form with reflection 1, expansion 2,
+// contraction 1/2 and shrink 1/2, every trial point clamped into the box.
+// Initial simplex: x0 and x0 + d_k e_k, d_k = step (ub_k - lb_k) (x0 - d_k
+// if that leaves the box).  Each iteration orders the vertices (best: lowest
+// cost, lowest index on ties; worst: highest cost, highest index on ties;
+// second worst likewise among the rest), stops when f_worst - f_best <=
+// tol |f_best|, and otherwise
+//   c = mean of the vertices other than the worst (summed in index order),
+//   x_r = c + (c - x_w):  f_r < f_b      -> x_e = c + 2 (c - x_w), keep the
+//                                           better of x_e and x_r;
+//                         f_r < f_sw     -> keep x_r;
+//                         f_r < f_w      -> x_c = c + (x_r - c)/2, keep it if
+//                                           f_c <= f_r, else shrink;
+//                         otherwise      -> x_c = c + (x_w - c)/2, keep it if
+//                                           f_c < f_w, else shrink;
+//   shrink: x_v <- x_b + (x_v - x_b)/2 for every v != b, re-evaluated.
+// Returns the best vertex, its cost and the iterations taken.
+// ---------------------------------------------------------------------------
+void nm_one(const Inst &I, int P, double *p, const double *lb, const double *ub, int max_iter,
+            double step, double tol, double *f_out, int *it_out) {
+  std::vector<std::vector<double>> S(P + 1, std::vector<double>(p, p + P));
+  std::vector<double> F(P + 1);
+  for (int k = 0; k < P; ++k) {
+    const double d = step * (ub[k] - lb[k]);
+    S[k + 1][k] = (p[k] + d <= ub[k]) ? p[k] + d : p[k] - d;
+  }
+  auto clampk = [&](double y, int k) { return std::min(std::max(y, lb[k]), ub[k]); };
+  for (int v = 0; v <= P; ++v) F[v] = cost_point<double>(I, S[v].data(), nullptr);
+  std::vector<double> c(P), xr(P), xe(P), xc(P);
+  int it = 0;
+  while (it < max_iter) {
+    int b = 0, w = 0;
+    for (int v = 1; v <= P; ++v) {
+      if (F[v] < F[b]) b = v;
+      if (F[v] >= F[w]) w = v;
+    }
+    int sw = (w == 0) ? 1 : 0;
+    for (int v = 0; v <= P; ++v)
+      if (v != w && F[v] >= F[sw]) sw = v;
+    if (F[w] - F[b] <= tol * std::fabs(F[b])) break;
+    ++it;
+    for (int k = 0; k < P; ++k) {
+      double sum = 0.0;
+      for (int v = 0; v <= P; ++v)
+        if (v != w) sum += S[v][k];
+      c[k] = sum / P;
+    }
+    for (int k = 0; k < P; ++k) xr[k] = clampk(c[k] + (c[k] - S[w][k]), k);
+    const double fr = cost_point<double>(I, xr.data(), nullptr);
+    bool shrink = false;
+    if (fr < F[b]) {
+      for (int k = 0; k < P; ++k) xe[k] = clampk(c[k] + 2.0 * (c[k] - S[w][k]), k);
+      const double fe = cost_point<double>(I, xe.data(), nullptr);
+      if (fe < fr) {
+        S[w] = xe;
+        F[w] = fe;
+      } else {
+        S[w] = xr;
+        F[w] = fr;
+      }
+    } else if (fr < F[sw]) {
+      S[w] = xr;
+      F[w] = fr;
+    } else if (fr < F[w]) {
+      for (int k = 0; k < P; ++k) xc[k] = clampk(c[k] + 0.5 * (xr[k] - c[k]), k);
+      const double fc = cost_point<double>(I, xc.data(), nullptr);
+      if (fc <= fr) {
+        S[w] = xc;
+        F[w] = fc;
+      } else {
+        shrink = true;
+      }
+    } else {
+      for (int k = 0; k < P; ++k) xc[k] = clampk(c[k] + 0.5 * (S[w][k] - c[k]), k);
+      const double fc = cost_point<double>(I, xc.data(), nullptr);
+      if (fc < F[w]) {
+        S[w] = xc;
+        F[w] = fc;
+      } else {
+        shrink = true;
+      }
+    }
+    if (shrink) {
+      for (int v = 0; v <= P; ++v) {
+        if (v == b) continue;
+        for (int k = 0; k < P; ++k) S[v][k] = S[b][k] + 0.5 * (S[v][k] - S[b][k]);
+        F[v] = cost_point<double>(I, S[v].data(), nullptr);
+      }
+    }
+  }
+  int b = 0;
+  for (int v = 1; v <= P; ++v)
+    if (F[v] < F[b]) b = v;
+  for (int k = 0; k < P; ++k) p[k] = S[b][k];
+  *f_out = F[b];
+  *it_out = it;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1097,6 +1197,30 @@ int32_t oracle_lm_polish(const oracle_market *m, int32_t n_pts, const int32_t *p
     else
       lm_one<12>(I, params + (size_t)i * 12, lb + (size_t)inst * 12, ub + (size_t)inst * 12,
                  max_iter, mu0, tol, &f, &it);
+    if (cost_out) cost_out[i] = f;
+    if (iters_out) iters_out[i] = it;
+  }
+  return 0;
+}
+
+int32_t oracle_nm_polish(const oracle_market *m, int32_t n_pts, const int32_t *pt_inst,
+                         double *params, const double *lb, const double *ub, int32_t max_iter,
+                         double step, double tol, double *cost_out, int32_t *iters_out) {
+  if (!m) return fail("null market");
+  std::vector<Inst> insts(m->n_inst);
+  for (int i = 0; i < m->n_inst; ++i)
+    if (build_inst(m, i, insts[i])) return -1;
+  const int P = market_params(m);
+  if (P < 0) return fail("unknown model or PERFWD instances of unequal size");
+  for (int i = 0; i < n_pts; ++i)
+    if (pt_inst[i] < 0 || pt_inst[i] >= m->n_inst) return fail("point instance out of range");
+#pragma omp parallel for schedule(dynamic)
+  for (int i = 0; i < n_pts; ++i) {
+    const int inst = pt_inst[i];
+    double f;
+    int it;
+    nm_one(insts[inst], P, params + (size_t)i * P, lb + (size_t)inst * P, ub + (size_t)inst * P,
+           max_iter, step, tol, &f, &it);
     if (cost_out) cost_out[i] = f;
     if (iters_out) iters_out[i] = it;
   }

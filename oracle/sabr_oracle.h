@@ -135,6 +135,14 @@ int32_t oracle_lm_polish(const oracle_market *m, int32_t n_pts, const int32_t *p
                          int32_t max_iter, double mu0, double tol, double *cost_out,
                          int32_t *iters_out);
 
+/* Nelder-Mead polish in place (reflection 1, expansion 2, contraction 1/2,
+ * shrink 1/2, trial points clamped into the box; initial simplex x0 and
+ * x0 + step (ub_k - lb_k) e_k; stop when f_worst - f_best <= tol |f_best|
+ * or after max_iter iterations).  Every model. */
+int32_t oracle_nm_polish(const oracle_market *m, int32_t n_pts, const int32_t *pt_inst,
+                         double *params, const double *lb, const double *ub, int32_t max_iter,
+                         double step, double tol, double *cost_out, int32_t *iters_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,11 @@ def lib():
     L.sabr_lm_polish.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _f64p, _f64p, ctypes.c_int32,
                                  ctypes.c_double, ctypes.c_double, _vp, _vp, _vp,
                                  ctypes.c_size_t, _vp]
+    L.sabr_nm_workspace_size.argtypes = [_vp]
+    L.sabr_nm_workspace_size.restype = ctypes.c_size_t
+    L.sabr_nm_polish.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _f64p, _f64p, ctypes.c_int32,
+                                 ctypes.c_double, ctypes.c_double, _vp, _vp, _vp,
+                                 ctypes.c_size_t, _vp]
     _lib = L
     return _lib
 

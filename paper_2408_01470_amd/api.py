@@ -228,6 +228,25 @@ class Plan:
                                    _stream(stream)))
         return x, cost, iters
 
+    def nm(self, params, lb, ub, pt_inst=None, max_iter=1000, step=0.05, tol=1e-12, stream=None,
+           workspace=None):
+        """Nelder-Mead polish (the paper's local minimizer, every model);
+        returns (params, cost, iterations)."""
+        params, pt_inst, n = self._pts(params, pt_inst)
+        x = params.clone()
+        lb = np.ascontiguousarray(np.broadcast_to(lb, (self.n_inst, self.P)), dtype=np.float64)
+        ub = np.ascontiguousarray(np.broadcast_to(ub, (self.n_inst, self.P)), dtype=np.float64)
+        cost = torch.empty(n, dtype=torch.float64, device=self.device)
+        iters = torch.empty(n, dtype=torch.int32, device=self.device)
+        need = int(lib().sabr_nm_workspace_size(self._h))
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        check(lib().sabr_nm_polish(self._h, n, _ptr(pt_inst), _ptr(x), lb.ctypes.data_as(_f64p),
+                                   ub.ctypes.data_as(_f64p), int(max_iter), float(step),
+                                   float(tol), _ptr(cost), _ptr(iters), _ptr(workspace),
+                                   workspace.numel(), _stream(stream)))
+        return x, cost, iters
+
 
 class SabrCost(torch.autograd.Function):
     """cost = f(params) through sabr_cost_batch; backward through the

@@ -1,5 +1,6 @@
-// sabr_adjoint.hpp -- launch interface of the adjoint and Levenberg-Marquardt
-// kernels (sabr_adjoint.hip).  Not part of the public ABI.
+// sabr_adjoint.hpp -- launch interface of the polish kernels: the adjoint and
+// Levenberg-Marquardt kernels (sabr_adjoint.hip) and the Nelder-Mead kernel
+// (sabr_nm.hip).  Not part of the public ABI.
 #pragma once
 #include "sabr_internal.hpp"
 
@@ -20,5 +21,11 @@ hipError_t launch_vjp(const DevMarket &m, int n_pts, const int *pt_inst, const d
 hipError_t launch_lm(const DevMarket &m, int n_pts, const int *pt_inst, double *params,
                      const double *lb, const double *ub, int max_iter, double mu0, double tol,
                      double *cost_out, int *iters_out, double *scratch, hipStream_t s);
+
+// Nelder-Mead: one wave per point, the simplex in LDS.
+size_t nm_lds_bytes(const DevMarket &m);
+hipError_t launch_nm(const DevMarket &m, int n_pts, const int *pt_inst, double *params,
+                     const double *lb, const double *ub, int max_iter, double step, double tol,
+                     double *cost_out, int *iters_out, hipStream_t s);
 
 }  // namespace sabr

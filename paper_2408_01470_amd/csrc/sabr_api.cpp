@@ -73,7 +73,7 @@ struct sabr_plan {
   char *dev = nullptr;
   DevMarket dm{};
   // host staging of per-call tables (kept until the next call)
-  std::vector<unsigned char> sa_staging, lm_staging;
+  std::vector<unsigned char> sa_staging, lm_staging, nm_staging;
   std::mutex mu;
   hipGraphExec_t graph_exec = nullptr;
   std::vector<uint64_t> graph_key;
@@ -720,6 +720,52 @@ sabr_status sabr_lm_polish(const sabr_plan *Pc, int32_t n_pts, const int32_t *pt
                       reinterpret_cast<const double *>(w + A.o_ub), max_iter, mu0, tol, cost_out,
                       iters_out, reinterpret_cast<double *>(w + A.o_scratch), s);
   if (e != hipSuccess) return hip_fail(e, "LM launch");
+  return SABR_OK;
+}
+
+size_t sabr_nm_workspace_size(const sabr_plan *P) {
+  if (!P) return 0;
+  Layout L;
+  L.take<double>((size_t)P->n_inst * P->np);
+  L.take<double>((size_t)P->n_inst * P->np);
+  return L.off;
+}
+
+sabr_status sabr_nm_polish(const sabr_plan *Pc, int32_t n_pts, const int32_t *pt_inst,
+                           double *params, const double *lb, const double *ub, int32_t max_iter,
+                           double step, double tol, double *cost_out, int32_t *iters_out,
+                           void *workspace, size_t ws_bytes, void *stream) {
+  sabr_status st = check_points(Pc, n_pts);
+  if (st != SABR_OK) return st;
+  if (n_pts == 0) return SABR_OK;
+  if (!pt_inst || !params || !lb || !ub) return fail(SABR_EINVAL, "null argument");
+  if (max_iter < 0 || !(step > 0.0 && step <= 1.0) || !(tol >= 0.0))
+    return fail(SABR_EINVAL, "bad Nelder-Mead settings");
+  sabr_plan *P = const_cast<sabr_plan *>(Pc);
+  const int Pn = P->np;
+  for (int i = 0; i < P->n_inst * Pn; ++i)
+    if (!std::isfinite(lb[i]) || !std::isfinite(ub[i]) || !(lb[i] <= ub[i]))
+      return fail(SABR_EINVAL, "box bound " + std::to_string(i) + ": need finite lb <= ub");
+  const size_t need = sabr_nm_workspace_size(P);
+  if (!workspace || ws_bytes < need) return fail(SABR_EWORKSPACE, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(SABR_EINVAL, "workspace not 256-byte aligned");
+  if (sabr::nm_lds_bytes(P->dm) > 160 * 1024) return fail(SABR_EUNSUPPORTED, "simplex does not fit in LDS");
+  Layout L;
+  const size_t o_lb = L.take<double>((size_t)P->n_inst * Pn);
+  const size_t o_ub = L.take<double>((size_t)P->n_inst * Pn);
+  char *w = static_cast<char *>(workspace);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> guard(P->mu);
+  std::vector<unsigned char> &stg = P->nm_staging;
+  stg.assign(L.off, 0);
+  std::memcpy(stg.data() + o_lb, lb, sizeof(double) * P->n_inst * Pn);
+  std::memcpy(stg.data() + o_ub, ub, sizeof(double) * P->n_inst * Pn);
+  hipError_t e = hipMemcpyAsync(w, stg.data(), L.off, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "Nelder-Mead box upload");
+  e = sabr::launch_nm(P->dm, n_pts, pt_inst, params, reinterpret_cast<const double *>(w + o_lb),
+                      reinterpret_cast<const double *>(w + o_ub), max_iter, step, tol, cost_out,
+                      iters_out, s);
+  if (e != hipSuccess) return hip_fail(e, "Nelder-Mead launch");
   return SABR_OK;
 }
 
