@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-paper-e2", action="store_true",
                     help="skip the replay of the paper's timed caplet calibration")
     ap.add_argument("--paper-e2-only", action="store_true")
+    ap.add_argument("--paper-reb-only", action="store_true",
+                    help="replay the paper's Rebonato caplet calibration (2.25e9 evaluations)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the cost / adjoint / LM measurement (one JSON line)")
     ap.add_argument("--waves", type=int, default=None,
@@ -281,7 +283,7 @@ def paper_e2(api, W, I, flops, autotune, shape=None, which="e2"):
     wall time of each polish including its host-side re-layout; MRE = mean
     |sigma_model - sigma_market| / sigma_market over the 117 quotes."""
     import torch
-    w = W.paper_e2() if which == "e2" else W.paper_mm()
+    w = {"e2": W.paper_e2, "mm": W.paper_mm, "reb": W.paper_reb}[which]()
     mk = w.market
     plan = api.Plan(mk)
     tuning = None
@@ -321,7 +323,8 @@ def paper_e2(api, W, I, flops, autotune, shape=None, which="e2"):
         mv = mv.cpu().numpy()[0, :len(vol)]
         return float(np.mean(np.abs(mv - vol) / vol))
 
-    r = plan.sa(w.chains, lb, ub, trace=False, **shape, **kw)        # warm-up
+    warm = dict(kw, n_levels=2) if which == "reb" else kw   # the long replay warms on 2 levels
+    r = plan.sa(w.chains, lb, ub, trace=False, **shape, **warm)        # warm-up
     polish(r["best_x"].cpu().numpy()[0])
     nm(r["best_x"].cpu().numpy()[0])
     ws = r["workspace"]
@@ -358,9 +361,7 @@ def paper_e2(api, W, I, flops, autotune, shape=None, which="e2"):
         params = {"alpha": t[:, 0].round(5).tolist(), "phi": t[:, 1].round(4).tolist(),
                   "sigma": t[:, 2].round(4).tolist()}
     else:
-        t = x_pol[:-1].reshape(-1, 2)
-        params = {"alpha": t[:, 0].round(5).tolist(), "phi": t[:, 1].round(4).tolist(),
-                  "sigma": round(float(x_pol[-1]), 4)}
+        params = None
     out = {
         "workload": w.name,
         "cost_evaluations": evals,
@@ -374,20 +375,29 @@ def paper_e2(api, W, I, flops, autotune, shape=None, which="e2"):
         "cost_sa": float(r["best_f"].item()),
         "launch_shape": shape,
         "tuning_level_ms": tuning,
-        "paper": {"t_sa_s": w.extra["paper_sa_s"], "t_nelder_mead_s": w.extra["paper_nm_s"],
+        "paper": {"t_sa_s": w.extra["paper_sa_s"],
+                  "t_nelder_mead_s": w.extra.get("paper_nm_s"),
+                  "t_total_s": w.extra.get("paper_total_s"),
                   "cost_evaluations": w.extra["paper_evals"], "mre": w.extra["paper_mre"],
-                  "hardware": "one GTX 470 (context, not a target)"},
+                  "hardware": ("two GTX 470" if which == "reb" else "one GTX 470")
+                  + " (context, not a target)"},
     }
     out.update({"t_nelder_mead_s": t_nm, "nelder_mead_iterations": int(it_nm[0]),
                 "mre_nelder_mead": mre(x_nm)})
     if which == "e2":
         out.update({"t_polish_s": t_pol, "polish_lm_iterations_max": int(it.max()),
                     "mre_polished": mre(x_pol), "params_polished": params})
-    else:
+    elif which == "mm":
         t = x_nm[:-1].reshape(-1, 2)
         out["params_nelder_mead"] = {"alpha": t[:, 0].round(5).tolist(),
                                      "phi": t[:, 1].round(4).tolist(),
                                      "sigma": round(float(x_nm[-1]), 4)}
+    else:
+        t = x_nm[:-8].reshape(-1, 2)
+        out["params_nelder_mead"] = {"kappa": t[:, 0].round(5).tolist(),
+                                     "phi": t[:, 1].round(4).tolist(),
+                                     "g_abcd": x_nm[-8:-4].round(4).tolist(),
+                                     "h_abcd": x_nm[-4:].round(4).tolist()}
     return out
 
 
@@ -412,6 +422,9 @@ def main():
     if args.paper_e2_only:
         print(json.dumps(paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape)))
         print(json.dumps(paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape, "mm")))
+        return
+    if args.paper_reb_only:
+        print(json.dumps(paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape, "reb")))
         return
     w = W.CONFIGS[args.config]()
     if args.levels is not None:

@@ -88,12 +88,26 @@ typedef enum {
  *           Caplet markets only; every instance holds the same number
  *           n <= 31 of forwards, P = 2 n + 1.  Domain: alpha_j > 0,
  *           |phi_j| < 1, sigma >= 0.  The adjoint and LM entry points return
- *           SABR_EUNSUPPORTED for it. */
+ *           SABR_EUNSUPPORTED for it.
+ *  REB:     p = (kappa_1, phi_1, ..., kappa_n, phi_n, a, b, c, d, a_h, b_h,
+ *           c_h, d_h), beta fixed: the Rebonato model of Sec. 2.2 (x = (phi_ii,
+ *           kappa_i, the parameters of g and h)) with the SABR parameters of
+ *           eq. (haganForRebonato) for the caplet on forward i, expiry T:
+ *             alpha_i = kappa_i sqrt(G / T), G = int_0^T g_i(t)^2 dt,
+ *             nu_i = sqrt(2 J / (T G)), J = int_0^T g_i(t)^2 H_i(t) dt,
+ *             H_i(t) = int_0^t h_i(s)^2 ds, rho_i = phi_i,
+ *           g_i(t) = (a + b (T - t)) e^{-c (T - t)} + d, h_i likewise; G and
+ *           H in closed form, J by the 32-point Gauss-Legendre rule.
+ *           Caplet markets only; every instance holds the same number
+ *           n <= 27 of forwards, P = 2 n + 8.  Domain: kappa_i > 0,
+ *           |phi_i| < 1, c >= 0, c_h >= 0, G > 0.  The adjoint and LM entry
+ *           points return SABR_EUNSUPPORTED for it. */
 typedef enum {
   SABR_MODEL_GLOBAL4 = 0,
   SABR_MODEL_LMM12 = 1,
   SABR_MODEL_PERFWD = 2,
-  SABR_MODEL_MM = 3
+  SABR_MODEL_MM = 3,
+  SABR_MODEL_REB = 4
 } sabr_model;
 
 /* Implied-vol formula.
@@ -138,8 +152,8 @@ typedef struct sabr_plan sabr_plan; /* opaque; host memory only */
 
 /* Validate the market (offsets monotone and in range, positive finite
  * forwards, strikes, accruals, discounts and vols, non-negative weights,
- * positive expiries, quotes sorted by underlying, GLOBAL4, PERFWD and MM
- * without swaps, PERFWD and MM instances of equal size) and
+ * positive expiries, quotes sorted by underlying, swaps in LMM12 markets
+ * only, PERFWD, MM and REB instances of equal size) and
  * build its packed image.  On success *out owns host memory only. */
 sabr_status sabr_plan_create(const sabr_problem *prob /*[host]*/, sabr_plan **out /*[host]*/);
 void sabr_plan_destroy(sabr_plan *plan);
@@ -152,8 +166,9 @@ size_t sabr_plan_device_bytes(const sabr_plan *plan);
  * market prices and vegas in price mode).  The plan keeps dev_buf. */
 sabr_status sabr_plan_upload(sabr_plan *plan, void *dev_buf, size_t bytes, void *stream);
 
-int32_t sabr_num_params(int32_t model);  /* 4 or 12; -1 if unknown, PERFWD or MM */
-int32_t sabr_plan_num_params(const sabr_plan *plan); /* P of the plan (PERFWD 3 n, MM 2 n + 1) */
+int32_t sabr_num_params(int32_t model);  /* 4 or 12; -1 if unknown, PERFWD, MM or REB */
+/* P of the plan (PERFWD 3 n, MM 2 n + 1, REB 2 n + 8) */
+int32_t sabr_plan_num_params(const sabr_plan *plan);
 int32_t sabr_plan_num_inst(const sabr_plan *plan);
 int32_t sabr_plan_max_quotes(const sabr_plan *plan); /* largest quotes per instance */
 
@@ -233,7 +248,7 @@ size_t sabr_adjoint_workspace_size(const sabr_plan *plan, int32_t n_pts);
  * d cost/d p = 2 J^T W r.  Out-of-domain points give cost +inf and zero
  * derivatives.  The derivative of the cost follows from the paper's f_c and
  * f_s (Sec. 3); the paper itself polishes with Nelder-Mead and has no
- * gradient.  GLOBAL4 and LMM12 plans (PERFWD, MM: SABR_EUNSUPPORTED). */
+ * gradient.  GLOBAL4 and LMM12 plans (PERFWD, MM, REB: SABR_EUNSUPPORTED). */
 sabr_status sabr_cost_vjp(const sabr_plan *plan, int32_t n_pts, const int32_t *pt_inst,
                           const double *params, const double *g_cost, double *cost,
                           double *g_params, double *jtwj, double *jtwr, void *workspace,
@@ -247,7 +262,7 @@ sabr_status sabr_cost_vjp(const sabr_plan *plan, int32_t n_pts, const int32_t *p
  * A zero diagonal entry is replaced by 1; coordinates with lb = ub, or on a
  * bound that -J^T W r points out of, are frozen for the iteration.  lb, ub:
  * [host][n_inst][P].  cost_out [n_pts] and iters_out [n_pts] nullable.
- * GLOBAL4 and LMM12 plans (PERFWD, MM: SABR_EUNSUPPORTED). */
+ * GLOBAL4 and LMM12 plans (PERFWD, MM, REB: SABR_EUNSUPPORTED). */
 sabr_status sabr_lm_polish(const sabr_plan *plan, int32_t n_pts, const int32_t *pt_inst,
                            double *params, const double *lb, const double *ub, int32_t max_iter,
                            double mu0, double tol, double *cost_out, int32_t *iters_out,

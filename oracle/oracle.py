@@ -96,7 +96,7 @@ class Market:
         self.model = int(m["model"])
         fo = a["fwd_off"]
         nf = int(fo[1] - fo[0]) if len(fo) > 1 else -1
-        self.P = {0: 4, 1: 12, 2: 3 * nf, 3: 2 * nf + 1}.get(self.model, -1)
+        self.P = {0: 4, 1: 12, 2: 3 * nf, 3: 2 * nf + 1, 4: 2 * nf + 8}.get(self.model, -1)
         self.nq = np.diff(a["q_off"])
         self.nu = np.diff(a["und_off"])
         self.s = OracleMarket(

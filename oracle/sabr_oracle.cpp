@@ -259,7 +259,7 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 int32_t build_inst(const oracle_market *m, int i, Inst &I) {
   if (!m) return fail("null market");
   if (i < 0 || i >= m->n_inst) return fail("instance index out of range");
-  if (m->model < 0 || m->model > 3) return fail("unknown model");
+  if (m->model < 0 || m->model > 4) return fail("unknown model");
   if (m->formula < 0 || m->formula > 1) return fail("unknown vol formula");
   if (m->residual < 0 || m->residual > 1) return fail("unknown residual mode");
   I.model = m->model;
@@ -287,7 +287,7 @@ int32_t build_inst(const oracle_market *m, int i, Inst &I) {
     U.first = m->und_first[k];
     U.len = m->und_len[k];
     if (U.len < 1 || U.first < 0 || U.first + U.len > nf) return fail("bad underlying range");
-    if (m->model != 1 && U.len != 1) return fail("GLOBAL4, PERFWD and MM markets hold caplets only");
+    if (m->model != 1 && U.len != 1) return fail("only LMM12 markets hold swaptions");
     U.A = 0.0;
     for (int j = U.first; j < U.first + U.len; ++j) U.A += I.f[j].tau * I.f[j].P;
     U.S0 = 0.0;
@@ -339,13 +339,84 @@ int num_params(int model) { return model == 0 ? 4 : (model == 1 ? 12 : -1); }
 // per forward plus one for MM.  PERFWD and MM instances must all hold the
 // same number of forwards; -1 otherwise.
 int market_params(const oracle_market *m) {
-  if (m->model != 2 && m->model != 3) return num_params(m->model);
+  if (m->model < 2) return num_params(m->model);
+  if (m->model > 4) return -1;
   if (m->n_inst < 1) return -1;
   const int nf = m->fwd_off[1] - m->fwd_off[0];
   for (int i = 1; i < m->n_inst; ++i)
     if (m->fwd_off[i + 1] - m->fwd_off[i] != nf) return -1;
   if (nf < 1) return -1;
-  return m->model == 2 ? 3 * nf : 2 * nf + 1;
+  return m->model == 2 ? 3 * nf : (m->model == 3 ? 2 * nf + 1 : 2 * nf + 8);
+}
+
+// ---------------------------------------------------------------------------
+// Helpers of the Rebonato map.
+// Moments I_m(k, x) = int_0^x u^m e^{-k u} du, m = 0, 1, 2, k >= 0: the
+// series x^{m+1} sum_j (-kx)^j / (j! (m + j + 1)) for kx < 1/2, else
+//   I_0 = (1 - e)/k, I_1 = (1 - e (1 + z))/k^2, I_2 = 2 (1 - e (1 + z + z^2/2))/k^3,
+// e = exp(-z), z = kx.
+// ---------------------------------------------------------------------------
+template <class S>
+void exp_moments(const S &k, double x, S I[3]) {
+  const S z = k * x;
+  if (val(z) < 0.5) {
+    S term(1.0), s0(0.0), s1(0.0), s2(0.0);
+    for (int j = 0; j < 40; ++j) {
+      s0 += term / double(j + 1);
+      s1 += term / double(j + 2);
+      s2 += term / double(j + 3);
+      term = term * (-z) / double(j + 1);
+    }
+    I[0] = s0 * x;
+    I[1] = s1 * (x * x);
+    I[2] = s2 * (x * x * x);
+  } else {
+    const S e = exp(-z);
+    I[0] = (1.0 - e) / k;
+    I[1] = (1.0 - e * (1.0 + z)) / (k * k);
+    I[2] = 2.0 * (1.0 - e * (1.0 + z + 0.5 * z * z)) / (k * k * k);
+  }
+}
+
+// int_0^x ((a + b u) e^{-c u} + d)^2 du
+template <class S>
+S abcd_square_integral(const S &a, const S &b, const S &c, const S &d, double x) {
+  S I2[3], I1[3];
+  exp_moments(2.0 * c, x, I2);
+  exp_moments(c, x, I1);
+  return a * a * I2[0] + 2.0 * a * b * I2[1] + b * b * I2[2] +
+         2.0 * d * (a * I1[0] + b * I1[1]) + d * d * x;
+}
+
+// Nodes and weights of the 64-point Gauss-Legendre rule on [-1, 1]: roots of
+// P_64 by Newton's method from cos(pi (k - 1/4) / (64 + 1/2)), weights
+// 2 / ((1 - x^2) P_64'(x)^2).
+struct GaussLegendre64 {
+  double x[64], w[64];
+  GaussLegendre64() {
+    const int n = 64;
+    for (int k = 1; k <= n; ++k) {
+      double t = std::cos(M_PI * (k - 0.25) / (n + 0.5)), dp = 0.0;
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = t;   // P_0, P_1, then the three-term recurrence
+        for (int j = 2; j <= n; ++j) {
+          const double p2 = ((2.0 * j - 1.0) * t * p1 - (j - 1.0) * p0) / j;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = n * (t * p1 - p0) / (t * t - 1.0);
+        const double step = p1 / dp;
+        t -= step;
+        if (std::fabs(step) < 1e-16) break;
+      }
+      x[k - 1] = t;
+      w[k - 1] = 2.0 / ((1.0 - t * t) * dp * dp);
+    }
+  }
+};
+const GaussLegendre64 &gl64() {
+  static const GaussLegendre64 g;
+  return g;
 }
 
 // ---------------------------------------------------------------------------
@@ -372,6 +443,18 @@ int market_params(const oracle_market *m) {
 //      c_j = tau_j phi_j alpha_j F_j^beta / (1 + tau_j F_j).
 //    Every (alpha_j, phi_j) must lie in the domain (alpha > 0, |phi| < 1),
 //    and sigma >= 0.
+//  REB: p = (kappa_1, phi_1, ..., kappa_n, phi_n, a, b, c, d, a_h, b_h, c_h,
+//    d_h), beta fixed: the Rebonato model of Sec. 2.2, x = (phi_ii, kappa_i,
+//    the parameters of g and h), with the SABR parameters of eq.
+//    (haganForRebonato) for the caplet on forward i (expiry T = T_i):
+//      alpha_i = kappa_i sqrt(G / T),  G = int_0^T g_i(t)^2 dt,
+//      nu_i = sqrt(2 J / (T G)),  J = int_0^T g_i(t)^2 H_i(t) dt,
+//      H_i(t) = int_0^t h_i(s)^2 ds = t hhat_i(t)^2,  rho_i = phi_i,
+//    g_i(t) = (a + b (T - t)) e^{-c (T - t)} + d and h_i likewise in the h
+//    parameters.  With tau = T - t: G = Qg(T) and J = int_0^T g(tau)^2
+//    (Qh(T) - Qh(tau)) dtau, Q(x) the closed-form square integral of the
+//    abcd function over [0, x]; J by the 64-point Gauss-Legendre rule.
+//    Domain: kappa_i > 0, |phi_i| < 1, c >= 0, c_h >= 0, G > 0.
 //  LMM12: p = (a, b, c, d, a_n, b_n, c_n, d_n, rho, lambda1, eta2, lambda2),
 //    beta fixed.  alpha_i = (a + b T_i) e^{-c T_i} + d and
 //    nu_i = (a_n + b_n T_i) e^{-c_n T_i} + d_n are the abcd forms of Sec. 2.3
@@ -399,6 +482,31 @@ bool map_params(const Inst &I, const S *p, std::vector<Theta<S>> &th) {
         !(std::fabs(val(rho)) < 1.0) || !(val(nu) >= 0.0))
       return false;
     for (size_t u = 0; u < I.u.size(); ++u) th[u] = Theta<S>{alpha, beta, rho, nu};
+    return true;
+  }
+  if (I.model == 4) {
+    const size_t nf = I.f.size();
+    const S *q = p + 2 * nf;   // a, b, c, d, a_h, b_h, c_h, d_h
+    if (!(val(q[2]) >= 0.0) || !(val(q[6]) >= 0.0)) return false;
+    for (size_t k = 0; k < nf; ++k)
+      if (!(val(p[2 * k]) > 0.0) || !(std::fabs(val(p[2 * k + 1])) < 1.0)) return false;
+    const GaussLegendre64 &gl = gl64();
+    for (size_t u = 0; u < I.u.size(); ++u) {
+      const int k = I.u[u].first;
+      const double T = I.u[u].Te;
+      const S G = abcd_square_integral(q[0], q[1], q[2], q[3], T);
+      const S QT = abcd_square_integral(q[4], q[5], q[6], q[7], T);
+      S J(0.0);
+      for (int j = 0; j < 64; ++j) {
+        const double tau = 0.5 * T * (1.0 + gl.x[j]);
+        const S g = (q[0] + q[1] * tau) * exp(-(q[2] * tau)) + q[3];
+        J += (0.5 * T * gl.w[j]) * (g * g) * (QT - abcd_square_integral(q[4], q[5], q[6], q[7], tau));
+      }
+      if (!(val(G) > 0.0) || !(val(J) >= 0.0)) return false;
+      const S alpha = p[2 * k] * sqrt(G / T);
+      const S nu = sqrt(2.0 * J / (T * G));
+      th[u] = Theta<S>{alpha, S(I.beta), p[2 * k + 1], nu};
+    }
     return true;
   }
   if (I.model == 3) {

@@ -45,17 +45,18 @@ typedef struct {
   const int32_t *q_off;                   /* [n_inst+1] */
   const int32_t *q_und, *q_kind;          /* underlying, 0 = call/payer, 1 = put/receiver */
   const double *q_K, *q_vol, *q_w;        /* strike, market implied vol, user weight */
-  int32_t model;                          /* 0 = GLOBAL4, 1 = LMM12, 2 = PERFWD, 3 = MM */
+  int32_t model;                          /* 0 GLOBAL4, 1 LMM12, 2 PERFWD, 3 MM, 4 REB */
   int32_t formula;                        /* 0 = Hagan 2002, 1 = paper eq. (sigmaHagan) */
   int32_t residual;                       /* 0 = vol residuals, 1 = Black price residuals */
-  double beta;                            /* fixed beta (LMM12, PERFWD, MM) */
+  double beta;                            /* fixed beta (all but GLOBAL4) */
 } oracle_market;
 
 const char *oracle_last_error(void);
 int32_t oracle_num_params(int32_t model);
 /* Parameters per point of a market (3 per forward for PERFWD, 2 per forward
- * plus one for MM, whose instances must hold equally many forwards); -1 if
- * invalid.  Gradients and LM take GLOBAL4 and LMM12 markets only. */
+ * plus one for MM, 2 per forward plus 8 for REB, whose instances must hold
+ * equally many forwards); -1 if invalid.  Gradients and LM take GLOBAL4 and
+ * LMM12 markets only. */
 int32_t oracle_market_num_params(const oracle_market *m);
 /* OpenMP threads of the calls below (n > 0); for timing on one core. */
 void oracle_set_threads(int32_t n);

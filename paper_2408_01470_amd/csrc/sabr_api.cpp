@@ -92,7 +92,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   if (!pr || !out) return fail(SABR_EINVAL, "null argument");
   *out = nullptr;
   if (pr->n_inst < 1) return fail(SABR_EINVAL, "n_inst must be >= 1");
-  if (pr->model < 0 || pr->model > 3) return fail(SABR_EINVAL, "unknown model");
+  if (pr->model < 0 || pr->model > 4) return fail(SABR_EINVAL, "unknown model");
   if (pr->vol_formula < 0 || pr->vol_formula > 1) return fail(SABR_EINVAL, "unknown formula");
   if (pr->residual < 0 || pr->residual > 1) return fail(SABR_EINVAL, "unknown residual mode");
   if (!(pr->beta >= 0.0 && pr->beta <= 1.0)) return fail(SABR_EINVAL, "beta outside [0, 1]");
@@ -114,22 +114,24 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   P->residual = pr->residual;
   P->beta = pr->beta;
   P->np = sabr_num_params(pr->model);
-  if (pr->model == 2 || pr->model == 3) {
+  if (pr->model >= 2) {
     // PERFWD: one (alpha, rho, nu) per forward; MM: one (alpha, phi) per
-    // forward and sigma.  Lanes k < P of a wave hold the point next to the
-    // Metropolis uniform, so every instance has the same nf with P <= 63.
-    const char *name = pr->model == 2 ? "PERFWD" : "MM";
+    // forward and sigma; REB: one (kappa, phi) per forward and the eight
+    // parameters of g and h.  Lanes k < P of a wave hold the point next to
+    // the Metropolis uniform, so every instance has the same nf with P <= 63.
+    const char *name = pr->model == 2 ? "PERFWD" : (pr->model == 3 ? "MM" : "REB");
     const int nf = pr->fwd_off[1] - pr->fwd_off[0];
     for (int i = 1; i < n; ++i)
       if (pr->fwd_off[i + 1] - pr->fwd_off[i] != nf) {
         delete P;
         return fail(SABR_EINVAL, std::string(name) + " instances must hold equally many forwards");
       }
-    const int np = pr->model == 2 ? 3 * nf : 2 * nf + 1;
+    const int np = pr->model == 2 ? 3 * nf : (pr->model == 3 ? 2 * nf + 1 : 2 * nf + 8);
     if (nf < 1 || np > sabr::kWave - 1) {
       delete P;
-      return fail(SABR_EINVAL, std::string(name) + (pr->model == 2 ? " needs 1..21 forwards per instance"
-                                                                   : " needs 1..31 forwards per instance"));
+      const int most = pr->model == 2 ? 21 : (pr->model == 3 ? 31 : 27);
+      return fail(SABR_EINVAL, std::string(name) + " needs 1.." + std::to_string(most) +
+                                   " forwards per instance");
     }
     P->np = np;
   }
@@ -169,7 +171,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
       const int first = pr->und_first[u], len = pr->und_len[u];
       if (len < 1 || first < 0 || first + len > d.nf)
         return bad("underlying " + std::to_string(u) + ": forward range out of bounds");
-      if (pr->model != 1 && len != 1) return bad("GLOBAL4, PERFWD and MM markets hold caplets only");
+      if (pr->model != 1 && len != 1) return bad("only LMM12 markets hold swaptions");
       if (len > d.maxlen) d.maxlen = len;
       // annuity, weights and swap rate, summed in forward order
       double A = 0.0;

@@ -2,6 +2,7 @@
 // cost, adjoint and Levenberg-Marquardt kernels: LDS layout of a wavefront,
 // the LMM12 parameter map and the quote loop.
 #pragma once
+#include "gauss_legendre.hpp"
 #include "sabr_internal.hpp"
 
 namespace sabr {
@@ -24,6 +25,10 @@ struct NP<2> {
 };
 template <>
 struct NP<3> {
+  static constexpr int P = 0;
+};
+template <>
+struct NP<4> {   // REB: two per forward and eight
   static constexpr int P = 0;
 };
 
@@ -320,9 +325,114 @@ __device__ bool mm_map(const DevMarket &m, const DevInst &in, const UndMkt *um, 
   return __any(bad);
 }
 
+// Square integral of an abcd function, Q(x) = int_0^x ((a + b u) e^{-c u} +
+// d)^2 du for c >= 0, x >= 0, from the moments I_m(k, x) = int_0^x u^m
+// e^{-k u} du (m = 0, 1, 2) at k = c and k = 2c.  With psi_m(z) =
+// int_0^1 s^m e^{-z s} ds, I_m = x^{m+1} psi_m(kx); psi_2 by its series
+// sum_j (-z)^j / (j! (j + 3)) when z < 1/2 (17 terms: truncation < 1e-19),
+// else (2 - e^{-z} (2 + 2z + z^2)) / z^3, and psi_1, psi_0 by the downward
+// recurrence psi_{m-1} = (z psi_m + e^{-z}) / m, stable for every z >= 0.
+// e1 = e^{-c x} is passed in (e^{-2cx} = e1^2).
+__device__ __forceinline__ void psi012(double z, double e, double &p0, double &p1, double &p2) {
+  double t = 1.0, s = 0.0;
+#pragma unroll
+  for (int j = 0; j < 17; ++j) {   // sum_j (-z)^j / (j! (j + 3))
+    s = fma(t, 1.0 / (double)(j + 3), s);
+    t = t * (-z) * (1.0 / (double)(j + 1));
+  }
+  const double iz = rcp_nr(z);
+  const double big = (2.0 - e * fma(z, z + 2.0, 2.0)) * (iz * iz * iz);
+  p2 = (z < 0.5) ? s : big;
+  p1 = fma(z, p2, e) * 0.5;
+  p0 = fma(z, p1, e);
+}
+
+__device__ __forceinline__ double abcd_sq_int(double a, double b, double c, double d, double x,
+                                              double e1) {
+  double p0, p1, p2, q0, q1, q2;
+  psi012(2.0 * c * x, e1 * e1, p0, p1, p2);
+  psi012(c * x, e1, q0, q1, q2);
+  // a^2 I0(2c) + 2ab I1(2c) + b^2 I2(2c) + 2d (a I0(c) + b I1(c)) + d^2 x
+  const double t2 = x * fma(a * a, p0, x * fma(2.0 * a * b, p1, x * (b * b) * p2));
+  const double t1 = 2.0 * d * x * fma(a, q0, b * x * q1);
+  return fma(d * d, x, t2 + t1);
+}
+
+// Rebonato map (the Rebonato model of Sec. 2.2 with the SABR parameters of
+// eq. (haganForRebonato)): lane k < np holds coordinate k of (kappa_1,
+// phi_1, ..., kappa_n, phi_n, a, b, c, d, a_h, b_h, c_h, d_h), beta fixed.
+// For the caplet on forward e with expiry T:
+//   alpha = kappa_e sqrt(G / T), G = Qg(T);  nu = sqrt(2 J / (T G)),
+//   J = int_0^T g(tau)^2 (Qh(T) - Qh(tau)) dtau  (tau = T - t),
+// Qg, Qh the square integrals of g and h (abcd_sq_int), J by the 32-point
+// Gauss-Legendre rule.  First pass (lanes over underlyings): G and Qh(T)
+// into the underlying's LDS record; second pass (lanes over underlying x
+// node pairs, 32 lanes per underlying): the quadrature terms, summed over
+// the 32 lanes, and the SABR constants.  Domain: kappa_e > 0, |phi_e| < 1,
+// c >= 0, c_h >= 0, G > 0.
+template <int FORMULA>
+__device__ bool reb_map(const DevMarket &m, const DevInst &in, const UndMkt *um, double xl,
+                        WaveLds w) {
+  const int lane = lane_id();
+  const int np = m.np;   // 2 nf + 8
+  const int q0 = np - 8;
+  const double beta = m.beta;
+  bool bad = false;
+  if (lane < q0) bad = ((lane & 1) == 0) ? !(xl > 0.0) : !(fabs(xl) < 1.0);
+  const double a = readlane_d(xl, q0), b = readlane_d(xl, q0 + 1);
+  const double c = readlane_d(xl, q0 + 2), d = readlane_d(xl, q0 + 3);
+  const double ah = readlane_d(xl, q0 + 4), bh = readlane_d(xl, q0 + 5);
+  const double ch = readlane_d(xl, q0 + 6), dh = readlane_d(xl, q0 + 7);
+  bad |= !(c >= 0.0) || !(ch >= 0.0);
+  const UndMap *umap = m.u_map + in.u0;
+  for (int i = lane; i < in.nu; i += kWave) {
+    const UndMap un = umap[i];
+    const double T = um[un.u].T;
+    SabrConst K{};
+    K.ca = abcd_sq_int(a, b, c, d, T, exp_neg(-(c * T)));
+    K.cb = abcd_sq_int(ah, bh, ch, dh, T, exp_neg(-(ch * T)));
+    bad |= !(K.ca > 0.0);
+    w.th[un.u] = K;
+  }
+  wave_lds_sync();
+  const int half = lane >> 5, j = lane & 31;
+  const double node = kGLNode[j], weight = kGLWeight[j];
+  for (int i0 = 0; i0 < in.nu; i0 += 2) {   // two underlyings a pass, one per half-wave
+    const int i = i0 + half;
+    double term = 0.0;
+    UndMap un{0, 0, 1, 0};
+    if (i < in.nu) {
+      un = umap[i];
+      const double T = um[un.u].T;
+      const double QT = w.th[un.u].cb;
+      const double ht = 0.5 * T;
+      const double tau = fma(ht, node, ht);
+      const double g = fma(b, tau, a) * exp_neg(-(c * tau)) + d;
+      const double Qt = abcd_sq_int(ah, bh, ch, dh, tau, exp_neg(-(ch * tau)));
+      term = (ht * weight) * (g * g) * (QT - Qt);
+    }
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) term += __shfl_xor(term, o, kWave);   // within the half
+    const double kap = __shfl(xl, 2 * un.e, kWave);
+    const double phi = __shfl(xl, 2 * un.e + 1, kWave);
+    wave_lds_sync();
+    if (i < in.nu && j == 0) {
+      const double T = um[un.u].T;
+      const double G = w.th[un.u].ca;
+      const double iT = rcp_nr(T);
+      const double ta = kap * sqrt_gs(G * iT);
+      const double tn = sqrt_gs(2.0 * term * iT * rcp_nr(G));
+      w.th[un.u] = und_const<FORMULA>(ta, phi, tn, beta, um[un.u].fp);
+    }
+    bad |= (i < in.nu) && !(term >= 0.0);
+    wave_lds_sync();
+  }
+  return __any(bad);
+}
+
 // Cost of one point for the wave: f = sum_q w_q r_q^2, +inf on a domain
-// failure.  p[] is wave-uniform (GLOBAL4, LMM12); PERFWD and MM read the
-// point from the lanes instead (xl: lane k holds coordinate k).  Optional
+// failure.  p[] is wave-uniform (GLOBAL4, LMM12); PERFWD, MM and REB read
+// the point from the lanes instead (xl: lane k holds coordinate k).  Optional
 // per-quote residual and model outputs (the quoted side in price mode).
 template <int MODEL, int FORMULA, int RESID>
 __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt *um,
@@ -344,8 +454,11 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
   } else if (MODEL == 2) {
     bad = perfwd_map<FORMULA>(m, in, um, xl, w);
     omb = 1.0 - m.beta;
-  } else {
+  } else if (MODEL == 3) {
     bad = mm_map<FORMULA>(m, in, um, xl, w);
+    omb = 1.0 - m.beta;
+  } else {
+    bad = reb_map<FORMULA>(m, in, um, xl, w);
     omb = 1.0 - m.beta;
   }
   double acc = 0.0;

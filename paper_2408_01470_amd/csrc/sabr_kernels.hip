@@ -488,11 +488,17 @@ hipError_t launch_prep(const DevMarket &m, QuoteRec *q, double *f_v, double *u_S
       } else {                                                       \
         if ((RESID_) == 0) { CALL(2, 1, 0); } else { CALL(2, 1, 1); } \
       }                                                              \
-    } else {                                                         \
+    } else if ((MODEL_) == 3) {                                      \
       if ((FORMULA_) == 0) {                                         \
         if ((RESID_) == 0) { CALL(3, 0, 0); } else { CALL(3, 0, 1); } \
       } else {                                                       \
         if ((RESID_) == 0) { CALL(3, 1, 0); } else { CALL(3, 1, 1); } \
+      }                                                              \
+    } else {                                                         \
+      if ((FORMULA_) == 0) {                                         \
+        if ((RESID_) == 0) { CALL(4, 0, 0); } else { CALL(4, 0, 1); } \
+      } else {                                                       \
+        if ((RESID_) == 0) { CALL(4, 1, 0); } else { CALL(4, 1, 1); } \
       }                                                              \
     }                                                                \
   } while (0)

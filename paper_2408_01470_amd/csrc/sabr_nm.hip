@@ -226,6 +226,7 @@ hipError_t launch_nm(const DevMarket &m, int n_pts, const int *pt_inst, double *
     case 1: SEL_FR(1); break;
     case 2: SEL_FR(2); break;
     case 3: SEL_FR(3); break;
+    case 4: SEL_FR(4); break;
     default: return hipErrorInvalidValue;
   }
 #undef SEL_FR

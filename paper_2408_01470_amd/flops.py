@@ -113,6 +113,18 @@ def map_flops_inst(market: dict, inst: int) -> float:
     formula = int(market["formula"])
     if int(market["model"]) == 2:
         return (u1 - u0) * sabr_const(2, formula)
+    if int(market["model"]) == 3:
+        # per forward: phi alpha w (2), the running sum (1), sigma D (1),
+        # exp, the product (1); per underlying its SABR constants
+        nf = f1 - f0
+        return nf * (5 + _e("exp")) + (u1 - u0) * sabr_const(3, formula)
+    if int(market["model"]) == 4:
+        # per underlying: G and Qh(T) (two square integrals), 32 quadrature
+        # nodes (g: exp + 4; Qh(tau): square integral; term: 5), the sum and
+        # alpha, nu (2 sqrt, 2 reciprocals, 5)
+        sq = SQ_INT
+        return (u1 - u0) * (2 * sq + 32 * (_e("exp") + 4 + sq + 5) + 31 + _e("sqrt", 2) +
+                            _e("rcp", 2) + 5 + sabr_const(4, formula))
     nf = f1 - f0
     lens = np.asarray(market["und_len"][u0:u1])
     fwd = nf * (10 + _e("exp", 2)) + max(nf - 1, 0) * (3 + _e("exp", 2))
@@ -122,10 +134,22 @@ def map_flops_inst(market: dict, inst: int) -> float:
     return fwd + und
 
 
+# Square integral of an abcd function (abcd_sq_int): two psi triples (the
+# 17-term series 51, the closed form 10 with a reciprocal, the downward
+# recurrence 4) at 2cx and cx sharing one exponential (given), and the
+# combination (14).
+SQ_INT = 2 * (51 + 10 + _e("rcp") + 4) + 14
+
+
 def num_params(market: dict) -> int:
     model = int(market["model"])
+    nf = int(market["fwd_off"][1] - market["fwd_off"][0])
     if model == 2:
-        return 3 * int(market["fwd_off"][1] - market["fwd_off"][0])
+        return 3 * nf
+    if model == 3:
+        return 2 * nf + 1
+    if model == 4:
+        return 2 * nf + 8
     return 4 if model == 0 else 12
 
 

@@ -42,6 +42,7 @@ MODEL_GLOBAL4 = 0
 MODEL_LMM12 = 1
 MODEL_PERFWD = 2
 MODEL_MM = 3
+MODEL_REB = 4
 FORMULA_HAGAN2002 = 0
 FORMULA_PAPER_EQ3 = 1
 RESID_VOL = 0
@@ -65,6 +66,8 @@ def num_params(model: int, n_fwd: int | None = None) -> int:
         return 3 * int(n_fwd)
     if model == MODEL_MM:
         return 2 * int(n_fwd) + 1
+    if model == MODEL_REB:
+        return 2 * int(n_fwd) + 8
     return 4 if model == MODEL_GLOBAL4 else 12
 
 
@@ -76,7 +79,12 @@ def box(model: int, n_fwd: int | None = None):
     alpha in [0.001, 0.2] as for GLOBAL4, rho in [-0.99, 0.99], nu in
     [0.001, 1] (the printed sigma_1 = 1.0000 of Sec. 4.1.1 sits on that
     bound).  MM (n_fwd pairs (alpha, phi), then sigma): alpha and phi as for
-    PERFWD, sigma in [0.001, 1]."""
+    PERFWD, sigma in [0.001, 1].  REB (n_fwd pairs (kappa, phi), then g's
+    (a, b, c, d) and h's (a_h, b_h, c_h, d_h)): kappa in [0.001, 0.2] (the
+    printed kappa_i = 0.0010 sit on that bound), phi as above, a, b in
+    [0, 50], c in [0.01, 10], d in [0.001, 50] (the printed g has b = 44.8,
+    d = 25.3), a_h in [0.001, 5], b_h in [0, 50], c_h in [0.01, 10], d_h in
+    [0.001, 5]."""
     if model == MODEL_PERFWD:
         lb = np.tile([0.001, -0.99, 0.001], int(n_fwd))
         ub = np.tile([0.2, 0.99, 1.0], int(n_fwd))
@@ -84,6 +92,12 @@ def box(model: int, n_fwd: int | None = None):
     if model == MODEL_MM:
         lb = np.concatenate([np.tile([0.001, -0.99], int(n_fwd)), [0.001]])
         ub = np.concatenate([np.tile([0.2, 0.99], int(n_fwd)), [1.0]])
+        return lb, ub
+    if model == MODEL_REB:
+        lb = np.concatenate([np.tile([0.001, -0.99], int(n_fwd)),
+                             [0.0, 0.0, 0.01, 0.001, 0.001, 0.0, 0.01, 0.001]])
+        ub = np.concatenate([np.tile([0.2, 0.99], int(n_fwd)),
+                             [50.0, 50.0, 10.0, 50.0, 5.0, 50.0, 10.0, 5.0]])
         return lb, ub
     if model == MODEL_GLOBAL4:
         lb = np.array([0.001, 0.0, -0.99, 0.001])
@@ -294,6 +308,28 @@ def mm_markets(seed=SEED_BASE + 7000, n_markets=3, M=13, nK=9, formula=FORMULA_H
         truths.append(np.concatenate([pairs, [g.uniform(0.2, 0.6)]]))
         noises.append(g.normal(0.0, 0.002, M * nK))
     m = _finish(parts, MODEL_MM, formula, residual, 0.5)
+    return m, np.array(truths), np.concatenate(noises)
+
+
+def reb_markets(seed=SEED_BASE + 8000, n_markets=3, M=13, nK=9, formula=FORMULA_HAGAN2002,
+                residual=RESID_VOL):
+    """Rebonato caplet markets (equal size), true kappa_i ~ U[0.001, 0.003],
+    phi_i ~ U[-0.5, 0], g = (a, b, c, d) ~ (U[2, 6], U[20, 60], U[0.2, 0.5],
+    U[15, 35]), h = (a_h, b_h, c_h, d_h) ~ (U[0.001, 0.1], U[10, 30],
+    U[3, 8], U[0.3, 0.8]) (around the paper's calibrated values); point
+    layout (kappa_1, phi_1, ..., kappa_M, phi_M, a, b, c, d, a_h, b_h, c_h,
+    d_h)."""
+    parts = _empty()
+    truths, noises = [], []
+    for j in range(n_markets):
+        g = rng(seed + j)
+        _append(parts, *_caplet_instance(g, M, nK))
+        pairs = np.column_stack([g.uniform(0.001, 0.003, M), g.uniform(-0.5, 0.0, M)]).ravel()
+        gh = [g.uniform(2, 6), g.uniform(20, 60), g.uniform(0.2, 0.5), g.uniform(15, 35),
+              g.uniform(0.001, 0.1), g.uniform(10, 30), g.uniform(3, 8), g.uniform(0.3, 0.8)]
+        truths.append(np.concatenate([pairs, gh]))
+        noises.append(g.normal(0.0, 0.002, M * nK))
+    m = _finish(parts, MODEL_REB, formula, residual, 0.5)
     return m, np.array(truths), np.concatenate(noises)
 
 

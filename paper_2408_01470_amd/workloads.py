@@ -143,6 +143,23 @@ def paper_mm(chains=16384):
                                        paper_mre=3.11e-2))
 
 
+def paper_reb(chains=32768, n_steps=100):
+    """The paper's Rebonato caplet calibration (Sec. 4.3.1) replayed on its
+    printed data: REB (13 forwards, P = 34, beta = 0.5), eq. (sigmaHagan),
+    T0 = 10, Tmin = 0.01, rho = 0.99 (688 levels), N = 100, and the chains of
+    its two GPUs (2 x 256 x 64 = 32768) on one: 32768 (1 + 100 x 688) =
+    2,254,471,168 cost evaluations ("roughly two billion").  Printed for
+    comparison: SA 119.913 s on two GTX 470, MRE 2.93e-2."""
+    m = I.paper_caplet_market(model=I.MODEL_REB)
+    T0, T_min, cool = 10.0, 0.01, 0.99
+    return Workload(f"reb: the paper's EURIBOR caplets 13x9, Rebonato P=34, eq. (sigmaHagan), "
+                    f"{chains} chains, T0=10, Tmin=0.01, rho=0.99, N={n_steps}", m, None, None,
+                    chains=chains, n_levels=paper_levels(T0, T_min, cool), n_steps=n_steps,
+                    seed=8, extra=dict(T0=T0, T_min=T_min, cool=cool, paper_sa_s=119.913,
+                                       paper_total_s=146.729, paper_evals=2254471168,
+                                       paper_mre=2.93e-2))
+
+
 CONFIGS = {"c1": config1, "c2": config2, "c3": config3, "c4": config4, "c5": config5}
 
 

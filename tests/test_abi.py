@@ -98,7 +98,7 @@ def test_plan_create_and_queries(L):
     (lambda m: m["und_first"].__setitem__(9, 10), "forward range"),
     (lambda m: m["q_kind"].__setitem__(4, 2), "kind"),
     (lambda m: m["q_w"].__setitem__(4, -1.0), "weight"),
-    (lambda m: m.__setitem__("model", 4), "model"),
+    (lambda m: m.__setitem__("model", 5), "model"),
     (lambda m: m.__setitem__("beta", 1.5), "beta"),
 ])
 def test_plan_rejects_bad_market(L, mutate, msg):
@@ -124,7 +124,7 @@ def test_global4_rejects_swaptions(L):
     m = dict(m, model=0)
     rc, _ = _create(L, m)
     assert rc == -1
-    assert "caplets only" in L.sabr_last_error().decode()
+    assert "only LMM12 markets hold swaptions" in L.sabr_last_error().decode()
 
 
 def test_sa_rejects_bad_config_without_gpu(L):

@@ -200,4 +200,4 @@ def test_plan_create_perfwd_rejects_swaps(L):
     m["und_len"] = m["und_len"].copy()
     m["und_len"][0] = 2
     rc, _ = _create(L, m)
-    assert rc == -1 and b"caplets only" in L.sabr_last_error()
+    assert rc == -1 and b"only LMM12 markets hold swaptions" in L.sabr_last_error()
