@@ -198,7 +198,7 @@ typedef struct {
   int32_t n_steps;       /* N >= 0 */
   uint64_t seed;         /* Philox key word 0; key word 1 = instance index */
   const double *T0_per_inst; /* [host] nullable [n_inst] per-instance T0 */
-  int32_t waves_per_group;   /* chains per workgroup (0 = library default) */
+  int32_t waves_per_group;   /* chains per workgroup, at most 8 (0 = library default 4) */
   int32_t use_graph;         /* 1: capture the launch sequence in a hipGraph and replay it */
   void *const *level_events; /* [host] nullable: 2 * n_levels hipEvent_t recorded on `stream`
                                 just before and just after each level's annealing kernel

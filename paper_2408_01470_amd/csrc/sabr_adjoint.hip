@@ -433,7 +433,7 @@ __device__ double point_normal(const DevMarket &m, const DevInst &in, const UndM
 }
 
 __device__ __forceinline__ size_t vjp_lds_doubles(const DevMarket &m) {
-  return 6 * m.max_nu + wave_lds_doubles(m) + (m.model == 1 ? 2 * m.max_nf + 5 * m.max_len * kWave : 0);
+  return 6 * m.max_nu + wave_lds_doubles(m, true) + (m.model == 1 ? 2 * m.max_nf + 5 * m.max_len * kWave : 0);
 }
 
 // sabr_cost_vjp: one wave per point (grid-stride), private M_u scratch per wave.
@@ -447,9 +447,9 @@ __global__ __launch_bounds__(64) void vjp_kernel(DevMarket m, int n_pts, const i
   constexpr int NT = P * (P + 1) / 2;
   const int lane = lane_id();
   UndMkt *um = reinterpret_cast<UndMkt *>(smem);
-  WaveLds w = wave_lds(m, smem + 6 * m.max_nu);
-  FwdExp *ef = reinterpret_cast<FwdExp *>(smem + 6 * m.max_nu + wave_lds_doubles(m));
-  double *col = smem + 6 * m.max_nu + wave_lds_doubles(m) + 2 * m.max_nf;
+  WaveLds w = wave_lds(m, smem + 6 * m.max_nu, true);
+  FwdExp *ef = reinterpret_cast<FwdExp *>(smem + 6 * m.max_nu + wave_lds_doubles(m, true));
+  double *col = smem + 6 * m.max_nu + wave_lds_doubles(m, true) + 2 * m.max_nf;
   double *M = scratch + (size_t)blockIdx.x * m.max_nu * 36;
   for (int pt = blockIdx.x; pt < n_pts; pt += gridDim.x) {
     const int inst = __builtin_amdgcn_readfirstlane(pt_inst[pt]);
@@ -533,9 +533,9 @@ __global__ __launch_bounds__(64) void lm_kernel(DevMarket m, int n_pts, const in
   constexpr int NT = P * (P + 1) / 2;
   const int lane = lane_id();
   UndMkt *um = reinterpret_cast<UndMkt *>(smem);
-  WaveLds w = wave_lds(m, smem + 6 * m.max_nu);
-  FwdExp *ef = reinterpret_cast<FwdExp *>(smem + 6 * m.max_nu + wave_lds_doubles(m));
-  double *col = smem + 6 * m.max_nu + wave_lds_doubles(m) + 2 * m.max_nf;
+  WaveLds w = wave_lds(m, smem + 6 * m.max_nu, true);
+  FwdExp *ef = reinterpret_cast<FwdExp *>(smem + 6 * m.max_nu + wave_lds_doubles(m, true));
+  double *col = smem + 6 * m.max_nu + wave_lds_doubles(m, true) + 2 * m.max_nf;
   double *sys = col + (MODEL == 1 ? 5 * m.max_len * kWave : 0);  // P*P + 3P doubles
   double *M = scratch + (size_t)blockIdx.x * m.max_nu * 36;
   for (int pt = blockIdx.x; pt < n_pts; pt += gridDim.x) {
@@ -654,7 +654,7 @@ __global__ __launch_bounds__(64) void lm_kernel(DevMarket m, int n_pts, const in
 
 size_t adjoint_lds_bytes(const DevMarket &m) {
   const int P = m.model == 0 ? 4 : 12;
-  return (size_t)(6 * m.max_nu + wave_lds_doubles(m) + 2 * m.max_nf +
+  return (size_t)(6 * m.max_nu + wave_lds_doubles(m, true) + 2 * m.max_nf +
                   (m.model == 1 ? 5 * m.max_len * kWave : 0) + P * P + 3 * P) *
          8;
 }

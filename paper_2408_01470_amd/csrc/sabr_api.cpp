@@ -57,13 +57,14 @@ struct sabr_plan {
   // host copies of the uploaded arrays
   std::vector<DevInst> inst;
   std::vector<double> f_T, f_tauP, f_F, f_mmw;
-  std::vector<int> u_first, u_len, u_order;
+  std::vector<int> u_first, u_len, u_order, u_ext, u_q0;
   std::vector<sabr::UndMap> u_map;
   std::vector<double> u_S0, u_A, u_invA, u_T;
   std::vector<sabr::QuoteRec> q;  // und, kind, K filled on the host
-  std::vector<int> q_und_g;
+  std::vector<int> q_und_g, q_ext;
   std::vector<double> q_vol, q_wuser;
   // device image offsets
+  size_t o_uq0, o_qext;
   size_t o_inst, o_fT, o_ftauP, o_fF, o_fmmw, o_ufirst, o_ulen, o_uorder, o_uS0, o_uA, o_uinvA, o_uT,
       o_q, o_qundg, o_qvol, o_qwuser;  // uploaded (contiguous prefix)
   size_t upload_bytes = 0;
@@ -167,7 +168,11 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
     d.nq = pr->q_off[i + 1] - d.q0;
     if (d.nq < 1) return bad("instance " + std::to_string(i) + " has no quotes");
     d.maxlen = 1;
-    for (int u = d.u0; u < d.u0 + d.nu; ++u) {
+    // underlyings in the caller's order: validation and market values
+    std::vector<int> ufirst(d.nu), ulen(d.nu);
+    std::vector<double> uS0(d.nu), uA(d.nu), uT(d.nu);
+    for (int j = 0; j < d.nu; ++j) {
+      const int u = d.u0 + j;
       const int first = pr->und_first[u], len = pr->und_len[u];
       if (len < 1 || first < 0 || first + len > d.nf)
         return bad("underlying " + std::to_string(u) + ": forward range out of bounds");
@@ -184,12 +189,11 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
       }
       const double Te = pr->fwd_T[d.f0 + first];
       if (!(Te > 0.0)) return bad("underlying " + std::to_string(u) + ": expiry must be > 0");
-      P->u_first.push_back(first);
-      P->u_len.push_back(len);
-      P->u_S0.push_back(S0);
-      P->u_A.push_back(A);
-      P->u_invA.push_back(1.0 / A);
-      P->u_T.push_back(Te);
+      ufirst[j] = first;
+      ulen[j] = len;
+      uS0[j] = S0;
+      uA[j] = A;
+      uT[j] = Te;
     }
     int prev = 0;
     for (int q = d.q0; q < d.q0 + d.nq; ++q) {
@@ -201,24 +205,49 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
       if (kind != 0 && kind != 1) return bad("quote " + std::to_string(q) + ": bad kind");
       if (!finite_pos(K) || !finite_pos(vol) || !(std::isfinite(w) && w >= 0.0))
         return bad("quote " + std::to_string(q) + ": bad strike, vol or weight");
-      sabr::QuoteRec R{};
-      R.und = u;
-      R.kind = kind;
-      R.K = K;
-      P->q.push_back(R);
-      P->q_und_g.push_back(d.u0 + u);
-      P->q_vol.push_back(vol);
-      P->q_wuser.push_back(w);
     }
-    // underlyings by decreasing length (stable), for the swap-map passes
-    std::vector<int> ord(d.nu);
-    for (int u = 0; u < d.nu; ++u) ord[u] = u;
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
-      return P->u_len[d.u0 + x] > P->u_len[d.u0 + y];
+    // Internal order: underlyings by decreasing length (stable), so a pass of
+    // the swap map over consecutive underlyings runs swaps of similar length,
+    // and the quotes grouped by that order, so the underlyings of a chunk own
+    // a contiguous range of quotes.  Per-quote outputs and the underlyings
+    // query go back to the caller's order.
+    std::vector<int> ord(d.nu), pos(d.nu);
+    for (int j = 0; j < d.nu; ++j) ord[j] = j;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return ulen[x] > ulen[y]; });
+    for (int p = 0; p < d.nu; ++p) pos[ord[p]] = p;
+    for (int p = 0; p < d.nu; ++p) {
+      const int j = ord[p];
+      P->u_first.push_back(ufirst[j]);
+      P->u_len.push_back(ulen[j]);
+      P->u_S0.push_back(uS0[j]);
+      P->u_A.push_back(uA[j]);
+      P->u_invA.push_back(1.0 / uA[j]);
+      P->u_T.push_back(uT[j]);
+      P->u_ext.push_back(d.u0 + j);
+      P->u_order.push_back(p);
+      P->u_map.push_back(sabr::UndMap{p, ufirst[j], ulen[j], 0});
+    }
+    std::vector<int> qord(d.nq);
+    for (int j = 0; j < d.nq; ++j) qord[j] = j;
+    std::stable_sort(qord.begin(), qord.end(), [&](int x, int y) {
+      return pos[pr->q_und[d.q0 + x]] < pos[pr->q_und[d.q0 + y]];
     });
-    P->u_order.insert(P->u_order.end(), ord.begin(), ord.end());
-    for (int u : ord)
-      P->u_map.push_back(sabr::UndMap{u, P->u_first[d.u0 + u], P->u_len[d.u0 + u], 0});
+    std::vector<int> uq0(d.nu + 1, d.nq);
+    for (int j = d.nq - 1; j >= 0; --j) uq0[pos[pr->q_und[d.q0 + qord[j]]]] = j;
+    for (int p = d.nu - 1; p >= 0; --p) uq0[p] = std::min(uq0[p], uq0[p + 1]);
+    for (int p = 0; p < d.nu; ++p) P->u_q0.push_back(uq0[p]);
+    for (int j = 0; j < d.nq; ++j) {
+      const int q = d.q0 + qord[j];
+      sabr::QuoteRec R{};
+      R.und = pos[pr->q_und[q]];
+      R.kind = pr->q_kind[q];
+      R.K = pr->q_K[q];
+      P->q.push_back(R);
+      P->q_und_g.push_back(d.u0 + R.und);
+      P->q_vol.push_back(pr->q_vol[q]);
+      P->q_wuser.push_back(pr->q_w[q]);
+      P->q_ext.push_back(qord[j]);
+    }
     if (d.nq > P->max_nq) P->max_nq = d.nq;
     if (d.nu > P->max_nu) P->max_nu = d.nu;
     if (d.nf > P->max_nf) P->max_nf = d.nf;
@@ -235,6 +264,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   P->o_ufirst = L.take<int>(P->nU);
   P->o_ulen = L.take<int>(P->nU);
   P->o_uorder = L.take<int>(P->nU);
+  P->o_uq0 = L.take<int>(P->nU);
   P->o_uS0 = L.take<double>(P->nU);
   P->o_uA = L.take<double>(P->nU);
   P->o_uinvA = L.take<double>(P->nU);
@@ -242,6 +272,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   P->o_umap = L.take<sabr::UndMap>(P->nU);
   P->o_q = L.take<sabr::QuoteRec>(P->nQ);
   P->o_qundg = L.take<int>(P->nQ);
+  P->o_qext = L.take<int>(P->nQ);
   P->o_qvol = L.take<double>(P->nQ);
   P->o_qwuser = L.take<double>(P->nQ);
   P->upload_bytes = L.off;
@@ -261,6 +292,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   put(P->o_fmmw, P->f_mmw.data(), P->nF * 8);
   put(P->o_ufirst, P->u_first.data(), P->nU * 4);
   put(P->o_ulen, P->u_len.data(), P->nU * 4);
+  put(P->o_uq0, P->u_q0.data(), P->nU * 4);
   put(P->o_uorder, P->u_order.data(), P->nU * 4);
   put(P->o_uS0, P->u_S0.data(), P->nU * 8);
   put(P->o_uA, P->u_A.data(), P->nU * 8);
@@ -269,6 +301,7 @@ sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {
   put(P->o_umap, P->u_map.data(), P->nU * sizeof(sabr::UndMap));
   put(P->o_q, P->q.data(), P->nQ * sizeof(sabr::QuoteRec));
   put(P->o_qundg, P->q_und_g.data(), P->nQ * 4);
+  put(P->o_qext, P->q_ext.data(), P->nQ * 4);
   put(P->o_qvol, P->q_vol.data(), P->nQ * 8);
   put(P->o_qwuser, P->q_wuser.data(), P->nQ * 8);
   *out = P;
@@ -284,10 +317,11 @@ int32_t sabr_plan_max_quotes(const sabr_plan *plan) { return plan ? plan->max_nq
 
 sabr_status sabr_plan_underlyings(const sabr_plan *plan, double *S0, double *A, double *T) {
   if (!plan) return fail(SABR_EINVAL, "null plan");
-  for (int u = 0; u < plan->nU; ++u) {
-    if (S0) S0[u] = plan->u_S0[u];
-    if (A) A[u] = plan->u_A[u];
-    if (T) T[u] = plan->u_T[u];
+  for (int g = 0; g < plan->nU; ++g) {   // internal order -> the caller's
+    const int u = plan->u_ext[g];
+    if (S0) S0[u] = plan->u_S0[g];
+    if (A) A[u] = plan->u_A[g];
+    if (T) T[u] = plan->u_T[g];
   }
   return SABR_OK;
 }
@@ -320,6 +354,8 @@ sabr_status sabr_plan_upload(sabr_plan *P, void *dev_buf, size_t bytes, void *st
   m.u_first = I(P->o_ufirst);
   m.u_len = I(P->o_ulen);
   m.u_order = I(P->o_uorder);
+  m.u_q0 = I(P->o_uq0);
+  m.q_ext = I(P->o_qext);
   m.u_S0 = D(P->o_uS0);
   m.u_A = D(P->o_uA);
   m.u_invA = D(P->o_uinvA);
@@ -382,7 +418,7 @@ SALayout sa_layout(const sabr_plan *P, const sa_config *cfg, const int32_t *chai
   const int n = P->n_inst;
   const int Pn = P->np;
   int want = cfg && cfg->waves_per_group > 0 ? cfg->waves_per_group : 4;
-  if (want > 4) want = 4;
+  if (want > sabr::kMaxWavesPerGroup) want = sabr::kMaxWavesPerGroup;
   DevMarket shape{};  // LDS budget depends on the market's shape only
   shape.model = P->model;
   shape.np = P->np;

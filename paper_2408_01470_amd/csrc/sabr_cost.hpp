@@ -48,11 +48,12 @@ struct WaveLds {
   double *lk;      // [max_len][64], used for swaps longer than kMapRegLen
 };
 
-__device__ __forceinline__ WaveLds wave_lds(const DevMarket &m, double *base) {
+__device__ __forceinline__ WaveLds wave_lds(const DevMarket &m, double *base,
+                                            bool full = false) {
   WaveLds w;
   w.fw = reinterpret_cast<FwdMap *>(base);
   w.th = reinterpret_cast<SabrConst *>(base + kFwdMapDoubles * m.max_nf);
-  w.lk = base + kFwdMapDoubles * m.max_nf + kSabrConstDoubles * m.max_nu;
+  w.lk = base + kFwdMapDoubles * m.max_nf + kSabrConstDoubles * th_entries(m, full);
   return w;
 }
 
@@ -193,20 +194,15 @@ __device__ __forceinline__ SabrConst und_const(double ta, double tr, double tn, 
 //   rho_S = rho (sum a)(sum b) / (sqrt(V) sqrt(Nb))   (0 if Nb = 0).
 // Underlyings are visited in decreasing length (the u_map table) so the lanes
 // of a pass run recursions of similar length.
-template <int FORMULA>
-__device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const UndMkt *um,
-                                 const double *p, WaveLds w) {
+// Forward part: the parameter domain and the per-forward records.
+__device__ inline bool lmm12_fwd(const DevMarket &m, const DevInst &in, const double *p,
+                                 WaveLds w) {
   const int lane = lane_id();
   const double a = p[0], b = p[1], c = p[2], d = p[3];
   const double an = p[4], bn = p[5], cn = p[6], dn = p[7];
   const double rho = p[8], lam1 = p[9], eta2 = p[10], lam2 = p[11];
-  const double beta = m.beta;
-  bool bad = !(fabs(rho) < 1.0) || !(lam1 >= 0.0) || !(lam2 >= 0.0) ||
-             !(eta2 >= 0.0 && eta2 <= 1.0);
-  // the first underlying pass's entry is loaded before the forward pass
-  const UndMap *umap = m.u_map + in.u0;
-  UndMap un{0, 0, 1, 0};
-  if (lane < in.nu) un = umap[lane];
+  const bool bad = !(fabs(rho) < 1.0) || !(lam1 >= 0.0) || !(lam2 >= 0.0) ||
+                   !(eta2 >= 0.0 && eta2 <= 1.0);
   for (int k = lane; k < in.nf; k += kWave) {
     const double T = m.f_T[in.f0 + k];
     FwdMap F;
@@ -223,10 +219,26 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const Un
     w.fw[k] = F;
   }
   wave_lds_sync();
+  return bad;
+}
+
+// Underlying part for the underlyings [i0, i1) of the map's visiting order
+// (the internal order): their SABR constants go to w.th[u - i0].  Returns
+// this lane's domain failure.
+template <int FORMULA>
+__device__ inline bool lmm12_und(const DevMarket &m, const DevInst &in, const UndMkt *um,
+                                 const double *p, WaveLds w, int i0, int i1) {
+  const int lane = lane_id();
+  const double rho = p[8], eta2 = p[10];
+  const double beta = m.beta;
+  bool bad = false;
+  const UndMap *umap = m.u_map + in.u0;
+  UndMap un{0, 0, 1, 0};
+  if (i0 + lane < i1) un = umap[i0 + lane];
   double *lk = w.lk + lane;
-  for (int i = lane; i < in.nu; i += kWave) {
+  for (int i = i0 + lane; i < i1; i += kWave) {
     const int u = un.u, e = un.e, n = un.n;
-    if (i + kWave < in.nu) un = umap[i + kWave];   // next pass's entry
+    if (i + kWave < i1) un = umap[i + kWave];   // next pass's entry
     double ta, tr, tn;
     if (n == 1) {
       const FwdMap F = w.fw[e];
@@ -247,9 +259,18 @@ __device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const Un
       tr = (sN > 0.0) ? rho * suma * Sb * rcp_nr(sV * sN) : 0.0;
       bad |= !(V > 0.0) || !(fabs(tr) < 1.0);
     }
-    w.th[u] = und_const<FORMULA>(ta, tr, tn, beta, um[u].fp);
+    w.th[u - i0] = und_const<FORMULA>(ta, tr, tn, beta, um[u].fp);
   }
   wave_lds_sync();
+  return bad;
+}
+
+// The whole map into the wave's LDS (a full-size underlying table).
+template <int FORMULA>
+__device__ inline bool lmm12_map(const DevMarket &m, const DevInst &in, const UndMkt *um,
+                                 const double *p, WaveLds w) {
+  bool bad = lmm12_fwd(m, in, p, w);
+  bad |= lmm12_und<FORMULA>(m, in, um, p, w, 0, in.nu);
   return __any(bad);
 }
 
@@ -449,7 +470,7 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
     omb = 1.0 - p[1];
     omb2 = omb * omb;
   } else if (MODEL == 1) {
-    bad = lmm12_map<FORMULA>(m, in, um, p, w);
+    bad = lmm12_fwd(m, in, p, w);   // the underlyings follow chunk by chunk
     omb = 1.0 - m.beta;
   } else if (MODEL == 2) {
     bad = perfwd_map<FORMULA>(m, in, um, xl, w);
@@ -462,11 +483,12 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
     omb = 1.0 - m.beta;
   }
   double acc = 0.0;
-  auto quote = [&](const QuoteRec &R, int q) {
+  const int *qx = m.q_ext + in.q0;   // per-quote outputs go to the caller's order
+  auto quote = [&](const QuoteRec &R, int q, int toff) {
     const double L = R.L;
     const int u = R.und;
     const UndMkt U = um[u];
-    const SabrConst k = (MODEL == 0) ? g : w.th[u];
+    const SabrConst k = (MODEL == 0) ? g : w.th[u - toff];
     // eq. (sigmaHagan) with beta fixed: the vol itself, a quadratic in
     // k = ln(K/f) = -L with the underlying's coefficients
     constexpr bool direct = (FORMULA == 1 && MODEL != 0);
@@ -485,7 +507,7 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
     if (RESID == 0) {
       mv = direct ? vf.numer : vf.numer * rcp_nr(vf.denom);
       bad |= !(mv > 0.0) || !(mv < kInf);
-      if (model) model[q] = mv;
+      if (model) model[qx[q]] = mv;
     } else {
       // one reciprocal gives sigma = numer/denom and 1/sigma = denom/numer
       const double rr = rcp_nr(vf.numer * vf.denom);
@@ -496,26 +518,41 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
       bad |= !(fabs(mv) < kInf);
       if (model) {
         const double sh = parity_shift(R.kind, U.f, R.K, L, U.D);
-        model[q] = sh == 0.0 ? mv : mv + sh;
+        model[qx[q]] = sh == 0.0 ? mv : mv + sh;
       }
     }
     const double r = mv - R.tgt;
     acc = fma(R.w * r, r, acc);
-    if (resid) resid[q] = r;
+    if (resid) resid[qx[q]] = r;
   };
-  // Two record buffers in turn: the next pass's record is loaded while this
-  // pass computes (the global load latency hides behind the arithmetic), and
-  // no register copies are needed between passes.
+  // Quotes [qa, qb) with two record buffers in turn: the next pass's record
+  // is loaded while this pass computes (the global load latency hides behind
+  // the arithmetic), and no register copies are needed between passes.
   const QuoteRec *qrec = m.q + in.q0;
-  const int nq = in.nq;
-  QuoteRec Ra{}, Rb{};
-  if (lane < nq) Ra = qrec[lane];
-  for (int q = lane; q < nq; q += 2 * kWave) {
-    if (q + kWave < nq) Rb = qrec[q + kWave];
-    quote(Ra, q);
-    if (q + kWave >= nq) break;
-    if (q + 2 * kWave < nq) Ra = qrec[q + 2 * kWave];
-    quote(Rb, q + kWave);
+  auto quotes = [&](int qa, int qb, int toff) {
+    QuoteRec Ra{}, Rb{};
+    if (qa + lane < qb) Ra = qrec[qa + lane];
+    for (int q = qa + lane; q < qb; q += 2 * kWave) {
+      if (q + kWave < qb) Rb = qrec[q + kWave];
+      quote(Ra, q, toff);
+      if (q + kWave >= qb) break;
+      if (q + 2 * kWave < qb) Ra = qrec[q + 2 * kWave];
+      quote(Rb, q + kWave, toff);
+    }
+  };
+  if (MODEL == 1) {
+    // LMM12: the underlyings' SABR constants chunk by chunk (kThChunk of
+    // them in LDS at a time), each followed by its underlyings' quotes (a
+    // contiguous range in the internal order)
+    const int *uq0 = m.u_q0 + in.u0;
+    for (int c0 = 0; c0 < in.nu; c0 += kThChunk) {
+      const int c1 = min(in.nu, c0 + kThChunk);
+      bad |= lmm12_und<FORMULA>(m, in, um, p, w, c0, c1);
+      quotes(uq0[c0], c1 < in.nu ? uq0[c1] : in.nq, c0);
+      wave_lds_sync();   // the next chunk overwrites the constants
+    }
+  } else {
+    quotes(0, in.nq, 0);
   }
   const double tot = wave_sum(acc);
   const bool any_bad = __any(bad);

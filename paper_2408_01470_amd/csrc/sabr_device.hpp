@@ -67,7 +67,9 @@ struct DevMarket {
   const double *f_mmw;   // MM drift weight T_{k-1} tau_k F_k^beta / (1 + tau_k F_k)
   // underlyings (caplet = one-period swap)
   const int *u_first, *u_len;
-  const int *u_order;    // per instance: underlyings by decreasing length
+  const int *u_order;    // per instance: the map's visiting order (the internal order)
+  const int *u_q0;       // per underlying: its first quote (local index)
+  const int *q_ext;      // per quote: its index in the caller's order (local)
   const double *u_S0, *u_A, *u_invA, *u_S0b, *u_T;  // swap rate, annuity, 1/A, S0^beta, expiry
   const UndMap *u_map;   // per instance: u_order[i] with its first forward and length
   const double *u_c0;    // 1/(A S0^beta) per underlying

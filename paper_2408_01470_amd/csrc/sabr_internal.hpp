@@ -18,9 +18,20 @@ constexpr int kMapRegLen = 16;
 // (for swaps longer than kMapRegLen) a per-lane column of max_len doubles for
 // the swap recursion.
 // Each workgroup adds 6 doubles per underlying of market values.
-__host__ __device__ inline int wave_lds_doubles(const DevMarket &m) {
+// The cost evaluation (point_cost) takes the LMM12 underlyings kThChunk at
+// a time, so its table holds min(max_nu, kThChunk) records; the adjoint's
+// whole-map table (full) holds max_nu.
+constexpr int kThChunk = 128;
+// Waves (chains) per annealing workgroup at most: the instance's market
+// values staged in LDS are shared by the workgroup's waves.
+constexpr int kMaxWavesPerGroup = 8;
+__host__ __device__ inline int th_entries(const DevMarket &m, bool full) {
+  return (m.model == 1 && !full && m.max_nu > kThChunk) ? kThChunk : m.max_nu;
+}
+
+__host__ __device__ inline int wave_lds_doubles(const DevMarket &m, bool full = false) {
   if (m.model == 0) return 0;
-  return 6 * m.max_nf + kSabrConstDoubles * m.max_nu +
+  return 6 * m.max_nf + kSabrConstDoubles * th_entries(m, full) +
          (m.max_len > kMapRegLen ? kWave * m.max_len : 0);
 }
 

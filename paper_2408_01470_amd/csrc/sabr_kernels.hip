@@ -151,8 +151,8 @@ __device__ __forceinline__ void wave_argmin(double &f, int &i, int C) {
 // best-ever cost, accepted moves.  Every wave of the workgroup calls it; a
 // wave without a chain passes c = C.
 __device__ void tile_partial(const SAArgs &a, int C, int c, double f, double bf, int nacc) {
-  __shared__ double red_f[4], red_b[4];
-  __shared__ int red_c[4], red_n[4];
+  __shared__ double red_f[kMaxWavesPerGroup], red_b[kMaxWavesPerGroup];
+  __shared__ int red_c[kMaxWavesPerGroup], red_n[kMaxWavesPerGroup];
   const int wid = threadIdx.x / kWave;
   if (lane_id() == 0) {
     red_f[wid] = f;
@@ -269,7 +269,8 @@ __device__ void level_end_block(const SAArgs &a, int inst, int level, double *sc
 }
 
 template <int MODEL, int FORMULA, int RESID>
-__global__ __launch_bounds__(256) void sa_init_kernel(DevMarket m, SAArgs a, int lds_per_wave) {
+__global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void sa_init_kernel(DevMarket m, SAArgs a,
+                                                                             int lds_per_wave) {
   extern __shared__ double smem[];
   constexpr int PC = NP<MODEL>::P;       // 0: known at run time (PERFWD)
   const int P = PC > 0 ? PC : a.P;
@@ -308,7 +309,9 @@ __global__ __launch_bounds__(256) void sa_init_kernel(DevMarket m, SAArgs a, int
 // OCC: minimum waves per SIMD the register allocation must allow (1 = the
 // compiler's choice); a tuning knob traded against spills.
 template <int MODEL, int FORMULA, int RESID, int OCC>
-__global__ __launch_bounds__(256, OCC) void sa_level_kernel(DevMarket m, SAArgs a, int level,
+__global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kernel(DevMarket m,
+                                                                                 SAArgs a,
+                                                                                 int level,
                                                             int lds_per_wave) {
   extern __shared__ double smem[];
   constexpr int PC = NP<MODEL>::P;       // 0: known at run time (PERFWD)
