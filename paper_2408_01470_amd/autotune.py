@@ -16,8 +16,8 @@ import os
 import numpy as np
 import torch
 
-CANDIDATES = ((1, 1), (2, 1), (4, 1), (1, 3), (2, 3), (4, 3), (2, 4), (4, 4), (8, 1), (8, 3),
-              (8, 4))
+CANDIDATES = ((1, 1), (2, 1), (4, 1), (1, 3), (2, 3), (4, 3), (2, 4), (4, 4), (6, 4), (8, 1),
+              (8, 3), (8, 4))
 
 
 def cache_path():

@@ -46,6 +46,12 @@ struct Layout {
   }
 };
 
+// Register column length of the LMM12 swap recursion in the cost kernels:
+// 16 or 24 forwards, or 0 (an LDS column) for longer swaps.
+int reglen_for(int max_len) {
+  return max_len <= sabr::kMapRegLen ? sabr::kMapRegLen : (max_len <= 24 ? 24 : 0);
+}
+
 }  // namespace
 
 struct sabr_plan {
@@ -345,6 +351,8 @@ sabr_status sabr_plan_upload(sabr_plan *P, void *dev_buf, size_t bytes, void *st
   m.max_nu = P->max_nu;
   m.max_nf = P->max_nf;
   m.max_len = P->max_len;
+  m.reglen = reglen_for(P->max_len);
+  m.thchunk = sabr::th_chunk_for(P->max_nu);
   m.inst = reinterpret_cast<const DevInst *>(d + P->o_inst);
   auto D = [&](size_t o) { return reinterpret_cast<double *>(d + o); };
   auto I = [&](size_t o) { return reinterpret_cast<int *>(d + o); };
@@ -425,6 +433,8 @@ SALayout sa_layout(const sabr_plan *P, const sa_config *cfg, const int32_t *chai
   shape.max_nf = P->max_nf;
   shape.max_nu = P->max_nu;
   shape.max_len = P->max_len;
+  shape.reglen = reglen_for(P->max_len);
+  shape.thchunk = sabr::th_chunk_for(P->max_nu);
   S.waves = sabr::sa_waves_per_group(shape, want);
   S.n_tiles = 0;
   S.max_tiles = 0;

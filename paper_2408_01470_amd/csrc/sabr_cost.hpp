@@ -31,6 +31,10 @@ template <>
 struct NP<4> {   // REB: two per forward and eight
   static constexpr int P = 0;
 };
+template <>
+struct NP<5> {   // LMM12, the swap column in 24 registers
+  static constexpr int P = 12;
+};
 
 // Per-wave LDS scratch of the LMM12 map: per forward {alpha, nu, g1, g2, a}
 // (g1, g2: correlation factors of the gap to the next forward; a = v alpha,
@@ -225,7 +229,7 @@ __device__ inline bool lmm12_fwd(const DevMarket &m, const DevInst &in, const do
 // Underlying part for the underlyings [i0, i1) of the map's visiting order
 // (the internal order): their SABR constants go to w.th[u - i0].  Returns
 // this lane's domain failure.
-template <int FORMULA>
+template <int FORMULA, int REG = kMapRegLen>
 __device__ inline bool lmm12_und(const DevMarket &m, const DevInst &in, const UndMkt *um,
                                  const double *p, WaveLds w, int i0, int i1) {
   const int lane = lane_id();
@@ -247,9 +251,8 @@ __device__ inline bool lmm12_und(const DevMarket &m, const DevInst &in, const Un
       tn = F.nv;
       bad |= !(ta > 0.0) || !(tn >= 0.0);
     } else {
-      const SwapMoments S = (m.max_len <= kMapRegLen)
-                                ? swap_moments_reg<kMapRegLen>(w.fw, e, n)
-                                : swap_moments_lds(w.fw, e, n, lk);
+      const SwapMoments S = (m.max_len <= REG) ? swap_moments_reg<REG>(w.fw, e, n)
+                                               : swap_moments_lds(w.fw, e, n, lk);
       const double V = S.V, suma = S.suma, Sb = S.Sb, Sbb = S.Sbb;
       bad |= S.bad;
       const double Nb = fma(eta2 * Sb, Sb, (1.0 - eta2) * Sbb);
@@ -459,6 +462,8 @@ template <int MODEL, int FORMULA, int RESID>
 __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt *um,
                              const double *p, double xl, WaveLds w, double *resid,
                              double *model) {
+  constexpr bool LMM = (MODEL == 1 || MODEL == 5);   // 5: LMM12, 24-register swap column
+  constexpr int REG = (MODEL == 5) ? 24 : kMapRegLen;
   const int lane = lane_id();
   bool bad = false;
   SabrConst g{};
@@ -469,7 +474,7 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
     g = sabr_const(p[0], p[1], p[2], p[3]);
     omb = 1.0 - p[1];
     omb2 = omb * omb;
-  } else if (MODEL == 1) {
+  } else if (LMM) {
     bad = lmm12_fwd(m, in, p, w);   // the underlyings follow chunk by chunk
     omb = 1.0 - m.beta;
   } else if (MODEL == 2) {
@@ -540,14 +545,15 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
       quote(Rb, q + kWave, toff);
     }
   };
-  if (MODEL == 1) {
-    // LMM12: the underlyings' SABR constants chunk by chunk (kThChunk of
+  if (LMM) {
+    // LMM12: the underlyings' SABR constants chunk by chunk (thchunk of
     // them in LDS at a time), each followed by its underlyings' quotes (a
     // contiguous range in the internal order)
     const int *uq0 = m.u_q0 + in.u0;
-    for (int c0 = 0; c0 < in.nu; c0 += kThChunk) {
-      const int c1 = min(in.nu, c0 + kThChunk);
-      bad |= lmm12_und<FORMULA>(m, in, um, p, w, c0, c1);
+    const int chunk = m.thchunk;
+    for (int c0 = 0; c0 < in.nu; c0 += chunk) {
+      const int c1 = min(in.nu, c0 + chunk);
+      bad |= lmm12_und<FORMULA, REG>(m, in, um, p, w, c0, c1);
       quotes(uq0[c0], c1 < in.nu ? uq0[c1] : in.nq, c0);
       wave_lds_sync();   // the next chunk overwrites the constants
     }

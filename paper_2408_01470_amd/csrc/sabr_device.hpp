@@ -58,6 +58,11 @@ struct alignas(16) UndMap {
 struct DevMarket {
   int n_inst, model, formula, residual;
   int np;                // parameters per point (3 per forward for PERFWD)
+  int thchunk;           // LMM12: underlyings whose SABR constants the cost kernels
+                         // hold in LDS at a time
+  int reglen;            // LMM12: swaps of up to this many forwards keep the map's
+                         // recursion column in registers in the cost kernels
+                         // (16 or 24; longer ones use an LDS column)
   double beta;           // fixed beta (LMM12, PERFWD)
   int max_nq, max_nu, max_nf, max_len;
   const DevInst *inst;

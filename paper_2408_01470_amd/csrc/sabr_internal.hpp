@@ -18,21 +18,35 @@ constexpr int kMapRegLen = 16;
 // (for swaps longer than kMapRegLen) a per-lane column of max_len doubles for
 // the swap recursion.
 // Each workgroup adds 6 doubles per underlying of market values.
-// The cost evaluation (point_cost) takes the LMM12 underlyings kThChunk at
-// a time, so its table holds min(max_nu, kThChunk) records; the adjoint's
-// whole-map table (full) holds max_nu.
-constexpr int kThChunk = 128;
+// The cost evaluation (point_cost) takes the LMM12 underlyings thchunk at a
+// time (128, or 64 for markets of more than 128 underlyings), so its table
+// holds min(max_nu, thchunk) records; the adjoint's whole-map table (full)
+// holds max_nu.
+__host__ __device__ inline int th_chunk_for(int max_nu) { return max_nu <= 128 ? 128 : 64; }
 // Waves (chains) per annealing workgroup at most: the instance's market
 // values staged in LDS are shared by the workgroup's waves.
 constexpr int kMaxWavesPerGroup = 8;
 __host__ __device__ inline int th_entries(const DevMarket &m, bool full) {
-  return (m.model == 1 && !full && m.max_nu > kThChunk) ? kThChunk : m.max_nu;
+  return (m.model == 1 && !full && m.max_nu > m.thchunk) ? m.thchunk : m.max_nu;
+}
+
+// Whether the wave's layout holds the per-lane LDS column of the swap
+// recursion: swaps longer than kMapRegLen, unless the cost kernels keep them
+// in registers (reglen; the adjoint's whole map always uses the column).
+__host__ __device__ inline bool lds_column(const DevMarket &m, bool full) {
+  return m.max_len > kMapRegLen && (full || m.reglen < m.max_len);
 }
 
 __host__ __device__ inline int wave_lds_doubles(const DevMarket &m, bool full = false) {
   if (m.model == 0) return 0;
   return 6 * m.max_nf + kSabrConstDoubles * th_entries(m, full) +
-         (m.max_len > kMapRegLen ? kWave * m.max_len : 0);
+         (lds_column(m, full) ? kWave * m.max_len : 0);
+}
+
+// Kernel variant of a plan: the model, or 5 for LMM12 with the swap column in
+// 24 registers (swaps of 17 to 24 forwards).
+__host__ __device__ inline int kernel_model(const DevMarket &m) {
+  return (m.model == 1 && m.reglen == 24) ? 5 : m.model;
 }
 
 // Steps whose uniforms one Philox pass of the annealing kernel produces: a

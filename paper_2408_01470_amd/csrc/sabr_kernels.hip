@@ -491,6 +491,12 @@ hipError_t launch_prep(const DevMarket &m, QuoteRec *q, double *f_v, double *u_S
       } else {                                                       \
         if ((RESID_) == 0) { CALL(2, 1, 0); } else { CALL(2, 1, 1); } \
       }                                                              \
+    } else if ((MODEL_) == 5) {                                      \
+      if ((FORMULA_) == 0) {                                         \
+        if ((RESID_) == 0) { CALL(5, 0, 0); } else { CALL(5, 0, 1); } \
+      } else {                                                       \
+        if ((RESID_) == 0) { CALL(5, 1, 0); } else { CALL(5, 1, 1); } \
+      }                                                              \
     } else if ((MODEL_) == 3) {                                      \
       if ((FORMULA_) == 0) {                                         \
         if ((RESID_) == 0) { CALL(3, 0, 0); } else { CALL(3, 0, 1); } \
@@ -543,7 +549,7 @@ hipError_t launch_cost(const DevMarket &m, int n_pts, const int *pt_inst, const 
 #define CALL(A, B, C)                                                                      \
   hipLaunchKernelGGL((cost_kernel<A, B, C>), grid, block, lds, s, m, n_pts, pt_inst, params, \
                      cost, resid, model, stride, ld)
-  SABR_SELECT(m.model, m.formula, m.residual, CALL);
+  SABR_SELECT(kernel_model(m), m.formula, m.residual, CALL);
 #undef CALL
   return hipGetLastError();
 }
@@ -555,7 +561,7 @@ hipError_t launch_sa_init(const DevMarket &m, const SAArgs &a, int n_tiles, int 
 #define CALL(A, B, C)                                                                    \
   hipLaunchKernelGGL((sa_init_kernel<A, B, C>), dim3(n_tiles), dim3(kWave * waves), lds, s, \
                      m, a, ld)
-  SABR_SELECT(m.model, m.formula, m.residual, CALL);
+  SABR_SELECT(kernel_model(m), m.formula, m.residual, CALL);
 #undef CALL
   return hipGetLastError();
 }
@@ -576,7 +582,7 @@ hipError_t launch_sa_level(const DevMarket &m, const SAArgs &a, int level, int n
     else                           \
       LAUNCH(A, B, C, 1);          \
   } while (0)
-  SABR_SELECT(m.model, m.formula, m.residual, CALL);
+  SABR_SELECT(kernel_model(m), m.formula, m.residual, CALL);
 #undef CALL
 #undef LAUNCH
   return hipGetLastError();

@@ -221,12 +221,13 @@ hipError_t launch_nm(const DevMarket &m, int n_pts, const int *pt_inst, double *
       if (m.residual == 0) CALL(A, 1, 0); else CALL(A, 1, 1); \
     }                                                     \
   } while (0)
-  switch (m.model) {
+  switch (kernel_model(m)) {
     case 0: SEL_FR(0); break;
     case 1: SEL_FR(1); break;
     case 2: SEL_FR(2); break;
     case 3: SEL_FR(3); break;
     case 4: SEL_FR(4); break;
+    case 5: SEL_FR(5); break;
     default: return hipErrorInvalidValue;
   }
 #undef SEL_FR
