@@ -296,3 +296,106 @@ def lm_polish(m, params, pt_inst, lb, ub, max_iter=50, mu0=1e-3, tol=1e-12):
                                   _p(lb, _f64p), _p(ub, _f64p), int(max_iter), ctypes.c_double(mu0),
                                   ctypes.c_double(tol), _p(f, _f64p), _p(it, _i32p)))
     return x, f, it
+
+
+# ---------------------------------------------------------------------------
+# Monte Carlo under the Hagan SABR/LIBOR dynamics (Sec. 2.1)
+# ---------------------------------------------------------------------------
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+
+
+def _mc_lib():
+    L = lib()
+    if not getattr(L, "_mc_ready", False):
+        L.oracle_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.oracle_mc_normals.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_int32, _f64p]
+        L.oracle_mc_steps.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.oracle_mc_steps.restype = ctypes.c_int32
+        L.oracle_mc_paths.argtypes = ([ctypes.c_int32] + [_f64p] * 8 + [ctypes.c_double, _f64p,
+                                      ctypes.c_int32, _i32p, _i32p, _f64p, ctypes.c_int64,
+                                      ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, _f64p])
+        L.oracle_mc_paths.restype = ctypes.c_int32
+        L._mc_ready = True
+    return L
+
+
+def philox4x32(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _mc_lib().oracle_philox4x32_10(_p(c, _u32p), _p(k, _u32p), _p(out, _u32p))
+    return out
+
+
+def mc_normals(seed, path, step, M):
+    xi = np.zeros(2 * M)
+    _mc_lib().oracle_mc_normals(int(seed), int(path), int(step), int(M), _p(xi, _f64p))
+    return xi
+
+
+def mc_steps(length, dt):
+    return _mc_lib().oracle_mc_steps(float(length), float(dt))
+
+
+def mc_corr_matrix(T, phi, y):
+    """The 2M x 2M correlation of (W_1..W_M, Z_1..Z_M) of Sec. 2.1: blocks rho
+    (eq. rhoij), phi with phi_{i,j} = E[dW_i dZ_j] (eq. phiij) and theta
+    (eq. thetaij)."""
+    T = np.asarray(T, float)
+    phi = np.asarray(phi, float)
+    eta1, lam1, eta2, lam2, lam3 = [float(v) for v in y]
+    dT = np.abs(T[:, None] - T[None, :])
+    rho = eta1 + (1.0 - eta1) * np.exp(-lam1 * dT)
+    theta = eta2 + (1.0 - eta2) * np.exp(-lam2 * dT)
+    ph = (np.sign(phi)[:, None] * np.sqrt(np.abs(phi[:, None] * phi[None, :]))
+          * np.exp(-lam3 * dT))
+    return np.block([[rho, ph], [ph.T, theta]])
+
+
+def mc_factor(T, phi, y):
+    """Correlation factor B with x = B xi (xi iid standard normal): the
+    spectral repair of Rebonato and Jaeckel (1999) of the matrix above --
+    eigenvalues clipped at zero, B = Q sqrt(Lambda+), rows rescaled to unit
+    length (B B^T = the matrix itself when it is positive semi-definite).
+    Columns in decreasing eigenvalue order, each eigenvector signed so that
+    its entry of largest magnitude is positive."""
+    C = mc_corr_matrix(T, phi, y)
+    lam, Q = np.linalg.eigh(C)
+    order = np.argsort(-lam, kind="stable")
+    lam, Q = lam[order], Q[:, order]
+    for c in range(Q.shape[1]):
+        if Q[np.argmax(np.abs(Q[:, c])), c] < 0.0:
+            Q[:, c] = -Q[:, c]
+    B = Q * np.sqrt(np.maximum(lam, 0.0))[None, :]
+    nrm = np.sqrt((B * B).sum(axis=1))
+    return B / np.where(nrm > 0.0, nrm, 1.0)[:, None]
+
+
+def mc_paths(prob, n_paths, dt, seed, path0=0, B=None):
+    """Discounted payoff [n_paths][n_opt] of every option on paths path0 ..
+    path0 + n_paths - 1 (see oracle_mc_paths)."""
+    f = {k: np.ascontiguousarray(prob[k], dtype=np.float64)
+         for k in ("T", "tau", "F0", "alpha", "beta", "phi", "sigma", "y", "opt_K")}
+    a = np.ascontiguousarray(prob["opt_a"], dtype=np.int32)
+    b = np.ascontiguousarray(prob["opt_b"], dtype=np.int32)
+    M = len(f["T"])
+    if B is None:
+        B = mc_factor(f["T"], f["phi"], f["y"])
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    X = np.zeros((int(n_paths), len(a)))
+    _check(_mc_lib().oracle_mc_paths(
+        M, _p(f["T"], _f64p), _p(f["tau"], _f64p), _p(f["F0"], _f64p), _p(f["alpha"], _f64p),
+        _p(f["beta"], _f64p), _p(f["phi"], _f64p), _p(f["sigma"], _f64p), _p(f["y"], _f64p),
+        float(prob["P0"]), _p(B, _f64p), len(a), _p(a, _i32p), _p(b, _i32p), _p(f["opt_K"], _f64p),
+        int(path0), int(n_paths), float(dt), int(seed), _p(X, _f64p)))
+    return X
+
+
+def mc_price(prob, n_paths, dt, seed, B=None):
+    """Monte Carlo price and standard error of every option."""
+    X = mc_paths(prob, n_paths, dt, seed, B=B)
+    n = X.shape[0]
+    mean = X.mean(axis=0)
+    se = X.std(axis=0, ddof=1) / np.sqrt(n) if n > 1 else np.zeros(X.shape[1])
+    return mean, se

@@ -959,6 +959,88 @@ void nm_one(const Inst &I, int P, double *p, const double *lb, const double *ub,
 }  // namespace
 
 // ===========================================================================
+// Monte Carlo pricing under the Hagan SABR/LIBOR dynamics (Sec. 2.1: eqs.
+// (dinamicasHagan1), (dinamicasHagan2), the spot-measure drifts with the
+// first unfixed index h(t) of eq. (h_t), the bank-account numeraire, and the
+// correlations of eqs. (rhoij), (thetaij), (phiij)); the pricer the paper
+// nests in its swaption cost S_MC (Sec. 3) and times in Table
+// (haganMCpricer).  The paper gives no discretisation; the readings below
+// are this oracle's definition.
+//
+//  - Forwards k = 0..M-1: F_k fixes at T_k and accrues tau_k until the next
+//    date; during [T_{j-1}, T_j) (T_{-1} = 0) the alive forwards are k >= j.
+//  - Each interval [T_{j-1}, T_j) is cut into n_j = ceil(len / dt) (at least
+//    one) equal steps of h = len / n_j; global step counter s = 0, 1, ...
+//  - Step, for alive k with pre-step values:
+//      s_k = V_k max(F_k, 0)^beta_k,  d_i = tau_i s_i / (1 + tau_i F_i),
+//      F_k <- max(F_k + s_k h sum_{i=j..k} rho_{k,i} d_i + s_k x_k, 0),
+//      V_k <- V_k exp((sigma_k sum_{i=j..k} phi_{i,k} d_i - sigma_k^2 / 2) h
+//                     + sigma_k x_{M+k}),
+//    with phi_{i,k} = E[dW_i dZ_k] (the covariance of Z_k with the
+//    numeraire's drivers) and x = sqrt(h) B xi, B (2M x 2M, rows W_0..W_{M-1},
+//    Z_0..Z_{M-1}) the correlation factor given by the caller, xi the step's
+//    2M standard normals.
+//  - Normals: pair m = 0..M-1 of step s on path p is Box-Muller of Philox4x32-10
+//    block (counter (m, s, p mod 2^32, p / 2^32), key (seed mod 2^32,
+//    seed / 2^32)): words (w0, w1) give u1 = (w0 2^21 + (w1 >> 11) + 1) 2^-53,
+//    (w2, w3) give u2 = (w2 2^21 + (w3 >> 11)) 2^-53;  r = sqrt(-2 ln u1),
+//    t = 2 pi u2, xi_{2m} = r cos t, xi_{2m+1} = r sin t.
+//  - Deflator D = P(0, T_0) at t = 0, divided by (1 + tau_j F_j(T_j)) at each
+//    fixing T_j after the payoffs expiring there are taken.
+//  - Option (a, b, K): payer swaption expiring at T_a on forwards a..b-1
+//    (b = a + 1: the caplet on F_a), value at T_a
+//      max(1 - P(T_a, T_b) - K sum_{i=a}^{b-1} tau_i P(T_a, T_{i+1}), 0),
+//    P(T_a, T_{i+1}) = prod_{l=a}^{i} 1 / (1 + tau_l F_l(T_a)); the path's
+//    discounted payoff is D times that.
+// ===========================================================================
+namespace {
+
+void philox4x32_10(const uint32_t in[4], const uint32_t key_in[2], uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t c[4] = {in[0], in[1], in[2], in[3]};
+  uint32_t k[2] = {key_in[0], key_in[1]};
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)M0 * c[0];
+    const uint64_t p1 = (uint64_t)M1 * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k[0];
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k[1];
+    c[0] = n0;
+    c[1] = (uint32_t)p1;
+    c[2] = n2;
+    c[3] = (uint32_t)p0;
+    k[0] += W0;
+    k[1] += W1;
+  }
+  for (int j = 0; j < 4; ++j) out[j] = c[j];
+}
+
+void mc_normals(uint64_t seed, int64_t path, int64_t step, int M, double *xi) {
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int m = 0; m < M; ++m) {
+    const uint32_t ctr[4] = {(uint32_t)m, (uint32_t)step, (uint32_t)path,
+                             (uint32_t)((uint64_t)path >> 32)};
+    uint32_t w[4];
+    philox4x32_10(ctr, key, w);
+    const uint64_t a = ((uint64_t)w[0] << 21) + (w[1] >> 11);
+    const uint64_t b = ((uint64_t)w[2] << 21) + (w[3] >> 11);
+    const double u1 = (double)(a + 1) * 0x1.0p-53;
+    const double u2 = (double)b * 0x1.0p-53;
+    const double r = std::sqrt(-2.0 * std::log(u1));
+    const double t = 6.283185307179586 * u2;
+    xi[2 * m] = r * std::cos(t);
+    xi[2 * m + 1] = r * std::sin(t);
+  }
+}
+
+int mc_steps(double len, double dt) {
+  const double n = std::ceil(len / dt);
+  return n < 1.0 ? 1 : (int)n;
+}
+
+}  // namespace
+
+// ===========================================================================
 // C ABI
 // ===========================================================================
 extern "C" {
@@ -996,6 +1078,93 @@ double oracle_black_vega(double f, double K, double T, double sigma, double D) {
 }
 void oracle_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
   philox4x64_10(ctr, key, out);
+}
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  philox4x32_10(ctr, key, out);
+}
+void oracle_mc_normals(uint64_t seed, int64_t path, int64_t step, int32_t M, double *xi) {
+  mc_normals(seed, path, step, M, xi);
+}
+int32_t oracle_mc_steps(double len, double dt) { return mc_steps(len, dt); }
+
+int32_t oracle_mc_paths(int32_t M, const double *T, const double *tau, const double *F0,
+                        const double *alpha, const double *beta, const double *phi,
+                        const double *sigma, const double *y, double P0, const double *B,
+                        int32_t n_opt, const int32_t *opt_a, const int32_t *opt_b,
+                        const double *opt_K, int64_t path0, int64_t n_paths, double dt,
+                        uint64_t seed, double *X) {
+  if (M < 1) return fail("mc: need at least one forward");
+  if (!(dt > 0.0)) return fail("mc: dt must be positive");
+  if (n_paths < 0 || path0 < 0) return fail("mc: bad path range");
+  int amax = -1;
+  for (int o = 0; o < n_opt; ++o) {
+    if (opt_a[o] < 0 || opt_b[o] <= opt_a[o] || opt_b[o] > M)
+      return fail("mc: option " + std::to_string(o) + " needs 0 <= a < b <= M");
+    if (opt_a[o] > amax) amax = opt_a[o];
+  }
+  const double eta1 = y[0], lam1 = y[1], lam3 = y[4];
+  // rho_{k,i} (eq. rhoij) and phi_{i,k} = E[dW_i dZ_k] (eq. phiij)
+  std::vector<double> rho((size_t)M * M), phw((size_t)M * M);
+  for (int k = 0; k < M; ++k)
+    for (int i = 0; i < M; ++i) {
+      const double dT = std::fabs(T[k] - T[i]);
+      rho[(size_t)k * M + i] = eta1 + (1.0 - eta1) * std::exp(-lam1 * dT);
+      const double sg = phi[i] > 0.0 ? 1.0 : (phi[i] < 0.0 ? -1.0 : 0.0);
+      phw[(size_t)i * M + k] = sg * std::sqrt(std::fabs(phi[i] * phi[k])) * std::exp(-lam3 * dT);
+    }
+  const int n2 = 2 * M;
+#pragma omp parallel for schedule(static)
+  for (int64_t pp = 0; pp < n_paths; ++pp) {
+    const int64_t path = path0 + pp;
+    std::vector<double> F(F0, F0 + M), V(alpha, alpha + M), Fn(M), Vn(M), s(M), d(M);
+    std::vector<double> xi(n2), x(n2);
+    double D = P0;
+    int64_t step = 0;
+    double *Xp = X + pp * n_opt;
+    for (int j = 0; j <= amax; ++j) {
+      const double len = T[j] - (j > 0 ? T[j - 1] : 0.0);
+      const int n = mc_steps(len, dt);
+      const double h = len / n, sh = std::sqrt(h);
+      for (int st = 0; st < n; ++st, ++step) {
+        mc_normals(seed, path, step, M, xi.data());
+        for (int r = 0; r < n2; ++r) {
+          double acc = 0.0;
+          for (int c = 0; c < n2; ++c) acc += B[(size_t)r * n2 + c] * xi[c];
+          x[r] = sh * acc;
+        }
+        for (int k = j; k < M; ++k) {
+          s[k] = V[k] * std::pow(std::fmax(F[k], 0.0), beta[k]);
+          d[k] = tau[k] * s[k] / (1.0 + tau[k] * F[k]);
+        }
+        for (int k = j; k < M; ++k) {
+          double sr = 0.0, sv = 0.0;
+          for (int i = j; i <= k; ++i) {
+            sr += rho[(size_t)k * M + i] * d[i];
+            sv += phw[(size_t)i * M + k] * d[i];
+          }
+          Fn[k] = std::fmax(F[k] + s[k] * sr * h + s[k] * x[k], 0.0);
+          Vn[k] = V[k] * std::exp((sigma[k] * sv - 0.5 * sigma[k] * sigma[k]) * h +
+                                  sigma[k] * x[M + k]);
+        }
+        for (int k = j; k < M; ++k) {
+          F[k] = Fn[k];
+          V[k] = Vn[k];
+        }
+      }
+      // fixing of F_j at T_j: payoffs expiring here, then the numeraire
+      for (int o = 0; o < n_opt; ++o) {
+        if (opt_a[o] != j) continue;
+        double Pb = 1.0, A = 0.0;
+        for (int i = j; i < opt_b[o]; ++i) {
+          Pb /= (1.0 + tau[i] * F[i]);
+          A += tau[i] * Pb;
+        }
+        Xp[o] = D * std::fmax(1.0 - Pb - opt_K[o] * A, 0.0);
+      }
+      D /= (1.0 + tau[j] * F[j]);
+    }
+  }
+  return 0;
 }
 
 int32_t oracle_underlyings(const oracle_market *m, int32_t inst, double *S0, double *A,

@@ -144,6 +144,27 @@ int32_t oracle_nm_polish(const oracle_market *m, int32_t n_pts, const int32_t *p
                          double *params, const double *lb, const double *ub, int32_t max_iter,
                          double step, double tol, double *cost_out, int32_t *iters_out);
 
+/* Philox4x32-10 block (Salmon et al., SC 2011). */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* The 2M standard normals of Monte Carlo step `step` on path `path`. */
+void oracle_mc_normals(uint64_t seed, int64_t path, int64_t step, int32_t M, double *xi);
+
+/* Steps of a fixing interval of length len at step size dt. */
+int32_t oracle_mc_steps(double len, double dt);
+
+/* Monte Carlo under the Hagan SABR/LIBOR dynamics (Sec. 2.1) under the spot
+ * measure: X[p][o] = discounted payoff of option o (payer swaption
+ * (opt_a, opt_b, opt_K); opt_b = opt_a + 1: caplet) on path path0 + p.
+ * Forward arrays [M]; y = (eta1, lambda1, eta2, lambda2, lambda3); B [2M][2M]
+ * the correlation factor (rows W_0..W_{M-1}, Z_0..Z_{M-1}); P0 = P(0, T_0). */
+int32_t oracle_mc_paths(int32_t M, const double *T, const double *tau, const double *F0,
+                        const double *alpha, const double *beta, const double *phi,
+                        const double *sigma, const double *y, double P0, const double *B,
+                        int32_t n_opt, const int32_t *opt_a, const int32_t *opt_b,
+                        const double *opt_K, int64_t path0, int64_t n_paths, double dt,
+                        uint64_t seed, double *X);
+
 #ifdef __cplusplus
 }
 #endif

@@ -472,3 +472,82 @@ def global4_points_as_perfwd(y):
     """Inverse of ``perfwd_points_as_global4`` (drops beta)."""
     y = np.asarray(y, float)
     return y[:, [0, 2, 3]].ravel()
+
+
+# ---------------------------------------------------------------------------
+# Monte Carlo pricing problems (the Hagan SABR/LIBOR dynamics of Sec. 2.1)
+# ---------------------------------------------------------------------------
+# Correlation parameters y = (eta1, lambda1, eta2, lambda2, lambda3) of the
+# paper's Hagan swaption calibration (Sec. 4.1.2).
+PAPER_HAGAN_CORR = (0.814904, 3.378797, 0.975928, 3.777324, 0.013940)
+
+
+def mc_problem_arrays(T, tau, F0, alpha, beta, phi, sigma, y, P0, opt_a, opt_b, opt_K):
+    """A Monte Carlo pricing problem as a dict of arrays (forward arrays [M],
+    y [5], options (a, b, K): payer swaption expiring at T_a on forwards
+    a..b-1, b = a + 1 the caplet on F_a)."""
+    M = len(T)
+
+    def f(v):
+        v = np.asarray(v, float)
+        if v.ndim == 0:
+            return np.full(M, float(v))
+        assert v.shape == (M,), "forward arrays need one entry per forward"
+        return v.copy()
+    return dict(T=f(T), tau=f(tau), F0=f(F0), alpha=f(alpha), beta=f(beta), phi=f(phi),
+                sigma=f(sigma), y=np.asarray(y, float).copy(), P0=float(P0),
+                opt_a=np.asarray(opt_a, np.int32).copy(), opt_b=np.asarray(opt_b, np.int32).copy(),
+                opt_K=np.asarray(opt_K, float).copy())
+
+
+def paper_mc_problem(golden_dir=None, moneyness=PAPER_MONEYNESS, y=PAPER_HAGAN_CORR):
+    """The paper's caplet market (Sec. 4.1.1: 13 EURIBOR forwards, fixing
+    dates, accruals and forwards from the printed curve) under the Hagan
+    model with its printed caplet calibration (phi_ii, sigma_i, alpha_i;
+    beta = 0.5) and swaption correlations y; options: the 13 x 9 caplets
+    K = F_i exp(m) of the smiles table.  P0 = P(0, T_1) from the curve."""
+    m = paper_caplet_market(golden_dir)
+    prm = np.array([[float(v) for v in r[1:]] for r in _rows("paper_hagan_caplet_params.txt",
+                                                             golden_dir)])
+    T, tau, F = m["fwd_T"], m["fwd_tau"], m["fwd_F"]
+    P0 = float(m["fwd_P"][0] * (1.0 + tau[0] * F[0]))
+    M = len(T)
+    mny = np.asarray(moneyness, float)
+    a = np.repeat(np.arange(M), len(mny))
+    return mc_problem_arrays(T, tau, F, prm[:, 2], 0.5, prm[:, 0], prm[:, 1], y, P0, a, a + 1,
+                             F[a] * np.exp(np.tile(mny, M)))
+
+
+def mc_problem(seed=SEED_BASE + 9000, M=10, n_cap_K=3, n_swaptions=6, beta=None):
+    """Synthetic pricing problem: semi-annual fixings from 0.5y with jitter,
+    forwards 1-4%, lognormal-equivalent vols 15-40%, phi_ii in (-0.7, 0.3),
+    sigma_i in (0.1, 0.8), beta 0.5 (or uniform in [0.2, 1] when beta is
+    'random'); caplets on every forward at n_cap_K strikes around the
+    forward and n_swaptions random payer swaptions (a < b <= M) at strikes
+    around the mean of their forwards."""
+    g = rng(seed)
+    T = 0.5 * np.arange(1, M + 1) + g.uniform(-0.02, 0.02, M)
+    tau = 0.5 + g.uniform(0.0, 0.02, M)
+    F = g.uniform(0.01, 0.04, M)
+    if beta == "random":
+        bet = g.uniform(0.2, 1.0, M)
+    else:
+        bet = np.full(M, 0.5 if beta is None else float(beta))
+    alpha = g.uniform(0.15, 0.40, M) * F ** (1.0 - bet)
+    phi = g.uniform(-0.7, 0.3, M)
+    sigma = g.uniform(0.1, 0.8, M)
+    y = (g.uniform(0.5, 0.9), g.uniform(0.5, 4.0), g.uniform(0.5, 0.95), g.uniform(0.5, 4.0),
+         g.uniform(0.0, 0.5))
+    P0 = float(np.exp(-0.02 * T[0]))
+    mny = np.linspace(-0.3, 0.3, n_cap_K) if n_cap_K > 1 else np.zeros(1)
+    ca = np.repeat(np.arange(M), len(mny))
+    K = list(F[ca] * np.exp(np.tile(mny, M)))
+    a = list(ca)
+    b = list(ca + 1)
+    for _ in range(n_swaptions):
+        sa = int(g.integers(0, M - 1)) if M > 1 else 0
+        sb = int(g.integers(sa + 1, M + 1))
+        a.append(sa)
+        b.append(sb)
+        K.append(float(F[sa:sb].mean() * np.exp(g.uniform(-0.3, 0.3))))
+    return mc_problem_arrays(T, tau, F, alpha, bet, phi, sigma, y, P0, a, b, K)
