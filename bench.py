@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--no-paper-e2", action="store_true",
                     help="skip the replay of the paper's timed caplet calibration")
     ap.add_argument("--paper-e2-only", action="store_true")
+    ap.add_argument("--no-paper-mc", action="store_true",
+                    help="skip the replay of the paper's Monte Carlo pricing table")
+    ap.add_argument("--paper-mc-only", action="store_true")
     ap.add_argument("--paper-reb-only", action="store_true",
                     help="replay the paper's Rebonato caplet calibration (2.25e9 evaluations)")
     ap.add_argument("--adjoint-only", action="store_true",
@@ -401,6 +404,91 @@ def paper_e2(api, W, I, flops, autotune, shape=None, which="e2"):
     return out
 
 
+# Table (haganMCpricer): caplet pricing by Monte Carlo in the Hagan model,
+# (paths, dt, CPU s, GPU s) on an Intel E5620 and one GTX 470 (single
+# precision; context, not a target).
+PAPER_MC_TABLE = [
+    (10**3, 1e-1, 0.558, 0.094), (10**3, 1e-2, 5.580, 0.222), (10**3, 1e-3, 55.956, 1.406),
+    (10**4, 1e-1, 5.572, 0.119), (10**4, 1e-2, 55.740, 0.390), (10**4, 1e-3, 557.698, 3.081),
+    (10**5, 1e-1, 55.692, 0.323), (10**5, 1e-2, 558.331, 2.886), (10**5, 1e-3, 5601.292, 28.550),
+    (10**6, 1e-1, 557.696, 2.375), (10**6, 1e-2, 5588.070, 27.950),
+    (10**6, 1e-3, 55904.184, 283.970),
+]
+
+
+def paper_mc(api, I, flops, cpu=True):
+    """Replay of the paper's Monte Carlo pricing table: the 117 caplets of its
+    EURIBOR market (13 forwards, fixings to 6.5 years) under the Hagan model
+    at its printed calibration (phi_ii, sigma_i, alpha_i, beta = 0.5) and
+    swaption correlations, every (paths, dt) cell of the table, FP64.  Device
+    time of sabr_mc_price (HIP events on the launch stream; the plan is
+    resident); path-steps/s; the level of the largest cell against the 78.6
+    TFLOP/s FP64 peak (algorithmic FLOP of flops.mc_launch_flops); the mean
+    absolute error of the 1e6-path prices against the market's Black prices
+    (caplet price = P(0, pay) tau Black(F, K, T, vol), in % of notional as the
+    paper prints it); and, with cpu, the oracle on a bounded sample."""
+    import torch
+    from scipy.stats import norm
+    prob = I.paper_mc_problem()
+    plan = api.McPlan(prob)
+    stream = torch.cuda.current_stream()
+    seed = 2408
+    plan.price(1000, 0.1, seed)
+    torch.cuda.synchronize()
+    cells = []
+    big = None
+    for n, dt, cpu_s, gpu_s in PAPER_MC_TABLE:
+        reps = 3 if n * (0.1 / dt) <= 10**6 else 1
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            price, se = plan.price(n, dt, seed)
+            e1.record(stream)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        t = min(ms) / 1e3
+        steps = flops.mc_path_steps(prob, n, dt)
+        cells.append({"paths": n, "dt": dt, "s": t, "path_steps_per_s": steps / t,
+                      "paper_gpu_s": gpu_s, "paper_cpu_s": cpu_s,
+                      "speedup_vs_paper_gpu": gpu_s / t})
+        if n == 10**6 and dt == 1e-3:
+            big = (t, price.cpu().numpy(), se.cpu().numpy())
+    t, price, se = big
+    fl = flops.mc_launch_flops(prob, 10**6, 1e-3)
+    # market prices from the smiles table's vols
+    mk = I.paper_caplet_market()
+    a = prob["opt_a"]
+    F, T, tau, K = prob["F0"][a], prob["T"][a], prob["tau"][a], prob["opt_K"]
+    pay = mk["fwd_P"][a]
+    vol = mk["q_vol"]
+    sd = vol * np.sqrt(T)
+    d1 = (np.log(F / K) + 0.5 * sd * sd) / sd
+    mkt = pay * tau * (F * norm.cdf(d1) - K * norm.cdf(d1 - sd))
+    out = {
+        "workload": "the paper's Monte Carlo caplet pricing: 117 caplets, 13 EURIBOR forwards, "
+                    "Hagan model at the printed calibration, spot measure, FP64",
+        "cells": cells,
+        "largest_cell": {"paths": 10**6, "dt": 1e-3, "s": t,
+                         "tflops": fl / t / 1e12, "fp64_frac": fl / t / 78.6e12,
+                         "flop": fl},
+        "mae_vs_market_pct": float(np.mean(np.abs(price - mkt)) * 100.0),
+        "max_stderr_pct": float(se.max() * 100.0),
+        "paper": {"mae_mc_pct": 4.08e-2, "mae_formula_pct": 4.14e-2,
+                  "hardware": "one GTX 470, single precision (context, not a target)"},
+    }
+    if cpu:
+        from oracle import oracle as O
+        n_cpu, dt_cpu = 2000, 1e-2
+        t0 = time.perf_counter()
+        O.mc_paths(prob, n_cpu, dt_cpu, seed)
+        tc = time.perf_counter() - t0
+        out["cpu_oracle"] = {"paths": n_cpu, "dt": dt_cpu, "s": tc,
+                             "path_steps_per_s": flops.mc_path_steps(prob, n_cpu, dt_cpu) / tc,
+                             "threads": int(O.max_threads()), "kind": "oracle"}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -422,6 +510,9 @@ def main():
     if args.paper_e2_only:
         print(json.dumps(paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape)))
         print(json.dumps(paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape, "mm")))
+        return
+    if args.paper_mc_only:
+        print(json.dumps(paper_mc(api, I, flops, not args.no_cpu_baseline)))
         return
     if args.paper_reb_only:
         print(json.dumps(paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape, "reb")))
@@ -542,6 +633,8 @@ def main():
     if not args.no_paper_e2:
         out["paper_e2"] = paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape)
         out["paper_mm"] = paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape, "mm")
+    if not args.no_paper_mc:
+        out["paper_mc"] = paper_mc(api, I, flops, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_levels, w.n_levels))
     print(json.dumps(out))

@@ -289,6 +289,77 @@ sabr_status sabr_nm_polish(const sabr_plan *plan, int32_t n_pts, const int32_t *
                            double step, double tol, double *cost_out, int32_t *iters_out,
                            void *workspace, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Monte Carlo pricer of caplets and swaptions under the Hagan SABR/LIBOR
+ * dynamics (Sec. 2.1: eqs. (dinamicasHagan1), (dinamicasHagan2) under the
+ * spot measure with the drifts mu^F, mu^V, the first unfixed index h(t) of
+ * eq. (h_t) and the bank-account numeraire; correlations eqs. (rhoij),
+ * (thetaij), (phiij)): the pricer S_MC that the paper nests in its swaption
+ * cost (Sec. 3) and times in Table (haganMCpricer).
+ *
+ * Forward k (k = 0..n_fwd-1) fixes at T[k] and accrues tau[k]; during
+ * [T[j-1], T[j]) (T[-1] = 0) the alive forwards are k >= j.  Each such
+ * interval is cut into ceil(length / dt) (at least one) equal steps; a step
+ * moves F_k by Euler (floored at 0) and V_k by log-Euler, driven by
+ * x = sqrt(h) B xi where B is the plan's correlation factor (below) and xi
+ * the step's 2 n_fwd standard normals: pair m of step s on path p is the
+ * Box-Muller transform of the Philox4x32-10 block at counter (m, s, p mod
+ * 2^32, p / 2^32) and key (seed mod 2^32, seed / 2^32), words (w0, w1) and
+ * (w2, w3) giving the 53-bit uniforms u1 = (w0 2^21 + (w1 >> 11) + 1) 2^-53
+ * and u2 = (w2 2^21 + (w3 >> 11)) 2^-53.  The drift of V_k takes the
+ * covariance of Z_k with W_i, phi_{i,k}.  At T[a] option (a, b, K) pays
+ * max(1 - P(T_a, T_b) - K sum_{i=a}^{b-1} tau_i P(T_a, T_{i+1}), 0)
+ * (a payer swaption on forwards a..b-1; b = a + 1 is the caplet on F_a),
+ * deflated by P0 / prod_{j<a} (1 + tau_j F_j(T_j)).
+ *
+ * Correlation factor: the 2 n_fwd x 2 n_fwd matrix of (W_0.., Z_0..) need
+ * not be positive semi-definite (the paper's calibrated Hagan parameters
+ * give an indefinite one); B is its spectral repair (Rebonato and Jaeckel
+ * 1999: eigenvalues clipped at 0, B = Q sqrt(Lambda+), rows rescaled to unit
+ * length; columns by decreasing eigenvalue, each eigenvector signed so that
+ * its first entry of largest magnitude is positive), computed on the host
+ * when the plan is created.  B B^T is the matrix itself when it is positive
+ * semi-definite.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n_fwd;             /* 1..16 */
+  const double *T;           /* [n_fwd] fixing times, 0 < T[0] < T[1] < ... */
+  const double *tau;         /* [n_fwd] accrual fractions > 0 */
+  const double *F0;          /* [n_fwd] initial forwards > 0 */
+  const double *alpha;       /* [n_fwd] V_k(0) > 0 */
+  const double *beta;        /* [n_fwd] in [0, 1] */
+  const double *phi;         /* [n_fwd] phi_kk, |phi_kk| <= 1 */
+  const double *sigma;       /* [n_fwd] vol of vol >= 0 */
+  double eta1, lambda1, eta2, lambda2, lambda3;  /* eta in [0, 1], lambda >= 0 */
+  double P0;                 /* P(0, T[0]) > 0 */
+  int32_t n_opt;             /* >= 1 */
+  const int32_t *opt_a;      /* [n_opt] expiry index a */
+  const int32_t *opt_b;      /* [n_opt] end index b, a < b <= n_fwd */
+  const double *opt_K;       /* [n_opt] strike */
+} sabr_mc_problem;           /* every array [host] */
+
+typedef struct sabr_mc_plan sabr_mc_plan; /* opaque; host memory only */
+
+/* Validate the problem and build its image (host only: no GPU call). */
+sabr_status sabr_mc_plan_create(const sabr_mc_problem *prob /*[host]*/, sabr_mc_plan **out);
+void sabr_mc_plan_destroy(sabr_mc_plan *plan);
+/* Bytes of the device image; sabr_mc_plan_upload copies it into the
+ * caller's 8-byte aligned device buffer and synchronises the stream. */
+size_t sabr_mc_plan_device_bytes(const sabr_mc_plan *plan);
+sabr_status sabr_mc_plan_upload(sabr_mc_plan *plan, void *dev_buf, size_t bytes, void *stream);
+/* The correlation factor B [2 n_fwd][2 n_fwd] (row-major, [host]). */
+sabr_status sabr_mc_factor(const sabr_mc_plan *plan, double *B);
+/* Workspace bytes of sabr_mc_price for n_paths paths (0 if invalid). */
+size_t sabr_mc_workspace_size(const sabr_mc_plan *plan, int64_t n_paths);
+/* Price every option over paths 0..n_paths-1 (1 <= n_paths <= 2^40; at
+ * most 2^31 time steps): price[o] the mean discounted payoff, stderr_out[o]
+ * (may be NULL) its standard error (sample standard deviation / sqrt(n)),
+ * both [n_opt] device arrays in the caller's option order.  The results
+ * depend only on the problem, n_paths, dt and seed. */
+sabr_status sabr_mc_price(const sabr_mc_plan *plan, int64_t n_paths, double dt, uint64_t seed,
+                          double *price, double *stderr_out, void *workspace, size_t ws_bytes,
+                          void *stream);
+
 /* Last error message of the calling thread ("" if none). */
 const char *sabr_last_error(void);
 

@@ -26,6 +26,17 @@ class SabrProblem(ctypes.Structure):
     ]
 
 
+class SabrMcProblem(ctypes.Structure):
+    _fields_ = [
+        ("n_fwd", ctypes.c_int32),
+        ("T", _f64p), ("tau", _f64p), ("F0", _f64p), ("alpha", _f64p), ("beta", _f64p),
+        ("phi", _f64p), ("sigma", _f64p),
+        ("eta1", ctypes.c_double), ("lambda1", ctypes.c_double), ("eta2", ctypes.c_double),
+        ("lambda2", ctypes.c_double), ("lambda3", ctypes.c_double), ("P0", ctypes.c_double),
+        ("n_opt", ctypes.c_int32), ("opt_a", _i32p), ("opt_b", _i32p), ("opt_K", _f64p),
+    ]
+
+
 class SAConfig(ctypes.Structure):
     _fields_ = [
         ("T0", ctypes.c_double), ("cool", ctypes.c_double), ("step_frac", ctypes.c_double),
@@ -82,6 +93,17 @@ def lib():
     L.sabr_nm_polish.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _f64p, _f64p, ctypes.c_int32,
                                  ctypes.c_double, ctypes.c_double, _vp, _vp, _vp,
                                  ctypes.c_size_t, _vp]
+    L.sabr_mc_plan_create.argtypes = [ctypes.POINTER(SabrMcProblem), ctypes.POINTER(_vp)]
+    L.sabr_mc_plan_destroy.argtypes = [_vp]
+    L.sabr_mc_plan_destroy.restype = None
+    L.sabr_mc_plan_device_bytes.argtypes = [_vp]
+    L.sabr_mc_plan_device_bytes.restype = ctypes.c_size_t
+    L.sabr_mc_plan_upload.argtypes = [_vp, _vp, ctypes.c_size_t, _vp]
+    L.sabr_mc_factor.argtypes = [_vp, _f64p]
+    L.sabr_mc_workspace_size.argtypes = [_vp, ctypes.c_int64]
+    L.sabr_mc_workspace_size.restype = ctypes.c_size_t
+    L.sabr_mc_price.argtypes = [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, _vp, _vp,
+                                _vp, ctypes.c_size_t, _vp]
     _lib = L
     return _lib
 

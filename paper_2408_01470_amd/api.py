@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import SAConfig, SabrProblem, check, lib
+from ._lib import SAConfig, SabrMcProblem, SabrProblem, check, lib
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)
@@ -273,3 +273,69 @@ def sabr_cost(plan: Plan, params, pt_inst=None):
     if pt_inst is None:
         pt_inst = torch.zeros(n, dtype=torch.int32, device=plan.device)
     return SabrCost.apply(params.reshape(-1, plan.P), plan, pt_inst)
+
+
+class McProblem:
+    """A validated Monte Carlo pricing problem (host only: the plan and its
+    correlation factor; see sabr_mc_plan_create)."""
+
+    def __init__(self, prob: dict):
+        L = lib()
+        self._keep = {k: np.ascontiguousarray(prob[k], dtype=np.float64)
+                      for k in ("T", "tau", "F0", "alpha", "beta", "phi", "sigma", "opt_K")}
+        for k in ("opt_a", "opt_b"):
+            self._keep[k] = np.ascontiguousarray(prob[k], dtype=np.int32)
+        a = self._keep
+        f = lambda k: a[k].ctypes.data_as(_lib._f64p)
+        y = [float(v) for v in prob["y"]]
+        self.M = len(a["T"])
+        self.n_opt = len(a["opt_a"])
+        self._prob = SabrMcProblem(self.M, f("T"), f("tau"), f("F0"), f("alpha"), f("beta"),
+                                   f("phi"), f("sigma"), *y, float(prob["P0"]), self.n_opt,
+                                   a["opt_a"].ctypes.data_as(_lib._i32p),
+                                   a["opt_b"].ctypes.data_as(_lib._i32p), f("opt_K"))
+        h = ctypes.c_void_p()
+        check(L.sabr_mc_plan_create(ctypes.byref(self._prob), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        try:
+            if h is not None and _lib is not None and _lib._lib is not None:
+                _lib._lib.sabr_mc_plan_destroy(h)
+        except Exception:  # interpreter shutdown
+            pass
+        self._h = None
+
+    def factor(self):
+        B = np.zeros((2 * self.M, 2 * self.M))
+        check(lib().sabr_mc_factor(self._h, B.ctypes.data_as(_lib._f64p)))
+        return B
+
+
+class McPlan(McProblem):
+    """A Monte Carlo pricing problem uploaded to device memory."""
+
+    def __init__(self, prob: dict, device: str = "cuda", stream=None):
+        _require_gpu()
+        super().__init__(prob)
+        self.device = torch.device(device)
+        nbytes = int(lib().sabr_mc_plan_device_bytes(self._h))
+        self._dev = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        check(lib().sabr_mc_plan_upload(self._h, _ptr(self._dev), nbytes, _stream(stream)))
+        self._ws = None
+
+    def workspace(self, n_paths):
+        n = int(lib().sabr_mc_workspace_size(self._h, int(n_paths)))
+        if self._ws is None or self._ws.numel() < n:
+            self._ws = torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
+        return self._ws, n
+
+    def price(self, n_paths, dt, seed, stream=None):
+        """(price, standard error) of every option, float64 device tensors."""
+        price = torch.empty(self.n_opt, dtype=torch.float64, device=self.device)
+        se = torch.empty(self.n_opt, dtype=torch.float64, device=self.device)
+        ws, n = self.workspace(n_paths)
+        check(lib().sabr_mc_price(self._h, int(n_paths), float(dt), int(seed), _ptr(price),
+                                  _ptr(se), _ptr(ws), ws.numel(), _stream(stream)))
+        return price, se

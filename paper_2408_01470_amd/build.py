@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsabr_hip.so")
-SOURCES = ["sabr_kernels.hip", "sabr_adjoint.hip", "sabr_nm.hip", "sabr_api.cpp"]
+SOURCES = ["sabr_kernels.hip", "sabr_adjoint.hip", "sabr_nm.hip", "sabr_mc.hip", "sabr_api.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",

@@ -13,6 +13,7 @@
 #include "../../include/sabr.h"
 #include "sabr_adjoint.hpp"
 #include "sabr_internal.hpp"
+#include "sabr_mc_internal.h"
 
 using sabr::DevInst;
 using sabr::DevMarket;
@@ -32,6 +33,15 @@ sabr_status hip_fail(hipError_t e, const char *what) {
 }
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+}  // namespace
+
+namespace sabr {
+sabr_status mc_fail(sabr_status st, const std::string &msg) { return fail(st, msg); }
+sabr_status mc_hip_fail(hipError_t e, const char *what) { return hip_fail(e, what); }
+}  // namespace sabr
+
+namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 

@@ -1,0 +1,523 @@
+// sabr_mc.hip -- Monte Carlo pricer of caplets and swaptions under the Hagan
+// SABR/LIBOR dynamics (Sec. 2.1: eqs. (dinamicasHagan1), (dinamicasHagan2)
+// with their spot-measure drifts and the first unfixed index of eq. (h_t),
+// the bank-account numeraire, the correlations of eqs. (rhoij), (thetaij),
+// (phiij)): the pricer S_MC of the swaption cost (Sec. 3) and of Table
+// (haganMCpricer).
+//
+// Scheme (the paper gives none): within each fixing interval [T_{j-1}, T_j)
+// equal steps of at most dt; per step, with the alive forwards k >= j,
+//   s_k = V_k max(F_k, 0)^beta_k,  d_i = tau_i s_i / (1 + tau_i F_i),
+//   F_k <- max(F_k + s_k h sum_{i=j..k} rho_{k,i} d_i + s_k x_k, 0)      (Euler)
+//   V_k <- V_k exp((sigma_k sum_{i=j..k} phi_{i,k} d_i - sigma_k^2/2) h
+//                  + sigma_k x_{M+k})                                   (log-Euler)
+// with x = sqrt(h) B xi, B the correlation factor of the plan and xi the
+// step's 2M normals (Box-Muller of Philox4x32-10 blocks, counter (pair,
+// step, path), key seed).  Both sums are O(M) recursions over the gaps:
+// rho_{k,i} = eta1 + (1 - eta1) prod_{l=i+1..k} g1_l and phi_{i,k} =
+// sgn(phi_i) sqrt|phi_i| sqrt|phi_k| prod_{l=i+1..k} g3_l, g = exp(-lambda
+// (T_l - T_{l-1})).  At each fixing T_j the payoffs of the options expiring
+// there are taken (payer swaption on forwards a..b-1, b = a + 1 the caplet)
+// and the deflator is divided by 1 + tau_j F_j(T_j).
+//
+// Layout: one path per lane, 4 waves per block; the forwards, their
+// volatilities and the step's normals in registers (at most 16 forwards);
+// the factor and the per-forward constants are wave-uniform and read through
+// the scalar cache.  Each wave reduces its 64 paths' payoffs and squares per
+// option (register lane moves) into a slot of the workspace; a second kernel
+// sums the slots in a fixed order, so prices do not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sabr.h"
+#include "sabr_device.hpp"
+#include "sabr_mc_internal.h"
+
+namespace sabr {
+namespace {
+
+constexpr int kMcMaxFwd = 16;
+constexpr int kMcWavesPerBlock = 4;
+constexpr int kMcReduceThreads = 256;
+
+// Per-forward constants: rows of the plan image's forward table.
+enum { MC_T, MC_TAU, MC_F0, MC_ALPHA, MC_BETA, MC_SIGMA, MC_PHS, MC_PHA, MC_G1, MC_G3, MC_ROWS };
+
+struct McArgs {
+  int M, n_opt, amax;
+  long long n_paths;
+  unsigned seed_lo, seed_hi;
+  double eta1, P0;
+  const double *fw;   // [MC_ROWS][M]
+  const double *B;    // [2M][2M]
+  const int *opt_a, *opt_b, *opt_off;   // options grouped by expiry; opt_off [M + 1]
+  const double *opt_K;
+  double *part;       // [n_opt][2][n_waves]
+  long long n_waves;
+  int nst[kMcMaxFwd];
+  double h[kMcMaxFwd], sh[kMcMaxFwd];
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011).
+__device__ __forceinline__ void philox4x32_10(unsigned c0, unsigned c1, unsigned c2, unsigned c3,
+                                              unsigned k0, unsigned k1, unsigned out[4]) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const unsigned hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const unsigned hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const unsigned n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+template <int MMAX>
+__global__ __launch_bounds__(kWave *kMcWavesPerBlock) void mc_kernel(McArgs a) {
+  const int lane = lane_id();
+  const long long wave = (long long)blockIdx.x * kMcWavesPerBlock + threadIdx.x / kWave;
+  if (wave >= a.n_waves) return;   // whole waves only
+  const long long path = wave * kWave + lane;
+  const bool live = path < a.n_paths;
+  const int M = a.M, n2 = 2 * M;
+  const double *__restrict__ fw = a.fw;
+  const double *__restrict__ Bf = a.B;
+  const double eta1 = a.eta1;
+
+  double F[MMAX], V[MMAX];
+#pragma unroll
+  for (int k = 0; k < MMAX; ++k) {
+    F[k] = k < M ? fw[MC_F0 * M + k] : 0.0;
+    V[k] = k < M ? fw[MC_ALPHA * M + k] : 0.0;
+  }
+  double D = a.P0;
+  unsigned step = 0;
+  const unsigned p_lo = (unsigned)path, p_hi = (unsigned)((unsigned long long)path >> 32);
+
+  for (int j = 0; j <= a.amax; ++j) {
+    const int n = a.nst[j];
+    const double h = a.h[j], sh = a.sh[j];
+    for (int st = 0; st < n; ++st, ++step) {
+      double xi[2 * MMAX];
+#pragma unroll
+      for (int m = 0; m < MMAX; ++m) {
+        xi[2 * m] = xi[2 * m + 1] = 0.0;
+        if (m < M) {
+          unsigned w[4];
+          philox4x32_10((unsigned)m, step, p_lo, p_hi, a.seed_lo, a.seed_hi, w);
+          const unsigned long long ua = ((unsigned long long)w[0] << 21) + (w[1] >> 11);
+          const unsigned long long ub = ((unsigned long long)w[2] << 21) + (w[3] >> 11);
+          const double u1 = (double)(ua + 1) * 0x1.0p-53;
+          const double u2 = (double)ub * 0x1.0p-53;
+          const double r = sqrt(-2.0 * log(u1));
+          double sn, cs;
+          sincos(6.283185307179586 * u2, &sn, &cs);
+          xi[2 * m] = r * cs;
+          xi[2 * m + 1] = r * sn;
+        }
+      }
+      double Ds = 0.0, E = 0.0, G = 0.0;
+#pragma unroll
+      for (int k = 0; k < MMAX; ++k) {
+        if (k >= j && k < M) {
+          const double f = F[k], v = V[k];
+          const double tk = fw[MC_TAU * M + k];
+          const double s = v * pow(fmax(f, 0.0), fw[MC_BETA * M + k]);
+          const double d = tk * s / (1.0 + tk * f);
+          Ds += d;
+          E = fw[MC_G1 * M + k] * E + d;
+          G = fw[MC_G3 * M + k] * G + fw[MC_PHS * M + k] * d;
+          double xf = 0.0, xv = 0.0;
+#pragma unroll
+          for (int c = 0; c < 2 * MMAX; ++c) {
+            if (c < n2) {
+              xf += Bf[k * n2 + c] * xi[c];
+              xv += Bf[(M + k) * n2 + c] * xi[c];
+            }
+          }
+          const double sg = fw[MC_SIGMA * M + k];
+          F[k] = fmax(f + s * (eta1 * Ds + (1.0 - eta1) * E) * h + s * (sh * xf), 0.0);
+          V[k] = v * exp((sg * fw[MC_PHA * M + k] * G - 0.5 * sg * sg) * h + sg * (sh * xv));
+        }
+      }
+    }
+    // fixing of F_j: the options expiring at T_j, then the deflator
+    for (int o = a.opt_off[j]; o < a.opt_off[j + 1]; ++o) {
+      const int ob = a.opt_b[o];
+      const double K = a.opt_K[o];
+      double Pb = 1.0, A = 0.0;
+#pragma unroll
+      for (int i = 0; i < MMAX; ++i) {
+        if (i >= j && i < ob) {
+          Pb /= (1.0 + fw[MC_TAU * M + i] * F[i]);
+          A += fw[MC_TAU * M + i] * Pb;
+        }
+      }
+      const double x = live ? D * fmax(1.0 - Pb - K * A, 0.0) : 0.0;
+      const double s1 = wave_sum(x), s2 = wave_sum(x * x);
+      if (lane == 0) {
+        a.part[(2 * (long long)o) * a.n_waves + wave] = s1;
+        a.part[(2 * (long long)o + 1) * a.n_waves + wave] = s2;
+      }
+    }
+    double Fj = 0.0;
+#pragma unroll
+    for (int i = 0; i < MMAX; ++i)
+      if (i == j) Fj = F[i];
+    D /= (1.0 + fw[MC_TAU * M + j] * Fj);
+  }
+}
+
+// Mean and standard error per option: block o sums its slots in a fixed
+// order (strided partial sums, then a tree).
+__global__ __launch_bounds__(kMcReduceThreads) void mc_reduce_kernel(const double *part,
+                                                                     long long n_waves,
+                                                                     long long n_paths,
+                                                                     const int *ext,
+                                                                     double *price, double *se) {
+  __shared__ double s1[kMcReduceThreads], s2[kMcReduceThreads];
+  const int o = blockIdx.x, t = threadIdx.x;
+  const double *p1 = part + (2 * (long long)o) * n_waves, *p2 = p1 + n_waves;
+  double a = 0.0, b = 0.0;
+  for (long long w = t; w < n_waves; w += kMcReduceThreads) {
+    a += p1[w];
+    b += p2[w];
+  }
+  s1[t] = a;
+  s2[t] = b;
+  __syncthreads();
+  for (int w = kMcReduceThreads / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      s1[t] += s1[t + w];
+      s2[t] += s2[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double n = (double)n_paths;
+    const double mean = s1[0] / n;
+    double var = n > 1.0 ? (s2[0] - s1[0] * mean) / (n - 1.0) : 0.0;
+    if (!(var > 0.0)) var = 0.0;
+    price[ext[o]] = mean;
+    if (se) se[ext[o]] = sqrt(var / n);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host: the correlation factor.  The 2M x 2M matrix of eqs. (rhoij),
+// (thetaij), (phiij) (rows W_0..W_{M-1}, Z_0..Z_{M-1}; entry (k, M + l) =
+// phi_{k,l} = E[dW_k dZ_l]) need not be positive semi-definite (the paper's
+// calibrated Hagan parameters give an indefinite one); the factor is its
+// spectral repair (Rebonato and Jaeckel, 1999): eigenvalues clipped at zero,
+// B = Q sqrt(Lambda+), rows rescaled to unit length.  Columns in decreasing
+// eigenvalue order, each eigenvector signed so that its entry of largest
+// magnitude (the first such) is positive.  Eigen-decomposition by cyclic
+// Jacobi rotations (Rutishauser's formulation).
+// ---------------------------------------------------------------------------
+void corr_matrix(int M, const double *T, const double *phi, const double y[5], double *C) {
+  const int n = 2 * M;
+  for (int k = 0; k < M; ++k)
+    for (int l = 0; l < M; ++l) {
+      const double dT = std::fabs(T[k] - T[l]);
+      C[k * n + l] = y[0] + (1.0 - y[0]) * std::exp(-y[1] * dT);
+      C[(M + k) * n + (M + l)] = y[2] + (1.0 - y[2]) * std::exp(-y[3] * dT);
+      const double sg = phi[k] > 0.0 ? 1.0 : (phi[k] < 0.0 ? -1.0 : 0.0);
+      const double ph = sg * std::sqrt(std::fabs(phi[k] * phi[l])) * std::exp(-y[4] * dT);
+      C[k * n + (M + l)] = ph;
+      C[(M + l) * n + k] = ph;
+    }
+}
+
+void jacobi_eigen(int n, std::vector<double> A, std::vector<double> &lam, std::vector<double> &Q) {
+  Q.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < n; ++q) {
+        tot += A[(size_t)p * n + q] * A[(size_t)p * n + q];
+        if (p != q) off += A[(size_t)p * n + q] * A[(size_t)p * n + q];
+      }
+    if (off <= 1e-34 * tot) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[(size_t)p * n + q];
+        if (apq == 0.0) continue;
+        const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) /
+                         (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c, tau = s / (1.0 + c);
+        A[(size_t)p * n + p] = app - t * apq;
+        A[(size_t)q * n + q] = aqq + t * apq;
+        A[(size_t)p * n + q] = A[(size_t)q * n + p] = 0.0;
+        for (int r = 0; r < n; ++r) {
+          if (r == p || r == q) continue;
+          const double arp = A[(size_t)r * n + p], arq = A[(size_t)r * n + q];
+          const double nrp = arp - s * (arq + tau * arp), nrq = arq + s * (arp - tau * arq);
+          A[(size_t)r * n + p] = A[(size_t)p * n + r] = nrp;
+          A[(size_t)r * n + q] = A[(size_t)q * n + r] = nrq;
+        }
+        for (int r = 0; r < n; ++r) {
+          const double qrp = Q[(size_t)r * n + p], qrq = Q[(size_t)r * n + q];
+          Q[(size_t)r * n + p] = qrp - s * (qrq + tau * qrp);
+          Q[(size_t)r * n + q] = qrq + s * (qrp - tau * qrq);
+        }
+      }
+  }
+  lam.resize(n);
+  for (int i = 0; i < n; ++i) lam[i] = A[(size_t)i * n + i];
+}
+
+void corr_factor(int M, const double *T, const double *phi, const double y[5], double *B) {
+  const int n = 2 * M;
+  std::vector<double> C((size_t)n * n), lam, Q;
+  corr_matrix(M, T, phi, y, C.data());
+  jacobi_eigen(n, C, lam, Q);
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int z) { return lam[x] > lam[z]; });
+  for (int c = 0; c < n; ++c) {
+    const int e = ord[c];
+    int arg = 0;
+    for (int r = 1; r < n; ++r)
+      if (std::fabs(Q[(size_t)r * n + e]) > std::fabs(Q[(size_t)arg * n + e])) arg = r;
+    const double sg = Q[(size_t)arg * n + e] < 0.0 ? -1.0 : 1.0;
+    const double sq = std::sqrt(std::max(lam[e], 0.0));
+    for (int r = 0; r < n; ++r) B[(size_t)r * n + c] = sg * Q[(size_t)r * n + e] * sq;
+  }
+  for (int r = 0; r < n; ++r) {
+    double s = 0.0;
+    for (int c = 0; c < n; ++c) s += B[(size_t)r * n + c] * B[(size_t)r * n + c];
+    const double nr = std::sqrt(s);
+    if (nr > 0.0)
+      for (int c = 0; c < n; ++c) B[(size_t)r * n + c] /= nr;
+  }
+}
+
+}  // namespace
+}  // namespace sabr
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+struct sabr_mc_plan {
+  int M = 0, n_opt = 0, amax = 0;
+  double eta1 = 0.0, P0 = 0.0;
+  std::vector<double> T;          // fixing times (host copy, for the step grid)
+  std::vector<double> img_d;      // fw [MC_ROWS][M], B [2M][2M], opt_K [n_opt]
+  std::vector<int> img_i;         // opt_a, opt_b [n_opt], opt_off [M + 1], ext [n_opt]
+  size_t off_B = 0, off_K = 0;    // in doubles
+  size_t off_a = 0, off_b = 0, off_off = 0, off_ext = 0;   // in ints
+  void *dev = nullptr;            // caller-owned image
+  size_t dev_bytes = 0;
+};
+
+namespace {
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+size_t image_bytes(const sabr_mc_plan *p) {
+  return p->img_d.size() * sizeof(double) + p->img_i.size() * sizeof(int);
+}
+
+}  // namespace
+
+extern "C" {
+
+sabr_status sabr_mc_plan_create(const sabr_mc_problem *pr, sabr_mc_plan **out) {
+  using namespace sabr;
+  if (!pr || !out) return mc_fail(SABR_EINVAL, "null argument");
+  *out = nullptr;
+  const int M = pr->n_fwd;
+  if (M < 1 || M > kMcMaxFwd)
+    return mc_fail(SABR_EINVAL, "mc: n_fwd must be 1.." + std::to_string(kMcMaxFwd));
+  if (!pr->T || !pr->tau || !pr->F0 || !pr->alpha || !pr->beta || !pr->phi || !pr->sigma)
+    return mc_fail(SABR_EINVAL, "mc: null forward array");
+  for (int k = 0; k < M; ++k) {
+    const double prev = k > 0 ? pr->T[k - 1] : 0.0;
+    if (!is_fin(pr->T[k]) || !(pr->T[k] > prev))
+      return mc_fail(SABR_EINVAL, "mc: fixing times must be positive and increasing");
+    if (!is_fin(pr->tau[k]) || !(pr->tau[k] > 0.0) || !is_fin(pr->F0[k]) || !(pr->F0[k] > 0.0) ||
+        !is_fin(pr->alpha[k]) || !(pr->alpha[k] > 0.0))
+      return mc_fail(SABR_EINVAL, "mc: tau, F0 and alpha must be positive");
+    if (!(pr->beta[k] >= 0.0 && pr->beta[k] <= 1.0))
+      return mc_fail(SABR_EINVAL, "mc: beta outside [0, 1]");
+    if (!(std::fabs(pr->phi[k]) <= 1.0)) return mc_fail(SABR_EINVAL, "mc: |phi_ii| > 1");
+    if (!is_fin(pr->sigma[k]) || !(pr->sigma[k] >= 0.0))
+      return mc_fail(SABR_EINVAL, "mc: sigma must be >= 0");
+  }
+  const double y[5] = {pr->eta1, pr->lambda1, pr->eta2, pr->lambda2, pr->lambda3};
+  if (!(y[0] >= 0.0 && y[0] <= 1.0) || !(y[2] >= 0.0 && y[2] <= 1.0))
+    return mc_fail(SABR_EINVAL, "mc: eta1 and eta2 must lie in [0, 1]");
+  if (!(y[1] >= 0.0) || !(y[3] >= 0.0) || !(y[4] >= 0.0) || !is_fin(y[1]) || !is_fin(y[3]) ||
+      !is_fin(y[4]))
+    return mc_fail(SABR_EINVAL, "mc: lambdas must be finite and >= 0");
+  if (!is_fin(pr->P0) || !(pr->P0 > 0.0)) return mc_fail(SABR_EINVAL, "mc: P0 must be positive");
+  const int n_opt = pr->n_opt;
+  if (n_opt < 1) return mc_fail(SABR_EINVAL, "mc: need at least one option");
+  if (!pr->opt_a || !pr->opt_b || !pr->opt_K) return mc_fail(SABR_EINVAL, "mc: null option array");
+  int amax = 0;
+  for (int o = 0; o < n_opt; ++o) {
+    if (pr->opt_a[o] < 0 || pr->opt_b[o] <= pr->opt_a[o] || pr->opt_b[o] > M)
+      return mc_fail(SABR_EINVAL, "mc: option " + std::to_string(o) + " needs 0 <= a < b <= n_fwd");
+    if (!is_fin(pr->opt_K[o])) return mc_fail(SABR_EINVAL, "mc: option strike not finite");
+    amax = std::max(amax, pr->opt_a[o]);
+  }
+  sabr_mc_plan *P = new (std::nothrow) sabr_mc_plan;
+  if (!P) return mc_fail(SABR_ENOMEM, "out of host memory");
+  P->M = M;
+  P->n_opt = n_opt;
+  P->amax = amax;
+  P->eta1 = y[0];
+  P->P0 = pr->P0;
+  P->T.assign(pr->T, pr->T + M);
+  const int n2 = 2 * M;
+  P->off_B = (size_t)MC_ROWS * M;
+  P->off_K = P->off_B + (size_t)n2 * n2;
+  P->img_d.assign(P->off_K + n_opt, 0.0);
+  double *fw = P->img_d.data();
+  for (int k = 0; k < M; ++k) {
+    fw[MC_T * M + k] = pr->T[k];
+    fw[MC_TAU * M + k] = pr->tau[k];
+    fw[MC_F0 * M + k] = pr->F0[k];
+    fw[MC_ALPHA * M + k] = pr->alpha[k];
+    fw[MC_BETA * M + k] = pr->beta[k];
+    fw[MC_SIGMA * M + k] = pr->sigma[k];
+    const double ap = std::sqrt(std::fabs(pr->phi[k]));
+    fw[MC_PHS * M + k] = pr->phi[k] > 0.0 ? ap : (pr->phi[k] < 0.0 ? -ap : 0.0);
+    fw[MC_PHA * M + k] = ap;
+    const double gap = k > 0 ? pr->T[k] - pr->T[k - 1] : 0.0;
+    fw[MC_G1 * M + k] = std::exp(-y[1] * gap);
+    fw[MC_G3 * M + k] = std::exp(-y[4] * gap);
+  }
+  corr_factor(M, pr->T, pr->phi, y, P->img_d.data() + P->off_B);
+  // options grouped by expiry (stable), outputs back to the caller's order
+  std::vector<int> ord(n_opt);
+  for (int o = 0; o < n_opt; ++o) ord[o] = o;
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int x, int z) { return pr->opt_a[x] < pr->opt_a[z]; });
+  P->off_a = 0;
+  P->off_b = n_opt;
+  P->off_off = 2 * (size_t)n_opt;
+  P->off_ext = P->off_off + M + 1;
+  P->img_i.assign(P->off_ext + n_opt, 0);
+  std::vector<int> cnt(M + 1, 0);
+  for (int i = 0; i < n_opt; ++i) {
+    const int o = ord[i];
+    P->img_i[P->off_a + i] = pr->opt_a[o];
+    P->img_i[P->off_b + i] = pr->opt_b[o];
+    P->img_d[P->off_K + i] = pr->opt_K[o];
+    P->img_i[P->off_ext + i] = o;
+    cnt[pr->opt_a[o] + 1] += 1;
+  }
+  for (int j = 0; j < M; ++j) cnt[j + 1] += cnt[j];
+  for (int j = 0; j <= M; ++j) P->img_i[P->off_off + j] = cnt[j];
+  *out = P;
+  return SABR_OK;
+}
+
+void sabr_mc_plan_destroy(sabr_mc_plan *plan) { delete plan; }
+
+size_t sabr_mc_plan_device_bytes(const sabr_mc_plan *plan) { return plan ? image_bytes(plan) : 0; }
+
+sabr_status sabr_mc_plan_upload(sabr_mc_plan *plan, void *dev_buf, size_t bytes, void *stream) {
+  using namespace sabr;
+  if (!plan || !dev_buf) return mc_fail(SABR_EINVAL, "null argument");
+  const size_t need = image_bytes(plan);
+  if (bytes < need) return mc_fail(SABR_EWORKSPACE, "mc: plan buffer too small");
+  if (reinterpret_cast<uintptr_t>(dev_buf) % 8 != 0)
+    return mc_fail(SABR_EINVAL, "mc: plan buffer must be 8-byte aligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t nd = plan->img_d.size() * sizeof(double);
+  hipError_t e = hipMemcpyAsync(dev_buf, plan->img_d.data(), nd, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(static_cast<char *>(dev_buf) + nd, plan->img_i.data(),
+                       plan->img_i.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return mc_hip_fail(e, "mc plan upload");
+  plan->dev = dev_buf;
+  plan->dev_bytes = need;
+  return SABR_OK;
+}
+
+sabr_status sabr_mc_factor(const sabr_mc_plan *plan, double *B) {
+  using namespace sabr;
+  if (!plan || !B) return mc_fail(SABR_EINVAL, "null argument");
+  const size_t n2 = 2 * (size_t)plan->M;
+  std::copy(plan->img_d.begin() + plan->off_B, plan->img_d.begin() + plan->off_B + n2 * n2, B);
+  return SABR_OK;
+}
+
+size_t sabr_mc_workspace_size(const sabr_mc_plan *plan, int64_t n_paths) {
+  if (!plan || n_paths < 1) return 0;
+  const long long n_waves = (n_paths + sabr::kWave - 1) / sabr::kWave;
+  return (size_t)plan->n_opt * 2 * (size_t)n_waves * sizeof(double);
+}
+
+sabr_status sabr_mc_price(const sabr_mc_plan *plan, int64_t n_paths, double dt, uint64_t seed,
+                          double *price, double *stderr_out, void *workspace, size_t ws_bytes,
+                          void *stream) {
+  using namespace sabr;
+  if (!plan || !price) return mc_fail(SABR_EINVAL, "null argument");
+  if (!plan->dev) return mc_fail(SABR_EINVAL, "mc: plan not uploaded");
+  if (n_paths < 1 || n_paths > (int64_t(1) << 40))
+    return mc_fail(SABR_EINVAL, "mc: n_paths must be 1..2^40");
+  if (!is_fin(dt) || !(dt > 0.0)) return mc_fail(SABR_EINVAL, "mc: dt must be positive");
+  const size_t need = sabr_mc_workspace_size(plan, n_paths);
+  if (!workspace || ws_bytes < need) return mc_fail(SABR_EWORKSPACE, "mc: workspace too small");
+  McArgs a{};
+  a.M = plan->M;
+  a.n_opt = plan->n_opt;
+  a.amax = plan->amax;
+  a.n_paths = n_paths;
+  a.seed_lo = (unsigned)seed;
+  a.seed_hi = (unsigned)(seed >> 32);
+  a.eta1 = plan->eta1;
+  a.P0 = plan->P0;
+  double total = 0.0;
+  for (int j = 0; j <= plan->amax; ++j) {
+    const double len = plan->T[j] - (j > 0 ? plan->T[j - 1] : 0.0);
+    const double n = std::ceil(len / dt);
+    total += n < 1.0 ? 1.0 : n;
+    if (total > 2147483647.0) return mc_fail(SABR_EINVAL, "mc: more than 2^31 time steps");
+    a.nst[j] = n < 1.0 ? 1 : (int)n;
+    a.h[j] = len / a.nst[j];
+    a.sh[j] = std::sqrt(a.h[j]);
+  }
+  const double *dd = static_cast<const double *>(plan->dev);
+  const int *di = reinterpret_cast<const int *>(dd + plan->img_d.size());
+  a.fw = dd;
+  a.B = dd + plan->off_B;
+  a.opt_K = dd + plan->off_K;
+  a.opt_a = di + plan->off_a;
+  a.opt_b = di + plan->off_b;
+  a.opt_off = di + plan->off_off;
+  a.part = static_cast<double *>(workspace);
+  a.n_waves = (n_paths + kWave - 1) / kWave;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const long long blocks = (a.n_waves + kMcWavesPerBlock - 1) / kMcWavesPerBlock;
+  hipLaunchKernelGGL((mc_kernel<kMcMaxFwd>), dim3((unsigned)blocks), dim3(kWave * kMcWavesPerBlock),
+                     0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return mc_hip_fail(e, "mc kernel launch");
+  hipLaunchKernelGGL(mc_reduce_kernel, dim3(plan->n_opt), dim3(kMcReduceThreads), 0, s, a.part,
+                     a.n_waves, (long long)n_paths, di + plan->off_ext, price, stderr_out);
+  e = hipGetLastError();
+  if (e != hipSuccess) return mc_hip_fail(e, "mc reduce launch");
+  return SABR_OK;
+}
+
+}  // extern "C"

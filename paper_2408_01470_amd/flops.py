@@ -183,3 +183,47 @@ def cost_launch_flops(market: dict, pt_inst) -> float:
     qf = quote_flops(model, formula, residual)
     pt_inst = np.asarray(pt_inst)
     return float(sum(nq[i] * qf + map_flops_inst(market, i) for i in pt_inst))
+
+
+# ---------------------------------------------------------------------------
+# Monte Carlo pricer (the Hagan SABR/LIBOR dynamics of Sec. 2.1)
+# ---------------------------------------------------------------------------
+# Device library calls of the path step, counted by their definition: log as
+# log1p, the power as log then exp, and the sine and cosine of one argument
+# as two exp-sized polynomial evaluations.
+MC_BOX_MULLER = _e("log1p") + _e("sqrt") + 2 * _e("exp") + 6          # per normal pair
+MC_PER_FORWARD = (_e("log1p") + _e("exp")        # max(F, 0)^beta
+                  + 3 + _e("div")                 # d = tau s / (1 + tau F)
+                  + 7                             # the three drift recursions
+                  + 8                             # the F update
+                  + _e("exp") + 9)                # the V update
+
+
+def mc_step_flops(M: int, n_alive: int) -> float:
+    """One path step with n_alive of M forwards alive: M normal pairs, the
+    two rows of the 2M-column factor per alive forward (2 x 2M fma), and the
+    per-forward drift and updates."""
+    return M * MC_BOX_MULLER + n_alive * (4 * 2 * M + MC_PER_FORWARD)
+
+
+def mc_steps(T, dt, amax):
+    """Steps of each fixing interval 0..amax (the pricer's grid)."""
+    out = []
+    for j in range(amax + 1):
+        length = T[j] - (T[j - 1] if j > 0 else 0.0)
+        out.append(max(1, int(np.ceil(length / dt))))
+    return out
+
+
+def mc_launch_flops(prob: dict, n_paths: int, dt: float) -> float:
+    """Algorithmic FLOP of one pricing call (path steps only; the payoffs,
+    once per option and path, are left out)."""
+    M = len(prob["T"])
+    amax = int(np.max(prob["opt_a"]))
+    n = mc_steps(prob["T"], dt, amax)
+    return float(n_paths) * sum(n[j] * mc_step_flops(M, M - j) for j in range(amax + 1))
+
+
+def mc_path_steps(prob: dict, n_paths: int, dt: float) -> float:
+    amax = int(np.max(prob["opt_a"]))
+    return float(n_paths) * sum(mc_steps(prob["T"], dt, amax))
