@@ -21,9 +21,11 @@
 // and the deflator is divided by 1 + tau_j F_j(T_j).
 //
 // Layout: one path per lane, 4 waves per block; the forwards, their
-// volatilities and the step's normals in registers (at most 16 forwards);
-// the factor and the per-forward constants are wave-uniform and read through
-// the scalar cache.  Each wave reduces its 64 paths' payoffs and squares per
+// volatilities and the step's increments in registers (at most 16
+// forwards); the factor (column-major, rows W_k and Z_k interleaved) and the
+// per-forward constants are wave-uniform and read through the scalar cache.
+// Logarithms, exponentials and the sine and cosine of the Box-Muller angle
+// are the library's branch-free polynomial versions.  Each wave reduces its 64 paths' payoffs and squares per
 // option (register lane moves) into a slot of the workspace; a second kernel
 // sums the slots in a fixed order, so prices do not depend on scheduling.
 #include <hip/hip_runtime.h>
@@ -54,7 +56,7 @@ struct McArgs {
   unsigned seed_lo, seed_hi;
   double eta1, P0;
   const double *fw;   // [MC_ROWS][M]
-  const double *B;    // [2M][2M]
+  const double *B;    // factor, column-major [2M][2M], rows W_k at 2k, Z_k at 2k + 1
   const int *opt_a, *opt_b, *opt_off;   // options grouped by expiry; opt_off [M + 1]
   const double *opt_K;
   double *part;       // [n_opt][2][n_waves]
@@ -84,6 +86,59 @@ __device__ __forceinline__ void philox4x32_10(unsigned c0, unsigned c1, unsigned
   out[3] = c3;
 }
 
+// log(x) for a positive x (method of log1p_tang with v = x exactly):
+// x = 2^k m, m in [sqrt(1/2), sqrt(2)), f = m - 1, s = f/(2 + f),
+// log m = f - s (f - s^2 P(s^2)).  Branch-free; 0 gives a finite garbage
+// value that callers select away.
+__device__ __forceinline__ double mc_log(double x) {
+  double m = __builtin_amdgcn_frexp_mant(x);
+  int k = __builtin_amdgcn_frexp_exp(x);
+  const bool up = m < M_SQRT1_2;
+  m = up ? m + m : m;
+  k = up ? k - 1 : k;
+  const double f = m - 1.0;
+  const double s = f * rcp_nr(2.0 + f);
+  const double z = s * s;
+  const double p = horner_s<kLog1pPoly, kLog1pDeg>(z);
+  const double lf = fma(-s, fma(-z, p, f), f);
+  const double kd = (double)k;
+  return fma(kd, kLn2Hi, fma(kd, kLn2Lo, lf));
+}
+
+// Taylor coefficients of sin x / x and (cos x - 1) / x^2 in z = x^2, for
+// |x| <= pi/4 (truncation below 2^-60 relative).
+constexpr double inv_fact(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return 1.0 / f;
+}
+constexpr int kMcSinDeg = 8, kMcCosDeg = 8;
+constexpr double kMcSinPoly[kMcSinDeg + 1] = {
+    -inv_fact(3), inv_fact(5), -inv_fact(7), inv_fact(9), -inv_fact(11),
+    inv_fact(13), -inv_fact(15), inv_fact(17), -inv_fact(19)};
+constexpr double kMcCosPoly[kMcCosDeg + 1] = {
+    -inv_fact(2), inv_fact(4), -inv_fact(6), inv_fact(8), -inv_fact(10),
+    inv_fact(12), -inv_fact(14), inv_fact(16), -inv_fact(18)};
+
+// (sin, cos)(2 pi u) for u in [0, 1): q = rint(4u) and r = u - q/4 (exact)
+// give 2 pi u = 2 pi r + q pi/2 with |2 pi r| <= pi/4; the quadrant swaps
+// and signs the pair.
+__device__ __forceinline__ void mc_sincos_2pi(double u, double &sn, double &cs) {
+  const double q = rint(4.0 * u);
+  const double x = 6.283185307179586 * (u - 0.25 * q);
+  const double z = x * x;
+  const double sx = fma(x * z, horner_s<kMcSinPoly, kMcSinDeg>(z), x);
+  const double cx = fma(z, horner_s<kMcCosPoly, kMcCosDeg>(z), 1.0);
+  const int iq = (int)q & 3;
+  const double a = (iq & 1) ? cx : sx, b = (iq & 1) ? sx : cx;
+  sn = (iq & 2) ? -a : a;
+  cs = ((iq + 1) & 2) ? -b : b;
+}
+
+// One path per lane.  Per step: the increments x of the alive rows are
+// accumulated column by column (pair m of normals, columns 2m and 2m + 1 of
+// the factor, stored column-major with rows W_k, Z_k interleaved), then the
+// forwards move in increasing k with the drift recursions.
 template <int MMAX>
 __global__ __launch_bounds__(kWave *kMcWavesPerBlock) void mc_kernel(McArgs a) {
   const int lane = lane_id();
@@ -93,7 +148,7 @@ __global__ __launch_bounds__(kWave *kMcWavesPerBlock) void mc_kernel(McArgs a) {
   const bool live = path < a.n_paths;
   const int M = a.M, n2 = 2 * M;
   const double *__restrict__ fw = a.fw;
-  const double *__restrict__ Bf = a.B;
+  const double *__restrict__ Bc = a.B;
   const double eta1 = a.eta1;
 
   double F[MMAX], V[MMAX];
@@ -110,46 +165,42 @@ __global__ __launch_bounds__(kWave *kMcWavesPerBlock) void mc_kernel(McArgs a) {
     const int n = a.nst[j];
     const double h = a.h[j], sh = a.sh[j];
     for (int st = 0; st < n; ++st, ++step) {
-      double xi[2 * MMAX];
+      double x[2 * MMAX];
 #pragma unroll
-      for (int m = 0; m < MMAX; ++m) {
-        xi[2 * m] = xi[2 * m + 1] = 0.0;
-        if (m < M) {
-          unsigned w[4];
-          philox4x32_10((unsigned)m, step, p_lo, p_hi, a.seed_lo, a.seed_hi, w);
-          const unsigned long long ua = ((unsigned long long)w[0] << 21) + (w[1] >> 11);
-          const unsigned long long ub = ((unsigned long long)w[2] << 21) + (w[3] >> 11);
-          const double u1 = (double)(ua + 1) * 0x1.0p-53;
-          const double u2 = (double)ub * 0x1.0p-53;
-          const double r = sqrt(-2.0 * log(u1));
-          double sn, cs;
-          sincos(6.283185307179586 * u2, &sn, &cs);
-          xi[2 * m] = r * cs;
-          xi[2 * m + 1] = r * sn;
-        }
+      for (int r = 0; r < 2 * MMAX; ++r) x[r] = 0.0;
+      for (int m = 0; m < M; ++m) {
+        unsigned w[4];
+        philox4x32_10((unsigned)m, step, p_lo, p_hi, a.seed_lo, a.seed_hi, w);
+        const unsigned long long ua = ((unsigned long long)w[0] << 21) + (w[1] >> 11);
+        const unsigned long long ub = ((unsigned long long)w[2] << 21) + (w[3] >> 11);
+        const double u1 = (double)(ua + 1) * 0x1.0p-53;
+        const double u2 = (double)ub * 0x1.0p-53;
+        const double rr = sqrt_gs(-2.0 * mc_log(u1));
+        double sn, cs;
+        mc_sincos_2pi(u2, sn, cs);
+        const double z0 = u1 < 1.0 ? rr * cs : 0.0, z1 = u1 < 1.0 ? rr * sn : 0.0;
+        const double *c0 = Bc + (size_t)(2 * m) * n2, *c1 = c0 + n2;
+#pragma unroll
+        for (int r = 0; r < 2 * MMAX; ++r)
+          if (r >= 2 * j && r < n2) x[r] = fma(c1[r], z1, fma(c0[r], z0, x[r]));
       }
       double Ds = 0.0, E = 0.0, G = 0.0;
 #pragma unroll
       for (int k = 0; k < MMAX; ++k) {
         if (k >= j && k < M) {
           const double f = F[k], v = V[k];
-          const double tk = fw[MC_TAU * M + k];
-          const double s = v * pow(fmax(f, 0.0), fw[MC_BETA * M + k]);
-          const double d = tk * s / (1.0 + tk * f);
+          const double tk = fw[MC_TAU * M + k], bk = fw[MC_BETA * M + k];
+          const double fp = fmax(f, 0.0);
+          const double fb = fp > 0.0 ? exp_cw(bk * mc_log(fp)) : (bk == 0.0 ? 1.0 : 0.0);
+          const double s = v * fb;
+          const double d = tk * s * rcp_nr(fma(tk, f, 1.0));
           Ds += d;
-          E = fw[MC_G1 * M + k] * E + d;
-          G = fw[MC_G3 * M + k] * G + fw[MC_PHS * M + k] * d;
-          double xf = 0.0, xv = 0.0;
-#pragma unroll
-          for (int c = 0; c < 2 * MMAX; ++c) {
-            if (c < n2) {
-              xf += Bf[k * n2 + c] * xi[c];
-              xv += Bf[(M + k) * n2 + c] * xi[c];
-            }
-          }
+          E = fma(fw[MC_G1 * M + k], E, d);
+          G = fma(fw[MC_G3 * M + k], G, fw[MC_PHS * M + k] * d);
           const double sg = fw[MC_SIGMA * M + k];
-          F[k] = fmax(f + s * (eta1 * Ds + (1.0 - eta1) * E) * h + s * (sh * xf), 0.0);
-          V[k] = v * exp((sg * fw[MC_PHA * M + k] * G - 0.5 * sg * sg) * h + sg * (sh * xv));
+          F[k] = fmax(f + s * (eta1 * Ds + (1.0 - eta1) * E) * h + s * (sh * x[2 * k]), 0.0);
+          V[k] = v * exp_cw((sg * fw[MC_PHA * M + k] * G - 0.5 * sg * sg) * h +
+                            sg * (sh * x[2 * k + 1]));
         }
       }
     }
@@ -165,8 +216,8 @@ __global__ __launch_bounds__(kWave *kMcWavesPerBlock) void mc_kernel(McArgs a) {
           A += fw[MC_TAU * M + i] * Pb;
         }
       }
-      const double x = live ? D * fmax(1.0 - Pb - K * A, 0.0) : 0.0;
-      const double s1 = wave_sum(x), s2 = wave_sum(x * x);
+      const double xo = live ? D * fmax(1.0 - Pb - K * A, 0.0) : 0.0;
+      const double s1 = wave_sum(xo), s2 = wave_sum(xo * xo);
       if (lane == 0) {
         a.part[(2 * (long long)o) * a.n_waves + wave] = s1;
         a.part[(2 * (long long)o + 1) * a.n_waves + wave] = s2;
@@ -317,6 +368,7 @@ struct sabr_mc_plan {
   int M = 0, n_opt = 0, amax = 0;
   double eta1 = 0.0, P0 = 0.0;
   std::vector<double> T;          // fixing times (host copy, for the step grid)
+  std::vector<double> B;          // factor [2M][2M], rows W_0..W_{M-1}, Z_0..Z_{M-1}
   std::vector<double> img_d;      // fw [MC_ROWS][M], B [2M][2M], opt_K [n_opt]
   std::vector<int> img_i;         // opt_a, opt_b [n_opt], opt_off [M + 1], ext [n_opt]
   size_t off_B = 0, off_K = 0;    // in doubles
@@ -403,7 +455,14 @@ sabr_status sabr_mc_plan_create(const sabr_mc_problem *pr, sabr_mc_plan **out) {
     fw[MC_G1 * M + k] = std::exp(-y[1] * gap);
     fw[MC_G3 * M + k] = std::exp(-y[4] * gap);
   }
-  corr_factor(M, pr->T, pr->phi, y, P->img_d.data() + P->off_B);
+  P->B.assign((size_t)n2 * n2, 0.0);
+  corr_factor(M, pr->T, pr->phi, y, P->B.data());
+  // device layout: column-major, rows interleaved (W_k at 2k, Z_k at 2k + 1)
+  for (int c = 0; c < n2; ++c)
+    for (int k = 0; k < M; ++k) {
+      P->img_d[P->off_B + (size_t)c * n2 + 2 * k] = P->B[(size_t)k * n2 + c];
+      P->img_d[P->off_B + (size_t)c * n2 + 2 * k + 1] = P->B[(size_t)(M + k) * n2 + c];
+    }
   // options grouped by expiry (stable), outputs back to the caller's order
   std::vector<int> ord(n_opt);
   for (int o = 0; o < n_opt; ++o) ord[o] = o;
@@ -457,7 +516,7 @@ sabr_status sabr_mc_factor(const sabr_mc_plan *plan, double *B) {
   using namespace sabr;
   if (!plan || !B) return mc_fail(SABR_EINVAL, "null argument");
   const size_t n2 = 2 * (size_t)plan->M;
-  std::copy(plan->img_d.begin() + plan->off_B, plan->img_d.begin() + plan->off_B + n2 * n2, B);
+  std::copy(plan->B.begin(), plan->B.begin() + n2 * n2, B);
   return SABR_OK;
 }
 
