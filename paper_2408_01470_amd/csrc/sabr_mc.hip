@@ -135,18 +135,21 @@ __device__ __forceinline__ void mc_sincos_2pi(double u, double &sn, double &cs) 
   cs = ((iq + 1) & 2) ? -b : b;
 }
 
-// One path per lane.  Per step: the increments x of the alive rows are
+// One path per lane, MF = the problem's forward count (one instantiation per
+// count keeps every register index and loop bound static).  Per step: the
+// increments x of the alive rows are
 // accumulated column by column (pair m of normals, columns 2m and 2m + 1 of
 // the factor, stored column-major with rows W_k, Z_k interleaved), then the
 // forwards move in increasing k with the drift recursions.
-template <int MMAX>
+template <int MF>
 __global__ __launch_bounds__(kWave *kMcWavesPerBlock) void mc_kernel(McArgs a) {
+  constexpr int MMAX = MF;
   const int lane = lane_id();
   const long long wave = (long long)blockIdx.x * kMcWavesPerBlock + threadIdx.x / kWave;
   if (wave >= a.n_waves) return;   // whole waves only
   const long long path = wave * kWave + lane;
   const bool live = path < a.n_paths;
-  const int M = a.M, n2 = 2 * M;
+  constexpr int M = MF, n2 = 2 * MF;
   const double *__restrict__ fw = a.fw;
   const double *__restrict__ Bc = a.B;
   const double eta1 = a.eta1;
@@ -568,8 +571,19 @@ sabr_status sabr_mc_price(const sabr_mc_plan *plan, int64_t n_paths, double dt, 
   a.n_waves = (n_paths + kWave - 1) / kWave;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const long long blocks = (a.n_waves + kMcWavesPerBlock - 1) / kMcWavesPerBlock;
-  hipLaunchKernelGGL((mc_kernel<kMcMaxFwd>), dim3((unsigned)blocks), dim3(kWave * kMcWavesPerBlock),
-                     0, s, a);
+  switch (plan->M) {
+#define SABR_MC_CASE(N)                                                                     \
+  case N:                                                                                   \
+    hipLaunchKernelGGL((mc_kernel<N>), dim3((unsigned)blocks), dim3(kWave * kMcWavesPerBlock), \
+                       0, s, a);                                                            \
+    break;
+    SABR_MC_CASE(1) SABR_MC_CASE(2) SABR_MC_CASE(3) SABR_MC_CASE(4) SABR_MC_CASE(5)
+    SABR_MC_CASE(6) SABR_MC_CASE(7) SABR_MC_CASE(8) SABR_MC_CASE(9) SABR_MC_CASE(10)
+    SABR_MC_CASE(11) SABR_MC_CASE(12) SABR_MC_CASE(13) SABR_MC_CASE(14) SABR_MC_CASE(15)
+    SABR_MC_CASE(16)
+#undef SABR_MC_CASE
+    default: return mc_fail(SABR_EINVAL, "mc: bad forward count");
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return mc_hip_fail(e, "mc kernel launch");
   hipLaunchKernelGGL(mc_reduce_kernel, dim3(plan->n_opt), dim3(kMcReduceThreads), 0, s, a.part,

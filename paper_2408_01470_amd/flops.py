@@ -188,21 +188,25 @@ def cost_launch_flops(market: dict, pt_inst) -> float:
 # ---------------------------------------------------------------------------
 # Monte Carlo pricer (the Hagan SABR/LIBOR dynamics of Sec. 2.1)
 # ---------------------------------------------------------------------------
-# Device library calls of the path step, counted by their definition: log as
-# log1p, the power as log then exp, and the sine and cosine of one argument
-# as two exp-sized polynomial evaluations.
-MC_BOX_MULLER = _e("log1p") + _e("sqrt") + 2 * _e("exp") + 6          # per normal pair
-MC_PER_FORWARD = (_e("log1p") + _e("exp")        # max(F, 0)^beta
-                  + 3 + _e("div")                 # d = tau s / (1 + tau F)
-                  + 7                             # the three drift recursions
-                  + 8                             # the F update
-                  + _e("exp") + 9)                # the V update
+# The path step's own functions, counted from their definitions:
+#   log        : m + m, m - 1, 2 + f, rcp, s, s^2, degree-6 Horner, two fma,
+#                k ln2 in two fma                               1+1+1+7+1+1+12+4+4 = 32
+#   sincos 2pi u: 4u, q/4, u - q/4, 2 pi r, x^2, x z, two degree-8 Horner
+#                chains and their closing fma                     5+1+16+2+16+2 = 42
+MC_LOG = 32.0
+MC_SINCOS = 42.0
+MC_BOX_MULLER = MC_LOG + _e("sqrt") + MC_SINCOS + 5          # per normal pair: 92
+MC_PER_FORWARD = (1 + MC_LOG + _e("exp")           # max(F, 0)^beta = exp(beta log F)
+                  + 1 + 4 + _e("rcp")              # s = V F^beta, d = tau s / (1 + tau F)
+                  + 6                              # the three drift recursions
+                  + 10                             # the F update
+                  + 10 + _e("exp"))                # the V update: 125 in all
 
 
 def mc_step_flops(M: int, n_alive: int) -> float:
-    """One path step with n_alive of M forwards alive: M normal pairs, the
-    two rows of the 2M-column factor per alive forward (2 x 2M fma), and the
-    per-forward drift and updates."""
+    """One path step with n_alive of M forwards alive: M normal pairs, each
+    adding its two factor columns into the 2 n_alive alive rows (two fma per
+    row), and the per-forward drift and updates."""
     return M * MC_BOX_MULLER + n_alive * (4 * 2 * M + MC_PER_FORWARD)
 
 
