@@ -185,21 +185,24 @@ def cost_and_adjoint(api, W, I, config="c5"):
 
 def measured_traffic(config, shape):
     """HBM bytes per launch of the level kernel from the committed counter
-    record (FETCH_SIZE and WRITE_SIZE passes scaled by a copy kernel's
-    readings), or None when there is no record for this workload and launch
-    shape or the kernel sources changed since the counters were taken."""
+    records (FETCH_SIZE and WRITE_SIZE passes scaled by a copy kernel's
+    readings; one record per launch shape), or None when there is no record
+    for this workload and launch shape or the kernel sources changed since
+    the counters were taken."""
     from paper_2408_01470_amd import build
     path = os.path.join(ROOT, "profiles", f"sa_level_kernel_{config}_counters.md")
     try:
         text = open(path).read()
-        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        recs = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
         return None
-    if (rec.get("source_sha256") != build.source_digest()
-            or rec.get("waves_per_group") != shape.get("waves_per_group")
-            or rec.get("occupancy") != shape.get("occupancy")):
-        return None
-    return float(rec["traffic_bytes_per_launch"])
+    digest = build.source_digest()
+    for rec in (recs if isinstance(recs, list) else [recs]):
+        if (rec.get("source_sha256") == digest
+                and rec.get("waves_per_group") == shape.get("waves_per_group")
+                and rec.get("occupancy") == shape.get("occupancy")):
+            return float(rec["traffic_bytes_per_launch"])
+    return None
 
 
 def time_to_rmse(api, W, I, autotune):

@@ -141,8 +141,10 @@ __device__ __forceinline__ void mc_sincos_2pi(double u, double &sn, double &cs) 
 // accumulated column by column (pair m of normals, columns 2m and 2m + 1 of
 // the factor, stored column-major with rows W_k, Z_k interleaved), then the
 // forwards move in increasing k with the drift recursions.
+// Register budget: 4 waves per SIMD up to 13 forwards (measured faster on the
+// paper's 13-forward market despite a few spilled registers), 3 beyond.
 template <int MF>
-__global__ __launch_bounds__(kWave *kMcWavesPerBlock) void mc_kernel(McArgs a) {
+__global__ __launch_bounds__(kWave *kMcWavesPerBlock, (MF <= 13 ? 4 : 3)) void mc_kernel(McArgs a) {
   constexpr int MMAX = MF;
   const int lane = lane_id();
   const long long wave = (long long)blockIdx.x * kMcWavesPerBlock + threadIdx.x / kWave;
