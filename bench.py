@@ -429,7 +429,9 @@ def paper_mc(api, I, flops, cpu=True):
     TFLOP/s FP64 peak (algorithmic FLOP of flops.mc_launch_flops); the mean
     absolute error of the 1e6-path prices against the market's Black prices
     (caplet price = P(0, pay) tau Black(F, K, T, vol), in % of notional as the
-    paper prints it); and, with cpu, the oracle on a bounded sample."""
+    paper prints it); the paper's fourteen swaptions x five strikes at the same
+    parameters against its printed market and Monte Carlo prices; and, with
+    cpu, the oracle on a bounded sample."""
     import torch
     from scipy.stats import norm
     prob = I.paper_mc_problem()
@@ -479,6 +481,23 @@ def paper_mc(api, I, flops, cpu=True):
         "max_stderr_pct": float(se.max() * 100.0),
         "paper": {"mae_mc_pct": 4.08e-2, "mae_formula_pct": 4.14e-2,
                   "hardware": "one GTX 470, single precision (context, not a target)"},
+    }
+    # the paper's fourteen swaptions x five strikes at the same parameters
+    sprob, printed = I.paper_mc_swaption_problem()
+    splan = api.McPlan(sprob)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sp, sse = splan.price(10**6, 1e-3, seed)
+    e1.record(stream)
+    e1.synchronize()
+    sp = 100.0 * sp.cpu().numpy()
+    out["swaptions"] = {
+        "cells": int(len(sp)), "paths": 10**6, "dt": 1e-3, "s": e0.elapsed_time(e1) / 1e3,
+        "mean_rel_dev_vs_paper_mc": float(np.mean(sp / printed[:, 1] - 1.0)),
+        "max_abs_rel_dev_vs_paper_mc": float(np.max(np.abs(sp / printed[:, 1] - 1.0))),
+        "mae_vs_market_pct": float(np.mean(np.abs(sp - printed[:, 0]))),
+        "paper_mae_vs_market_pct_these_cells": float(np.mean(np.abs(printed[:, 1] - printed[:, 0]))),
+        "paper_mae_all_swaptions_pct": 6.19e-2,
     }
     if cpu:
         from oracle import oracle as O

@@ -551,3 +551,33 @@ def mc_problem(seed=SEED_BASE + 9000, M=10, n_cap_K=3, n_swaptions=6, beta=None)
         b.append(sb)
         K.append(float(F[sa:sb].mean() * np.exp(g.uniform(-0.3, 0.3))))
     return mc_problem_arrays(T, tau, F, alpha, bet, phi, sigma, y, P0, a, b, K)
+
+
+def paper_mc_swaption_problem(golden_dir=None, y=PAPER_HAGAN_CORR):
+    """The fourteen swaptions of the paper's Hagan swaption table (Sec. 4.1.2:
+    expiries 0.5-2 years, tenors 1-4 years, moneyness -40%..40%) on its
+    EURIBOR market under the printed caplet calibration and correlations.
+    Swaption x by L expires at the fixing x years out (fixing index 2x - 1)
+    and covers the 2L semi-annual forwards from there; K = S0 exp(m), S0 the
+    forward swap rate of those forwards with their own accruals as the fixed
+    leg's (the paper does not state the fixed leg's conventions).  Also
+    returns the printed market and Monte Carlo prices (% of notional)."""
+    base = paper_mc_problem(golden_dir, y=y)
+    rows = [[float(v) for v in r] for r in _rows("paper_hagan_swaption_prices.txt", golden_dir)]
+    tau, F = base["tau"], base["F0"]
+    P = [base["P0"]]
+    for k in range(len(F)):
+        P.append(P[-1] / (1.0 + tau[k] * F[k]))
+    a, b, K = [], [], []
+    for e, t, m, _, _ in rows:
+        sa = int(round(2 * e)) - 1
+        sb = sa + int(round(2 * t))
+        A = sum(tau[i] * P[i + 1] for i in range(sa, sb))
+        S0 = (P[sa] - P[sb]) / A
+        a.append(sa)
+        b.append(sb)
+        K.append(S0 * np.exp(m / 100.0))
+    prob = mc_problem_arrays(base["T"], tau, F, base["alpha"], base["beta"], base["phi"],
+                             base["sigma"], y, base["P0"], a, b, K)
+    printed = np.array([[r[3], r[4]] for r in rows])
+    return prob, printed

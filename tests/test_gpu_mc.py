@@ -64,6 +64,8 @@ def test_mc_parity_shapes(api, oracle, M, beta):
 def test_mc_parity_paper_market(api, oracle):
     p = I.paper_mc_problem()
     _compare(api, oracle, p, 512, 0.02, 2408)
+    q, _ = I.paper_mc_swaption_problem()       # the paper's fourteen swaptions
+    _compare(api, oracle, q, 300, 0.01, 2408)
 
 
 def test_mc_parity_coarse_and_fine_steps(api, oracle):

@@ -246,3 +246,18 @@ def test_caplet_does_not_depend_on_the_other_forwards(oracle, phi):
                             opt_b=[1, 1], opt_K=[F, 1.5 * F])
     m1, se1 = oracle.mc_price(q, 60000, 0.02, 32)
     assert np.all(np.abs(m - m1) <= 4.5 * np.hypot(se, se1)), np.c_[m, m1, se, se1]
+
+
+def test_paper_swaption_prices(oracle):
+    """Sec. 4.1.2: at the printed caplet calibration and swaption
+    correlations, the Monte Carlo prices of the paper's fourteen swaptions x
+    five strikes (70 cells, % of notional) reproduce the printed S_MC within
+    5% each and 3% on average (the fixed leg's conventions are not printed:
+    the remainder is a common +2.4%), while the printed market prices S_Black
+    lie up to 20% away: the pin follows the model, not the market."""
+    p, printed = I.paper_mc_swaption_problem()
+    m, se = oracle.mc_price(p, 100000, 0.01, 5)
+    mc = 100.0 * m
+    rel = mc / printed[:, 1] - 1.0
+    assert np.max(np.abs(rel)) < 0.05 and np.mean(np.abs(rel)) < 0.03, rel
+    assert np.max(np.abs(mc / printed[:, 0] - 1.0)) > 0.10
