@@ -349,9 +349,10 @@ size_t sabr_mc_plan_device_bytes(const sabr_mc_plan *plan);
 sabr_status sabr_mc_plan_upload(sabr_mc_plan *plan, void *dev_buf, size_t bytes, void *stream);
 /* The correlation factor B [2 n_fwd][2 n_fwd] (row-major, [host]). */
 sabr_status sabr_mc_factor(const sabr_mc_plan *plan, double *B);
-/* Workspace bytes of sabr_mc_price for n_paths paths (0 if invalid). */
+/* Workspace bytes of sabr_mc_price for n_paths paths (0 if n_paths is out
+ * of range). */
 size_t sabr_mc_workspace_size(const sabr_mc_plan *plan, int64_t n_paths);
-/* Price every option over paths 0..n_paths-1 (1 <= n_paths <= 2^40; at
+/* Price every option over paths 0..n_paths-1 (1 <= n_paths <= 2^38; at
  * most 2^31 time steps): price[o] the mean discounted payoff, stderr_out[o]
  * (may be NULL) its standard error (sample standard deviation / sqrt(n)),
  * both [n_opt] device arrays in the caller's option order.  The results

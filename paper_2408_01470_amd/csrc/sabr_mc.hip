@@ -526,7 +526,7 @@ sabr_status sabr_mc_factor(const sabr_mc_plan *plan, double *B) {
 }
 
 size_t sabr_mc_workspace_size(const sabr_mc_plan *plan, int64_t n_paths) {
-  if (!plan || n_paths < 1) return 0;
+  if (!plan || n_paths < 1 || n_paths > (int64_t(1) << 38)) return 0;
   const long long n_waves = (n_paths + sabr::kWave - 1) / sabr::kWave;
   return (size_t)plan->n_opt * 2 * (size_t)n_waves * sizeof(double);
 }
@@ -537,8 +537,9 @@ sabr_status sabr_mc_price(const sabr_mc_plan *plan, int64_t n_paths, double dt, 
   using namespace sabr;
   if (!plan || !price) return mc_fail(SABR_EINVAL, "null argument");
   if (!plan->dev) return mc_fail(SABR_EINVAL, "mc: plan not uploaded");
-  if (n_paths < 1 || n_paths > (int64_t(1) << 40))
-    return mc_fail(SABR_EINVAL, "mc: n_paths must be 1..2^40");
+  // 2^38 paths = 2^32 waves = 2^30 blocks of four waves: within one grid dimension
+  if (n_paths < 1 || n_paths > (int64_t(1) << 38))
+    return mc_fail(SABR_EINVAL, "mc: n_paths must be 1..2^38");
   if (!is_fin(dt) || !(dt > 0.0)) return mc_fail(SABR_EINVAL, "mc: dt must be positive");
   const size_t need = sabr_mc_workspace_size(plan, n_paths);
   if (!workspace || ws_bytes < need) return mc_fail(SABR_EWORKSPACE, "mc: workspace too small");

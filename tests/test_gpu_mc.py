@@ -109,6 +109,9 @@ def test_mc_errors(api):
     with pytest.raises(Exception) as e:
         plan.price(10, 0.0, 1)
     assert "dt" in str(e.value)
+    with pytest.raises(Exception) as e:       # rejected before any allocation or launch
+        plan.price((1 << 38) + 1, 0.1, 1)
+    assert "n_paths" in str(e.value)
     from paper_2408_01470_amd import _lib
     L = _lib.lib()
     out = torch.empty(plan.n_opt, dtype=torch.float64, device="cuda")
