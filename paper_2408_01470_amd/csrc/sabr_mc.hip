@@ -135,23 +135,49 @@ __device__ __forceinline__ void mc_sincos_2pi(double u, double &sn, double &cs) 
   cs = ((iq + 1) & 2) ? -b : b;
 }
 
-// One path per lane, MF = the problem's forward count (one instantiation per
-// count keeps every register index and loop bound static).  Per step: the
-// increments x of the alive rows are
+// Sum of v over the LPP consecutive lanes of a group (LPP = 4: a quad;
+// 16: a row), by register lane moves; every lane of the group ends with the
+// same bits (each step adds two partial sums, in either order).
+template <int LPP>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (LPP >= 4) {
+    v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  }
+  if constexpr (LPP >= 16) {
+    v += dpp_d<0x141>(v);  // row_half_mirror
+    v += dpp_d<0x140>(v);  // row_mirror
+  }
+  return v;
+}
+
+// MF = the problem's forward count (one instantiation per count keeps every
+// register index and loop bound static); LPP lanes per path: with few paths
+// (LPP = 4 or 16) lane g of a path's group draws the normal pairs m = g,
+// g + LPP, ... and adds their factor columns (a copy of the factor in LDS)
+// into its partial increments, the group sums them, and every lane of the
+// group moves the same forwards.  Per step: the increments x of the alive
+// rows are
 // accumulated column by column (pair m of normals, columns 2m and 2m + 1 of
 // the factor, stored column-major with rows W_k, Z_k interleaved), then the
 // forwards move in increasing k with the drift recursions.
 // Register budget: 4 waves per SIMD up to 13 forwards (measured faster on the
 // paper's 13-forward market despite a few spilled registers), 3 beyond.
-template <int MF>
+template <int MF, int LPP>
 __global__ __launch_bounds__(kWave *kMcWavesPerBlock, (MF <= 13 ? 4 : 3)) void mc_kernel(McArgs a) {
   constexpr int MMAX = MF;
+  constexpr int M = MF, n2 = 2 * MF;
+  __shared__ double Bs[LPP > 1 ? n2 * n2 : 1];
+  if constexpr (LPP > 1) {   // before any wave leaves: the barrier needs them all
+    for (int i = threadIdx.x; i < n2 * n2; i += blockDim.x) Bs[i] = a.B[i];
+    __syncthreads();
+  }
   const int lane = lane_id();
   const long long wave = (long long)blockIdx.x * kMcWavesPerBlock + threadIdx.x / kWave;
   if (wave >= a.n_waves) return;   // whole waves only
-  const long long path = wave * kWave + lane;
+  const int g = lane % LPP;
+  const long long path = wave * (kWave / LPP) + lane / LPP;
   const bool live = path < a.n_paths;
-  constexpr int M = MF, n2 = 2 * MF;
   const double *__restrict__ fw = a.fw;
   const double *__restrict__ Bc = a.B;
   const double eta1 = a.eta1;
@@ -173,21 +199,29 @@ __global__ __launch_bounds__(kWave *kMcWavesPerBlock, (MF <= 13 ? 4 : 3)) void m
       double x[2 * MMAX];
 #pragma unroll
       for (int r = 0; r < 2 * MMAX; ++r) x[r] = 0.0;
-      for (int m = 0; m < M; ++m) {
-        unsigned w[4];
-        philox4x32_10((unsigned)m, step, p_lo, p_hi, a.seed_lo, a.seed_hi, w);
-        const unsigned long long ua = ((unsigned long long)w[0] << 21) + (w[1] >> 11);
-        const unsigned long long ub = ((unsigned long long)w[2] << 21) + (w[3] >> 11);
-        const double u1 = (double)(ua + 1) * 0x1.0p-53;
-        const double u2 = (double)ub * 0x1.0p-53;
-        const double rr = sqrt_gs(-2.0 * mc_log(u1));
-        double sn, cs;
-        mc_sincos_2pi(u2, sn, cs);
-        const double z0 = u1 < 1.0 ? rr * cs : 0.0, z1 = u1 < 1.0 ? rr * sn : 0.0;
-        const double *c0 = Bc + (size_t)(2 * m) * n2, *c1 = c0 + n2;
+      for (int i = 0; i < (M + LPP - 1) / LPP; ++i) {
+        const int m = i * LPP + g;
+        if (LPP == 1 || m < M) {
+          unsigned w[4];
+          philox4x32_10((unsigned)m, step, p_lo, p_hi, a.seed_lo, a.seed_hi, w);
+          const unsigned long long ua = ((unsigned long long)w[0] << 21) + (w[1] >> 11);
+          const unsigned long long ub = ((unsigned long long)w[2] << 21) + (w[3] >> 11);
+          const double u1 = (double)(ua + 1) * 0x1.0p-53;
+          const double u2 = (double)ub * 0x1.0p-53;
+          const double rr = sqrt_gs(-2.0 * mc_log(u1));
+          double sn, cs;
+          mc_sincos_2pi(u2, sn, cs);
+          const double z0 = u1 < 1.0 ? rr * cs : 0.0, z1 = u1 < 1.0 ? rr * sn : 0.0;
+          const double *c0 = (LPP > 1 ? Bs : Bc) + (size_t)(2 * m) * n2, *c1 = c0 + n2;
+#pragma unroll
+          for (int r = 0; r < 2 * MMAX; ++r)
+            if (r >= 2 * j && r < n2) x[r] = fma(c1[r], z1, fma(c0[r], z0, x[r]));
+        }
+      }
+      if constexpr (LPP > 1) {
 #pragma unroll
         for (int r = 0; r < 2 * MMAX; ++r)
-          if (r >= 2 * j && r < n2) x[r] = fma(c1[r], z1, fma(c0[r], z0, x[r]));
+          if (r >= 2 * j) x[r] = group_sum<LPP>(x[r]);
       }
       double Ds = 0.0, E = 0.0, G = 0.0;
 #pragma unroll
@@ -221,7 +255,7 @@ __global__ __launch_bounds__(kWave *kMcWavesPerBlock, (MF <= 13 ? 4 : 3)) void m
           A += fw[MC_TAU * M + i] * Pb;
         }
       }
-      const double xo = live ? D * fmax(1.0 - Pb - K * A, 0.0) : 0.0;
+      const double xo = (live && g == 0) ? D * fmax(1.0 - Pb - K * A, 0.0) : 0.0;
       const double s1 = wave_sum(xo), s2 = wave_sum(xo * xo);
       if (lane == 0) {
         a.part[(2 * (long long)o) * a.n_waves + wave] = s1;
@@ -364,6 +398,15 @@ void corr_factor(int M, const double *T, const double *phi, const double y[5], d
 }
 
 }  // namespace
+
+// Lanes per path: with few paths a path's normal pairs spread over a quad or
+// a row of lanes, so more waves share the steps' latency.
+int mc_lanes_per_path(int M, long long n_paths) {
+  if (M >= 5 && n_paths <= 4096) return 16;
+  if (M >= 4 && n_paths <= 16384) return 4;
+  return 1;
+}
+
 }  // namespace sabr
 
 // ---------------------------------------------------------------------------
@@ -527,7 +570,8 @@ sabr_status sabr_mc_factor(const sabr_mc_plan *plan, double *B) {
 
 size_t sabr_mc_workspace_size(const sabr_mc_plan *plan, int64_t n_paths) {
   if (!plan || n_paths < 1 || n_paths > (int64_t(1) << 38)) return 0;
-  const long long n_waves = (n_paths + sabr::kWave - 1) / sabr::kWave;
+  const long long lanes = n_paths * sabr::mc_lanes_per_path(plan->M, n_paths);
+  const long long n_waves = (lanes + sabr::kWave - 1) / sabr::kWave;
   return (size_t)plan->n_opt * 2 * (size_t)n_waves * sizeof(double);
 }
 
@@ -571,20 +615,26 @@ sabr_status sabr_mc_price(const sabr_mc_plan *plan, int64_t n_paths, double dt, 
   a.opt_b = di + plan->off_b;
   a.opt_off = di + plan->off_off;
   a.part = static_cast<double *>(workspace);
-  a.n_waves = (n_paths + kWave - 1) / kWave;
+  const int lpp = mc_lanes_per_path(plan->M, n_paths);
+  a.n_waves = (n_paths * lpp + kWave - 1) / kWave;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const long long blocks = (a.n_waves + kMcWavesPerBlock - 1) / kMcWavesPerBlock;
   switch (plan->M) {
-#define SABR_MC_CASE(N)                                                                     \
-  case N:                                                                                   \
-    hipLaunchKernelGGL((mc_kernel<N>), dim3((unsigned)blocks), dim3(kWave * kMcWavesPerBlock), \
-                       0, s, a);                                                            \
+#define SABR_MC_LAUNCH(N, L)                                                                   \
+  hipLaunchKernelGGL((mc_kernel<N, L>), dim3((unsigned)blocks), dim3(kWave * kMcWavesPerBlock), \
+                     0, s, a)
+#define SABR_MC_CASE(N)                                                \
+  case N:                                                              \
+    if (N >= 5 && lpp == 16) SABR_MC_LAUNCH(N, (N >= 5 ? 16 : 1));     \
+    else if (N >= 4 && lpp == 4) SABR_MC_LAUNCH(N, (N >= 4 ? 4 : 1));  \
+    else SABR_MC_LAUNCH(N, 1);                                         \
     break;
     SABR_MC_CASE(1) SABR_MC_CASE(2) SABR_MC_CASE(3) SABR_MC_CASE(4) SABR_MC_CASE(5)
     SABR_MC_CASE(6) SABR_MC_CASE(7) SABR_MC_CASE(8) SABR_MC_CASE(9) SABR_MC_CASE(10)
     SABR_MC_CASE(11) SABR_MC_CASE(12) SABR_MC_CASE(13) SABR_MC_CASE(14) SABR_MC_CASE(15)
     SABR_MC_CASE(16)
 #undef SABR_MC_CASE
+#undef SABR_MC_LAUNCH
     default: return mc_fail(SABR_EINVAL, "mc: bad forward count");
   }
   hipError_t e = hipGetLastError();
