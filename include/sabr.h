@@ -361,6 +361,15 @@ sabr_status sabr_mc_price(const sabr_mc_plan *plan, int64_t n_paths, double dt, 
                           double *price, double *stderr_out, void *workspace, size_t ws_bytes,
                           void *stream);
 
+/* The swaption cost f_s of Sec. 3 by this pricer: cost[0] = sum_o w_o
+ * (price_o - target_o)^2 with price as sabr_mc_price computes it over the
+ * same paths (target, weight [n_opt] device arrays in the caller's option
+ * order; weight NULL = 1; price [n_opt] device, or NULL to keep the prices
+ * in the workspace).  The sum runs in a fixed order on the device. */
+sabr_status sabr_mc_cost(const sabr_mc_plan *plan, int64_t n_paths, double dt, uint64_t seed,
+                         const double *target, const double *weight, double *price,
+                         double *cost, void *workspace, size_t ws_bytes, void *stream);
+
 /* Last error message of the calling thread ("" if none). */
 const char *sabr_last_error(void);
 

@@ -104,6 +104,8 @@ def lib():
     L.sabr_mc_workspace_size.restype = ctypes.c_size_t
     L.sabr_mc_price.argtypes = [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, _vp, _vp,
                                 _vp, ctypes.c_size_t, _vp]
+    L.sabr_mc_cost.argtypes = [_vp, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, _vp, _vp,
+                               _vp, _vp, _vp, ctypes.c_size_t, _vp]
     _lib = L
     return _lib
 

@@ -339,3 +339,17 @@ class McPlan(McProblem):
         check(lib().sabr_mc_price(self._h, int(n_paths), float(dt), int(seed), _ptr(price),
                                   _ptr(se), _ptr(ws), ws.numel(), _stream(stream)))
         return price, se
+
+    def cost(self, n_paths, dt, seed, target, weight=None, stream=None):
+        """The swaption cost sum_o w_o (price_o - target_o)^2 over the same
+        paths as price(); returns (cost, price) as float64 device tensors."""
+        target = torch.as_tensor(target, dtype=torch.float64, device=self.device).contiguous()
+        w = None if weight is None else torch.as_tensor(weight, dtype=torch.float64,
+                                                        device=self.device).contiguous()
+        price = torch.empty(self.n_opt, dtype=torch.float64, device=self.device)
+        cost = torch.empty(1, dtype=torch.float64, device=self.device)
+        ws, n = self.workspace(n_paths)
+        check(lib().sabr_mc_cost(self._h, int(n_paths), float(dt), int(seed), _ptr(target),
+                                 _ptr(w), _ptr(price), _ptr(cost), _ptr(ws), ws.numel(),
+                                 _stream(stream)))
+        return cost, price

@@ -305,6 +305,28 @@ __global__ __launch_bounds__(kMcReduceThreads) void mc_reduce_kernel(const doubl
   }
 }
 
+// The swaption cost of Sec. 3 over the options' prices: sum_o w_o (price_o -
+// target_o)^2 (w = 1 without weights), one block, a fixed order.
+__global__ __launch_bounds__(kMcReduceThreads) void mc_cost_kernel(const double *price,
+                                                                   const double *target,
+                                                                   const double *weight, int n,
+                                                                   double *cost) {
+  __shared__ double s1[kMcReduceThreads];
+  const int t = threadIdx.x;
+  double a = 0.0;
+  for (int o = t; o < n; o += kMcReduceThreads) {
+    const double r = price[o] - target[o];
+    a += (weight ? weight[o] : 1.0) * r * r;
+  }
+  s1[t] = a;
+  __syncthreads();
+  for (int w = kMcReduceThreads / 2; w > 0; w >>= 1) {
+    if (t < w) s1[t] += s1[t + w];
+    __syncthreads();
+  }
+  if (t == 0) cost[0] = s1[0];
+}
+
 // ---------------------------------------------------------------------------
 // Host: the correlation factor.  The 2M x 2M matrix of eqs. (rhoij),
 // (thetaij), (phiij) (rows W_0..W_{M-1}, Z_0..Z_{M-1}; entry (k, M + l) =
@@ -572,7 +594,8 @@ size_t sabr_mc_workspace_size(const sabr_mc_plan *plan, int64_t n_paths) {
   if (!plan || n_paths < 1 || n_paths > (int64_t(1) << 38)) return 0;
   const long long lanes = n_paths * sabr::mc_lanes_per_path(plan->M, n_paths);
   const long long n_waves = (lanes + sabr::kWave - 1) / sabr::kWave;
-  return (size_t)plan->n_opt * 2 * (size_t)n_waves * sizeof(double);
+  // per-wave partial sums, then one price per option (used by sabr_mc_cost)
+  return ((size_t)plan->n_opt * 2 * (size_t)n_waves + (size_t)plan->n_opt) * sizeof(double);
 }
 
 sabr_status sabr_mc_price(const sabr_mc_plan *plan, int64_t n_paths, double dt, uint64_t seed,
@@ -643,6 +666,28 @@ sabr_status sabr_mc_price(const sabr_mc_plan *plan, int64_t n_paths, double dt, 
                      a.n_waves, (long long)n_paths, di + plan->off_ext, price, stderr_out);
   e = hipGetLastError();
   if (e != hipSuccess) return mc_hip_fail(e, "mc reduce launch");
+  return SABR_OK;
+}
+
+sabr_status sabr_mc_cost(const sabr_mc_plan *plan, int64_t n_paths, double dt, uint64_t seed,
+                         const double *target, const double *weight, double *price,
+                         double *cost, void *workspace, size_t ws_bytes, void *stream) {
+  using namespace sabr;
+  if (!plan || !target || !cost) return mc_fail(SABR_EINVAL, "null argument");
+  const size_t need = sabr_mc_workspace_size(plan, n_paths);
+  if (need == 0) return mc_fail(SABR_EINVAL, "mc: n_paths must be 1..2^38");
+  if (!workspace || ws_bytes < need) return mc_fail(SABR_EWORKSPACE, "mc: workspace too small");
+  double *p = price ? price
+                    : reinterpret_cast<double *>(static_cast<char *>(workspace) + need) -
+                          plan->n_opt;
+  const sabr_status st =
+      sabr_mc_price(plan, n_paths, dt, seed, p, nullptr, workspace, ws_bytes, stream);
+  if (st != SABR_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(mc_cost_kernel, dim3(1), dim3(kMcReduceThreads), 0, s, p, target, weight,
+                     plan->n_opt, cost);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return mc_hip_fail(e, "mc cost launch");
   return SABR_OK;
 }
 

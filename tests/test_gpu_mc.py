@@ -121,3 +121,31 @@ def test_mc_errors(api):
     rc = L.sabr_mc_price(plan._h, 1000, 0.1, 1, ctypes.c_void_p(out.data_ptr()), None,
                          ctypes.c_void_p(ws.data_ptr()), 8, None)
     assert rc == -5 and b"workspace" in L.sabr_last_error()
+
+
+def test_mc_cost(api, oracle):
+    """sabr_mc_cost: the swaption cost of Sec. 3 over the same paths, against
+    the oracle's prices; with and without weights, with the prices kept in
+    the workspace."""
+    p, printed = I.paper_mc_swaption_problem()
+    tgt = printed[:, 0] / 100.0                  # the printed market prices
+    w = np.linspace(0.5, 2.0, len(tgt))
+    plan = api.McPlan(p)
+    mo, _ = oracle.mc_price(p, 400, 0.02, 9)
+    for weight in (None, w):
+        c, pr = plan.cost(400, 0.02, 9, tgt, weight)
+        ww = np.ones(len(tgt)) if weight is None else w
+        np.testing.assert_allclose(pr.cpu().numpy(), mo, rtol=RTOL, atol=1e-15)
+        assert float(c.cpu()[0]) == pytest.approx(float(np.sum(ww * (mo - tgt) ** 2)), rel=1e-8)
+    from paper_2408_01470_amd import _lib
+    import ctypes
+    L = _lib.lib()
+    ws, n = plan.workspace(400)
+    t = torch.tensor(tgt, device="cuda")
+    out = torch.empty(1, dtype=torch.float64, device="cuda")
+    assert L.sabr_mc_cost(plan._h, 400, 0.02, 9, ctypes.c_void_p(t.data_ptr()), None, None,
+                          ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), n,
+                          None) == 0
+    torch.cuda.synchronize()
+    c, _ = plan.cost(400, 0.02, 9, tgt)
+    assert float(out.cpu()[0]) == float(c.cpu()[0])
