@@ -261,3 +261,42 @@ def test_paper_swaption_prices(oracle):
     rel = mc / printed[:, 1] - 1.0
     assert np.max(np.abs(rel)) < 0.05 and np.mean(np.abs(rel)) < 0.03, rel
     assert np.max(np.abs(mc / printed[:, 0] - 1.0)) > 0.10
+
+
+def _sabr_forward_measure(F0, alpha, beta, phi, sigma, T, K, n, dt, seed):
+    """Plain numpy Monte Carlo of one forward's SABR pair under its payment
+    measure (no drifts: dF = V F^beta dW, dV = sigma V dZ, corr phi), the
+    textbook form a caplet sees; E[(F_T - K)^+] per strike with its error."""
+    g = np.random.default_rng(seed)
+    steps = int(np.ceil(T / dt))
+    h = T / steps
+    F = np.full(n, F0)
+    V = np.full(n, alpha)
+    for _ in range(steps):
+        z1 = g.standard_normal(n)
+        z2 = phi * z1 + math.sqrt(1.0 - phi * phi) * g.standard_normal(n)
+        s = V * np.maximum(F, 0.0) ** beta
+        F = np.maximum(F + s * math.sqrt(h) * z1, 0.0)
+        V = V * np.exp(-0.5 * sigma * sigma * h + sigma * math.sqrt(h) * z2)
+    pay = np.maximum(F[:, None] - np.asarray(K)[None, :], 0.0)
+    return pay.mean(axis=0), pay.std(axis=0, ddof=1) / math.sqrt(n)
+
+
+def test_caplet_matches_its_forward_measure_sabr(oracle):
+    """The joint spot-measure simulation of five forwards prices the last
+    forward's caplets as the SABR model under that caplet's payment measure
+    does (an independent drift-free simulation): the spot-measure drifts of
+    F and of V (mu^F, mu^V of Sec. 2.1) are exactly the change of measure."""
+    M = 5
+    phi = np.array([-0.5] * M)
+    F, alpha = 0.10, 0.6 * math.sqrt(0.10)
+    K = [F, 1.5 * F]
+    p = I.mc_problem_arrays(T=np.arange(1.0, M + 1), tau=1.0, F0=F, alpha=alpha, beta=0.5,
+                            phi=phi, sigma=0.8, y=(0.0, 1.0, 0.0, 1.0, 0.3), P0=0.97,
+                            opt_a=[M - 1, M - 1], opt_b=[M, M], opt_K=K)
+    assert np.linalg.eigvalsh(oracle.mc_corr_matrix(p["T"], p["phi"], p["y"])).min() > 0
+    m, se = oracle.mc_price(p, 100000, 0.02, 41)
+    P = _discounts(p)
+    ref, rse = _sabr_forward_measure(F, alpha, 0.5, -0.5, 0.8, float(M), K, 100000, 0.02, 42)
+    ref, rse = P[M] * ref, P[M] * rse            # tau = 1: the caplet is P(0, pay) E[(F - K)^+]
+    assert np.all(np.abs(m - ref) <= 4.5 * np.hypot(se, rse)), np.c_[m, ref, se, rse]
