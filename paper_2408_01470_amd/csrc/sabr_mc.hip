@@ -135,15 +135,13 @@ __device__ __forceinline__ void mc_sincos_2pi(double u, double &sn, double &cs) 
   cs = ((iq + 1) & 2) ? -b : b;
 }
 
-// Sum of v over the LPP consecutive lanes of a group (LPP = 4: a quad;
-// 16: a row), by register lane moves; every lane of the group ends with the
-// same bits (each step adds two partial sums, in either order).
+// Sum of v over the LPP consecutive lanes of a group (LPP = 2: a pair; 4: a
+// quad; 16: a row), by register lane moves; every lane of the group ends
+// with the same bits (each step adds two partial sums, in either order).
 template <int LPP>
 __device__ __forceinline__ double group_sum(double v) {
-  if constexpr (LPP >= 4) {
-    v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
-    v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-  }
+  if constexpr (LPP >= 2) v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  if constexpr (LPP >= 4) v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
   if constexpr (LPP >= 16) {
     v += dpp_d<0x141>(v);  // row_half_mirror
     v += dpp_d<0x140>(v);  // row_mirror
@@ -153,7 +151,7 @@ __device__ __forceinline__ double group_sum(double v) {
 
 // MF = the problem's forward count (one instantiation per count keeps every
 // register index and loop bound static); LPP lanes per path: with few paths
-// (LPP = 4 or 16) lane g of a path's group draws the normal pairs m = g,
+// (LPP = 2, 4 or 16) lane g of a path's group draws the normal pairs m = g,
 // g + LPP, ... and adds their factor columns (a copy of the factor in LDS)
 // into its partial increments, the group sums them, and every lane of the
 // group moves the same forwards.  Per step: the increments x of the alive
@@ -426,6 +424,7 @@ void corr_factor(int M, const double *T, const double *phi, const double y[5], d
 int mc_lanes_per_path(int M, long long n_paths) {
   if (M >= 5 && n_paths <= 4096) return 16;
   if (M >= 4 && n_paths <= 16384) return 4;
+  if (M >= 2 && n_paths <= 131072) return 2;
   return 1;
 }
 
@@ -650,6 +649,7 @@ sabr_status sabr_mc_price(const sabr_mc_plan *plan, int64_t n_paths, double dt, 
   case N:                                                              \
     if (N >= 5 && lpp == 16) SABR_MC_LAUNCH(N, (N >= 5 ? 16 : 1));     \
     else if (N >= 4 && lpp == 4) SABR_MC_LAUNCH(N, (N >= 4 ? 4 : 1));  \
+    else if (N >= 2 && lpp == 2) SABR_MC_LAUNCH(N, (N >= 2 ? 2 : 1));  \
     else SABR_MC_LAUNCH(N, 1);                                         \
     break;
     SABR_MC_CASE(1) SABR_MC_CASE(2) SABR_MC_CASE(3) SABR_MC_CASE(4) SABR_MC_CASE(5)

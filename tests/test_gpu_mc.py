@@ -3,8 +3,8 @@ Monte Carlo under the Hagan SABR/LIBOR dynamics (Sec. 2.1): the same paths
 (the counter-based normals of both sides, the same scheme), so every price
 and standard error agrees to rounding (the elementary functions and the
 order of the sums differ: relative 1e-9 is allowed); across path counts
-that leave ragged waves and select 16, 4 or 1 lanes per path (up to 4096,
-16384 and beyond), one forward and the most forwards, expiries at the
+that leave ragged waves and select 16, 4, 2 or 1 lanes per path (up to
+4096, 16384, 131072 and beyond), one forward and the most forwards, expiries at the
 first and last fixing, and the paper's market.  At the replay's full size
 (1e6 paths, dt = 1e-3) the prices are checked by properties that hold at any
 size: a zero-strike swaption is worth P(0, T_a) - P(0, T_b), and the
@@ -42,7 +42,7 @@ def _compare(api, oracle, p, n_paths, dt, seed):
     return m, se
 
 
-@pytest.mark.parametrize("n_paths", [1, 63, 64, 65, 1000, 4099, 16385])
+@pytest.mark.parametrize("n_paths", [1, 63, 64, 65, 1000, 4099, 16385, 131073])
 def test_mc_parity_path_counts(api, oracle, n_paths):
     p = I.mc_problem(seed=I.SEED_BASE + 9800, M=8, n_cap_K=3, n_swaptions=6)
     m, se = _compare(api, oracle, p, n_paths, 0.05, 17)
