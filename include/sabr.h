@@ -302,11 +302,11 @@ sabr_status sabr_nm_polish(const sabr_plan *plan, int32_t n_pts, const int32_t *
  * interval is cut into ceil(length / dt) (at least one) equal steps; a step
  * moves F_k by Euler (floored at 0) and V_k by log-Euler, driven by
  * x = sqrt(h) B xi where B is the plan's correlation factor (below) and xi
- * the step's 2 n_fwd standard normals: pair m of step s on path p is the
- * Box-Muller transform of the Philox4x32-10 block at counter (m, s, p mod
- * 2^32, p / 2^32) and key (seed mod 2^32, seed / 2^32), words (w0, w1) and
- * (w2, w3) giving the 53-bit uniforms u1 = (w0 2^21 + (w1 >> 11) + 1) 2^-53
- * and u2 = (w2 2^21 + (w3 >> 11)) 2^-53.  The drift of V_k takes the
+ * the step's 2 n_fwd standard normals: pairs 2b and 2b + 1 of step s on
+ * path p are the Box-Muller transforms of the Philox4x32-10 block at
+ * counter (b, s, p mod 2^32, p / 2^32) and key (seed mod 2^32, seed / 2^32),
+ * words (w0, w1) for pair 2b and (w2, w3) for pair 2b + 1, each giving
+ * u1 = (w_first + 1) 2^-32 and u2 = w_second 2^-32.  The drift of V_k takes the
  * covariance of Z_k with W_i, phi_{i,k}.  At T[a] option (a, b, K) pays
  * max(1 - P(T_a, T_b) - K sum_{i=a}^{b-1} tau_i P(T_a, T_{i+1}), 0)
  * (a payer swaption on forwards a..b-1; b = a + 1 is the caplet on F_a),

@@ -980,10 +980,10 @@ void nm_one(const Inst &I, int P, double *p, const double *lb, const double *ub,
 //    numeraire's drivers) and x = sqrt(h) B xi, B (2M x 2M, rows W_0..W_{M-1},
 //    Z_0..Z_{M-1}) the correlation factor given by the caller, xi the step's
 //    2M standard normals.
-//  - Normals: pair m = 0..M-1 of step s on path p is Box-Muller of Philox4x32-10
-//    block (counter (m, s, p mod 2^32, p / 2^32), key (seed mod 2^32,
-//    seed / 2^32)): words (w0, w1) give u1 = (w0 2^21 + (w1 >> 11) + 1) 2^-53,
-//    (w2, w3) give u2 = (w2 2^21 + (w3 >> 11)) 2^-53;  r = sqrt(-2 ln u1),
+//  - Normals: pairs 2b and 2b + 1 of step s on path p are Box-Muller of the
+//    Philox4x32-10 block (counter (b, s, p mod 2^32, p / 2^32), key (seed mod
+//    2^32, seed / 2^32)): words (w0, w1) for pair 2b, (w2, w3) for pair
+//    2b + 1, u1 = (w_first + 1) 2^-32, u2 = w_second 2^-32;  r = sqrt(-2 ln u1),
 //    t = 2 pi u2, xi_{2m} = r cos t, xi_{2m+1} = r sin t.
 //  - Deflator D = P(0, T_0) at t = 0, divided by (1 + tau_j F_j(T_j)) at each
 //    fixing T_j after the payoffs expiring there are taken.
@@ -1017,15 +1017,16 @@ void philox4x32_10(const uint32_t in[4], const uint32_t key_in[2], uint32_t out[
 
 void mc_normals(uint64_t seed, int64_t path, int64_t step, int M, double *xi) {
   const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4] = {0, 0, 0, 0};
   for (int m = 0; m < M; ++m) {
-    const uint32_t ctr[4] = {(uint32_t)m, (uint32_t)step, (uint32_t)path,
-                             (uint32_t)((uint64_t)path >> 32)};
-    uint32_t w[4];
-    philox4x32_10(ctr, key, w);
-    const uint64_t a = ((uint64_t)w[0] << 21) + (w[1] >> 11);
-    const uint64_t b = ((uint64_t)w[2] << 21) + (w[3] >> 11);
-    const double u1 = (double)(a + 1) * 0x1.0p-53;
-    const double u2 = (double)b * 0x1.0p-53;
+    if (m % 2 == 0) {
+      const uint32_t ctr[4] = {(uint32_t)(m / 2), (uint32_t)step, (uint32_t)path,
+                               (uint32_t)((uint64_t)path >> 32)};
+      philox4x32_10(ctr, key, w);
+    }
+    const uint32_t wa = w[2 * (m % 2)], wb = w[2 * (m % 2) + 1];
+    const double u1 = ((double)wa + 1.0) * 0x1.0p-32;
+    const double u2 = (double)wb * 0x1.0p-32;
     const double r = std::sqrt(-2.0 * std::log(u1));
     const double t = 6.283185307179586 * u2;
     xi[2 * m] = r * std::cos(t);

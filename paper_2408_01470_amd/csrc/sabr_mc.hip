@@ -12,8 +12,8 @@
 //   V_k <- V_k exp((sigma_k sum_{i=j..k} phi_{i,k} d_i - sigma_k^2/2) h
 //                  + sigma_k x_{M+k})                                   (log-Euler)
 // with x = sqrt(h) B xi, B the correlation factor of the plan and xi the
-// step's 2M normals (Box-Muller of Philox4x32-10 blocks, counter (pair,
-// step, path), key seed).  Both sums are O(M) recursions over the gaps:
+// step's 2M normals (Box-Muller of Philox4x32-10 blocks, two pairs a block
+// from 32-bit uniforms, counter (block, step, path), key seed).  Both sums are O(M) recursions over the gaps:
 // rho_{k,i} = eta1 + (1 - eta1) prod_{l=i+1..k} g1_l and phi_{i,k} =
 // sgn(phi_i) sqrt|phi_i| sqrt|phi_k| prod_{l=i+1..k} g3_l, g = exp(-lambda
 // (T_l - T_{l-1})).  At each fixing T_j the payoffs of the options expiring
@@ -136,25 +136,23 @@ __device__ __forceinline__ void mc_sincos_2pi(double u, double &sn, double &cs) 
 }
 
 // Sum of v over the LPP consecutive lanes of a group (LPP = 2: a pair; 4: a
-// quad; 16: a row), by register lane moves; every lane of the group ends
-// with the same bits (each step adds two partial sums, in either order).
+// quad; 8: a half row), by register lane moves; every lane of the group
+// ends with the same bits (each step adds two partial sums, in either
+// order).
 template <int LPP>
 __device__ __forceinline__ double group_sum(double v) {
-  if constexpr (LPP >= 2) v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
-  if constexpr (LPP >= 4) v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-  if constexpr (LPP >= 16) {
-    v += dpp_d<0x141>(v);  // row_half_mirror
-    v += dpp_d<0x140>(v);  // row_mirror
-  }
+  if constexpr (LPP >= 2) v += dpp_d<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  if constexpr (LPP >= 4) v += dpp_d<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  if constexpr (LPP >= 8) v += dpp_d<0x141>(v);   // row_half_mirror
   return v;
 }
 
 // MF = the problem's forward count (one instantiation per count keeps every
 // register index and loop bound static); LPP lanes per path: with few paths
-// (LPP = 2, 4 or 16) lane g of a path's group draws the normal pairs m = g,
-// g + LPP, ... and adds their factor columns (a copy of the factor in LDS)
-// into its partial increments, the group sums them, and every lane of the
-// group moves the same forwards.  Per step: the increments x of the alive
+// (LPP = 2, 4 or 8) lane g of a path's group draws the Philox blocks b = g,
+// g + LPP, ... (normal pairs 2b and 2b + 1) and adds their factor columns
+// (a copy of the factor in LDS) into its partial increments, the group sums
+// them, and every lane of the group moves the same forwards.  Per step: the increments x of the alive
 // rows are
 // accumulated column by column (pair m of normals, columns 2m and 2m + 1 of
 // the factor, stored column-major with rows W_k, Z_k interleaved), then the
@@ -197,23 +195,27 @@ __global__ __launch_bounds__(kWave *kMcWavesPerBlock, (MF <= 13 ? 4 : 3)) void m
       double x[2 * MMAX];
 #pragma unroll
       for (int r = 0; r < 2 * MMAX; ++r) x[r] = 0.0;
-      for (int i = 0; i < (M + LPP - 1) / LPP; ++i) {
-        const int m = i * LPP + g;
-        if (LPP == 1 || m < M) {
-          unsigned w[4];
-          philox4x32_10((unsigned)m, step, p_lo, p_hi, a.seed_lo, a.seed_hi, w);
-          const unsigned long long ua = ((unsigned long long)w[0] << 21) + (w[1] >> 11);
-          const unsigned long long ub = ((unsigned long long)w[2] << 21) + (w[3] >> 11);
-          const double u1 = (double)(ua + 1) * 0x1.0p-53;
-          const double u2 = (double)ub * 0x1.0p-53;
-          const double rr = sqrt_gs(-2.0 * mc_log(u1));
-          double sn, cs;
-          mc_sincos_2pi(u2, sn, cs);
-          const double z0 = u1 < 1.0 ? rr * cs : 0.0, z1 = u1 < 1.0 ? rr * sn : 0.0;
-          const double *c0 = (LPP > 1 ? Bs : Bc) + (size_t)(2 * m) * n2, *c1 = c0 + n2;
+      // normal pair m from words (wa, wb): its two factor columns into x
+      auto pair = [&](int m, unsigned wa, unsigned wb) {
+        const double u1 = ((double)wa + 1.0) * 0x1.0p-32;
+        const double u2 = (double)wb * 0x1.0p-32;
+        const double rr = sqrt_gs(-2.0 * mc_log(u1));
+        double sn, cs;
+        mc_sincos_2pi(u2, sn, cs);
+        const double z0 = u1 < 1.0 ? rr * cs : 0.0, z1 = u1 < 1.0 ? rr * sn : 0.0;
+        const double *c0 = (LPP > 1 ? Bs : Bc) + (size_t)(2 * m) * n2, *c1 = c0 + n2;
 #pragma unroll
-          for (int r = 0; r < 2 * MMAX; ++r)
-            if (r >= 2 * j && r < n2) x[r] = fma(c1[r], z1, fma(c0[r], z0, x[r]));
+        for (int r = 0; r < 2 * MMAX; ++r)
+          if (r >= 2 * j && r < n2) x[r] = fma(c1[r], z1, fma(c0[r], z0, x[r]));
+      };
+      constexpr int NB = (M + 1) / 2;   // Philox blocks a step: two pairs each
+      for (int i = 0; i < (NB + LPP - 1) / LPP; ++i) {
+        const int b = i * LPP + g;
+        if (LPP == 1 || b < NB) {
+          unsigned w[4];
+          philox4x32_10((unsigned)b, step, p_lo, p_hi, a.seed_lo, a.seed_hi, w);
+          pair(2 * b, w[0], w[1]);
+          if (2 * b + 1 < M) pair(2 * b + 1, w[2], w[3]);
         }
       }
       if constexpr (LPP > 1) {
@@ -228,7 +230,13 @@ __global__ __launch_bounds__(kWave *kMcWavesPerBlock, (MF <= 13 ? 4 : 3)) void m
           const double f = F[k], v = V[k];
           const double tk = fw[MC_TAU * M + k], bk = fw[MC_BETA * M + k];
           const double fp = fmax(f, 0.0);
-          const double fb = fp > 0.0 ? exp_cw(bk * mc_log(fp)) : (bk == 0.0 ? 1.0 : 0.0);
+          double fb;   // F^beta; beta is wave-uniform: a scalar branch
+          if (bk == 0.5)
+            fb = fp > 0.0 ? sqrt_gs(fp) : 0.0;
+          else if (bk == 1.0)
+            fb = fp;
+          else
+            fb = fp > 0.0 ? exp_cw(bk * mc_log(fp)) : (bk == 0.0 ? 1.0 : 0.0);
           const double s = v * fb;
           const double d = tk * s * rcp_nr(fma(tk, f, 1.0));
           Ds += d;
@@ -422,9 +430,10 @@ void corr_factor(int M, const double *T, const double *phi, const double y[5], d
 // Lanes per path: with few paths a path's normal pairs spread over a quad or
 // a row of lanes, so more waves share the steps' latency.
 int mc_lanes_per_path(int M, long long n_paths) {
-  if (M >= 5 && n_paths <= 4096) return 16;
-  if (M >= 4 && n_paths <= 16384) return 4;
-  if (M >= 2 && n_paths <= 131072) return 2;
+  const int nb = (M + 1) / 2;   // Philox blocks a step
+  if (n_paths <= 4096 && nb >= 5) return 8;
+  if (n_paths <= 16384 && nb >= 3) return 4;
+  if (n_paths <= 131072 && nb >= 2) return 2;
   return 1;
 }
 
@@ -647,9 +656,9 @@ sabr_status sabr_mc_price(const sabr_mc_plan *plan, int64_t n_paths, double dt, 
                      0, s, a)
 #define SABR_MC_CASE(N)                                                \
   case N:                                                              \
-    if (N >= 5 && lpp == 16) SABR_MC_LAUNCH(N, (N >= 5 ? 16 : 1));     \
-    else if (N >= 4 && lpp == 4) SABR_MC_LAUNCH(N, (N >= 4 ? 4 : 1));  \
-    else if (N >= 2 && lpp == 2) SABR_MC_LAUNCH(N, (N >= 2 ? 2 : 1));  \
+    if (N >= 9 && lpp == 8) SABR_MC_LAUNCH(N, (N >= 9 ? 8 : 1));       \
+    else if (N >= 5 && lpp == 4) SABR_MC_LAUNCH(N, (N >= 5 ? 4 : 1));  \
+    else if (N >= 3 && lpp == 2) SABR_MC_LAUNCH(N, (N >= 3 ? 2 : 1));  \
     else SABR_MC_LAUNCH(N, 1);                                         \
     break;
     SABR_MC_CASE(1) SABR_MC_CASE(2) SABR_MC_CASE(3) SABR_MC_CASE(4) SABR_MC_CASE(5)

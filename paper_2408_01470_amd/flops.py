@@ -196,18 +196,27 @@ def cost_launch_flops(market: dict, pt_inst) -> float:
 MC_LOG = 32.0
 MC_SINCOS = 42.0
 MC_BOX_MULLER = MC_LOG + _e("sqrt") + MC_SINCOS + 5          # per normal pair: 92
-MC_PER_FORWARD = (1 + MC_LOG + _e("exp")           # max(F, 0)^beta = exp(beta log F)
-                  + 1 + 4 + _e("rcp")              # s = V F^beta, d = tau s / (1 + tau F)
-                  + 6                              # the three drift recursions
-                  + 10                             # the F update
-                  + 10 + _e("exp"))                # the V update: 125 in all
+MC_PER_FORWARD_REST = (1 + 4 + _e("rcp")          # s = V F^beta, d = tau s / (1 + tau F)
+                       + 6                         # the three drift recursions
+                       + 10                        # the F update
+                       + 10 + _e("exp"))           # the V update: 65
 
 
-def mc_step_flops(M: int, n_alive: int) -> float:
-    """One path step with n_alive of M forwards alive: M normal pairs, each
-    adding its two factor columns into the 2 n_alive alive rows (two fma per
-    row), and the per-forward drift and updates."""
-    return M * MC_BOX_MULLER + n_alive * (4 * 2 * M + MC_PER_FORWARD)
+def mc_power_flops(beta: float) -> float:
+    """max(F, 0)^beta: sqrt at beta = 1/2, F itself at 1, else exp(beta log F)."""
+    if beta == 0.5:
+        return _e("sqrt")
+    if beta == 1.0:
+        return 0.0
+    return 1 + MC_LOG + _e("exp")
+
+
+def mc_step_flops(M: int, betas_alive) -> float:
+    """One path step with the forwards of betas_alive alive (of M): M normal
+    pairs, each adding its two factor columns into the alive rows (two fma
+    per row), and each alive forward's power, drift and updates."""
+    return M * MC_BOX_MULLER + sum(4 * 2 * M + mc_power_flops(b) + MC_PER_FORWARD_REST
+                                   for b in betas_alive)
 
 
 def mc_steps(T, dt, amax):
@@ -225,7 +234,8 @@ def mc_launch_flops(prob: dict, n_paths: int, dt: float) -> float:
     M = len(prob["T"])
     amax = int(np.max(prob["opt_a"]))
     n = mc_steps(prob["T"], dt, amax)
-    return float(n_paths) * sum(n[j] * mc_step_flops(M, M - j) for j in range(amax + 1))
+    beta = [float(b) for b in prob["beta"]]
+    return float(n_paths) * sum(n[j] * mc_step_flops(M, beta[j:]) for j in range(amax + 1))
 
 
 def mc_path_steps(prob: dict, n_paths: int, dt: float) -> float:

@@ -3,8 +3,8 @@ Monte Carlo under the Hagan SABR/LIBOR dynamics (Sec. 2.1): the same paths
 (the counter-based normals of both sides, the same scheme), so every price
 and standard error agrees to rounding (the elementary functions and the
 order of the sums differ: relative 1e-9 is allowed); across path counts
-that leave ragged waves and select 16, 4, 2 or 1 lanes per path (up to
-4096, 16384, 131072 and beyond), one forward and the most forwards, expiries at the
+that leave ragged waves and select 4, 2 or 1 lanes per path (up to 16384,
+131072 and beyond; 8 lanes on the 13- and 16-forward cases), one forward and the most forwards, expiries at the
 first and last fixing, and the paper's market.  At the replay's full size
 (1e6 paths, dt = 1e-3) the prices are checked by properties that hold at any
 size: a zero-strike swaption is worth P(0, T_a) - P(0, T_b), and the

@@ -31,15 +31,16 @@ def test_philox4x32_known_answers(oracle, ctr, key, out):
 
 
 def test_normals_layout(oracle):
-    """Pair m of step s on path p: Box-Muller of block (m, s, p_lo, p_hi)
-    under key (seed_lo, seed_hi), 53-bit uniforms from word pairs."""
-    seed, path, step, M = (7 << 32) + 3, (1 << 32) + 5, 11, 3
+    """Pairs 2b and 2b + 1 of step s on path p: Box-Muller of block (b, s,
+    p_lo, p_hi) under key (seed_lo, seed_hi), words (w0, w1) and (w2, w3),
+    32-bit uniforms u1 = (w + 1) 2^-32, u2 = w' 2^-32."""
+    seed, path, step, M = (7 << 32) + 3, (1 << 32) + 5, 11, 5
     xi = oracle.mc_normals(seed, path, step, M)
     for m in range(M):
-        w = [int(v) for v in oracle.philox4x32((m, step, path & 0xFFFFFFFF, path >> 32),
+        w = [int(v) for v in oracle.philox4x32((m // 2, step, path & 0xFFFFFFFF, path >> 32),
                                                (seed & 0xFFFFFFFF, seed >> 32))]
-        u1 = ((w[0] << 21) + (w[1] >> 11) + 1) / 2.0 ** 53
-        u2 = ((w[2] << 21) + (w[3] >> 11)) / 2.0 ** 53
+        u1 = (w[2 * (m % 2)] + 1) / 2.0 ** 32
+        u2 = w[2 * (m % 2) + 1] / 2.0 ** 32
         r = math.sqrt(-2.0 * math.log(u1))
         assert xi[2 * m] == pytest.approx(r * math.cos(2 * math.pi * u2), rel=1e-15, abs=1e-15)
         assert xi[2 * m + 1] == pytest.approx(r * math.sin(2 * math.pi * u2), rel=1e-15,
