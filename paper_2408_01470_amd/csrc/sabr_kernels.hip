@@ -62,40 +62,58 @@ __global__ void prep_kernel(DevMarket m, QuoteRec *q, double *f_v, double *u_S0b
 }
 
 // ---------------------------------------------------------------------------
-// sabr_cost_batch: one wave per point.
+// sabr_cost_batch: one wave per point, up to kCostWaves points per workgroup.
 // ---------------------------------------------------------------------------
+constexpr int kCostWaves = 8;
+
 template <int MODEL, int FORMULA, int RESID>
-__global__ __launch_bounds__(256) void cost_kernel(DevMarket m, int n_pts, const int *pt_inst,
-                                                   const double *params, double *cost,
-                                                   double *resid, double *model, int stride,
-                                                   int lds_per_wave) {
+__global__ __launch_bounds__(kWave *kCostWaves, 4) void cost_kernel(DevMarket m, int n_pts,
+                                                                   const int *pt_inst,
+                                                                   const double *params,
+                                                                   double *cost, double *resid,
+                                                                   double *model, int stride,
+                                                                   int lds_per_wave) {
   extern __shared__ double smem[];
+  __shared__ int s_inst[kCostWaves];
   constexpr int PC = NP<MODEL>::P;       // 0: known at run time (PERFWD)
   const int P = PC > 0 ? PC : m.np;
+  const int nw = blockDim.x / kWave;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int pt = blockIdx.x * (blockDim.x / kWave) + wid;
-  if (pt >= n_pts) return;
-  const int inst = __builtin_amdgcn_readfirstlane(pt_inst[pt]);
-  if (inst < 0 || inst >= m.n_inst) {
-    if (lane_id() == 0) cost[pt] = __builtin_nan("");
-    return;
-  }
-  const DevInst in = m.inst[inst];
-  // each wave stages its own copy: the points of one workgroup may belong to
-  // different instances
-  double *base = smem + (size_t)wid * lds_per_wave;
-  UndMkt *um = reinterpret_cast<UndMkt *>(base);
-  for (int u = lane_id(); u < in.nu; u += kWave) um[u] = und_mkt(m, in.u0 + u);
-  wave_lds_sync();
-  double p[PC > 0 ? PC : 1];
+  const int pt = blockIdx.x * nw + wid;
+  int inst = -1;
+  if (pt < n_pts) inst = __builtin_amdgcn_readfirstlane(pt_inst[pt]);
+  const bool valid = pt < n_pts && inst >= 0 && inst < m.n_inst;
+  if (pt < n_pts && !valid && lane_id() == 0) cost[pt] = __builtin_nan("");
+  if (lane_id() == 0) s_inst[wid] = valid ? inst : -1;
+  __syncthreads();
+  // The workgroup's waves share one copy of the per-underlying market values:
+  // one round per distinct instance among them (one round when the points of
+  // a workgroup belong to one instance, the usual batch layout).  Every wave
+  // takes part in every round's barriers.
+  UndMkt *um = reinterpret_cast<UndMkt *>(smem);
+  double *wbase = smem + 6 * m.max_nu + (size_t)wid * lds_per_wave;
+  for (int r = 0; r < nw; ++r) {
+    const int ri = s_inst[r];
+    bool first = ri >= 0;
+    for (int q = 0; q < r; ++q) first = first && s_inst[q] != ri;
+    if (!first) continue;   // the same for the whole workgroup
+    const DevInst rin = m.inst[ri];
+    for (int u = threadIdx.x; u < rin.nu; u += blockDim.x) um[u] = und_mkt(m, rin.u0 + u);
+    __syncthreads();
+    if (valid && inst == ri) {
+      const DevInst in = m.inst[inst];
+      double p[PC > 0 ? PC : 1];
 #pragma unroll
-  for (int k = 0; k < PC; ++k) p[k] = params[(size_t)pt * PC + k];
-  const double xl = (PC == 0 && lane_id() < P) ? params[(size_t)pt * P + lane_id()] : 0.0;
-  WaveLds w = wave_lds(m, base + 6 * m.max_nu);
-  const double c = point_cost<MODEL, FORMULA, RESID>(
-      m, in, um, p, xl, w, resid ? resid + (size_t)pt * stride : nullptr,
-      model ? model + (size_t)pt * stride : nullptr);
-  if (lane_id() == 0) cost[pt] = c;
+      for (int k = 0; k < PC; ++k) p[k] = params[(size_t)pt * PC + k];
+      const double xl = (PC == 0 && lane_id() < P) ? params[(size_t)pt * P + lane_id()] : 0.0;
+      WaveLds w = wave_lds(m, wbase);
+      const double c = point_cost<MODEL, FORMULA, RESID>(
+          m, in, um, p, xl, w, resid ? resid + (size_t)pt * stride : nullptr,
+          model ? model + (size_t)pt * stride : nullptr);
+      if (lane_id() == 0) cost[pt] = c;
+    }
+    __syncthreads();   // the next round overwrites the market values
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -539,13 +557,15 @@ int sa_waves_per_group(const DevMarket &m, int want) {
 hipError_t launch_cost(const DevMarket &m, int n_pts, const int *pt_inst, const double *params,
                        double *cost, double *resid, double *model, int stride, hipStream_t s) {
   if (n_pts == 0) return hipSuccess;
-  // cost waves keep their own copy of the per-underlying market values
-  const int ld = wave_lds_doubles(m) + 6 * m.max_nu;
-  if ((long)ld * 8 > lds_budget_bytes()) return hipErrorInvalidValue;
-  int waves = 4;
-  while (waves > 1 && (long)ld * 8 * waves > lds_budget_bytes()) --waves;
+  // one shared copy of the per-underlying market values, a wave-private
+  // region per wave
+  const int ld = wave_lds_doubles(m);
+  auto bytes = [&](int w) { return (long)(6 * m.max_nu + (long)w * ld) * 8; };
+  if (bytes(1) > lds_budget_bytes()) return hipErrorInvalidValue;
+  int waves = kCostWaves;
+  while (waves > 1 && bytes(waves) > lds_budget_bytes()) --waves;
   const dim3 grid((n_pts + waves - 1) / waves), block(kWave * waves);
-  const size_t lds = (size_t)ld * 8 * waves;
+  const size_t lds = (size_t)bytes(waves);
 #define CALL(A, B, C)                                                                      \
   hipLaunchKernelGGL((cost_kernel<A, B, C>), grid, block, lds, s, m, n_pts, pt_inst, params, \
                      cost, resid, model, stride, ld)
