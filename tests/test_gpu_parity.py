@@ -112,6 +112,24 @@ def test_cost_parity_ragged_batch(api, oracle):
     _cmp_model(plan, oracle, mk, pts[::7], inst[::7], "ragged batch")
 
 
+def test_cost_parity_interleaved_instances(api, oracle):
+    """Workgroups whose points alternate between instances (one round of
+    the shared market values per distinct instance) and hold an invalid
+    one, with a ragged last workgroup."""
+    m, truth, noise = I.batch_markets(n_markets=3, M_range=(5, 20), nK_range=(3, 9))
+    mk = complete_with_oracle(oracle, m, truth, noise)
+    plan = api.Plan(mk)
+    inst = np.array([0, 1, 2, 1, 0, 2, 2, 0, 1, 0, 2, 1, 0], np.int32)
+    pts = np.vstack([_points(0, truth[i], 1, 50 + k)[1] for k, i in enumerate(inst)])
+    bad = inst.copy()
+    bad[5] = 7
+    c_gpu = plan.cost(torch.tensor(pts, device="cuda"),
+                      pt_inst=torch.tensor(bad, device="cuda")).cpu().numpy()
+    keep = np.arange(len(inst)) != 5
+    _cmp_cost(c_gpu[keep], oracle.cost_batch(mk, pts[keep], inst[keep]), "interleaved")
+    assert np.isnan(c_gpu[5])
+
+
 def test_cost_single_quote_and_bad_instance(api, oracle):
     m, truth, noise = I.caplet_market(M=1, nK=1)
     mk = complete_with_oracle(oracle, m, truth, noise)
