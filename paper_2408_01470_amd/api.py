@@ -314,7 +314,9 @@ class McProblem:
 
 
 class McPlan(McProblem):
-    """A Monte Carlo pricing problem uploaded to device memory."""
+    """A Monte Carlo pricing problem uploaded to device memory.  Its calls
+    share one workspace: issue them on one stream (or synchronise between
+    streams), as concurrent calls would overwrite each other's sums."""
 
     def __init__(self, prob: dict, device: str = "cuda", stream=None):
         _require_gpu()
