@@ -302,7 +302,8 @@ sabr_status sabr_nm_polish(const sabr_plan *plan, int32_t n_pts, const int32_t *
  * interval is cut into ceil(length / dt) (at least one) equal steps; a step
  * moves F_k by Euler (floored at 0) and V_k by log-Euler, driven by
  * x = sqrt(h) B xi where B is the plan's correlation factor (below) and xi
- * the step's 2 n_fwd standard normals: pairs 2b and 2b + 1 of step s on
+ * the step's first 2n standard normals, n = the alive forwards (the factor's
+ * alive rows vanish beyond column 2n): pairs 2b and 2b + 1 of step s on
  * path p are the Box-Muller transforms of the Philox4x32-10 block at
  * counter (b, s, p mod 2^32, p / 2^32) and key (seed mod 2^32, seed / 2^32),
  * words (w0, w1) for pair 2b and (w2, w3) for pair 2b + 1, each giving
@@ -314,12 +315,13 @@ sabr_status sabr_nm_polish(const sabr_plan *plan, int32_t n_pts, const int32_t *
  *
  * Correlation factor: the 2 n_fwd x 2 n_fwd matrix of (W_0.., Z_0..) need
  * not be positive semi-definite (the paper's calibrated Hagan parameters
- * give an indefinite one); B is its spectral repair (Rebonato and Jaeckel
- * 1999: eigenvalues clipped at 0, B = Q sqrt(Lambda+), rows rescaled to unit
- * length; columns by decreasing eigenvalue, each eigenvector signed so that
- * its first entry of largest magnitude is positive), computed on the host
- * when the plan is created.  B B^T is the matrix itself when it is positive
- * semi-definite.
+ * give an indefinite one); it is repaired spectrally (Rebonato and Jaeckel
+ * 1999: eigenvalues clipped at 0, unit diagonal restored) and B is the
+ * Cholesky factor of the repaired matrix with the components ordered
+ * W_{n-1}, Z_{n-1}, ..., W_0, Z_0 (a pivot at or below 1e-9 leaves its
+ * column zero), rows returned in the order W_0.., Z_0..; computed on the
+ * host when the plan is created.  B B^T is the matrix itself when it is
+ * positive semi-definite.
  * ------------------------------------------------------------------------ */
 typedef struct {
   int32_t n_fwd;             /* 1..16 */

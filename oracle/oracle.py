@@ -353,23 +353,43 @@ def mc_corr_matrix(T, phi, y):
     return np.block([[rho, ph], [ph.T, theta]])
 
 
-def mc_factor(T, phi, y):
-    """Correlation factor B with x = B xi (xi iid standard normal): the
-    spectral repair of Rebonato and Jaeckel (1999) of the matrix above --
-    eigenvalues clipped at zero, B = Q sqrt(Lambda+), rows rescaled to unit
-    length (B B^T = the matrix itself when it is positive semi-definite).
-    Columns in decreasing eigenvalue order, each eigenvector signed so that
-    its entry of largest magnitude is positive."""
+def mc_repaired_corr(T, phi, y):
+    """The spectral repair of Rebonato and Jaeckel (1999) of the matrix above:
+    eigenvalues clipped at zero, then rescaled to unit diagonal (the matrix
+    itself when it is positive semi-definite)."""
     C = mc_corr_matrix(T, phi, y)
     lam, Q = np.linalg.eigh(C)
-    order = np.argsort(-lam, kind="stable")
-    lam, Q = lam[order], Q[:, order]
-    for c in range(Q.shape[1]):
-        if Q[np.argmax(np.abs(Q[:, c])), c] < 0.0:
-            Q[:, c] = -Q[:, c]
-    B = Q * np.sqrt(np.maximum(lam, 0.0))[None, :]
-    nrm = np.sqrt((B * B).sum(axis=1))
-    return B / np.where(nrm > 0.0, nrm, 1.0)[:, None]
+    R = (Q * np.maximum(lam, 0.0)[None, :]) @ Q.T
+    d = np.sqrt(np.diag(R))
+    d = np.where(d > 0.0, d, 1.0)
+    return R / d[:, None] / d[None, :]
+
+
+def mc_factor(T, phi, y):
+    """Correlation factor B with x = B xi (xi iid standard normal), rows W_0..
+    W_{M-1}, Z_0..Z_{M-1}: the Cholesky factor of the repaired matrix with its
+    components ordered W_{M-1}, Z_{M-1}, W_{M-2}, ..., W_0, Z_0 (a pivot at or
+    below 1e-9 leaves its column zero: the semi-definite case, whose zero
+    pivots come out as rounding noise of order 1e-12), rows put back
+    in the natural order.  In that ordering the forwards alive during
+    [T_{j-1}, T_j) (k >= j) are the leading 2(M - j) components, so they use
+    the first 2(M - j) normals only."""
+    R = mc_repaired_corr(T, phi, y)
+    M = len(T)
+    rows = [t * M + k for k in range(M - 1, -1, -1) for t in (0, 1)]
+    A = R[np.ix_(rows, rows)]
+    n = 2 * M
+    L = np.zeros((n, n))
+    for c in range(n):
+        dd = A[c, c] - float(np.dot(L[c, :c], L[c, :c]))
+        if dd <= 1e-9:
+            continue
+        L[c, c] = np.sqrt(dd)
+        for r in range(c + 1, n):
+            L[r, c] = (A[r, c] - float(np.dot(L[r, :c], L[c, :c]))) / L[c, c]
+    B = np.zeros((n, n))
+    B[rows, :] = L
+    return B
 
 
 def mc_paths(prob, n_paths, dt, seed, path0=0, B=None):

@@ -978,8 +978,9 @@ void nm_one(const Inst &I, int P, double *p, const double *lb, const double *ub,
 //                     + sigma_k x_{M+k}),
 //    with phi_{i,k} = E[dW_i dZ_k] (the covariance of Z_k with the
 //    numeraire's drivers) and x = sqrt(h) B xi, B (2M x 2M, rows W_0..W_{M-1},
-//    Z_0..Z_{M-1}) the correlation factor given by the caller, xi the step's
-//    2M standard normals.
+//    Z_0..Z_{M-1}) the correlation factor given by the caller, whose alive
+//    rows vanish beyond column 2(M - j), xi the step's first 2(M - j)
+//    standard normals (M - j pairs).
 //  - Normals: pairs 2b and 2b + 1 of step s on path p are Box-Muller of the
 //    Philox4x32-10 block (counter (b, s, p mod 2^32, p / 2^32), key (seed mod
 //    2^32, seed / 2^32)): words (w0, w1) for pair 2b, (w2, w3) for pair
@@ -1127,10 +1128,13 @@ int32_t oracle_mc_paths(int32_t M, const double *T, const double *tau, const dou
       const int n = mc_steps(len, dt);
       const double h = len / n, sh = std::sqrt(h);
       for (int st = 0; st < n; ++st, ++step) {
-        mc_normals(seed, path, step, M, xi.data());
+        // the alive forwards' increments take the step's first 2(M - j)
+        // normals (the factor's columns beyond are zero on their rows)
+        const int na = 2 * (M - j);
+        mc_normals(seed, path, step, M - j, xi.data());
         for (int r = 0; r < n2; ++r) {
           double acc = 0.0;
-          for (int c = 0; c < n2; ++c) acc += B[(size_t)r * n2 + c] * xi[c];
+          for (int c = 0; c < na; ++c) acc += B[(size_t)r * n2 + c] * xi[c];
           x[r] = sh * acc;
         }
         for (int k = j; k < M; ++k) {

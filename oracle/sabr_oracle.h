@@ -157,7 +157,8 @@ int32_t oracle_mc_steps(double len, double dt);
  * measure: X[p][o] = discounted payoff of option o (payer swaption
  * (opt_a, opt_b, opt_K); opt_b = opt_a + 1: caplet) on path path0 + p.
  * Forward arrays [M]; y = (eta1, lambda1, eta2, lambda2, lambda3); B [2M][2M]
- * the correlation factor (rows W_0..W_{M-1}, Z_0..Z_{M-1}); P0 = P(0, T_0). */
+ * the correlation factor (rows W_0..W_{M-1}, Z_0..Z_{M-1}; the rows of
+ * forwards k >= j vanish beyond column 2(M - j)); P0 = P(0, T_0). */
 int32_t oracle_mc_paths(int32_t M, const double *T, const double *tau, const double *F0,
                         const double *alpha, const double *beta, const double *phi,
                         const double *sigma, const double *y, double P0, const double *B,

@@ -195,7 +195,9 @@ __global__ __launch_bounds__(kWave *kMcWavesPerBlock, (MF <= 13 ? 4 : 3)) void m
       double x[2 * MMAX];
 #pragma unroll
       for (int r = 0; r < 2 * MMAX; ++r) x[r] = 0.0;
+      const int na = M - j;   // alive forwards: pairs 0..na-1, rows 0..2na-1
       // normal pair m from words (wa, wb): its two factor columns into x
+      // (lower triangular: rows 2m..2na-1)
       auto pair = [&](int m, unsigned wa, unsigned wb) {
         const double u1 = ((double)wa + 1.0) * 0x1.0p-32;
         const double u2 = (double)wb * 0x1.0p-32;
@@ -206,22 +208,23 @@ __global__ __launch_bounds__(kWave *kMcWavesPerBlock, (MF <= 13 ? 4 : 3)) void m
         const double *c0 = (LPP > 1 ? Bs : Bc) + (size_t)(2 * m) * n2, *c1 = c0 + n2;
 #pragma unroll
         for (int r = 0; r < 2 * MMAX; ++r)
-          if (r >= 2 * j && r < n2) x[r] = fma(c1[r], z1, fma(c0[r], z0, x[r]));
+          if (r >= 2 * m && r < 2 * na) x[r] = fma(c1[r], z1, fma(c0[r], z0, x[r]));
       };
-      constexpr int NB = (M + 1) / 2;   // Philox blocks a step: two pairs each
+      constexpr int NB = (M + 1) / 2;   // Philox blocks a step at most: two pairs each
+      const int nb = (na + 1) / 2;
       for (int i = 0; i < (NB + LPP - 1) / LPP; ++i) {
         const int b = i * LPP + g;
-        if (LPP == 1 || b < NB) {
+        if (b < nb) {
           unsigned w[4];
           philox4x32_10((unsigned)b, step, p_lo, p_hi, a.seed_lo, a.seed_hi, w);
           pair(2 * b, w[0], w[1]);
-          if (2 * b + 1 < M) pair(2 * b + 1, w[2], w[3]);
+          if (2 * b + 1 < na) pair(2 * b + 1, w[2], w[3]);
         }
       }
       if constexpr (LPP > 1) {
 #pragma unroll
         for (int r = 0; r < 2 * MMAX; ++r)
-          if (r >= 2 * j) x[r] = group_sum<LPP>(x[r]);
+          if (r < 2 * na) x[r] = group_sum<LPP>(x[r]);
       }
       double Ds = 0.0, E = 0.0, G = 0.0;
 #pragma unroll
@@ -243,9 +246,10 @@ __global__ __launch_bounds__(kWave *kMcWavesPerBlock, (MF <= 13 ? 4 : 3)) void m
           E = fma(fw[MC_G1 * M + k], E, d);
           G = fma(fw[MC_G3 * M + k], G, fw[MC_PHS * M + k] * d);
           const double sg = fw[MC_SIGMA * M + k];
-          F[k] = fmax(f + s * (eta1 * Ds + (1.0 - eta1) * E) * h + s * (sh * x[2 * k]), 0.0);
+          const int pk = 2 * (M - 1 - k);   // this forward's rows
+          F[k] = fmax(f + s * (eta1 * Ds + (1.0 - eta1) * E) * h + s * (sh * x[pk]), 0.0);
           V[k] = v * exp_cw((sg * fw[MC_PHA * M + k] * G - 0.5 * sg * sg) * h +
-                            sg * (sh * x[2 * k + 1]));
+                            sg * (sh * x[pk + 1]));
         }
       }
     }
@@ -337,12 +341,13 @@ __global__ __launch_bounds__(kMcReduceThreads) void mc_cost_kernel(const double 
 // Host: the correlation factor.  The 2M x 2M matrix of eqs. (rhoij),
 // (thetaij), (phiij) (rows W_0..W_{M-1}, Z_0..Z_{M-1}; entry (k, M + l) =
 // phi_{k,l} = E[dW_k dZ_l]) need not be positive semi-definite (the paper's
-// calibrated Hagan parameters give an indefinite one); the factor is its
-// spectral repair (Rebonato and Jaeckel, 1999): eigenvalues clipped at zero,
-// B = Q sqrt(Lambda+), rows rescaled to unit length.  Columns in decreasing
-// eigenvalue order, each eigenvector signed so that its entry of largest
-// magnitude (the first such) is positive.  Eigen-decomposition by cyclic
-// Jacobi rotations (Rutishauser's formulation).
+// calibrated Hagan parameters give an indefinite one); it is repaired
+// spectrally (Rebonato and Jaeckel, 1999: eigenvalues clipped at zero, unit
+// diagonal restored), and the factor is the Cholesky factor of the repaired
+// matrix with the components ordered W_{M-1}, Z_{M-1}, ..., W_0, Z_0, so
+// that the forwards alive after a fixing are a leading block drawing on the
+// first normals only.  Eigen-decomposition by cyclic Jacobi rotations
+// (Rutishauser's formulation).
 // ---------------------------------------------------------------------------
 void corr_matrix(int M, const double *T, const double *phi, const double y[5], double *C) {
   const int n = 2 * M;
@@ -404,25 +409,46 @@ void corr_factor(int M, const double *T, const double *phi, const double y[5], d
   std::vector<double> C((size_t)n * n), lam, Q;
   corr_matrix(M, T, phi, y, C.data());
   jacobi_eigen(n, C, lam, Q);
-  std::vector<int> ord(n);
-  for (int i = 0; i < n; ++i) ord[i] = i;
-  std::stable_sort(ord.begin(), ord.end(), [&](int x, int z) { return lam[x] > lam[z]; });
-  for (int c = 0; c < n; ++c) {
-    const int e = ord[c];
-    int arg = 0;
-    for (int r = 1; r < n; ++r)
-      if (std::fabs(Q[(size_t)r * n + e]) > std::fabs(Q[(size_t)arg * n + e])) arg = r;
-    const double sg = Q[(size_t)arg * n + e] < 0.0 ? -1.0 : 1.0;
-    const double sq = std::sqrt(std::max(lam[e], 0.0));
-    for (int r = 0; r < n; ++r) B[(size_t)r * n + c] = sg * Q[(size_t)r * n + e] * sq;
-  }
+  // the repaired matrix Q max(Lambda, 0) Q^T at unit diagonal
+  std::vector<double> R((size_t)n * n, 0.0);
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) {
+      double acc = 0.0;
+      for (int e = 0; e < n; ++e)
+        acc += Q[(size_t)r * n + e] * std::max(lam[e], 0.0) * Q[(size_t)c * n + e];
+      R[(size_t)r * n + c] = acc;
+    }
+  std::vector<double> d(n);
   for (int r = 0; r < n; ++r) {
-    double s = 0.0;
-    for (int c = 0; c < n; ++c) s += B[(size_t)r * n + c] * B[(size_t)r * n + c];
-    const double nr = std::sqrt(s);
-    if (nr > 0.0)
-      for (int c = 0; c < n; ++c) B[(size_t)r * n + c] /= nr;
+    const double v = std::sqrt(R[(size_t)r * n + r]);
+    d[r] = v > 0.0 ? v : 1.0;
   }
+  // Cholesky in the order W_{M-1}, Z_{M-1}, ..., W_0, Z_0 (semi-definite: a
+  // pivot at or below 1e-9 leaves its column zero; the zero pivots of a
+  // clipped spectrum come out as rounding noise of order 1e-12)
+  std::vector<int> rows(n);
+  for (int k = M - 1, p = 0; k >= 0; --k) {
+    rows[p++] = k;
+    rows[p++] = M + k;
+  }
+  std::vector<double> L((size_t)n * n, 0.0);
+  auto A = [&](int p, int q) {
+    return R[(size_t)rows[p] * n + rows[q]] / (d[rows[p]] * d[rows[q]]);
+  };
+  for (int c = 0; c < n; ++c) {
+    double dd = A(c, c);
+    for (int i = 0; i < c; ++i) dd -= L[(size_t)c * n + i] * L[(size_t)c * n + i];
+    if (dd <= 1e-9) continue;
+    const double lc = std::sqrt(dd);
+    L[(size_t)c * n + c] = lc;
+    for (int r = c + 1; r < n; ++r) {
+      double v = A(r, c);
+      for (int i = 0; i < c; ++i) v -= L[(size_t)r * n + i] * L[(size_t)c * n + i];
+      L[(size_t)r * n + c] = v / lc;
+    }
+  }
+  for (int p = 0; p < n; ++p)
+    for (int c = 0; c < n; ++c) B[(size_t)rows[p] * n + c] = L[(size_t)p * n + c];
 }
 
 }  // namespace
@@ -535,11 +561,13 @@ sabr_status sabr_mc_plan_create(const sabr_mc_problem *pr, sabr_mc_plan **out) {
   }
   P->B.assign((size_t)n2 * n2, 0.0);
   corr_factor(M, pr->T, pr->phi, y, P->B.data());
-  // device layout: column-major, rows interleaved (W_k at 2k, Z_k at 2k + 1)
+  // device layout: column-major, rows by decreasing forward (W_k at
+  // 2(M - 1 - k), Z_k at 2(M - 1 - k) + 1): the alive rows lead
   for (int c = 0; c < n2; ++c)
     for (int k = 0; k < M; ++k) {
-      P->img_d[P->off_B + (size_t)c * n2 + 2 * k] = P->B[(size_t)k * n2 + c];
-      P->img_d[P->off_B + (size_t)c * n2 + 2 * k + 1] = P->B[(size_t)(M + k) * n2 + c];
+      const int pos = 2 * (M - 1 - k);
+      P->img_d[P->off_B + (size_t)c * n2 + pos] = P->B[(size_t)k * n2 + c];
+      P->img_d[P->off_B + (size_t)c * n2 + pos + 1] = P->B[(size_t)(M + k) * n2 + c];
     }
   // options grouped by expiry (stable), outputs back to the caller's order
   std::vector<int> ord(n_opt);

@@ -212,11 +212,13 @@ def mc_power_flops(beta: float) -> float:
 
 
 def mc_step_flops(M: int, betas_alive) -> float:
-    """One path step with the forwards of betas_alive alive (of M): M normal
-    pairs, each adding its two factor columns into the alive rows (two fma
-    per row), and each alive forward's power, drift and updates."""
-    return M * MC_BOX_MULLER + sum(4 * 2 * M + mc_power_flops(b) + MC_PER_FORWARD_REST
-                                   for b in betas_alive)
+    """One path step with the n forwards of betas_alive alive (of M): n
+    normal pairs, pair m adding its two factor columns into the alive rows
+    2m..2n-1 (lower triangular: two fma per row, 4 n (n + 1) FLOP in all),
+    and each alive forward's power, drift and updates."""
+    n = len(betas_alive)
+    return (n * MC_BOX_MULLER + 4 * n * (n + 1)
+            + sum(mc_power_flops(b) + MC_PER_FORWARD_REST for b in betas_alive))
 
 
 def mc_steps(T, dt, amax):

@@ -20,16 +20,22 @@ def api():
     return A
 
 
-@pytest.mark.parametrize("which", ["paper", "synthetic", "max", "one"])
+@pytest.mark.parametrize("which", ["paper", "synthetic", "max", "one", "seven-clipped"])
 def test_factor_matches_oracle(api, oracle, which):
+    """The plan's factor (its own Jacobi eigen-solver, repair and semi-definite
+    Cholesky) against the oracle's (numpy's eigh); with seven clipped
+    eigenvalues the zero pivots are rounding noise and the rest agrees to
+    1e-10."""
     p = {"paper": lambda: I.paper_mc_problem(),
          "synthetic": lambda: I.mc_problem(),
          "max": lambda: I.mc_problem(seed=I.SEED_BASE + 9600, M=16, n_swaptions=4),
-         "one": lambda: I.mc_problem(seed=I.SEED_BASE + 9601, M=1, n_swaptions=0)}[which]()
+         "one": lambda: I.mc_problem(seed=I.SEED_BASE + 9601, M=1, n_swaptions=0),
+         "seven-clipped": lambda: I.mc_problem(seed=I.SEED_BASE + 9826, M=16, n_cap_K=2,
+                                               n_swaptions=5)}[which]()
     B = api.McProblem(p).factor()
     Bo = oracle.mc_factor(p["T"], p["phi"], p["y"])
-    np.testing.assert_allclose(B, Bo, rtol=0, atol=1e-12)
-    np.testing.assert_allclose((B * B).sum(axis=1), 1.0, atol=1e-14)
+    np.testing.assert_allclose(B, Bo, rtol=0, atol=1e-10 if which == "seven-clipped" else 1e-12)
+    np.testing.assert_allclose((B * B).sum(axis=1), 1.0, atol=1e-11)
 
 
 @pytest.mark.parametrize("mutate,msg", [

@@ -80,6 +80,17 @@ def test_factor_reproduces_a_valid_correlation(oracle):
     assert C[2, 8 + 5] == pytest.approx(-0.4 * math.exp(-0.2 * 1.5))
 
 
+def test_factor_alive_rows_are_leading(oracle):
+    """The forwards alive during [T_{j-1}, T_j) (k >= j) draw on the first
+    2(M - j) normals only: their rows of the factor vanish beyond."""
+    for p in (I.paper_mc_problem(), I.mc_problem()):
+        M = len(p["T"])
+        B = oracle.mc_factor(p["T"], p["phi"], p["y"])
+        for j in range(M):
+            for k in range(j, M):
+                assert not np.any(B[k, 2 * (M - j):]) and not np.any(B[M + k, 2 * (M - j):])
+
+
 def test_factor_repairs_the_paper_correlation(oracle):
     """The paper's calibrated phi_ii (mixed signs) and y give an indefinite
     matrix; the repaired B B^T is a correlation matrix (unit diagonal,
