@@ -318,7 +318,7 @@ sabr_status sabr_nm_polish(const sabr_plan *plan, int32_t n_pts, const int32_t *
  * give an indefinite one); it is repaired spectrally (Rebonato and Jaeckel
  * 1999: eigenvalues clipped at 0, unit diagonal restored) and B is the
  * Cholesky factor of the repaired matrix with the components ordered
- * W_{n-1}, Z_{n-1}, ..., W_0, Z_0 (a pivot at or below 1e-9 leaves its
+ * W_{n_fwd-1}, Z_{n_fwd-1}, ..., W_0, Z_0 (a pivot at or below 1e-9 leaves its
  * column zero), rows returned in the order W_0.., Z_0..; computed on the
  * host when the plan is created.  B B^T is the matrix itself when it is
  * positive semi-definite.
