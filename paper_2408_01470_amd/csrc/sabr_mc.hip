@@ -11,23 +11,27 @@
 //   F_k <- max(F_k + s_k h sum_{i=j..k} rho_{k,i} d_i + s_k x_k, 0)      (Euler)
 //   V_k <- V_k exp((sigma_k sum_{i=j..k} phi_{i,k} d_i - sigma_k^2/2) h
 //                  + sigma_k x_{M+k})                                   (log-Euler)
-// with x = sqrt(h) B xi, B the correlation factor of the plan and xi the
-// step's 2M normals (Box-Muller of Philox4x32-10 blocks, two pairs a block
-// from 32-bit uniforms, counter (block, step, path), key seed).  Both sums are O(M) recursions over the gaps:
+// with x = sqrt(h) B xi, B the correlation factor of the plan (lower
+// triangular with the alive forwards leading) and xi the step's first 2n
+// normals, n = M - j alive forwards (Box-Muller of Philox4x32-10 blocks, two
+// pairs a block from 32-bit uniforms, counter (block, step, path), key
+// seed).  Both sums are O(M) recursions over the gaps:
 // rho_{k,i} = eta1 + (1 - eta1) prod_{l=i+1..k} g1_l and phi_{i,k} =
 // sgn(phi_i) sqrt|phi_i| sqrt|phi_k| prod_{l=i+1..k} g3_l, g = exp(-lambda
 // (T_l - T_{l-1})).  At each fixing T_j the payoffs of the options expiring
 // there are taken (payer swaption on forwards a..b-1, b = a + 1 the caplet)
 // and the deflator is divided by 1 + tau_j F_j(T_j).
 //
-// Layout: one path per lane, 4 waves per block; the forwards, their
-// volatilities and the step's increments in registers (at most 16
-// forwards); the factor (column-major, rows W_k and Z_k interleaved) and the
-// per-forward constants are wave-uniform and read through the scalar cache.
-// Logarithms, exponentials and the sine and cosine of the Box-Muller angle
-// are the library's branch-free polynomial versions.  Each wave reduces its 64 paths' payoffs and squares per
-// option (register lane moves) into a slot of the workspace; a second kernel
-// sums the slots in a fixed order, so prices do not depend on scheduling.
+// Layout: one path per lane (2, 4 or 8 lanes per path when there are few
+// paths), 4 waves per block; the forwards, their volatilities and the step's
+// increments in registers (at most 16 forwards); the factor (column-major,
+// rows by decreasing forward, W_k and Z_k interleaved) and the per-forward
+// constants are wave-uniform and read through the scalar cache.  Logarithms,
+// exponentials and the sine and cosine of the Box-Muller angle are the
+// library's branch-free polynomial versions.  Each wave reduces its paths'
+// payoffs and squares per option (register lane moves) into a slot of the
+// workspace; a second kernel sums the slots in a fixed order, so prices do
+// not depend on scheduling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
