@@ -312,3 +312,17 @@ def test_caplet_matches_its_forward_measure_sabr(oracle):
     ref, rse = _sabr_forward_measure(F, alpha, 0.5, -0.5, 0.8, float(M), K, 100000, 0.02, 42)
     ref, rse = P[M] * ref, P[M] * rse            # tau = 1: the caplet is P(0, pay) E[(F - K)^+]
     assert np.all(np.abs(m - ref) <= 4.5 * np.hypot(se, rse)), np.c_[m, ref, se, rse]
+
+
+def test_paths_do_not_depend_on_threads(oracle):
+    """Each path's numbers come from its own counters: one host thread and
+    all of them give the same paths bit for bit."""
+    p = I.mc_problem(seed=I.SEED_BASE + 9450, M=7, n_cap_K=2, n_swaptions=4)
+    n = oracle.max_threads()
+    try:
+        oracle.set_threads(1)
+        X1 = oracle.mc_paths(p, 300, 0.05, 13)
+    finally:
+        oracle.set_threads(n)
+    Xn = oracle.mc_paths(p, 300, 0.05, 13)
+    assert np.array_equal(X1, Xn)
