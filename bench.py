@@ -515,7 +515,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
-              "multi-GPU sharding of chains and markets is described in DESIGN.md",
+              "sharding of chains, markets and paths across GPUs is designed, not built",
               file=sys.stderr)
         sys.exit(2)
     import torch
