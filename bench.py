@@ -514,7 +514,7 @@ def paper_mc(api, I, flops, cpu=True):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the "
               "sharding of chains, markets and paths across GPUs is designed, not built",
               file=sys.stderr)
         sys.exit(2)
