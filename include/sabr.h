@@ -324,7 +324,7 @@ sabr_status sabr_nm_polish(const sabr_plan *plan, int32_t n_pts, const int32_t *
  * positive semi-definite.
  * ------------------------------------------------------------------------ */
 typedef struct {
-  int32_t n_fwd;             /* 1..16 */
+  int32_t n_fwd;             /* 1..24 */
   const double *T;           /* [n_fwd] fixing times, 0 < T[0] < T[1] < ... */
   const double *tau;         /* [n_fwd] accrual fractions > 0 */
   const double *F0;          /* [n_fwd] initial forwards > 0 */

@@ -24,7 +24,7 @@
 //
 // Layout: one path per lane (2, 4 or 8 lanes per path when there are few
 // paths), 4 waves per block; the forwards, their volatilities and the step's
-// increments in registers (at most 16 forwards); the factor (column-major,
+// increments in registers (at most 24 forwards); the factor (column-major,
 // rows by decreasing forward, W_k and Z_k interleaved) and the per-forward
 // constants are wave-uniform and read through the scalar cache.  Logarithms,
 // exponentials and the sine and cosine of the Box-Muller angle are the
@@ -47,7 +47,7 @@
 namespace sabr {
 namespace {
 
-constexpr int kMcMaxFwd = 16;
+constexpr int kMcMaxFwd = 24;
 constexpr int kMcWavesPerBlock = 4;
 constexpr int kMcReduceThreads = 256;
 
@@ -162,9 +162,11 @@ __device__ __forceinline__ double group_sum(double v) {
 // the factor, stored column-major with rows W_k, Z_k interleaved), then the
 // forwards move in increasing k with the drift recursions.
 // Register budget: 4 waves per SIMD up to 13 forwards (measured faster on the
-// paper's 13-forward market despite a few spilled registers), 3 beyond.
+// paper's 13-forward market despite a few spilled registers), 3 up to 16, 2
+// beyond.
 template <int MF, int LPP>
-__global__ __launch_bounds__(kWave *kMcWavesPerBlock, (MF <= 13 ? 4 : 3)) void mc_kernel(McArgs a) {
+__global__ __launch_bounds__(kWave *kMcWavesPerBlock, (MF <= 13 ? 4 : (MF <= 16 ? 3 : 2)))
+void mc_kernel(McArgs a) {
   constexpr int MMAX = MF;
   constexpr int M = MF, n2 = 2 * MF;
   __shared__ double Bs[LPP > 1 ? n2 * n2 : 1];
@@ -696,7 +698,8 @@ sabr_status sabr_mc_price(const sabr_mc_plan *plan, int64_t n_paths, double dt, 
     SABR_MC_CASE(1) SABR_MC_CASE(2) SABR_MC_CASE(3) SABR_MC_CASE(4) SABR_MC_CASE(5)
     SABR_MC_CASE(6) SABR_MC_CASE(7) SABR_MC_CASE(8) SABR_MC_CASE(9) SABR_MC_CASE(10)
     SABR_MC_CASE(11) SABR_MC_CASE(12) SABR_MC_CASE(13) SABR_MC_CASE(14) SABR_MC_CASE(15)
-    SABR_MC_CASE(16)
+    SABR_MC_CASE(16) SABR_MC_CASE(17) SABR_MC_CASE(18) SABR_MC_CASE(19) SABR_MC_CASE(20)
+    SABR_MC_CASE(21) SABR_MC_CASE(22) SABR_MC_CASE(23) SABR_MC_CASE(24)
 #undef SABR_MC_CASE
 #undef SABR_MC_LAUNCH
     default: return mc_fail(SABR_EINVAL, "mc: bad forward count");

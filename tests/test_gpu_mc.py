@@ -50,8 +50,8 @@ def test_mc_parity_path_counts(api, oracle, n_paths):
         assert np.all(se == 0.0)
 
 
-@pytest.mark.parametrize("M,beta", [(1, None), (5, "random"), (16, None)],
-                         ids=["one-forward", "random-beta", "most-forwards"])
+@pytest.mark.parametrize("M,beta", [(1, None), (5, "random"), (16, None), (24, None)],
+                         ids=["one-forward", "random-beta", "sixteen-forwards", "most-forwards"])
 def test_mc_parity_shapes(api, oracle, M, beta):
     p = I.mc_problem(seed=I.SEED_BASE + 9810 + M, M=M, n_cap_K=2, n_swaptions=0 if M == 1 else 5,
                      beta=beta)

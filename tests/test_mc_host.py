@@ -63,8 +63,8 @@ def test_plan_rejects_bad_problem(api, mutate, msg):
 
 def test_plan_limits(api):
     with pytest.raises(Exception) as e:
-        api.McProblem(I.mc_problem(seed=I.SEED_BASE + 9701, M=17, n_swaptions=0))
-    assert "n_fwd must be 1..16" in str(e.value)
+        api.McProblem(I.mc_problem(seed=I.SEED_BASE + 9701, M=25, n_swaptions=0))
+    assert "n_fwd must be 1..24" in str(e.value)
     p = I.mc_problem(seed=I.SEED_BASE + 9702, M=3, n_swaptions=0)
     for k in ("opt_a", "opt_b", "opt_K"):
         p[k] = p[k][:0]
