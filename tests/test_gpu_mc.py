@@ -149,3 +149,15 @@ def test_mc_cost(api, oracle):
     torch.cuda.synchronize()
     c, _ = plan.cost(400, 0.02, 9, tgt)
     assert float(out.cpu()[0]) == float(c.cpu()[0])
+
+
+def test_mc_full_size_paper_swaptions(api):
+    """The paper's fourteen swaptions x five strikes at its printed
+    parameters, at the replay's full size (1e6 paths, dt = 1e-3): every cell
+    within 5% of the printed Monte Carlo prices (the fixed leg's conventions
+    are not printed; the oracle's pin has the same bound)."""
+    p, printed = I.paper_mc_swaption_problem()
+    m, se = [t.cpu().numpy() for t in api.McPlan(p).price(1_000_000, 1e-3, 2408)]
+    rel = 100.0 * m / printed[:, 1] - 1.0
+    assert np.max(np.abs(rel)) < 0.05 and np.mean(np.abs(rel)) < 0.03, rel
+    assert np.all(100.0 * se < 0.01 * printed[:, 1])
