@@ -49,7 +49,8 @@ class OracleSAConfig(ctypes.Structure):
     _fields_ = [
         ("T0", ctypes.c_double), ("cool", ctypes.c_double), ("step_frac", ctypes.c_double),
         ("n_levels", ctypes.c_int32), ("n_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
-        ("T0_per_inst", _f64p),
+        ("T0_per_inst", _f64p), ("level0", ctypes.c_int32), ("inst_key", _i32p),
+        ("state_in", _f64p), ("state_out", _f64p),
     ]
 
 
@@ -209,8 +210,19 @@ def cost_grad(m, params, pt_inst=None, normal=False):
     return (cost, grad, A, g) if normal else (cost, grad)
 
 
+def sa_state_doubles(chains, P):
+    """Doubles of the annealing state of instances with these chain counts:
+    per instance X [C][P], F [C], BX [C][P], BF [C], T."""
+    return int(sum(2 * int(c) * (P + 1) + 1 for c in np.atleast_1d(chains)))
+
+
 def sa_calibrate(m, chains, lb, ub, T0, cool, n_levels, n_steps, seed, step_frac=0.05,
-                 x0=None, T0_per_inst=None, record=False):
+                 x0=None, T0_per_inst=None, record=False, level0=0, inst_key=None,
+                 state_in=None, keep_state=False):
+    """Synchronous parallel SA (Sec. 3).  level0 > 0 starts at that level of
+    the schedule (Philox counters and temperature); state_in resumes from the
+    state a previous call returned with keep_state (then no initial
+    evaluation); inst_key overrides the Philox key word 1 of each instance."""
     M = _mk(m)
     P = M.P
     ch = np.ascontiguousarray(np.broadcast_to(np.asarray(chains, np.int32), (M.n_inst,)),
@@ -220,7 +232,14 @@ def sa_calibrate(m, chains, lb, ub, T0, cool, n_levels, n_steps, seed, step_frac
     x0a = None if x0 is None else np.ascontiguousarray(np.broadcast_to(x0, (M.n_inst, P)),
                                                        dtype=np.float64)
     t0i = None if T0_per_inst is None else np.ascontiguousarray(T0_per_inst, dtype=np.float64)
-    cfg = OracleSAConfig(T0, cool, step_frac, n_levels, n_steps, seed, _p(t0i, _f64p))
+    key = None if inst_key is None else np.ascontiguousarray(inst_key, dtype=np.int32)
+    nst = sa_state_doubles(ch, P)
+    sin = None if state_in is None else np.ascontiguousarray(state_in, dtype=np.float64)
+    if sin is not None and sin.size != nst:
+        raise ValueError(f"state_in holds {sin.size} doubles, need {nst}")
+    sout = np.zeros(nst) if keep_state else None
+    cfg = OracleSAConfig(T0, cool, step_frac, n_levels, n_steps, seed, _p(t0i, _f64p),
+                         level0, _p(key, _i32p), _p(sin, _f64p), _p(sout, _f64p))
     best_x = np.zeros((M.n_inst, P))
     best_f = np.zeros(M.n_inst)
     tot = int(ch.sum())
@@ -234,8 +253,52 @@ def sa_calibrate(m, chains, lb, ub, T0, cool, n_levels, n_steps, seed, step_frac
         ctypes.byref(M.s), ctypes.byref(cfg), _p(ch, _i32p), _p(lb, _f64p), _p(ub, _f64p),
         _p(x0a, _f64p), _p(best_x, _f64p), _p(best_f, _f64p), _p(cbx, _f64p), _p(cbf, _f64p),
         _p(acc, _u8p), _p(trace, _f64p), _p(lbest, _i32p), _p(nev, _i64p)))
-    return dict(best_x=best_x, best_f=best_f, chain_best_x=cbx, chain_best_f=cbf, accept=acc,
-                trace=trace, level_best=lbest, n_evals=nev)
+    out = dict(best_x=best_x, best_f=best_f, chain_best_x=cbx, chain_best_f=cbf, accept=acc,
+               trace=trace, level_best=lbest, n_evals=nev)
+    if keep_state:
+        out["state"] = sout
+    return out
+
+
+def sa_state_split(state, chains, P):
+    """Per instance (X [C][P], F [C], BX [C][P], BF [C], T) of a state vector."""
+    out, o = [], 0
+    for C in np.atleast_1d(chains):
+        C = int(C)
+        X = state[o:o + C * P].reshape(C, P)
+        o += C * P
+        F = state[o:o + C]
+        o += C
+        BX = state[o:o + C * P].reshape(C, P)
+        o += C * P
+        BF = state[o:o + C]
+        o += C
+        out.append((X, F, BX, BF, float(state[o])))
+        o += 1
+    return out
+
+
+def sa_chain_steps(m, inst, chain, level, T, lb, ub, x, f, n_steps, seed, step_frac=0.05,
+                   inst_key=None):
+    """One chain's steps of one level, step by step, from point x (cost f):
+    proposals, their costs, the acceptance uniforms and the accept flags."""
+    M = _mk(m)
+    P = M.P
+    lb = np.ascontiguousarray(np.broadcast_to(lb, (M.n_inst, P)), dtype=np.float64)
+    ub = np.ascontiguousarray(np.broadcast_to(ub, (M.n_inst, P)), dtype=np.float64)
+    key = None if inst_key is None else np.ascontiguousarray(inst_key, dtype=np.int32)
+    cfg = OracleSAConfig(1.0, 1.0, step_frac, 1, n_steps, seed, None, 0, _p(key, _i32p),
+                         None, None)
+    xa = np.ascontiguousarray(x, dtype=np.float64)
+    xp = np.zeros((n_steps, P))
+    fp = np.zeros(n_steps)
+    u = np.zeros(n_steps)
+    acc = np.zeros(n_steps, np.uint8)
+    _check(lib().oracle_sa_chain_steps(
+        ctypes.byref(M.s), ctypes.byref(cfg), int(inst), int(chain), int(level),
+        ctypes.c_double(T), _p(lb, _f64p), _p(ub, _f64p), _p(xa, _f64p), ctypes.c_double(f),
+        _p(xp, _f64p), _p(fp, _f64p), _p(u, _f64p), _p(acc, _u8p)))
+    return dict(xp=xp, fp=fp, u=u, accept=acc)
 
 
 def sa_level0_sample(m, chains, lb, ub, T0, n_steps, seed, sample_inst, sample_chain,

@@ -1300,20 +1300,28 @@ int32_t oracle_cost_grad(const oracle_market *m, int32_t n_pts, const int32_t *p
 // One chain's N Metropolis steps of level l at temperature T: proposal from
 // the level's uniforms, cost, acceptance test, best-ever update.  x, F, bx,
 // BF are the chain's state (updated); accept flags go to acc[s * stride].
+// key: Philox key word 1 of the instance.  Per-step detail (nullable):
+// proposal xp_out[s][P], its cost fp_out[s], acceptance uniform u_out[s].
 // Returns the number of accepted proposals.
-static int chain_level(const Inst &I, const oracle_sa_config &cfg, int i, int l, int c, double T,
-                       int P, const double *lo, const double *hi, double *x, double &F,
-                       double *bx, double &BF, uint8_t *acc, int64_t stride) {
+static int chain_level(const Inst &I, const oracle_sa_config &cfg, int key, int l, int c,
+                       double T, int P, const double *lo, const double *hi, double *x, double &F,
+                       double *bx, double &BF, uint8_t *acc, int64_t stride,
+                       double *xp_out = nullptr, double *fp_out = nullptr,
+                       double *u_out = nullptr) {
   const int N = cfg.n_steps;
   std::vector<double> u(P + 1), xp(P);
   int na = 0;
   for (int s = 0; s < N; ++s) {
-    sa_uniforms(cfg.seed, i, l, N, s, c, P, u.data());
+    sa_uniforms(cfg.seed, key, l, N, s, c, P, u.data());
     propose(P, x, u.data(), lo, hi, cfg.step_frac, xp.data());
     double fp = cost_d(I, xp.data());
     if (std::isnan(fp)) fp = kInf;
     const double dE = fp - F;
     const bool a = (dE <= 0.0) || (u[P] < std::exp(-dE / T));
+    if (xp_out)
+      for (int k = 0; k < P; ++k) xp_out[(size_t)s * P + k] = xp[k];
+    if (fp_out) fp_out[s] = fp;
+    if (u_out) u_out[s] = u[P];
     if (a) {
       for (int k = 0; k < P; ++k) x[k] = xp[k];
       F = fp;
@@ -1328,6 +1336,10 @@ static int chain_level(const Inst &I, const oracle_sa_config &cfg, int i, int l,
   return na;
 }
 
+// Doubles of one instance's annealing state with C chains of P parameters:
+// X [C][P], F [C], BX [C][P], BF [C], T.
+static size_t state_doubles(int C, int P) { return 2 * (size_t)C * (P + 1) + 1; }
+
 int32_t oracle_sa_calibrate(const oracle_market *m, const oracle_sa_config *cfg,
                             const int32_t *chains, const double *lb, const double *ub,
                             const double *x0, double *best_x, double *best_f,
@@ -1339,7 +1351,9 @@ int32_t oracle_sa_calibrate(const oracle_market *m, const oracle_sa_config *cfg,
   if (cfg->n_levels < 0 || cfg->n_steps < 0) return fail("negative level or step count");
   if (!(cfg->cool > 0.0 && cfg->cool <= 1.0) || !(cfg->T0 > 0.0)) return fail("bad schedule");
   const int L = cfg->n_levels, N = cfg->n_steps;
+  if (cfg->level0 < 0) return fail("negative first level");
   int64_t chain_base = 0, acc_base = 0;
+  size_t state_off = 0;
   for (int i = 0; i < m->n_inst; ++i) {
     Inst I;
     if (build_inst(m, i, I)) return -1;
@@ -1348,24 +1362,39 @@ int32_t oracle_sa_calibrate(const oracle_market *m, const oracle_sa_config *cfg,
     const double *lo = lb + (size_t)i * P, *hi = ub + (size_t)i * P;
     for (int k = 0; k < P; ++k)
       if (!(lo[k] <= hi[k])) return fail("lb > ub");
-    // 1. every chain starts at x0 (default: box midpoint) and evaluates it
-    std::vector<double> start(P);
-    for (int k = 0; k < P; ++k) start[k] = x0 ? x0[(size_t)i * P + k] : 0.5 * (lo[k] + hi[k]);
+    const int key = cfg->inst_key ? cfg->inst_key[i] : i;
     std::vector<double> X((size_t)C * P), F(C), BX((size_t)C * P), BF(C);
-    for (int c = 0; c < C; ++c) {
-      for (int k = 0; k < P; ++k) X[(size_t)c * P + k] = start[k];
-      F[c] = cost_d(I, start.data());
-      for (int k = 0; k < P; ++k) BX[(size_t)c * P + k] = start[k];
-      BF[c] = F[c];
+    double T;
+    int64_t evals = 0;
+    if (cfg->state_in) {
+      // resume: the state a run of levels 0..level0-1 left
+      const double *st = cfg->state_in + state_off;
+      std::copy(st, st + (size_t)C * P, X.begin());
+      std::copy(st + (size_t)C * P, st + (size_t)C * (P + 1), F.begin());
+      std::copy(st + (size_t)C * (P + 1), st + (size_t)C * (2 * P + 1), BX.begin());
+      std::copy(st + (size_t)C * (2 * P + 1), st + (size_t)C * (2 * P + 2), BF.begin());
+      T = st[(size_t)C * (2 * P + 2)];
+    } else {
+      // 1. every chain starts at x0 (default: box midpoint) and evaluates it
+      std::vector<double> start(P);
+      for (int k = 0; k < P; ++k) start[k] = x0 ? x0[(size_t)i * P + k] : 0.5 * (lo[k] + hi[k]);
+      for (int c = 0; c < C; ++c) {
+        for (int k = 0; k < P; ++k) X[(size_t)c * P + k] = start[k];
+        F[c] = cost_d(I, start.data());
+        for (int k = 0; k < P; ++k) BX[(size_t)c * P + k] = start[k];
+        BF[c] = F[c];
+      }
+      evals = C;
+      T = (cfg->T0_per_inst ? cfg->T0_per_inst[i] : cfg->T0);
+      for (int l = 0; l < cfg->level0; ++l) T = cfg->cool * T;
     }
-    int64_t evals = C;
-    double T = (cfg->T0_per_inst ? cfg->T0_per_inst[i] : cfg->T0);
     std::vector<int> nacc(C);
     for (int l = 0; l < L; ++l) {
       // 2. N Metropolis steps per chain at temperature T (chains independent)
+      const int lg = cfg->level0 + l;
 #pragma omp parallel for schedule(static)
       for (int c = 0; c < C; ++c)
-        nacc[c] = chain_level(I, *cfg, i, l, c, T, P, lo, hi, &X[(size_t)c * P], F[c],
+        nacc[c] = chain_level(I, *cfg, key, lg, c, T, P, lo, hi, &X[(size_t)c * P], F[c],
                               &BX[(size_t)c * P], BF[c],
                               accept ? accept + acc_base + (int64_t)l * N * C + c : nullptr, C);
       evals += (int64_t)C * N;
@@ -1404,6 +1433,15 @@ int32_t oracle_sa_calibrate(const oracle_market *m, const oracle_sa_config *cfg,
     if (chain_best_f)
       for (int c = 0; c < C; ++c) chain_best_f[chain_base + c] = BF[c];
     if (n_evals) n_evals[i] = evals;
+    if (cfg->state_out) {
+      double *st = cfg->state_out + state_off;
+      std::copy(X.begin(), X.end(), st);
+      std::copy(F.begin(), F.end(), st + (size_t)C * P);
+      std::copy(BX.begin(), BX.end(), st + (size_t)C * (P + 1));
+      std::copy(BF.begin(), BF.end(), st + (size_t)C * (2 * P + 1));
+      st[(size_t)C * (2 * P + 2)] = T;
+    }
+    state_off += state_doubles(C, P);
     chain_base += C;
     acc_base += (int64_t)L * N * C;
   }
@@ -1448,11 +1486,35 @@ int32_t oracle_sa_level0_sample(const oracle_market *m, const oracle_sa_config *
     double *bx = BX_out + (size_t)j * P;
     for (int k = 0; k < P; ++k) bx[k] = x[k];
     const double T = cfg->T0_per_inst ? cfg->T0_per_inst[i] : cfg->T0;
-    chain_level(insts[i], *cfg, i, 0, sample_chain[j], T, P, lo, hi, x.data(), F, bx, BF,
-                accept + (size_t)j * N, 1);
+    chain_level(insts[i], *cfg, cfg->inst_key ? cfg->inst_key[i] : i, 0, sample_chain[j], T, P,
+                lo, hi, x.data(), F, bx, BF, accept + (size_t)j * N, 1);
     F_out[j] = F;
     BF_out[j] = BF;
   }
+  return 0;
+}
+
+// The N steps of one chain in one level, step by step: chain `chain` of
+// instance `inst` at level `level` (Philox counter level N + s) and
+// temperature T, from point x (cost f).  Outputs per step s: proposal
+// xp_out[s][P], its cost fp_out[s], acceptance uniform u_out[s], accept flag
+// acc_out[s].  For locating where two runs of the same annealing part.
+int32_t oracle_sa_chain_steps(const oracle_market *m, const oracle_sa_config *cfg, int32_t inst,
+                              int32_t chain, int32_t level, double T, const double *lb,
+                              const double *ub, const double *x, double f, double *xp_out,
+                              double *fp_out, double *u_out, uint8_t *acc_out) {
+  if (!m || !cfg || !x || !lb || !ub) return fail("null argument");
+  const int P = market_params(m);
+  if (P < 0) return fail("unknown model or PERFWD instances of unequal size");
+  if (inst < 0 || inst >= m->n_inst) return fail("instance out of range");
+  if (cfg->n_steps < 0 || level < 0 || chain < 0) return fail("negative step, level or chain");
+  Inst I;
+  if (build_inst(m, inst, I)) return -1;
+  std::vector<double> xc(x, x + P), bx(x, x + P);
+  double F = f, BF = f;
+  chain_level(I, *cfg, cfg->inst_key ? cfg->inst_key[inst] : inst, level, chain, T, P,
+              lb + (size_t)inst * P, ub + (size_t)inst * P, xc.data(), F, bx.data(), BF, acc_out,
+              1, xp_out, fp_out, u_out);
   return 0;
 }
 

@@ -105,7 +105,18 @@ typedef struct {
   int32_t n_steps;    /* N */
   uint64_t seed;      /* Philox key word 0; key word 1 = instance id */
   const double *T0_per_inst; /* nullable */
+  int32_t level0;            /* first level index: the Philox counter of step s of run level l
+                                is (level0 + l) N + s; without state_in, T starts at
+                                T0 cool^level0 (repeated multiplication) */
+  const int32_t *inst_key;   /* nullable [n_inst]: Philox key word 1 per instance (default: the
+                                instance index), so one instance of a batch runs alone */
+  const double *state_in;    /* nullable: resume from this state (no initial evaluation) */
+  double *state_out;         /* nullable: the state after the last level (its restart done,
+                                T cooled) */
 } oracle_sa_config;
+/* State layout (state_in, state_out): per instance, in order, with C its
+ * chains: X [C][P], F [C], BX [C][P], BF [C] (current and best-ever points
+ * and costs), T (the next level's temperature): 2 C (P + 1) + 1 doubles. */
 
 /* Synchronous parallel SA, chains[i] chains on instance i.
  * best_x [n_inst][P], best_f [n_inst]; nullable outputs:
@@ -129,6 +140,14 @@ int32_t oracle_sa_level0_sample(const oracle_market *m, const oracle_sa_config *
                                 const double *x0, int32_t n_sample, const int32_t *sample_inst,
                                 const int32_t *sample_chain, uint8_t *accept, double *F_out,
                                 double *BF_out, double *BX_out);
+
+/* One chain's N steps of one level, step by step (proposal xp_out [N][P],
+ * its cost fp_out [N], acceptance uniform u_out [N], accept flag acc_out
+ * [N]) from point x with cost f at temperature T; lb, ub [n_inst][P]. */
+int32_t oracle_sa_chain_steps(const oracle_market *m, const oracle_sa_config *cfg, int32_t inst,
+                              int32_t chain, int32_t level, double T, const double *lb,
+                              const double *ub, const double *x, double f, double *xp_out,
+                              double *fp_out, double *u_out, uint8_t *acc_out);
 
 /* Projected Levenberg-Marquardt polish of n_pts points (in place). */
 int32_t oracle_lm_polish(const oracle_market *m, int32_t n_pts, const int32_t *pt_inst,

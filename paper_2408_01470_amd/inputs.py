@@ -356,6 +356,25 @@ def random_box_points(model, n, seed, lb=None, ub=None):
     return lb + (ub - lb) * u
 
 
+def select_instances(market, idx):
+    """The sub-batch of instances idx (in that order) of a CSR market."""
+    idx = [int(i) for i in np.atleast_1d(idx)]
+    out = {k: v for k, v in market.items() if not isinstance(v, np.ndarray)}
+    spans = {"fwd": ("fwd_off", ("fwd_T", "fwd_tau", "fwd_F", "fwd_P")),
+             "und": ("und_off", ("und_first", "und_len")),
+             "q": ("q_off", ("q_und", "q_kind", "q_K", "q_w", "q_vol"))}
+    for off_key, keys in spans.values():
+        off = np.asarray(market[off_key])
+        out[off_key] = np.concatenate([[0], np.cumsum([off[i + 1] - off[i] for i in idx])]
+                                      ).astype(np.int32)
+        for k in keys:
+            if k in market:
+                a = np.asarray(market[k])
+                out[k] = np.ascontiguousarray(np.concatenate(
+                    [a[off[i]:off[i + 1]] for i in idx]) if idx else a[:0])
+    return out
+
+
 def n_quotes(market):
     return np.diff(np.asarray(market["q_off"]))
 

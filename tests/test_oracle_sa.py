@@ -175,3 +175,122 @@ def test_level0_sample_matches_full_annealing(oracle, c1_market):
         assert np.array_equal(smp["accept"][j], acc[:, c])
         assert smp["BF"][j] == full["chain_best_f"][c]
         assert np.array_equal(smp["BX"][j], full["chain_best_x"][c])
+
+
+def _small_batch(oracle):
+    from conftest import complete_with_oracle
+    m, truth, noise = I.batch_markets(n_markets=3, M_range=(3, 8), nK_range=(3, 7))
+    return complete_with_oracle(oracle, m, truth, noise)
+
+
+@pytest.mark.parametrize("split", [1, 4, 9])
+def test_checkpoint_resume_equals_one_run(oracle, split):
+    """L levels in one call equal `split` levels, then the saved state resumed
+    for L - split more (the Philox counters and temperatures continue): the
+    same accept flags, restart chains, best points and final state, bit for
+    bit, on a ragged batch."""
+    mk = _small_batch(oracle)
+    lb, ub = I.box(0)
+    chains = np.array([5, 12, 3], np.int32)
+    L, N = 10, 7
+    kw = dict(T0=0.05, cool=0.8, n_steps=N, seed=17, record=True)
+    full = oracle.sa_calibrate(mk, chains, lb, ub, n_levels=L, keep_state=True, **kw)
+    a = oracle.sa_calibrate(mk, chains, lb, ub, n_levels=split, keep_state=True, **kw)
+    b = oracle.sa_calibrate(mk, chains, lb, ub, n_levels=L - split, level0=split,
+                            state_in=a["state"], keep_state=True, **kw)
+    # accept flags: per instance [L][N][C] blocks
+    off_f = off_a = off_b = 0
+    for C in chains:
+        C = int(C)
+        fa = full["accept"][off_f:off_f + L * N * C]
+        aa = a["accept"][off_a:off_a + split * N * C]
+        bb = b["accept"][off_b:off_b + (L - split) * N * C]
+        assert np.array_equal(fa, np.concatenate([aa, bb]))
+        off_f += L * N * C
+        off_a += split * N * C
+        off_b += (L - split) * N * C
+    assert np.array_equal(full["level_best"], np.hstack([a["level_best"], b["level_best"]]))
+    assert np.array_equal(full["best_x"], b["best_x"])
+    assert np.array_equal(full["best_f"], b["best_f"])
+    assert np.array_equal(full["chain_best_f"], b["chain_best_f"])
+    assert np.array_equal(full["state"], b["state"])
+    assert np.array_equal(full["n_evals"], a["n_evals"] + b["n_evals"])
+    # the state's temperature is the schedule's, by repeated multiplication
+    T = 0.05
+    for _ in range(L):
+        T = 0.8 * T
+    for (_, F, _, BF, Ts) in oracle.sa_state_split(full["state"], chains, 4):
+        assert Ts == T
+        assert np.all(F == F[0])            # every chain restarted at one point
+        assert BF.min() <= F[0]          # the restart point was evaluated by some chain
+
+
+def test_instance_key_runs_one_instance_alone(oracle):
+    """An instance of a batch, run alone with its Philox key word and
+    temperature, repeats its part of the batch run exactly; with the default
+    key (index 0) it draws other numbers."""
+    mk = _small_batch(oracle)
+    lb, ub = I.box(0)
+    chains = np.array([5, 12, 3], np.int32)
+    T0s = np.array([0.05, 0.02, 0.08])
+    L, N = 4, 9
+    kw = dict(T0=1.0, cool=0.8, n_levels=L, n_steps=N, seed=5, record=True)
+    full = oracle.sa_calibrate(mk, chains, lb, ub, T0_per_inst=T0s, **kw)
+    one = oracle.sa_calibrate(I.select_instances(mk, [1]), [12], lb, ub, T0_per_inst=T0s[1:2],
+                              inst_key=[1], **kw)
+    o = L * N * 5
+    assert np.array_equal(full["accept"][o:o + L * N * 12], one["accept"])
+    assert np.array_equal(full["level_best"][1], one["level_best"][0])
+    assert np.array_equal(full["best_x"][1], one["best_x"][0])
+    other = oracle.sa_calibrate(I.select_instances(mk, [1]), [12], lb, ub,
+                                T0_per_inst=T0s[1:2], **kw)
+    assert not np.array_equal(other["accept"], one["accept"])
+
+
+def test_chain_steps_replay_a_level(oracle, c1_market):
+    """The step-by-step replay of one chain's level reproduces the accept
+    flags of the full annealing, and each flag is the Metropolis rule applied
+    to the reported costs and uniform (accept iff dE <= 0 or u < exp(-dE/T))."""
+    mk, _ = c1_market
+    lb, ub = I.box(0)
+    C, N, T0, cool = 6, 15, 0.05, 0.8
+    kw = dict(T0=T0, cool=cool, n_steps=N, seed=29, record=True)
+    full = oracle.sa_calibrate(mk, C, lb, ub, n_levels=3, **kw)
+    st = oracle.sa_calibrate(mk, C, lb, ub, n_levels=2, keep_state=True, **kw)["state"]
+    X, F, _, _, T = oracle.sa_state_split(st, [C], 4)[0]
+    acc = full["accept"].reshape(3, N, C)
+    for c in range(C):
+        r = oracle.sa_chain_steps(mk, 0, c, 2, T, lb, ub, X[c], F[c], N, 29)
+        assert np.array_equal(r["accept"], acc[2, :, c])
+        f = F[c]
+        for s in range(N):
+            dE = r["fp"][s] - f
+            assert bool(r["accept"][s]) == bool(dE <= 0 or r["u"][s] < math.exp(-dE / T))
+            if r["accept"][s]:
+                f = r["fp"][s]
+
+
+def test_divergence_report_names_the_planted_step(oracle):
+    """The divergence report finds a flag planted into one run's record and
+    replays that chain to it: dE, T and -T ln u come from the replay, and with
+    identical costs on both sides a flipped flag is a real divergence."""
+    from sa_divergence import describe, first_mismatch
+    mk = _small_batch(oracle)
+    lb, ub = I.box(0)
+    chains = np.array([5, 12, 3], np.int32)
+    T0s = np.array([0.05, 0.02, 0.08])
+    L, N, cool, seed = 4, 9, 0.8, 5
+    r = oracle.sa_calibrate(mk, chains, lb, ub, T0=1.0, cool=cool, n_levels=L, n_steps=N,
+                            seed=seed, T0_per_inst=T0s, record=True)
+    acc = r["accept"].copy()
+    where = (1, 2, 4, 7)
+    acc[L * N * 5 + (2 * N + 4) * 12 + 7] ^= 1
+    assert first_mismatch(acc, r["accept"], L, N, chains) == where
+
+    def ora_cost(pts, inst):
+        return oracle.cost_batch(mk, pts, np.full(len(pts), inst, np.int32))
+    msg = describe(ora_cost, 4, 3, oracle, mk, chains, lb, ub, T0s, cool, N, seed, 0.05, where)
+    assert "instance 1, level 2, step 4, chain 7" in msg
+    assert msg.endswith("real divergence")
+    T = 0.02 * cool * cool
+    assert f"T {T:.17g}" in msg
