@@ -235,6 +235,31 @@ sabr_status sa_calibrate(const sabr_plan *plan, const sa_config *cfg /*[host]*/,
                          double *chain_best_f, uint8_t *accept, double *level_trace,
                          int32_t *level_best, void *workspace, size_t ws_bytes, void *stream);
 
+/* Bytes of the fixed device scratch of sa_calibrate_noalloc (64 MiB). */
+#define SA_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+
+/* sa_calibrate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, results and errors as sa_calibrate, without the
+ * workspace.  The scratch is a fixed array of SA_NOALLOC_MAX_BYTES bytes in
+ * the library's device code, one per device, held until the process ends;
+ * its address for the current device is looked up on the first call there.
+ * A call whose sa_workspace_size exceeds SA_NOALLOC_MAX_BYTES fails with
+ * SABR_EWORKSPACE; use_graph must be 0 (SABR_EINVAL otherwise).  The call
+ * allocates no device memory (the small host tables go through the plan's
+ * own staging buffer, as in sa_calibrate).  Every call on one device shares
+ * that device's array and leaves its contents there: calls that overlap on
+ * one device (concurrent streams or threads) race and must be serialised by
+ * the caller.  Nothing in the array needs to start at zero: every word is
+ * written by the call before it is read. */
+sabr_status sa_calibrate_noalloc(const sabr_plan *plan, const sa_config *cfg /*[host]*/,
+                                 const int32_t *chains /*[host]*/, const double *lb /*[host]*/,
+                                 const double *ub /*[host]*/,
+                                 const double *x0 /*[host] nullable*/, double *best_x,
+                                 double *best_f, double *chain_best_x, double *chain_best_f,
+                                 uint8_t *accept, double *level_trace, int32_t *level_best,
+                                 void *stream);
+
 /* Device workspace bytes sabr_cost_vjp and sabr_lm_polish need for n_pts
  * points (per-wave scratch of the LMM12 map Jacobian, box tables). */
 size_t sabr_adjoint_workspace_size(const sabr_plan *plan, int32_t n_pts);

@@ -47,6 +47,8 @@ class SAConfig(ctypes.Structure):
     ]
 
 
+SA_NOALLOC_MAX_BYTES = 64 << 20   # include/sabr.h
+
 _lib = None
 
 
@@ -81,6 +83,8 @@ def lib():
     L.sa_workspace_size.restype = ctypes.c_size_t
     L.sa_calibrate.argtypes = [_vp, ctypes.POINTER(SAConfig), _i32p, _f64p, _f64p, _f64p,
                                _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.sa_calibrate_noalloc.argtypes = [_vp, ctypes.POINTER(SAConfig), _i32p, _f64p, _f64p,
+                                       _f64p, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     L.sabr_adjoint_workspace_size.argtypes = [_vp, ctypes.c_int32]
     L.sabr_adjoint_workspace_size.restype = ctypes.c_size_t
     L.sabr_cost_vjp.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,

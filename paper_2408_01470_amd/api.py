@@ -154,10 +154,12 @@ class Plan:
     def sa(self, chains, lb, ub, T0, cool, n_levels, n_steps, seed, step_frac=0.05, x0=None,
            T0_per_inst=None, record=False, trace=True, chain_best=False, waves=0,
            use_graph=False, stream=None, workspace=None, out=None, level_events=None,
-           occupancy=0):
+           occupancy=0, noalloc=False):
         """Synchronous parallel simulated annealing on every instance.  ``out``
         (a dict returned by an earlier call with the same shapes) reuses its
-        output tensors, so a captured graph can be replayed."""
+        output tensors, so a captured graph can be replayed.  noalloc: run
+        through sa_calibrate_noalloc (the library's fixed device scratch, no
+        workspace; the returned "workspace" is None)."""
         L = lib()
         n, P = self.n_inst, self.P
         cfg = self.sa_config(T0, cool, n_levels, n_steps, seed, step_frac, T0_per_inst, waves,
@@ -167,16 +169,27 @@ class Plan:
         ub = np.ascontiguousarray(np.broadcast_to(ub, (n, P)), dtype=np.float64)
         x0a = None if x0 is None else np.ascontiguousarray(np.broadcast_to(x0, (n, P)),
                                                            dtype=np.float64)
+        tot = int(ch.sum())
+        out = dict(out) if out is not None else self._sa_outputs(tot, n_levels, n_steps,
+                                                                  record, trace, chain_best)
+        o = out
+        args = (lb.ctypes.data_as(_f64p), ub.ctypes.data_as(_f64p),
+                x0a.ctypes.data_as(_f64p) if x0a is not None else None,
+                _ptr(o["best_x"]), _ptr(o["best_f"]), _ptr(o["chain_best_x"]),
+                _ptr(o["chain_best_f"]), _ptr(o["accept"]), _ptr(o["trace"]),
+                _ptr(o["level_best"]))
+        if noalloc:
+            check(L.sa_calibrate_noalloc(self._h, ctypes.byref(cfg), ch.ctypes.data_as(_i32p),
+                                         *args, _stream(stream)))
+            out["workspace"] = None
+            out["n_evals"] = ch.astype(np.int64) * (1 + int(n_steps) * int(n_levels))
+            return out
         ws = int(L.sa_workspace_size(self._h, ctypes.byref(cfg), ch.ctypes.data_as(_i32p)))
         if ws == 0:
             check(-1 if L.sabr_last_error() else 0)
             raise _lib.SabrError("sa_workspace_size: " + L.sabr_last_error().decode())
         if workspace is None or workspace.numel() < ws:
             workspace = torch.empty(ws, dtype=torch.uint8, device=self.device)
-        tot = int(ch.sum())
-        out = dict(out) if out is not None else self._sa_outputs(tot, n_levels, n_steps,
-                                                                  record, trace, chain_best)
-        o = out
         check(L.sa_calibrate(self._h, ctypes.byref(cfg), ch.ctypes.data_as(_i32p),
                              lb.ctypes.data_as(_f64p), ub.ctypes.data_as(_f64p),
                              x0a.ctypes.data_as(_f64p) if x0a is not None else None,

@@ -508,29 +508,40 @@ size_t sa_workspace_size(const sabr_plan *P, const sa_config *cfg, const int32_t
   return sa_layout(P, cfg, chains).total;
 }
 
-sabr_status sa_calibrate(const sabr_plan *Pc, const sa_config *cfg, const int32_t *chains,
-                         const double *lb, const double *ub, const double *x0, double *best_x,
-                         double *best_f, double *chain_best_x, double *chain_best_f,
-                         uint8_t *accept, double *level_trace, int32_t *level_best,
-                         void *workspace, size_t ws_bytes, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// Validation of the arguments sa_calibrate and sa_calibrate_noalloc share
+// (everything but the workspace).
+sabr_status check_sa_call(const sabr_plan *Pc, const sa_config *cfg, const int32_t *chains,
+                          const double *lb, const double *ub, const double *x0,
+                          const double *best_x, const double *best_f) {
   sabr_status st = check_sa_args(Pc, cfg, chains);
   if (st != SABR_OK) return st;
-  sabr_plan *P = const_cast<sabr_plan *>(Pc);
-  if (!P->dev) return fail(SABR_EINVAL, "plan not uploaded");
+  if (!Pc->dev) return fail(SABR_EINVAL, "plan not uploaded");
   if (!lb || !ub) return fail(SABR_EINVAL, "null box");
   if (!best_x || !best_f) return fail(SABR_EINVAL, "null best_x or best_f");
-  if (!workspace) return fail(SABR_EINVAL, "null workspace");
-  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(SABR_EINVAL, "workspace not 256-byte aligned");
-  const int n = P->n_inst;
-  const int Pn = P->np;
+  const int n = Pc->n_inst;
+  const int Pn = Pc->np;
   for (int i = 0; i < n * Pn; ++i) {
     if (!std::isfinite(lb[i]) || !std::isfinite(ub[i]) || !(lb[i] <= ub[i]))
       return fail(SABR_EINVAL, "box bound " + std::to_string(i) + ": need finite lb <= ub");
     if (x0 && !(x0[i] >= lb[i] && x0[i] <= ub[i]))
       return fail(SABR_EINVAL, "x0 outside the box");
   }
-  const SALayout S = sa_layout(P, cfg, chains);
-  if (ws_bytes < S.total) return fail(SABR_EWORKSPACE, "workspace too small");
+  return SABR_OK;
+}
+
+// The annealing run of sa_calibrate on a validated call with a workspace of
+// at least sa_layout(...).total bytes.
+sabr_status sa_run(sabr_plan *P, const sa_config *cfg, const int32_t *chains, const double *lb,
+                   const double *ub, const double *x0, double *best_x, double *best_f,
+                   double *chain_best_x, double *chain_best_f, uint8_t *accept,
+                   double *level_trace, int32_t *level_best, const SALayout &S, void *workspace,
+                   void *stream) {
+  const int n = P->n_inst;
+  const int Pn = P->np;
   const int L = cfg->n_levels, N = cfg->n_steps;
   // host-side tables
   std::lock_guard<std::mutex> guard(P->mu);
@@ -683,6 +694,50 @@ sabr_status sa_calibrate(const sabr_plan *Pc, const sa_config *cfg, const int32_
   e = hipGraphLaunch(P->graph_exec, s);
   if (e != hipSuccess) return hip_fail(e, "graph launch");
   return SABR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sabr_status sa_calibrate(const sabr_plan *Pc, const sa_config *cfg, const int32_t *chains,
+                         const double *lb, const double *ub, const double *x0, double *best_x,
+                         double *best_f, double *chain_best_x, double *chain_best_f,
+                         uint8_t *accept, double *level_trace, int32_t *level_best,
+                         void *workspace, size_t ws_bytes, void *stream) {
+  sabr_status st = check_sa_call(Pc, cfg, chains, lb, ub, x0, best_x, best_f);
+  if (st != SABR_OK) return st;
+  if (!workspace) return fail(SABR_EINVAL, "null workspace");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(SABR_EINVAL, "workspace not 256-byte aligned");
+  sabr_plan *P = const_cast<sabr_plan *>(Pc);
+  const SALayout S = sa_layout(P, cfg, chains);
+  if (ws_bytes < S.total) return fail(SABR_EWORKSPACE, "workspace too small");
+  return sa_run(P, cfg, chains, lb, ub, x0, best_x, best_f, chain_best_x, chain_best_f, accept,
+                level_trace, level_best, S, workspace, stream);
+}
+
+sabr_status sa_calibrate_noalloc(const sabr_plan *Pc, const sa_config *cfg,
+                                 const int32_t *chains, const double *lb, const double *ub,
+                                 const double *x0, double *best_x, double *best_f,
+                                 double *chain_best_x, double *chain_best_f, uint8_t *accept,
+                                 double *level_trace, int32_t *level_best, void *stream) {
+  sabr_status st = check_sa_call(Pc, cfg, chains, lb, ub, x0, best_x, best_f);
+  if (st != SABR_OK) return st;
+  if (cfg->use_graph)
+    return fail(SABR_EINVAL, "sa_calibrate_noalloc: use_graph must be 0 (instantiating a graph "
+                             "allocates; capture the eager launches instead)");
+  sabr_plan *P = const_cast<sabr_plan *>(Pc);
+  const SALayout S = sa_layout(P, cfg, chains);
+  if (S.total > SA_NOALLOC_MAX_BYTES)
+    return fail(SABR_EWORKSPACE, "sa_calibrate_noalloc: this call needs " +
+                                     std::to_string(S.total) + " bytes of scratch, more than "
+                                     "the fixed " + std::to_string(SA_NOALLOC_MAX_BYTES) +
+                                     " (use sa_calibrate with a workspace)");
+  void *scratch_ptr = nullptr;
+  hipError_t e = sabr::sa_noalloc_scratch(&scratch_ptr);
+  if (e != hipSuccess) return hip_fail(e, "sa_calibrate_noalloc: scratch lookup");
+  return sa_run(P, cfg, chains, lb, ub, x0, best_x, best_f, chain_best_x, chain_best_f, accept,
+                level_trace, level_best, S, scratch_ptr, stream);
 }
 
 }  // extern "C"

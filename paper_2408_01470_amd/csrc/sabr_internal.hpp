@@ -110,6 +110,12 @@ hipError_t launch_sa_level(const DevMarket &m, const SAArgs &a, int level, int n
 hipError_t launch_sa_level_end(const SAArgs &a, int level, int max_tiles, hipStream_t s);
 hipError_t launch_sa_final(const SAArgs &a, hipStream_t s);
 
+// Bytes of the fixed per-device scratch array of the allocation-free
+// annealing entry point, and the current device's address of it (looked up
+// on the first call on each device).
+constexpr size_t kSaNoallocBytes = (size_t)64 << 20;
+hipError_t sa_noalloc_scratch(void **ptr);
+
 // Wavefronts per SA/cost workgroup that fit the LDS budget (at most `want`).
 int sa_waves_per_group(const DevMarket &m, int want);
 

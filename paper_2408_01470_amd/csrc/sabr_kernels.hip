@@ -10,6 +10,8 @@
 // kernel here (no dense contraction: no MFMA).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "sabr_cost.hpp"
 
 namespace sabr {
@@ -617,6 +619,35 @@ hipError_t launch_sa_level_end(const SAArgs &a, int level, int max_tiles, hipStr
 hipError_t launch_sa_final(const SAArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(sa_final_kernel, dim3(a.n_inst), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free annealing entry point
+// (sa_calibrate_noalloc): one copy of this array per device, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, never the
+// device memory: host code uses only the address hipGetSymbolAddress returns
+// for the current device, looked up once per device and kept.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kSaNoallocBytes];
+
+hipError_t sa_noalloc_scratch(void **ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void *per_dev[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> guard(mu);
+  if (per_dev[dev] == nullptr) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr || reinterpret_cast<uintptr_t>(p) % 256) return hipErrorInvalidSymbol;
+    per_dev[dev] = p;
+  }
+  *ptr = per_dev[dev];
+  return hipSuccess;
 }
 
 }  // namespace sabr

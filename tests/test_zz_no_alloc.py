@@ -1,0 +1,73 @@
+"""sa_calibrate_noalloc (the allocation-free annealing entry point) against
+sa_calibrate: the same results bit for bit on two calls in a row, the second
+smaller than the first, so stale scratch contents of the first call must not
+leak into the second; plus its refusals (too much scratch, graph replay)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2408_01470_amd import _lib, api
+from paper_2408_01470_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(plan, chains, lb, ub, noalloc, **kw):
+    r = plan.sa(chains, lb, ub, record=True, chain_best=True, noalloc=noalloc, **kw)
+    torch.cuda.synchronize()
+    keys = ("best_x", "best_f", "chain_best_x", "chain_best_f", "accept", "level_best", "trace")
+    return {k: r[k].cpu().numpy() for k in keys}
+
+
+def _same(a, b):
+    for k in a:
+        x, y = a[k], b[k]
+        if k == "trace":          # column 2 is the device clock
+            x, y = x[..., :2], y[..., :2]
+        assert np.array_equal(x, y), f"{k} differs"
+
+
+def test_noalloc_matches_sa_calibrate_on_two_calls(c2_market, c1_market):
+    print("noalloc: LMM12 c2 market, 512 chains x 6 levels x 10 steps, then caplets "
+          "64 chains x 3 levels x 20 steps", flush=True)
+    mk2, _ = c2_market
+    plan2 = api.Plan(mk2)
+    lb2, ub2 = I.box(1)
+    kw2 = dict(T0=0.05, cool=0.7, n_levels=6, n_steps=10, seed=11, waves=8)
+    ref2 = _run(plan2, 512, lb2, ub2, False, **kw2)
+    got2 = _run(plan2, 512, lb2, ub2, True, **kw2)
+    _same(ref2, got2)
+    mk1, _ = c1_market
+    plan1 = api.Plan(mk1)
+    lb1, ub1 = I.box(0)
+    kw1 = dict(T0=0.02, cool=0.8, n_levels=3, n_steps=20, seed=12)
+    got1 = _run(plan1, 64, lb1, ub1, True, **kw1)
+    ref1 = _run(plan1, 64, lb1, ub1, False, **kw1)
+    _same(ref1, got1)
+    # and a batch of instances (ragged chain counts) through the same array
+    mb, tb, nb = I.batch_markets(n_markets=5, seed=I.SEED_BASE + 77)
+    from conftest import complete_with_oracle
+    from oracle import oracle as O
+    mkb = complete_with_oracle(O, mb, tb, nb)
+    planb = api.Plan(mkb)
+    ch = np.array([7, 64, 1, 33, 20], np.int32)
+    kwb = dict(T0=0.02, cool=0.8, n_levels=2, n_steps=15, seed=13, waves=4)
+    _same(_run(planb, ch, lb1, ub1, False, **kwb), _run(planb, ch, lb1, ub1, True, **kwb))
+
+
+def test_noalloc_refusals(c1_market):
+    mk1, _ = c1_market
+    plan = api.Plan(mk1)
+    lb, ub = I.box(0)
+    kw = dict(T0=0.02, cool=0.8, n_levels=1, n_steps=1, seed=1)
+    cfg = plan.sa_config(**kw)
+    big = 1 << 20
+    assert plan.sa_workspace_bytes(cfg, big) > _lib.SA_NOALLOC_MAX_BYTES
+    with pytest.raises(_lib.SabrError, match="scratch"):
+        plan.sa(big, lb, ub, noalloc=True, trace=False, **kw)
+    with pytest.raises(_lib.SabrError, match="use_graph"):
+        plan.sa(64, lb, ub, noalloc=True, use_graph=True, **kw)
+    # a refused call leaves the entry point usable
+    r = plan.sa(64, lb, ub, noalloc=True, **kw)
+    torch.cuda.synchronize()
+    assert np.isfinite(r["best_f"].item())
