@@ -33,11 +33,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c5", choices=["c1", "c2", "c3", "c5"],
+                    help="the headline workload (default: the largest, c5)")
+    ap.add_argument("--graph", action="store_true",
+                    help="time the headline as hipGraph replays")
+    ap.add_argument("--no-extra-configs", action="store_true",
+                    help="skip c1, c2 and c3 beside the headline")
     ap.add_argument("--levels", type=int, default=None, help="override the level count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-levels", type=int, default=6,
-                    help="levels of the oracle's bounded sample")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-time-to-rmse", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -80,43 +83,63 @@ def oracle_vols(O, vol_market, truth):
     return np.concatenate(out)
 
 
-def cpu_baseline(w, n_levels):
-    """The oracle, as it stands, on the first n_levels levels of the same
-    calibration (its own copy of the market and schedule)."""
+# The oracle's bounded sample per headline workload: (instances from the
+# first, levels, chains per instance or None for all) -- about 1e9 quote
+# evaluations, 10-20 s on 16 host threads.
+CPU_SAMPLE = {"c1": (1, None, None), "c2": (1, 6, None), "c3": (8, 1, None), "c5": (1, 1, None)}
+
+
+def cpu_baseline(config, levels=None):
+    """The oracle, as it stands, on a bounded sample of the same calibration
+    (its own copy of the market and schedule): the first levels of the first
+    instances, every chain, OpenMP over chains; and on one host thread the
+    first level of 64 chains of the first instance."""
     from oracle import oracle as O
     from paper_2408_01470_amd import inputs as I
     from paper_2408_01470_amd import workloads as W
 
+    w = W.CONFIGS[config]()
+    if levels is not None:
+        w.n_levels = levels
     mk = W.synthesize(w, lambda vm, t: oracle_vols(O, vm, t))
-    M = O.Market(mk)
     lb, ub = I.box(w.model)
     pts = W.schedule_points(w.model, w.seed)
     nq = I.n_quotes(mk)
     T0s, cool = [], None
     for i in range(w.n_inst):
-        c = O.cost_batch(M, pts, np.full(len(pts), i, np.int32))
+        c = O.cost_batch(mk, pts, np.full(len(pts), i, np.int32))
         T0, cool = W.schedule(c, nq[i], w.n_levels)
         T0s.append(T0)
+    n_i, n_lv, n_ch = CPU_SAMPLE[config]
+    n_lv = w.n_levels if n_lv is None else min(n_lv, w.n_levels)
+    C = w.chains if n_ch is None else n_ch
+    idx = list(range(n_i))
+    sub = I.select_instances(mk, idx)
     threads = int(O.max_threads())
+    kw = dict(cool=cool, n_steps=w.n_steps, seed=w.seed, step_frac=w.step_frac, inst_key=idx)
     t = time.perf_counter()
-    O.sa_calibrate(M, w.chains, lb, ub, T0=T0s[0], cool=cool, n_levels=n_levels,
-                   n_steps=w.n_steps, seed=w.seed, T0_per_inst=np.array(T0s))
+    O.sa_calibrate(sub, C, lb, ub, T0=T0s[0], T0_per_inst=np.array(T0s[:n_i]),
+                   n_levels=n_lv, **kw)
     dt = time.perf_counter() - t
-    qe = w.quote_evals(n_levels=n_levels)
-    # one core: the first level of 512 of the chains
-    c1 = min(512, w.chains)
+    qe = int(np.sum(np.int64(C) * (1 + np.int64(w.n_steps) * n_lv) * nq[:n_i]))
+    # one core: the first level of 64 chains of the first instance
+    one = I.select_instances(mk, [0])
+    c1 = min(64, w.chains)
     O.set_threads(1)
     t = time.perf_counter()
-    O.sa_calibrate(M, c1, lb, ub, T0=T0s[0], cool=cool, n_levels=1, n_steps=w.n_steps,
-                   seed=w.seed, T0_per_inst=np.array(T0s))
+    O.sa_calibrate(one, c1, lb, ub, T0=T0s[0], n_levels=1, cool=cool, n_steps=w.n_steps,
+                   seed=w.seed, step_frac=w.step_frac, inst_key=[0])
     dt1 = time.perf_counter() - t
     O.set_threads(threads)
-    qe1 = w.n_inst * c1 * (1 + w.n_steps) * int(I.n_quotes(mk).max())
+    qe1 = c1 * (1 + w.n_steps) * int(nq[0])
     return dict(value=qe / dt, unit="quote-evals/s", cores=threads, kind="oracle",
-                sample=f"first {n_levels} of {w.n_levels} levels of the same calibration "
-                       f"({qe:.3e} quote-evals, {dt:.1f} s, OpenMP over chains)",
-                single_core={"value": qe1 / dt1, "sample": f"first level, {c1} chains "
-                                                          f"({qe1:.3e} quote-evals, {dt1:.1f} s)"},
+                sample=f"{w.name.split(':')[0]}: the first {n_lv} of {w.n_levels} levels of the "
+                       f"first {n_i} of {w.n_inst} instances, {C} chains each, the headline's "
+                       f"market and schedule ({qe:.3e} quote-evals, {dt:.1f} s, OpenMP over "
+                       "chains)",
+                single_core={"value": qe1 / dt1, "sample": f"first level, {c1} chains of the "
+                                                          f"first instance ({qe1:.3e} "
+                                                          f"quote-evals, {dt1:.1f} s)"},
                 host_cpu=host_cpu())
 
 
@@ -207,11 +230,18 @@ def measured_traffic(config, shape):
 
 def time_to_rmse(api, W, I, autotune):
     """Config c4: SA (512 chains, 50 levels x 100 steps) then LM polish of the
-    64 best chain points, against plain SA (same chains) run for up to 4 x 200
-    levels.  R* = (1 + 1e-3) x the RMSE of the polished optimum; the hybrid's
-    time is its wall time to the end of the polish, plain SA's time the device
-    timestamp of the first level whose best-ever RMSE <= R* (a lower bound
-    when never reached)."""
+    64 best chain points (the hybrid), against plain SA (same chains) run for
+    up to 4 x 200 levels.  Times are device times (HIP events; plain SA's
+    from its level trace: the first level whose best-ever RMSE reaches the
+    target).
+
+    * the ratio at the plain run's own final RMSE R_plain: t_plain = when the
+      plain run first reaches R_plain, t_hybrid = when the hybrid does (the
+      first level of its SA part, else the end of its polish);
+    * the ratios at (1 + 1e-2) R* and (1 + 1e-3) R*, R* the RMSE of the
+      polished optimum: t_hybrid = the end of the polish; where the plain run
+      never gets there the ratio is a lower bound (its full time);
+    * plain SA's best-ever RMSE against time (every 20th level)."""
     import torch
     w = W.config4()
     mk = W.synthesize(w, lambda vm, t: gpu_vols(api, vm, t))
@@ -248,29 +278,46 @@ def time_to_rmse(api, W, I, autotune):
     torch.cuda.synchronize()
     t_sa = e0.elapsed_time(e1) / 1e3
     t_hyb = e0.elapsed_time(e2) / 1e3
+    tr_h = r["trace"].cpu().numpy()[0]
+    rmse_h = np.sqrt(tr_h[:, 0] / Q)
+    # the hybrid's level-trace clock starts at its own initial evaluation
     f_opt = float(f.min())
     rmse_opt = np.sqrt(f_opt / Q)
-    target = (1 + 1e-3) * rmse_opt
     rp = plan.sa(w.chains, lb, ub, cool=cool_p, n_levels=L_plain, **kw)
     torch.cuda.synchronize()
     tr = rp["trace"].cpu().numpy()[0]
     rmse_p = np.sqrt(tr[:, 0] / Q)
-    hit = np.nonzero(rmse_p <= target)[0]
-    reached = len(hit) > 0
-    t_plain = float(tr[hit[0], 2] if reached else tr[-1, 2]) / 1e9
+    t_lv = tr[:, 2] / 1e9
+
+    def plain_time(target):
+        hit = np.nonzero(rmse_p <= target)[0]
+        return (float(t_lv[hit[0]]), True) if len(hit) else (float(t_lv[-1]), False)
+
+    ratios = {}
+    for tag, target in (("1e-2", (1 + 1e-2) * rmse_opt), ("1e-3", (1 + 1e-3) * rmse_opt)):
+        tp, reached = plain_time(target)
+        ratios[tag] = {"rmse_target": target, "t_plain_s": tp, "plain_reached": reached,
+                       "t_hybrid_s": t_hyb, "speedup": tp / t_hyb,
+                       "speedup_is_lower_bound": not reached}
+    R_plain = float(rmse_p[-1])
+    tp, _ = plain_time(R_plain)
+    hit_h = np.nonzero(rmse_h <= R_plain)[0]
+    th = float(tr_h[hit_h[0], 2] / 1e9) if len(hit_h) else t_hyb
+    assert rmse_opt <= R_plain or len(hit_h), "the hybrid never reaches plain SA's RMSE"
+    curve = [[round(float(t_lv[l]), 6), float(rmse_p[l])] for l in range(0, L_plain, 20)]
     return {
         "workload": w.name,
-        "rmse_target": target,
         "rmse_sa_plus_lm": rmse_opt,
         "rmse_sa_before_polish": float(np.sqrt(r["best_f"].item() / Q)),
-        "rmse_plain_sa_final": float(rmse_p[-1]),
+        "rmse_plain_sa_final": R_plain,
         "t_sa_plus_lm_s": t_hyb,
         "t_sa_part_s": t_sa,
         "lm_iterations_max": int(it.max()),
-        "t_plain_sa_s": t_plain,
-        "plain_reached_target": bool(reached),
-        "speedup": t_plain / t_hyb,
-        "speedup_is_lower_bound": not reached,
+        "at_plain_final_rmse": {"rmse": R_plain, "t_plain_s": tp, "t_hybrid_s": th,
+                                "speedup": tp / th},
+        "at_polished_rmse": ratios,
+        "plain_rmse_vs_time": curve,
+        "speedup": tp / th,
     }
 
 
@@ -511,6 +558,137 @@ def paper_mc(api, I, flops, cpu=True):
     return out
 
 
+# launch shapes the tuner tries per workload (waves per workgroup, waves per
+# SIMD); the large LMM12 batch keeps to the shapes its LDS and registers allow
+TUNE_CANDIDATES = {"c5": ((8, 3), (8, 4), (4, 3), (4, 4))}
+
+
+def measure_sa(api, W, I, flops, config, steps, warmup, autotune=True, fixed_shape=None,
+               levels=None, use_graph=False):
+    """One workload's calibration, timed: `steps` whole calibrations after
+    `warmup` untimed ones, with the market resident in HBM.  Eager launches
+    carry HIP events around every EVENT_STRIDE-th level kernel (the roofline
+    of the dominant kernel); with use_graph the timed calibrations are
+    hipGraph replays on a side stream, and one eager calibration after them
+    supplies the per-launch kernel time."""
+    import torch
+    w = W.CONFIGS[config]()
+    if levels is not None:
+        w.n_levels = levels
+    mk = W.synthesize(w, lambda vm, t: gpu_vols(api, vm, t))
+    plan = api.Plan(mk)
+    lb, ub = I.box(w.model)
+    nq = I.n_quotes(mk)
+    pts = torch.tensor(W.schedule_points(w.model, w.seed), device="cuda")
+    T0s, cool = [], None
+    for i in range(w.n_inst):
+        c = plan.cost(pts, pt_inst=torch.full((len(pts),), i, dtype=torch.int32,
+                                              device="cuda")).cpu().numpy()
+        T0, cool = W.schedule(c, nq[i], w.n_levels)
+        T0s.append(T0)
+    T0s = np.array(T0s)
+    kw = dict(T0=T0s[0], cool=cool, n_levels=w.n_levels, n_steps=w.n_steps, seed=w.seed,
+              step_frac=w.step_frac, T0_per_inst=T0s, trace=True)
+    tuned = None
+    if fixed_shape is not None:
+        kw.update(waves=fixed_shape["waves"], occupancy=fixed_shape["occupancy"])
+    elif autotune:
+        from paper_2408_01470_amd import autotune as AT
+        cand = TUNE_CANDIDATES.get(config, AT.CANDIDATES)
+        tuned = AT.tune(plan, w.chains, lb, ub, w.n_steps, levels=3 if config == "c5" else 4,
+                        candidates=cand)
+        kw.update(waves=tuned["waves"], occupancy=tuned["occupancy"])
+    L = w.n_levels
+    sampled = list(range(0, L, EVENT_STRIDE))
+
+    def level_events(stream):
+        evs = [None] * (2 * L)
+        for l in sampled:
+            evs[2 * l] = torch.cuda.Event(enable_timing=True)
+            evs[2 * l + 1] = torch.cuda.Event(enable_timing=True)
+            evs[2 * l].record(stream)       # create the HIP events on this stream
+            evs[2 * l + 1].record(stream)
+        return evs
+
+    stream = torch.cuda.Stream() if use_graph else torch.cuda.current_stream()
+    ws, outs = None, None
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            r = plan.sa(w.chains, lb, ub, workspace=ws, out=outs, use_graph=use_graph,
+                        stream=stream, **kw)
+            ws = r["workspace"]
+            outs = r if use_graph else None
+        events = [None if use_graph else level_events(stream) for _ in range(steps)]
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        start.record(stream)
+        results = []
+        for k in range(steps):
+            r = plan.sa(w.chains, lb, ub, workspace=ws, out=outs, level_events=events[k],
+                        use_graph=use_graph, stream=stream, **kw)
+            ws = r["workspace"]
+            outs = r if use_graph else None
+            results.append(r)
+        end.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if use_graph:     # one eager calibration for the per-launch kernel time
+            events = [level_events(stream)]
+            plan.sa(w.chains, lb, ub, workspace=ws, level_events=events[0], stream=stream, **kw)
+            torch.cuda.synchronize()
+    ms_per_step = start.elapsed_time(end) / steps
+    qe = w.quote_evals()
+    lvl_ms = np.array([[evs[2 * l].elapsed_time(evs[2 * l + 1]) for l in sampled]
+                       for evs in events])
+    avg_launch_s = float(lvl_ms.mean()) / 1e3
+    flop_launch = flops.level_launch_flops(mk, w.chains, w.n_steps)
+    achieved = flop_launch / avg_launch_s / 1e12
+    best_f = results[-1]["best_f"].cpu().numpy()
+    shape = {"waves_per_group": kw.get("waves", 0), "occupancy": kw.get("occupancy", 0)}
+    return {
+        "workload": w.name,
+        "value": qe / (ms_per_step / 1e3),
+        "unit": "quote-evals/s",
+        "ms_per_step": ms_per_step,
+        "steps": steps,
+        "launch": "hipGraph replay" if use_graph else "eager",
+        "config": {
+            "workload": w.name,
+            "instances": int(w.n_inst),
+            "quotes_per_instance": int(nq.max()),
+            "quotes_total": int(nq.sum()),
+            "chains_per_instance": int(w.chains),
+            "levels": int(w.n_levels),
+            "steps_per_level": int(w.n_steps),
+            "quote_evals_per_step": qe,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "sa_level_kernel",
+            "achieved": achieved,
+            "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+            "traffic": measured_traffic(config, shape),
+            "flop_per_launch": flop_launch,
+            "avg_launch_ms": avg_launch_s * 1e3,
+            "launches_timed": int(lvl_ms.size),
+        },
+        "calibration": {"rmse_best": float(np.sqrt(best_f / nq).max()),
+                        "wall_s_per_step": wall / steps},
+        "launch_shape": dict(shape, autotuned=tuned is not None),
+        "_market": mk,
+    }
+
+
+# the other workloads reported beside the headline: (config, timed steps,
+# level count override, graph replay)
+EXTRA_SA = (("c1", 3, None, False), ("c2", 3, None, False), ("c3", 2, 20, True))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -539,115 +717,37 @@ def main():
     if args.paper_reb_only:
         print(json.dumps(paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape, "reb")))
         return
-    w = W.CONFIGS[args.config]()
-    if args.levels is not None:
-        w.n_levels = args.levels
-    mk = W.synthesize(w, lambda vm, t: gpu_vols(api, vm, t))
-    plan = api.Plan(mk)
-    lb, ub = I.box(w.model)
-    nq = I.n_quotes(mk)
-    pts = torch.tensor(W.schedule_points(w.model, w.seed), device="cuda")
-    T0s, cool = [], None
-    for i in range(w.n_inst):
-        c = plan.cost(pts, pt_inst=torch.full((len(pts),), i, dtype=torch.int32,
-                                              device="cuda")).cpu().numpy()
-        T0, cool = W.schedule(c, nq[i], w.n_levels)
-        T0s.append(T0)
-    T0s = np.array(T0s)
-    kw = dict(T0=T0s[0], cool=cool, n_levels=w.n_levels, n_steps=w.n_steps, seed=w.seed,
-              step_frac=w.step_frac, T0_per_inst=T0s, trace=True)
-    tuned = None
-    if args.waves is not None:
-        kw.update(waves=args.waves, occupancy=args.occupancy or 1)
-    elif not args.no_autotune:
-        from paper_2408_01470_amd import autotune as AT
-        tuned = AT.tune(plan, w.chains, lb, ub, w.n_steps)
-        kw.update(waves=tuned["waves"], occupancy=tuned["occupancy"])
-    stream = torch.cuda.current_stream()
-    ws = None
-    for _ in range(args.warmup):
-        r = plan.sa(w.chains, lb, ub, workspace=ws, **kw)
-        ws = r["workspace"]
-    torch.cuda.synchronize()
-    L = w.n_levels
-    # HIP events around every EVENT_STRIDE-th level kernel of the timed steps
-    # (recording around every level costs ~2% of the throughput)
-    sampled = list(range(0, L, EVENT_STRIDE))
-    events = []
-    for _ in range(args.steps):
-        evs = [None] * (2 * L)
-        for l in sampled:
-            evs[2 * l] = torch.cuda.Event(enable_timing=True)
-            evs[2 * l + 1] = torch.cuda.Event(enable_timing=True)
-            evs[2 * l].record(stream)       # create the HIP events on this stream
-            evs[2 * l + 1].record(stream)
-        events.append(evs)
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    start.record(stream)
-    results = []
-    for k in range(args.steps):
-        results.append(plan.sa(w.chains, lb, ub, workspace=ws, level_events=events[k], **kw))
-    end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = start.elapsed_time(end)
-    ms_per_step = ms_total / args.steps
-    qe = w.quote_evals()
-    value = qe / (ms_per_step / 1e3)
-    lvl_ms = np.array([[evs[2 * l].elapsed_time(evs[2 * l + 1]) for l in sampled]
-                       for evs in events])
-    avg_launch_s = float(lvl_ms.mean()) / 1e3
-    flop_launch = flops.level_launch_flops(mk, w.chains, w.n_steps)
-    achieved = flop_launch / avg_launch_s / 1e12
-    best_f = results[-1]["best_f"].cpu().numpy()
-    rmse = np.sqrt(best_f / nq)
+    head = measure_sa(api, W, I, flops, args.config, args.steps, args.warmup,
+                      not args.no_autotune, fixed_shape, args.levels, args.graph)
+    mk = head.pop("_market")
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "quote-evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {
-            "workload": w.name,
-            "instances": int(w.n_inst),
-            "quotes_per_instance": int(nq.max()),
-            "chains": int(w.chains),
-            "levels": int(w.n_levels),
-            "steps_per_level": int(w.n_steps),
-            "quote_evals_per_step": qe,
-        },
-        "roofline": {
-            "bound": "alu",
-            "kernel": "sa_level_kernel",
-            "achieved": achieved,
-            "peak": FP64_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": measured_traffic(args.config, {"waves_per_group": kw.get("waves", 0),
-                                                      "occupancy": kw.get("occupancy", 0)}),
-            "flop_per_launch": flop_launch,
-            "avg_launch_ms": avg_launch_s * 1e3,
-            "launches_timed": int(lvl_ms.size),
-        },
-        "calibration": {
-            "rmse_best": float(rmse.max()),
-            "wall_s_per_step": wall / args.steps,
-        },
-        "launch_shape": {"waves_per_group": kw.get("waves", 0),
-                         "occupancy": kw.get("occupancy", 0),
-                         "autotuned": tuned is not None},
+        "config": head["config"],
+        "roofline": head["roofline"],
+        "calibration": head["calibration"],
+        "launch_shape": head["launch_shape"],
+        "launch": head["launch"],
     }
+    if not args.no_extra_configs:
+        out["other_workloads"] = {}
+        for cfg, steps, levels, graph in EXTRA_SA:
+            if cfg == args.config:
+                continue
+            r = measure_sa(api, W, I, flops, cfg, steps, 1, not args.no_autotune, None, levels,
+                           graph)
+            r.pop("_market")
+            out["other_workloads"][cfg] = r
     if not args.no_time_to_rmse:
         out["time_to_rmse"] = time_to_rmse(api, W, I, not args.no_autotune)
     if not args.no_adjoint:
@@ -658,7 +758,7 @@ def main():
     if not args.no_paper_mc:
         out["paper_mc"] = paper_mc(api, I, flops, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_levels, w.n_levels))
+        out["cpu_baseline"] = cpu_baseline(args.config, args.levels)
     print(json.dumps(out))
 
 

@@ -357,7 +357,6 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
     double f = a.RF[inst];
     double bf = a.BF[gc];
     const double T = a.Tcur[inst];
-    const double iT = 1.0 / T;
     double *wbase = smem + 6 * m.max_nu + (size_t)wid * lds_per_wave;
     WaveLds w = wave_lds(m, wbase);
     double *uw = wbase + wave_lds_doubles(m);   // [spp][P + 1] uniforms
@@ -394,8 +393,10 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
         const double uP = us[P];
         const double dE = fp - f;
         // dE > 0 here: the argument is <= 0 (or NaN when both costs are +inf,
-        // which exp_neg maps to 0: a rejection, as exp(NaN) would give)
-        const bool acc = (dE <= 0.0) || (uP < exp_neg(-dE * iT));
+        // which exp_neg maps to 0: a rejection, as exp(NaN) would give).  The
+        // exponent is the correctly rounded quotient -dE/T, one division a
+        // step, so it carries no rounding beyond that of dE itself.
+        const bool acc = (dE <= 0.0) || (uP < exp_neg(-dE / T));
         if (acc) {
           x = xp;
           f = fp;

@@ -28,16 +28,31 @@ def bench():
     return B
 
 
-def test_traffic_records(bench, monkeypatch):
-    shapes = [(4, 4), (8, 4), (6, 4), (4, 3), (8, 3)]
-    vals = [bench.measured_traffic("c2", {"waves_per_group": w, "occupancy": o})
-            for w, o in shapes]
-    assert all(v is not None and 1e6 < v < 1e7 for v in vals), vals
-    assert bench.measured_traffic("c2", {"waves_per_group": 2, "occupancy": 4}) is None
-    assert bench.measured_traffic("c9", {"waves_per_group": 4, "occupancy": 4}) is None
+def _records(config):
+    import json
+    text = open(os.path.join(ROOT, "profiles", f"sa_level_kernel_{config}_counters.md")).read()
+    return json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+
+
+@pytest.mark.parametrize("config,lo,hi", [("c2", 1e6, 1e7), ("c5", 1e7, 1e11)])
+def test_traffic_records(bench, monkeypatch, config, lo, hi):
+    """Each committed record gives the HBM bytes of its launch shape while the
+    sources hash to its digest, and nothing otherwise."""
     from paper_2408_01470_amd import build
-    monkeypatch.setattr(build, "source_digest", lambda: "0" * 64)
-    assert bench.measured_traffic("c2", {"waves_per_group": 4, "occupancy": 4}) is None
+    recs = _records(config)
+    assert recs
+    for rec in recs:
+        monkeypatch.setattr(build, "source_digest", lambda d=rec["source_sha256"]: d)
+        shape = {"waves_per_group": rec["waves_per_group"], "occupancy": rec["occupancy"]}
+        v = bench.measured_traffic(config, shape)
+        assert v is not None and lo < v < hi, (config, shape, v)
+        assert v == pytest.approx(1024 * (rec["fetch_kib_per_dispatch"] * rec["fetch_scale"] +
+                                          rec["write_kib_per_dispatch"] * rec["write_scale"]),
+                                  rel=1e-5)
+        assert bench.measured_traffic(config, {"waves_per_group": 3, "occupancy": 2}) is None
+        monkeypatch.setattr(build, "source_digest", lambda: "0" * 64)
+        assert bench.measured_traffic(config, shape) is None
+    assert bench.measured_traffic("c9", {"waves_per_group": 4, "occupancy": 4}) is None
 
 
 def _executed(name, unit):

@@ -1,0 +1,184 @@
+"""Accept/reject parity with the oracle over whole annealing schedules.
+
+The Metropolis test of Sec. 3's SA box compares u with exp(-dE/T); at the
+low temperatures the benchmark schedules end at (T_end = 0.01 Q sigma_noise^2)
+dE/T is large and a rounding difference between the two cost evaluations is
+most likely to move dE across the threshold -T ln u.  These tests run the
+schedules to their last level and require every accept flag to match; a
+mismatch is reported with the first differing step, both dE values, T and
+-T ln u, and classified as an ulp tie or a real divergence.
+
+* c1 (caplets 10 x 11, GLOBAL4, 64 chains): all 200 levels x 100 steps at
+  the benchmark's T0 and cooling;
+* the c2 market (LMM12, 985 quotes, price residuals) with 64 chains over all
+  688 levels x 10 steps at the benchmark's T0 and cooling;
+* c3 (256 caplet markets) and c5 (64 LMM12 markets x 8838 quotes) at full
+  size over two levels, every chain of sampled instances against the
+  oracle's run of that instance alone, so the level-end restart over
+  thousands of workgroups of a batch is compared too.
+Markets are completed with oracle model vols."""
+import numpy as np
+import pytest
+
+from paper_2408_01470_amd import inputs as I
+from paper_2408_01470_amd import workloads as W
+from sa_divergence import check_restarts, describe, first_mismatch, gpu_cost_fn
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_01470_amd import api as A
+    return A
+
+
+def _oracle_vols(oracle, vm, truth):
+    M = oracle.Market(vm)
+    out = []
+    for i in range(M.n_inst):
+        mv, _, _, ok = oracle.model_values(M, i, truth[i])
+        assert ok
+        out.append(mv)
+    return np.concatenate(out)
+
+
+def _workload(oracle, w):
+    """The workload's market (oracle vols + noise) and its per-instance T0
+    and cooling factor by the benchmark's rule, with oracle costs."""
+    mk = W.synthesize(w, lambda vm, t: _oracle_vols(oracle, vm, t))
+    pts = W.schedule_points(w.model, w.seed)
+    nq = I.n_quotes(mk)
+    T0s, cool = [], None
+    for i in range(w.n_inst):
+        c = oracle.cost_batch(mk, pts, np.full(len(pts), i, np.int32))
+        T0, cool = W.schedule(c, nq[i], w.n_levels)
+        T0s.append(T0)
+    return mk, np.array(T0s), cool
+
+
+def _report(plan, oracle, mk, w, chains, lb, ub, T0s, cool, where):
+    return describe(gpu_cost_fn(plan), len(lb), I.n_inst(mk), oracle, mk, chains, lb, ub, T0s,
+                    cool, w.n_steps, w.seed, w.step_frac, where)
+
+
+def _full_schedule(api, oracle, w, chains, waves):
+    mk, T0s, cool = _workload(oracle, w)
+    lb, ub = I.box(w.model)
+    L, N = w.n_levels, w.n_steps
+    kw = dict(T0=T0s[0], cool=cool, n_levels=L, n_steps=N, seed=w.seed, step_frac=w.step_frac,
+              T0_per_inst=T0s)
+    print(f"{w.name}: {chains} chains, T0 {T0s[0]:.4g}, T_end {T0s[0] * cool ** (L - 1):.4g}",
+          flush=True)
+    plan = api.Plan(mk)
+    g = plan.sa(chains, lb, ub, record=True, chain_best=True, waves=waves, **kw)
+    o = oracle.sa_calibrate(mk, chains, lb, ub, record=True, **kw)
+    acc = g["accept"].cpu().numpy()
+    where = first_mismatch(acc, o["accept"], L, N, [chains])
+    if where is not None:
+        pytest.fail(_report(plan, oracle, mk, w, chains, lb, ub, T0s, cool, where))
+    msg = check_restarts(g["level_best"].cpu().numpy(), o["level_best"])
+    assert msg is None, msg
+    assert np.array_equal(g["best_x"].cpu().numpy(), o["best_x"])
+    np.testing.assert_allclose(g["best_f"].cpu().numpy(), o["best_f"], rtol=RTOL)
+    np.testing.assert_allclose(g["chain_best_f"].cpu().numpy(), o["chain_best_f"], rtol=RTOL)
+    tr = g["trace"].cpu().numpy()
+    np.testing.assert_array_equal(tr[0, :, 1], o["trace"][0, :, 1])
+    # the schedule reaches the cold end: the last levels accept rarely
+    rate = acc.reshape(L, N * chains).mean(axis=1)
+    assert rate[-1] < 0.5 * rate[0]
+    return acc
+
+
+def test_c1_full_schedule_accept_parity(api, oracle):
+    w = W.config1()
+    _full_schedule(api, oracle, w, w.chains, 4)
+
+
+def test_c2_market_full_schedule_accept_parity(api, oracle):
+    w = W.config2()
+    _full_schedule(api, oracle, w, 64, 8)
+
+
+def _sampled_instances(api, oracle, w, sample, waves, occupancy, n_levels=2):
+    mk, T0s, cool = _workload(oracle, w)
+    lb, ub = I.box(w.model)
+    L, N, C = n_levels, w.n_steps, w.chains
+    kw = dict(cool=cool, n_levels=L, n_steps=N, seed=w.seed, step_frac=w.step_frac)
+    print(f"{w.name}: full size, {L} levels, sampled instances {sample}", flush=True)
+    plan = api.Plan(mk)
+    g = plan.sa(C, lb, ub, T0=T0s[0], T0_per_inst=T0s, record=True, chain_best=True,
+                waves=waves, occupancy=occupancy, **kw)
+    torch.cuda.synchronize()
+    acc = g["accept"].cpu().numpy()
+    lbest = g["level_best"].cpu().numpy()
+    bf = g["best_f"].cpu().numpy()
+    cbf = g["chain_best_f"].cpu().numpy()
+    for i in sample:
+        one = I.select_instances(mk, [i])
+        o = oracle.sa_calibrate(one, [C], lb, ub, T0=float(T0s[i]), record=True, inst_key=[i],
+                                **kw)
+        blk = acc[i * L * N * C:(i + 1) * L * N * C]
+        where = first_mismatch(blk, o["accept"], L, N, [C])
+        if where is not None:
+            where = (i,) + where[1:]
+            pytest.fail(_report(plan, oracle, mk, w, np.full(I.n_inst(mk), C), lb, ub, T0s,
+                                cool, where))
+        msg = check_restarts(lbest[i:i + 1], o["level_best"])
+        assert msg is None, f"instance {i}: {msg}"
+        np.testing.assert_allclose(bf[i], o["best_f"][0], rtol=RTOL)
+        np.testing.assert_allclose(cbf[i * C:(i + 1) * C], o["chain_best_f"], rtol=RTOL)
+
+
+def test_c3_full_size_two_levels_sampled_instances(api, oracle):
+    w = W.config3()
+    nq = I.n_quotes(w.market)
+    sample = sorted({0, int(np.argmax(nq)), int(np.argmin(nq)), w.n_inst - 1})
+    _sampled_instances(api, oracle, w, sample, 8, 4)
+
+
+def test_c5_full_size_two_levels_sampled_instance(api, oracle):
+    w = W.config5()
+    _sampled_instances(api, oracle, w, [w.n_inst - 1], 8, 3)
+
+
+def test_graph_replay_ragged_batch_matches_eager_and_oracle(api, oracle):
+    """hipGraph replay of a ragged batch (6 markets, uneven chain counts, a
+    workgroup tiling that leaves partial tiles) equals the eager launches and
+    the oracle on every replay, with other eager work between replays."""
+    from conftest import complete_with_oracle
+    m, truth, noise = I.batch_markets(n_markets=6, M_range=(3, 20), nK_range=(3, 11),
+                                      seed=I.SEED_BASE + 91)
+    mk = complete_with_oracle(oracle, m, truth, noise)
+    lb, ub = I.box(0)
+    plan = api.Plan(mk)
+    chains = np.array([3, 17, 64, 1, 9, 40], np.int32)
+    T0s = np.array([0.05, 0.02, 0.08, 0.01, 0.03, 0.05])
+    kw = dict(T0=0.05, T0_per_inst=T0s, cool=0.8, n_levels=7, n_steps=12, seed=31, waves=4,
+              record=True, chain_best=True)
+    eager = plan.sa(chains, lb, ub, **kw)
+    torch.cuda.synchronize()
+    okw = {k: v for k, v in kw.items() if k not in ("waves", "chain_best")}
+    o = oracle.sa_calibrate(mk, chains, lb, ub, **okw)
+    where = first_mismatch(eager["accept"].cpu().numpy(), o["accept"], 7, 12, chains)
+    assert where is None, f"eager vs oracle: first mismatch at {where}"
+    assert np.array_equal(eager["level_best"].cpu().numpy(), o["level_best"])
+    np.testing.assert_allclose(eager["best_f"].cpu().numpy(), o["best_f"], rtol=RTOL)
+    side = torch.cuda.Stream()
+    ws, outs = eager["workspace"], None
+    pts = torch.tensor(I.random_box_points(0, 256, 5), device="cuda")
+    for rep in range(4):
+        with torch.cuda.stream(side):
+            g = plan.sa(chains, lb, ub, use_graph=True, stream=side, workspace=ws, out=outs, **kw)
+        outs = g
+        side.synchronize()
+        plan.cost(pts)                    # eager work between replays
+        torch.cuda.synchronize()
+        for k in ("accept", "level_best", "best_x", "best_f", "chain_best_x", "chain_best_f"):
+            assert torch.equal(g[k], eager[k]), f"replay {rep}: {k}"
+        assert torch.equal(g["trace"][..., :2], eager["trace"][..., :2]), f"replay {rep}: trace"
