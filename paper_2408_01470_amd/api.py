@@ -208,15 +208,16 @@ class Plan:
             workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=self.device)
         return workspace
 
-    def vjp(self, params, pt_inst=None, g_cost=None, normal=False, stream=None, workspace=None):
+    def vjp(self, params, pt_inst=None, g_cost=None, normal=False, stream=None, workspace=None,
+            want_jtwr=False):
         """Hand-written adjoint: dict(cost, grad = g_cost * d cost/d p, and with
-        normal=True jtwj [n,P,P], jtwr [n,P])."""
+        normal=True jtwj [n,P,P], jtwr [n,P]; want_jtwr: jtwr alone)."""
         params, pt_inst, n = self._pts(params, pt_inst)
         f64 = dict(dtype=torch.float64, device=self.device)
         cost = torch.empty(n, **f64)
         grad = torch.empty((n, self.P), **f64)
         jtwj = torch.empty((n, self.P, self.P), **f64) if normal else None
-        jtwr = torch.empty((n, self.P), **f64) if normal else None
+        jtwr = torch.empty((n, self.P), **f64) if (normal or want_jtwr) else None
         if g_cost is not None:
             g_cost = torch.as_tensor(g_cost, **f64).reshape(n).contiguous()
         ws = self._adj_workspace(n, workspace)

@@ -13,6 +13,8 @@
 // across the wave in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sabr_adjoint.hpp"
 #include "sabr_cost.hpp"
 
@@ -487,6 +489,442 @@ __global__ __launch_bounds__(64) void vjp_kernel(DevMarket m, int n_pts, const i
 }
 
 // ---------------------------------------------------------------------------
+// Gradient of the LMM12 cost without the map Jacobian.  With J_q = M_u^T s_q
+// (s_q = dm_q/d(alpha_u, rho_u, nu_u) of the quote's underlying u):
+//   sum_q w_q r_q J_q = sum_u M_u^T t_u,   t_u = sum_{q of u} w_q r_q s_q,
+// and M_u^T t_u is one reverse sweep of u's map with the seed t_u.  Per chunk
+// of kGradChunk underlyings (the map's order, quotes contiguous per
+// underlying): the SABR constants into LDS, the quotes (lanes over quotes;
+// each lane's w r s summed per underlying by a segmented scan across the
+// wave, the segment ends adding into the chunk's t table in LDS), then one
+// lane per underlying runs the reverse sweep into per-lane gradient
+// accumulators.  Up to kGradWaves points per workgroup share one LDS copy of
+// the per-underlying market values.
+// ---------------------------------------------------------------------------
+constexpr int kGradChunk = kWave;
+constexpr int kGradWaves = 8;
+
+// Per-forward values the reverse sweep needs besides the map's record:
+// e^{-c T}, e^{-c_n T}, T and the frozen weight v = tau P F^beta.
+struct FwdAux {
+  double E, En, T, v;
+};
+
+// Black-76 out-of-the-money price (black_otm) and its vega D f phi(d1)
+// sqrt(T), sharing the exponential.
+__device__ __forceinline__ double black_otm_vega(double f, double K, double L, double sqrtT,
+                                                 double isqrtT, double sigma, double isigma,
+                                                 double D, double &vega) {
+  const double sd = sigma * sqrtT;
+  const double d1 = fma(L * isigma, isqrtT, 0.5 * sd);
+  const double d2 = d1 - sd;
+  double E, X1, X2;
+  exp_erfcx2(-0.5 * d1 * d1, fabs(d1) * M_SQRT1_2, fabs(d2) * M_SQRT1_2, E, X1, X2);
+  const double hE = 0.5 * f * E;
+  vega = D * f * E * (0.39894228040143267794 * sqrtT);
+  if (L <= 0.0)
+    return D * (d1 <= 0.0 ? hE * (X1 - X2) : fma(-hE, X1 + X2, f));
+  return D * (d2 >= 0.0 ? hE * (X2 - X1) : fma(-hE, X1 + X2, K));
+}
+
+// Relative sensitivities of sigma for one quote (Hagan 2002, beta fixed:
+// q = R.qa, D1 = R.qb), d sigma/d(alpha, rho, nu) = sigma (ra, rr, rn), with
+// k the underlying's SABR constants:
+//   sigma = alpha Pq chi / (q^3 D1),  Pq = q^2 + T (ca + cb q + cc q^2),
+//   chi = z/x(z),  z = (nu/alpha) q L;
+//   ra = [1 + T (2 ca + cb q)/Pq - z chi_z/chi] / alpha,
+//   rr = T q nu (beta alpha - rho nu q)/(4 Pq) + chi_rho/chi,
+//   rn = T q (rho beta alpha/4 + (2 - 3 rho^2) nu q/12)/Pq + (q L/alpha) chi_z/chi;
+// chi_z and chi_rho by the log1p form, or by their series below |z| = 2^-10
+// (as hagan2002_grad).  sigma itself comes from hagan2002_frac, as in the
+// cost kernels (these lines repeat its intermediate values, which the
+// compiler shares).
+struct SigRatio {
+  double ra, rr, rn;
+};
+
+__device__ __forceinline__ SigRatio hagan_ratios(const SabrConst &k, double beta, double L,
+                                                 double q, double T) {
+  const double al = k.alpha, rho = k.rho, nua = k.nua;
+  const double z = nua * q * L;
+  const double s = sqrt_gs(fma(z, z - 2.0 * rho, 1.0));
+  const double az = fabs(z);
+  const bool mid = az <= 1.0;
+  const double num = mid ? 2.0 * z : (z > 0.0 ? (s + z) - 1.0 : (1.0 + z) - s);
+  const double den = mid ? (s + 1.0) - z : (z > 0.0 ? 1.0 - rho : (s - z) + rho);
+  const double t = num * rcp_nr(den);
+  const double x = log1p_tang(t);
+  const double ix = rcp_nr(x);
+  const double r2 = rho * rho;
+  const double s2 = fma(-0.25, r2, 1.0 / 6.0);   // (2 - 3 rho^2)/12
+  const double chi = az < kZSeries ? fma(z, fma(z, s2, -0.5 * rho), 1.0) : z * ix;
+  double chi_z, chi_r;
+  if (az < 0x1.0p-10) {
+    const double s3 = -rho * (6.0 * r2 - 5.0) * (1.0 / 24.0);
+    const double s4 = -((225.0 * r2 - 240.0) * r2 + 34.0) * (1.0 / 720.0);
+    const double s5 = -rho * ((210.0 * r2 - 275.0) * r2 + 74.0) * (1.0 / 480.0);
+    chi_z = fma(z, fma(z, fma(z, fma(z, 5.0 * s5, 4.0 * s4), 3.0 * s3), 2.0 * s2), -0.5 * rho);
+    const double d3 = -(18.0 * r2 - 5.0) * (1.0 / 24.0);
+    const double d4 = -(900.0 * r2 - 480.0) * rho * (1.0 / 720.0);
+    const double d5 = -((1050.0 * r2 - 825.0) * r2 + 74.0) * (1.0 / 480.0);
+    chi_r = z * fma(z, fma(z, fma(z, fma(z, d5, d4), d3), -0.5 * rho), -0.5);
+  } else {
+    const double zs = z * rcp_nr(s);
+    const double x_num = mid ? t * zs : (z > 0.0 ? t - zs : zs - t * (1.0 - zs));
+    const double x_r = x_num * rcp_nr(den * (1.0 + t));
+    const double ix2 = ix * ix;
+    chi_z = (x - zs) * ix2;
+    chi_r = -z * x_r * ix2;
+  }
+  const double Pq = fma(q, q, T * fma(q, fma(q, k.cc, k.cb), k.ca));
+  const double iPq = rcp_nr(Pq);
+  const double ichi = rcp_nr(chi);
+  const double ia = rcp_nr(al);
+  const double nu = nua * al;
+  const double cz = chi_z * ichi;
+  SigRatio o;
+  o.ra = ia * (1.0 + T * fma(k.cb, q, 2.0 * k.ca) * iPq - z * cz);
+  o.rr = fma(T * q * 0.25 * nu * fma(-rho * nu, q, beta * al), iPq, chi_r * ichi);
+  o.rn = fma(T * q * fma(rho * beta * al, 0.25, (2.0 - 3.0 * r2) * nu * q * (1.0 / 12.0)), iPq,
+             q * L * ia * cz);
+  return o;
+}
+
+// Model value m of one LMM12 quote (vol, or the out-of-the-money Black price:
+// the same operations as the cost kernels) and dm/d(alpha, rho, nu) of its
+// underlying.
+struct QuoteSens {
+  double m, sa, sr, sn;
+  bool bad;
+};
+
+template <int FORMULA, int RESID>
+__device__ __forceinline__ QuoteSens quote_sens(const SabrConst &k, double beta,
+                                                const QuoteRec &R, const UndMkt &U) {
+  VolFrac vf;
+  double da, dr, dn;   // d sigma/d(alpha, rho, nu)
+  if (FORMULA == 0) {
+    vf = hagan2002_frac(k, R.L, R.qa, R.qb, U.T);
+  } else {   // eq. (sigmaHagan), beta fixed: the quadratic in k = -L itself
+    vf.numer = fma(-R.L, fma(-R.L, k.cc, k.cb), k.ca);
+    vf.denom = 1.0;
+  }
+  QuoteSens o;
+  double sig, sc = 1.0;
+  if (RESID == 0) {
+    sig = FORMULA == 1 ? vf.numer : vf.numer * rcp_nr(vf.denom);
+    o.m = sig;
+    o.bad = !(sig > 0.0) || !(sig < kInf);
+  } else {
+    const double rr = rcp_nr(vf.numer * vf.denom);
+    sig = FORMULA == 1 ? vf.numer : vf.numer * (vf.numer * rr);
+    const double isig = FORMULA == 1 ? rr : vf.denom * (vf.denom * rr);
+    o.m = black_otm_vega(U.f, R.K, R.L, U.sqrtT, U.isqrtT, sig, isig, U.D, sc);
+    o.bad = !(sig > 0.0) || !(sig < kInf) || !(fabs(o.m) < kInf);
+  }
+  if (FORMULA == 0) {
+    const SigRatio h = hagan_ratios(k, beta, R.L, R.qa, U.T);
+    const double ss = sig * sc;
+    da = ss * h.ra;
+    dr = ss * h.rr;
+    dn = ss * h.rn;
+  } else {
+    const SigGrad e3 = eq3_grad(k.alpha, beta, k.rho, k.nua * k.alpha, R.L, U.fp, false);
+    da = sc * e3.da;
+    dr = sc * e3.dr;
+    dn = sc * e3.dn;
+  }
+  o.sa = da;
+  o.sr = dr;
+  o.sn = dn;
+  return o;
+}
+
+// Register or LDS storage of the two per-lane columns of the reverse sweep.
+template <int NMAX>
+struct SweepCols {
+  double c1[NMAX], c2[NMAX];
+  __device__ __forceinline__ double &a(int j) { return c1[j]; }
+  __device__ __forceinline__ double &b(int j) { return c2[j]; }
+};
+template <>
+struct SweepCols<0> {
+  double *c1, *c2;   // stride kWave
+  __device__ __forceinline__ double &a(int j) { return c1[j * kWave]; }
+  __device__ __forceinline__ double &b(int j) { return c2[j * kWave]; }
+};
+
+// g += M_u^T (tA, tR, tN) for the swap of forwards [e, e + n) (n >= 2): the
+// frozen-weight map forward (a_j = v_j alpha_j, R_j = sum_l a_l rho_jl,
+// V = sum a_j R_j, s_a = sum a_j, b_j = a_j R_j nu_j, S_b = sum b_j,
+// Be_j = sum_l b_l e_jl, Nb = eta2 S_b^2 + (1 - eta2) sum_j b_j Be_j,
+// alpha_S = c0 sqrt V, nu_S = sqrt(Nb)/V, rho_S = rho s_a S_b/sqrt(V Nb)),
+// then its reverse sweep with that seed.  Pair sums with an exp(-lambda |dT|)
+// kernel are left plus right recursions over the gap factors; |dT|-weighted
+// pair sums (the lambda derivatives) take the time-weighted left sums.
+// Columns: c1 holds the left a sums, then R_j, then the a-bar terms the
+// last pass completes; c2 the right b sums, then Be_j, then b-bar_j.
+template <int NMAX>
+__device__ __forceinline__ void swap_vjp(const FwdMap *fw, const FwdAux *fx, int n, double c0,
+                                         const double *p, double tA, double tR, double tN,
+                                         SweepCols<NMAX> &col, double *g) {
+  constexpr bool REG = NMAX > 0;
+  const int J = REG ? NMAX : n;
+  const double rho = p[8], eta2 = p[10];
+  double La = 0.0, sa = 0.0;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (REG && j >= n) continue;
+    col.a(j) = La;
+    sa += fw[j].a;
+    La = fw[j].g1 * (La + fw[j].a);
+  }
+  double Ra = 0.0, Rb = 0.0, V = 0.0, Sb = 0.0;
+#pragma unroll
+  for (int j = J - 1; j >= 0; --j) {
+    if (REG && j >= n) continue;
+    const FwdMap F = fw[j];
+    const double Rj = col.a(j) + F.a + Ra;
+    col.a(j) = Rj;
+    V = fma(F.a, Rj, V);
+    const double bj = F.a * Rj * F.nv;
+    Sb += bj;
+    col.b(j) = Rb;
+    if (j > 0) {
+      Ra = fw[j - 1].g1 * (Ra + F.a);
+      Rb = fw[j - 1].g2 * (Rb + bj);
+    }
+  }
+  double Lb = 0.0, LbT = 0.0, bBe = 0.0, lam2h = 0.0;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (REG && j >= n) continue;
+    const FwdMap F = fw[j];
+    const double T = fx[j].T;
+    const double bj = F.a * col.a(j) * F.nv;
+    const double Be = Lb + bj + col.b(j);
+    col.b(j) = Be;
+    bBe = fma(bj, Be, bBe);
+    lam2h = fma(bj, fma(T, Lb, -LbT), lam2h);
+    Lb = F.g2 * (Lb + bj);
+    LbT = F.g2 * fma(bj, T, LbT);
+  }
+  const double Nb = fma(eta2 * Sb, Sb, (1.0 - eta2) * bBe);
+  const double sV = sqrt_gs(V), sN = sqrt_gs(Nb);
+  double Vb = tA * c0 * 0.5 * rcp_nr(sV);
+  double Nbb = 0.0, sab = 0.0, Sbb = 0.0;
+  if (sN > 0.0) {
+    const double iV = rcp_nr(V), inv = rcp_nr(sV * sN);
+    const double rhoS = rho * sa * Sb * inv;
+    Vb -= iV * fma(tN * sN, iV, 0.5 * tR * rhoS);
+    Nbb = 0.5 * fma(tN, inv * sV * iV, -tR * rhoS * rcp_nr(Nb));
+    sab = tR * rho * Sb * inv;
+    Sbb = tR * rho * sa * inv;
+    g[8] = fma(tR, sa * Sb * inv, g[8]);
+  }
+  g[10] = fma(Nbb, fma(Sb, Sb, -bBe), g[10]);
+  g[11] = fma(-2.0 * Nbb * (1.0 - eta2), lam2h, g[11]);
+  const double an = p[4], bn = p[5];
+  double RR = 0.0;
+#pragma unroll
+  for (int j = J - 1; j >= 0; --j) {
+    if (REG && j >= n) continue;
+    const FwdMap F = fw[j];
+    const FwdAux X = fx[j];
+    const double bb = fma(2.0 * Nbb, fma(eta2, Sb, (1.0 - eta2) * col.b(j)), Sbb);
+    const double Rj = col.a(j);
+    const double Rbar = F.a * fma(bb, F.nv, Vb);
+    const double nub = bb * F.a * Rj;
+    g[4] = fma(nub, X.En, g[4]);
+    g[5] = fma(nub * X.T, X.En, g[5]);
+    g[6] = fma(-nub * X.T * fma(bn, X.T, an), X.En, g[6]);
+    g[7] += nub;
+    col.a(j) = fma(fma(bb, F.nv, Vb), Rj, sab) + (Rbar + RR);
+    col.b(j) = bb;
+    if (j > 0) RR = fw[j - 1].g1 * (RR + Rbar);
+  }
+  const double a = p[0], b = p[1];
+  double LR = 0.0, LRT = 0.0, Lx = 0.0, LxT = 0.0, l1 = 0.0;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (REG && j >= n) continue;
+    const FwdMap F = fw[j];
+    const FwdAux X = fx[j];
+    const double Rbar = F.a * fma(col.b(j), F.nv, Vb);
+    const double alb = (col.a(j) + LR) * X.v;
+    g[0] = fma(alb, X.E, g[0]);
+    g[1] = fma(alb * X.T, X.E, g[1]);
+    g[2] = fma(-alb * X.T * fma(b, X.T, a), X.E, g[2]);
+    g[3] += alb;
+    l1 -= fma(Rbar, fma(X.T, Lx, -LxT), F.a * fma(X.T, LR, -LRT));
+    LR = F.g1 * (LR + Rbar);
+    LRT = F.g1 * fma(Rbar, X.T, LRT);
+    Lx = F.g1 * (Lx + F.a);
+    LxT = F.g1 * fma(F.a, X.T, LxT);
+  }
+  g[9] += l1;
+}
+
+// The wave's LDS of the gradient kernel: the map's forward records and the
+// sweep's per-forward values, the chunk's SABR constants and t table, and
+// (swaps longer than 24 forwards) the sweep's two per-lane columns.
+__host__ __device__ inline int grad_wave_doubles(const DevMarket &m) {
+  return kFwdMapDoubles * m.max_nf + 4 * m.max_nf + (kSabrConstDoubles + 3) * kGradChunk +
+         (m.max_len > 24 ? 2 * kWave * m.max_len : 0);
+}
+
+// Segmented inclusive sum over the wave's lanes: segments are runs of equal
+// key (heads: bit l set where lane l starts a run); afterwards the last lane
+// of each run holds the run's sum.
+__device__ __forceinline__ double seg_scan(double v, int lane, int start) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const double w = __shfl_up(v, o, kWave);
+    if (lane - o >= start) v += w;
+  }
+  return v;
+}
+
+template <int FORMULA, int RESID, int REG>
+__global__ __launch_bounds__(kWave *kGradWaves) void grad_kernel(DevMarket m, int n_pts,
+                                                                 const int *pt_inst,
+                                                                 const double *params,
+                                                                 const double *g_cost,
+                                                                 double *cost, double *g_params,
+                                                                 double *jtwr, int lds_per_wave) {
+  extern __shared__ double smem[];
+  __shared__ int s_inst[kGradWaves];
+  constexpr int P = 12;
+  const int nw = blockDim.x / kWave;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = lane_id();
+  const int pt = blockIdx.x * nw + wid;
+  int inst = -1;
+  if (pt < n_pts) inst = __builtin_amdgcn_readfirstlane(pt_inst[pt]);
+  const bool valid = pt < n_pts && inst >= 0 && inst < m.n_inst;
+  if (pt < n_pts && !valid && lane == 0 && cost) cost[pt] = __builtin_nan("");
+  if (lane == 0) s_inst[wid] = valid ? inst : -1;
+  __syncthreads();
+  UndMkt *um = reinterpret_cast<UndMkt *>(smem);
+  double *wb = smem + 6 * m.max_nu + (size_t)wid * lds_per_wave;
+  WaveLds w;
+  w.fw = reinterpret_cast<FwdMap *>(wb);
+  FwdAux *fx = reinterpret_cast<FwdAux *>(wb + kFwdMapDoubles * m.max_nf);
+  w.th = reinterpret_cast<SabrConst *>(wb + (kFwdMapDoubles + 4) * m.max_nf);
+  double *tt = wb + (kFwdMapDoubles + 4) * m.max_nf + kSabrConstDoubles * kGradChunk;
+  w.lk = tt + 3 * kGradChunk;   // the map's LDS column (swaps beyond 24 forwards)
+  for (int r = 0; r < nw; ++r) {   // one round per distinct instance (see cost_kernel)
+    const int ri = s_inst[r];
+    bool first = ri >= 0;
+    for (int q = 0; q < r; ++q) first = first && s_inst[q] != ri;
+    if (!first) continue;
+    const DevInst rin = m.inst[ri];
+    for (int u = threadIdx.x; u < rin.nu; u += blockDim.x) um[u] = und_mkt(m, rin.u0 + u);
+    __syncthreads();
+    if (valid && inst == ri) {
+      const DevInst in = m.inst[inst];
+      double p[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) p[k] = params[(size_t)pt * P + k];
+      bool bad = lmm12_fwd(m, in, p, w);
+      for (int k = lane; k < in.nf; k += kWave) {
+        const double T = m.f_T[in.f0 + k];
+        fx[k] = FwdAux{exp_neg(-(p[2] * T)), exp_neg(-(p[6] * T)), T, m.f_v[in.f0 + k]};
+      }
+      wave_lds_sync();
+      double g[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) g[k] = 0.0;
+      double acc = 0.0;
+      const int *uq0 = m.u_q0 + in.u0;
+      const UndMap *umap = m.u_map + in.u0;
+      const QuoteRec *qrec = m.q + in.q0;
+      const double beta = m.beta;
+      for (int c0 = 0; c0 < in.nu; c0 += kGradChunk) {
+        const int c1 = min(in.nu, c0 + kGradChunk);
+        bad |= lmm12_und<FORMULA, (REG > 0 ? REG : kMapRegLen)>(m, in, um, p, w, c0, c1);
+        for (int k = lane; k < 3 * kGradChunk; k += kWave) tt[k] = 0.0;
+        wave_lds_sync();
+        const int qa = uq0[c0], qb = c1 < in.nu ? uq0[c1] : in.nq;
+        for (int q0 = qa; q0 < qb; q0 += kWave) {   // wave-uniform trip count
+          const int q = q0 + lane;
+          int key = -1 - lane;                        // no quote: a run of its own
+          double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+          if (q < qb) {
+            const QuoteRec R = qrec[q];
+            const UndMkt U = um[R.und];
+            const SabrConst k = w.th[R.und - c0];
+            key = R.und;
+            const QuoteSens qs = quote_sens<FORMULA, RESID>(k, beta, R, U);
+            bad |= qs.bad;
+            const double r = qs.m - R.tgt;
+            acc = fma(R.w * r, r, acc);
+            const double wr = R.w * r;
+            v0 = wr * qs.sa;
+            v1 = wr * qs.sr;
+            v2 = wr * qs.sn;
+          }
+          const int prev = __shfl_up(key, 1, kWave);
+          const unsigned long long heads = __ballot(lane == 0 || prev != key);
+          const unsigned long long upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1);
+          const int start = kWave - 1 - __clzll(heads & upto);
+          v0 = seg_scan(v0, lane, start);
+          v1 = seg_scan(v1, lane, start);
+          v2 = seg_scan(v2, lane, start);
+          const bool tail = key >= 0 && (lane == kWave - 1 || ((heads >> (lane + 1)) & 1));
+          if (tail) {
+            double *t = tt + 3 * (key - c0);
+            t[0] += v0;
+            t[1] += v1;
+            t[2] += v2;
+          }
+        }
+        wave_lds_sync();
+        const int i = c0 + lane;   // one underlying per lane (kGradChunk = kWave)
+        if (i < c1) {
+          const UndMap un = umap[i];
+          const double tA = tt[3 * lane], tR = tt[3 * lane + 1], tN = tt[3 * lane + 2];
+          if (un.n == 1) {
+            const FwdAux X = fx[un.e];
+            g[0] = fma(tA, X.E, g[0]);
+            g[1] = fma(tA * X.T, X.E, g[1]);
+            g[2] = fma(-tA * X.T * fma(p[1], X.T, p[0]), X.E, g[2]);
+            g[3] += tA;
+            g[4] = fma(tN, X.En, g[4]);
+            g[5] = fma(tN * X.T, X.En, g[5]);
+            g[6] = fma(-tN * X.T * fma(p[5], X.T, p[4]), X.En, g[6]);
+            g[7] += tN;
+            g[8] += tR;
+          } else {
+            SweepCols<REG> col;
+            if constexpr (REG == 0) {
+              col.c1 = w.lk + lane;
+              col.c2 = w.lk + (size_t)m.max_len * kWave + lane;
+            }
+            swap_vjp<REG>(w.fw + un.e, fx + un.e, un.n, m.u_c0[in.u0 + un.u], p, tA, tR, tN,
+                          col, g);
+          }
+        }
+        wave_lds_sync();   // the next chunk overwrites the constants and the t table
+      }
+      const double tot = wave_sum(acc);
+      const bool any_bad = __any(bad) || !(tot < kInf);
+      const double gc = g_cost ? g_cost[pt] : 1.0;
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const double s = wave_sum(g[k]);
+        if (lane == 0) {
+          g_params[(size_t)pt * P + k] = any_bad ? 0.0 : gc * (2.0 * s);
+          if (jtwr) jtwr[(size_t)pt * P + k] = any_bad ? 0.0 : s;
+        }
+      }
+      if (lane == 0 && cost) cost[pt] = any_bad ? kInf : tot;
+    }
+    __syncthreads();   // the next round overwrites the market values
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Projected Levenberg-Marquardt, one wave per point for all iterations:
 //   (J^T W J + mu diag(J^T W J)) delta = -J^T W r, trial = clamp(p + delta),
 //   accept if the cost decreases (mu /= 10; stop when the relative decrease
@@ -665,11 +1103,62 @@ size_t adjoint_scratch_bytes(const DevMarket &m, int n_waves) {
 
 int adjoint_waves(int n_pts) { return n_pts < kAdjointMaxWaves ? n_pts : kAdjointMaxWaves; }
 
+// Waves per workgroup of the gradient kernel: the most waves per CU that
+// 160 KB of LDS holds (each workgroup stages the market values once), ties
+// to the larger workgroup; 0 if not even one wave fits.
+int grad_waves(const DevMarket &m) {
+  const long per_cu = 160 * 1024;
+  int best = 0, best_res = 0;
+  for (int w = kGradWaves; w >= 1; w >>= 1) {
+    const long bytes = (long)(6 * m.max_nu + (long)w * grad_wave_doubles(m)) * 8;
+    if (bytes > lds_budget_bytes()) continue;
+    const int res = (int)std::min<long>(per_cu / bytes * w, 16);
+    if (res > best_res) {
+      best_res = res;
+      best = w;
+    }
+  }
+  return best;
+}
+
+hipError_t launch_grad(const DevMarket &m, int n_pts, const int *pt_inst, const double *params,
+                       const double *g_cost, double *cost, double *g_params, double *jtwr,
+                       hipStream_t s) {
+  const int waves = grad_waves(m);
+  if (waves == 0) return hipErrorInvalidValue;
+  const int ld = grad_wave_doubles(m);
+  const size_t lds = (size_t)(6 * m.max_nu + waves * ld) * 8;
+  const dim3 grid((n_pts + waves - 1) / waves), block(kWave * waves);
+#define LAUNCH(B, C, R)                                                                     \
+  hipLaunchKernelGGL((grad_kernel<B, C, R>), grid, block, lds, s, m, n_pts, pt_inst, params, \
+                     g_cost, cost, g_params, jtwr, ld)
+#define CALL(B, C)                     \
+  do {                                 \
+    if (m.max_len <= kMapRegLen)       \
+      LAUNCH(B, C, 16);                \
+    else if (m.max_len <= 24)          \
+      LAUNCH(B, C, 24);                \
+    else                               \
+      LAUNCH(B, C, 0);                 \
+  } while (0)
+  if (m.formula == 0) {
+    if (m.residual == 0) CALL(0, 0); else CALL(0, 1);
+  } else {
+    if (m.residual == 0) CALL(1, 0); else CALL(1, 1);
+  }
+#undef CALL
+#undef LAUNCH
+  return hipGetLastError();
+}
+
 hipError_t launch_vjp(const DevMarket &m, int n_pts, const int *pt_inst, const double *params,
                       const double *g_cost, double *cost, double *g_params, double *jtwj,
                       double *jtwr, double *scratch, hipStream_t s) {
   if (n_pts == 0) return hipSuccess;
   if (m.model != 0 && m.model != 1) return hipErrorInvalidValue;   // GLOBAL4 and LMM12 only
+  // LMM12 gradient (no J^T W J): per-underlying seeds and one map sweep each
+  if (m.model == 1 && !jtwj)
+    return launch_grad(m, n_pts, pt_inst, params, g_cost, cost, g_params, jtwr, s);
   const size_t lds = adjoint_lds_bytes(m);
   const int waves = adjoint_waves(n_pts);
 #define CALL(A, B, C)                                                                        \

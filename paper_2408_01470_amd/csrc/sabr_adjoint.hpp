@@ -11,6 +11,8 @@ namespace sabr {
 constexpr int kAdjointMaxWaves = 2048;
 
 size_t adjoint_scratch_bytes(const DevMarket &m, int n_waves);
+// Largest LDS allocation of one workgroup on the current device (bytes).
+int lds_budget_bytes();
 int adjoint_waves(int n_pts);
 size_t adjoint_lds_bytes(const DevMarket &m);
 
