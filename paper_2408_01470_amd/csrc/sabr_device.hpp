@@ -297,6 +297,33 @@ __device__ __forceinline__ double erfcx_pos(double x) {
   return horner_s<kErfcxPoly, kErfcxDeg>(t) * r;
 }
 
+// One step of three interleaved Horner chains: step I of the two chains on
+// C (degree DEG) and, over its last DEG2 steps, of a third chain on C2
+// (degree DEG2 <= DEG).  The coefficients reach the scalar registers in
+// program order, so the interleaving is written out here rather than left
+// to the scheduler.
+template <const double *C, int DEG, const double *C2, int DEG2, size_t I>
+__device__ __forceinline__ void horner3_step(double t1, double t2, double t3, double &h1,
+                                             double &h2, double &h3) {
+  const double c = SABR_SCONST(C[DEG - 1 - I]);
+  h1 = fma_s(h1, t1, c);
+  h2 = fma_s(h2, t2, c);
+  if constexpr (I + DEG2 >= DEG) {
+    const double c2 = SABR_SCONST(C2[DEG - 1 - I]);
+    h3 = fma_s(h3, t3, c2);
+  }
+}
+template <const double *C, int DEG, const double *C2, int DEG2, size_t... I>
+__device__ __forceinline__ void horner3_s(double t1, double t2, double t3, double &h1, double &h2,
+                                          double &h3, std::index_sequence<I...>) {
+  static_assert(DEG2 <= DEG, "the third chain rides along the last steps");
+  const double c = SABR_SCONST(C[DEG]);
+  h1 = c;
+  h2 = c;
+  h3 = SABR_SCONST(C2[DEG2]);
+  (horner3_step<C, DEG, C2, DEG2, I>(t1, t2, t3, h1, h2, h3), ...);
+}
+
 // erfcx_pos of two arguments, the two polynomial chains interleaved.
 __device__ __forceinline__ void erfcx_pos2(double x1, double x2, double &X1, double &X2) {
   x1 = fmin(x1, 1e100);
@@ -307,6 +334,27 @@ __device__ __forceinline__ void erfcx_pos2(double x1, double x2, double &X1, dou
                                     std::make_index_sequence<kErfcxDeg>{});
   X1 = h1 * r1;
   X2 = h2 * r2;
+}
+
+// exp_neg(xe) and erfcx_pos of x1 and x2 (as those functions compute them),
+// the exponential's Horner chain interleaved with the last steps of the two
+// erfcx chains.
+__device__ __forceinline__ void exp_erfcx2(double xe, double x1, double x2, double &E, double &X1,
+                                           double &X2) {
+  const double xc = fmax(xe, -746.0);
+  const double kd = rint(xc * kExpInvLn2);
+  double r = fma(-kd, kExpLn2Hi, xc);
+  r = fma(-kd, kExpLn2Lo, r);
+  x1 = fmin(x1, 1e100);
+  x2 = fmin(x2, 1e100);
+  const double r1 = rcp_nr(x1 + kErfcxK), r2 = rcp_nr(x2 + kErfcxK);
+  double h1, h2, he;
+  horner3_s<kErfcxPoly, kErfcxDeg, kExpPoly, kExpDeg>((x1 - kErfcxK) * r1, (x2 - kErfcxK) * r2, r,
+                                                       h1, h2, he,
+                                                       std::make_index_sequence<kErfcxDeg>{});
+  X1 = h1 * r1;
+  X2 = h2 * r2;
+  E = ldexp(he, (int)kd);
 }
 
 // ---------------------------------------------------------------------------
@@ -417,9 +465,8 @@ __device__ __forceinline__ double black_otm(double f, double K, double L, double
   const double sd = sigma * sqrtT;
   const double d1 = fma(L * isigma, isqrtT, 0.5 * sd);
   const double d2 = d1 - sd;
-  const double E = exp_neg(-0.5 * d1 * d1);
-  double X1, X2;
-  erfcx_pos2(fabs(d1) * M_SQRT1_2, fabs(d2) * M_SQRT1_2, X1, X2);
+  double E, X1, X2;
+  exp_erfcx2(-0.5 * d1 * d1, fabs(d1) * M_SQRT1_2, fabs(d2) * M_SQRT1_2, E, X1, X2);
   const double hE = 0.5 * f * E;
   if (L <= 0.0)
     return D * (d1 <= 0.0 ? hE * (X1 - X2) : fma(-hE, X1 + X2, f));
