@@ -23,9 +23,21 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _stream(stream=None):
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+def _stream(stream=None, *tensors):
+    """The stream a launch runs on: the caller's, or torch's current one.  On
+    a stream other than the current one the launch first waits for the
+    current stream (where torch allocated and filled the tensors), and every
+    tensor it touches is recorded on that stream, so torch's caching
+    allocator does not hand the memory out while the launch may still use
+    it."""
+    cur = torch.cuda.current_stream()
+    if stream is None or stream == cur:
+        return ctypes.c_void_p(cur.cuda_stream)
+    stream.wait_stream(cur)
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
 
 
 def _require_gpu():
@@ -66,7 +78,7 @@ class Plan:
         self.nq = np.diff(a["q_off"])
         nbytes = int(L.sabr_plan_device_bytes(h))
         self._dev = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
-        check(L.sabr_plan_upload(h, _ptr(self._dev), nbytes, _stream(stream)))
+        check(L.sabr_plan_upload(h, _ptr(self._dev), nbytes, _stream(stream, self._dev)))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -104,7 +116,8 @@ class Plan:
         m = torch.full((n, self.max_q), float("nan"), dtype=torch.float64,
                        device=self.device) if model else None
         check(lib().sabr_cost_batch(self._h, n, _ptr(pt_inst), _ptr(params), _ptr(cost), _ptr(r),
-                                    _ptr(m), self.max_q, _stream(stream)))
+                                    _ptr(m), self.max_q,
+                                    _stream(stream, self._dev, params, pt_inst, cost, r, m)))
         out = [cost]
         if resid:
             out.append(r)
@@ -179,8 +192,9 @@ class Plan:
                 _ptr(o["chain_best_f"]), _ptr(o["accept"]), _ptr(o["trace"]),
                 _ptr(o["level_best"]))
         if noalloc:
-            check(L.sa_calibrate_noalloc(self._h, ctypes.byref(cfg), ch.ctypes.data_as(_i32p),
-                                         *args, _stream(stream)))
+            check(L.sa_calibrate_noalloc(
+                self._h, ctypes.byref(cfg), ch.ctypes.data_as(_i32p), *args,
+                _stream(stream, self._dev, *[v for v in o.values() if isinstance(v, torch.Tensor)])))
             out["workspace"] = None
             out["n_evals"] = ch.astype(np.int64) * (1 + int(n_steps) * int(n_levels))
             return out
@@ -196,7 +210,8 @@ class Plan:
                              _ptr(o["best_x"]), _ptr(o["best_f"]), _ptr(o["chain_best_x"]),
                              _ptr(o["chain_best_f"]), _ptr(o["accept"]), _ptr(o["trace"]),
                              _ptr(o["level_best"]), _ptr(workspace), workspace.numel(),
-                             _stream(stream)))
+                             _stream(stream, self._dev, workspace,
+                                     *[v for v in o.values() if isinstance(v, torch.Tensor)])))
         out["workspace"] = workspace
         out["n_evals"] = ch.astype(np.int64) * (1 + int(n_steps) * int(n_levels))
         return out
@@ -223,7 +238,9 @@ class Plan:
         ws = self._adj_workspace(n, workspace)
         check(lib().sabr_cost_vjp(self._h, n, _ptr(pt_inst), _ptr(params), _ptr(g_cost),
                                   _ptr(cost), _ptr(grad), _ptr(jtwj), _ptr(jtwr), _ptr(ws),
-                                  ws.numel(), _stream(stream)))
+                                  ws.numel(),
+                                  _stream(stream, self._dev, params, pt_inst, g_cost, cost, grad,
+                                          jtwj, jtwr, ws)))
         return dict(cost=cost, grad=grad, jtwj=jtwj, jtwr=jtwr)
 
     def lm(self, params, lb, ub, pt_inst=None, max_iter=50, mu0=1e-3, tol=1e-12, stream=None,
@@ -239,7 +256,7 @@ class Plan:
         check(lib().sabr_lm_polish(self._h, n, _ptr(pt_inst), _ptr(x), lb.ctypes.data_as(_f64p),
                                    ub.ctypes.data_as(_f64p), int(max_iter), float(mu0),
                                    float(tol), _ptr(cost), _ptr(iters), _ptr(ws), ws.numel(),
-                                   _stream(stream)))
+                                   _stream(stream, self._dev, pt_inst, x, cost, iters, ws)))
         return x, cost, iters
 
     def nm(self, params, lb, ub, pt_inst=None, max_iter=1000, step=0.05, tol=1e-12, stream=None,
@@ -258,7 +275,8 @@ class Plan:
         check(lib().sabr_nm_polish(self._h, n, _ptr(pt_inst), _ptr(x), lb.ctypes.data_as(_f64p),
                                    ub.ctypes.data_as(_f64p), int(max_iter), float(step),
                                    float(tol), _ptr(cost), _ptr(iters), _ptr(workspace),
-                                   workspace.numel(), _stream(stream)))
+                                   workspace.numel(),
+                                   _stream(stream, self._dev, pt_inst, x, cost, iters, workspace)))
         return x, cost, iters
 
 
@@ -338,7 +356,8 @@ class McPlan(McProblem):
         self.device = torch.device(device)
         nbytes = int(lib().sabr_mc_plan_device_bytes(self._h))
         self._dev = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
-        check(lib().sabr_mc_plan_upload(self._h, _ptr(self._dev), nbytes, _stream(stream)))
+        check(lib().sabr_mc_plan_upload(self._h, _ptr(self._dev), nbytes,
+                                        _stream(stream, self._dev)))
         self._ws = None
 
     def workspace(self, n_paths):
@@ -353,7 +372,8 @@ class McPlan(McProblem):
         se = torch.empty(self.n_opt, dtype=torch.float64, device=self.device)
         ws, n = self.workspace(n_paths)
         check(lib().sabr_mc_price(self._h, int(n_paths), float(dt), int(seed), _ptr(price),
-                                  _ptr(se), _ptr(ws), ws.numel(), _stream(stream)))
+                                  _ptr(se), _ptr(ws), ws.numel(),
+                                  _stream(stream, self._dev, price, se, ws)))
         return price, se
 
     def cost(self, n_paths, dt, seed, target, weight=None, stream=None):
@@ -367,5 +387,5 @@ class McPlan(McProblem):
         ws, n = self.workspace(n_paths)
         check(lib().sabr_mc_cost(self._h, int(n_paths), float(dt), int(seed), _ptr(target),
                                  _ptr(w), _ptr(price), _ptr(cost), _ptr(ws), ws.numel(),
-                                 _stream(stream)))
+                                 _stream(stream, self._dev, target, w, price, cost, ws)))
         return cost, price

@@ -120,3 +120,42 @@ def test_lmm_cost_at_box_corners_sampled(api, oracle, c2_market):
     assert np.array_equal(fin, np.isfinite(c_g))
     scale = np.maximum(np.abs(c_o[fin]), 1e-300)
     assert np.max(np.abs(c_g[fin] - c_o[fin]) / scale) <= RTOL
+
+
+def test_calls_on_a_stream_other_than_the_current_one(api, oracle, c1_market, c2_market):
+    """Every entry point given a side stream while torch's current stream is
+    another: the launch waits for the current stream's allocations and
+    fills, its tensors are recorded on the side stream, and the results
+    equal those of the same calls on the current stream."""
+    mk, truth = c1_market
+    plan = api.Plan(mk)
+    side = torch.cuda.Stream()
+    cur = torch.cuda.current_stream()
+    pts = torch.tensor(I.random_box_points(0, 300, 9), device="cuda")
+    lb, ub = I.box(0)
+    ref_c, ref_r = plan.cost(pts, resid=True)
+    ref_v = plan.vjp(pts)
+    kw = dict(T0=0.05, cool=0.8, n_levels=3, n_steps=10, seed=5, record=True)
+    ref_s = plan.sa(32, lb, ub, **kw)
+    ref_l = plan.lm(pts[:8], lb, ub, max_iter=5)
+    got_c, got_r = plan.cost(pts, resid=True, stream=side)
+    got_v = plan.vjp(pts, stream=side)
+    got_s = plan.sa(32, lb, ub, stream=side, **kw)
+    got_l = plan.lm(pts[:8], lb, ub, max_iter=5, stream=side)
+    cur.wait_stream(side)
+    assert torch.equal(ref_c, got_c) and torch.equal(ref_r.nan_to_num(), got_r.nan_to_num())
+    assert torch.equal(ref_v["grad"], got_v["grad"])
+    assert torch.equal(ref_s["accept"], got_s["accept"]) and torch.equal(ref_s["best_x"],
+                                                                          got_s["best_x"])
+    assert torch.equal(ref_l[0], got_l[0])
+    mk2, _ = c2_market
+    plan2 = api.Plan(mk2, stream=side)        # upload on the side stream
+    p2 = torch.tensor(np.clip(I.random_box_points(1, 64, 4), *I.box(1)), device="cuda")
+    g2 = plan2.vjp(p2, stream=side)
+    cur.wait_stream(side)
+    np.testing.assert_array_equal(g2["grad"].cpu().numpy(), plan2.vjp(p2)["grad"].cpu().numpy())
+    mc = api.McPlan(I.mc_problem(M=6, n_cap_K=2, n_swaptions=3), stream=side)
+    pr, _ = mc.price(1000, 0.05, 3, stream=side)
+    cur.wait_stream(side)
+    pr0, _ = mc.price(1000, 0.05, 3)
+    assert torch.equal(pr, pr0)

@@ -62,6 +62,19 @@ def test_mc_parity_shapes(api, oracle, M, beta):
     _compare(api, oracle, p, 700, 0.1, 23)
 
 
+@pytest.mark.parametrize("M", [13, 16, 24])
+@pytest.mark.parametrize("n_paths", [4096, 4097, 16385, 131073])
+def test_mc_parity_lanes_per_path_by_register_budget(api, oracle, M, n_paths):
+    """Every lanes-per-path variant (8, 4, 2 and 1 lanes at these path counts)
+    of the kernels of each register budget (up to 13 forwards, 14 to 16,
+    beyond 16) against the oracle on the same paths, at a coarse step."""
+    p = I.mc_problem(seed=I.SEED_BASE + 9830 + M, M=M, n_cap_K=2, n_swaptions=4)
+    p["opt_a"] = np.concatenate([p["opt_a"], [0, M - 1]]).astype(np.int32)
+    p["opt_b"] = np.concatenate([p["opt_b"], [M, M]]).astype(np.int32)
+    p["opt_K"] = np.concatenate([p["opt_K"], [p["F0"].mean(), p["F0"][-1]]])
+    _compare(api, oracle, p, n_paths, 0.25, 29)
+
+
 def test_mc_parity_paper_market(api, oracle):
     p = I.paper_mc_problem()
     _compare(api, oracle, p, 512, 0.02, 2408)
