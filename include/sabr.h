@@ -260,8 +260,8 @@ sabr_status sa_calibrate_noalloc(const sabr_plan *plan, const sa_config *cfg /*[
                                  uint8_t *accept, double *level_trace, int32_t *level_best,
                                  void *stream);
 
-/* Device workspace bytes sabr_cost_vjp and sabr_lm_polish need for n_pts
- * points (per-wave scratch of the LMM12 map Jacobian, box tables). */
+/* Device workspace bytes sabr_lm_polish needs (the box tables; independent
+ * of n_pts).  sabr_cost_vjp needs none. */
 size_t sabr_adjoint_workspace_size(const sabr_plan *plan, int32_t n_pts);
 
 /* Hand-written adjoint of the cost (reverse sweep of the implied-vol formula,
@@ -273,7 +273,8 @@ size_t sabr_adjoint_workspace_size(const sabr_plan *plan, int32_t n_pts);
  * d cost/d p = 2 J^T W r.  Out-of-domain points give cost +inf and zero
  * derivatives.  The derivative of the cost follows from the paper's f_c and
  * f_s (Sec. 3); the paper itself polishes with Nelder-Mead and has no
- * gradient.  GLOBAL4 and LMM12 plans (PERFWD, MM, REB: SABR_EUNSUPPORTED). */
+ * gradient.  GLOBAL4 and LMM12 plans (PERFWD, MM, REB: SABR_EUNSUPPORTED).
+ * workspace, ws_bytes: unused (may be null and 0; kept for ABI stability). */
 sabr_status sabr_cost_vjp(const sabr_plan *plan, int32_t n_pts, const int32_t *pt_inst,
                           const double *params, const double *g_cost, double *cost,
                           double *g_params, double *jtwj, double *jtwr, void *workspace,

@@ -235,12 +235,10 @@ class Plan:
         jtwr = torch.empty((n, self.P), **f64) if (normal or want_jtwr) else None
         if g_cost is not None:
             g_cost = torch.as_tensor(g_cost, **f64).reshape(n).contiguous()
-        ws = self._adj_workspace(n, workspace)
         check(lib().sabr_cost_vjp(self._h, n, _ptr(pt_inst), _ptr(params), _ptr(g_cost),
-                                  _ptr(cost), _ptr(grad), _ptr(jtwj), _ptr(jtwr), _ptr(ws),
-                                  ws.numel(),
+                                  _ptr(cost), _ptr(grad), _ptr(jtwj), _ptr(jtwr), None, 0,
                                   _stream(stream, self._dev, params, pt_inst, g_cost, cost, grad,
-                                          jtwj, jtwr, ws)))
+                                          jtwj, jtwr)))
         return dict(cost=cost, grad=grad, jtwj=jtwj, jtwr=jtwr)
 
     def lm(self, params, lb, ub, pt_inst=None, max_iter=50, mu0=1e-3, tol=1e-12, stream=None,

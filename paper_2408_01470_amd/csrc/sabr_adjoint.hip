@@ -167,207 +167,20 @@ __device__ __forceinline__ SigGrad quote_grad(double alpha, double beta, double 
   return g;
 }
 
-// ---------------------------------------------------------------------------
-// Jacobian of the LMM12 map.  Row 0: alpha_u, row 1: rho_u, row 2: nu_u, each
-// over the 12 parameters, written to M[u*36 ..] (global scratch of the wave).
-// Caplet (forward e): alpha_e = (a + b T) E + d, E = e^{-cT}; nu_e alike;
-// rho_u = rho.  Swap: reverse sweep of the O(n^2) form of the frozen-weight
-// map (pair factors by running products of the gap factors g1, g2):
-//   a_j = v_j alpha_j, R_j = sum_l a_l rho_jl, V = sum a_j R_j, s_a = sum a_j,
-//   b_j = a_j R_j nu_j, S_b = sum b_j, Be_j = sum_l b_l e_jl (e = theta's
-//   exponential), Btheta_j = eta2 S_b + (1 - eta2) Be_j, Nb = sum b_j Btheta_j,
-//   alpha_S = sqrt(V)/(A S0^b), nu_S = sqrt(Nb)/V, rho_S = rho s_a S_b/sqrt(V Nb).
-// ---------------------------------------------------------------------------
-struct FwdExp {
-  double E, En;  // e^{-c T_k}, e^{-c_n T_k}
-};
-
-__device__ void lmm12_jacobian(const DevMarket &m, const DevInst &in, const double *p, WaveLds w,
-                               const FwdExp *ef, double *col, double *M) {
-  const int lane = lane_id();
-  const double a = p[0], b = p[1];
-  const double an = p[4], bn = p[5];
-  const double rho = p[8], eta2 = p[10];
-  const int ML = m.max_len;
-  // per-lane columns (stride kWave): R_j, b_j, Be_j, and two scratch columns
-  double *cR = col + lane;
-  double *cb = col + ML * kWave + lane;
-  double *cB = col + 2 * ML * kWave + lane;
-  double *c3 = col + 3 * ML * kWave + lane;
-  double *c4 = col + 4 * ML * kWave + lane;
-  const double *fT = m.f_T + in.f0;
-  const double *fv = m.f_v + in.f0;
-  for (int u = lane; u < in.nu; u += kWave) {
-    double *Mu = M + (size_t)u * 36;
-    const int e = m.u_first[in.u0 + u];
-    const int n = m.u_len[in.u0 + u];
-    if (n == 1) {
-      for (int j = 0; j < 36; ++j) Mu[j] = 0.0;
-      const double T = fT[e];
-      const double E = ef[e].E, En = ef[e].En;
-      Mu[0] = E;
-      Mu[1] = T * E;
-      Mu[2] = -T * fma(b, T, a) * E;
-      Mu[3] = 1.0;
-      Mu[12 + 8] = 1.0;
-      Mu[24 + 4] = En;
-      Mu[24 + 5] = T * En;
-      Mu[24 + 6] = -T * fma(bn, T, an) * En;
-      Mu[24 + 7] = 1.0;
-      continue;
-    }
-    const FwdMap *fw = w.fw + e;
-    // Forward values in O(n): every sum over pairs with a factor
-    // exp(-lambda |T_j - T_l|) is a left plus a right recursion over the gap
-    // factors (g1 for rho_jl, g2 for the theta kernel e_jl); the |T_l - T_j|
-    // weighted sums add a time-weighted recursion (sum x_l k_jl (T_j - T_l)
-    // over l < j = T_j L_j - LT_j, and symmetrically on the right).
-    double sa = 0.0, V = 0.0, Sb = 0.0;
-    double acc = 0.0;
-    for (int j = 0; j < n; ++j) {        // left sums of a (g1)
-      cR[j * kWave] = acc;
-      const double aj = fw[j].a;
-      sa += aj;
-      acc = fw[j].g1 * (acc + aj);
-    }
-    acc = 0.0;
-    for (int j = n - 1; j >= 0; --j) {   // R_j = left + a_j + right; b_j
-      const double aj = fw[j].a;
-      const double Rj = cR[j * kWave] + aj + acc;
-      cR[j * kWave] = Rj;
-      V = fma(aj, Rj, V);
-      const double bj = aj * Rj * fw[j].nv;
-      cb[j * kWave] = bj;
-      Sb += bj;
-      if (j > 0) acc = fw[j - 1].g1 * (acc + aj);
-    }
-    double Lb = 0.0, LbT = 0.0;
-    for (int j = 0; j < n; ++j) {        // left sums of b (g2), plain and time-weighted
-      const double bj = cb[j * kWave], T = fT[e + j];
-      cB[j * kWave] = Lb;
-      c3[j * kWave] = fma(T, Lb, -LbT);
-      const double g2 = fw[j].g2;
-      Lb = g2 * (Lb + bj);
-      LbT = g2 * fma(bj, T, LbT);
-    }
-    double Nb = 0.0, bBe = 0.0, lam2_pairs = 0.0, Rb = 0.0, RbT = 0.0;
-    for (int j = n - 1; j >= 0; --j) {   // Be_j, sum_l b_l e_jl |T_l - T_j|
-      const double bj = cb[j * kWave], T = fT[e + j];
-      const double Be = cB[j * kWave] + bj + Rb;
-      cB[j * kWave] = Be;
-      const double dBe = c3[j * kWave] + fma(-T, Rb, RbT);
-      Nb = fma(bj, fma(eta2, Sb, (1.0 - eta2) * Be), Nb);
-      bBe = fma(bj, Be, bBe);
-      lam2_pairs = fma(bj, dBe, lam2_pairs);
-      if (j > 0) {
-        const double g2 = fw[j - 1].g2;
-        Rb = g2 * (Rb + bj);
-        RbT = g2 * fma(bj, T, RbT);
-      }
-    }
-    const double sV = sqrt(V), sN = sqrt(Nb);
-    const double c0 = m.u_invA[in.u0 + u] / m.u_S0b[in.u0 + u];
-    const double rhoS = (sN > 0.0) ? rho * sa * Sb / (sV * sN) : 0.0;
-    for (int row = 0; row < 3; ++row) {
-      const double sA = row == 0 ? 1.0 : 0.0, sR = row == 1 ? 1.0 : 0.0,
-                   sNu = row == 2 ? 1.0 : 0.0;
-      double Vb = sA * c0 / (2.0 * sV);
-      double Nbb = 0.0, sab = 0.0, Sbb = 0.0, rb = 0.0;
-      if (sN > 0.0) {
-        Vb += -sNu * sN / (V * V) - sR * rhoS / (2.0 * V);
-        Nbb = sNu / (2.0 * sN * V) - sR * rhoS / (2.0 * Nb);
-        const double inv = 1.0 / (sV * sN);
-        sab = sR * rho * Sb * inv;
-        Sbb = sR * rho * sa * inv;
-        rb = sR * sa * Sb * inv;
-      }
-      // R-bar_j = a_j (b-bar_j nu_j + V-bar), b-bar_j = 2 Nb-bar Btheta_j + S_b-bar;
-      // right sums of R-bar (g1), plain (cb) and time-weighted (c4)
-      double RR = 0.0, RRT = 0.0;
-      for (int j = n - 1; j >= 0; --j) {
-        const double T = fT[e + j];
-        const double bbj = fma(2.0 * Nbb, fma(eta2, Sb, (1.0 - eta2) * cB[j * kWave]), Sbb);
-        const double Rbj = fw[j].a * fma(bbj, fw[j].nv, Vb);
-        c3[j * kWave] = Rbj;
-        cb[j * kWave] = RR;
-        c4[j * kWave] = fma(-T, RR, RRT);
-        if (j > 0) {
-          const double g1 = fw[j - 1].g1;
-          RR = g1 * (RR + Rbj);
-          RRT = g1 * fma(Rbj, T, RRT);
-        }
-      }
-      // a-bar_j = b-bar_j nu_j R_j + V-bar R_j + s_a-bar + sum_m R-bar_m rho_mj, and
-      // the lambda1 term -sum_j a_j sum_l R-bar_l rho_jl |T_l - T_j|
-      double LR = 0.0, LRT = 0.0, l1 = 0.0;
-      double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, m4 = 0.0, m5 = 0.0, m6 = 0.0, m7 = 0.0;
-      for (int j = 0; j < n; ++j) {
-        const FwdMap F = fw[j];
-        const double T = fT[e + j];
-        const double aj = F.a, Rj = cR[j * kWave], Rbj = c3[j * kWave];
-        const double bbj = fma(2.0 * Nbb, fma(eta2, Sb, (1.0 - eta2) * cB[j * kWave]), Sbb);
-        const double abar =
-            fma(bbj * F.nv, Rj, fma(Vb, Rj, sab)) + ((LR + Rbj) + cb[j * kWave]);
-        l1 = fma(-aj, fma(T, LR, -LRT) + c4[j * kWave], l1);
-        const double alb = abar * fv[e + j];   // alpha-bar_j
-        const double nub = bbj * aj * Rj;      // nu-bar_j
-        const double E = ef[e + j].E, En = ef[e + j].En;
-        m0 = fma(alb, E, m0);
-        m1 = fma(alb * T, E, m1);
-        m2 = fma(-alb * T * fma(b, T, a), E, m2);
-        m3 += alb;
-        m4 = fma(nub, En, m4);
-        m5 = fma(nub * T, En, m5);
-        m6 = fma(-nub * T * fma(bn, T, an), En, m6);
-        m7 += nub;
-        LR = F.g1 * (LR + Rbj);
-        LRT = F.g1 * fma(Rbj, T, LRT);
-      }
-      double *Mr = Mu + row * 12;
-      Mr[0] = m0;
-      Mr[1] = m1;
-      Mr[2] = m2;
-      Mr[3] = m3;
-      Mr[4] = m4;
-      Mr[5] = m5;
-      Mr[6] = m6;
-      Mr[7] = m7;
-      Mr[8] = rb;
-      Mr[9] = l1;                                     // lambda1
-      Mr[10] = Nbb * (Sb * Sb - bBe);                 // eta2
-      Mr[11] = -Nbb * (1.0 - eta2) * lam2_pairs;      // lambda2 (ordered pairs)
-    }
-  }
-}
-
 // Accumulates the cost, gradient and (optionally) normal equations of one
-// point over the wave's quotes.  Out-of-domain points give cost +inf and
-// zero derivatives.  grad, jtwr: P values; jtwj: P(P+1)/2 (upper triangle).
-template <int MODEL, int FORMULA, int RESID, bool NORMAL>
+// GLOBAL4 point over the wave's quotes (J_q = dm_q/d(alpha, beta, rho, nu)).
+// Out-of-domain points give cost +inf and zero derivatives.  grad, jtwr: P
+// values; jtwj: P(P+1)/2 (upper triangle).  (LMM12 takes lmm_normal and
+// grad_kernel below: per-underlying seeds and sweeps of the map.)
+template <int FORMULA, int RESID, bool NORMAL>
 __device__ double point_normal(const DevMarket &m, const DevInst &in, const UndMkt *um,
-                               const double *p, WaveLds w, FwdExp *ef, double *col,
-                               double *M, double *grad, double *jtwj, double *jtwr) {
-  constexpr int P = NP<MODEL>::P;
+                               const double *p, double *grad, double *jtwj, double *jtwr) {
+  constexpr int P = 4;
   constexpr int NT = P * (P + 1) / 2;
   const int lane = lane_id();
-  bool bad;
-  double beta;
-  if (MODEL == 0) {
-    bad = !(p[0] > 0.0) || !(p[1] >= 0.0 && p[1] <= 1.0) || !(fabs(p[2]) < 1.0) ||
-          !(p[3] >= 0.0);
-    beta = p[1];
-  } else {
-    bad = lmm12_map<FORMULA>(m, in, um, p, w);
-    beta = m.beta;
-    for (int k = lane; k < in.nf; k += kWave) {
-      const double T = m.f_T[in.f0 + k];
-      ef[k] = FwdExp{exp(-(p[2] * T)), exp(-(p[6] * T))};
-    }
-    wave_lds_sync();
-    if (!bad) lmm12_jacobian(m, in, p, w, ef, col, M);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-  }
+  bool bad = !(p[0] > 0.0) || !(p[1] >= 0.0 && p[1] <= 1.0) || !(fabs(p[2]) < 1.0) ||
+             !(p[3] >= 0.0);
+  const double beta = p[1];
   double g[P], jr[P], jj[NORMAL ? NT : 1];
 #pragma unroll
   for (int k = 0; k < P; ++k) g[k] = jr[k] = 0.0;
@@ -377,32 +190,11 @@ __device__ double point_normal(const DevMarket &m, const DevInst &in, const UndM
   for (int q = lane; q < in.nq; q += kWave) {
     const QuoteRec &R = m.q[in.q0 + q];
     const UndMkt U = um[R.und];
-    double al, rh, nu;
-    if (MODEL == 0) {
-      al = p[0];
-      rh = p[2];
-      nu = p[3];
-    } else {
-      const SabrConst &K = w.th[R.und];
-      al = K.alpha;
-      rh = K.rho;
-      nu = K.nua * K.alpha;
-    }
-    const SigGrad sg = quote_grad<FORMULA, RESID>(al, beta, rh, nu, R, U, MODEL == 0);
+    const SigGrad sg = quote_grad<FORMULA, RESID>(p[0], beta, p[2], p[3], R, U, true);
     bad |= !(sg.vol > 0.0) || !(sg.vol < kInf) || !(fabs(sg.sig) < kInf);
     const double r = sg.sig - R.tgt;
     acc = fma(R.w * r, r, acc);
-    double J[P];
-    if (MODEL == 0) {
-      J[0] = sg.da;
-      J[1] = sg.db;
-      J[2] = sg.dr;
-      J[3] = sg.dn;
-    } else {
-      const double *Mu = M + (size_t)R.und * 36;
-#pragma unroll
-      for (int k = 0; k < P; ++k) J[k] = sg.da * Mu[k] + sg.dr * Mu[12 + k] + sg.dn * Mu[24 + k];
-    }
+    const double J[P] = {sg.da, sg.db, sg.dr, sg.dn};
     const double wr = R.w * r;
 #pragma unroll
     for (int k = 0; k < P; ++k) g[k] = fma(wr, J[k], g[k]);
@@ -434,25 +226,18 @@ __device__ double point_normal(const DevMarket &m, const DevInst &in, const UndM
   return any_bad ? kInf : tot;
 }
 
-__device__ __forceinline__ size_t vjp_lds_doubles(const DevMarket &m) {
-  return 6 * m.max_nu + wave_lds_doubles(m, true) + (m.model == 1 ? 2 * m.max_nf + 5 * m.max_len * kWave : 0);
-}
-
-// sabr_cost_vjp: one wave per point (grid-stride), private M_u scratch per wave.
-template <int MODEL, int FORMULA, int RESID, bool NORMAL>
+// sabr_cost_vjp on GLOBAL4 plans: one wave per point (grid-stride), the
+// instance's market values in LDS.
+template <int FORMULA, int RESID, bool NORMAL>
 __global__ __launch_bounds__(64) void vjp_kernel(DevMarket m, int n_pts, const int *pt_inst,
                                                  const double *params, const double *g_cost,
                                                  double *cost, double *g_params, double *jtwj,
-                                                 double *jtwr, double *scratch) {
+                                                 double *jtwr) {
   extern __shared__ double smem[];
-  constexpr int P = NP<MODEL>::P;
+  constexpr int P = 4;
   constexpr int NT = P * (P + 1) / 2;
   const int lane = lane_id();
   UndMkt *um = reinterpret_cast<UndMkt *>(smem);
-  WaveLds w = wave_lds(m, smem + 6 * m.max_nu, true);
-  FwdExp *ef = reinterpret_cast<FwdExp *>(smem + 6 * m.max_nu + wave_lds_doubles(m, true));
-  double *col = smem + 6 * m.max_nu + wave_lds_doubles(m, true) + 2 * m.max_nf;
-  double *M = scratch + (size_t)blockIdx.x * m.max_nu * 36;
   for (int pt = blockIdx.x; pt < n_pts; pt += gridDim.x) {
     const int inst = __builtin_amdgcn_readfirstlane(pt_inst[pt]);
     if (inst < 0 || inst >= m.n_inst) {
@@ -467,8 +252,7 @@ __global__ __launch_bounds__(64) void vjp_kernel(DevMarket m, int n_pts, const i
 #pragma unroll
     for (int k = 0; k < P; ++k) p[k] = params[(size_t)pt * P + k];
     double grad[P], jr[P], jj[NORMAL ? NT : 1];
-    const double f = point_normal<MODEL, FORMULA, RESID, NORMAL>(m, in, um, p, w, ef, col, M,
-                                                                 grad, jj, jr);
+    const double f = point_normal<FORMULA, RESID, NORMAL>(m, in, um, p, grad, jj, jr);
     if (lane == 0) {
       const double gc = g_cost ? g_cost[pt] : 1.0;
       if (cost) cost[pt] = f;
@@ -960,22 +744,19 @@ __device__ bool cholesky_solve_lds(double *A, double *rhs, double *x) {
   return true;
 }
 
-template <int MODEL, int FORMULA, int RESID>
+// The GLOBAL4 LM (LMM12: lm12_kernel below).
+template <int FORMULA, int RESID>
 __global__ __launch_bounds__(64) void lm_kernel(DevMarket m, int n_pts, const int *pt_inst,
                                                 double *params, const double *lb,
                                                 const double *ub, int max_iter, double mu0,
-                                                double tol, double *cost_out, int *iters_out,
-                                                double *scratch) {
+                                                double tol, double *cost_out, int *iters_out) {
   extern __shared__ double smem[];
-  constexpr int P = NP<MODEL>::P;
+  constexpr int P = 4;
   constexpr int NT = P * (P + 1) / 2;
   const int lane = lane_id();
   UndMkt *um = reinterpret_cast<UndMkt *>(smem);
-  WaveLds w = wave_lds(m, smem + 6 * m.max_nu, true);
-  FwdExp *ef = reinterpret_cast<FwdExp *>(smem + 6 * m.max_nu + wave_lds_doubles(m, true));
-  double *col = smem + 6 * m.max_nu + wave_lds_doubles(m, true) + 2 * m.max_nf;
-  double *sys = col + (MODEL == 1 ? 5 * m.max_len * kWave : 0);  // P*P + 3P doubles
-  double *M = scratch + (size_t)blockIdx.x * m.max_nu * 36;
+  const WaveLds w{};   // no map
+  double *sys = smem + 6 * m.max_nu;   // P*P + 3P doubles
   for (int pt = blockIdx.x; pt < n_pts; pt += gridDim.x) {
     const int inst = __builtin_amdgcn_readfirstlane(pt_inst[pt]);
     if (inst < 0 || inst >= m.n_inst) {
@@ -997,8 +778,7 @@ __global__ __launch_bounds__(64) void lm_kernel(DevMarket m, int n_pts, const in
       hi[k] = ub[(size_t)inst * P + k];
     }
     double grad[P], g[P], jj[NT];
-    double f = point_normal<MODEL, FORMULA, RESID, true>(m, in, um, p, w, ef, col, M, grad, jj,
-                                                          g);
+    double f = point_normal<FORMULA, RESID, true>(m, in, um, p, grad, jj, g);
     double mu = mu0;
     int it = 0;
     if (f < kInf) {
@@ -1039,12 +819,12 @@ __global__ __launch_bounds__(64) void lm_kernel(DevMarket m, int n_pts, const in
           if (y < lo[k]) y = lo[k];
           trial[k] = y;
         }
-        const double ft = point_cost<MODEL, FORMULA, RESID>(m, in, um, trial, 0.0, w, nullptr, nullptr);
+        const double ft = point_cost<0, FORMULA, RESID>(m, in, um, trial, 0.0, w, nullptr, nullptr);
         if (ft < f) {
           const double rel = (f - ft) / f;
 #pragma unroll
           for (int k = 0; k < P; ++k) p[k] = trial[k];
-          point_normal<MODEL, FORMULA, RESID, true>(m, in, um, p, w, ef, col, M, grad, jj, g);
+          point_normal<FORMULA, RESID, true>(m, in, um, p, grad, jj, g);
           f = ft;
           mu /= 10.0;
           if (rel < tol) {
@@ -1068,37 +848,469 @@ __global__ __launch_bounds__(64) void lm_kernel(DevMarket m, int n_pts, const in
   }
 }
 
+// ---------------------------------------------------------------------------
+// LMM12 normal equations without a per-quote Jacobian.  With J_q = M_u^T s_q:
+//   J^T W r = sum_u M_u^T t_u,       t_u = sum_{q of u} w_q r_q s_q,
+//   J^T W J = sum_u M_u^T S_u M_u,   S_u = sum_{q of u} w_q s_q s_q^T (3 x 3).
+// Per chunk of kGradChunk underlyings: the SABR constants, then the quotes
+// (lanes over quotes; w r s and the six entries of w s s^T summed per
+// underlying by the segmented scan), then one lane per underlying runs three
+// reverse sweeps of the map (unit seeds: the rows of M_u), adds M_u^T t_u to
+// its J^T W r accumulators and stores M_u and S_u in LDS, and last the lanes
+// take the 78 entries of the upper triangle of J^T W J (lane l entry l, lanes
+// 0..13 also entry 64 + l) and add sum_u m_i^T S_u m_j over the chunk.
+// ---------------------------------------------------------------------------
+constexpr int kNormP = 12;
+constexpr int kNormT = kNormP * (kNormP + 1) / 2;   // 78
+constexpr int kMSDoubles = 3 * kNormP + 6;          // M_u rows and S_u
+
+// Upper-triangle entry t (row-major, i <= j) of a kNormP x kNormP matrix.
+__device__ __forceinline__ void tri_ij(int t, int &i, int &j) {
+  i = 0;
+  int rem = t;
+  while (rem >= kNormP - i) {
+    rem -= kNormP - i;
+    ++i;
+  }
+  j = i + rem;
+}
+
+struct NormLds {
+  WaveLds w;     // map records, SABR constants (>= kGradChunk entries), LDS columns
+  FwdAux *fx;    // [max_nf]
+  double *ts;    // [kGradChunk][9]: t_u (3) and S_u (6)
+  double *ms;    // [kGradChunk][kMSDoubles]
+  double *sys;   // 2 kNormP^2 + 6 kNormP: the LM system and its inputs
+};
+
+__host__ __device__ inline int norm_th_entries(const DevMarket &m) {
+  const int t = th_entries(m, false);
+  return t > kGradChunk ? t : kGradChunk;
+}
+
+// Two LDS columns per lane: the sweep's beyond 24 forwards (the map's own
+// column, for the cost of a trial point, is the first of them).
+__host__ __device__ inline bool norm_lds_columns(const DevMarket &m) {
+  return m.max_len > 24 || lds_column(m, false);
+}
+
+__host__ __device__ inline int norm_wave_doubles(const DevMarket &m) {
+  return kFwdMapDoubles * m.max_nf + kSabrConstDoubles * norm_th_entries(m) +
+         (norm_lds_columns(m) ? 2 * kWave * m.max_len : 0) + 4 * m.max_nf + 9 * kGradChunk +
+         kMSDoubles * kGradChunk + 2 * kNormP * kNormP + 6 * kNormP;
+}
+
+__device__ __forceinline__ NormLds norm_lds(const DevMarket &m, double *base) {
+  NormLds L;
+  L.w.fw = reinterpret_cast<FwdMap *>(base);
+  double *o = base + kFwdMapDoubles * m.max_nf;
+  L.w.th = reinterpret_cast<SabrConst *>(o);
+  o += kSabrConstDoubles * norm_th_entries(m);
+  L.w.lk = o;
+  o += norm_lds_columns(m) ? 2 * kWave * m.max_len : 0;
+  L.fx = reinterpret_cast<FwdAux *>(o);
+  o += 4 * m.max_nf;
+  L.ts = o;
+  o += 9 * kGradChunk;
+  L.ms = o;
+  o += kMSDoubles * kGradChunk;
+  L.sys = o;
+  return L;
+}
+
+// The map Jacobian rows of one underlying, row r = M_u^T e_r for
+// r = (alpha_u, rho_u, nu_u) over the 12 parameters, one at a time into
+// ms[12 r ..]; g += sum_r t_r row_r.
+template <int REG>
+__device__ __forceinline__ void und_rows(const UndMap &un, const NormLds &L, int max_len,
+                                         const double *p, double c0, const double *t,
+                                         double *ms, double (&g)[kNormP]) {
+  if (un.n == 1) {
+    const FwdAux X = L.fx[un.e];
+    double M[3][kNormP];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int k = 0; k < kNormP; ++k) M[r][k] = 0.0;
+    M[0][0] = X.E;
+    M[0][1] = X.T * X.E;
+    M[0][2] = -X.T * fma(p[1], X.T, p[0]) * X.E;
+    M[0][3] = 1.0;
+    M[1][8] = 1.0;
+    M[2][4] = X.En;
+    M[2][5] = X.T * X.En;
+    M[2][6] = -X.T * fma(p[5], X.T, p[4]) * X.En;
+    M[2][7] = 1.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int k = 0; k < kNormP; ++k) {
+        ms[r * kNormP + k] = M[r][k];
+        g[k] = fma(t[r], M[r][k], g[k]);
+      }
+    return;
+  }
+  for (int r = 0; r < 3; ++r) {
+    double row[kNormP];
+#pragma unroll
+    for (int k = 0; k < kNormP; ++k) row[k] = 0.0;
+    SweepCols<REG> col;
+    if constexpr (REG == 0) {
+      col.c1 = L.w.lk + lane_id();
+      col.c2 = L.w.lk + (size_t)max_len * kWave + lane_id();
+    }
+    swap_vjp<REG>(L.w.fw + un.e, L.fx + un.e, un.n, c0, p, r == 0 ? 1.0 : 0.0,
+                  r == 1 ? 1.0 : 0.0, r == 2 ? 1.0 : 0.0, col, row);
+#pragma unroll
+    for (int k = 0; k < kNormP; ++k) {
+      ms[r * kNormP + k] = row[k];
+      g[k] = fma(t[r], row[k], g[k]);
+    }
+  }
+}
+
+// Cost, J^T W r (wave-uniform, jr) and J^T W J (lane l holds entries l and,
+// for l < kNormT - kWave, 64 + l: h[0], h[1]) of one LMM12 point; +inf cost
+// and zero derivatives outside the domain.
+template <int FORMULA, int RESID, int REG>
+__device__ double lmm_normal(const DevMarket &m, const DevInst &in, const UndMkt *um,
+                             const double *p, const NormLds &L, double (&jr)[kNormP],
+                             double (&h)[2]) {
+  const int lane = lane_id();
+  bool bad = lmm12_fwd(m, in, p, L.w);
+  for (int k = lane; k < in.nf; k += kWave) {
+    const double T = m.f_T[in.f0 + k];
+    L.fx[k] = FwdAux{exp_neg(-(p[2] * T)), exp_neg(-(p[6] * T)), T, m.f_v[in.f0 + k]};
+  }
+  wave_lds_sync();
+  double g[kNormP];
+#pragma unroll
+  for (int k = 0; k < kNormP; ++k) g[k] = 0.0;
+  h[0] = h[1] = 0.0;
+  int hi0, hj0, hi1 = 0, hj1 = 0;
+  tri_ij(lane, hi0, hj0);
+  const bool two = lane + kWave < kNormT;
+  if (two) tri_ij(lane + kWave, hi1, hj1);
+  double acc = 0.0;
+  const int *uq0 = m.u_q0 + in.u0;
+  const UndMap *umap = m.u_map + in.u0;
+  const QuoteRec *qrec = m.q + in.q0;
+  const double beta = m.beta;
+  for (int c0 = 0; c0 < in.nu; c0 += kGradChunk) {
+    const int c1 = min(in.nu, c0 + kGradChunk);
+    bad |= lmm12_und<FORMULA, (REG > 0 ? REG : kMapRegLen)>(m, in, um, p, L.w, c0, c1);
+    for (int k = lane; k < 9 * kGradChunk; k += kWave) L.ts[k] = 0.0;
+    wave_lds_sync();
+    const int qa = uq0[c0], qb = c1 < in.nu ? uq0[c1] : in.nq;
+    for (int q0 = qa; q0 < qb; q0 += kWave) {   // wave-uniform trip count
+      const int q = q0 + lane;
+      int key = -1 - lane;                        // no quote: a run of its own
+      double v[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) v[k] = 0.0;
+      if (q < qb) {
+        const QuoteRec R = qrec[q];
+        const QuoteSens qs = quote_sens<FORMULA, RESID>(L.w.th[R.und - c0], beta, R, um[R.und]);
+        key = R.und;
+        bad |= qs.bad;
+        const double r = qs.m - R.tgt;
+        acc = fma(R.w * r, r, acc);
+        const double wr = R.w * r;
+        v[0] = wr * qs.sa;
+        v[1] = wr * qs.sr;
+        v[2] = wr * qs.sn;
+        const double wa = R.w * qs.sa, wrh = R.w * qs.sr;
+        v[3] = wa * qs.sa;
+        v[4] = wa * qs.sr;
+        v[5] = wa * qs.sn;
+        v[6] = wrh * qs.sr;
+        v[7] = wrh * qs.sn;
+        v[8] = R.w * qs.sn * qs.sn;
+      }
+      const int prev = __shfl_up(key, 1, kWave);
+      const unsigned long long heads = __ballot(lane == 0 || prev != key);
+      const unsigned long long upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1);
+      const int start = kWave - 1 - __clzll(heads & upto);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) v[k] = seg_scan(v[k], lane, start);
+      const bool tail = key >= 0 && (lane == kWave - 1 || ((heads >> (lane + 1)) & 1));
+      if (tail) {
+        double *t = L.ts + 9 * (key - c0);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) t[k] += v[k];
+      }
+    }
+    wave_lds_sync();
+    const int i = c0 + lane;   // one underlying per lane (kGradChunk = kWave)
+    if (i < c1) {
+      const UndMap un = umap[i];
+      const double *t = L.ts + 9 * lane;
+      double *ms = L.ms + kMSDoubles * lane;
+      und_rows<REG>(un, L, m.max_len, p, m.u_c0[in.u0 + un.u], t, ms, g);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) ms[3 * kNormP + k] = t[3 + k];
+    }
+    wave_lds_sync();
+    // J^T W J entries: sum over the chunk's underlyings of m_i^T S m_j,
+    // S = [[s0 s1 s2], [s1 s3 s4], [s2 s4 s5]]
+    for (int u = 0; u < c1 - c0; ++u) {
+      const double *ms = L.ms + kMSDoubles * u;
+      const double *S = ms + 3 * kNormP;
+      {
+        const double a0 = ms[hi0], a1 = ms[kNormP + hi0], a2 = ms[2 * kNormP + hi0];
+        const double b0 = ms[hj0], b1 = ms[kNormP + hj0], b2 = ms[2 * kNormP + hj0];
+        const double Sb0 = fma(S[0], b0, fma(S[1], b1, S[2] * b2));
+        const double Sb1 = fma(S[1], b0, fma(S[3], b1, S[4] * b2));
+        const double Sb2 = fma(S[2], b0, fma(S[4], b1, S[5] * b2));
+        h[0] = fma(a0, Sb0, fma(a1, Sb1, fma(a2, Sb2, h[0])));
+      }
+      if (two) {
+        const double a0 = ms[hi1], a1 = ms[kNormP + hi1], a2 = ms[2 * kNormP + hi1];
+        const double b0 = ms[hj1], b1 = ms[kNormP + hj1], b2 = ms[2 * kNormP + hj1];
+        const double Sb0 = fma(S[0], b0, fma(S[1], b1, S[2] * b2));
+        const double Sb1 = fma(S[1], b0, fma(S[3], b1, S[4] * b2));
+        const double Sb2 = fma(S[2], b0, fma(S[4], b1, S[5] * b2));
+        h[1] = fma(a0, Sb0, fma(a1, Sb1, fma(a2, Sb2, h[1])));
+      }
+    }
+    wave_lds_sync();   // the next chunk overwrites the constants and both tables
+  }
+  const double tot = wave_sum(acc);
+  const bool any_bad = __any(bad) || !(tot < kInf);
+#pragma unroll
+  for (int k = 0; k < kNormP; ++k) {
+    const double s = wave_sum(g[k]);
+    jr[k] = any_bad ? 0.0 : s;
+  }
+  if (any_bad) h[0] = h[1] = 0.0;
+  return any_bad ? kInf : tot;
+}
+
+// Writes the lanes' J^T W J entries into a full kNormP x kNormP row-major
+// matrix A (both triangles).
+__device__ __forceinline__ void scatter_jtwj(double *A, const double (&h)[2]) {
+  const int lane = lane_id();
+  int i, j;
+  tri_ij(lane, i, j);
+  A[i * kNormP + j] = h[0];
+  A[j * kNormP + i] = h[0];
+  if (lane + kWave < kNormT) {
+    tri_ij(lane + kWave, i, j);
+    A[i * kNormP + j] = h[1];
+    A[j * kNormP + i] = h[1];
+  }
+}
+
+// sabr_cost_vjp with J^T W J on LMM12 plans: one wave per point, up to
+// kGradWaves points per workgroup sharing the market values (rounds per
+// distinct instance, as cost_kernel).
+template <int FORMULA, int RESID, int REG>
+__global__ __launch_bounds__(kWave *kGradWaves) void normal_kernel(DevMarket m, int n_pts,
+                                                                   const int *pt_inst,
+                                                                   const double *params,
+                                                                   const double *g_cost,
+                                                                   double *cost, double *g_params,
+                                                                   double *jtwj, double *jtwr,
+                                                                   int lds_per_wave) {
+  extern __shared__ double smem[];
+  __shared__ int s_inst[kGradWaves];
+  const int nw = blockDim.x / kWave;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = lane_id();
+  const int pt = blockIdx.x * nw + wid;
+  int inst = -1;
+  if (pt < n_pts) inst = __builtin_amdgcn_readfirstlane(pt_inst[pt]);
+  const bool valid = pt < n_pts && inst >= 0 && inst < m.n_inst;
+  if (pt < n_pts && !valid && lane == 0 && cost) cost[pt] = __builtin_nan("");
+  if (lane == 0) s_inst[wid] = valid ? inst : -1;
+  __syncthreads();
+  UndMkt *um = reinterpret_cast<UndMkt *>(smem);
+  const NormLds L = norm_lds(m, smem + 6 * m.max_nu + (size_t)wid * lds_per_wave);
+  for (int r = 0; r < nw; ++r) {
+    const int ri = s_inst[r];
+    bool first = ri >= 0;
+    for (int q = 0; q < r; ++q) first = first && s_inst[q] != ri;
+    if (!first) continue;
+    const DevInst rin = m.inst[ri];
+    for (int u = threadIdx.x; u < rin.nu; u += blockDim.x) um[u] = und_mkt(m, rin.u0 + u);
+    __syncthreads();
+    if (valid && inst == ri) {
+      const DevInst in = m.inst[inst];
+      double p[kNormP], jr[kNormP], h[2];
+#pragma unroll
+      for (int k = 0; k < kNormP; ++k) p[k] = params[(size_t)pt * kNormP + k];
+      const double f = lmm_normal<FORMULA, RESID, REG>(m, in, um, p, L, jr, h);
+      const double gc = g_cost ? g_cost[pt] : 1.0;
+      if (lane == 0) {
+        if (cost) cost[pt] = f;
+#pragma unroll
+        for (int k = 0; k < kNormP; ++k) {
+          g_params[(size_t)pt * kNormP + k] = gc * (2.0 * jr[k]);
+          if (jtwr) jtwr[(size_t)pt * kNormP + k] = jr[k];
+        }
+      }
+      if (jtwj) scatter_jtwj(jtwj + (size_t)pt * kNormP * kNormP, h);
+    }
+    __syncthreads();
+  }
+}
+
+// Projected Levenberg-Marquardt (as lm_kernel) for LMM12 plans with the
+// normal equations of lmm_normal; one wave per point for all its
+// iterations, up to kGradWaves points per workgroup.
+template <int FORMULA, int RESID, int REG>
+__global__ __launch_bounds__(kWave *kGradWaves) void lm12_kernel(DevMarket m, int n_pts,
+                                                                 const int *pt_inst,
+                                                                 double *params, const double *lb,
+                                                                 const double *ub, int max_iter,
+                                                                 double mu0, double tol,
+                                                                 double *cost_out,
+                                                                 int *iters_out,
+                                                                 int lds_per_wave) {
+  extern __shared__ double smem[];
+  __shared__ int s_inst[kGradWaves];
+  constexpr int P = kNormP;
+  constexpr int CM = (REG == 24) ? 5 : 1;   // the cost kernels' model variant
+  const int nw = blockDim.x / kWave;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = lane_id();
+  const int pt = blockIdx.x * nw + wid;
+  int inst = -1;
+  if (pt < n_pts) inst = __builtin_amdgcn_readfirstlane(pt_inst[pt]);
+  const bool valid = pt < n_pts && inst >= 0 && inst < m.n_inst;
+  if (pt < n_pts && !valid && lane == 0) {
+    if (cost_out) cost_out[pt] = __builtin_nan("");
+    if (iters_out) iters_out[pt] = 0;
+  }
+  if (lane == 0) s_inst[wid] = valid ? inst : -1;
+  __syncthreads();
+  UndMkt *um = reinterpret_cast<UndMkt *>(smem);
+  const NormLds L = norm_lds(m, smem + 6 * m.max_nu + (size_t)wid * lds_per_wave);
+  for (int r = 0; r < nw; ++r) {
+    const int ri = s_inst[r];
+    bool first = ri >= 0;
+    for (int q = 0; q < r; ++q) first = first && s_inst[q] != ri;
+    if (!first) continue;
+    const DevInst rin = m.inst[ri];
+    for (int u = threadIdx.x; u < rin.nu; u += blockDim.x) um[u] = und_mkt(m, rin.u0 + u);
+    __syncthreads();
+    if (valid && inst == ri) {
+      const DevInst in = m.inst[inst];
+      // LDS: A (P x P, overwritten by its factor), rhs, solution, solved
+      // flag, J^T W r, box, J^T W J
+      double *A = L.sys, *rhs = A + P * P, *dl = rhs + P, *flag = dl + P;
+      double *gj = flag + P, *lo = gj + P, *hi = lo + P, *Hs = hi + P;
+      double p[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) p[k] = params[(size_t)pt * P + k];
+      if (lane < P) {
+        lo[lane] = lb[(size_t)inst * P + lane];
+        hi[lane] = ub[(size_t)inst * P + lane];
+      }
+      double f = kInf, mu = mu0;
+      int it = 0;
+      bool need = true, start = true;
+      // one call site each for the normal equations (at the start and after
+      // every accepted step) and for the trial cost
+      for (;;) {
+        if (need) {
+          double g[P], h[2];
+          const double fn = lmm_normal<FORMULA, RESID, REG>(m, in, um, p, L, g, h);
+          wave_lds_sync();
+          if (lane == 0)
+            for (int k = 0; k < P; ++k) gj[k] = g[k];
+          scatter_jtwj(Hs, h);
+          wave_lds_sync();
+          need = false;
+          if (start) {
+            start = false;
+            f = fn;
+            if (!(f < kInf)) break;
+          }
+        }
+        if (it >= max_iter) break;
+        // damped, frozen system from the stored J^T W J; lane 0 solves
+        if (lane == 0) {
+          for (int k = 0; k < P * P; ++k) A[k] = Hs[k];
+          for (int k = 0; k < P; ++k) {
+            const double akk = A[k * P + k];
+            A[k * P + k] = akk + mu * (akk > 0.0 ? akk : 1.0);
+            rhs[k] = -gj[k];
+          }
+          for (int k = 0; k < P; ++k) {
+            const bool frozen = (lo[k] == hi[k]) || (p[k] <= lo[k] && gj[k] > 0.0) ||
+                                (p[k] >= hi[k] && gj[k] < 0.0);
+            if (!frozen) continue;
+            for (int j = 0; j < P; ++j) A[k * P + j] = A[j * P + k] = 0.0;
+            A[k * P + k] = 1.0;
+            rhs[k] = 0.0;
+          }
+          flag[0] = cholesky_solve_lds<P>(A, rhs, dl) ? 1.0 : 0.0;
+        }
+        wave_lds_sync();
+        const bool solved = flag[0] != 0.0;
+        double trial[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+          double y = p[k] + dl[k];
+          if (y > hi[k]) y = hi[k];
+          if (y < lo[k]) y = lo[k];
+          trial[k] = y;
+        }
+        ++it;
+        bool accept = false, stop = false;
+        if (solved) {
+          const double ft = point_cost<CM, FORMULA, RESID>(m, in, um, trial, 0.0, L.w, nullptr,
+                                                            nullptr);
+          if (ft < f) {
+            const double rel = (f - ft) / f;
+            f = ft;
+            mu /= 10.0;
+            accept = true;
+            stop = rel < tol;
+          } else {
+            mu *= 10.0;
+            stop = mu > 1e16;
+          }
+        } else {
+          mu *= 10.0;
+        }
+        if (accept) {
+#pragma unroll
+          for (int k = 0; k < P; ++k) p[k] = trial[k];
+          need = true;
+        }
+        if (stop) break;
+        wave_lds_sync();   // the next pass overwrites A, rhs and dl
+      }
+      if (lane == 0) {
+        for (int k = 0; k < P; ++k) params[(size_t)pt * P + k] = p[k];
+        if (cost_out) cost_out[pt] = f;
+        if (iters_out) iters_out[pt] = it;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Launch wrappers
 // ---------------------------------------------------------------------------
-#define SABR_SELECT3(MODEL_, FORMULA_, RESID_, CALL)                  \
-  do {                                                                \
-    if ((MODEL_) == 0) {                                              \
-      if ((FORMULA_) == 0) {                                          \
-        if ((RESID_) == 0) { CALL(0, 0, 0); } else { CALL(0, 0, 1); } \
-      } else {                                                        \
-        if ((RESID_) == 0) { CALL(0, 1, 0); } else { CALL(0, 1, 1); } \
-      }                                                               \
-    } else {                                                          \
-      if ((FORMULA_) == 0) {                                          \
-        if ((RESID_) == 0) { CALL(1, 0, 0); } else { CALL(1, 0, 1); } \
-      } else {                                                        \
-        if ((RESID_) == 0) { CALL(1, 1, 0); } else { CALL(1, 1, 1); } \
-      }                                                               \
-    }                                                                 \
+#define SABR_SELECT_FR(FORMULA_, RESID_, CALL)                      \
+  do {                                                              \
+    if ((FORMULA_) == 0) {                                          \
+      if ((RESID_) == 0) { CALL(0, 0); } else { CALL(0, 1); }       \
+    } else {                                                        \
+      if ((RESID_) == 0) { CALL(1, 0); } else { CALL(1, 1); }       \
+    }                                                               \
   } while (0)
 
+// LDS of the GLOBAL4 vjp and LM kernels: the market values and the LM system.
 size_t adjoint_lds_bytes(const DevMarket &m) {
-  const int P = m.model == 0 ? 4 : 12;
-  return (size_t)(6 * m.max_nu + wave_lds_doubles(m, true) + 2 * m.max_nf +
-                  (m.model == 1 ? 5 * m.max_len * kWave : 0) + P * P + 3 * P) *
-         8;
-}
-
-size_t adjoint_scratch_bytes(const DevMarket &m, int n_waves) {
-  return m.model == 1 ? (size_t)n_waves * m.max_nu * 36 * 8 : 0;
+  constexpr int P = 4;
+  return (size_t)(6 * m.max_nu + P * P + 3 * P) * 8;
 }
 
 int adjoint_waves(int n_pts) { return n_pts < kAdjointMaxWaves ? n_pts : kAdjointMaxWaves; }
@@ -1119,6 +1331,72 @@ int grad_waves(const DevMarket &m) {
     }
   }
   return best;
+}
+
+// Waves per workgroup of the normal-equation kernels, by the same rule.
+int norm_waves(const DevMarket &m) {
+  const long per_cu = 160 * 1024;
+  int best = 0, best_res = 0;
+  for (int w = kGradWaves; w >= 1; w >>= 1) {
+    const long bytes = (long)(6 * m.max_nu + (long)w * norm_wave_doubles(m)) * 8;
+    if (bytes > lds_budget_bytes()) continue;
+    const int res = (int)std::min<long>(per_cu / bytes * w, 16);
+    if (res > best_res) {
+      best_res = res;
+      best = w;
+    }
+  }
+  return best;
+}
+
+#define SABR_REG_SELECT(LAUNCH, B, C)   \
+  do {                                 \
+    if (m.max_len <= kMapRegLen)       \
+      LAUNCH(B, C, 16);                \
+    else if (m.max_len <= 24)          \
+      LAUNCH(B, C, 24);                \
+    else                               \
+      LAUNCH(B, C, 0);                 \
+  } while (0)
+#define SABR_FR_SELECT(LAUNCH)                                                  \
+  do {                                                                          \
+    if (m.formula == 0) {                                                       \
+      if (m.residual == 0) SABR_REG_SELECT(LAUNCH, 0, 0); else SABR_REG_SELECT(LAUNCH, 0, 1); \
+    } else {                                                                    \
+      if (m.residual == 0) SABR_REG_SELECT(LAUNCH, 1, 0); else SABR_REG_SELECT(LAUNCH, 1, 1); \
+    }                                                                           \
+  } while (0)
+
+hipError_t launch_normal(const DevMarket &m, int n_pts, const int *pt_inst, const double *params,
+                         const double *g_cost, double *cost, double *g_params, double *jtwj,
+                         double *jtwr, hipStream_t s) {
+  const int waves = norm_waves(m);
+  if (waves == 0) return hipErrorInvalidValue;
+  const int ld = norm_wave_doubles(m);
+  const size_t lds = (size_t)(6 * m.max_nu + waves * ld) * 8;
+  const dim3 grid((n_pts + waves - 1) / waves), block(kWave * waves);
+#define LAUNCH(B, C, R)                                                                       \
+  hipLaunchKernelGGL((normal_kernel<B, C, R>), grid, block, lds, s, m, n_pts, pt_inst, params, \
+                     g_cost, cost, g_params, jtwj, jtwr, ld)
+  SABR_FR_SELECT(LAUNCH);
+#undef LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_lm12(const DevMarket &m, int n_pts, const int *pt_inst, double *params,
+                       const double *lb, const double *ub, int max_iter, double mu0, double tol,
+                       double *cost_out, int *iters_out, hipStream_t s) {
+  const int waves = norm_waves(m);
+  if (waves == 0) return hipErrorInvalidValue;
+  const int ld = norm_wave_doubles(m);
+  const size_t lds = (size_t)(6 * m.max_nu + waves * ld) * 8;
+  const dim3 grid((n_pts + waves - 1) / waves), block(kWave * waves);
+#define LAUNCH(B, C, R)                                                                     \
+  hipLaunchKernelGGL((lm12_kernel<B, C, R>), grid, block, lds, s, m, n_pts, pt_inst, params, \
+                     lb, ub, max_iter, mu0, tol, cost_out, iters_out, ld)
+  SABR_FR_SELECT(LAUNCH);
+#undef LAUNCH
+  return hipGetLastError();
 }
 
 hipError_t launch_grad(const DevMarket &m, int n_pts, const int *pt_inst, const double *params,
@@ -1153,39 +1431,45 @@ hipError_t launch_grad(const DevMarket &m, int n_pts, const int *pt_inst, const 
 
 hipError_t launch_vjp(const DevMarket &m, int n_pts, const int *pt_inst, const double *params,
                       const double *g_cost, double *cost, double *g_params, double *jtwj,
-                      double *jtwr, double *scratch, hipStream_t s) {
+                      double *jtwr, hipStream_t s) {
   if (n_pts == 0) return hipSuccess;
   if (m.model != 0 && m.model != 1) return hipErrorInvalidValue;   // GLOBAL4 and LMM12 only
-  // LMM12 gradient (no J^T W J): per-underlying seeds and one map sweep each
+  // LMM12: per-underlying seeds and map sweeps (the gradient alone: one
+  // sweep each; with J^T W J: the three rows of M_u)
   if (m.model == 1 && !jtwj)
     return launch_grad(m, n_pts, pt_inst, params, g_cost, cost, g_params, jtwr, s);
+  if (m.model == 1)
+    return launch_normal(m, n_pts, pt_inst, params, g_cost, cost, g_params, jtwj, jtwr, s);
   const size_t lds = adjoint_lds_bytes(m);
   const int waves = adjoint_waves(n_pts);
-#define CALL(A, B, C)                                                                        \
+#define CALL(B, C)                                                                           \
   do {                                                                                       \
     if (jtwj)                                                                                \
-      hipLaunchKernelGGL((vjp_kernel<A, B, C, true>), dim3(waves), dim3(kWave), lds, s, m,   \
-                         n_pts, pt_inst, params, g_cost, cost, g_params, jtwj, jtwr, scratch); \
+      hipLaunchKernelGGL((vjp_kernel<B, C, true>), dim3(waves), dim3(kWave), lds, s, m,      \
+                         n_pts, pt_inst, params, g_cost, cost, g_params, jtwj, jtwr);          \
     else                                                                                     \
-      hipLaunchKernelGGL((vjp_kernel<A, B, C, false>), dim3(waves), dim3(kWave), lds, s, m,  \
-                         n_pts, pt_inst, params, g_cost, cost, g_params, jtwj, jtwr, scratch); \
+      hipLaunchKernelGGL((vjp_kernel<B, C, false>), dim3(waves), dim3(kWave), lds, s, m,     \
+                         n_pts, pt_inst, params, g_cost, cost, g_params, jtwj, jtwr);          \
   } while (0)
-  SABR_SELECT3(m.model, m.formula, m.residual, CALL);
+  SABR_SELECT_FR(m.formula, m.residual, CALL);
 #undef CALL
   return hipGetLastError();
 }
 
 hipError_t launch_lm(const DevMarket &m, int n_pts, const int *pt_inst, double *params,
                      const double *lb, const double *ub, int max_iter, double mu0, double tol,
-                     double *cost_out, int *iters_out, double *scratch, hipStream_t s) {
+                     double *cost_out, int *iters_out, hipStream_t s) {
   if (n_pts == 0) return hipSuccess;
   if (m.model != 0 && m.model != 1) return hipErrorInvalidValue;   // GLOBAL4 and LMM12 only
+  if (m.model == 1)
+    return launch_lm12(m, n_pts, pt_inst, params, lb, ub, max_iter, mu0, tol, cost_out,
+                       iters_out, s);
   const size_t lds = adjoint_lds_bytes(m);
   const int waves = adjoint_waves(n_pts);
-#define CALL(A, B, C)                                                                       \
-  hipLaunchKernelGGL((lm_kernel<A, B, C>), dim3(waves), dim3(kWave), lds, s, m, n_pts, pt_inst, \
-                     params, lb, ub, max_iter, mu0, tol, cost_out, iters_out, scratch)
-  SABR_SELECT3(m.model, m.formula, m.residual, CALL);
+#define CALL(B, C)                                                                          \
+  hipLaunchKernelGGL((lm_kernel<B, C>), dim3(waves), dim3(kWave), lds, s, m, n_pts, pt_inst,   \
+                     params, lb, ub, max_iter, mu0, tol, cost_out, iters_out)
+  SABR_SELECT_FR(m.formula, m.residual, CALL);
 #undef CALL
   return hipGetLastError();
 }

@@ -6,23 +6,21 @@
 
 namespace sabr {
 
-// Waves of the persistent adjoint / LM grid; each owns one slot of the
-// M_u scratch (max_nu x 36 doubles, LMM12 only).
+// Waves of the GLOBAL4 adjoint / LM grid (one wave per point, grid-stride).
 constexpr int kAdjointMaxWaves = 2048;
 
-size_t adjoint_scratch_bytes(const DevMarket &m, int n_waves);
-// Largest LDS allocation of one workgroup on the current device (bytes).
-int lds_budget_bytes();
 int adjoint_waves(int n_pts);
 size_t adjoint_lds_bytes(const DevMarket &m);
+// Largest LDS allocation of one workgroup on the current device (bytes).
+int lds_budget_bytes();
 
 hipError_t launch_vjp(const DevMarket &m, int n_pts, const int *pt_inst, const double *params,
                       const double *g_cost, double *cost, double *g_params, double *jtwj,
-                      double *jtwr, double *scratch, hipStream_t s);
+                      double *jtwr, hipStream_t s);
 
 hipError_t launch_lm(const DevMarket &m, int n_pts, const int *pt_inst, double *params,
                      const double *lb, const double *ub, int max_iter, double mu0, double tol,
-                     double *cost_out, int *iters_out, double *scratch, hipStream_t s);
+                     double *cost_out, int *iters_out, hipStream_t s);
 
 // Nelder-Mead: one wave per point, the simplex in LDS.
 size_t nm_lds_bytes(const DevMarket &m);

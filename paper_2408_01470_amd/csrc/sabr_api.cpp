@@ -747,21 +747,17 @@ sabr_status sa_calibrate_noalloc(const sabr_plan *Pc, const sa_config *cfg,
 // ---------------------------------------------------------------------------
 namespace {
 
+// Device workspace of the LM polish: the box tables (the adjoint needs none).
 struct AdjLayout {
-  size_t o_lb, o_ub, o_scratch, total;
+  size_t o_lb, o_ub, total;
 };
 
-AdjLayout adj_layout(const sabr_plan *P, int n_pts) {
+AdjLayout adj_layout(const sabr_plan *P) {
   AdjLayout A{};
   Layout L;
   const int Pn = P->np;
   A.o_lb = L.take<double>((size_t)P->n_inst * Pn);
   A.o_ub = L.take<double>((size_t)P->n_inst * Pn);
-  DevMarket shape{};
-  shape.model = P->model;
-  shape.np = P->np;
-  shape.max_nu = P->max_nu;
-  A.o_scratch = L.take<unsigned char>(sabr::adjoint_scratch_bytes(shape, sabr::adjoint_waves(n_pts)));
   A.total = L.off;
   return A;
 }
@@ -779,7 +775,7 @@ extern "C" {
 
 size_t sabr_adjoint_workspace_size(const sabr_plan *P, int32_t n_pts) {
   if (!P || n_pts < 0) return 0;
-  return adj_layout(P, n_pts).total;
+  return adj_layout(P).total;
 }
 
 sabr_status sabr_cost_vjp(const sabr_plan *P, int32_t n_pts, const int32_t *pt_inst,
@@ -791,13 +787,10 @@ sabr_status sabr_cost_vjp(const sabr_plan *P, int32_t n_pts, const int32_t *pt_i
   if (n_pts == 0) return SABR_OK;
   if (!pt_inst || !params || !g_params) return fail(SABR_EINVAL, "null pt_inst, params or g_params");
   if (P->model >= 2) return fail(SABR_EUNSUPPORTED, "the adjoint takes GLOBAL4 and LMM12 plans");
-  const AdjLayout A = adj_layout(P, n_pts);
-  if (A.total > 0 && (!workspace || ws_bytes < A.total))
-    return fail(SABR_EWORKSPACE, "workspace too small");
-  char *w = static_cast<char *>(workspace);
+  (void)workspace;   // no device scratch: the kernels keep everything in LDS
+  (void)ws_bytes;
   hipError_t e = sabr::launch_vjp(P->dm, n_pts, pt_inst, params, g_cost, cost, g_params, jtwj,
-                                  jtwr, w ? reinterpret_cast<double *>(w + A.o_scratch) : nullptr,
-                                  static_cast<hipStream_t>(stream));
+                                  jtwr, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "adjoint launch");
   return SABR_OK;
 }
@@ -817,21 +810,21 @@ sabr_status sabr_lm_polish(const sabr_plan *Pc, int32_t n_pts, const int32_t *pt
   for (int i = 0; i < P->n_inst * Pn; ++i)
     if (!std::isfinite(lb[i]) || !std::isfinite(ub[i]) || !(lb[i] <= ub[i]))
       return fail(SABR_EINVAL, "box bound " + std::to_string(i) + ": need finite lb <= ub");
-  const AdjLayout A = adj_layout(P, n_pts);
+  const AdjLayout A = adj_layout(P);
   if (!workspace || ws_bytes < A.total) return fail(SABR_EWORKSPACE, "workspace too small");
   if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(SABR_EINVAL, "workspace not 256-byte aligned");
   char *w = static_cast<char *>(workspace);
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> guard(P->mu);
   std::vector<unsigned char> &stg = P->lm_staging;
-  stg.assign(A.o_scratch, 0);
+  stg.assign(A.total, 0);
   std::memcpy(stg.data() + A.o_lb, lb, sizeof(double) * P->n_inst * Pn);
   std::memcpy(stg.data() + A.o_ub, ub, sizeof(double) * P->n_inst * Pn);
-  hipError_t e = hipMemcpyAsync(w, stg.data(), A.o_scratch, hipMemcpyHostToDevice, s);
+  hipError_t e = hipMemcpyAsync(w, stg.data(), A.total, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "LM box upload");
   e = sabr::launch_lm(P->dm, n_pts, pt_inst, params, reinterpret_cast<const double *>(w + A.o_lb),
                       reinterpret_cast<const double *>(w + A.o_ub), max_iter, mu0, tol, cost_out,
-                      iters_out, reinterpret_cast<double *>(w + A.o_scratch), s);
+                      iters_out, s);
   if (e != hipSuccess) return hip_fail(e, "LM launch");
   return SABR_OK;
 }
