@@ -4,11 +4,12 @@
 // Each kernel evaluates one function once per thread over n inputs drawn
 // from the ranges the cost kernels see (the device library's exp, log1p,
 // sqrt and division, and the kernels' own erfcx, exp, log1p, sqrt and
-// reciprocal); under
+// reciprocal, and the exp + erfcx pair of the Black price); under
 //   rocprofv3 --pmc SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64
 //                   SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64
 // the FP64 FLOP per call is 64 (ADD + MUL + TRANS + 2 FMA) / n minus the
-// identical counts of the "copy" kernel (load, store, no arithmetic).
+// identical counts of the "copy" kernel (load, store, no arithmetic).  The
+// last kernel adds its three results (2 FLOP beyond the call).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -42,7 +43,12 @@ __global__ void elem_kernel(const double *__restrict__ x, const double *__restri
   else if (FN == 6) r = sabr::exp_cw(a);
   else if (FN == 7) r = sabr::log1p_tang(a);
   else if (FN == 8) r = sabr::sqrt_gs(a);
-  else r = a * sabr::rcp_nr(b);
+  else if (FN == 9) r = a * sabr::rcp_nr(b);
+  else {
+    double E, X1, X2;
+    sabr::exp_erfcx2(-a, a, b, E, X1, X2);
+    r = E + X1 + X2;
+  }
   out[i] = r;
 }
 
@@ -50,12 +56,12 @@ int main() {
   const int n = 1 << 20;
   // inputs per function: exp in [-12, 0], log1p in [-0.6, 1.5], sqrt in
   // [0.2, 4], div in [0.1, 10]/[0.1, 10], erfcx in [0, 8]; the library
-  // functions (1-4), then the kernels' own (5-9)
-  constexpr int NF = 10;
-  const double lo[NF] = {0.0, -12.0, -0.6, 0.2, 0.1, 0.0, -12.0, -0.6, 0.2, 0.1};
-  const double hi[NF] = {1.0, 0.0, 1.5, 4.0, 10.0, 8.0, 0.0, 1.5, 4.0, 10.0};
-  const char *names[NF] = {"copy", "exp", "log1p", "sqrt", "div",
-                           "erfcx_pos", "exp_cw", "log1p_tang", "sqrt_gs", "rcp_nr*x"};
+  // functions (1-4), then the kernels' own (5-10)
+  constexpr int NF = 11;
+  const double lo[NF] = {0.0, -12.0, -0.6, 0.2, 0.1, 0.0, -12.0, -0.6, 0.2, 0.1, 0.0};
+  const double hi[NF] = {1.0, 0.0, 1.5, 4.0, 10.0, 8.0, 0.0, 1.5, 4.0, 10.0, 8.0};
+  const char *names[NF] = {"copy",   "exp",        "log1p",   "sqrt",     "div",       "erfcx_pos",
+                           "exp_cw", "log1p_tang", "sqrt_gs", "rcp_nr*x", "exp_erfcx2"};
   double *dx, *dy, *dout;
   CHECK(hipMalloc(&dx, n * sizeof(double)));
   CHECK(hipMalloc(&dy, n * sizeof(double)));
@@ -88,7 +94,8 @@ int main() {
       case 6: hipLaunchKernelGGL(elem_kernel<6>, grid, block, 0, 0, dx, dy, dout, n); break;
       case 7: hipLaunchKernelGGL(elem_kernel<7>, grid, block, 0, 0, dx, dy, dout, n); break;
       case 8: hipLaunchKernelGGL(elem_kernel<8>, grid, block, 0, 0, dx, dy, dout, n); break;
-      default: hipLaunchKernelGGL(elem_kernel<9>, grid, block, 0, 0, dx, dy, dout, n); break;
+      case 9: hipLaunchKernelGGL(elem_kernel<9>, grid, block, 0, 0, dx, dy, dout, n); break;
+      default: hipLaunchKernelGGL(elem_kernel<10>, grid, block, 0, 0, dx, dy, dout, n); break;
     }
     CHECK(hipGetLastError());
     CHECK(hipDeviceSynchronize());

@@ -261,9 +261,9 @@ __device__ __forceinline__ double exp_neg(double x) {
 
 // log1p(t) for t > -1 (method of log1p_poly.hpp): v = 1 + t rounded with its
 // exact error e (two-sum), v = 2^k m with m in [sqrt(1/2), sqrt(2)),
-// f = m - 1, s = f/(2 + f), log m = f - s (f - s^2 P(s^2)), and
-// log1p(t) = k ln2 + log m + e/v.  NaN for t <= -1, t = +inf or NaN t;
-// branch-free.
+// f = (m - 1) + e 2^-k (so 1 + f = (1 + t)/2^k), s = f/(2 + f),
+// log(1 + f) = f - s (f - s^2 P(s^2)), and log1p(t) = k ln2 + log(1 + f).
+// NaN for t <= -1, t = +inf or NaN t; branch-free.
 __device__ __forceinline__ double log1p_tang(double t) {
   const double v = 1.0 + t;
   const double vv = v - 1.0;
@@ -273,15 +273,15 @@ __device__ __forceinline__ double log1p_tang(double t) {
   const bool up = m < M_SQRT1_2;
   m = up ? m + m : m;
   k = up ? k - 1 : k;
-  const double f = m - 1.0;
+  // 1 + t = 2^k (m + e 2^-k) exactly: the rounding error of v joins f (it is
+  // below 2^-53 of m, so f's own rounding stays relative to f)
+  const double f = (m - 1.0) + ldexp(e, -k);
   const double s = f * rcp_nr(2.0 + f);
   const double z = s * s;
   const double p = horner_s<kLog1pPoly, kLog1pDeg>(z);
   const double lf = fma(-s, fma(-z, p, f), f);
-  double rv = __builtin_amdgcn_rcp(v);   // e/v is below 2^-53 |v|: one step suffices
-  rv = fma(rv, fma(-v, rv, 1.0), rv);
   const double kd = (double)k;
-  const double res = fma(kd, kLn2Hi, lf + fma(kd, kLn2Lo, e * rv));
+  const double res = fma(kd, kLn2Hi, lf + kd * kLn2Lo);
   return v > 0.0 ? res : __builtin_nan("");
 }
 
@@ -347,7 +347,10 @@ __device__ __forceinline__ void exp_erfcx2(double xe, double x1, double x2, doub
   r = fma(-kd, kExpLn2Lo, r);
   x1 = fmin(x1, 1e100);
   x2 = fmin(x2, 1e100);
-  const double r1 = rcp_nr(x1 + kErfcxK), r2 = rcp_nr(x2 + kErfcxK);
+  // one reciprocal for both: 1/a1 = a2/(a1 a2), 1/a2 = a1/(a1 a2)
+  const double a1 = x1 + kErfcxK, a2 = x2 + kErfcxK;
+  const double ip = rcp_nr(a1 * a2);
+  const double r1 = a2 * ip, r2 = a1 * ip;
   double h1, h2, he;
   horner3_s<kErfcxPoly, kErfcxDeg, kExpPoly, kExpDeg>((x1 - kErfcxK) * r1, (x2 - kErfcxK) * r2, r,
                                                        h1, h2, he,

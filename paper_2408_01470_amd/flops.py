@@ -21,12 +21,18 @@ import numpy as np
 
 # FP64 FLOP per call (confirmed by the counters of the pricing program).
 #   exp   : x/ln2, two-step Cody-Waite reduction, degree-11 Horner      1+4+22
-#   log1p : two-sum, reduction, reciprocal, degree-6 Horner in s^2, sum    45
+#   log1p : two-sum (6), m + m (1), f with the two-sum's error (2),
+#           s = f/(2 + f) (9), s^2 (1), degree-6 Horner (12), the two fma
+#           (4), k ln2 (4)                                                  39
 #   sqrt  : rsq seed, one Goldschmidt pass, final correction          1+2+10
 #   rcp   : rcp seed, r0 + r0 (e + e^2)                                  1+6
 #   erfcx : x +- K, reciprocal, degree-24 Horner, scale              2+7+48+2
+#   erfcx2: a pair sharing one reciprocal of the product (the two
+#           arguments' x +- K 4, product 1, reciprocal 7, the two
+#           reciprocals 2, t 2, Horner 96, scales 2)                      114
 #   div   : device library division                                        14
-ELEMENTARY = {"exp": 27.0, "log1p": 45.0, "sqrt": 13.0, "rcp": 7.0, "erfcx": 59.0, "div": 14.0}
+ELEMENTARY = {"exp": 27.0, "log1p": 39.0, "sqrt": 13.0, "rcp": 7.0, "erfcx": 59.0,
+              "erfcx2": 114.0, "div": 14.0}
 
 
 def _e(name, n=1):
@@ -79,8 +85,8 @@ def black_quote(direct: bool = False) -> float:
     reciprocal when the formula gives sigma itself), then the Black-76
     out-of-the-money price: sd, d1, d2 (6), E = exp(-d1^2/2) (2), the two
     erfcx arguments (2), f E/2 (2), the combination (3) and the discount
-    (1)."""
-    return (1 if direct else 5) + _e("rcp") + 16 + _e("exp") + _e("erfcx", 2)
+    (1); the two erfcx share one reciprocal (erfcx2)."""
+    return (1 if direct else 5) + _e("rcp") + 16 + _e("exp") + _e("erfcx2")
 
 
 RESIDUAL = 4.0   # r = m - target, acc += (w r) r
