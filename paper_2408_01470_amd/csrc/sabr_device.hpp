@@ -191,24 +191,47 @@ __device__ __forceinline__ double fma_s(double h, double t, double c) {
 }
 
 // Horner's rule on the coefficients C[0..DEG] (constant arrays), one chain
-// or two interleaved chains sharing each coefficient.
+// or two interleaved chains sharing each coefficient.  Each step's
+// coefficient is materialized one step ahead: a vector instruction may not
+// read a scalar register the instruction just before it wrote (the hardware
+// then needs a wait state, one s_nop per step).
+template <const double *C, int DEG, size_t I>
+__device__ __forceinline__ double next_coef(double c) {
+  if constexpr (I + 1 < DEG) return SABR_SCONST(C[DEG - 2 - I]);
+  return c;
+}
+template <const double *C, int DEG, size_t I>
+__device__ __forceinline__ void horner_step(double t, double &h, double &c) {
+  const double cn = next_coef<C, DEG, I>(c);
+  h = fma_s(h, t, c);
+  c = cn;
+}
 template <const double *C, int DEG, size_t... I>
 __device__ __forceinline__ double horner_s(double t, std::index_sequence<I...>) {
   double h = SABR_SCONST(C[DEG]);
-  ((h = fma_s(h, t, SABR_SCONST(C[DEG - 1 - I]))), ...);
+  double c = SABR_SCONST(C[DEG - 1]);
+  (horner_step<C, DEG, I>(t, h, c), ...);
   return h;
 }
 template <const double *C, int DEG>
 __device__ __forceinline__ double horner_s(double t) {
   return horner_s<C, DEG>(t, std::make_index_sequence<DEG>{});
 }
+template <const double *C, int DEG, size_t I>
+__device__ __forceinline__ void horner2_step(double t1, double t2, double &h1, double &h2,
+                                             double &c) {
+  const double cn = next_coef<C, DEG, I>(c);
+  h1 = fma_s(h1, t1, c);
+  h2 = fma_s(h2, t2, c);
+  c = cn;
+}
 template <const double *C, int DEG, size_t... I>
 __device__ __forceinline__ void horner2_s(double t1, double t2, double &h1, double &h2,
                                           std::index_sequence<I...>) {
-  double c = SABR_SCONST(C[DEG]);
-  h1 = c;
-  h2 = c;
-  ((c = SABR_SCONST(C[DEG - 1 - I]), h1 = fma_s(h1, t1, c), h2 = fma_s(h2, t2, c)), ...);
+  h1 = SABR_SCONST(C[DEG]);
+  h2 = h1;
+  double c = SABR_SCONST(C[DEG - 1]);
+  (horner2_step<C, DEG, I>(t1, t2, h1, h2, c), ...);
 }
 
 // 1/d for a normal, finite d.  The v_rcp_f64 seed r0 has a relative error
@@ -300,28 +323,32 @@ __device__ __forceinline__ double erfcx_pos(double x) {
 // One step of three interleaved Horner chains: step I of the two chains on
 // C (degree DEG) and, over its last DEG2 steps, of a third chain on C2
 // (degree DEG2 <= DEG).  The coefficients reach the scalar registers in
-// program order, so the interleaving is written out here rather than left
-// to the scheduler.
+// program order, one step ahead of their use (see horner_step), so the
+// interleaving is written out here rather than left to the scheduler.
 template <const double *C, int DEG, const double *C2, int DEG2, size_t I>
 __device__ __forceinline__ void horner3_step(double t1, double t2, double t3, double &h1,
-                                             double &h2, double &h3) {
-  const double c = SABR_SCONST(C[DEG - 1 - I]);
+                                             double &h2, double &h3, double &c, double &c2) {
+  const double cn = next_coef<C, DEG, I>(c);
+  // the third chain's step J = I - (DEG - DEG2) uses C2[DEG2 - 1 - J]; its
+  // first coefficient is materialized with the step before its first use
+  double c2n = c2;
+  if constexpr (I + 1 + DEG2 == DEG) c2n = SABR_SCONST(C2[DEG2 - 1]);
+  if constexpr (I + DEG2 >= DEG && I + 1 < DEG) c2n = SABR_SCONST(C2[DEG - 2 - I]);
   h1 = fma_s(h1, t1, c);
   h2 = fma_s(h2, t2, c);
-  if constexpr (I + DEG2 >= DEG) {
-    const double c2 = SABR_SCONST(C2[DEG - 1 - I]);
-    h3 = fma_s(h3, t3, c2);
-  }
+  if constexpr (I + DEG2 >= DEG) h3 = fma_s(h3, t3, c2);
+  c = cn;
+  c2 = c2n;
 }
 template <const double *C, int DEG, const double *C2, int DEG2, size_t... I>
 __device__ __forceinline__ void horner3_s(double t1, double t2, double t3, double &h1, double &h2,
                                           double &h3, std::index_sequence<I...>) {
-  static_assert(DEG2 <= DEG, "the third chain rides along the last steps");
-  const double c = SABR_SCONST(C[DEG]);
-  h1 = c;
-  h2 = c;
+  static_assert(DEG2 < DEG, "the third chain rides along the last steps");
+  h1 = SABR_SCONST(C[DEG]);
+  h2 = h1;
   h3 = SABR_SCONST(C2[DEG2]);
-  (horner3_step<C, DEG, C2, DEG2, I>(t1, t2, t3, h1, h2, h3), ...);
+  double c = SABR_SCONST(C[DEG - 1]), c2 = 0.0;
+  (horner3_step<C, DEG, C2, DEG2, I>(t1, t2, t3, h1, h2, h3, c, c2), ...);
 }
 
 // erfcx_pos of two arguments, the two polynomial chains interleaved.
@@ -395,11 +422,12 @@ constexpr double kZSeries = 0x1.0p-18;
 // D1 = 1 + (1-b)^2 L^2/24 + (1-b)^4 L^4/1920 and expiry T, as a fraction
 //   sigma = numer / denom,  numer = alpha corr q^2 chi_num,
 //                           denom = q^3 D1 chi_den,
-// with chi = z/x(z) = chi_num/chi_den.  x(z) = log1p(t), t = num/den chosen so
+// with chi = z/x(z) = chi_num/chi_den.  s = sqrt(1 - 2 rho z + z^2) is
+// unchanged and x(z) changes sign under (z, rho) -> (-z, -rho), so with
+// a = |z| and r = sign(z) rho, chi = a / log1p(t) with t = num/den chosen so
 // that neither num nor den cancels:
-//   |z| <= 1:  t = 2z / (s + 1 - z)
-//   z  >  1:   t = (s + z - 1) / (1 - rho)
-//   z  < -1:   t = (1 + z - s) / (s - z + rho),      s = sqrt(1 - 2 rho z + z^2);
+//   a <= 1:  t = 2a / (s + (1 - a))
+//   a >  1:  t = (s + (a - 1)) / (1 - r);
 // for |z| < kZSeries the series replaces the quotient (removable singularity
 // at z = 0).
 struct VolFrac {
@@ -412,9 +440,9 @@ __device__ __forceinline__ VolFrac hagan2002_frac(const SabrConst &k, double L, 
   const double s = sqrt_gs(fma(z, z - 2.0 * k.rho, 1.0));
   const double az = fabs(z);
   const bool mid = az <= 1.0;
-  const double num = mid ? 2.0 * z : (z > 0.0 ? (s + z) - 1.0 : (1.0 + z) - s);
-  const double den = mid ? (s + 1.0) - z : (z > 0.0 ? 1.0 - k.rho : (s - z) + k.rho);
-  double cn = z, cd = log1p_tang(num * rcp_nr(den));   // chi = cn / cd
+  const double num = mid ? 2.0 * az : s + (az - 1.0);
+  const double den = mid ? s + (1.0 - az) : fma(-copysign(1.0, z), k.rho, 1.0);
+  double cn = az, cd = log1p_tang(num * rcp_nr(den));   // chi = cn / cd
   if (az < kZSeries) {   // rare: the series, with (2 - 3 rho^2)/12 = 1/6 - rho^2/4
     cn = fma(z, fma(z, fma(-0.25, k.rho * k.rho, 1.0 / 6.0), -0.5 * k.rho), 1.0);
     cd = 1.0;
