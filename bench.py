@@ -60,6 +60,8 @@ def parse():
                     help="fixed waves per workgroup of the level kernel (skips the autotuner)")
     ap.add_argument("--occupancy", type=int, default=None,
                     help="fixed register budget in waves per SIMD (with --waves)")
+    ap.add_argument("--waves-per-chain", type=int, default=1,
+                    help="fixed waves per chain (with --waves; > 1 splits each chain's quotes)")
     return ap.parse_args()
 
 
@@ -223,7 +225,8 @@ def measured_traffic(config, shape):
     for rec in (recs if isinstance(recs, list) else [recs]):
         if (rec.get("source_sha256") == digest
                 and rec.get("waves_per_group") == shape.get("waves_per_group")
-                and rec.get("occupancy") == shape.get("occupancy")):
+                and rec.get("occupancy") == shape.get("occupancy")
+                and rec.get("waves_per_chain", 1) == shape.get("waves_per_chain", 1)):
             return float(rec["traffic_bytes_per_launch"])
     return None
 
@@ -255,8 +258,10 @@ def time_to_rmse(api, W, I, autotune):
     shape = {}
     if autotune:
         from paper_2408_01470_amd import autotune as AT
-        t = AT.tune(plan, w.chains, lb, ub, w.n_steps)
-        shape = dict(waves=t["waves"], occupancy=t["occupancy"])
+        t = AT.tune(plan, w.chains, lb, ub, w.n_steps,
+                    candidates=AT.CANDIDATES + AT.split_candidates(plan, w.chains))
+        shape = dict(waves=t["waves"], occupancy=t["occupancy"],
+                     waves_per_chain=t["waves_per_chain"])
     kw = dict(T0=T0, n_steps=w.n_steps, seed=w.seed, step_frac=w.step_frac, **shape)
     k = w.extra["polish"]
 
@@ -318,6 +323,7 @@ def time_to_rmse(api, W, I, autotune):
         "at_polished_rmse": ratios,
         "plain_rmse_vs_time": curve,
         "speedup": tp / th,
+        "launch_shape": shape,
     }
 
 
@@ -591,13 +597,15 @@ def measure_sa(api, W, I, flops, config, steps, warmup, autotune=True, fixed_sha
               step_frac=w.step_frac, T0_per_inst=T0s, trace=True)
     tuned = None
     if fixed_shape is not None:
-        kw.update(waves=fixed_shape["waves"], occupancy=fixed_shape["occupancy"])
+        kw.update(waves=fixed_shape["waves"], occupancy=fixed_shape["occupancy"],
+                  waves_per_chain=fixed_shape.get("waves_per_chain", 1))
     elif autotune:
         from paper_2408_01470_amd import autotune as AT
-        cand = TUNE_CANDIDATES.get(config, AT.CANDIDATES)
+        cand = TUNE_CANDIDATES.get(config, AT.CANDIDATES + AT.split_candidates(plan, w.chains))
         tuned = AT.tune(plan, w.chains, lb, ub, w.n_steps, levels=3 if config == "c5" else 4,
                         candidates=cand)
-        kw.update(waves=tuned["waves"], occupancy=tuned["occupancy"])
+        kw.update(waves=tuned["waves"], occupancy=tuned["occupancy"],
+                  waves_per_chain=tuned["waves_per_chain"])
     L = w.n_levels
     sampled = list(range(0, L, EVENT_STRIDE))
 
@@ -647,7 +655,8 @@ def measure_sa(api, W, I, flops, config, steps, warmup, autotune=True, fixed_sha
     flop_launch = flops.level_launch_flops(mk, w.chains, w.n_steps)
     achieved = flop_launch / avg_launch_s / 1e12
     best_f = results[-1]["best_f"].cpu().numpy()
-    shape = {"waves_per_group": kw.get("waves", 0), "occupancy": kw.get("occupancy", 0)}
+    shape = {"waves_per_group": kw.get("waves", 0), "occupancy": kw.get("occupancy", 0),
+             "waves_per_chain": max(1, kw.get("waves_per_chain", 1))}
     return {
         "workload": w.name,
         "value": qe / (ms_per_step / 1e3),
@@ -705,7 +714,8 @@ def main():
     if args.adjoint_only:
         print(json.dumps(cost_and_adjoint(api, W, I, args.adjoint_config)))
         return
-    fixed_shape = (dict(waves=args.waves, occupancy=args.occupancy or 1)
+    fixed_shape = (dict(waves=args.waves, occupancy=args.occupancy or 1,
+                        waves_per_chain=args.waves_per_chain)
                    if args.waves is not None else None)
     if args.paper_e2_only:
         print(json.dumps(paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape)))

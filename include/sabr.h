@@ -206,6 +206,12 @@ typedef struct {
                                 pair skips that level */
   int32_t occupancy;         /* register budget of the level kernel: minimum waves per SIMD
                                 (0 or 1 = compiler's choice, 3, 4); a tuning knob */
+  int32_t waves_per_chain;   /* 0 or 1: one wave per chain; 2..8: each chain is a workgroup of
+                                that many waves splitting its quotes (blocks of 64, round
+                                robin), for few chains of many quotes; waves_per_group is then
+                                ignored.  The cost sums the waves' partials in wave order, so
+                                it may differ from the one-wave sum in the last bits.
+                                SABR_EINVAL when the waves' LDS does not fit a workgroup */
 } sa_config;
 
 /* Device workspace bytes sa_calibrate needs for these chain counts. */

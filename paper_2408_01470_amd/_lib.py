@@ -43,7 +43,7 @@ class SAConfig(ctypes.Structure):
         ("n_levels", ctypes.c_int32), ("n_steps", ctypes.c_int32), ("seed", ctypes.c_uint64),
         ("T0_per_inst", _f64p), ("waves_per_group", ctypes.c_int32),
         ("use_graph", ctypes.c_int32), ("level_events", ctypes.POINTER(ctypes.c_void_p)),
-        ("occupancy", ctypes.c_int32),
+        ("occupancy", ctypes.c_int32), ("waves_per_chain", ctypes.c_int32),
     ]
 
 

@@ -427,7 +427,7 @@ struct SALayout {
   size_t o_X, o_BX, o_BF, o_RX, o_RF, o_Tcur, o_tstart;
   size_t o_TF, o_TB, o_TI, o_TJ, o_TN;
   size_t total;
-  int n_tiles, waves, max_tiles;
+  int n_tiles, waves, wpc, max_tiles;
   int64_t tot_chains;
 };
 
@@ -445,12 +445,15 @@ SALayout sa_layout(const sabr_plan *P, const sa_config *cfg, const int32_t *chai
   shape.max_len = P->max_len;
   shape.reglen = reglen_for(P->max_len);
   shape.thchunk = sabr::th_chunk_for(P->max_nu);
-  S.waves = sabr::sa_waves_per_group(shape, want);
+  // waves_per_chain > 1: one chain per workgroup, its waves split the quotes
+  S.wpc = cfg && cfg->waves_per_chain > 1 ? cfg->waves_per_chain : 1;
+  S.waves = S.wpc > 1 ? S.wpc : sabr::sa_waves_per_group(shape, want);
+  const int cpt = S.waves / S.wpc;   // chains per tile
   S.n_tiles = 0;
   S.max_tiles = 0;
   S.tot_chains = 0;
   for (int i = 0; i < n; ++i) {
-    const int ti = (chains[i] + S.waves - 1) / S.waves;
+    const int ti = (chains[i] + cpt - 1) / cpt;
     S.n_tiles += ti;
     if (ti > S.max_tiles) S.max_tiles = ti;
     S.tot_chains += chains[i];
@@ -491,6 +494,20 @@ sabr_status check_sa_args(const sabr_plan *P, const sa_config *cfg, const int32_
   if (!(cfg->step_frac > 0.0 && cfg->step_frac <= 1.0))
     return fail(SABR_EINVAL, "step_frac outside (0, 1]");
   if (cfg->n_levels < 0 || cfg->n_steps < 0) return fail(SABR_EINVAL, "negative L or N");
+  if (cfg->waves_per_chain < 0 || cfg->waves_per_chain > sabr::kMaxWavesPerGroup)
+    return fail(SABR_EINVAL, "waves_per_chain outside [0, 8]");
+  if (cfg->waves_per_chain > 1) {
+    DevMarket shape{};
+    shape.model = P->model;
+    shape.np = P->np;
+    shape.max_nf = P->max_nf;
+    shape.max_nu = P->max_nu;
+    shape.max_len = P->max_len;
+    shape.reglen = reglen_for(P->max_len);
+    shape.thchunk = sabr::th_chunk_for(P->max_nu);
+    if (sabr::sa_waves_per_group(shape, cfg->waves_per_chain) != cfg->waves_per_chain)
+      return fail(SABR_EINVAL, "waves_per_chain: the waves' LDS exceeds one workgroup's");
+  }
   for (int i = 0; i < P->n_inst; ++i) {
     if (chains[i] < 1) return fail(SABR_EINVAL, "every instance needs >= 1 chain");
     if (cfg->T0_per_inst && !(cfg->T0_per_inst[i] > 0.0 && std::isfinite(cfg->T0_per_inst[i])))
@@ -566,7 +583,7 @@ sabr_status sa_run(sabr_plan *P, const sa_config *cfg, const int32_t *chains, co
     h_toff[i] = t;
     cb += chains[i];
     ab += (int64_t)L * N * chains[i];
-    for (int c = 0; c < chains[i]; c += S.waves) {
+    for (int c = 0; c < chains[i]; c += S.waves / S.wpc) {
       h_tinst[t] = i;
       h_tchain[t] = c;
       ++t;
@@ -592,6 +609,7 @@ sabr_status sa_run(sabr_plan *P, const sa_config *cfg, const int32_t *chains, co
     rate_khz = 100000;
   sabr::SAArgs a{};
   a.n_inst = n;
+  a.wpc = S.wpc;
   a.P = Pn;
   a.N = N;
   a.L = L;
@@ -664,7 +682,8 @@ sabr_status sa_run(sabr_plan *P, const sa_config *cfg, const int32_t *chains, co
                                (uint64_t)(uintptr_t)chain_best_f, (uint64_t)(uintptr_t)accept,
                                (uint64_t)(uintptr_t)level_trace, (uint64_t)(uintptr_t)level_best,
                                (uint64_t)L, (uint64_t)N, cfg->seed, (uint64_t)S.waves,
-                               (uint64_t)S.n_tiles, (uint64_t)cfg->occupancy};
+                               (uint64_t)S.n_tiles, (uint64_t)cfg->occupancy,
+                               (uint64_t)S.wpc};
   uint64_t bits;
   std::memcpy(&bits, &cfg->step_frac, 8);
   key.push_back(bits);

@@ -458,10 +458,13 @@ __device__ bool reb_map(const DevMarket &m, const DevInst &in, const UndMkt *um,
 // failure.  p[] is wave-uniform (GLOBAL4, LMM12); PERFWD, MM and REB read
 // the point from the lanes instead (xl: lane k holds coordinate k).  Optional
 // per-quote residual and model outputs (the quoted side in price mode).
+// Split evaluation: with nsub > 1 waves sharing the point, wave sub takes
+// the quotes of every nsub-th block of 64 (from block sub on) and returns
+// their partial sum (+inf on a domain failure); the map is every wave's.
 template <int MODEL, int FORMULA, int RESID>
 __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt *um,
                              const double *p, double xl, WaveLds w, double *resid,
-                             double *model) {
+                             double *model, int sub = 0, int nsub = 1) {
   constexpr bool LMM = (MODEL == 1 || MODEL == 5);   // 5: LMM12, 24-register swap column
   constexpr int REG = (MODEL == 5) ? 24 : kMapRegLen;
   const int lane = lane_id();
@@ -530,19 +533,22 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
     acc = fma(R.w * r, r, acc);
     if (resid) resid[qx[q]] = r;
   };
-  // Quotes [qa, qb) with two record buffers in turn: the next pass's record
-  // is loaded while this pass computes (the global load latency hides behind
-  // the arithmetic), and no register copies are needed between passes.
+  // Quotes [qa, qb) (this wave's blocks of them) with two record buffers in
+  // turn: the next pass's record is loaded while this pass computes (the
+  // global load latency hides behind the arithmetic), and no register copies
+  // are needed between passes.
   const QuoteRec *qrec = m.q + in.q0;
+  const int qs = nsub * kWave;
   auto quotes = [&](int qa, int qb, int toff) {
     QuoteRec Ra{}, Rb{};
-    if (qa + lane < qb) Ra = qrec[qa + lane];
-    for (int q = qa + lane; q < qb; q += 2 * kWave) {
-      if (q + kWave < qb) Rb = qrec[q + kWave];
+    const int q0 = qa + sub * kWave + lane;
+    if (q0 < qb) Ra = qrec[q0];
+    for (int q = q0; q < qb; q += 2 * qs) {
+      if (q + qs < qb) Rb = qrec[q + qs];
       quote(Ra, q, toff);
-      if (q + kWave >= qb) break;
-      if (q + 2 * kWave < qb) Ra = qrec[q + 2 * kWave];
-      quote(Rb, q + kWave, toff);
+      if (q + qs >= qb) break;
+      if (q + 2 * qs < qb) Ra = qrec[q + 2 * qs];
+      quote(Rb, q + qs, toff);
     }
   };
   if (LMM) {

@@ -67,6 +67,7 @@ __host__ __device__ inline int sa_wave_doubles(const DevMarket &m) {
 
 struct SAArgs {
   int n_inst, P, N, L;
+  int wpc;                      // waves per chain: 1, or every wave of a one-chain workgroup
   uint64_t seed;
   double step_frac, cool, ns_per_tick;
   const int *chains;            // [n_inst]

@@ -288,6 +288,22 @@ __device__ void level_end_block(const SAArgs &a, int inst, int level, double *sc
   if (threadIdx.x < P) a.RX[(size_t)inst * P + threadIdx.x] = a.X[(base + bstar) * P + threadIdx.x];
 }
 
+// Cost of a point whose quotes the nsub waves of a one-chain workgroup split
+// (point_cost with sub, nsub): each wave's partial goes to LDS slot
+// [parity][sub]; after the barrier every wave sums the slots in sub order,
+// so all of them hold the same total and take the same Metropolis decision.
+// Alternating the parity between calls makes one barrier per call enough:
+// a wave writes a slot again only after every wave passed the barrier that
+// followed its last read of it.
+__device__ __forceinline__ double split_total(double part, int sub, int nsub, int parity) {
+  __shared__ double xs[2][kMaxWavesPerGroup];
+  if (lane_id() == 0) xs[parity][sub] = part;
+  __syncthreads();
+  double t = xs[parity][0];
+  for (int k = 1; k < nsub; ++k) t += xs[parity][k];
+  return t;
+}
+
 template <int MODEL, int FORMULA, int RESID>
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void sa_init_kernel(DevMarket m, SAArgs a,
                                                                              int lds_per_wave) {
@@ -300,14 +316,21 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void sa_init_kernel(DevM
   const DevInst in = m.inst[inst];
   const UndMkt *um = stage_underlyings(m, in, smem);
   const int C = a.chains[inst];
-  const int c = a.tile_chain[blockIdx.x] + wid;
+  // wpc > 1: the workgroup is one chain, its waves split the quotes
+  const int wpc = a.wpc;
+  const int c = a.tile_chain[blockIdx.x] + wid / wpc;
+  const int sub = wid - (wid / wpc) * wpc;
   double f = kInf;
-  if (c < C) {   // wave-uniform
+  if (c < C) {   // wave-uniform (workgroup-uniform when wpc > 1)
     const double xl = (lane < P) ? a.x0[(size_t)inst * P + lane] : 0.0;
     double x[PC > 0 ? PC : 1];
     broadcast_params<PC>(xl, x);
     WaveLds w = wave_lds(m, smem + 6 * m.max_nu + (size_t)wid * lds_per_wave);
-    f = point_cost<MODEL, FORMULA, RESID>(m, in, um, x, xl, w, nullptr, nullptr);
+    f = point_cost<MODEL, FORMULA, RESID>(m, in, um, x, xl, w, nullptr, nullptr, sub, wpc);
+    if (wpc > 1) f = split_total(f, sub, wpc, 0);
+  }
+  if (c < C && sub == 0) {
+    const double xl = (lane < P) ? a.x0[(size_t)inst * P + lane] : 0.0;
     const int64_t gc = a.chain_base[inst] + c;
     if (lane < P) {
       a.X[gc * P + lane] = xl;
@@ -323,7 +346,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void sa_init_kernel(DevM
       }
     }
   }
-  tile_partial(a, C, c < C ? c : C, f, f, 0);
+  tile_partial(a, C, (c < C && sub == 0) ? c : C, f, f, 0);
 }
 
 // OCC: minimum waves per SIMD the register allocation must allow (1 = the
@@ -343,7 +366,11 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
   const DevInst in = m.inst[inst];
   const UndMkt *um = stage_underlyings(m, in, smem);
   const int C = a.chains[inst];
-  const int c = a.tile_chain[blockIdx.x] + wid;
+  // wpc > 1: the workgroup is one chain, its waves split the quotes and take
+  // the same steps; wave sub = 0 writes the chain's results
+  const int wpc = a.wpc;
+  const int c = a.tile_chain[blockIdx.x] + wid / wpc;
+  const int sub = wid - (wid / wpc) * wpc;
   double f_end = kInf, bf_end = kInf;
   int nacc_end = 0;
   if (c < C) {   // wave-uniform: waves past the instance's last chain have no work
@@ -388,7 +415,9 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
         const double xp = own ? propose1(x, u, lo, hi, a.step_frac) : 0.0;
         double p[PC > 0 ? PC : 1];
         broadcast_params<PC>(xp, p);
-        double fp = point_cost<MODEL, FORMULA, RESID>(m, in, um, p, xp, w, nullptr, nullptr);
+        double fp =
+            point_cost<MODEL, FORMULA, RESID>(m, in, um, p, xp, w, nullptr, nullptr, sub, wpc);
+        if (wpc > 1) fp = split_total(fp, sub, wpc, s & 1);
         if (fp != fp) fp = kInf;
         const double uP = us[P];
         const double dE = fp - f;
@@ -402,7 +431,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
           f = fp;
           ++nacc;
         }
-        if (a.accept && lane == 0)
+        if (a.accept && lane == 0 && sub == 0)
           a.accept[a.acc_base[inst] + ((int64_t)level * a.N + s) * C + c] = acc ? 1 : 0;
         if (fp < bf) {
           bf = fp;
@@ -411,18 +440,18 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
       }
       wave_lds_sync();   // the next chunk overwrites the uniforms
     }
-    if (own) {
+    if (own && sub == 0) {
       a.X[gc * P + lane] = x;
       a.BX[gc * P + lane] = bx;
     }
-    if (lane == 0) {
+    if (lane == 0 && sub == 0) {
       a.BF[gc] = bf;
     }
     f_end = f;
     bf_end = bf;
     nacc_end = nacc;
   }
-  tile_partial(a, C, c < C ? c : C, f_end, bf_end, nacc_end);
+  tile_partial(a, C, (c < C && sub == 0) ? c : C, f_end, bf_end, nacc_end);
 }
 
 // Level end, one workgroup per instance: argmin of the final costs (ties ->

@@ -140,6 +140,15 @@ def test_sa_rejects_bad_config_without_gpu(L):
     assert L.sa_workspace_size(h, ctypes.byref(cfg), ch.ctypes.data_as(i32)) > 16 * 8
     bad = SAConfig(1.0, 1.5, 0.05, 10, 10, 1, None, 0, 0, None, 0)   # cool > 1
     assert L.sa_workspace_size(h, ctypes.byref(bad), ch.ctypes.data_as(i32)) == 0
+    # waves per chain: 0..8, and a one-chain workgroup per chain (more tiles)
+    split = SAConfig(1.0, 0.9, 0.05, 10, 10, 1, None, 4, 0, None, 0, 2)
+    many = np.array([4096], np.int32)
+    assert (L.sa_workspace_size(h, ctypes.byref(split), many.ctypes.data_as(i32)) >
+            L.sa_workspace_size(h, ctypes.byref(cfg), many.ctypes.data_as(i32)))
+    for wpc in (-1, 9):
+        bad = SAConfig(1.0, 0.9, 0.05, 10, 10, 1, None, 0, 0, None, 0, wpc)
+        assert L.sa_workspace_size(h, ctypes.byref(bad), ch.ctypes.data_as(i32)) == 0
+        assert "waves_per_chain" in L.sabr_last_error().decode()
     # not uploaded: sa_calibrate refuses before touching the GPU
     f64 = ctypes.POINTER(ctypes.c_double)
     lb, ub = (np.ascontiguousarray(b) for b in I.box(0))
@@ -147,4 +156,21 @@ def test_sa_rejects_bad_config_without_gpu(L):
                         ub.ctypes.data_as(f64), None, None, None, None, None, None, None, None,
                         None, 0, None)
     assert rc == -1
+    L.sabr_plan_destroy(h)
+
+
+def test_sa_split_chain_lds_refusal_without_gpu(L):
+    """A chain split over more waves than one workgroup's LDS holds is
+    refused by name (the per-wave tables of a large LMM12 market)."""
+    from paper_2408_01470_amd._lib import SAConfig
+    m, _, _ = I.lmm_market(M=60, n_cap_K=3, n_exp=12, n_ten=12, n_swp_K=3)
+    rc, h = _create(L, m)
+    assert rc == 0
+    ch = np.array([4], np.int32)
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    ok = SAConfig(1.0, 0.9, 0.05, 10, 10, 1, None, 0, 0, None, 0, 1)
+    assert L.sa_workspace_size(h, ctypes.byref(ok), ch.ctypes.data_as(i32)) > 0
+    big = SAConfig(1.0, 0.9, 0.05, 10, 10, 1, None, 0, 0, None, 0, 8)
+    assert L.sa_workspace_size(h, ctypes.byref(big), ch.ctypes.data_as(i32)) == 0
+    assert "LDS" in L.sabr_last_error().decode()
     L.sabr_plan_destroy(h)

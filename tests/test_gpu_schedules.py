@@ -67,16 +67,17 @@ def _report(plan, oracle, mk, w, chains, lb, ub, T0s, cool, where):
                     cool, w.n_steps, w.seed, w.step_frac, where)
 
 
-def _full_schedule(api, oracle, w, chains, waves):
+def _full_schedule(api, oracle, w, chains, waves, waves_per_chain=0, n_levels=None):
     mk, T0s, cool = _workload(oracle, w)
     lb, ub = I.box(w.model)
-    L, N = w.n_levels, w.n_steps
+    L, N = n_levels or w.n_levels, w.n_steps
     kw = dict(T0=T0s[0], cool=cool, n_levels=L, n_steps=N, seed=w.seed, step_frac=w.step_frac,
               T0_per_inst=T0s)
     print(f"{w.name}: {chains} chains, T0 {T0s[0]:.4g}, T_end {T0s[0] * cool ** (L - 1):.4g}",
           flush=True)
     plan = api.Plan(mk)
-    g = plan.sa(chains, lb, ub, record=True, chain_best=True, waves=waves, **kw)
+    g = plan.sa(chains, lb, ub, record=True, chain_best=True, waves=waves,
+                waves_per_chain=waves_per_chain, **kw)
     o = oracle.sa_calibrate(mk, chains, lb, ub, record=True, **kw)
     acc = g["accept"].cpu().numpy()
     where = first_mismatch(acc, o["accept"], L, N, [chains])
@@ -89,9 +90,9 @@ def _full_schedule(api, oracle, w, chains, waves):
     np.testing.assert_allclose(g["chain_best_f"].cpu().numpy(), o["chain_best_f"], rtol=RTOL)
     tr = g["trace"].cpu().numpy()
     np.testing.assert_array_equal(tr[0, :, 1], o["trace"][0, :, 1])
-    # the schedule reaches the cold end: the last levels accept rarely
-    rate = acc.reshape(L, N * chains).mean(axis=1)
-    assert rate[-1] < 0.5 * rate[0]
+    if L == w.n_levels:   # the schedule reaches the cold end: the last levels accept rarely
+        rate = acc.reshape(L, N * chains).mean(axis=1)
+        assert rate[-1] < 0.5 * rate[0]
     return acc
 
 
