@@ -286,7 +286,10 @@ __device__ __forceinline__ double exp_neg(double x) {
 // exact error e (two-sum), v = 2^k m with m in [sqrt(1/2), sqrt(2)),
 // f = (m - 1) + e 2^-k (so 1 + f = (1 + t)/2^k), s = f/(2 + f),
 // log(1 + f) = f - s (f - s^2 P(s^2)), and log1p(t) = k ln2 + log(1 + f).
-// NaN for t <= -1, t = +inf or NaN t; branch-free.
+// NaN for t <= -1, t = +inf or NaN t; branch-free.  CHECKED = false leaves
+// out the select of NaN for t <= -1, for callers whose t >= 0 (NaN and +inf
+// still give NaN).
+template <bool CHECKED = true>
 __device__ __forceinline__ double log1p_tang(double t) {
   const double v = 1.0 + t;
   const double vv = v - 1.0;
@@ -305,6 +308,7 @@ __device__ __forceinline__ double log1p_tang(double t) {
   const double lf = fma(-s, fma(-z, p, f), f);
   const double kd = (double)k;
   const double res = fma(kd, kLn2Hi, lf + kd * kLn2Lo);
+  if constexpr (!CHECKED) return res;
   return v > 0.0 ? res : __builtin_nan("");
 }
 
@@ -414,9 +418,11 @@ __device__ __forceinline__ SabrConst sabr_const(double alpha, double beta, doubl
   return k;
 }
 
-// |z| below which z/x(z) takes its series: three terms leave a truncation
-// error below 1e-17 here, and for larger |z| the log1p form is accurate.
+// |z| below which the adjoint's chi = z/x(z) takes its series (three terms
+// leave a truncation error below 1e-17 here).
 constexpr double kZSeries = 0x1.0p-18;
+// Smallest |z| the cost kernels' quotient form takes (see hagan2002_frac).
+constexpr double kZFloor = 0x1.0p-60;
 
 // Hagan 2002 lognormal vol given L = ln(f/K), q = (f K)^((1-beta)/2),
 // D1 = 1 + (1-b)^2 L^2/24 + (1-b)^4 L^4/1920 and expiry T, as a fraction
@@ -427,9 +433,15 @@ constexpr double kZSeries = 0x1.0p-18;
 // a = |z| and r = sign(z) rho, chi = a / log1p(t) with t = num/den chosen so
 // that neither num nor den cancels:
 //   a <= 1:  t = 2a / (s + (1 - a))
-//   a >  1:  t = (s + (a - 1)) / (1 - r);
-// for |z| < kZSeries the series replaces the quotient (removable singularity
-// at z = 0).
+//   a >  1:  t = (s + (a - 1)) / (1 - r).
+// At the removable singularity z = 0 (chi -> 1) the quotient a/log1p(t)
+// stays accurate to a few ulps for every a > 0 (t has no cancellation and
+// log1p is accurate for small t), so a is kept at kZFloor = 2^-60 or above
+// instead of switching to the series: below it chi = 1 - rho z/2 + O(z^2)
+// rounds to 1, and at a = kZFloor the quotient gives chi = 1 exactly
+// (s + (1 - a) rounds to 2, t = a, log1p(t) rounds to t).  The floor keeps
+// numer and denom (both carry the factor a) far from underflow, also in
+// their product.  t >= 0 in the domain (|rho| < 1).
 struct VolFrac {
   double numer, denom;
 };
@@ -438,15 +450,11 @@ __device__ __forceinline__ VolFrac hagan2002_frac(const SabrConst &k, double L, 
                                                   double D1, double T) {
   const double z = k.nua * q * L;
   const double s = sqrt_gs(fma(z, z - 2.0 * k.rho, 1.0));
-  const double az = fabs(z);
+  const double az = fmax(fabs(z), kZFloor);
   const bool mid = az <= 1.0;
   const double num = mid ? 2.0 * az : s + (az - 1.0);
   const double den = mid ? s + (1.0 - az) : fma(-copysign(1.0, z), k.rho, 1.0);
-  double cn = az, cd = log1p_tang(num * rcp_nr(den));   // chi = cn / cd
-  if (az < kZSeries) {   // rare: the series, with (2 - 3 rho^2)/12 = 1/6 - rho^2/4
-    cn = fma(z, fma(z, fma(-0.25, k.rho * k.rho, 1.0 / 6.0), -0.5 * k.rho), 1.0);
-    cd = 1.0;
-  }
+  const double cn = az, cd = log1p_tang<false>(num * rcp_nr(den));   // chi = cn / cd
   const double Pq = fma(q, q, T * fma(q, fma(q, k.cc, k.cb), k.ca));
   VolFrac v;
   v.numer = k.alpha * Pq * cn;

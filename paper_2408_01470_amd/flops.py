@@ -4,8 +4,8 @@ Counts follow the formulas as the kernels state them, each operation counted
 once where the definition needs it: add, sub and mul count 1, fma counts 2,
 a hardware reciprocal or reciprocal square root seed counts 1, comparisons,
 selects, negations, exponent manipulation and integer work (the Philox
-generator) count 0; a branch counts its common side only (the |z| <= 1
-quotient of z/x(z), not its series).  Elementary functions count the FP64
+generator) count 0; of two forms selected between, the common one counts
+(the |z| <= 1 quotient of z/x(z)).  Elementary functions count the FP64
 operations of their implementation (``ELEMENTARY``): the kernels' own
 branch-free exp, log1p, sqrt, reciprocal and erfcx (counted from their
 definitions, and confirmed by the hardware counters

@@ -1,10 +1,13 @@
 """Parity in the removable singularity of Hagan's formula (Sec. 2.1, eq.
 (sigmaHagan) cites Hagan 2002): chi = z/x(z) at z = (nu/alpha) q ln(f/K)
--> 0.  The cost kernels switch from the log1p form to the series below
-|z| = 2^-18, the adjoint's derivatives of chi below |z| = 2^-10; these tests
-place quotes so that |z| spans both sides of each switch (both signs of z)
-and compare with the oracle: model values and costs to 1e-12 relative,
-gradients, J^T W J and J^T W r to 1e-10."""
+-> 0.  The cost kernels keep the log1p quotient down to |z| = 2^-60 (only
+the exact at-the-money z = 0 goes below it, where |z| is floored and chi
+rounds to its limit 1); the adjoint takes the series of chi below
+|z| = 2^-18 and of its derivatives below 2^-10.  These tests place quotes
+so that |z| spans both sides of each switch (both signs of z), down to the
+smallest nonzero |z| a strike can give and z = 0, and compare with the
+oracle: model values and costs to 1e-12 relative, gradients, J^T W J and
+J^T W r to 1e-10."""
 import numpy as np
 import pytest
 
@@ -71,7 +74,7 @@ def _points(n, seed):
 @pytest.mark.gpu
 @pytest.mark.parametrize("residual", [I.RESID_VOL, I.RESID_PRICE])
 def test_cost_series_switch_parity(api, oracle, residual):
-    zs = _targets(2.0 ** -18)
+    zs = np.concatenate([_targets(2.0 ** -18), [1e-15, -1e-15, 0.0]])
     mk, L = _completed(oracle, zs, residual)
     plan = api.Plan(mk)
     # at the point itself every |z| is on target; the nearby points move z
