@@ -495,8 +495,8 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
   auto quote = [&](const QuoteRec &R, int q, int toff) {
     const double L = R.L;
     const int u = R.und;
-    const UndMkt U = um[u];
-    const SabrConst k = (MODEL == 0) ? g : w.th[u - toff];
+    const UndMkt U = lds_elem(um, u);
+    const SabrConst k = (MODEL == 0) ? g : lds_elem(w.th, u - toff);
     // eq. (sigmaHagan) with beta fixed: the vol itself, a quadratic in
     // k = ln(K/f) = -L with the underlying's coefficients
     constexpr bool direct = (FORMULA == 1 && MODEL != 0);
@@ -542,12 +542,12 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
   auto quotes = [&](int qa, int qb, int toff) {
     QuoteRec Ra{}, Rb{};
     const int q0 = qa + sub * kWave + lane;
-    if (q0 < qb) Ra = qrec[q0];
+    if (q0 < qb) Ra = glb_elem(qrec, q0);
     for (int q = q0; q < qb; q += 2 * qs) {
-      if (q + qs < qb) Rb = qrec[q + qs];
+      if (q + qs < qb) Rb = glb_elem(qrec, q + qs);
       quote(Ra, q, toff);
       if (q + qs >= qb) break;
-      if (q + 2 * qs < qb) Ra = qrec[q + 2 * qs];
+      if (q + 2 * qs < qb) Ra = glb_elem(qrec, q + 2 * qs);
       quote(Rb, q + qs, toff);
     }
   };

@@ -155,6 +155,29 @@ __device__ __forceinline__ double wave_sum(double v) {
   return readlane_d(v, kWave - 1);
 }
 
+// Element i of an array the caller knows to lie in LDS, addressed in 32 bits
+// (one 24-bit multiply, where the generic pointer's index takes a 64-bit
+// multiply-add); i * sizeof(T) < 2^24 always holds in LDS.
+template <class T>
+__device__ __forceinline__ T lds_elem(const T *p, int i) {
+  static_assert(sizeof(T) % sizeof(double) == 0, "records of doubles");
+  using lcp = __attribute__((address_space(3))) const char *;
+  using ldp = __attribute__((address_space(3))) const double *;
+  const ldp src = (ldp)((lcp)p + __umul24((unsigned)i, (unsigned)sizeof(T)));
+  T v;
+  double *dst = reinterpret_cast<double *>(&v);
+#pragma unroll
+  for (size_t k = 0; k < sizeof(T) / sizeof(double); ++k) dst[k] = src[k];
+  return v;
+}
+
+// Element i >= 0 of a global array by a 32-bit byte offset from its base
+// (the scalar-base form of the global load; i * sizeof(T) < 2^32).
+template <class T>
+__device__ __forceinline__ T glb_elem(const T *p, int i) {
+  return *(const T *)((const char *)p + (unsigned)i * (unsigned)sizeof(T));
+}
+
 // Orders LDS traffic of one wavefront: a wave's LDS operations execute in
 // issue order, so only the compiler must be kept from reordering them.
 __device__ __forceinline__ void wave_lds_sync() {
@@ -206,16 +229,26 @@ __device__ __forceinline__ void horner_step(double t, double &h, double &c) {
   h = fma_s(h, t, c);
   c = cn;
 }
+// The leading step t C[DEG] + C[DEG-1] of a single chain as a multiply and
+// an add, each reading its constant from scalar registers (an fma would need
+// C[DEG] copied to vector registers first: two more vector instructions).
+__device__ __forceinline__ double lead_step(double t, double c0, double c1) {
+#pragma clang fp contract(off)
+  return t * c0 + c1;
+}
 template <const double *C, int DEG, size_t... I>
 __device__ __forceinline__ double horner_s(double t, std::index_sequence<I...>) {
-  double h = SABR_SCONST(C[DEG]);
-  double c = SABR_SCONST(C[DEG - 1]);
-  (horner_step<C, DEG, I>(t, h, c), ...);
+  const double c0 = SABR_SCONST(C[DEG]);
+  const double c1 = SABR_SCONST(C[DEG - 1]);
+  double c = SABR_SCONST(C[DEG - 2]);
+  double h = lead_step(t, c0, c1);
+  (horner_step<C, DEG, I + 1>(t, h, c), ...);
   return h;
 }
 template <const double *C, int DEG>
 __device__ __forceinline__ double horner_s(double t) {
-  return horner_s<C, DEG>(t, std::make_index_sequence<DEG>{});
+  static_assert(DEG >= 2, "a leading step and at least one more");
+  return horner_s<C, DEG>(t, std::make_index_sequence<DEG - 1>{});
 }
 template <const double *C, int DEG, size_t I>
 __device__ __forceinline__ void horner2_step(double t1, double t2, double &h1, double &h2,
