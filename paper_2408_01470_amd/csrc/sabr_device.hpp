@@ -131,13 +131,19 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 }
 
 // A double moved across lanes by a DPP pattern (both halves); lanes whose
-// row is not in ROW_MASK read 0.
+// row is not in ROW_MASK read 0.  With every row enabled the pattern writes
+// every lane, so no old value is needed (no zeroing moves).
 template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ double dpp_d(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROW_MASK, 0xf,
-                                             false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  int lo, hi;
+  if constexpr (ROW_MASK == 0xf) {
+    lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+  } else {
+    lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROW_MASK, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  }
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -444,7 +450,7 @@ __device__ __forceinline__ SabrConst sabr_const(double alpha, double beta, doubl
   const double r2 = rho * rho;
   k.alpha = alpha;
   k.rho = rho;
-  k.nua = nu / alpha;
+  k.nua = nu * rcp_nr(alpha);
   k.ca = omb * omb * alpha * alpha * (1.0 / 24.0);
   k.cb = rho * beta * nu * alpha * 0.25;
   k.cc = (2.0 - 3.0 * r2) * nu * nu * (1.0 / 24.0);

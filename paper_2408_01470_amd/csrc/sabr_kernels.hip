@@ -425,7 +425,9 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
         // which exp_neg maps to 0: a rejection, as exp(NaN) would give).  The
         // exponent is the correctly rounded quotient -dE/T, one division a
         // step, so it carries no rounding beyond that of dE itself.
-        const bool acc = (dE <= 0.0) || (uP < exp_neg(-dE / T));
+        // (dE is wave-uniform: the exponential runs for uphill moves only)
+        bool acc = dE <= 0.0;
+        if (!acc) acc = uP < exp_neg(-dE / T);
         if (acc) {
           x = xp;
           f = fp;

@@ -41,16 +41,15 @@ def _e(name, n=1):
 
 def sabr_const(model: int, formula: int = 0) -> float:
     """Constants of one (alpha, beta, rho, nu): rho^2 and 2 - 3 rho^2 (3),
-    nu/alpha (a library division for GLOBAL4, a reciprocal and a product
-    for LMM12 and PERFWD), the three corr coefficients alpha^2 (1-b)^2/24,
-    rho b nu alpha/4, (2 - 3 rho^2) nu^2/24 (3 + 4 + 3) and the series
-    coefficient (2 - 3 rho^2)/12 (1); (1-b) and (1-b)^2 add 2 when beta is a
-    parameter.  Eq. (sigmaHagan) with beta fixed instead takes the three
-    coefficients of its quadratic in k: nu/alpha (reciprocal and product),
-    w = fp/alpha (1), alpha/fp (reciprocal and product), d = 1-b - rho nu w
-    (3), nu w (1), the linear coefficient (2) and the quadratic one (13)."""
+    nu/alpha (a reciprocal and a product), the three corr coefficients
+    alpha^2 (1-b)^2/24, rho b nu alpha/4, (2 - 3 rho^2) nu^2/24 (3 + 4 + 3);
+    (1-b) and (1-b)^2 add 2 when beta is a parameter (GLOBAL4).  Eq.
+    (sigmaHagan) with beta fixed instead takes the three coefficients of its
+    quadratic in k: nu/alpha (reciprocal and product), w = fp/alpha (1),
+    alpha/fp (reciprocal and product), d = 1-b - rho nu w (3), nu w (1), the
+    linear coefficient (2) and the quadratic one (13)."""
     if model == 0:
-        return 16.0 + _e("div")
+        return 16.0 + _e("rcp")
     if formula == 1:
         return 22.0 + _e("rcp", 2)
     return 15.0 + _e("rcp")
