@@ -304,7 +304,9 @@ __device__ __forceinline__ double split_total(double part, int sub, int nsub, in
   return t;
 }
 
-template <int MODEL, int FORMULA, int RESID>
+// SPLIT: compiled for chains split over the waves of their workgroup
+// (a.wpc > 1); the one-wave-per-chain variant keeps no trace of it.
+template <int MODEL, int FORMULA, int RESID, bool SPLIT>
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void sa_init_kernel(DevMarket m, SAArgs a,
                                                                              int lds_per_wave) {
   extern __shared__ double smem[];
@@ -316,10 +318,10 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void sa_init_kernel(DevM
   const DevInst in = m.inst[inst];
   const UndMkt *um = stage_underlyings(m, in, smem);
   const int C = a.chains[inst];
-  // wpc > 1: the workgroup is one chain, its waves split the quotes
-  const int wpc = a.wpc;
-  const int c = a.tile_chain[blockIdx.x] + wid / wpc;
-  const int sub = wid - (wid / wpc) * wpc;
+  // SPLIT: the workgroup is one chain, its wpc waves split the quotes
+  const int wpc = SPLIT ? a.wpc : 1;
+  const int c = a.tile_chain[blockIdx.x] + (SPLIT ? 0 : wid);
+  const int sub = SPLIT ? wid : 0;
   double f = kInf;
   if (c < C) {   // wave-uniform (workgroup-uniform when wpc > 1)
     const double xl = (lane < P) ? a.x0[(size_t)inst * P + lane] : 0.0;
@@ -327,7 +329,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void sa_init_kernel(DevM
     broadcast_params<PC>(xl, x);
     WaveLds w = wave_lds(m, smem + 6 * m.max_nu + (size_t)wid * lds_per_wave);
     f = point_cost<MODEL, FORMULA, RESID>(m, in, um, x, xl, w, nullptr, nullptr, sub, wpc);
-    if (wpc > 1) f = split_total(f, sub, wpc, 0);
+    if (SPLIT) f = split_total(f, sub, wpc, 0);
   }
   if (c < C && sub == 0) {
     const double xl = (lane < P) ? a.x0[(size_t)inst * P + lane] : 0.0;
@@ -350,8 +352,9 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void sa_init_kernel(DevM
 }
 
 // OCC: minimum waves per SIMD the register allocation must allow (1 = the
-// compiler's choice); a tuning knob traded against spills.
-template <int MODEL, int FORMULA, int RESID, int OCC>
+// compiler's choice); a tuning knob traded against spills.  SPLIT as for
+// sa_init_kernel.
+template <int MODEL, int FORMULA, int RESID, int OCC, bool SPLIT>
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kernel(DevMarket m,
                                                                                  SAArgs a,
                                                                                  int level,
@@ -366,11 +369,11 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
   const DevInst in = m.inst[inst];
   const UndMkt *um = stage_underlyings(m, in, smem);
   const int C = a.chains[inst];
-  // wpc > 1: the workgroup is one chain, its waves split the quotes and take
-  // the same steps; wave sub = 0 writes the chain's results
-  const int wpc = a.wpc;
-  const int c = a.tile_chain[blockIdx.x] + wid / wpc;
-  const int sub = wid - (wid / wpc) * wpc;
+  // SPLIT: the workgroup is one chain, its wpc waves split the quotes and
+  // take the same steps; wave sub = 0 writes the chain's results
+  const int wpc = SPLIT ? a.wpc : 1;
+  const int c = a.tile_chain[blockIdx.x] + (SPLIT ? 0 : wid);
+  const int sub = SPLIT ? wid : 0;
   double f_end = kInf, bf_end = kInf;
   int nacc_end = 0;
   if (c < C) {   // wave-uniform: waves past the instance's last chain have no work
@@ -417,7 +420,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
         broadcast_params<PC>(xp, p);
         double fp =
             point_cost<MODEL, FORMULA, RESID>(m, in, um, p, xp, w, nullptr, nullptr, sub, wpc);
-        if (wpc > 1) fp = split_total(fp, sub, wpc, s & 1);
+        if (SPLIT) fp = split_total(fp, sub, wpc, s & 1);
         if (fp != fp) fp = kInf;
         const double uP = us[P];
         const double dE = fp - f;
@@ -612,9 +615,15 @@ hipError_t launch_sa_init(const DevMarket &m, const SAArgs &a, int n_tiles, int 
                           hipStream_t s) {
   const int ld = sa_wave_doubles(m);
   const size_t lds = sa_lds_bytes(m, waves);
-#define CALL(A, B, C)                                                                    \
-  hipLaunchKernelGGL((sa_init_kernel<A, B, C>), dim3(n_tiles), dim3(kWave * waves), lds, s, \
-                     m, a, ld)
+#define CALL(A, B, C)                                                                      \
+  do {                                                                                      \
+    if (a.wpc > 1)                                                                          \
+      hipLaunchKernelGGL((sa_init_kernel<A, B, C, true>), dim3(n_tiles), dim3(kWave * waves), \
+                         lds, s, m, a, ld);                                                 \
+    else                                                                                    \
+      hipLaunchKernelGGL((sa_init_kernel<A, B, C, false>), dim3(n_tiles),                   \
+                         dim3(kWave * waves), lds, s, m, a, ld);                            \
+  } while (0)
   SABR_SELECT(kernel_model(m), m.formula, m.residual, CALL);
 #undef CALL
   return hipGetLastError();
@@ -624,17 +633,20 @@ hipError_t launch_sa_level(const DevMarket &m, const SAArgs &a, int level, int n
                            int waves, int occupancy, hipStream_t s) {
   const int ld = sa_wave_doubles(m);
   const size_t lds = sa_lds_bytes(m, waves);
-#define LAUNCH(A, B, C, O)                                                                   \
-  hipLaunchKernelGGL((sa_level_kernel<A, B, C, O>), dim3(n_tiles), dim3(kWave * waves), lds, \
-                     s, m, a, level, ld)
-#define CALL(A, B, C)              \
-  do {                             \
-    if (occupancy >= 4)            \
-      LAUNCH(A, B, C, 4);          \
-    else if (occupancy == 3)       \
-      LAUNCH(A, B, C, 3);          \
-    else                           \
-      LAUNCH(A, B, C, 1);          \
+#define LAUNCH(A, B, C, O, SP)                                                            \
+  hipLaunchKernelGGL((sa_level_kernel<A, B, C, O, SP>), dim3(n_tiles), dim3(kWave * waves), \
+                     lds, s, m, a, level, ld)
+  // split chains are few (latency-bound): one register budget serves them
+#define CALL(A, B, C)                   \
+  do {                                  \
+    if (a.wpc > 1)                      \
+      LAUNCH(A, B, C, 1, true);         \
+    else if (occupancy >= 4)            \
+      LAUNCH(A, B, C, 4, false);        \
+    else if (occupancy == 3)            \
+      LAUNCH(A, B, C, 3, false);        \
+    else                                \
+      LAUNCH(A, B, C, 1, false);        \
   } while (0)
   SABR_SELECT(kernel_model(m), m.formula, m.residual, CALL);
 #undef CALL
