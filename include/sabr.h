@@ -407,6 +407,16 @@ sabr_status sabr_mc_cost(const sabr_mc_plan *plan, int64_t n_paths, double dt, u
 /* Last error message of the calling thread ("" if none). */
 const char *sabr_last_error(void);
 
+/* Forget the library's process-wide state: the per-device address of the
+ * no-allocation scratch array (looked up again on the next
+ * sa_calibrate_noalloc), the cached LDS budget and the calling thread's last
+ * error.  Nothing else is process-wide: each plan owns its device image and
+ * its captured graph and releases them in sabr_plan_destroy (Monte Carlo
+ * plans in sabr_mc_plan_destroy); the scratch array itself is a static
+ * device variable held until the process ends.  Call it with no other call
+ * of the library in flight.  Always SABR_OK. */
+sabr_status sabr_shutdown(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -210,6 +210,39 @@ def cost_grad(m, params, pt_inst=None, normal=False):
     return (cost, grad, A, g) if normal else (cost, grad)
 
 
+def sabr_cost_batch(m, params, pt_inst=None, resid=False, model=False):
+    """The mirror of the library's sabr_cost_batch: cost, and the residuals
+    and model values ([n, stride], the caller's quote order) when asked."""
+    M = _mk(m)
+    params = np.ascontiguousarray(np.atleast_2d(params), dtype=np.float64)
+    n = params.shape[0]
+    pt = np.zeros(n, np.int32) if pt_inst is None else np.ascontiguousarray(pt_inst, np.int32)
+    cost = np.zeros(n)
+    stride = int(M.nq.max()) if len(M.nq) else 0
+    r = np.full((n, stride), np.nan) if resid else None
+    mv = np.full((n, stride), np.nan) if model else None
+    _check(lib().oracle_sabr_cost_batch(ctypes.byref(M.s), n, _p(pt, _i32p), _p(params, _f64p),
+                                        _p(cost, _f64p), _p(r, _f64p), _p(mv, _f64p), stride))
+    return cost, r, mv
+
+
+def sabr_cost_vjp(m, params, pt_inst=None, g_cost=None, normal=False):
+    """The mirror of the library's sabr_cost_vjp: cost, g_cost-weighted
+    gradient and (normal) J^T W J, J^T W r."""
+    M = _mk(m)
+    params = np.ascontiguousarray(np.atleast_2d(params), dtype=np.float64)
+    n, P = params.shape
+    pt = np.zeros(n, np.int32) if pt_inst is None else np.ascontiguousarray(pt_inst, np.int32)
+    gc = None if g_cost is None else np.ascontiguousarray(g_cost, dtype=np.float64)
+    cost, gp = np.zeros(n), np.zeros((n, P))
+    A = np.zeros((n, P, P)) if normal else None
+    g = np.zeros((n, P)) if normal else None
+    _check(lib().oracle_sabr_cost_vjp(ctypes.byref(M.s), n, _p(pt, _i32p), _p(params, _f64p),
+                                      _p(gc, _f64p), _p(cost, _f64p), _p(gp, _f64p),
+                                      _p(A, _f64p), _p(g, _f64p)))
+    return cost, gp, A, g
+
+
 def sa_state_doubles(chains, P):
     """Doubles of the annealing state of instances with these chain counts:
     per instance X [C][P], F [C], BX [C][P], BF [C], T."""

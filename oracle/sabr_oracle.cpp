@@ -1294,6 +1294,56 @@ int32_t oracle_cost_grad(const oracle_market *m, int32_t n_pts, const int32_t *p
   return 0;
 }
 
+// Mirrors of the library's cost entry points on host pointers (no stream,
+// no workspace): sabr_cost_batch and sabr_cost_vjp, argument for argument.
+int32_t oracle_sabr_cost_batch(const oracle_market *m, int32_t n_pts, const int32_t *pt_inst,
+                               const double *params, double *cost, double *resid, double *model,
+                               int32_t stride) {
+  if (!m) return fail("null market");
+  std::vector<Inst> insts(m->n_inst);
+  for (int i = 0; i < m->n_inst; ++i)
+    if (build_inst(m, i, insts[i])) return -1;
+  const int P = market_params(m);
+  if (P < 0) return fail("unknown model or PERFWD instances of unequal size");
+  if ((resid || model) && stride < 1) return fail("stride below the quote count");
+  for (int i = 0; i < m->n_inst; ++i)
+    if ((resid || model) && (int)insts[i].q.size() > stride)
+      return fail("stride below the quote count");
+#pragma omp parallel for schedule(dynamic)
+  for (int i = 0; i < n_pts; ++i) {
+    if (pt_inst[i] < 0 || pt_inst[i] >= m->n_inst) {   // out of range: NaN, as on the device
+      cost[i] = std::nan("");
+      continue;
+    }
+    const Inst &I = insts[pt_inst[i]];
+    const double *p = params + (size_t)i * P;
+    cost[i] = cost_point<double>(I, p, resid ? resid + (size_t)i * stride : nullptr);
+    if (model) {
+      std::vector<double> mv, rv;
+      const bool ok = model_values(I, p, mv, rv);
+      for (size_t q = 0; q < I.q.size(); ++q)
+        model[(size_t)i * stride + q] = ok ? mv[q] : std::nan("");
+    }
+  }
+  return 0;
+}
+
+int32_t oracle_sabr_cost_vjp(const oracle_market *m, int32_t n_pts, const int32_t *pt_inst,
+                             const double *params, const double *g_cost, double *cost,
+                             double *g_params, double *jtwj, double *jtwr) {
+  if (!m) return fail("null market");
+  const int P = market_params(m);
+  if (m->model >= 2 || P < 0) return fail("gradients need GLOBAL4 or LMM12");
+  std::vector<double> c((size_t)n_pts), g((size_t)n_pts * P);
+  if (oracle_cost_grad(m, n_pts, pt_inst, params, c.data(), g.data(), jtwj, jtwr)) return -1;
+  for (int i = 0; i < n_pts; ++i) {
+    if (cost) cost[i] = c[i];
+    const double s = g_cost ? g_cost[i] : 1.0;
+    for (int k = 0; k < P; ++k) g_params[(size_t)i * P + k] = s * g[(size_t)i * P + k];
+  }
+  return 0;
+}
+
 // Synchronous parallel simulated annealing (Sec. 3: the boxed SA loop, run by
 // many Markov chains; at the end of every temperature level all chains
 // restart from the final point with the lowest cost).

@@ -118,6 +118,21 @@ typedef struct {
  * chains: X [C][P], F [C], BX [C][P], BF [C] (current and best-ever points
  * and costs), T (the next level's temperature): 2 C (P + 1) + 1 doubles. */
 
+/* Mirrors of sabr_cost_batch and sabr_cost_vjp (include/sabr.h) with the
+ * same argument lists on host pointers, without stream and workspace:
+ * cost[i] (+inf on a domain failure, NaN for an out-of-range pt_inst[i]),
+ * resid and model (nullable) at [i*stride + q] in the caller's quote order
+ * (stride >= the largest instance's quote count); g_params[i*P + k] =
+ * g_cost[i] (nullable -> 1) * d cost_i / d p_k, jtwj and jtwr (nullable) as
+ * oracle_cost_grad.  oracle_sa_calibrate is the mirror of sa_calibrate (its
+ * last argument, n_evals, in place of the workspace and the stream). */
+int32_t oracle_sabr_cost_batch(const oracle_market *m, int32_t n_pts, const int32_t *pt_inst,
+                               const double *params, double *cost, double *resid, double *model,
+                               int32_t stride);
+int32_t oracle_sabr_cost_vjp(const oracle_market *m, int32_t n_pts, const int32_t *pt_inst,
+                             const double *params, const double *g_cost, double *cost,
+                             double *g_params, double *jtwj, double *jtwr);
+
 /* Synchronous parallel SA, chains[i] chains on instance i.
  * best_x [n_inst][P], best_f [n_inst]; nullable outputs:
  *   chain_best_x [sum chains][P], chain_best_f [sum chains]   (per-chain best ever)

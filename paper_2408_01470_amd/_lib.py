@@ -67,6 +67,8 @@ def lib():
             "g.build()'` (hipcc, gfx950)")
     L = ctypes.CDLL(LIB_PATH)
     L.sabr_last_error.restype = ctypes.c_char_p
+    L.sabr_shutdown.restype = ctypes.c_int32
+    L.sabr_shutdown.argtypes = []
     L.sabr_plan_create.argtypes = [ctypes.POINTER(SabrProblem), ctypes.POINTER(_vp)]
     L.sabr_plan_destroy.argtypes = [_vp]
     L.sabr_plan_destroy.restype = None

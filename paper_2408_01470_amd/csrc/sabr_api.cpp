@@ -103,6 +103,22 @@ extern "C" {
 
 const char *sabr_last_error(void) { return g_err.c_str(); }
 
+}  // extern "C"
+
+namespace sabr {
+// Clears the process-wide caches (LDS budget, scratch addresses; in the
+// kernels' file); the next use looks them up again.
+void forget_process_caches();
+}  // namespace sabr
+
+extern "C" {
+
+sabr_status sabr_shutdown(void) {
+  sabr::forget_process_caches();
+  g_err.clear();
+  return SABR_OK;
+}
+
 int32_t sabr_num_params(int32_t model) { return model == 0 ? 4 : (model == 1 ? 12 : -1); }
 
 sabr_status sabr_plan_create(const sabr_problem *pr, sabr_plan **out) {

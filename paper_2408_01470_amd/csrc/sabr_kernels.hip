@@ -567,8 +567,11 @@ hipError_t launch_prep(const DevMarket &m, QuoteRec *q, double *f_v, double *u_S
     }                                                                \
   } while (0)
 
+// The LDS budget of one workgroup, read from the device once (0: not yet).
+static int g_lds_budget = 0;
+
 int lds_budget_bytes() {
-  static int bytes = 0;
+  int bytes = __atomic_load_n(&g_lds_budget, __ATOMIC_RELAXED);
   if (bytes == 0) {
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
@@ -577,6 +580,7 @@ int lds_budget_bytes() {
       bytes = v;
     else
       bytes = 64 * 1024;
+    __atomic_store_n(&g_lds_budget, bytes, __ATOMIC_RELAXED);
   }
   return bytes;
 }
@@ -674,10 +678,13 @@ hipError_t launch_sa_final(const SAArgs &a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 static __device__ __align__(256) unsigned char scratch[kSaNoallocBytes];
 
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kMaxDevices] = {};   // the array's address on each device
+
 hipError_t sa_noalloc_scratch(void **ptr) {
-  constexpr int kMaxDevices = 64;
-  static std::mutex mu;
-  static void *per_dev[kMaxDevices] = {};
+  auto &mu = g_scratch_mu;
+  auto &per_dev = g_scratch_dev;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -692,6 +699,12 @@ hipError_t sa_noalloc_scratch(void **ptr) {
   }
   *ptr = per_dev[dev];
   return hipSuccess;
+}
+
+void forget_process_caches() {
+  __atomic_store_n(&g_lds_budget, 0, __ATOMIC_RELAXED);
+  std::lock_guard<std::mutex> guard(g_scratch_mu);
+  for (void *&p : g_scratch_dev) p = nullptr;
 }
 
 }  // namespace sabr

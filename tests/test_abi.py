@@ -174,3 +174,19 @@ def test_sa_split_chain_lds_refusal_without_gpu(L):
     assert L.sa_workspace_size(h, ctypes.byref(big), ch.ctypes.data_as(i32)) == 0
     assert "LDS" in L.sabr_last_error().decode()
     L.sabr_plan_destroy(h)
+
+
+def test_shutdown_forgets_process_state_without_gpu(L):
+    """sabr_shutdown clears the calling thread's last error and the library
+    keeps working after it (its caches are looked up again)."""
+    m, _, _ = I.caplet_market()
+    bad = dict(m)
+    bad["q_K"] = bad["q_K"].copy()
+    bad["q_K"][0] = -1.0
+    rc, _ = _create(L, bad)
+    assert rc == -1 and L.sabr_last_error().decode()
+    assert L.sabr_shutdown() == 0
+    assert L.sabr_last_error().decode() == ""
+    rc, h = _create(L, m)
+    assert rc == 0
+    L.sabr_plan_destroy(h)

@@ -71,3 +71,17 @@ def test_noalloc_refusals(c1_market):
     r = plan.sa(64, lb, ub, noalloc=True, **kw)
     torch.cuda.synchronize()
     assert np.isfinite(r["best_f"].item())
+
+
+def test_noalloc_after_shutdown(c1_market):
+    """sabr_shutdown forgets the scratch array's address; the next call looks
+    it up again and still matches sa_calibrate bit for bit."""
+    mk1, _ = c1_market
+    plan = api.Plan(mk1)
+    lb, ub = I.box(0)
+    kw = dict(T0=0.02, cool=0.8, n_levels=2, n_steps=10, seed=21)
+    first = _run(plan, 32, lb, ub, True, **kw)
+    assert _lib.lib().sabr_shutdown() == 0
+    again = _run(plan, 32, lb, ub, True, **kw)
+    _same(first, again)
+    _same(_run(plan, 32, lb, ub, False, **kw), again)
