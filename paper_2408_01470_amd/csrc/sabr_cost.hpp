@@ -38,11 +38,22 @@ struct NP<5> {   // LMM12, the swap column in 24 registers
 
 // Per-wave LDS scratch of the LMM12 map: per forward {alpha, nu, g1, g2, a}
 // (g1, g2: correlation factors of the gap to the next forward; a = v alpha,
-// the forward's term of the swap recursions); per underlying its SABR
-// constants; a per-lane column for long swap recursions.
+// the forward's term of the swap recursions) and the count of forwards
+// outside the domain (alpha > 0, nu >= 0) before it and up to it (two 32-bit
+// counts in one word, so a swap's check is one difference); per underlying
+// its SABR constants; a per-lane column for long swap recursions.
 struct FwdMap {
-  double al, nv, g1, g2, a, pad;
+  double al, nv, g1, g2, a, nbad;
 };
+__device__ __forceinline__ double pack_counts(int before, int upto) {
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)upto << 32) | (unsigned)before);
+}
+__device__ __forceinline__ int count_before(double c) {
+  return (int)(unsigned)__builtin_bit_cast(unsigned long long, c);
+}
+__device__ __forceinline__ int count_upto(double c) {
+  return (int)(unsigned)(__builtin_bit_cast(unsigned long long, c) >> 32);
+}
 static_assert(sizeof(FwdMap) == 48, "16-byte aligned LDS record");
 constexpr int kFwdMapDoubles = 6;
 
@@ -67,6 +78,14 @@ __device__ __forceinline__ UndMkt und_mkt(const DevMarket &m, int g) {
   return UndMkt{m.u_S0[g], m.u_A[g], T, sT, 1.0 / sT, m.model != 0 ? m.u_fp[g] : 0.0};
 }
 
+// The forward records of a swap from forward e on, as an LDS pointer: the
+// unrolled recursions below then address them with constant offsets.
+using FwdLds = __attribute__((address_space(3))) const FwdMap *;
+__device__ __forceinline__ FwdLds fwd_at(const FwdMap *fw, int e) {
+  using lcp = __attribute__((address_space(3))) const char *;
+  return (FwdLds)((lcp)fw + __umul24((unsigned)e, (unsigned)sizeof(FwdMap)));
+}
+
 // Moments of the frozen-weight map of one swap over forwards [e, e+n),
 // n >= 2, with a_j = v_j alpha_j and R_j = sum_l a_l rho_jl:
 //   V = sum_j a_j R_j, suma = sum_j a_j, b_j = a_j R_j nu_j, Sb = sum_j b_j,
@@ -76,56 +95,51 @@ __device__ __forceinline__ UndMkt und_mkt(const DevMarket &m, int g) {
 // backward.  Two storage variants of the per-lane column: registers for
 // swaps of up to kMapRegLen forwards (loops unrolled so every index is
 // static), an LDS column of max_len doubles per lane beyond that.
+// The forwards' domain (alpha > 0, nu >= 0) is checked once per forward by
+// the map (FwdMap::nbad), not here.
 struct SwapMoments {
   double V, suma, Sb, Sbb;
-  bool bad;
 };
 
 template <int NMAX>
 __device__ __forceinline__ SwapMoments swap_moments_reg(const FwdMap *fw, int e, int n) {
+  const FwdLds f = fwd_at(fw, e);
   double Lk[NMAX];
   double Lacc = 0.0, suma = 0.0;
-  bool bad = false;
 #pragma unroll
   for (int j = 0; j < NMAX; ++j) {
     if (j < n) {
-      const FwdMap F = fw[e + j];
-      bad |= !(F.al > 0.0) || !(F.nv >= 0.0);
-      const double aj = F.a;
+      const double aj = f[j].a;
       Lk[j] = Lacc;
       suma += aj;
-      Lacc = F.g1 * (Lacc + aj);
+      Lacc = f[j].g1 * (Lacc + aj);
     }
   }
   double Rr = 0.0, Rb = 0.0, V = 0.0, Sb = 0.0, Sbb = 0.0;
 #pragma unroll
   for (int j = NMAX - 1; j >= 0; --j) {
     if (j < n) {
-      const FwdMap F = fw[e + j];
-      const double aj = F.a;
+      const double aj = f[j].a;
       const double Rj = Lk[j] + aj + Rr;
       const double ar = aj * Rj;
       V += ar;
-      const double bj = ar * F.nv;
+      const double bj = ar * f[j].nv;
       Sb += bj;
       Sbb = fma(bj, fma(2.0, Rb, bj), Sbb);
       if (j > 0) {
-        const FwdMap G = fw[e + j - 1];
-        Rr = G.g1 * (Rr + aj);
-        Rb = G.g2 * (Rb + bj);
+        Rr = f[j - 1].g1 * (Rr + aj);
+        Rb = f[j - 1].g2 * (Rb + bj);
       }
     }
   }
-  return SwapMoments{V, suma, Sb, Sbb, bad};
+  return SwapMoments{V, suma, Sb, Sbb};
 }
 
 __device__ __forceinline__ SwapMoments swap_moments_lds(const FwdMap *fw, int e, int n,
                                                         double *lk) {
   double Lacc = 0.0, suma = 0.0;
-  bool bad = false;
   for (int j = 0; j < n; ++j) {
     const FwdMap F = fw[e + j];
-    bad |= !(F.al > 0.0) || !(F.nv >= 0.0);
     const double aj = F.a;
     lk[j * kWave] = Lacc;
     suma += aj;
@@ -147,7 +161,7 @@ __device__ __forceinline__ SwapMoments swap_moments_lds(const FwdMap *fw, int e,
       Rb = G.g2 * (Rb + bj);
     }
   }
-  return SwapMoments{V, suma, Sb, Sbb, bad};
+  return SwapMoments{V, suma, Sb, Sbb};
 }
 
 // SABR constants of one underlying with SABR parameters (alpha, rho, nu) and
@@ -207,23 +221,38 @@ __device__ inline bool lmm12_fwd(const DevMarket &m, const DevInst &in, const do
   const double rho = p[8], lam1 = p[9], eta2 = p[10], lam2 = p[11];
   const bool bad = !(fabs(rho) < 1.0) || !(lam1 >= 0.0) || !(lam2 >= 0.0) ||
                    !(eta2 >= 0.0 && eta2 <= 1.0);
-  for (int k = lane; k < in.nf; k += kWave) {
-    const double T = m.f_T[in.f0 + k];
-    FwdMap F;
-    F.al = fma(b, T, a) * exp_neg(-(c * T)) + d;
-    F.nv = fma(bn, T, an) * exp_neg(-(cn * T)) + dn;
-    F.a = m.f_v[in.f0 + k] * F.al;
-    F.pad = 0.0;
-    F.g1 = F.g2 = 0.0;
-    if (k + 1 < in.nf) {
-      const double dT = m.f_T[in.f0 + k + 1] - T;
-      F.g1 = exp_neg(-(lam1 * dT));
-      F.g2 = exp_neg(-(lam2 * dT));
+  int carry = 0;   // forwards outside the domain in earlier passes
+  for (int k0 = 0; k0 < in.nf; k0 += kWave) {   // wave-uniform: the counts need every lane
+    const int k = k0 + lane;
+    const bool live = k < in.nf;
+    FwdMap F{};
+    if (live) {
+      const double T = m.f_T[in.f0 + k];
+      F.al = fma(b, T, a) * exp_neg(-(c * T)) + d;
+      F.nv = fma(bn, T, an) * exp_neg(-(cn * T)) + dn;
+      F.a = m.f_v[in.f0 + k] * F.al;
+      if (k + 1 < in.nf) {
+        const double dT = m.f_T[in.f0 + k + 1] - T;
+        F.g1 = exp_neg(-(lam1 * dT));
+        F.g2 = exp_neg(-(lam2 * dT));
+      }
     }
-    w.fw[k] = F;
+    const bool out = live && (!(F.al > 0.0) || !(F.nv >= 0.0));
+    const uint64_t mask = __ballot(out);
+    const int before =
+        carry + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+    F.nbad = pack_counts(before, before + (out ? 1 : 0));
+    if (live) w.fw[k] = F;
+    carry += __popcll(mask);
   }
   wave_lds_sync();
   return bad;
+}
+
+// Whether a forward of [e, e+n) lies outside the domain (the map's counts).
+__device__ __forceinline__ bool fwd_out_of_domain(const FwdMap *fw, int e, int n) {
+  return count_upto(fw[e + n - 1].nbad) > count_before(fw[e].nbad);
 }
 
 // Underlying part for the underlyings [i0, i1) of the map's visiting order
@@ -254,7 +283,7 @@ __device__ inline bool lmm12_und(const DevMarket &m, const DevInst &in, const Un
       const SwapMoments S = (m.max_len <= REG) ? swap_moments_reg<REG>(w.fw, e, n)
                                                : swap_moments_lds(w.fw, e, n, lk);
       const double V = S.V, suma = S.suma, Sb = S.Sb, Sbb = S.Sbb;
-      bad |= S.bad;
+      bad |= fwd_out_of_domain(w.fw, e, n);
       const double Nb = fma(eta2 * Sb, Sb, (1.0 - eta2) * Sbb);
       const double sV = sqrt_gs(V), sN = sqrt_gs(Nb);
       ta = sV * m.u_c0[in.u0 + u];
