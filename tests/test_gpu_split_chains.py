@@ -100,3 +100,27 @@ def test_split_graph_replay_and_noalloc_match_eager(api, oracle):
         torch.cuda.synchronize()
         for k in keys:
             assert torch.equal(g[k], eager[k]), f"replay {rep}: {k}"
+
+
+@pytest.mark.parametrize("n_ten", [22, 30])
+def test_long_swaps_split_over_waves(api, oracle, n_ten):
+    """Swaps of 22 forwards (the 24-register swap column) and of 30 (the LDS
+    column, one per wave) with their quotes split over three waves."""
+    m, truth, noise = I.lmm_market(M=n_ten + 4, n_cap_K=3, n_exp=3, n_ten=n_ten, n_swp_K=3,
+                                   residual=I.RESID_PRICE)
+    vm = I.as_vol_market(m)
+    mv, _, _, ok = oracle.model_values(vm, 0, truth[0])
+    assert ok
+    mk = I.complete_market(m, mv, noise[:len(mv)])
+    assert max(mk["und_len"]) == n_ten
+    lb, ub = I.box(1)
+    x0 = np.clip(truth[0], lb, ub)
+    kw = dict(T0=0.02, cool=0.8, n_levels=3, n_steps=8, seed=29, x0=x0, record=True)
+    plan = api.Plan(mk)
+    g = plan.sa(6, lb, ub, chain_best=True, waves_per_chain=3, **kw)
+    torch.cuda.synchronize()
+    o = oracle.sa_calibrate(mk, 6, lb, ub, **kw)
+    where = first_mismatch(g["accept"].cpu().numpy(), o["accept"], 3, 8, [6])
+    assert where is None, f"first mismatch at {where}"
+    assert np.array_equal(g["level_best"].cpu().numpy(), o["level_best"])
+    np.testing.assert_allclose(g["best_f"].cpu().numpy(), o["best_f"], rtol=RTOL)
