@@ -303,7 +303,8 @@ __device__ __forceinline__ double black_otm_vega(double f, double K, double L, d
   const double d1 = fma(L * isigma, isqrtT, 0.5 * sd);
   const double d2 = d1 - sd;
   double E, X1, X2;
-  exp_erfcx2(-0.5 * d1 * d1, fabs(d1) * M_SQRT1_2, fabs(d2) * M_SQRT1_2, E, X1, X2);
+  const double x1 = fabs(d1) * M_SQRT1_2;   // black_otm's arithmetic
+  exp_erfcx2(-(x1 * x1), x1, fabs(d2) * M_SQRT1_2, E, X1, X2);
   const double hE = 0.5 * f * E;
   vega = D * f * E * (0.39894228040143267794 * sqrtT);
   if (L <= 0.0)
@@ -312,7 +313,7 @@ __device__ __forceinline__ double black_otm_vega(double f, double K, double L, d
 }
 
 // Relative sensitivities of sigma for one quote (Hagan 2002, beta fixed:
-// q = R.qa, D1 = R.qb), d sigma/d(alpha, rho, nu) = sigma (ra, rr, rn), with
+// q = R.qa, q^3 D1 = R.qb), d sigma/d(alpha, rho, nu) = sigma (ra, rr, rn), with
 // k the underlying's SABR constants:
 //   sigma = alpha Pq chi / (q^3 D1),  Pq = q^2 + T (ca + cb q + cc q^2),
 //   chi = z/x(z),  z = (nu/alpha) q L;

@@ -532,8 +532,8 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
     VolFrac vf;
     if (FORMULA == 0) {
       const double qv = (MODEL == 0) ? exp_cw(0.5 * omb * R.qa) : R.qa;
-      const double D1 = (MODEL == 0) ? d1_term(omb2, L) : R.qb;
-      vf = hagan2002_frac(k, L, qv, D1, U.T);
+      const double q3D1 = (MODEL == 0) ? qv * qv * qv * d1_term(omb2, L) : R.qb;
+      vf = hagan2002_frac(k, L, qv, q3D1, U.T);
     } else if (direct) {
       vf.numer = fma(-L, fma(-L, k.cc, k.cb), k.ca);
       vf.denom = 1.0;

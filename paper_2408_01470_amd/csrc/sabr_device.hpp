@@ -36,7 +36,8 @@ struct DevInst {
 
 // One quote.  qa/qb/qc hold the market-only factors of the vol formula:
 //   beta a parameter (GLOBAL4): qa = ln(f K), qb = 0, qc = ln f;
-//   beta fixed (LMM12):         qa = (f K)^((1-b)/2), qb = D1(L), qc = f^(1-b).
+//   beta fixed (LMM12):         qa = q = (f K)^((1-b)/2), qb = q^3 D1(L),
+//                               qc = f^(1-b).
 struct QuoteRec {
   double L;     // ln(f/K)
   double qa, qb;
@@ -464,7 +465,8 @@ constexpr double kZSeries = 0x1.0p-18;
 constexpr double kZFloor = 0x1.0p-60;
 
 // Hagan 2002 lognormal vol given L = ln(f/K), q = (f K)^((1-beta)/2),
-// D1 = 1 + (1-b)^2 L^2/24 + (1-b)^4 L^4/1920 and expiry T, as a fraction
+// q3D1 = q^3 D1 with D1 = 1 + (1-b)^2 L^2/24 + (1-b)^4 L^4/1920 (a quote's
+// constant when beta is fixed) and expiry T, as a fraction
 //   sigma = numer / denom,  numer = alpha corr q^2 chi_num,
 //                           denom = q^3 D1 chi_den,
 // with chi = z/x(z) = chi_num/chi_den.  s = sqrt(1 - 2 rho z + z^2) is
@@ -486,7 +488,7 @@ struct VolFrac {
 };
 
 __device__ __forceinline__ VolFrac hagan2002_frac(const SabrConst &k, double L, double q,
-                                                  double D1, double T) {
+                                                  double q3D1, double T) {
   const double z = k.nua * q * L;
   const double s = sqrt_gs(fma(z, z - 2.0 * k.rho, 1.0));
   const double az = fmax(fabs(z), kZFloor);
@@ -497,7 +499,7 @@ __device__ __forceinline__ VolFrac hagan2002_frac(const SabrConst &k, double L, 
   const double Pq = fma(q, q, T * fma(q, fma(q, k.cc, k.cb), k.ca));
   VolFrac v;
   v.numer = k.alpha * Pq * cn;
-  v.denom = q * q * q * D1 * cd;
+  v.denom = q3D1 * cd;
   return v;
 }
 
@@ -544,7 +546,8 @@ __device__ __forceinline__ double black_otm(double f, double K, double L, double
   const double d1 = fma(L * isigma, isqrtT, 0.5 * sd);
   const double d2 = d1 - sd;
   double E, X1, X2;
-  exp_erfcx2(-0.5 * d1 * d1, fabs(d1) * M_SQRT1_2, fabs(d2) * M_SQRT1_2, E, X1, X2);
+  const double x1 = fabs(d1) * M_SQRT1_2;   // -d1^2/2 = -x1^2
+  exp_erfcx2(-(x1 * x1), x1, fabs(d2) * M_SQRT1_2, E, X1, X2);
   const double hE = 0.5 * f * E;
   if (L <= 0.0)
     return D * (d1 <= 0.0 ? hE * (X1 - X2) : fma(-hE, X1 + X2, f));

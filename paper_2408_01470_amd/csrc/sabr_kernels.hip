@@ -47,8 +47,9 @@ __global__ void prep_kernel(DevMarket m, QuoteRec *q, double *f_v, double *u_S0b
     R.qb = 0.0;
     R.qc = log(f);
   } else {
-    R.qa = pow(f * K, 0.5 * omb);
-    R.qb = d1_term(omb * omb, L);
+    const double q = pow(f * K, 0.5 * omb);
+    R.qa = q;
+    R.qb = q * q * q * d1_term(omb * omb, L);
     R.qc = pow(f, omb);
   }
   const double vol = q_vol[i];

@@ -59,12 +59,13 @@ def hagan_quote(fixed_beta: bool) -> float:
     """Hagan 2002 vol fraction for one quote: z = (nu/alpha) q L (2),
     s = sqrt(1 - 2 rho z + z^2) (4), the log1p argument 2z/(s + 1 - z)
     (3 and a division), P = q^2 + T (ca + cb q + cc q^2) (7), the numerator
-    alpha P z (2) and denominator q^3 D1 x (4); with beta a parameter also
+    alpha P z (2) and the denominator (q^3 D1) x (1: q^3 D1 is the quote's
+    constant when beta is fixed); with beta a parameter also q^3 D1 (3),
     q = exp((1-b)/2 ln(fK)) (2) and D1 = 1 + u/24 + u^2/1920,
     u = (1-b)^2 L^2 (6).  The quotient is a reciprocal and a product."""
-    f = 22 + _e("sqrt") + _e("log1p") + _e("rcp")
+    f = 19 + _e("sqrt") + _e("log1p") + _e("rcp")
     if not fixed_beta:
-        f += 2 + _e("exp") + 6
+        f += 3 + 2 + _e("exp") + 6
     return f
 
 
@@ -82,10 +83,10 @@ def eq3_quote(fixed_beta: bool) -> float:
 def black_quote(direct: bool = False) -> float:
     """sigma and 1/sigma from the vol fraction (5 and one reciprocal; one
     reciprocal when the formula gives sigma itself), then the Black-76
-    out-of-the-money price: sd, d1, d2 (6), E = exp(-d1^2/2) (2), the two
-    erfcx arguments (2), f E/2 (2), the combination (3) and the discount
-    (1); the two erfcx share one reciprocal (erfcx2)."""
-    return (1 if direct else 5) + _e("rcp") + 16 + _e("exp") + _e("erfcx2")
+    out-of-the-money price: sd, d1, d2 (6), the two erfcx arguments
+    x = |d|/sqrt(2) (2), E = exp(-x1^2) (1), f E/2 (2), the combination (3)
+    and the discount (1); the two erfcx share one reciprocal (erfcx2)."""
+    return (1 if direct else 5) + _e("rcp") + 15 + _e("exp") + _e("erfcx2")
 
 
 RESIDUAL = 4.0   # r = m - target, acc += (w r) r
