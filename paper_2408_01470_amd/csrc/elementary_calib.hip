@@ -10,6 +10,13 @@
 // the FP64 FLOP per call is 64 (ADD + MUL + TRANS + 2 FMA) / n minus the
 // identical counts of the "copy" kernel (load, store, no arithmetic).  The
 // last kernel adds its three results (2 FLOP beyond the call).
+//
+// Then the FP64 rate the chip delivers: fma_peak_kernel runs eight
+// independent FMA chains per lane (enough to keep the VALU issuing every
+// cycle at any wave count) over a grid of many waves per SIMD; HIP events
+// time each launch and the program prints TFLOP/s next to the device's CU
+// count and rated clock.  Under rocprofv3 --kernel-trace --pmc GRBM_COUNT
+// the same launches give the clock the chip holds under pure FMA work.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -50,6 +57,69 @@ __global__ void elem_kernel(const double *__restrict__ x, const double *__restri
     r = E + X1 + X2;
   }
   out[i] = r;
+}
+
+constexpr int kPeakChains = 8;
+constexpr int kPeakIters = 4096;
+
+// 2 kPeakChains kPeakIters FLOP per lane: a <- a b + c on every chain, with
+// b just below 1 and c small so the values stay normal and bounded.  x holds
+// at least 512 doubles; every lane stores (so no chain is dead code) to
+// out[i mod n], n a power of two.
+__global__ void __launch_bounds__(256) fma_peak_kernel(const double *__restrict__ x,
+                                                       double *__restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double b = 1.0 - 0x1.0p-30 * x[threadIdx.x];
+  const double c = 0x1.0p-20 * x[threadIdx.x + 256];
+  double a[kPeakChains];
+#pragma unroll
+  for (int k = 0; k < kPeakChains; ++k) a[k] = x[(threadIdx.x + 37 * k) & 511];
+  for (int it = 0; it < kPeakIters; ++it) {
+#pragma unroll
+    for (int k = 0; k < kPeakChains; ++k) a[k] = fma(a[k], b, c);
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kPeakChains; ++k) s += a[k];
+  out[i & (n - 1)] = s;
+}
+
+int fma_peak(double *dx, double *dout, int n) {
+  hipDeviceProp_t prop;
+  CHECK(hipGetDeviceProperties(&prop, 0));
+  const int blocks = 16384, threads = 256;   // 65536 waves: 64 per SIMD of 1024
+  const double flop = 2.0 * kPeakChains * kPeakIters * (double)blocks * threads;
+  hipEvent_t e0, e1;
+  CHECK(hipEventCreate(&e0));
+  CHECK(hipEventCreate(&e1));
+  // about 2 s of launches: the clock ramps up over the first ones, so the
+  // figures are the mean and best of the second half
+  const int reps = 400;
+  std::vector<double> tfs(reps);
+  for (int r = 0; r < reps; ++r) {
+    CHECK(hipEventRecord(e0, 0));
+    hipLaunchKernelGGL(fma_peak_kernel, dim3(blocks), dim3(threads), 0, 0, dx, dout, n);
+    CHECK(hipGetLastError());
+    CHECK(hipEventRecord(e1, 0));
+    CHECK(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    CHECK(hipEventElapsedTime(&ms, e0, e1));
+    tfs[r] = flop / (ms * 1e-3) / 1e12;
+    if (r % 50 == 0 || r == reps - 1)
+      std::printf("fma_peak launch %d: %.3f ms, %.2f TFLOP/s\n", r, ms, tfs[r]);
+  }
+  double best = 0.0, sum = 0.0;
+  for (int r = reps / 2; r < reps; ++r) {
+    sum += tfs[r];
+    best = tfs[r] > best ? tfs[r] : best;
+  }
+  CHECK(hipEventDestroy(e0));
+  CHECK(hipEventDestroy(e1));
+  std::printf("fma_peak: %s (%s), %d CUs, rated clock %.0f MHz; FP64 FMA %.2f TFLOP/s mean, %.2f best "
+              "over the last %d of the launches (%.3e FLOP each)\n",
+              prop.name, prop.gcnArchName, prop.multiProcessorCount, prop.clockRate * 1e-3,
+              sum / (reps - reps / 2), best, reps - reps / 2, flop);
+  return 0;
 }
 
 int main() {
@@ -101,6 +171,7 @@ int main() {
     CHECK(hipDeviceSynchronize());
     std::printf("%s: %d calls\n", names[f], n);
   }
+  if (fma_peak(dx, dout, n) != 0) return 1;   // n = 2^20 >= 512, a power of two
   CHECK(hipFree(dx));
   CHECK(hipFree(dy));
   CHECK(hipFree(dout));
