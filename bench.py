@@ -62,6 +62,9 @@ def parse():
                     help="fixed register budget in waves per SIMD (with --waves)")
     ap.add_argument("--waves-per-chain", type=int, default=1,
                     help="fixed waves per chain (with --waves; > 1 splits each chain's quotes)")
+    ap.add_argument("--chains-per-wave", type=int, default=1,
+                    help="fixed chains per wave (with --waves; 2 pairs chains in half-waves, "
+                         "GLOBAL4 workloads)")
     return ap.parse_args()
 
 
@@ -226,7 +229,8 @@ def measured_traffic(config, shape):
         if (rec.get("source_sha256") == digest
                 and rec.get("waves_per_group") == shape.get("waves_per_group")
                 and rec.get("occupancy") == shape.get("occupancy")
-                and rec.get("waves_per_chain", 1) == shape.get("waves_per_chain", 1)):
+                and rec.get("waves_per_chain", 1) == shape.get("waves_per_chain", 1)
+                and rec.get("chains_per_wave", 1) == shape.get("chains_per_wave", 1)):
             return float(rec["traffic_bytes_per_launch"])
     return None
 
@@ -259,9 +263,10 @@ def time_to_rmse(api, W, I, autotune):
     if autotune:
         from paper_2408_01470_amd import autotune as AT
         t = AT.tune(plan, w.chains, lb, ub, w.n_steps,
-                    candidates=AT.CANDIDATES + AT.split_candidates(plan, w.chains))
+                    candidates=AT.CANDIDATES + AT.split_candidates(plan, w.chains) +
+                    AT.pair_candidates(plan, w.chains))
         shape = dict(waves=t["waves"], occupancy=t["occupancy"],
-                     waves_per_chain=t["waves_per_chain"])
+                     waves_per_chain=t["waves_per_chain"], chains_per_wave=t["chains_per_wave"])
     kw = dict(T0=T0, n_steps=w.n_steps, seed=w.seed, step_frac=w.step_frac, **shape)
     k = w.extra["polish"]
 
@@ -598,14 +603,17 @@ def measure_sa(api, W, I, flops, config, steps, warmup, autotune=True, fixed_sha
     tuned = None
     if fixed_shape is not None:
         kw.update(waves=fixed_shape["waves"], occupancy=fixed_shape["occupancy"],
-                  waves_per_chain=fixed_shape.get("waves_per_chain", 1))
+                  waves_per_chain=fixed_shape.get("waves_per_chain", 1),
+                  chains_per_wave=fixed_shape.get("chains_per_wave", 1))
     elif autotune:
         from paper_2408_01470_amd import autotune as AT
-        cand = TUNE_CANDIDATES.get(config, AT.CANDIDATES + AT.split_candidates(plan, w.chains))
+        cand = TUNE_CANDIDATES.get(config, AT.CANDIDATES + AT.split_candidates(plan, w.chains) +
+                                   AT.pair_candidates(plan, w.chains))
         tuned = AT.tune(plan, w.chains, lb, ub, w.n_steps, levels=3 if config == "c5" else 4,
                         candidates=cand)
         kw.update(waves=tuned["waves"], occupancy=tuned["occupancy"],
-                  waves_per_chain=tuned["waves_per_chain"])
+                  waves_per_chain=tuned["waves_per_chain"],
+                  chains_per_wave=tuned["chains_per_wave"])
     L = w.n_levels
     sampled = list(range(0, L, EVENT_STRIDE))
 
@@ -656,7 +664,8 @@ def measure_sa(api, W, I, flops, config, steps, warmup, autotune=True, fixed_sha
     achieved = flop_launch / avg_launch_s / 1e12
     best_f = results[-1]["best_f"].cpu().numpy()
     shape = {"waves_per_group": kw.get("waves", 0), "occupancy": kw.get("occupancy", 0),
-             "waves_per_chain": max(1, kw.get("waves_per_chain", 1))}
+             "waves_per_chain": max(1, kw.get("waves_per_chain", 1)),
+             "chains_per_wave": max(1, kw.get("chains_per_wave", 1))}
     return {
         "workload": w.name,
         "value": qe / (ms_per_step / 1e3),
@@ -715,7 +724,8 @@ def main():
         print(json.dumps(cost_and_adjoint(api, W, I, args.adjoint_config)))
         return
     fixed_shape = (dict(waves=args.waves, occupancy=args.occupancy or 1,
-                        waves_per_chain=args.waves_per_chain)
+                        waves_per_chain=args.waves_per_chain,
+                        chains_per_wave=args.chains_per_wave)
                    if args.waves is not None else None)
     if args.paper_e2_only:
         print(json.dumps(paper_e2(api, W, I, flops, not args.no_autotune, fixed_shape)))

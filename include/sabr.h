@@ -212,6 +212,14 @@ typedef struct {
                                 ignored.  The cost sums the waves' partials in wave order, so
                                 it may differ from the one-wave sum in the last bits.
                                 SABR_EINVAL when the waves' LDS does not fit a workgroup */
+  int32_t chains_per_wave;   /* 0 or 1: one chain per wave; 2: two chains per wave, one per
+                                half (32 lanes): each half proposes, prices the quotes 32 at a
+                                time and takes its Metropolis decision on its own, for many
+                                chains of few quotes (the per-step work and the last, partial
+                                pass of quotes are shared by two chains).  Same Philox streams
+                                and accept rules; the cost's lane sums run over 32 lanes, so it
+                                may differ from the one-wave sum in the last bits.  GLOBAL4
+                                plans only, and not with waves_per_chain > 1: SABR_EINVAL */
 } sa_config;
 
 /* Device workspace bytes sa_calibrate needs for these chain counts. */

@@ -127,7 +127,8 @@ class Plan:
 
     # ------------------------------------------------------------------
     def sa_config(self, T0, cool, n_levels, n_steps, seed, step_frac=0.05, T0_per_inst=None,
-                  waves=0, use_graph=False, level_events=None, occupancy=0, waves_per_chain=0):
+                  waves=0, use_graph=False, level_events=None, occupancy=0, waves_per_chain=0,
+                  chains_per_wave=0):
         t0i = None
         if T0_per_inst is not None:
             t0i = np.ascontiguousarray(T0_per_inst, dtype=np.float64)
@@ -143,7 +144,7 @@ class Plan:
                         int(seed), t0i.ctypes.data_as(_f64p) if t0i is not None else None,
                         int(waves), 1 if use_graph else 0,
                         ctypes.cast(ev, ctypes.POINTER(ctypes.c_void_p)) if ev is not None
-                        else None, int(occupancy), int(waves_per_chain))
+                        else None, int(occupancy), int(waves_per_chain), int(chains_per_wave))
 
     def sa_workspace_bytes(self, cfg, chains):
         ch = np.ascontiguousarray(np.broadcast_to(chains, (self.n_inst,)), dtype=np.int32)
@@ -167,17 +168,19 @@ class Plan:
     def sa(self, chains, lb, ub, T0, cool, n_levels, n_steps, seed, step_frac=0.05, x0=None,
            T0_per_inst=None, record=False, trace=True, chain_best=False, waves=0,
            use_graph=False, stream=None, workspace=None, out=None, level_events=None,
-           occupancy=0, noalloc=False, waves_per_chain=0):
+           occupancy=0, noalloc=False, waves_per_chain=0, chains_per_wave=0):
         """Synchronous parallel simulated annealing on every instance.  ``out``
         (a dict returned by an earlier call with the same shapes) reuses its
         output tensors, so a captured graph can be replayed.  noalloc: run
         through sa_calibrate_noalloc (the library's fixed device scratch, no
         workspace; the returned "workspace" is None).  waves_per_chain > 1:
-        each chain's quotes split over that many waves of one workgroup."""
+        each chain's quotes split over that many waves of one workgroup;
+        chains_per_wave = 2 (GLOBAL4): two chains per wave, one per half."""
         L = lib()
         n, P = self.n_inst, self.P
         cfg = self.sa_config(T0, cool, n_levels, n_steps, seed, step_frac, T0_per_inst, waves,
-                             use_graph, level_events, occupancy, waves_per_chain)
+                             use_graph, level_events, occupancy, waves_per_chain,
+                             chains_per_wave)
         ch = np.ascontiguousarray(np.broadcast_to(chains, (n,)), dtype=np.int32)
         lb = np.ascontiguousarray(np.broadcast_to(lb, (n, P)), dtype=np.float64)
         ub = np.ascontiguousarray(np.broadcast_to(ub, (n, P)), dtype=np.float64)

@@ -443,7 +443,7 @@ struct SALayout {
   size_t o_X, o_BX, o_BF, o_RX, o_RF, o_Tcur, o_tstart;
   size_t o_TF, o_TB, o_TI, o_TJ, o_TN;
   size_t total;
-  int n_tiles, waves, wpc, max_tiles;
+  int n_tiles, waves, wpc, cpw, max_tiles;
   int64_t tot_chains;
 };
 
@@ -461,10 +461,12 @@ SALayout sa_layout(const sabr_plan *P, const sa_config *cfg, const int32_t *chai
   shape.max_len = P->max_len;
   shape.reglen = reglen_for(P->max_len);
   shape.thchunk = sabr::th_chunk_for(P->max_nu);
-  // waves_per_chain > 1: one chain per workgroup, its waves split the quotes
+  // waves_per_chain > 1: one chain per workgroup, its waves split the quotes;
+  // chains_per_wave = 2: two chains per wave, one per half
   S.wpc = cfg && cfg->waves_per_chain > 1 ? cfg->waves_per_chain : 1;
-  S.waves = S.wpc > 1 ? S.wpc : sabr::sa_waves_per_group(shape, want);
-  const int cpt = S.waves / S.wpc;   // chains per tile
+  S.cpw = cfg && cfg->chains_per_wave == 2 ? 2 : 1;
+  S.waves = S.wpc > 1 ? S.wpc : sabr::sa_waves_per_group(shape, want, S.cpw == 2);
+  const int cpt = S.waves / S.wpc * S.cpw;   // chains per tile
   S.n_tiles = 0;
   S.max_tiles = 0;
   S.tot_chains = 0;
@@ -523,6 +525,13 @@ sabr_status check_sa_args(const sabr_plan *P, const sa_config *cfg, const int32_
     shape.thchunk = sabr::th_chunk_for(P->max_nu);
     if (sabr::sa_waves_per_group(shape, cfg->waves_per_chain) != cfg->waves_per_chain)
       return fail(SABR_EINVAL, "waves_per_chain: the waves' LDS exceeds one workgroup's");
+  }
+  if (cfg->chains_per_wave < 0 || cfg->chains_per_wave > 2)
+    return fail(SABR_EINVAL, "chains_per_wave outside [0, 2]");
+  if (cfg->chains_per_wave == 2) {
+    if (P->model != 0) return fail(SABR_EINVAL, "chains_per_wave = 2 needs a GLOBAL4 plan");
+    if (cfg->waves_per_chain > 1)
+      return fail(SABR_EINVAL, "chains_per_wave = 2 with waves_per_chain > 1");
   }
   for (int i = 0; i < P->n_inst; ++i) {
     if (chains[i] < 1) return fail(SABR_EINVAL, "every instance needs >= 1 chain");
@@ -599,7 +608,7 @@ sabr_status sa_run(sabr_plan *P, const sa_config *cfg, const int32_t *chains, co
     h_toff[i] = t;
     cb += chains[i];
     ab += (int64_t)L * N * chains[i];
-    for (int c = 0; c < chains[i]; c += S.waves / S.wpc) {
+    for (int c = 0; c < chains[i]; c += S.waves / S.wpc * S.cpw) {
       h_tinst[t] = i;
       h_tchain[t] = c;
       ++t;
@@ -626,6 +635,7 @@ sabr_status sa_run(sabr_plan *P, const sa_config *cfg, const int32_t *chains, co
   sabr::SAArgs a{};
   a.n_inst = n;
   a.wpc = S.wpc;
+  a.cpw = S.cpw;
   a.P = Pn;
   a.N = N;
   a.L = L;
@@ -699,7 +709,7 @@ sabr_status sa_run(sabr_plan *P, const sa_config *cfg, const int32_t *chains, co
                                (uint64_t)(uintptr_t)level_trace, (uint64_t)(uintptr_t)level_best,
                                (uint64_t)L, (uint64_t)N, cfg->seed, (uint64_t)S.waves,
                                (uint64_t)S.n_tiles, (uint64_t)cfg->occupancy,
-                               (uint64_t)S.wpc};
+                               (uint64_t)S.wpc, (uint64_t)S.cpw};
   uint64_t bits;
   std::memcpy(&bits, &cfg->step_frac, 8);
   key.push_back(bits);

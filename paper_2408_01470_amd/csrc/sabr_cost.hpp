@@ -490,13 +490,18 @@ __device__ bool reb_map(const DevMarket &m, const DevInst &in, const UndMkt *um,
 // Split evaluation: with nsub > 1 waves sharing the point, wave sub takes
 // the quotes of every nsub-th block of 64 (from block sub on) and returns
 // their partial sum (+inf on a domain failure); the map is every wave's.
-template <int MODEL, int FORMULA, int RESID>
+// PAIR (GLOBAL4 only): each half of the wave evaluates its own point (p[]
+// holds the half's coordinates) over the instance's quotes, 32 at a time,
+// and every lane gets its half's cost.
+template <int MODEL, int FORMULA, int RESID, bool PAIR = false>
 __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt *um,
                              const double *p, double xl, WaveLds w, double *resid,
                              double *model, int sub = 0, int nsub = 1) {
+  static_assert(!PAIR || MODEL == 0, "paired chains: the map must be per-lane arithmetic");
   constexpr bool LMM = (MODEL == 1 || MODEL == 5);   // 5: LMM12, 24-register swap column
   constexpr int REG = (MODEL == 5) ? 24 : kMapRegLen;
-  const int lane = lane_id();
+  // the lane's place among the lanes of its point
+  const int lane = PAIR ? (lane_id() & (kHalf - 1)) : lane_id();
   bool bad = false;
   SabrConst g{};
   double omb, omb2 = 0.0;
@@ -567,7 +572,7 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
   // global load latency hides behind the arithmetic), and no register copies
   // are needed between passes.
   const QuoteRec *qrec = m.q + in.q0;
-  const int qs = nsub * kWave;
+  const int qs = PAIR ? kHalf : nsub * kWave;
   auto quotes = [&](int qa, int qb, int toff) {
     QuoteRec Ra{}, Rb{};
     const int q0 = qa + sub * kWave + lane;
@@ -595,8 +600,8 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
   } else {
     quotes(0, in.nq, 0);
   }
-  const double tot = wave_sum(acc);
-  const bool any_bad = __any(bad);
+  const double tot = PAIR ? half_sum(acc) : wave_sum(acc);
+  const bool any_bad = PAIR ? half_any(bad) : __any(bad);
   return (any_bad || !(tot < kInf)) ? kInf : tot;
 }
 

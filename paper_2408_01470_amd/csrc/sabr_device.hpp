@@ -162,6 +162,34 @@ __device__ __forceinline__ double wave_sum(double v) {
   return readlane_d(v, kWave - 1);
 }
 
+// Paired chains: lanes 0-31 serve one chain, lanes 32-63 another.
+constexpr int kHalf = kWave / 2;
+
+// The value of lane k of the caller's half (k < 32), in every lane of it.
+__device__ __forceinline__ double half_lane(double v, int k) {
+  const double lo = readlane_d(v, k), hi = readlane_d(v, kHalf + k);
+  return (threadIdx.x & kHalf) ? hi : lo;
+}
+
+// Sum over each half of the wave (all lanes active), in every lane of that
+// half: the row sums of wave_sum's first four moves, then the broadcast of
+// lanes 15 and 47 into rows 1 and 3 leaves the halves' totals in lanes 31
+// and 63.
+__device__ __forceinline__ double half_sum(double v) {
+  v += dpp_d<0xB1>(v);        // quad_perm [1, 0, 3, 2]
+  v += dpp_d<0x4E>(v);        // quad_perm [2, 3, 0, 1]
+  v += dpp_d<0x141>(v);       // row_half_mirror
+  v += dpp_d<0x140>(v);       // row_mirror
+  v += dpp_d<0x142, 0xa>(v);  // row_bcast15 into rows 1 and 3
+  return half_lane(v, kHalf - 1);
+}
+
+// Whether any lane of the caller's half has b set.
+__device__ __forceinline__ bool half_any(bool b) {
+  const unsigned long long m = __ballot(b);
+  return ((threadIdx.x & kHalf) ? (m >> kHalf) : (m & 0xffffffffULL)) != 0;
+}
+
 // Element i of an array the caller knows to lie in LDS, addressed in 32 bits
 // (one 24-bit multiply, where the generic pointer's index takes a 64-bit
 // multiply-add); i * sizeof(T) < 2^24 always holds in LDS.

@@ -51,23 +51,30 @@ __host__ __device__ inline int kernel_model(const DevMarket &m) {
 
 // Steps whose uniforms one Philox pass of the annealing kernel produces: a
 // step takes P + 1 uniforms, the words of (P + 4) / 4 Philox blocks; lane l
-// computes block l mod nb of step l / nb, at most kUniSteps steps a pass, and
-// the uniforms wait in LDS.
+// of the chain's lanes (the wave, or its half for paired chains) computes
+// block l mod nb of step l / nb, at most kUniSteps steps a pass, and the
+// uniforms wait in LDS.
 constexpr int kUniSteps = 16;
 __host__ __device__ constexpr int uni_blocks(int P) { return (P + 4) / 4; }
-__host__ __device__ constexpr int uni_steps(int P) {
-  return kWave / uni_blocks(P) < kUniSteps ? kWave / uni_blocks(P) : kUniSteps;
+__host__ __device__ constexpr int uni_steps(int P, int lanes = kWave) {
+  return lanes / uni_blocks(P) < kUniSteps ? lanes / uni_blocks(P) : kUniSteps;
 }
 
 // Doubles of LDS per wave of the annealing kernels: the map's scratch and
-// uni_steps(P) x (P + 1) uniforms.
-__host__ __device__ inline int sa_wave_doubles(const DevMarket &m) {
-  return wave_lds_doubles(m) + uni_steps(m.np) * (m.np + 1);
+// uni_steps(P) x (P + 1) uniforms per chain of the wave (two with pair).
+__host__ __device__ inline int sa_wave_doubles(const DevMarket &m, bool pair = false) {
+  return wave_lds_doubles(m) +
+         (pair ? 2 * uni_steps(m.np, kHalf) : uni_steps(m.np)) * (m.np + 1);
 }
+
+// Paired chains (two chains per wave, one per half) need a map that is plain
+// per-lane arithmetic of the point and at most 32 coordinates: GLOBAL4.
+__host__ __device__ inline bool pair_capable(const DevMarket &m) { return m.model == 0; }
 
 struct SAArgs {
   int n_inst, P, N, L;
   int wpc;                      // waves per chain: 1, or every wave of a one-chain workgroup
+  int cpw;                      // chains per wave: 1, or 2 (one per half-wave; GLOBAL4)
   uint64_t seed;
   double step_frac, cool, ns_per_tick;
   const int *chains;            // [n_inst]
@@ -117,7 +124,8 @@ hipError_t launch_sa_final(const SAArgs &a, hipStream_t s);
 constexpr size_t kSaNoallocBytes = (size_t)64 << 20;
 hipError_t sa_noalloc_scratch(void **ptr);
 
-// Wavefronts per SA/cost workgroup that fit the LDS budget (at most `want`).
-int sa_waves_per_group(const DevMarket &m, int want);
+// Wavefronts per SA/cost workgroup that fit the LDS budget (at most `want`),
+// with one chain per wave or two (pair).
+int sa_waves_per_group(const DevMarket &m, int want, bool pair = false);
 
 }  // namespace sabr

@@ -168,24 +168,29 @@ __device__ __forceinline__ void wave_argmin(double &f, int &i, int C) {
 }
 
 // Level-end partial of one workgroup's chains (its waves hold consecutive
-// chains of one instance): lowest final cost (ties: lowest chain), lowest
-// best-ever cost, accepted moves.  Every wave of the workgroup calls it; a
-// wave without a chain passes c = C.
+// chains of one instance; with PAIR each half-wave holds one, in lane
+// order): lowest final cost (ties: lowest chain), lowest best-ever cost,
+// accepted moves.  Every wave of the workgroup calls it; a wave (half)
+// without a chain passes c = C.
+template <bool PAIR = false>
 __device__ void tile_partial(const SAArgs &a, int C, int c, double f, double bf, int nacc) {
-  __shared__ double red_f[kMaxWavesPerGroup], red_b[kMaxWavesPerGroup];
-  __shared__ int red_c[kMaxWavesPerGroup], red_n[kMaxWavesPerGroup];
+  constexpr int S = PAIR ? 2 : 1;   // chain slots per wave
+  __shared__ double red_f[S * kMaxWavesPerGroup], red_b[S * kMaxWavesPerGroup];
+  __shared__ int red_c[S * kMaxWavesPerGroup], red_n[S * kMaxWavesPerGroup];
   const int wid = threadIdx.x / kWave;
-  if (lane_id() == 0) {
-    red_f[wid] = f;
-    red_b[wid] = bf;
-    red_c[wid] = c;
-    red_n[wid] = nacc;
+  const int lane = lane_id();
+  if (lane == 0 || (PAIR && lane == kHalf)) {
+    const int v = S * wid + (PAIR ? lane / kHalf : 0);
+    red_f[v] = f;
+    red_b[v] = bf;
+    red_c[v] = c;
+    red_n[v] = nacc;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     double bestf = kInf, bestb = kInf;
     int bi = C, bj = C, na = 0;
-    for (int v = 0; v < (int)(blockDim.x / kWave); ++v) {   // chains in increasing order
+    for (int v = 0; v < S * (int)(blockDim.x / kWave); ++v) {   // chains in increasing order
       const int cv = red_c[v];
       if (cv >= C) continue;
       if (bi == C || red_f[v] < bestf) {   // strict: the lowest chain wins ties
@@ -305,31 +310,49 @@ __device__ __forceinline__ double split_total(double part, int sub, int nsub, in
   return t;
 }
 
+// The coordinates of the point whose lane k < P holds coordinate k, for
+// every lane of the chain: wave-uniform, or per half-wave with PAIR.
+template <int PC, bool PAIR>
+__device__ __forceinline__ void chain_params(double xl, double *p) {
+  if constexpr (PAIR) {
+#pragma unroll
+    for (int k = 0; k < PC; ++k) p[k] = half_lane(xl, k);
+  } else {
+    broadcast_params<PC>(xl, p);
+  }
+}
+
 // SPLIT: compiled for chains split over the waves of their workgroup
-// (a.wpc > 1); the one-wave-per-chain variant keeps no trace of it.
-template <int MODEL, int FORMULA, int RESID, bool SPLIT>
+// (a.wpc > 1); PAIR: two chains per wave, one per half (a.cpw = 2); the
+// one-wave-per-chain variant keeps no trace of either.
+template <int MODEL, int FORMULA, int RESID, bool SPLIT, bool PAIR>
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void sa_init_kernel(DevMarket m, SAArgs a,
                                                                              int lds_per_wave) {
+  static_assert(!(SPLIT && PAIR), "a chain spans waves or shares one, not both");
   extern __shared__ double smem[];
   constexpr int PC = NP<MODEL>::P;       // 0: known at run time (PERFWD)
   const int P = PC > 0 ? PC : a.P;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int lane = lane_id();
+  // the lane's place among its chain's lanes (the wave, or its half)
+  const int lane = PAIR ? (lane_id() & (kHalf - 1)) : lane_id();
   const int inst = a.tile_inst[blockIdx.x];
   const DevInst in = m.inst[inst];
   const UndMkt *um = stage_underlyings(m, in, smem);
   const int C = a.chains[inst];
   // SPLIT: the workgroup is one chain, its wpc waves split the quotes
   const int wpc = SPLIT ? a.wpc : 1;
-  const int c = a.tile_chain[blockIdx.x] + (SPLIT ? 0 : wid);
+  // the wave's first chain; with PAIR the upper half takes the next one
+  const int c0 = a.tile_chain[blockIdx.x] + (SPLIT ? 0 : (PAIR ? 2 * wid : wid));
+  const int c = c0 + (PAIR ? lane_id() / kHalf : 0);
   const int sub = SPLIT ? wid : 0;
   double f = kInf;
-  if (c < C) {   // wave-uniform (workgroup-uniform when wpc > 1)
+  if (c0 < C) {   // wave-uniform (workgroup-uniform when wpc > 1)
     const double xl = (lane < P) ? a.x0[(size_t)inst * P + lane] : 0.0;
     double x[PC > 0 ? PC : 1];
-    broadcast_params<PC>(xl, x);
+    chain_params<PC, PAIR>(xl, x);
     WaveLds w = wave_lds(m, smem + 6 * m.max_nu + (size_t)wid * lds_per_wave);
-    f = point_cost<MODEL, FORMULA, RESID>(m, in, um, x, xl, w, nullptr, nullptr, sub, wpc);
+    f = point_cost<MODEL, FORMULA, RESID, PAIR>(m, in, um, x, xl, w, nullptr, nullptr, sub,
+                                                 wpc);
     if (SPLIT) f = split_total(f, sub, wpc, 0);
   }
   if (c < C && sub == 0) {
@@ -349,23 +372,26 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void sa_init_kernel(DevM
       }
     }
   }
-  tile_partial(a, C, (c < C && sub == 0) ? c : C, f, f, 0);
+  tile_partial<PAIR>(a, C, (c < C && sub == 0) ? c : C, f, f, 0);
 }
 
 // OCC: minimum waves per SIMD the register allocation must allow (1 = the
-// compiler's choice); a tuning knob traded against spills.  SPLIT as for
-// sa_init_kernel.
-template <int MODEL, int FORMULA, int RESID, int OCC, bool SPLIT>
+// compiler's choice); a tuning knob traded against spills.  SPLIT and PAIR
+// as for sa_init_kernel.
+template <int MODEL, int FORMULA, int RESID, int OCC, bool SPLIT, bool PAIR>
 __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kernel(DevMarket m,
                                                                                  SAArgs a,
                                                                                  int level,
                                                             int lds_per_wave) {
+  static_assert(!(SPLIT && PAIR), "a chain spans waves or shares one, not both");
   extern __shared__ double smem[];
   constexpr int PC = NP<MODEL>::P;       // 0: known at run time (PERFWD)
   const int P = PC > 0 ? PC : a.P;
-  const int nb = uni_blocks(P), spp = uni_steps(P);
+  const int nb = uni_blocks(P), spp = uni_steps(P, PAIR ? kHalf : kWave);
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int lane = lane_id();
+  // the lane's place among its chain's lanes (the wave, or its half)
+  const int lane = PAIR ? (lane_id() & (kHalf - 1)) : lane_id();
+  const int half = PAIR ? lane_id() / kHalf : 0;
   const int inst = a.tile_inst[blockIdx.x];
   const DevInst in = m.inst[inst];
   const UndMkt *um = stage_underlyings(m, in, smem);
@@ -373,12 +399,17 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
   // SPLIT: the workgroup is one chain, its wpc waves split the quotes and
   // take the same steps; wave sub = 0 writes the chain's results
   const int wpc = SPLIT ? a.wpc : 1;
-  const int c = a.tile_chain[blockIdx.x] + (SPLIT ? 0 : wid);
+  // the wave's first chain; with PAIR the upper half takes the next one
+  const int c0 = a.tile_chain[blockIdx.x] + (SPLIT ? 0 : (PAIR ? 2 * wid : wid));
+  const int c = c0 + half;
+  // PAIR: the upper half of an instance's last wave may hold no chain; it
+  // steps along on its partner's records and writes nothing
+  const bool live = c < C;
   const int sub = SPLIT ? wid : 0;
   double f_end = kInf, bf_end = kInf;
   int nacc_end = 0;
-  if (c < C) {   // wave-uniform: waves past the instance's last chain have no work
-    const int64_t gc = a.chain_base[inst] + c;
+  if (c0 < C) {   // wave-uniform: waves past the instance's last chain have no work
+    const int64_t gc = a.chain_base[inst] + (live ? c : c0);
     // lane k < P holds coordinate k of the chain's point, best point and box
     const bool own = lane < P;
     double x = own ? a.RX[(size_t)inst * P + lane] : 0.0;
@@ -390,7 +421,8 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
     const double T = a.Tcur[inst];
     double *wbase = smem + 6 * m.max_nu + (size_t)wid * lds_per_wave;
     WaveLds w = wave_lds(m, wbase);
-    double *uw = wbase + wave_lds_doubles(m);   // [spp][P + 1] uniforms
+    // [spp][P + 1] uniforms of the chain (each half's own with PAIR)
+    double *uw = wbase + wave_lds_doubles(m) + half * spp * (P + 1);
     int nacc = 0;
     for (int s0 = 0; s0 < a.N; s0 += spp) {
       // Uniforms u_0..u_P of step s are the words of Philox blocks 0..P/4 of
@@ -418,9 +450,9 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
         const double u = lane <= P ? us[lane] : 0.0;
         const double xp = own ? propose1(x, u, lo, hi, a.step_frac) : 0.0;
         double p[PC > 0 ? PC : 1];
-        broadcast_params<PC>(xp, p);
-        double fp =
-            point_cost<MODEL, FORMULA, RESID>(m, in, um, p, xp, w, nullptr, nullptr, sub, wpc);
+        chain_params<PC, PAIR>(xp, p);
+        double fp = point_cost<MODEL, FORMULA, RESID, PAIR>(m, in, um, p, xp, w, nullptr,
+                                                             nullptr, sub, wpc);
         if (SPLIT) fp = split_total(fp, sub, wpc, s & 1);
         if (fp != fp) fp = kInf;
         const double uP = us[P];
@@ -429,7 +461,8 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
         // which exp_neg maps to 0: a rejection, as exp(NaN) would give).  The
         // exponent is the correctly rounded quotient -dE/T, one division a
         // step, so it carries no rounding beyond that of dE itself.
-        // (dE is wave-uniform: the exponential runs for uphill moves only)
+        // (dE is uniform over the chain's lanes: the exponential runs for
+        // uphill moves only)
         bool acc = dE <= 0.0;
         if (!acc) acc = uP < exp_neg(-dE / T);
         if (acc) {
@@ -437,7 +470,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
           f = fp;
           ++nacc;
         }
-        if (a.accept && lane == 0 && sub == 0)
+        if (a.accept && lane == 0 && sub == 0 && live)
           a.accept[a.acc_base[inst] + ((int64_t)level * a.N + s) * C + c] = acc ? 1 : 0;
         if (fp < bf) {
           bf = fp;
@@ -446,18 +479,18 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
       }
       wave_lds_sync();   // the next chunk overwrites the uniforms
     }
-    if (own && sub == 0) {
+    if (own && sub == 0 && live) {
       a.X[gc * P + lane] = x;
       a.BX[gc * P + lane] = bx;
     }
-    if (lane == 0 && sub == 0) {
+    if (lane == 0 && sub == 0 && live) {
       a.BF[gc] = bf;
     }
     f_end = f;
     bf_end = bf;
     nacc_end = nacc;
   }
-  tile_partial(a, C, (c < C && sub == 0) ? c : C, f_end, bf_end, nacc_end);
+  tile_partial<PAIR>(a, C, (live && sub == 0) ? c : C, f_end, bf_end, nacc_end);
 }
 
 // Level end, one workgroup per instance: argmin of the final costs (ties ->
@@ -586,13 +619,13 @@ int lds_budget_bytes() {
   return bytes;
 }
 
-size_t sa_lds_bytes(const DevMarket &m, int waves) {
-  return (size_t)(6 * m.max_nu + waves * sa_wave_doubles(m)) * 8;
+size_t sa_lds_bytes(const DevMarket &m, int waves, bool pair) {
+  return (size_t)(6 * m.max_nu + waves * sa_wave_doubles(m, pair)) * 8;
 }
 
-int sa_waves_per_group(const DevMarket &m, int want) {
+int sa_waves_per_group(const DevMarket &m, int want, bool pair) {
   int w = want;
-  while (w > 1 && (long)sa_lds_bytes(m, w) > lds_budget_bytes()) --w;
+  while (w > 1 && (long)sa_lds_bytes(m, w, pair) > lds_budget_bytes()) --w;
   return w;
 }
 
@@ -616,47 +649,84 @@ hipError_t launch_cost(const DevMarket &m, int n_pts, const int *pt_inst, const 
   return hipGetLastError();
 }
 
+// One annealing kernel launch; the paired-chain variants exist for GLOBAL4
+// only (the host refuses two chains per wave for the other models).
+template <int A, int B, int C, bool SP, bool PR>
+hipError_t init_launch(dim3 g, dim3 blk, size_t lds, hipStream_t s, const DevMarket &m,
+                       const SAArgs &a, int ld) {
+  if constexpr (PR && A != 0) {
+    return hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((sa_init_kernel<A, B, C, SP, PR>), g, blk, lds, s, m, a, ld);
+    return hipGetLastError();
+  }
+}
+
+template <int A, int B, int C, int O, bool SP, bool PR>
+hipError_t level_launch(dim3 g, dim3 blk, size_t lds, hipStream_t s, const DevMarket &m,
+                        const SAArgs &a, int level, int ld) {
+  if constexpr (PR && A != 0) {
+    return hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((sa_level_kernel<A, B, C, O, SP, PR>), g, blk, lds, s, m, a, level, ld);
+    return hipGetLastError();
+  }
+}
+
 hipError_t launch_sa_init(const DevMarket &m, const SAArgs &a, int n_tiles, int waves,
                           hipStream_t s) {
-  const int ld = sa_wave_doubles(m);
-  const size_t lds = sa_lds_bytes(m, waves);
-#define CALL(A, B, C)                                                                      \
-  do {                                                                                      \
-    if (a.wpc > 1)                                                                          \
-      hipLaunchKernelGGL((sa_init_kernel<A, B, C, true>), dim3(n_tiles), dim3(kWave * waves), \
-                         lds, s, m, a, ld);                                                 \
-    else                                                                                    \
-      hipLaunchKernelGGL((sa_init_kernel<A, B, C, false>), dim3(n_tiles),                   \
-                         dim3(kWave * waves), lds, s, m, a, ld);                            \
+  const bool pair = a.cpw == 2;
+  const int ld = sa_wave_doubles(m, pair);
+  const size_t lds = sa_lds_bytes(m, waves, pair);
+  const dim3 g(n_tiles), blk(kWave * waves);
+  hipError_t e = hipSuccess;
+#define CALL(A, B, C)                                                \
+  do {                                                               \
+    if (a.wpc > 1)                                                   \
+      e = init_launch<A, B, C, true, false>(g, blk, lds, s, m, a, ld); \
+    else if (pair)                                                   \
+      e = init_launch<A, B, C, false, true>(g, blk, lds, s, m, a, ld); \
+    else                                                             \
+      e = init_launch<A, B, C, false, false>(g, blk, lds, s, m, a, ld); \
   } while (0)
   SABR_SELECT(kernel_model(m), m.formula, m.residual, CALL);
 #undef CALL
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_sa_level(const DevMarket &m, const SAArgs &a, int level, int n_tiles,
                            int waves, int occupancy, hipStream_t s) {
-  const int ld = sa_wave_doubles(m);
-  const size_t lds = sa_lds_bytes(m, waves);
-#define LAUNCH(A, B, C, O, SP)                                                            \
-  hipLaunchKernelGGL((sa_level_kernel<A, B, C, O, SP>), dim3(n_tiles), dim3(kWave * waves), \
-                     lds, s, m, a, level, ld)
+  const bool pair = a.cpw == 2;
+  const int ld = sa_wave_doubles(m, pair);
+  const size_t lds = sa_lds_bytes(m, waves, pair);
+  const dim3 g(n_tiles), blk(kWave * waves);
+  hipError_t e = hipSuccess;
+#define LAUNCH(A, B, C, O, SP, PR) \
+  e = level_launch<A, B, C, O, SP, PR>(g, blk, lds, s, m, a, level, ld)
   // split chains are few (latency-bound): one register budget serves them
+#define BY_OCC(A, B, C, PR)             \
+  do {                                  \
+    if (occupancy >= 4)                 \
+      LAUNCH(A, B, C, 4, false, PR);    \
+    else if (occupancy == 3)            \
+      LAUNCH(A, B, C, 3, false, PR);    \
+    else                                \
+      LAUNCH(A, B, C, 1, false, PR);    \
+  } while (0)
 #define CALL(A, B, C)                   \
   do {                                  \
     if (a.wpc > 1)                      \
-      LAUNCH(A, B, C, 1, true);         \
-    else if (occupancy >= 4)            \
-      LAUNCH(A, B, C, 4, false);        \
-    else if (occupancy == 3)            \
-      LAUNCH(A, B, C, 3, false);        \
+      LAUNCH(A, B, C, 1, true, false);  \
+    else if (pair)                      \
+      BY_OCC(A, B, C, true);            \
     else                                \
-      LAUNCH(A, B, C, 1, false);        \
+      BY_OCC(A, B, C, false);           \
   } while (0)
   SABR_SELECT(kernel_model(m), m.formula, m.residual, CALL);
 #undef CALL
+#undef BY_OCC
 #undef LAUNCH
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_sa_level_end(const SAArgs &a, int level, int max_tiles, hipStream_t s) {

@@ -190,3 +190,36 @@ def test_shutdown_forgets_process_state_without_gpu(L):
     rc, h = _create(L, m)
     assert rc == 0
     L.sabr_plan_destroy(h)
+
+
+def test_sa_paired_chain_refusals_without_gpu(L):
+    """chains_per_wave: 2 pairs two GLOBAL4 chains in one wave and halves the
+    workgroups (tiles) of the workspace; other values, other models and the
+    combination with split chains are refused by name."""
+    from paper_2408_01470_amd._lib import SAConfig
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    m = I.caplet_market()[0]
+    rc, h = _create(L, m)
+    assert rc == 0
+    ch = np.array([4096], np.int32)
+    one = SAConfig(1.0, 0.9, 0.05, 10, 10, 1, None, 4, 0, None, 0, 1, 1)
+    two = SAConfig(1.0, 0.9, 0.05, 10, 10, 1, None, 4, 0, None, 0, 1, 2)
+    s1 = L.sa_workspace_size(h, ctypes.byref(one), ch.ctypes.data_as(i32))
+    s2 = L.sa_workspace_size(h, ctypes.byref(two), ch.ctypes.data_as(i32))
+    # 4096 chains: 1024 tiles of 4 waves, or 512 of 4 paired waves; each
+    # tile holds 2 doubles and 3 ints of level-end partials
+    assert s1 > 0 and s2 > 0
+    assert s1 - s2 >= 512 * (2 * 8 + 3 * 4) - 5 * 256
+    for cpw in (-1, 3):
+        bad = SAConfig(1.0, 0.9, 0.05, 10, 10, 1, None, 4, 0, None, 0, 1, cpw)
+        assert L.sa_workspace_size(h, ctypes.byref(bad), ch.ctypes.data_as(i32)) == 0
+        assert "chains_per_wave" in L.sabr_last_error().decode()
+    both = SAConfig(1.0, 0.9, 0.05, 10, 10, 1, None, 4, 0, None, 0, 2, 2)
+    assert L.sa_workspace_size(h, ctypes.byref(both), ch.ctypes.data_as(i32)) == 0
+    assert "waves_per_chain" in L.sabr_last_error().decode()
+    L.sabr_plan_destroy(h)
+    rc, h = _create(L, I.lmm_market()[0])
+    assert rc == 0
+    assert L.sa_workspace_size(h, ctypes.byref(two), ch.ctypes.data_as(i32)) == 0
+    assert "GLOBAL4" in L.sabr_last_error().decode()
+    L.sabr_plan_destroy(h)

@@ -67,7 +67,8 @@ def _report(plan, oracle, mk, w, chains, lb, ub, T0s, cool, where):
                     cool, w.n_steps, w.seed, w.step_frac, where)
 
 
-def _full_schedule(api, oracle, w, chains, waves, waves_per_chain=0, n_levels=None):
+def _full_schedule(api, oracle, w, chains, waves, waves_per_chain=0, n_levels=None,
+                   chains_per_wave=0):
     mk, T0s, cool = _workload(oracle, w)
     lb, ub = I.box(w.model)
     L, N = n_levels or w.n_levels, w.n_steps
@@ -77,7 +78,7 @@ def _full_schedule(api, oracle, w, chains, waves, waves_per_chain=0, n_levels=No
           flush=True)
     plan = api.Plan(mk)
     g = plan.sa(chains, lb, ub, record=True, chain_best=True, waves=waves,
-                waves_per_chain=waves_per_chain, **kw)
+                waves_per_chain=waves_per_chain, chains_per_wave=chains_per_wave, **kw)
     o = oracle.sa_calibrate(mk, chains, lb, ub, record=True, **kw)
     acc = g["accept"].cpu().numpy()
     where = first_mismatch(acc, o["accept"], L, N, [chains])
@@ -106,7 +107,7 @@ def test_c2_market_full_schedule_accept_parity(api, oracle):
     _full_schedule(api, oracle, w, 64, 8)
 
 
-def _sampled_instances(api, oracle, w, sample, waves, occupancy, n_levels=2):
+def _sampled_instances(api, oracle, w, sample, waves, occupancy, n_levels=2, chains_per_wave=0):
     mk, T0s, cool = _workload(oracle, w)
     lb, ub = I.box(w.model)
     L, N, C = n_levels, w.n_steps, w.chains
@@ -114,7 +115,7 @@ def _sampled_instances(api, oracle, w, sample, waves, occupancy, n_levels=2):
     print(f"{w.name}: full size, {L} levels, sampled instances {sample}", flush=True)
     plan = api.Plan(mk)
     g = plan.sa(C, lb, ub, T0=T0s[0], T0_per_inst=T0s, record=True, chain_best=True,
-                waves=waves, occupancy=occupancy, **kw)
+                waves=waves, occupancy=occupancy, chains_per_wave=chains_per_wave, **kw)
     torch.cuda.synchronize()
     acc = g["accept"].cpu().numpy()
     lbest = g["level_best"].cpu().numpy()
