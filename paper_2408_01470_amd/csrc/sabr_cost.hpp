@@ -383,16 +383,26 @@ __device__ bool mm_map(const DevMarket &m, const DevInst &in, const UndMkt *um, 
 // e^{-k u} du (m = 0, 1, 2) at k = c and k = 2c.  With psi_m(z) =
 // int_0^1 s^m e^{-z s} ds, I_m = x^{m+1} psi_m(kx); psi_2 by its series
 // sum_j (-z)^j / (j! (j + 3)) when z < 1/2 (17 terms: truncation < 1e-19),
-// else (2 - e^{-z} (2 + 2z + z^2)) / z^3, and psi_1, psi_0 by the downward
+// a polynomial in -z evaluated by Horner's rule, else
+// (2 - e^{-z} (2 + 2z + z^2)) / z^3, and psi_1, psi_0 by the downward
 // recurrence psi_{m-1} = (z psi_m + e^{-z}) / m, stable for every z >= 0.
 // e1 = e^{-c x} is passed in (e^{-2cx} = e1^2).
-__device__ __forceinline__ void psi012(double z, double e, double &p0, double &p1, double &p2) {
-  double t = 1.0, s = 0.0;
-#pragma unroll
-  for (int j = 0; j < 17; ++j) {   // sum_j (-z)^j / (j! (j + 3))
-    s = fma(t, 1.0 / (double)(j + 3), s);
-    t = t * (-z) * (1.0 / (double)(j + 1));
-  }
+constexpr double psi2_series_coef(int j) {
+  double f = 1.0;   // j!, exact in double for j <= 16
+  for (int i = 2; i <= j; ++i) f *= i;
+  return 1.0 / (f * (j + 3));
+}
+constexpr int kPsi2Deg = 16;
+constexpr double kPsi2Series[kPsi2Deg + 1] = {
+    psi2_series_coef(0),  psi2_series_coef(1),  psi2_series_coef(2),  psi2_series_coef(3),
+    psi2_series_coef(4),  psi2_series_coef(5),  psi2_series_coef(6),  psi2_series_coef(7),
+    psi2_series_coef(8),  psi2_series_coef(9),  psi2_series_coef(10), psi2_series_coef(11),
+    psi2_series_coef(12), psi2_series_coef(13), psi2_series_coef(14), psi2_series_coef(15),
+    psi2_series_coef(16)};
+
+// psi_0, psi_1, psi_2 at z >= 0 given e = e^{-z} and the series value s.
+__device__ __forceinline__ void psi012(double z, double e, double s, double &p0, double &p1,
+                                       double &p2) {
   const double iz = rcp_nr(z);
   const double big = (2.0 - e * fma(z, z + 2.0, 2.0)) * (iz * iz * iz);
   p2 = (z < 0.5) ? s : big;
@@ -402,9 +412,12 @@ __device__ __forceinline__ void psi012(double z, double e, double &p0, double &p
 
 __device__ __forceinline__ double abcd_sq_int(double a, double b, double c, double d, double x,
                                               double e1) {
+  const double z2 = 2.0 * c * x, z1 = c * x;
+  double s2, s1;   // the two series, their Horner chains interleaved
+  horner2_s<kPsi2Series, kPsi2Deg>(-z2, -z1, s2, s1, std::make_index_sequence<kPsi2Deg>{});
   double p0, p1, p2, q0, q1, q2;
-  psi012(2.0 * c * x, e1 * e1, p0, p1, p2);
-  psi012(c * x, e1, q0, q1, q2);
+  psi012(z2, e1 * e1, s2, p0, p1, p2);
+  psi012(z1, e1, s1, q0, q1, q2);
   // a^2 I0(2c) + 2ab I1(2c) + b^2 I2(2c) + 2d (a I0(c) + b I1(c)) + d^2 x
   const double t2 = x * fma(a * a, p0, x * fma(2.0 * a * b, p1, x * (b * b) * p2));
   const double t1 = 2.0 * d * x * fma(a, q0, b * x * q1);

@@ -141,10 +141,10 @@ def map_flops_inst(market: dict, inst: int) -> float:
 
 
 # Square integral of an abcd function (abcd_sq_int): two psi triples (the
-# 17-term series 51, the closed form 10 with a reciprocal, the downward
-# recurrence 4) at 2cx and cx sharing one exponential (given), and the
-# combination (14).
-SQ_INT = 2 * (51 + 10 + _e("rcp") + 4) + 14
+# 17-term series by Horner's rule, 16 fma = 32, the closed form 10 with a
+# reciprocal, the downward recurrence 4) at 2cx and cx sharing one
+# exponential (given), and the combination (14).
+SQ_INT = 2 * (32 + 10 + _e("rcp") + 4) + 14
 
 
 def num_params(market: dict) -> int:
