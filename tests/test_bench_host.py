@@ -3,7 +3,7 @@ records of the level kernel's counter profile, and the accounting behind
 roofline.achieved -- the algorithmic FLOP of flops.py against the FP64
 operations the hardware counters executed, as committed under profiles/
 (executed may exceed algorithmic by at most 1.5x, and the algorithmic count
-may not exceed what ran)."""
+may not exceed what ran), and the launch shapes the autotuner proposes."""
 import os
 import re
 import subprocess
@@ -74,3 +74,31 @@ def test_monte_carlo_flop_accounting():
     alg = flops.mc_launch_flops(I.paper_mc_problem(), 10**6, 1e-3)
     ex = _executed("mc_kernel_paper_table.md", "T") * 1e12
     assert 0.98 <= ex / alg <= 1.5, (ex, alg)
+
+
+class _PlanShape:
+    """The attributes of api.Plan the tuner's candidate lists read."""
+
+    def __init__(self, n_inst, max_q, model):
+        self.n_inst, self.max_q, self.model = n_inst, max_q, model
+
+
+def test_autotune_split_and_pair_candidates():
+    """Split shapes (several waves per chain) only when the chains leave most
+    of the 1024 SIMDs idle and a chain has two or more blocks of 64 quotes;
+    paired shapes (two chains per wave) only for GLOBAL4 plans whose chains
+    fill the chip four times over."""
+    from paper_2408_01470_amd import autotune as AT
+    c1 = _PlanShape(1, 110, 0)
+    assert AT.split_candidates(c1, 64) == ((2, 1, 2), (2, 3, 2))
+    assert AT.pair_candidates(c1, 64) == ()
+    assert AT.split_candidates(_PlanShape(1, 60, 0), 64) == ()          # one block of quotes
+    assert AT.split_candidates(_PlanShape(1, 985, 1), 4096) == ()        # the chip is full
+    wide = AT.split_candidates(_PlanShape(1, 8838, 1), 64)
+    assert {k for k, _, _ in wide} == {2, 4, 8} and all(w == k for w, _, k in wide)
+    c3 = _PlanShape(256, 585, 0)
+    pairs = AT.pair_candidates(c3, 1024)
+    assert pairs and all(len(p) == 4 and p[2] == 1 and p[3] == 2 for p in pairs)
+    assert AT.pair_candidates(_PlanShape(64, 8838, 1), 8192) == ()       # LMM12: no pairing
+    assert AT.pair_candidates(_PlanShape(1, 110, 0), 512) == ()          # too few chains
+    assert AT.split_candidates(c3, 1024) == ()
