@@ -217,9 +217,10 @@ typedef struct {
                                 time and takes its Metropolis decision on its own, for many
                                 chains of few quotes (the per-step work and the last, partial
                                 pass of quotes are shared by two chains).  Same Philox streams
-                                and accept rules; the cost's lane sums run over 32 lanes, so it
-                                may differ from the one-wave sum in the last bits.  GLOBAL4
-                                plans only, and not with waves_per_chain > 1: SABR_EINVAL */
+                                and accept rules, and the same results bit for bit: each half
+                                keeps the partial sums of the 64 lanes one wave would use and
+                                adds them in the same order.  GLOBAL4 plans only, and not with
+                                waves_per_chain > 1: SABR_EINVAL */
 } sa_config;
 
 /* Device workspace bytes sa_calibrate needs for these chain counts. */

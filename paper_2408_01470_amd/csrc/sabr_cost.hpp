@@ -505,7 +505,10 @@ __device__ bool reb_map(const DevMarket &m, const DevInst &in, const UndMkt *um,
 // their partial sum (+inf on a domain failure); the map is every wave's.
 // PAIR (GLOBAL4 only): each half of the wave evaluates its own point (p[]
 // holds the half's coordinates) over the instance's quotes, 32 at a time,
-// and every lane gets its half's cost.
+// and every lane gets its half's cost, bit for bit the cost one wave gives:
+// half-lane l stands for wave lanes l (the even passes) and l + 32 (the odd
+// ones), keeps their two partial sums apart and adds them in wave_sum's
+// order (half_sum2).
 template <int MODEL, int FORMULA, int RESID, bool PAIR = false>
 __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt *um,
                              const double *p, double xl, WaveLds w, double *resid,
@@ -537,9 +540,9 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
     bad = reb_map<FORMULA>(m, in, um, xl, w);
     omb = 1.0 - m.beta;
   }
-  double acc = 0.0;
+  double acc = 0.0, acc_hi = 0.0;   // acc_hi: PAIR's odd passes (wave lanes 32-63)
   const int *qx = m.q_ext + in.q0;   // per-quote outputs go to the caller's order
-  auto quote = [&](const QuoteRec &R, int q, int toff) {
+  auto quote = [&](const QuoteRec &R, int q, int toff, double &acc) {
     const double L = R.L;
     const int u = R.und;
     const UndMkt U = lds_elem(um, u);
@@ -592,10 +595,10 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
     if (q0 < qb) Ra = glb_elem(qrec, q0);
     for (int q = q0; q < qb; q += 2 * qs) {
       if (q + qs < qb) Rb = glb_elem(qrec, q + qs);
-      quote(Ra, q, toff);
+      quote(Ra, q, toff, acc);
       if (q + qs >= qb) break;
       if (q + 2 * qs < qb) Ra = glb_elem(qrec, q + 2 * qs);
-      quote(Rb, q + qs, toff);
+      quote(Rb, q + qs, toff, PAIR ? acc_hi : acc);
     }
   };
   if (LMM) {
@@ -613,7 +616,7 @@ __device__ double point_cost(const DevMarket &m, const DevInst &in, const UndMkt
   } else {
     quotes(0, in.nq, 0);
   }
-  const double tot = PAIR ? half_sum(acc) : wave_sum(acc);
+  const double tot = PAIR ? half_sum2(acc, acc_hi) : wave_sum(acc);
   const bool any_bad = PAIR ? half_any(bad) : __any(bad);
   return (any_bad || !(tot < kInf)) ? kInf : tot;
 }

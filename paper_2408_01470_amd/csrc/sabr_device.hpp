@@ -171,17 +171,27 @@ __device__ __forceinline__ double half_lane(double v, int k) {
   return (threadIdx.x & kHalf) ? hi : lo;
 }
 
-// Sum over each half of the wave (all lanes active), in every lane of that
-// half: the row sums of wave_sum's first four moves, then the broadcast of
-// lanes 15 and 47 into rows 1 and 3 leaves the halves' totals in lanes 31
-// and 63.
-__device__ __forceinline__ double half_sum(double v) {
+// Sums over the 16-lane rows (all lanes active): the first four moves of
+// wave_sum, after which every lane of a row holds the row's sum.
+__device__ __forceinline__ double row_sums(double v) {
   v += dpp_d<0xB1>(v);        // quad_perm [1, 0, 3, 2]
   v += dpp_d<0x4E>(v);        // quad_perm [2, 3, 0, 1]
   v += dpp_d<0x141>(v);       // row_half_mirror
   v += dpp_d<0x140>(v);       // row_mirror
-  v += dpp_d<0x142, 0xa>(v);  // row_bcast15 into rows 1 and 3
-  return half_lane(v, kHalf - 1);
+  return v;
+}
+
+// For each half of the wave, the wave_sum of the 64 values whose lanes 0-31
+// are the half's lo and lanes 32-63 its hi, bit for bit (IEEE addition
+// commutes): wave_sum adds rows 0 + 1 and rows 2 + 3 (row_bcast15), then the
+// two pairs (row_bcast31); here lo's and hi's rows stand for rows 0, 1 and
+// 2, 3.  Every lane of the half gets its total.
+__device__ __forceinline__ double half_sum2(double lo, double hi) {
+  lo = row_sums(lo);
+  hi = row_sums(hi);
+  lo += dpp_d<0x142, 0xa>(lo);  // row_bcast15 into rows 1 and 3
+  hi += dpp_d<0x142, 0xa>(hi);
+  return half_lane(hi + lo, kHalf - 1);
 }
 
 // Whether any lane of the caller's half has b set.
