@@ -5,8 +5,9 @@ decision of Sec. 3's SA box.  The accept/reject sequences must match the
 oracle's over the whole c1 schedule, on sampled instances of c3 at full
 size, on a ragged batch whose odd chain counts leave the upper half of an
 instance's last wave without a chain, in both residual modes and with
-eq. (3), under hipGraph replay and through the entry point that allocates
-nothing."""
+eq. (3), on markets smaller than one 32-lane pass, under hipGraph replay and
+through the entry point that allocates nothing; and the results must equal
+those of one chain per wave bit for bit."""
 import numpy as np
 import pytest
 
@@ -142,3 +143,28 @@ def test_paired_full_size_c3_equals_one_chain_per_wave(api, oracle):
     torch.cuda.synchronize()
     for k in ("accept", "level_best", "best_x", "best_f", "chain_best_f"):
         assert torch.equal(a[k], b[k]), k
+
+
+def test_paired_tiny_markets_and_lone_chains(api, oracle):
+    """Markets of 6..9 quotes (one 32-lane pass, most lanes idle) and
+    instances of one and three chains (the upper half of their last wave
+    holds no chain): the oracle's accept flags, and one chain per wave bit
+    for bit."""
+    from conftest import complete_with_oracle
+    m, truth, noise = I.batch_markets(n_markets=4, M_range=(2, 3), nK_range=(2, 4),
+                                      seed=I.SEED_BASE + 93)
+    mk = complete_with_oracle(oracle, m, truth, noise)
+    assert I.n_quotes(mk).max() < 32
+    lb, ub = I.box(0)
+    chains = np.array([1, 3, 2, 1], np.int32)
+    kw = dict(T0=0.02, cool=0.7, n_levels=5, n_steps=12, seed=43, record=True)
+    plan = api.Plan(mk)
+    g = plan.sa(chains, lb, ub, chain_best=True, waves=2, chains_per_wave=2, **kw)
+    one = plan.sa(chains, lb, ub, chain_best=True, waves=2, **kw)
+    torch.cuda.synchronize()
+    o = oracle.sa_calibrate(mk, chains, lb, ub, **kw)
+    where = first_mismatch(g["accept"].cpu().numpy(), o["accept"], 5, 12, chains)
+    assert where is None, f"first mismatch at {where}"
+    np.testing.assert_allclose(g["best_f"].cpu().numpy(), o["best_f"], rtol=RTOL)
+    for k in ("accept", "level_best", "best_x", "best_f", "chain_best_x", "chain_best_f"):
+        assert torch.equal(g[k], one[k]), k
