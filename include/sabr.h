@@ -221,6 +221,21 @@ typedef struct {
                                 keeps the partial sums of the 64 lanes one wave would use and
                                 adds them in the same order.  GLOBAL4 plans only, and not with
                                 waves_per_chain > 1: SABR_EINVAL */
+  int32_t level0;            /* index of the first level (>= 0, else SABR_EINVAL): step s of run
+                                level l draws the Philox counter (level0 + l) N + s, and without
+                                state_in the temperature starts at T0 cool^level0 (repeated
+                                multiplication).  A run of L levels equals a run of l levels
+                                with state_out followed by L - l levels from level0 = l with
+                                that state as state_in, bit for bit */
+  const double *state_in;    /* [device] nullable: resume from this annealing state (layout
+                                below) instead of evaluating x0; T is the state's.  Every chain
+                                of an instance must sit at one point with one cost, as in every
+                                state sa_calibrate or the CPU oracle writes; x0 is then unused */
+  double *state_out;         /* [device] nullable: the state after the last level (its restart
+                                done, T cooled).  Layout, per instance i in order with C its
+                                chains: X [C][P], F [C] (every chain's point and cost), BX [C][P],
+                                BF [C] (best-ever points and costs), T: 2 C (P + 1) + 1 doubles,
+                                starting at 2 (P + 1) (chains of instances before i) + i */
 } sa_config;
 
 /* Device workspace bytes sa_calibrate needs for these chain counts. */

@@ -44,7 +44,8 @@ class SAConfig(ctypes.Structure):
         ("T0_per_inst", _f64p), ("waves_per_group", ctypes.c_int32),
         ("use_graph", ctypes.c_int32), ("level_events", ctypes.POINTER(ctypes.c_void_p)),
         ("occupancy", ctypes.c_int32), ("waves_per_chain", ctypes.c_int32),
-        ("chains_per_wave", ctypes.c_int32),
+        ("chains_per_wave", ctypes.c_int32), ("level0", ctypes.c_int32),
+        ("state_in", ctypes.c_void_p), ("state_out", ctypes.c_void_p),   # device pointers
     ]
 
 

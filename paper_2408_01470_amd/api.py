@@ -128,7 +128,7 @@ class Plan:
     # ------------------------------------------------------------------
     def sa_config(self, T0, cool, n_levels, n_steps, seed, step_frac=0.05, T0_per_inst=None,
                   waves=0, use_graph=False, level_events=None, occupancy=0, waves_per_chain=0,
-                  chains_per_wave=0):
+                  chains_per_wave=0, level0=0, state_in=None, state_out=None):
         t0i = None
         if T0_per_inst is not None:
             t0i = np.ascontiguousarray(T0_per_inst, dtype=np.float64)
@@ -144,7 +144,8 @@ class Plan:
                         int(seed), t0i.ctypes.data_as(_f64p) if t0i is not None else None,
                         int(waves), 1 if use_graph else 0,
                         ctypes.cast(ev, ctypes.POINTER(ctypes.c_void_p)) if ev is not None
-                        else None, int(occupancy), int(waves_per_chain), int(chains_per_wave))
+                        else None, int(occupancy), int(waves_per_chain), int(chains_per_wave),
+                        int(level0), _ptr(state_in), _ptr(state_out))
 
     def sa_workspace_bytes(self, cfg, chains):
         ch = np.ascontiguousarray(np.broadcast_to(chains, (self.n_inst,)), dtype=np.int32)
@@ -168,14 +169,18 @@ class Plan:
     def sa(self, chains, lb, ub, T0, cool, n_levels, n_steps, seed, step_frac=0.05, x0=None,
            T0_per_inst=None, record=False, trace=True, chain_best=False, waves=0,
            use_graph=False, stream=None, workspace=None, out=None, level_events=None,
-           occupancy=0, noalloc=False, waves_per_chain=0, chains_per_wave=0):
+           occupancy=0, noalloc=False, waves_per_chain=0, chains_per_wave=0, level0=0,
+           state_in=None, state_out=False):
         """Synchronous parallel simulated annealing on every instance.  ``out``
         (a dict returned by an earlier call with the same shapes) reuses its
         output tensors, so a captured graph can be replayed.  noalloc: run
         through sa_calibrate_noalloc (the library's fixed device scratch, no
         workspace; the returned "workspace" is None).  waves_per_chain > 1:
         each chain's quotes split over that many waves of one workgroup;
-        chains_per_wave = 2 (GLOBAL4): two chains per wave, one per half."""
+        chains_per_wave = 2 (GLOBAL4): two chains per wave, one per half.
+        Resume: level0 is the first level's index; state_in (a float64 device
+        tensor of state_doubles(chains) values, as a run with state_out=True
+        returned in "state") replaces the evaluation of x0."""
         L = lib()
         n, P = self.n_inst, self.P
         cfg = self.sa_config(T0, cool, n_levels, n_steps, seed, step_frac, T0_per_inst, waves,
@@ -189,6 +194,15 @@ class Plan:
         tot = int(ch.sum())
         out = dict(out) if out is not None else self._sa_outputs(tot, n_levels, n_steps,
                                                                   record, trace, chain_best)
+        nst = self.state_doubles(ch)
+        if state_in is not None and (state_in.dtype != torch.float64 or state_in.numel() != nst
+                                     or not state_in.is_contiguous()):
+            raise ValueError(f"state_in: a contiguous float64 tensor of {nst} values")
+        if state_out and out.get("state") is None:
+            out["state"] = torch.empty(nst, dtype=torch.float64, device=self.device)
+        elif not state_out:
+            out["state"] = None
+        cfg.level0, cfg.state_in, cfg.state_out = int(level0), _ptr(state_in), _ptr(out["state"])
         o = out
         args = (lb.ctypes.data_as(_f64p), ub.ctypes.data_as(_f64p),
                 x0a.ctypes.data_as(_f64p) if x0a is not None else None,
@@ -198,9 +212,11 @@ class Plan:
         if noalloc:
             check(L.sa_calibrate_noalloc(
                 self._h, ctypes.byref(cfg), ch.ctypes.data_as(_i32p), *args,
-                _stream(stream, self._dev, *[v for v in o.values() if isinstance(v, torch.Tensor)])))
+                _stream(stream, self._dev, state_in,
+                        *[v for v in o.values() if isinstance(v, torch.Tensor)])))
             out["workspace"] = None
-            out["n_evals"] = ch.astype(np.int64) * (1 + int(n_steps) * int(n_levels))
+            out["n_evals"] = ch.astype(np.int64) * (int(state_in is None) +
+                                                    int(n_steps) * int(n_levels))
             return out
         ws = int(L.sa_workspace_size(self._h, ctypes.byref(cfg), ch.ctypes.data_as(_i32p)))
         if ws == 0:
@@ -214,11 +230,18 @@ class Plan:
                              _ptr(o["best_x"]), _ptr(o["best_f"]), _ptr(o["chain_best_x"]),
                              _ptr(o["chain_best_f"]), _ptr(o["accept"]), _ptr(o["trace"]),
                              _ptr(o["level_best"]), _ptr(workspace), workspace.numel(),
-                             _stream(stream, self._dev, workspace,
+                             _stream(stream, self._dev, workspace, state_in,
                                      *[v for v in o.values() if isinstance(v, torch.Tensor)])))
         out["workspace"] = workspace
-        out["n_evals"] = ch.astype(np.int64) * (1 + int(n_steps) * int(n_levels))
+        out["n_evals"] = ch.astype(np.int64) * (int(state_in is None) +
+                                                int(n_steps) * int(n_levels))
         return out
+
+    def state_doubles(self, chains):
+        """Doubles of an annealing state (sa_config.state_in/state_out) for
+        these chain counts: 2 C (P + 1) + 1 per instance."""
+        ch = np.broadcast_to(np.asarray(chains, dtype=np.int64), (self.n_inst,))
+        return int(np.sum(2 * ch * (self.P + 1) + 1))
 
     # ------------------------------------------------------------------
     def _adj_workspace(self, n, workspace=None):

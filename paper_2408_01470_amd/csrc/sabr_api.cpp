@@ -526,6 +526,7 @@ sabr_status check_sa_args(const sabr_plan *P, const sa_config *cfg, const int32_
     if (sabr::sa_waves_per_group(shape, cfg->waves_per_chain) != cfg->waves_per_chain)
       return fail(SABR_EINVAL, "waves_per_chain: the waves' LDS exceeds one workgroup's");
   }
+  if (cfg->level0 < 0) return fail(SABR_EINVAL, "level0 must be >= 0");
   if (cfg->chains_per_wave < 0 || cfg->chains_per_wave > 2)
     return fail(SABR_EINVAL, "chains_per_wave outside [0, 2]");
   if (cfg->chains_per_wave == 2) {
@@ -636,6 +637,9 @@ sabr_status sa_run(sabr_plan *P, const sa_config *cfg, const int32_t *chains, co
   a.n_inst = n;
   a.wpc = S.wpc;
   a.cpw = S.cpw;
+  a.level0 = cfg->level0;
+  a.state_in = cfg->state_in;
+  a.state_out = cfg->state_out;
   a.P = Pn;
   a.N = N;
   a.L = L;
@@ -692,7 +696,9 @@ sabr_status sa_run(sabr_plan *P, const sa_config *cfg, const int32_t *chains, co
       r = sabr::launch_sa_level_end(a, l, S.max_tiles, q);
       if (r != hipSuccess) return r;
     }
-    return sabr::launch_sa_final(a, q);
+    r = sabr::launch_sa_final(a, q);
+    if (r != hipSuccess || !cfg->state_out) return r;
+    return sabr::launch_sa_state_out(a, q);
   };
 
   if (!cfg->use_graph) {
@@ -709,7 +715,9 @@ sabr_status sa_run(sabr_plan *P, const sa_config *cfg, const int32_t *chains, co
                                (uint64_t)(uintptr_t)level_trace, (uint64_t)(uintptr_t)level_best,
                                (uint64_t)L, (uint64_t)N, cfg->seed, (uint64_t)S.waves,
                                (uint64_t)S.n_tiles, (uint64_t)cfg->occupancy,
-                               (uint64_t)S.wpc, (uint64_t)S.cpw};
+                               (uint64_t)S.wpc, (uint64_t)S.cpw, (uint64_t)cfg->level0,
+                               (uint64_t)(uintptr_t)cfg->state_in,
+                               (uint64_t)(uintptr_t)cfg->state_out};
   uint64_t bits;
   std::memcpy(&bits, &cfg->step_frac, 8);
   key.push_back(bits);

@@ -75,6 +75,7 @@ struct SAArgs {
   int n_inst, P, N, L;
   int wpc;                      // waves per chain: 1, or every wave of a one-chain workgroup
   int cpw;                      // chains per wave: 1, or 2 (one per half-wave; GLOBAL4)
+  int level0;                   // index of the first level (Philox counters, temperature)
   uint64_t seed;
   double step_frac, cool, ns_per_tick;
   const int *chains;            // [n_inst]
@@ -98,6 +99,11 @@ struct SAArgs {
   int *level_best;              // nullable: [inst][level]
   double *best_x, *best_f;      // [n_inst][P], [n_inst]
   double *chain_best_x, *chain_best_f;  // nullable
+  // nullable: the annealing state to resume from, and the state after the
+  // last level; per instance X [C][P], F [C], BX [C][P], BF [C], T, i.e.
+  // 2 C (P + 1) + 1 doubles from 2 (P + 1) chain_base + instance index
+  const double *state_in;
+  double *state_out;
 };
 
 hipError_t launch_prep(const DevMarket &m, QuoteRec *q, double *f_v, double *u_S0b, double *u_c0,
@@ -117,6 +123,7 @@ hipError_t launch_sa_level(const DevMarket &m, const SAArgs &a, int level, int n
 // level-end block (256 threads, 1024 beyond 1024 tiles).
 hipError_t launch_sa_level_end(const SAArgs &a, int level, int max_tiles, hipStream_t s);
 hipError_t launch_sa_final(const SAArgs &a, hipStream_t s);
+hipError_t launch_sa_state_out(const SAArgs &a, hipStream_t s);
 
 // Bytes of the fixed per-device scratch array of the allocation-free
 // annealing entry point, and the current device's address of it (looked up

@@ -345,8 +345,17 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void sa_init_kernel(DevM
   const int c0 = a.tile_chain[blockIdx.x] + (SPLIT ? 0 : (PAIR ? 2 * wid : wid));
   const int c = c0 + (PAIR ? lane_id() / kHalf : 0);
   const int sub = SPLIT ? wid : 0;
-  double f = kInf;
-  if (c0 < C) {   // wave-uniform (workgroup-uniform when wpc > 1)
+  // resume: the state that the levels before level0 left (every chain of an
+  // instance at its restart point) in place of the evaluation of x0
+  const double *st =
+      a.state_in ? a.state_in + 2 * (size_t)(P + 1) * a.chain_base[inst] + inst : nullptr;
+  double f = kInf, bf = kInf;
+  if (st) {
+    if (c < C) {
+      f = st[(size_t)C * P + c];
+      bf = st[(size_t)C * (2 * P + 1) + c];
+    }
+  } else if (c0 < C) {   // wave-uniform (workgroup-uniform when wpc > 1)
     const double xl = (lane < P) ? a.x0[(size_t)inst * P + lane] : 0.0;
     double x[PC > 0 ? PC : 1];
     chain_params<PC, PAIR>(xl, x);
@@ -354,25 +363,30 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup) void sa_init_kernel(DevM
     f = point_cost<MODEL, FORMULA, RESID, PAIR>(m, in, um, x, xl, w, nullptr, nullptr, sub,
                                                  wpc);
     if (SPLIT) f = split_total(f, sub, wpc, 0);
+    bf = f;
   }
   if (c < C && sub == 0) {
-    const double xl = (lane < P) ? a.x0[(size_t)inst * P + lane] : 0.0;
+    const bool own = lane < P;
+    const double xl = own ? (st ? st[(size_t)c * P + lane] : a.x0[(size_t)inst * P + lane]) : 0.0;
+    const double bxl = own && st ? st[(size_t)C * (P + 1) + (size_t)c * P + lane] : xl;
     const int64_t gc = a.chain_base[inst] + c;
-    if (lane < P) {
+    if (own) {
       a.X[gc * P + lane] = xl;
-      a.BX[gc * P + lane] = xl;
+      a.BX[gc * P + lane] = bxl;
       if (c == 0) a.RX[(size_t)inst * P + lane] = xl;
     }
     if (lane == 0) {
-      a.BF[gc] = f;
+      a.BF[gc] = bf;
       if (c == 0) {
         a.RF[inst] = f;
-        a.Tcur[inst] = a.T0[inst];
+        double T = a.T0[inst];   // T0 cool^level0 by repeated multiplication
+        for (int l = 0; l < a.level0; ++l) T = a.cool * T;
+        a.Tcur[inst] = st ? st[(size_t)C * (2 * P + 2)] : T;
         if (inst == 0) a.t_start[0] = wall_clock64();
       }
     }
   }
-  tile_partial<PAIR>(a, C, (c < C && sub == 0) ? c : C, f, f, 0);
+  tile_partial<PAIR>(a, C, (c < C && sub == 0) ? c : C, f, bf, 0);
 }
 
 // OCC: minimum waves per SIMD the register allocation must allow (1 = the
@@ -436,7 +450,8 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerGroup, OCC) void sa_level_kerne
         const int sl = ln / nb, blk = ln - sl * nb;
         if (sl < spp && s0 + sl < a.N) {
           uint64_t wds[4];
-          philox4x64_10((uint64_t)level * (uint64_t)a.N + (uint64_t)(s0 + sl), (uint64_t)c,
+          philox4x64_10((uint64_t)(a.level0 + level) * (uint64_t)a.N + (uint64_t)(s0 + sl),
+                        (uint64_t)c,
                         (uint64_t)blk, 0, a.seed, (uint64_t)inst, wds);
 #pragma unroll
           for (int j = 0; j < 4; ++j)
@@ -538,6 +553,27 @@ __global__ __launch_bounds__(256) void sa_final_kernel(SAArgs a) {
   const int g = sj[0];
   if (threadIdx.x < P) a.best_x[(size_t)inst * P + threadIdx.x] = a.BX[(base + g) * P + threadIdx.x];
   if (threadIdx.x == 0) a.best_f[inst] = a.BF[base + g];
+}
+
+// The annealing state after the last level (layout of SAArgs::state_out):
+// every chain at the instance's restart point with its cost, the chains'
+// best-ever points and costs, the next level's temperature.
+__global__ __launch_bounds__(256) void sa_state_out_kernel(SAArgs a) {
+  const int inst = blockIdx.x;
+  const int C = a.chains[inst];
+  const int P = a.P;
+  const int64_t base = a.chain_base[inst];
+  double *st = a.state_out + 2 * (size_t)(P + 1) * base + inst;
+  const size_t CP = (size_t)C * P;
+  for (size_t k = threadIdx.x; k < CP; k += blockDim.x) {
+    st[k] = a.RX[(size_t)inst * P + k % P];
+    st[(size_t)C * (P + 1) + k] = a.BX[(size_t)base * P + k];
+  }
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    st[CP + c] = a.RF[inst];
+    st[(size_t)C * (2 * P + 1) + c] = a.BF[base + c];
+  }
+  if (threadIdx.x == 0) st[(size_t)C * (2 * P + 2)] = a.Tcur[inst];
 }
 
 }  // namespace
@@ -737,6 +773,11 @@ hipError_t launch_sa_level_end(const SAArgs &a, int level, int max_tiles, hipStr
 
 hipError_t launch_sa_final(const SAArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(sa_final_kernel, dim3(a.n_inst), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sa_state_out(const SAArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(sa_state_out_kernel, dim3(a.n_inst), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -214,6 +214,9 @@ def test_sa_paired_chain_refusals_without_gpu(L):
         bad = SAConfig(1.0, 0.9, 0.05, 10, 10, 1, None, 4, 0, None, 0, 1, cpw)
         assert L.sa_workspace_size(h, ctypes.byref(bad), ch.ctypes.data_as(i32)) == 0
         assert "chains_per_wave" in L.sabr_last_error().decode()
+    neg = SAConfig(1.0, 0.9, 0.05, 10, 10, 1, None, 4, 0, None, 0, 1, 1, -1)
+    assert L.sa_workspace_size(h, ctypes.byref(neg), ch.ctypes.data_as(i32)) == 0
+    assert "level0" in L.sabr_last_error().decode()
     both = SAConfig(1.0, 0.9, 0.05, 10, 10, 1, None, 4, 0, None, 0, 2, 2)
     assert L.sa_workspace_size(h, ctypes.byref(both), ch.ctypes.data_as(i32)) == 0
     assert "waves_per_chain" in L.sabr_last_error().decode()
