@@ -125,3 +125,29 @@ def test_state_in_size_is_checked(api, oracle):
     with pytest.raises(ValueError):
         plan.sa(3, lb, ub, T0=0.05, cool=0.8, n_levels=1, n_steps=2, seed=1, level0=1,
                 state_in=torch.zeros(5, dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("L,N", [(0, 5), (3, 0), (2, 6)])
+def test_level0_without_state_and_degenerate_schedules(api, oracle, L, N):
+    """A run that starts at level 4 without a state (temperature T0 cool^4,
+    the Philox counters of levels 4, 5, ...), also with no level at all (the
+    state is the evaluated start) and with levels of no step (restarts and
+    cooling only): the oracle's flags and state."""
+    mk = _ragged(oracle)
+    lb, ub = I.box(0)
+    chains = np.array([3, 2, 5, 1, 4], np.int32)
+    kw = dict(T0=0.05, cool=0.8, n_levels=L, n_steps=N, seed=37, record=True, level0=4)
+    plan = api.Plan(mk)
+    g = plan.sa(chains, lb, ub, state_out=True, **kw)
+    torch.cuda.synchronize()
+    o = oracle.sa_calibrate(mk, chains, lb, ub, keep_state=True, **kw)
+    if L * N:
+        where = first_mismatch(g["accept"].cpu().numpy(), o["accept"], L, N, chains)
+        assert where is None, f"first mismatch at {where}"
+    for i, (gs, os_) in enumerate(zip(_state_parts(g["state"].cpu().numpy(), chains, plan.P),
+                                      _state_parts(o["state"], chains, plan.P))):
+        assert np.array_equal(gs[0], os_[0]) and np.array_equal(gs[2], os_[2]), f"points, {i}"
+        np.testing.assert_allclose(gs[1], os_[1], rtol=RTOL)
+        np.testing.assert_allclose(gs[3], os_[3], rtol=RTOL)
+        assert gs[4] == os_[4], f"temperature, instance {i}"
+    np.testing.assert_allclose(g["best_f"].cpu().numpy(), o["best_f"], rtol=RTOL)
