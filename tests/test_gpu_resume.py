@@ -151,3 +151,37 @@ def test_level0_without_state_and_degenerate_schedules(api, oracle, L, N):
         np.testing.assert_allclose(gs[3], os_[3], rtol=RTOL)
         assert gs[4] == os_[4], f"temperature, instance {i}"
     np.testing.assert_allclose(g["best_f"].cpu().numpy(), o["best_f"], rtol=RTOL)
+
+
+def test_resume_under_graph_replay_and_noalloc(api, oracle):
+    """The resumed run (state in, state out) replayed from a hipGraph, with
+    other eager work between replays, and through sa_calibrate_noalloc gives
+    the eager results bit for bit."""
+    mk = _ragged(oracle)
+    lb, ub = I.box(0)
+    chains = np.array([5, 1, 12, 3, 7], np.int32)
+    kw = dict(T0=0.05, cool=0.8, n_steps=9, seed=47, record=True, chain_best=True, waves=4)
+    plan = api.Plan(mk)
+    first = plan.sa(chains, lb, ub, n_levels=2, state_out=True, **kw)
+    st = first["state"].clone()
+    rkw = dict(kw, n_levels=3, level0=2, state_in=st, state_out=True)
+    eager = plan.sa(chains, lb, ub, **rkw)
+    torch.cuda.synchronize()
+    keys = ("accept", "level_best", "best_x", "best_f", "chain_best_x", "chain_best_f", "state")
+    na = plan.sa(chains, lb, ub, noalloc=True, **rkw)
+    torch.cuda.synchronize()
+    for k in keys:
+        assert torch.equal(na[k], eager[k]), f"noalloc: {k}"
+    side = torch.cuda.Stream()
+    ws, outs = eager["workspace"], None
+    pts = torch.tensor(I.random_box_points(0, 64, 5), device="cuda")
+    for rep in range(3):
+        with torch.cuda.stream(side):
+            g = plan.sa(chains, lb, ub, use_graph=True, stream=side, workspace=ws, out=outs,
+                        **rkw)
+        outs = g
+        side.synchronize()
+        plan.cost(pts)
+        torch.cuda.synchronize()
+        for k in keys:
+            assert torch.equal(g[k], eager[k]), f"replay {rep}: {k}"
